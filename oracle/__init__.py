@@ -1,0 +1,39 @@
+"""FP64 CPU oracle for the periodic Stokes mobility solver (TEST INFRASTRUCTURE).
+
+This package is the independent reference that the HIP path is checked
+against. It is test infrastructure only: nothing in the product library or its
+Python binding imports, links or executes it. Only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may use
+it. It shares no code with the HIP path (no kernels, headers, helpers or
+tables); the only shared module is the seeded input generator
+``paper_1912_04501_amd.workloads``, which holds none of the method's
+arithmetic.
+
+Everything is plain FP64: NumPy/SciPy for the linear algebra (SVD
+pseudo-inverse, LU, FFT) and a plain C loop (``csrc/oracle_direct.c``) for the
+O(N^2) direct image sums, which NumPy would take minutes over at 5,000 nodes.
+
+Map of the method (citations are to the paper's sections and equations):
+
+* ``geometry``   - lattice (Sec. 2, Sec. 7 skew reduction), ellipse nodes and
+                   the periodic trapezoid rule (Sec. 6, weights w = (2 pi/N)|x'|)
+* ``kernels``    - Stokeslet G, pressure G^p, traction G^t (Sec. 4.1, eqs. Gv, Gp, Gt)
+* ``near``       - 3x3 near-image traction sum and the smooth self term (Sec. 4.2
+                   Def. of G_near; Sec. 6 Nystrom discretization)
+* ``close``      - barycentric close evaluation of the single-layer traction
+                   (Sec. 6.3), re-derived for the exterior of each curve
+* ``periodizer`` - wall discrepancy, proxy Stokeslets (MFS) and the correction
+                   (Sec. 4.2 eqs. discrepCorr, Sec. 6.1, Sec. 6.2 four-step algorithm)
+* ``operator``   - completed BIE (1/2 I + K + L) sigma with the pressure pin
+                   (Sec. 5 eq. BIEPerturbed, Sec. 6.2 pressure-correction remark),
+                   dense assembly, LU and GMRES
+* ``readout``    - particle velocities, angular velocities, effective viscosity
+                   (Sec. 3 eq. RigidBodyMotion and eq. mueff)
+* ``step``       - forward Euler time stepping (Sec. 7)
+
+Parity unpinned (consistent by construction only): the absolute velocity gauge
+away from symmetric configurations, and the exact truncation of the proxy
+least-squares pseudo-inverse.
+"""
+from .geometry import Geometry, build_geometry, reduce_skew  # noqa: F401
+from .operator import Problem, make_problem  # noqa: F401

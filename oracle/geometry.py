@@ -1,0 +1,101 @@
+"""Lattice and particle discretisation (Sec. 2, Sec. 6 trapezoid rule, Sec. 7).
+
+* Lattice: e1 = (1, 0), e2 = (s, 1). The skew is reduced to [-1/2, 1/2) with
+  s <- s - floor(s + 1/2); this is the integer shift e2 <- e2 - round(s) e1 of
+  Sec. 7 (same lattice, bounded skewness).
+* Cell: centre c_U = (0, 0); a particle centre is wrapped into the cell by
+  reducing its lattice coordinates (alpha, beta) = [e1 e2]^{-1} (c - c_U) the same way.
+* Ellipse i: x(t) = c + R(theta) (a cos t, b sin t), t_k = 2 pi k / N_i.
+  Periodic trapezoid rule (Sec. 6): w_k = (2 pi / N_i) |x'(t_k)|.
+  Tangent tau = x'/|x'|, outward normal n = (tau_2, -tau_1), curvature
+  kappa = a b / |x'|^3. The perimeter centroid (Sec. 2) of an ellipse is c.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def reduce_skew(s: float) -> float:
+    return float(s - np.floor(s + 0.5))
+
+
+def lattice(skew: float):
+    s = reduce_skew(skew)
+    return np.array([1.0, 0.0]), np.array([s, 1.0])
+
+
+def wrap_centers(c, e1, e2, cU=(0.0, 0.0)):
+    B = np.stack([e1, e2], axis=1)  # columns e1, e2
+    ab = np.linalg.solve(B, (np.asarray(c, float) - np.asarray(cU)).T).T
+    ab = ab - np.floor(ab + 0.5)
+    return np.asarray(cU) + ab @ B.T
+
+
+@dataclass
+class Geometry:
+    e1: np.ndarray
+    e2: np.ndarray
+    cU: np.ndarray
+    centers: np.ndarray   # (No, 2), wrapped
+    theta: np.ndarray
+    a: np.ndarray
+    b: np.ndarray
+    n_nodes: np.ndarray   # (No,)
+    offsets: np.ndarray   # (No + 1,)
+    x: np.ndarray         # (N, 2) nodes
+    xp: np.ndarray        # (N, 2) dx/dt
+    tau: np.ndarray       # (N, 2) unit tangent
+    n: np.ndarray         # (N, 2) outward normal
+    w: np.ndarray         # (N,) trapezoid weights
+    kappa: np.ndarray     # (N,) curvature
+    pid: np.ndarray       # (N,) particle index of each node
+
+    @property
+    def N(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def No(self) -> int:
+        return len(self.a)
+
+    def shifts(self, rng=1):
+        """Image shifts m e1 + n e2 for m, n in [-rng, rng] (the zero shift is the centre entry)."""
+        out = []
+        for m in range(-rng, rng + 1):
+            for k in range(-rng, rng + 1):
+                out.append(m * self.e1 + k * self.e2)
+        return np.array(out)
+
+    def particle_slice(self, i):
+        return slice(int(self.offsets[i]), int(self.offsets[i + 1]))
+
+
+def ellipse_nodes(c, theta, a, b, N):
+    t = 2.0 * np.pi * np.arange(N) / N
+    ct, st = np.cos(theta), np.sin(theta)
+    px, py = a * np.cos(t), b * np.sin(t)
+    dx, dy = -a * np.sin(t), b * np.cos(t)
+    x = np.stack([c[0] + ct * px - st * py, c[1] + st * px + ct * py], axis=1)
+    xp = np.stack([ct * dx - st * dy, st * dx + ct * dy], axis=1)
+    sp = np.sqrt((xp * xp).sum(1))
+    tau = xp / sp[:, None]
+    n = np.stack([tau[:, 1], -tau[:, 0]], axis=1)
+    w = 2.0 * np.pi * sp / N
+    kappa = a * b / sp ** 3
+    return x, xp, tau, n, w, kappa
+
+
+def build_geometry(wl) -> Geometry:
+    e1, e2 = lattice(wl["skew"])
+    cU = np.zeros(2)
+    c = wrap_centers(np.asarray(wl["centers"], float), e1, e2, cU)
+    nn = np.asarray(wl["n_nodes"], dtype=np.int64)
+    offs = np.concatenate([[0], np.cumsum(nn)])
+    parts = [ellipse_nodes(c[i], float(wl["theta"][i]), float(wl["a"][i]), float(wl["b"][i]), int(nn[i]))
+             for i in range(len(nn))]
+    x, xp, tau, n, w, kappa = (np.concatenate([p[k] for p in parts]) for k in range(6))
+    pid = np.repeat(np.arange(len(nn)), nn)
+    return Geometry(e1, e2, cU, c, np.asarray(wl["theta"], float), np.asarray(wl["a"], float),
+                    np.asarray(wl["b"], float), nn, offs, x, xp, tau, n, w, kappa, pid)

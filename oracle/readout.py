@@ -1,0 +1,68 @@
+"""Rigid-body velocities and effective viscosity (Sec. 3).
+
+Velocities. Inside particle i the total flow u + u0 is the rigid motion
+v_i + omega_i (x - c_i)^perp (eq. RigidBodyMotion; the BIE makes the interior
+traction vanish, Sec. 5), so both are read at the centroid c_i:
+
+    v_i     = u0(c_i) + u_near(c_i) + [u_corr(c_i) - u_corr(c_U)]
+    omega_i = (1/2) [vort_near(c_i) + vort_corr(c_i)] - gamma/2
+
+u is defined only up to a constant velocity (Sec. 3 nullspace lemma; Sec. 4.2,
+G_per up to a constant); differencing u_corr against the cell centre fixes that
+gauge, and omega is gauge-free. u0 = (gamma x_2, 0) has vorticity -gamma.
+
+Effective viscosity. eq. (mueff) integrates the shear traction through the
+bottom wall D. The particle-stresslet form used here equals it by the force
+balance of the cell (Gauss law, Sec. 4.1 lemma on net quantities): the force on
+particle i is -int sigma_i, and the cell-averaged shear stress gives
+
+    mu_eff = mu - (1/(2 gamma |U|)) sum_i sum_k w_k [(x_k - c_i)_1 sigma_k,2 + (x_k - c_i)_2 sigma_k,1],
+
+|U| = |det(e1, e2)|. ``mu_eff_wall`` evaluates eq. (mueff) directly with
+Gauss-Legendre on D; it is valid only when no particle comes near D.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import _clib, near, periodizer
+from .operator import proxy_strengths, to2
+
+
+def velocities(prob, sigma):
+    g = prob.geom
+    s2 = to2(np.asarray(sigma, dtype=np.float64))
+    f = near.forces(g, s2)
+    xi, _, _ = proxy_strengths(prob, s2)
+    un, vn = _clib.stokeslet_velocity(g.centers, g.x, f, g.shifts(prob.cfg.image_range), prob.cfg.mu)
+    uc = periodizer.correction_velocity(prob.P, xi, g.centers, prob.cfg.mu)
+    uc0 = periodizer.correction_velocity(prob.P, xi, g.cU[None, :], prob.cfg.mu)
+    vc = periodizer.correction_vorticity(prob.P, xi, g.centers, prob.cfg.mu)
+    u0 = np.stack([prob.cfg.gamma * g.centers[:, 1], np.zeros(g.No)], axis=1)
+    v = u0 + un + uc - uc0
+    omega = 0.5 * (vn + vc) - 0.5 * prob.cfg.gamma
+    return v, omega
+
+
+def mu_eff(prob, sigma):
+    g = prob.geom
+    s2 = to2(np.asarray(sigma, dtype=np.float64))
+    rel = g.x - g.centers[g.pid]
+    st = (g.w * (rel[:, 0] * s2[:, 1] + rel[:, 1] * s2[:, 0])).sum()
+    area = abs(g.e1[0] * g.e2[1] - g.e1[1] * g.e2[0])
+    return prob.cfg.mu - st / (2.0 * prob.cfg.gamma * area)
+
+
+def mu_eff_wall(prob, sigma, nq=64):
+    g = prob.geom
+    s2 = to2(np.asarray(sigma, dtype=np.float64))
+    f = near.forces(g, s2)
+    xi, _, _ = proxy_strengths(prob, s2)
+    t, wt = periodizer.gauss_legendre(nq)
+    xq = g.cU - 0.5 * g.e2 + (0.5 * t)[:, None] * g.e1
+    wq = 0.5 * wt * np.linalg.norm(g.e1)
+    nD = np.repeat(np.array([[0.0, 1.0]]), nq, axis=0)
+    Tn = _clib.near_traction(xq, nD, g.x, f, g.shifts(prob.cfg.image_range))
+    Tc = periodizer.correction_traction(prob.P, xi, xq, nD)
+    T1 = Tn[:, 0] + Tc[:, 0]
+    return prob.cfg.mu + (wq * T1).sum() / (prob.cfg.gamma * np.linalg.norm(g.e1))

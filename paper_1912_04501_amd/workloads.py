@@ -1,0 +1,258 @@
+"""Seeded synthetic workloads: ellipse suspensions in a sheared unit cell.
+
+This module only *generates inputs* (particle tables, lattice skews, random
+densities). It holds none of the method's arithmetic: no kernels, no
+quadrature, no solver. Both the HIP path and the CPU oracle take their inputs
+from here, so the two never share numerical code.
+
+A workload is a dict::
+
+    {"name": str, "skew": float,            # e2 = (skew, 1), e1 = (1, 0), cell centre (0, 0)
+     "centers": (No, 2) float64, "theta": (No,), "a": (No,), "b": (No,),
+     "n_nodes": (No,) int32, "mu": float, "gamma": float}
+
+Geometry conventions follow the paper's setup (Sec. 2): lattice vectors
+e1 = (1, 0), e2 = (gamma t, 1); an ellipse is x(t) = c + R(theta) (a cos t, b sin t).
+
+Recipes (stated in the design doc as well):
+
+* ``single_ellipse``: one ellipse a=0.2, b=0.1, theta=0 at the cell centre,
+  skew 0, N=128 nodes.
+* ``random_ellipses(n, phi, seed, ...)``: n ellipses of equal area phi/n,
+  aspect ratio AR ~ U[ar_lo, ar_hi], a = sqrt(area*AR/pi), b = a/AR,
+  theta ~ U[0, pi), skew ~ U[0, 1) (reduced later by the library/oracle to
+  [-1/2, 1/2), which is the same lattice), centres uniform in lattice
+  coordinates, random sequential placement rejecting any candidate whose
+  periodic gap to an already placed ellipse is below ``min_gap``.
+  Node counts: fixed ``nodes`` if given, else the perimeter rule
+  N_i = clamp(8*ceil(P_i / (8 h)), 64, 256) with h = sum(P_i) / target_total.
+* ``two_ellipses(d)``: two ellipses with semi-axes (0.25, 0.125) and
+  (0.125, 0.25) on a horizontal line, boundary gap d (the paper's two-ellipse
+  convergence example, Sec. 8 Example 1).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+# node density of the 25-ellipse, 5,000-node workload (used by ensembles and
+# time stepping, whose cells draw their node counts from the same density)
+_C1_TARGET_TOTAL = 5000
+
+
+def _ellipse_perimeter(a: float, b: float) -> float:
+    """Ramanujan's second approximation (rel. error < 1e-9 for AR <= 3); only
+    used to pick node counts, never inside the method."""
+    h = ((a - b) / (a + b)) ** 2
+    return math.pi * (a + b) * (1 + 3 * h / (10 + math.sqrt(4 - 3 * h)))
+
+
+def node_rule(a, b, h_star, lo=64, hi=256):
+    """N_i = clamp(8 ceil(P_i / (8 h*)), lo, hi)."""
+    out = []
+    for ai, bi in zip(a, b):
+        p = _ellipse_perimeter(float(ai), float(bi))
+        n = 8 * int(math.ceil(p / (8.0 * h_star)))
+        out.append(min(max(n, lo), hi))
+    return np.asarray(out, dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
+# periodic gap test used only by the placement loop
+# ---------------------------------------------------------------------------
+
+def _boundary(c, th, a, b, t):
+    ct, st = math.cos(th), math.sin(th)
+    px = a * np.cos(t)
+    py = b * np.sin(t)
+    return np.stack([c[0] + ct * px - st * py, c[1] + st * px + ct * py], axis=-1)
+
+
+def _inside(p, c, th, a, b):
+    ct, st = math.cos(th), math.sin(th)
+    dx = p[..., 0] - c[0]
+    dy = p[..., 1] - c[1]
+    u = ct * dx + st * dy
+    v = -st * dx + ct * dy
+    return (u / a) ** 2 + (v / b) ** 2 < 1.0
+
+
+def _pair_gap(c1, th1, a1, b1, c2, th2, a2, b2, ns=256):
+    """Minimum distance between two ellipse boundaries (<= 0 if they overlap)."""
+    t = np.arange(ns) * (2 * math.pi / ns)
+    p1 = _boundary(c1, th1, a1, b1, t)
+    p2 = _boundary(c2, th2, a2, b2, t)
+    if _inside(p1, c2, th2, a2, b2).any() or _inside(p2, c1, th1, a1, b1).any():
+        return -1.0
+    d2 = ((p1[:, None, :] - p2[None, :, :]) ** 2).sum(-1)
+    k = np.unravel_index(np.argmin(d2), d2.shape)
+    t1, t2 = t[k[0]], t[k[1]]
+    step = 2 * math.pi / ns
+    best = math.sqrt(d2[k])
+    for _ in range(3):  # local refinement around the best pair
+        s = np.linspace(-2 * step, 2 * step, 41)
+        q1 = _boundary(c1, th1, a1, b1, t1 + s)
+        q2 = _boundary(c2, th2, a2, b2, t2 + s)
+        dd = ((q1[:, None, :] - q2[None, :, :]) ** 2).sum(-1)
+        kk = np.unravel_index(np.argmin(dd), dd.shape)
+        t1, t2 = t1 + s[kk[0]], t2 + s[kk[1]]
+        best = min(best, math.sqrt(dd[kk]))
+        step = step / 10
+    return best
+
+
+def periodic_min_gap(wl) -> float:
+    """Smallest boundary gap over all pairs and the 3x3 lattice images."""
+    c, th, a, b = wl["centers"], wl["theta"], wl["a"], wl["b"]
+    e1 = np.array([1.0, 0.0])
+    e2 = np.array([wl["skew"], 1.0])
+    n = len(a)
+    g = math.inf
+    for i in range(n):
+        for j in range(i, n):
+            for m in (-1, 0, 1):
+                for k in (-1, 0, 1):
+                    if i == j and m == 0 and k == 0:
+                        continue
+                    cj = c[j] + m * e1 + k * e2
+                    if np.linalg.norm(c[i] - cj) > a[i] + a[j] + 0.05:
+                        continue
+                    g = min(g, _pair_gap(c[i], th[i], a[i], b[i], cj, th[j], a[j], b[j]))
+    return g
+
+
+def _place(rng, area, n, ar_lo, ar_hi, skew, min_gap, max_tries=100000):
+    e1 = np.array([1.0, 0.0])
+    e2 = np.array([skew, 1.0])
+    centers, thetas, aa, bb = [], [], [], []
+    for _ in range(n):
+        ar = rng.uniform(ar_lo, ar_hi)
+        a = math.sqrt(area * ar / math.pi)
+        b = a / ar
+        for _try in range(max_tries):
+            al, be = rng.uniform(-0.5, 0.5, size=2)
+            c = al * e1 + be * e2
+            th = rng.uniform(0.0, math.pi)
+            ok = True
+            for j in range(len(centers)):
+                for m in (-1, 0, 1):
+                    for k in (-1, 0, 1):
+                        cj = centers[j] + m * e1 + k * e2
+                        dist = float(np.linalg.norm(c - cj))
+                        if dist > a + aa[j] + min_gap:
+                            continue
+                        if dist < b + bb[j] + min_gap:
+                            ok = False
+                            break
+                        if _pair_gap(c, th, a, b, cj, thetas[j], aa[j], bb[j]) < min_gap:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if ok:
+                # the ellipse must also clear its own periodic images
+                for m in (-1, 0, 1):
+                    for k in (-1, 0, 1):
+                        if m == 0 and k == 0:
+                            continue
+                        cj = c + m * e1 + k * e2
+                        if float(np.linalg.norm(c - cj)) < 2 * a + min_gap:
+                            if _pair_gap(c, th, a, b, cj, th, a, b) < min_gap:
+                                ok = False
+            if ok:
+                centers.append(c)
+                thetas.append(th)
+                aa.append(a)
+                bb.append(b)
+                break
+        else:
+            return None
+    return (np.array(centers), np.array(thetas), np.array(aa), np.array(bb))
+
+
+def random_ellipses(n, phi, seed, ar_lo=1.5, ar_hi=3.0, min_gap=1e-3, nodes=None,
+                    target_total=_C1_TARGET_TOTAL, h_star=None, skew=None, name=None,
+                    mu=1.0, gamma=1.0):
+    rng = np.random.default_rng(seed)
+    sk = float(rng.uniform(0.0, 1.0)) if skew is None else float(skew)
+    area = phi / n
+    for attempt in range(20):
+        placed = _place(rng, area, n, ar_lo, ar_hi, sk, min_gap)
+        if placed is not None:
+            break
+    else:  # pragma: no cover - reseeding never needed for the shipped recipes
+        raise RuntimeError("random sequential placement failed")
+    c, th, a, b = placed
+    if nodes is not None:
+        nn = np.full(n, int(nodes), dtype=np.int32)
+    else:
+        if h_star is None:
+            per = sum(_ellipse_perimeter(x, y) for x, y in zip(a, b))
+            h_star = per / float(target_total)
+        nn = node_rule(a, b, h_star)
+    return {"name": name or f"random_{n}_phi{phi}_seed{seed}", "skew": sk, "centers": c,
+            "theta": th, "a": a, "b": b, "n_nodes": nn, "mu": mu, "gamma": gamma}
+
+
+def c1_h_star(seed=1):
+    """Node spacing of the 25-ellipse, ~5,000-node workload (reused by other recipes)."""
+    wl = random_ellipses(25, 0.3, seed, nodes=64)
+    per = sum(_ellipse_perimeter(x, y) for x, y in zip(wl["a"], wl["b"]))
+    return per / float(_C1_TARGET_TOTAL)
+
+
+# ---------------------------------------------------------------------------
+# named recipes
+# ---------------------------------------------------------------------------
+
+def single_ellipse(n_nodes=128, a=0.2, b=0.1, theta=0.0, skew=0.0, center=(0.0, 0.0), mu=1.0, gamma=1.0):
+    return {"name": "single_ellipse_128", "skew": float(skew), "centers": np.array([center], dtype=float),
+            "theta": np.array([theta], dtype=float), "a": np.array([a], dtype=float),
+            "b": np.array([b], dtype=float), "n_nodes": np.array([n_nodes], dtype=np.int32),
+            "mu": mu, "gamma": gamma}
+
+
+def ellipses_25(seed=1):
+    """25 ellipses, area fraction 0.3, AR in [1.5, 3], ~5,000 nodes, min gap 1e-3."""
+    wl = random_ellipses(25, 0.3, seed, name="ellipses_25_phi0.3")
+    return wl
+
+
+def ellipses_200(seed=2):
+    """200 ellipses, area fraction 0.4, 256 nodes each (N = 51,200)."""
+    return random_ellipses(200, 0.4, seed, nodes=256, name="ellipses_200_phi0.4_N51200")
+
+
+def ensemble_cells(n_cells=64, base_seed=1000, h_star=None, lo=4, hi=50, phi=0.3):
+    """Independent cells for the batched ensemble: cell c uses seed base_seed + c,
+    particle count ~ U{lo..hi}, area fraction phi, node counts from the
+    25-ellipse node density."""
+    if h_star is None:
+        h_star = c1_h_star()
+    cells = []
+    for c in range(n_cells):
+        rng = np.random.default_rng(base_seed + c)
+        n = int(rng.integers(lo, hi + 1))
+        cells.append(random_ellipses(n, phi, base_seed + c, h_star=h_star, name=f"cell{c}"))
+    return cells
+
+
+def two_ellipses(d, n_nodes=64, skew=0.0):
+    """Semi-axes (0.25, 0.125) and (0.125, 0.25) with boundary gap d along x."""
+    sep = d + 0.375
+    c = np.array([[-sep / 2, 0.0], [sep / 2, 0.0]])
+    return {"name": f"two_ellipses_d{d:g}", "skew": float(skew), "centers": c,
+            "theta": np.array([0.0, 0.0]), "a": np.array([0.25, 0.125]), "b": np.array([0.125, 0.25]),
+            "n_nodes": np.array([n_nodes, n_nodes], dtype=np.int32), "mu": 1.0, "gamma": 1.0}
+
+
+def random_density(n_total, seed=7):
+    """sigma ~ N(0, 1), SoA [sigma_1(0..N-1), sigma_2(0..N-1)]."""
+    return np.random.default_rng(seed).standard_normal(2 * int(n_total))
+
+
+def total_nodes(wl) -> int:
+    return int(np.sum(wl["n_nodes"]))
