@@ -1,0 +1,164 @@
+#!/usr/bin/env python
+"""Benchmark of the periodic Stokes mobility solve on one MI355X.
+
+Workload: 200 random ellipses at area fraction 0.4, 256 nodes each (N = 51,200),
+seed 2 (the large-cell configuration on which node-pair evaluations per second are
+quoted). One step = one complete mobility solve from a zero initial guess to an FP64
+relative residual of 1e-10 (matvecs + GMRES + readout of v, omega, mu_eff), with the
+geometry already resident in HBM. Default precision: FP32 near sums inside FP64
+iterative refinement; --precision fp64 times plain FP64 GMRES.
+
+value = node-image pair evaluations (9 N^2 per matvec, all matvecs of the step) per
+second of wall time over the timed steps.
+
+roofline: the near-sum kernel (the dominant kernel), timed live with HIP events
+recorded on the library's stream around every launch inside the timed region;
+algorithmic work 19 flop per pair (r: 2, |r|^2: 3, r.n: 3, r.f: 3, 1/|r|^2: 1,
+square: 1, coefficient: 2, accumulate: 4).
+
+cpu_baseline: the FP64 CPU oracle's near-image traction sum (plain C, OpenMP) on a
+bounded sample of targets of the same workload, in pair evaluations per second.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 19
+PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector ALU peaks, TFLOP/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, target_seconds=10.0):
+    import numpy as np
+
+    from oracle import _clib, geometry
+    g = geometry.build_geometry(wl)
+    sig = np.random.default_rng(7).standard_normal((g.N, 2))
+    f = g.w[:, None] * sig
+    sh = g.shifts(1)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def run(nt):
+        t0 = time.perf_counter()
+        _clib.near_traction(g.x[:nt], g.n[:nt], g.x, f, sh, np.arange(nt))
+        return time.perf_counter() - t0
+
+    run(64)
+    t = run(256)
+    rate = 256 * g.N * 9 / t
+    nt = int(min(g.N, max(256, rate * target_seconds / (g.N * 9))))
+    t = run(nt)
+    pairs = nt * g.N * 9
+    return {"value": pairs / t, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle near-image traction sum (plain C, OpenMP) for {nt} of the {g.N} targets "
+                      f"against all {g.N} sources x 9 images ({pairs:.3e} pairs, {t:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp32_ir", "fp64"], default="fp32_ir")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the untimed FP64-vs-FP32+IR comparison solves")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1912_04501_amd import spm
+    from paper_1912_04501_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    t0 = time.perf_counter()
+    wl = W.ellipses_200()
+    log(f"[bench] workload {wl['name']} generated in {time.perf_counter() - t0:.1f}s")
+    prec = spm.SPM_FP32_IR if args.precision == "fp32_ir" else spm.SPM_FP64
+    s = spm.Solver("cuda:0", precision=prec)
+    s.set_workload(wl)
+    N = s.N
+    pairs_per_matvec = 9.0 * N * N
+    log(f"[bench] N={N} particles={s.No} close pairs={len(s.close_pairs())}")
+
+    for k in range(args.warmup):
+        r = s.solve()
+        log(f"[bench] warmup {k}: {r['info']}")
+    torch.cuda.synchronize()
+    s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        r = s.solve()
+        infos.append(r["info"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = 1 if prec == spm.SPM_FP32_IR else 0
+    prof = s.profile_read(kern)
+    s.profile(False)
+    for k, i in enumerate(infos):
+        log(f"[bench] step {k}: {i}")
+    matvecs = sum(i["fp64_matvecs"] + i["fp32_matvecs"] for i in infos)
+    value = matvecs * pairs_per_matvec / elapsed
+    avg_ms = prof["ms"] / max(prof["launches"], 1)
+    achieved = FLOP_PER_PAIR * pairs_per_matvec / (avg_ms * 1e-3) / 1e12
+    dt = "fp32" if kern == 1 else "fp64"
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK[dt], "unit": "TFLOP/s",
+                "frac": achieved / PEAK[dt], "traffic": None,
+                "kernel": f"k_near<{'float' if kern else 'double'}> (near-image traction sum, {dt})",
+                "avg_launch_ms": avg_ms, "launches": prof["launches"],
+                "pairs_per_launch": pairs_per_matvec}
+
+    extra = {}
+    if not args.no_compare:
+        for name, p in (("fp64", spm.SPM_FP64), ("fp32_ir", spm.SPM_FP32_IR)):
+            c = spm.Solver("cuda:0", precision=p)
+            c.set_workload(wl)
+            c.solve()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rr = c.solve()
+            torch.cuda.synchronize()
+            extra[f"solve_s_{name}"] = time.perf_counter() - t1
+            extra[f"solve_info_{name}"] = {k: rr["info"][k] for k in ("iterations", "fp64_matvecs", "fp32_matvecs",
+                                                                       "refinements", "rel_residual")}
+            extra[f"mu_eff_{name}"] = float(rr["mu_eff"].item())
+            c.close()
+        log(f"[bench] comparison {extra}")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle sample ...")
+        cpu = cpu_baseline(wl)
+        log(f"[bench] cpu baseline {cpu}")
+
+    out = {"metric": "Stokes matvec pair-evals/s (whole mobility solve to 1e-10 FP64 residual)",
+           "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64" if kern == 1 else "f64", "data": "synthetic",
+           "config": {"workload": wl["name"], "N": N, "particles": s.No, "nodes_per_particle": 256,
+                      "precision": args.precision, "tol": 1e-10, "images": "3x3", "proxies": 32,
+                      "wall_points": 24, "close_factor": 10},
+           "roofline": roofline, "cpu_baseline": cpu, **extra}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

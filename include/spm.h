@@ -1,0 +1,207 @@
+/*
+ * spm.h - C ABI of the MI355X periodic Stokes mobility solver.
+ *
+ * Method: Wang, Nazockdast & Barnett, "An integral equation method for the
+ * simulation of doubly-periodic suspensions of rigid bodies in a shearing viscous
+ * flow" (arXiv:1912.04501). The library solves the quasi-static mobility problem
+ * of Sec. 3 for rigid ellipses in a sheared, skewed unit cell through the
+ * completed second-kind BIE of Sec. 5 (eq. BIEPerturbed):
+ *
+ *     (1/2 I + K + L) sigma = -T(u0, p0) = -mu gamma (n_2, n_1),
+ *
+ * where K is the traction of the periodic single-layer potential, applied as a
+ * 3x3 near-image sum + exterior barycentric close correction + proxy-Stokeslet
+ * periodizing correction (Sec. 4.2, Sec. 6.1-6.3), with the pressure pin of the
+ * Sec. 6.2 remark, and L the rigid-mode completion of Sec. 5.
+ *
+ * Conventions (all calls):
+ *  - Lattice e1 = (1, 0), e2 = (s, 1) (Sec. 2, Sec. 7); the skew s is reduced to
+ *    [-1/2, 1/2) internally (same lattice); the cell centre is c_U.
+ *  - Angles are radians, counter-clockwise. Ellipse i is
+ *    x(t) = c_i + R(theta_i) (a_i cos t, b_i sin t), nodes t_k = 2 pi k / N_i,
+ *    particle-major: the nodes of particle 0 first.
+ *  - Densities and node-vectors are SoA FP64: v[0..N-1] first components,
+ *    v[N..2N-1] second components.
+ *  - Background flow u0 = (gamma x_2, 0). Velocities are reported in the gauge
+ *    where the proxy (periodizing) field vanishes at the cell centre; omega is
+ *    gauge-free.
+ *
+ * Memory and streams: every array argument is a DEVICE pointer on the handle's
+ * stream unless its name ends in _host. The caller owns all arrays; the library
+ * only borrows them for the duration of the call and never frees them. The
+ * handle owns its device workspace, which it obtains through the allocator
+ * callbacks given to spm_create (or hipMalloc/hipFree when they are NULL). All
+ * kernels run on the stream given to spm_create; calls return after that stream
+ * has finished the call's work (so outputs are ready). A handle is not
+ * thread-safe; distinct handles are independent.
+ *
+ * Errors: every call returns 0 on success or a negative SPM_E* code;
+ * spm_last_error() returns a message for the last failure on that handle.
+ * On error no output is guaranteed except where stated (SPM_ENOCONV).
+ */
+#ifndef SPM_H
+#define SPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPM_OK 0
+#define SPM_EINVAL (-1)    /* bad argument (null pointer, size out of range, call order) */
+#define SPM_EOVERLAP (-2)  /* particles overlap or come closer than cfg.min_gap */
+#define SPM_ENOCONV (-3)   /* GMRES hit max_iter; outputs hold the last iterate */
+#define SPM_EHIP (-4)      /* a HIP runtime call failed; message carries the HIP error */
+#define SPM_ENOMEM (-5)    /* the allocator returned NULL */
+#define SPM_ESTATE (-6)    /* call made before the lattice/particles were set */
+
+#define SPM_FP64 0         /* every sum in FP64 */
+#define SPM_FP32 1         /* near-image sum in FP32 with FP32 accumulation; the rest FP64 */
+#define SPM_FP32_IR 2      /* solve: FP64 iterative refinement around FP32-near-sum GMRES */
+
+typedef struct spm_handle spm_handle;
+
+/* Solver configuration; spm_default_config() fills the values in brackets. */
+typedef struct {
+  double mu;            /* viscosity [1] */
+  double gamma;         /* shear rate [1] */
+  int32_t M;            /* proxy Stokeslets on a circle about c_U [32] (Sec. 6.1) */
+  double R_proxy;       /* proxy circle radius [1.5] */
+  int32_t m_wall;       /* Gauss-Legendre collocation points per wall [24] (Sec. 6.1) */
+  double close_factor;  /* close-evaluation threshold in node spacings [10] (Sec. 6.3 remark) */
+  double tol;           /* relative residual of the solve [1e-10] */
+  int32_t max_iter;     /* GMRES iteration cap per Krylov solve [500] */
+  int32_t precision;    /* SPM_FP64 or SPM_FP32_IR for spm_solve [SPM_FP64] */
+  double inner_tol;     /* inner relative tolerance of SPM_FP32_IR [1e-5] */
+  double min_gap;       /* reject geometries with a periodic boundary gap below this [0] */
+  double rcond;         /* proxy pseudo-inverse relative cutoff [1e-14] */
+} spm_config;
+
+typedef struct {
+  int32_t status;          /* 0 or SPM_ENOCONV */
+  int32_t iterations;      /* total GMRES iterations (all inner solves for FP32_IR) */
+  int32_t fp64_matvecs;
+  int32_t fp32_matvecs;
+  int32_t n_close_pairs;   /* (target, source image) pairs given the close correction */
+  int32_t refinements;     /* outer iterations of FP32_IR (0 for FP64) */
+  double rel_residual;     /* final ||b - A sigma|| / ||b|| with the FP64 operator */
+  double seconds_setup;    /* geometry, proxy pseudo-inverse, close pairs */
+  double seconds_solve;
+  double seconds_readout;
+} spm_solve_info;
+
+typedef void* (*spm_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*spm_free_fn)(void* ptr, void* stream, void* ctx);
+
+/* Fill cfg with the defaults listed in spm_config. */
+void spm_default_config(spm_config* cfg);
+
+/* Create a handle. stream: a hipStream_t (NULL = the null stream). alloc/free may
+ * both be NULL (hipMalloc/hipFree). The config is copied. */
+int spm_create(spm_handle** h, const spm_config* cfg, void* hip_stream,
+               spm_alloc_fn alloc, spm_free_fn free_fn, void* alloc_ctx);
+void spm_destroy(spm_handle* h);
+const char* spm_last_error(const spm_handle* h);
+
+/* Lattice (Sec. 2): e1 must be (1, 0) and e2 = (s, 1); s is reduced to
+ * [-1/2, 1/2) (the nearest-integer shift of Sec. 7). center = c_U (may be NULL:
+ * origin). Host pointers. Invalidates particles set before. */
+int spm_set_lattice(spm_handle* h, const double e1_host[2], const double e2_host[2],
+                    const double center_host[2]);
+
+/* Ellipses (Sec. 2 geometry; Sec. 6 periodic trapezoid rule). Host arrays of
+ * length n: centres [2n] (x0, y0, x1, y1, ...), theta, semi-axes a and b, node
+ * counts (even, 8 <= N_i <= 512). Centres are wrapped into the cell. Builds
+ * the nodes, the proxy pseudo-inverse and the close-pair list. Returns
+ * SPM_EOVERLAP if two boundaries (any images) come within cfg.min_gap or
+ * overlap. */
+int spm_set_ellipses(spm_handle* h, int32_t n, const double* centers_host, const double* theta_host,
+                     const double* a_host, const double* b_host, const int32_t* n_nodes_host);
+
+int spm_num_nodes(const spm_handle* h, int64_t* N);
+int spm_num_particles(const spm_handle* h, int32_t* n);
+
+/* Node data (device arrays of length N each; any may be NULL). */
+int spm_get_nodes(spm_handle* h, double* x, double* y, double* nx, double* ny, double* w);
+
+/* Wrapped particle centres (host [2n]). */
+int spm_get_centers(spm_handle* h, double* centers_host);
+
+/* y = (1/2 I + K + L) sigma with the pressure pin (Sec. 5 eq. BIEPerturbed,
+ * Sec. 6.2 pin). precision: SPM_FP64 or SPM_FP32 (near sum only). sigma, out: [2N]. */
+int spm_apply(spm_handle* h, const double* sigma, double* out, int32_t precision);
+
+/* Right-hand side b = -mu gamma (n_2, n_1) (Sec. 3, u0 = (gamma x_2, 0)). out [2N]. */
+int spm_rhs(spm_handle* h, double* out);
+
+/* Solve the completed BIE by GMRES (cfg.precision selects FP64 or FP32_IR) and
+ * read out particle velocities vel [2n] (v_x0, v_y0, ...), angular velocities
+ * omega [n] and mu_eff (device scalar) - any of the three may be NULL.
+ * sigma0 (may be NULL) is the initial guess; sigma [2N] receives the density.
+ * info (host, may be NULL). Returns SPM_ENOCONV with the last iterate if GMRES
+ * does not reach cfg.tol in cfg.max_iter iterations. */
+int spm_solve(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega,
+              double* mu_eff, spm_solve_info* info_host);
+
+/* Velocities and angular velocities of the rigid particles for a given density
+ * (Sec. 3 eq. RigidBodyMotion, read at the centroids). vel [2n], omega [n]. */
+int spm_velocities(spm_handle* h, const double* sigma, double* vel, double* omega);
+
+/* Effective viscosity (Sec. 3 eq. mueff, evaluated by the particle-stresslet
+ * identity; valid whether or not particles cross the wall D). mu_eff: device scalar. */
+int spm_effective_viscosity(spm_handle* h, const double* sigma, double* mu_eff);
+
+/* Forward Euler time stepping (Sec. 7). t_inout (host): time on entry/exit;
+ * the skew follows s(t) = s(0) + gamma t from the lattice set last plus the
+ * elapsed time. centers_inout [2n], theta_inout [n] (host) hold the state;
+ * mu_eff_series_host [n_steps] receives mu_eff(t_k); infos_host [n_steps] may be NULL. */
+int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers_inout_host,
+             double* theta_inout_host, double* mu_eff_series_host, spm_solve_info* infos_host);
+
+/* ---- stage entry points (each one step of the matvec, for checking) ---- */
+
+/* Near-image traction sum T_near(x_i) = sum_j sum_{s in S9} G^t(x_i, y_j + s; n_i) w_j sigma_j,
+ * self pair skipped (Sec. 4.2 G_near; 3x3 images per particle). out [2N]. */
+int spm_near_traction(spm_handle* h, const double* sigma, double* out, int32_t precision);
+
+/* Close-evaluation correction Delta T (Sec. 6.3): barycentric traction minus the
+ * plain near-sum terms over each close (target, source image) pair. out [2N].
+ * precision selects which plain terms are subtracted (those of the FP64 or the
+ * FP32 near sum). */
+int spm_close_correction(spm_handle* h, const double* sigma, double* out, int32_t precision);
+
+/* Proxy strengths xi = Q^+ (g0 - g) (Sec. 6.2 steps 2-3). xi [2M] (device),
+ * ordered all first components then all second components. */
+int spm_proxy_strengths(spm_handle* h, const double* sigma, double* xi);
+
+/* Number of close (target, source particle, shift) triples, and the triples
+ * themselves (host arrays of length count, sorted by target, particle, shift;
+ * shift index = 3 (m + 1) + (n + 1) for the image m e1 + n e2). */
+int spm_close_pairs(spm_handle* h, int64_t* count, int32_t* target_host, int32_t* particle_host,
+                    int32_t* shift_host, int64_t capacity);
+
+/* The proxy least-squares pseudo-inverse Q^+ (host [2M * 8m], row-major). */
+int spm_proxy_pinv(spm_handle* h, double* pinv_host);
+
+/* The proxy matrix Q (host [8m * 2M], row-major), the singular values of its
+ * Jacobi SVD (host [2M], unsorted, may be NULL) and the number of Jacobi sweeps used. */
+int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps_host);
+
+/* ---- measurement ---- */
+
+/* Enable (1) or disable (0) timing of the near-sum kernel with HIP events recorded
+ * on the handle's stream around every launch; resets the counters. */
+int spm_profile(spm_handle* h, int32_t enable);
+
+/* Totals since spm_profile(h, 1): kernel 0 = FP64 near sum, 1 = FP32 near sum.
+ * total_ms: summed launch durations; launches: number of launches; pairs: node-image
+ * pair evaluations (9 N^2 per launch). Any output may be NULL. Synchronises. */
+int spm_profile_read(spm_handle* h, int32_t kernel, double* total_ms, int64_t* launches, double* pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPM_H */

@@ -1,0 +1,233 @@
+// Close evaluation of the single-layer traction (Sec. 6.3), exterior barycentric rule.
+//
+// For source curve q with nodes y_k (complex), y'_k = dy/dt, tangent tau_k, and the three
+// real densities f in {sigma_1, sigma_2, (y - c_q).sigma}: phi = f conj(tau),
+//   v+_j = sum_{k != j} (phi_k - phi_j) W_k / (y_k - y_j) + phi'_j / (i N),  W_k = y'_k / (i N),
+// phi' the spectral t-derivative (Nyquist mode zeroed) by the closed-form matrix
+//   D_jk = (1/2) (-1)^(j-k) cot((j-k) pi / N), j != k  (N even).
+// At an exterior target z:  den = -1 + sum W_k/(y_k - z),  v = sum v+_k W_k/(y_k - z) / den,
+//   v' = sum (v+_k - v) W_k/(y_k - z)^2 / den.
+// With A = i v, A' = i v':  grad S_L[f] = (Re A, -Im A), Hess S_L[f] = [[Re A', -Im A'], [-Im A', -Re A']],
+// and the traction of the Stokes single layer (the Sec. 6.3 decomposition; sign as in eq. Gt)
+//   T = H[f3] n - (x-c)_1 H[f1] n - (x-c)_2 H[f2] n + (d1 S_L[f1] + d2 S_L[f2]) n.
+// The correction for a close (target, image) pair is T minus the plain near-sum terms of
+// that image, recomputed with the near kernel's own per-pair arithmetic and precision.
+#include "spm_internal.h"
+
+namespace spm {
+
+struct cplx {
+  double re, im;
+};
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ cplx cinv(cplx a) {
+  const double d = rcp64(a.re * a.re + a.im * a.im);
+  return {a.re * d, -a.im * d};
+}
+
+// One block per particle: v+ of the three densities, written to vp[6][N].
+__global__ __launch_bounds__(256) void k_vplus(int64_t N, Geo g, const double* __restrict__ sigma,
+                                               double* __restrict__ vp) {
+  __shared__ double s_yr[kMaxNodesPerParticle], s_yi[kMaxNodesPerParticle];
+  __shared__ double s_wr[kMaxNodesPerParticle], s_wi[kMaxNodesPerParticle];
+  __shared__ double s_ph[6][kMaxNodesPerParticle];
+  __shared__ double s_d[kMaxNodesPerParticle];
+  const int q = blockIdx.x;
+  const int o = g.poff[q], n = g.pn[q];
+  const double cx = g.pcx[q], cy = g.pcy[q];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int64_t i = o + k;
+    s_yr[k] = g.x[i];
+    s_yi[k] = g.y[i];
+    // W = y' / (i n) = (y'_im - i y'_re) / n
+    s_wr[k] = g.xpy[i] / (double)n;
+    s_wi[k] = -g.xpx[i] / (double)n;
+    const double t1 = g.tx[i], t2 = g.ty[i];
+    const double sg1 = sigma[i], sg2 = sigma[N + i];
+    const double f[3] = {sg1, sg2, (g.x[i] - cx) * sg1 + (g.y[i] - cy) * sg2};
+    for (int d = 0; d < 3; ++d) {  // phi = f conj(tau)
+      s_ph[2 * d][k] = f[d] * t1;
+      s_ph[2 * d + 1][k] = -f[d] * t2;
+    }
+    // differentiation weights by distance m = k (k = 0 unused)
+    if (k > 0) {
+      const double c = cos(kPi * (double)k / (double)n) / sin(kPi * (double)k / (double)n);
+      s_d[k] = ((k & 1) ? -0.5 : 0.5) * c;
+    } else {
+      s_d[0] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    const double yjr = s_yr[j], yji = s_yi[j];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double der[6] = {0, 0, 0, 0, 0, 0};
+    const double pj[6] = {s_ph[0][j], s_ph[1][j], s_ph[2][j], s_ph[3][j], s_ph[4][j], s_ph[5][j]};
+    for (int k = 0; k < n; ++k) {
+      if (k == j) continue;
+      const cplx u = cmul({s_wr[k], s_wi[k]}, cinv({s_yr[k] - yjr, s_yi[k] - yji}));
+      const int dm = j - k >= 0 ? j - k : j - k + n;
+      const double dw = s_d[dm];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const cplx dp = {s_ph[2 * d][k] - pj[2 * d], s_ph[2 * d + 1][k] - pj[2 * d + 1]};
+        const cplx t = cmul(dp, u);
+        acc[2 * d] += t.re;
+        acc[2 * d + 1] += t.im;
+        der[2 * d] += dw * s_ph[2 * d][k];
+        der[2 * d + 1] += dw * s_ph[2 * d + 1][k];
+      }
+    }
+    const int64_t i = o + j;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      // phi' / (i n) = (phi'_im - i phi'_re) / n
+      vp[(2 * d) * N + i] = acc[2 * d] + der[2 * d + 1] / (double)n;
+      vp[(2 * d + 1) * N + i] = acc[2 * d + 1] - der[2 * d] / (double)n;
+    }
+  }
+}
+
+void launch_vplus(spm_handle* h, const double* sigma) {
+  k_vplus<<<h->geo.No, 256, 0, h->stream>>>(h->geo.N, h->geo, sigma, h->cl.vp);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// One 64-lane wave per close target; lanes stride over the source nodes.
+template <int PREC>
+__global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets, Geo g,
+                                                     const int32_t* __restrict__ tlist, const int32_t* __restrict__ row,
+                                                     const int32_t* __restrict__ cq, const int32_t* __restrict__ cs,
+                                                     Shifts<double> sh, Shifts<float> shf,
+                                                     const double* __restrict__ vp, const double* __restrict__ f1,
+                                                     const double* __restrict__ f2, const float* __restrict__ f1f,
+                                                     const float* __restrict__ f2f, double* __restrict__ T) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= ntargets) return;
+  const int i = tlist[wave];
+  const double xi = g.x[i], yi = g.y[i], nxi = g.nx[i], nyi = g.ny[i];
+  double dT1 = 0, dT2 = 0;
+  for (int e = row[i]; e < row[i + 1]; ++e) {
+    const int q = cq[e], s = cs[e];
+    const int o = g.poff[q], n = g.pn[q];
+    const double zr = xi - sh.x[s], zi = yi - sh.y[s];  // target shifted instead of the image
+    // pass 1: den and v for the three densities; plain near-sum terms of this image
+    double dr = 0, di = 0, v[6] = {0, 0, 0, 0, 0, 0};
+    double p1 = 0, p2 = 0;
+    float p1f = 0.f, p2f = 0.f;
+    for (int k = lane; k < n; k += 64) {
+      const int64_t kk = o + k;
+      const cplx W = {g.xpy[kk] / (double)n, -g.xpx[kk] / (double)n};
+      const cplx u = cmul(W, cinv({g.x[kk] - zr, g.y[kk] - zi}));
+      dr += u.re;
+      di += u.im;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const cplx t = cmul({vp[(2 * d) * N + kk], vp[(2 * d + 1) * N + kk]}, u);
+        v[2 * d] += t.re;
+        v[2 * d + 1] += t.im;
+      }
+      if (PREC == SPM_FP64) {
+        const double dx = xi - g.x[kk], dy = yi - g.y[kk];
+        double a1 = 0.0, a2 = 0.0;
+        gt_pair(dx - sh.x[s], dy - sh.y[s], nxi, nyi, f1[kk], f2[kk], a1, a2);
+        p1 += a1;
+        p2 += a2;
+      } else {
+        const float dx = g.xf[i] - g.xf[kk], dy = g.yf[i] - g.yf[kk];
+        float a1 = 0.f, a2 = 0.f;
+        gt_pair(dx - shf.x[s], dy - shf.y[s], g.nxf[i], g.nyf[i], f1f[kk], f2f[kk], a1, a2);
+        p1 += (double)a1;
+        p2 += (double)a2;
+      }
+    }
+    (void)p1f;
+    (void)p2f;
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+#pragma unroll
+    for (int d = 0; d < 6; ++d) v[d] = wave_sum(v[d]);
+    p1 = wave_sum(p1);
+    p2 = wave_sum(p2);
+    const cplx iden = cinv({dr - 1.0, di});
+    cplx vv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vv[d] = cmul({v[2 * d], v[2 * d + 1]}, iden);
+    // pass 2: v' = sum (v+_k - v) W_k / (y_k - z)^2 / den
+    double w[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = lane; k < n; k += 64) {
+      const int64_t kk = o + k;
+      const cplx W = {g.xpy[kk] / (double)n, -g.xpx[kk] / (double)n};
+      const cplx id = cinv({g.x[kk] - zr, g.y[kk] - zi});
+      const cplx u2 = cmul(cmul(W, id), id);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const cplx t = cmul({vp[(2 * d) * N + kk] - vv[d].re, vp[(2 * d + 1) * N + kk] - vv[d].im}, u2);
+        w[2 * d] += t.re;
+        w[2 * d + 1] += t.im;
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) w[d] = wave_sum(w[d]);
+    // A = i v, A' = i v'
+    double g1[3], g2[3], h11[3], h12[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const cplx vd = cmul({w[2 * d], w[2 * d + 1]}, iden);
+      const cplx A = {-vv[d].im, vv[d].re};
+      const cplx Ap = {-vd.im, vd.re};
+      g1[d] = A.re;
+      g2[d] = -A.im;
+      h11[d] = Ap.re;
+      h12[d] = -Ap.im;
+    }
+    const double rx = zr - g.pcx[q], ry = zi - g.pcy[q];
+    double Hn1[3], Hn2[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      Hn1[d] = h11[d] * nxi + h12[d] * nyi;
+      Hn2[d] = h12[d] * nxi - h11[d] * nyi;
+    }
+    const double dv = g1[0] + g2[1];
+    const double Tb1 = Hn1[2] - rx * Hn1[0] - ry * Hn1[1] + dv * nxi;
+    const double Tb2 = Hn2[2] - rx * Hn2[0] - ry * Hn2[1] + dv * nyi;
+    dT1 += Tb1 - (-(1.0 / kPi)) * p1;
+    dT2 += Tb2 - (-(1.0 / kPi)) * p2;
+  }
+  if (lane == 0) {
+    T[i] += dT1;
+    T[N + i] += dT2;
+  }
+}
+
+template <typename R>
+static Shifts<R> shifts_of(spm_handle* h) {
+  Shifts<R> sh;
+  for (int m = -1; m <= 1; ++m)
+    for (int n = -1; n <= 1; ++n) {
+      const int s = 3 * (m + 1) + (n + 1);
+      sh.x[s] = (R)((double)m * h->e1[0] + (double)n * h->e2[0]);
+      sh.y[s] = (R)((double)m * h->e1[1] + (double)n * h->e2[1]);
+    }
+  return sh;
+}
+
+void launch_close_apply(spm_handle* h, const double* sigma, double* T, int precision) {
+  (void)sigma;
+  const int nt = h->cl.ntargets;
+  if (nt == 0) return;
+  const int waves_per_block = 4;
+  const unsigned blocks = (unsigned)((nt + waves_per_block - 1) / waves_per_block);
+  if (precision == SPM_FP64)
+    k_close_apply<SPM_FP64><<<blocks, 256, 0, h->stream>>>(
+        h->geo.N, nt, h->geo, h->cl.tlist, h->cl.row, h->cl.q, h->cl.s, shifts_of<double>(h), shifts_of<float>(h),
+        h->cl.vp, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f, T);
+  else
+    k_close_apply<SPM_FP32><<<blocks, 256, 0, h->stream>>>(
+        h->geo.N, nt, h->geo, h->cl.tlist, h->cl.row, h->cl.q, h->cl.s, shifts_of<double>(h), shifts_of<float>(h),
+        h->cl.vp, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f, T);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace spm

@@ -1,0 +1,258 @@
+// Geometry (Sec. 2, Sec. 6 trapezoid rule), RHS (Sec. 3) and close-pair lists (Sec. 6.3).
+#include "spm_internal.h"
+
+namespace spm {
+
+// One thread per node: ellipse x(t) = c + R(theta)(a cos t, b sin t), t = 2 pi k / N_p.
+// w = (2 pi / N_p)|x'|, tau = x'/|x'|, n = (tau_2, -tau_1), kappa = a b / |x'|^3.
+__global__ void k_geometry(int64_t N, const int32_t* __restrict__ pid, const int32_t* __restrict__ poff,
+                           const int32_t* __restrict__ pn, const double* __restrict__ pcx,
+                           const double* __restrict__ pcy, const double* __restrict__ pth,
+                           const double* __restrict__ pa, const double* __restrict__ pb, Geo g) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int p = pid[i];
+  const int k = (int)(i - poff[p]);
+  const int n = pn[p];
+  const double t = 2.0 * kPi * (double)k / (double)n;
+  double st, ct, sth, cth;
+  sincos(t, &st, &ct);
+  sincos(pth[p], &sth, &cth);
+  const double a = pa[p], b = pb[p];
+  const double px = a * ct, py = b * st;
+  const double dx = -a * st, dy = b * ct;
+  const double x = pcx[p] + (cth * px - sth * py);
+  const double y = pcy[p] + (sth * px + cth * py);
+  const double xpx = cth * dx - sth * dy;
+  const double xpy = sth * dx + cth * dy;
+  const double sp = sqrt(xpx * xpx + xpy * xpy);
+  const double tx = xpx / sp, ty = xpy / sp;
+  g.x[i] = x;
+  g.y[i] = y;
+  g.xpx[i] = xpx;
+  g.xpy[i] = xpy;
+  g.tx[i] = tx;
+  g.ty[i] = ty;
+  g.nx[i] = ty;
+  g.ny[i] = -tx;
+  g.w[i] = 2.0 * kPi * sp / (double)n;
+  g.kap[i] = a * b / (sp * sp * sp);
+  g.xf[i] = (float)x;
+  g.yf[i] = (float)y;
+  g.nxf[i] = (float)ty;
+  g.nyf[i] = (float)(-tx);
+}
+
+// Perimeter of every particle (sum of its trapezoid weights), one block per particle.
+__global__ void k_perimeter(const int32_t* __restrict__ poff, const double* __restrict__ w, double* per) {
+  __shared__ double sc[16];
+  const int p = blockIdx.x;
+  double s = 0.0;
+  for (int k = poff[p] + threadIdx.x; k < poff[p + 1]; k += blockDim.x) s += w[k];
+  s = block_sum(s, sc);
+  if (threadIdx.x == 0) per[p] = s;
+}
+
+void launch_geometry(spm_handle* h) {
+  Geo& g = h->geo;
+  const int bs = 256;
+  k_geometry<<<(unsigned)((g.N + bs - 1) / bs), bs, 0, h->stream>>>(g.N, g.pid, g.poff, g.pn, g.pcx, g.pcy,
+                                                                    g.pth, g.pa, g.pb, g);
+  SPM_HIP_CHECK(hipGetLastError());
+  k_perimeter<<<g.No, 256, 0, h->stream>>>(g.poff, g.w, g.pper);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// b = -mu gamma (n_2, n_1): minus the traction of the background shear u0 = (gamma x_2, 0), p0 = 0.
+__global__ void k_rhs(int64_t N, const double* __restrict__ nx, const double* __restrict__ ny, double c,
+                      double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  out[i] = c * ny[i];
+  out[N + i] = c * nx[i];
+}
+
+void launch_rhs(spm_handle* h, double* out) {
+  const int bs = 256;
+  const int64_t N = h->geo.N;
+  k_rhs<<<(unsigned)((N + bs - 1) / bs), bs, 0, h->stream>>>(N, h->geo.nx, h->geo.ny,
+                                                             -h->cfg.mu * h->cfg.gamma, out);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// ----------------------------------------------------------------------------
+// Close pairs: target x_i on particle p, source image Gamma_q + s with (q, s) != (p, 0),
+// close when min_k |x_i - (y_k + s)| < factor * h_q, h_q = perimeter_q / N_q.
+// Pass 1 counts per target (and records the smallest node distance to any other
+// particle image and whether the node lies inside one: the overlap check);
+// a scan makes row pointers; pass 2 fills (q, s) in ascending (q, s) order.
+// ----------------------------------------------------------------------------
+template <bool FILL>
+__global__ void k_close_pass(int64_t N, int32_t No, Geo g, Shifts<double> sh, double factor,
+                             const int32_t* __restrict__ row, int32_t* __restrict__ count,
+                             int32_t* __restrict__ outq, int32_t* __restrict__ outs,
+                             double* __restrict__ dmin, int32_t* __restrict__ inside) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double xi = g.x[i], yi = g.y[i];
+  const int pi = g.pid[i];
+  int cnt = 0;
+  int64_t pos = FILL ? row[i] : 0;
+  double best = 1e300;
+  int ins = 0;
+  for (int q = 0; q < No; ++q) {
+    const double lim = factor * g.pper[q] / (double)g.pn[q];
+    const double reach = g.pa[q] + (lim > 0.0 ? lim : 0.0);
+    for (int s = 0; s < kShifts; ++s) {
+      if (q == pi && s == kZeroShift) continue;
+      const double cx = g.pcx[q] + sh.x[s], cy = g.pcy[q] + sh.y[s];
+      const double ddx = xi - cx, ddy = yi - cy;
+      if (ddx * ddx + ddy * ddy >= reach * reach) continue;
+      // inside test against the ellipse (body frame)
+      double sth, cth;
+      sincos(g.pth[q], &sth, &cth);
+      const double u = (cth * ddx + sth * ddy) / g.pa[q];
+      const double v = (-sth * ddx + cth * ddy) / g.pb[q];
+      if (u * u + v * v < 1.0) ins = 1;
+      double m2 = 1e300;
+      for (int k = g.poff[q]; k < g.poff[q + 1]; ++k) {
+        const double rx = xi - (g.x[k] + sh.x[s]);
+        const double ry = yi - (g.y[k] + sh.y[s]);
+        const double d2 = rx * rx + ry * ry;
+        m2 = d2 < m2 ? d2 : m2;
+      }
+      best = m2 < best ? m2 : best;
+      if (lim > 0.0 && m2 < lim * lim) {
+        if (FILL) {
+          outq[pos] = q;
+          outs[pos] = s;
+          ++pos;
+        }
+        ++cnt;
+      }
+    }
+  }
+  if (!FILL) {
+    count[i] = cnt;
+    dmin[i] = sqrt(best);
+    inside[i] = ins;
+  }
+}
+
+// Exclusive scan of count[N] into row[N+1] by one block; also collects the
+// targets with a nonempty row. scal[0] = total pairs, scal[1] = number of targets.
+__global__ void k_scan(int64_t N, const int32_t* __restrict__ count, int32_t* __restrict__ row,
+                       int32_t* __restrict__ tlist, int32_t* __restrict__ totals) {
+  __shared__ int32_t part[1024];
+  __shared__ int32_t tpart[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int64_t per = (N + nt - 1) / nt;
+  const int64_t lo = t * per, hi = (lo + per < N) ? lo + per : N;
+  int32_t s = 0, c = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    s += count[i];
+    c += count[i] > 0;
+  }
+  part[t] = s;
+  tpart[t] = c;
+  __syncthreads();
+  if (t == 0) {
+    int32_t acc = 0, acc2 = 0;
+    for (int k = 0; k < nt; ++k) {
+      const int32_t v = part[k], v2 = tpart[k];
+      part[k] = acc;
+      tpart[k] = acc2;
+      acc += v;
+      acc2 += v2;
+    }
+    totals[0] = acc;
+    totals[1] = acc2;
+    row[N] = acc;
+  }
+  __syncthreads();
+  int32_t acc = part[t], acc2 = tpart[t];
+  for (int64_t i = lo; i < hi; ++i) {
+    row[i] = acc;
+    acc += count[i];
+    if (count[i] > 0) tlist[acc2++] = (int32_t)i;
+  }
+}
+
+static Shifts<double> shifts64(spm_handle* h) {
+  Shifts<double> sh;
+  for (int m = -1; m <= 1; ++m)
+    for (int n = -1; n <= 1; ++n) {
+      const int s = 3 * (m + 1) + (n + 1);
+      sh.x[s] = (double)m * h->e1[0] + (double)n * h->e2[0];
+      sh.y[s] = (double)m * h->e1[1] + (double)n * h->e2[1];
+    }
+  return sh;
+}
+
+void launch_close_count(spm_handle* h) {
+  const int bs = 128;
+  const int64_t N = h->geo.N;
+  k_close_pass<false><<<(unsigned)((N + bs - 1) / bs), bs, 0, h->stream>>>(
+      N, h->geo.No, h->geo, shifts64(h), h->cfg.close_factor, nullptr, h->cl.count, nullptr, nullptr,
+      h->cl.dmin, h->cl.inside);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+void launch_close_scan(spm_handle* h, int32_t* total_host, int32_t* ntargets_host) {
+  int32_t* tot = reinterpret_cast<int32_t*>(h->wk.scal);
+  k_scan<<<1, 1024, 0, h->stream>>>(h->geo.N, h->cl.count, h->cl.row, h->cl.tlist, tot);
+  SPM_HIP_CHECK(hipGetLastError());
+  int32_t hv[2];
+  SPM_HIP_CHECK(hipMemcpyAsync(hv, tot, sizeof(hv), hipMemcpyDeviceToHost, h->stream));
+  SPM_HIP_CHECK(hipStreamSynchronize(h->stream));
+  *total_host = hv[0];
+  *ntargets_host = hv[1];
+}
+
+void launch_close_fill(spm_handle* h) {
+  const int bs = 128;
+  const int64_t N = h->geo.N;
+  k_close_pass<true><<<(unsigned)((N + bs - 1) / bs), bs, 0, h->stream>>>(
+      N, h->geo.No, h->geo, shifts64(h), h->cfg.close_factor, h->cl.row, nullptr, h->cl.q, h->cl.s, nullptr,
+      nullptr);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// min over nodes of dmin, max of inside, one block
+__global__ void k_gap_reduce(int64_t N, const double* __restrict__ dmin, const int32_t* __restrict__ inside,
+                             double* out) {
+  __shared__ double sm[1024];
+  __shared__ int si[1024];
+  double b = 1e300;
+  int in = 0;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) {
+    b = dmin[i] < b ? dmin[i] : b;
+    in |= inside[i];
+  }
+  sm[threadIdx.x] = b;
+  si[threadIdx.x] = in;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bb = 1e300;
+    int ii = 0;
+    for (int k = 0; k < (int)blockDim.x; ++k) {
+      bb = sm[k] < bb ? sm[k] : bb;
+      ii |= si[k];
+    }
+    out[0] = bb;
+    out[1] = (double)ii;
+  }
+}
+
+void launch_gap(spm_handle* h, double* gap_host, int32_t* overlap_host) {
+  double* o = h->wk.scal + 4;
+  k_gap_reduce<<<1, 1024, 0, h->stream>>>(h->geo.N, h->cl.dmin, h->cl.inside, o);
+  SPM_HIP_CHECK(hipGetLastError());
+  double hv[2];
+  SPM_HIP_CHECK(hipMemcpyAsync(hv, o, sizeof(hv), hipMemcpyDeviceToHost, h->stream));
+  SPM_HIP_CHECK(hipStreamSynchronize(h->stream));
+  *gap_host = hv[0];
+  *overlap_host = hv[1] != 0.0;
+}
+
+}  // namespace spm

@@ -1,0 +1,159 @@
+// Operator assembly and readouts.
+//
+// prep:     f = w sigma (FP64 and FP32 copies) and per-particle moments
+//           F_q = sum w sigma, tau_q = sum w (x - c)^perp . sigma, stresslet_q (Sec. 5 operator L).
+// assemble: y = sigma/2 + T + alpha n + L sigma,  alpha = -(T(x0) . n0)   (Sec. 5 eq. BIEPerturbed;
+//           Sec. 6.2 pressure pin with x0 the first node of the first particle),
+//           L_q sigma (x) = F_q + (x - c_q)^perp tau_q.
+// readout:  v_q = u0(c_q) + u_near(c_q) + u_corr(c_q) - u_corr(c_U);
+//           omega_q = (vort_near(c_q) + vort_corr(c_q))/2 - gamma/2   (Sec. 3 eq. RigidBodyMotion).
+//           mu_eff = mu - sum_q stresslet_q / (2 gamma |U|)           (Sec. 3 eq. mueff via the
+//           cell force balance: the traction on a particle is -sigma).
+#include "spm_internal.h"
+
+namespace spm {
+
+__global__ __launch_bounds__(256) void k_prep(int64_t N, Geo g, const double* __restrict__ sigma,
+                                              double* __restrict__ f1, double* __restrict__ f2,
+                                              float* __restrict__ f1f, float* __restrict__ f2f,
+                                              double* __restrict__ pF) {
+  __shared__ double sc[16];
+  const int q = blockIdx.x;
+  const double cx = g.pcx[q], cy = g.pcy[q];
+  double F1 = 0, F2 = 0, tq = 0, st = 0;
+  for (int64_t i = g.poff[q] + threadIdx.x; i < g.poff[q + 1]; i += blockDim.x) {
+    const double w = g.w[i], s1 = sigma[i], s2 = sigma[N + i];
+    const double a = w * s1, b = w * s2;
+    f1[i] = a;
+    f2[i] = b;
+    f1f[i] = (float)a;
+    f2f[i] = (float)b;
+    const double rx = g.x[i] - cx, ry = g.y[i] - cy;
+    F1 += a;
+    F2 += b;
+    tq += -ry * a + rx * b;
+    st += rx * b + ry * a;
+  }
+  F1 = block_sum(F1, sc);
+  F2 = block_sum(F2, sc);
+  tq = block_sum(tq, sc);
+  st = block_sum(st, sc);
+  if (threadIdx.x == 0) {
+    pF[4 * q + 0] = F1;
+    pF[4 * q + 1] = F2;
+    pF[4 * q + 2] = tq;
+    pF[4 * q + 3] = st;
+  }
+}
+
+void launch_prep(spm_handle* h, const double* sigma) {
+  k_prep<<<h->geo.No, 256, 0, h->stream>>>(h->geo.N, h->geo, sigma, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f,
+                                           h->wk.pF);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+__global__ void k_assemble(int64_t N, Geo g, const double* __restrict__ sigma, const double* __restrict__ T,
+                           const double* __restrict__ pF, double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double alpha = -(T[0] * g.nx[0] + T[N] * g.ny[0]);
+  const int q = g.pid[i];
+  const double rx = g.x[i] - g.pcx[q], ry = g.y[i] - g.pcy[q];
+  const double F1 = pF[4 * q + 0], F2 = pF[4 * q + 1], tq = pF[4 * q + 2];
+  out[i] = 0.5 * sigma[i] + T[i] + alpha * g.nx[i] + F1 - ry * tq;
+  out[N + i] = 0.5 * sigma[N + i] + T[N + i] + alpha * g.ny[i] + F2 + rx * tq;
+}
+
+void launch_assemble(spm_handle* h, const double* sigma, double* out) {
+  const int64_t N = h->geo.N;
+  k_assemble<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, h->geo, sigma, h->wk.T, h->wk.pF, out);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// Velocity and vorticity at the particle centres: one block per particle, all nodes x 9 images.
+__global__ __launch_bounds__(256) void k_velocities(int64_t N, Geo g, Shifts<double> sh, const double* __restrict__ f1,
+                                                    const double* __restrict__ f2, int M, const double* __restrict__ px,
+                                                    const double* __restrict__ py, const double* __restrict__ xi,
+                                                    double cUx, double cUy, double mu, double gamma,
+                                                    double* __restrict__ vel, double* __restrict__ omega) {
+  __shared__ double sc[16];
+  const int q = blockIdx.x;
+  const double cx = g.pcx[q], cy = g.pcy[q];
+  const double k4 = 1.0 / (4.0 * kPi * mu), k2 = -1.0 / (2.0 * kPi * mu);
+  double u1 = 0, u2 = 0, vo = 0;
+  for (int64_t j = threadIdx.x; j < N; j += blockDim.x) {
+    const double yx = g.x[j], yy = g.y[j], a = f1[j], b = f2[j];
+    for (int s = 0; s < kShifts; ++s) {
+      const double rx = cx - (yx + sh.x[s]), ry = cy - (yy + sh.y[s]);
+      const double r2 = rx * rx + ry * ry;
+      const double ir2 = rcp64(r2);
+      const double lg = -0.5 * log(r2);
+      const double rf = (rx * a + ry * b) * ir2;
+      u1 += k4 * (lg * a + rx * rf);
+      u2 += k4 * (lg * b + ry * rf);
+      vo += k2 * (rx * b - ry * a) * ir2;
+    }
+  }
+  u1 = block_sum(u1, sc);
+  u2 = block_sum(u2, sc);
+  vo = block_sum(vo, sc);
+  if (threadIdx.x == 0) {
+    double c1 = 0, c2 = 0, z1 = 0, z2 = 0, cv = 0;
+    for (int p = 0; p < M; ++p) {
+      const double a = xi[p], b = xi[M + p];
+      {
+        const double rx = cx - px[p], ry = cy - py[p];
+        const double r2 = rx * rx + ry * ry;
+        const double lg = -0.5 * log(r2);
+        const double rf = (rx * a + ry * b) / r2;
+        c1 += k4 * (lg * a + rx * rf);
+        c2 += k4 * (lg * b + ry * rf);
+        cv += k2 * (rx * b - ry * a) / r2;
+      }
+      {
+        const double rx = cUx - px[p], ry = cUy - py[p];
+        const double r2 = rx * rx + ry * ry;
+        const double lg = -0.5 * log(r2);
+        const double rf = (rx * a + ry * b) / r2;
+        z1 += k4 * (lg * a + rx * rf);
+        z2 += k4 * (lg * b + ry * rf);
+      }
+    }
+    if (vel) {
+      vel[2 * q] = gamma * cy + u1 + (c1 - z1);
+      vel[2 * q + 1] = u2 + (c2 - z2);
+    }
+    if (omega) omega[q] = 0.5 * (vo + cv) - 0.5 * gamma;
+  }
+}
+
+void launch_velocities(spm_handle* h, double* vel, double* omega) {
+  Shifts<double> sh;
+  for (int m = -1; m <= 1; ++m)
+    for (int n = -1; n <= 1; ++n) {
+      const int s = 3 * (m + 1) + (n + 1);
+      sh.x[s] = (double)m * h->e1[0] + (double)n * h->e2[0];
+      sh.y[s] = (double)m * h->e1[1] + (double)n * h->e2[1];
+    }
+  k_velocities<<<h->geo.No, 256, 0, h->stream>>>(h->geo.N, h->geo, sh, h->wk.f1, h->wk.f2, h->per.M, h->per.px,
+                                                 h->per.py, h->wk.xi, h->cU[0], h->cU[1], h->cfg.mu, h->cfg.gamma,
+                                                 vel, omega);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+__global__ void k_mu_eff(int No, const double* __restrict__ pF, double mu, double gamma, double area,
+                         double* __restrict__ out) {
+  __shared__ double sc[16];
+  double s = 0;
+  for (int q = threadIdx.x; q < No; q += blockDim.x) s += pF[4 * q + 3];
+  s = block_sum(s, sc);
+  if (threadIdx.x == 0) out[0] = mu - s / (2.0 * gamma * area);
+}
+
+void launch_mu_eff(spm_handle* h, double* mu_eff) {
+  const double area = fabs(h->e1[0] * h->e2[1] - h->e1[1] * h->e2[0]);
+  k_mu_eff<<<1, 256, 0, h->stream>>>(h->geo.No, h->wk.pF, h->cfg.mu, h->cfg.gamma, area, mu_eff);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace spm

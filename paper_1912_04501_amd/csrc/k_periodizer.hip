@@ -1,0 +1,374 @@
+// Periodizing correction by proxy Stokeslets (Sec. 4.2; Sec. 6.1 MFS; Sec. 6.2 four steps).
+//
+// Walls: L(t) = c_U - e1/2 + t e2, D(t) = c_U - e2/2 + t e1 at m Gauss-Legendre points;
+// R = L + e1, U = D + e2; normals n_L = (e2_2, -e2_1)/|e2|, n_D = (0, 1) on both walls of a pair.
+// Discrepancy rows (length 8m): [u_R-u_L (2m); T_R-T_L (2m); u_U-u_D (2m); T_U-T_D (2m)],
+// each block ordered first components then second components.
+// Jump target: g0 = [0; -F/(2|e2|); 0; -F/(2|e1|)], F = sum_j f_j (net force balance of the cell).
+// xi = Q^+ (g0 - g): [xi_1 (M); xi_2 (M)].
+#include "spm_internal.h"
+
+namespace spm {
+
+// Stokeslet velocity G(r) f (eq. Gv) and traction G^t(r; n) f (eq. Gt), r = x - y.
+__device__ __forceinline__ void stokeslet_uv(double rx, double ry, double f1, double f2, double inv4pimu,
+                                             double& u1, double& u2) {
+  const double r2 = rx * rx + ry * ry;
+  const double ir2 = rcp64(r2);
+  const double lg = -0.5 * log(r2);
+  const double rf = (rx * f1 + ry * f2) * ir2;
+  u1 += inv4pimu * (lg * f1 + rx * rf);
+  u2 += inv4pimu * (lg * f2 + ry * rf);
+}
+
+__device__ __forceinline__ void traction_uv(double rx, double ry, double nx, double ny, double f1, double f2,
+                                            double& t1, double& t2) {
+  const double r2 = rx * rx + ry * ry;
+  const double ir2 = rcp64(r2);
+  const double c = -(1.0 / kPi) * (rx * nx + ry * ny) * (rx * f1 + ry * f2) * ir2 * ir2;
+  t1 += c * rx;
+  t2 += c * ry;
+}
+
+struct Lat {
+  double e1x, e1y, e2x, e2y;
+  double nLx, nLy, nDx, nDy;
+  double inv4pimu;
+  int m, M;
+};
+
+static Lat lattice_args(spm_handle* h) {
+  Lat L;
+  L.e1x = h->e1[0];
+  L.e1y = h->e1[1];
+  L.e2x = h->e2[0];
+  L.e2y = h->e2[1];
+  L.nLx = h->per.nL[0];
+  L.nLy = h->per.nL[1];
+  L.nDx = h->per.nD[0];
+  L.nDy = h->per.nD[1];
+  L.inv4pimu = 1.0 / (4.0 * kPi * h->cfg.mu);
+  L.m = h->per.m;
+  L.M = h->per.M;
+  return L;
+}
+
+// Q[row][col], row in [0, 8m), col = comp * M + p: the wall jumps of the field of a unit
+// force e_comp at proxy p.
+__global__ void k_build_Q(Lat L, const double* __restrict__ wx, const double* __restrict__ wy,
+                          const double* __restrict__ px, const double* __restrict__ py, double* __restrict__ Q) {
+  const int m = L.m, M = L.M;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 8 * m * 2 * M) return;
+  const int row = idx / (2 * M), col = idx % (2 * M);
+  const int comp = col / M, p = col % M;
+  const int blk = row / m, q = row % m;       // blk: 0,1 u on L; 2,3 T on L; 4,5 u on D; 6,7 T on D
+  const bool onD = blk >= 4;
+  const int kind = (blk % 4) / 2;              // 0 velocity, 1 traction
+  const int outc = blk % 2;                    // output component
+  const double x0 = wx[onD ? m + q : q], y0 = wy[onD ? m + q : q];
+  const double sx = onD ? L.e2x : L.e1x, sy = onD ? L.e2y : L.e1y;
+  const double nx = onD ? L.nDx : L.nLx, ny = onD ? L.nDy : L.nLy;
+  const double f1 = comp == 0 ? 1.0 : 0.0, f2 = comp == 1 ? 1.0 : 0.0;
+  double a1 = 0, a2 = 0, b1 = 0, b2 = 0;
+  if (kind == 0) {
+    stokeslet_uv(x0 + sx - px[p], y0 + sy - py[p], f1, f2, L.inv4pimu, a1, a2);
+    stokeslet_uv(x0 - px[p], y0 - py[p], f1, f2, L.inv4pimu, b1, b2);
+  } else {
+    traction_uv(x0 + sx - px[p], y0 + sy - py[p], nx, ny, f1, f2, a1, a2);
+    traction_uv(x0 - px[p], y0 - py[p], nx, ny, f1, f2, b1, b2);
+  }
+  Q[idx] = outc == 0 ? (a1 - b1) : (a2 - b2);
+}
+
+void launch_build_Q(spm_handle* h) {
+  const Lat L = lattice_args(h);
+  const int n = 8 * L.m * 2 * L.M;
+  k_build_Q<<<(n + 255) / 256, 256, 0, h->stream>>>(L, h->per.wx, h->per.wy, h->per.px, h->per.py, h->per.Q);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// ----------------------------------------------------------------------------
+// Pseudo-inverse of Q by one-sided (Hestenes) Jacobi SVD in one workgroup.
+// A = Q (rows x ncol, column-major copy) is orthogonalised column pair by column pair,
+// A V = U S; round-robin pairing gives ncol/2 disjoint pairs per round, one group of
+// G = blockDim/(ncol/2) lanes per pair. The three smallest singular triplets (the
+// gauge modes of the empty-box problem: constant velocity and pressure) and any
+// singular value below rcond * s_max are dropped:  Q^+ = sum_k v_k u_k^T / s_k.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_jacobi(int rows, int ncol, const double* __restrict__ Q,
+                                                 double* __restrict__ A, double* __restrict__ V,
+                                                 double* __restrict__ S, int max_sweeps) {
+  __shared__ int perm[1024];
+  __shared__ double offmax[1024];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int k = tid; k < rows * ncol; k += nt) {
+    const int r = k / ncol, c = k % ncol;
+    A[c * rows + r] = Q[k];
+  }
+  for (int k = tid; k < ncol * ncol; k += nt) V[k] = (k / ncol == k % ncol) ? 1.0 : 0.0;
+  for (int k = tid; k < ncol; k += nt) perm[k] = k;
+  __syncthreads();
+  const int npair = ncol / 2;
+  const int G = nt / npair;  // lanes per pair (power of two, <= 64)
+  const int pair = tid / G, gl = tid % G;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    double local_off = 0.0;
+    for (int round = 0; round < ncol - 1; ++round) {
+      if (pair < npair) {
+        const int cp = perm[pair], cq = perm[ncol - 1 - pair];
+        const int p = cp < cq ? cp : cq, q = cp < cq ? cq : cp;
+        double al = 0, be = 0, ga = 0;
+        for (int r = gl; r < rows; r += G) {
+          const double ap = A[p * rows + r], aq = A[q * rows + r];
+          al += ap * ap;
+          be += aq * aq;
+          ga += ap * aq;
+        }
+        for (int o = G / 2; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, G);
+          be += __shfl_xor(be, o, G);
+          ga += __shfl_xor(ga, o, G);
+        }
+        const double nrm = sqrt(al * be);
+        if (nrm > 0.0 && fabs(ga) > 1e-15 * nrm) {
+          const double rel = fabs(ga) / nrm;
+          local_off = rel > local_off ? rel : local_off;
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+          for (int r = gl; r < rows; r += G) {
+            const double ap = A[p * rows + r], aq = A[q * rows + r];
+            A[p * rows + r] = c * ap - s * aq;
+            A[q * rows + r] = s * ap + c * aq;
+          }
+          for (int r = gl; r < ncol; r += G) {
+            const double vp = V[p * ncol + r], vq = V[q * ncol + r];
+            V[p * ncol + r] = c * vp - s * vq;
+            V[q * ncol + r] = s * vp + c * vq;
+          }
+        }
+      }
+      __syncthreads();
+      // circle method: keep perm[0], rotate the rest by one
+      if (tid == 0) {
+        const int last = perm[ncol - 1];
+        for (int k = ncol - 1; k > 1; --k) perm[k] = perm[k - 1];
+        perm[1] = last;
+      }
+      __syncthreads();
+    }
+    offmax[tid] = local_off;
+    __syncthreads();
+    if (tid == 0) {
+      double mx = 0;
+      for (int k = 0; k < nt; ++k) mx = offmax[k] > mx ? offmax[k] : mx;
+      offmax[0] = mx;
+    }
+    __syncthreads();
+    const bool done = offmax[0] <= 1e-15;
+    __syncthreads();
+    if (done) break;
+  }
+  for (int c = tid; c < ncol; c += nt) {
+    double s = 0;
+    for (int r = 0; r < rows; ++r) s += A[c * rows + r] * A[c * rows + r];
+    S[c] = sqrt(s);
+  }
+  if (tid == 0) S[ncol] = (double)sweep;
+}
+
+// Qp[i][r] = sum_{k kept} V[k][i] A[k][r] / s_k^2  (u_k = A_k / s_k)
+__global__ void k_pinv_assemble(int rows, int ncol, const double* __restrict__ A, const double* __restrict__ V,
+                                const double* __restrict__ S, double rcond, int n_gauge, double* __restrict__ Qp) {
+  __shared__ double w[1024];
+  if (threadIdx.x == 0) {
+    double smax = 0;
+    for (int k = 0; k < ncol; ++k) smax = S[k] > smax ? S[k] : smax;
+    for (int k = 0; k < ncol; ++k) w[k] = (S[k] > rcond * smax) ? 1.0 / (S[k] * S[k]) : 0.0;
+    // drop the n_gauge smallest
+    for (int g = 0; g < n_gauge; ++g) {
+      int arg = -1;
+      double best = 1e300;
+      for (int k = 0; k < ncol; ++k)
+        if (w[k] != 0.0 && S[k] < best) {
+          best = S[k];
+          arg = k;
+        }
+      if (arg >= 0) w[arg] = 0.0;
+    }
+  }
+  __syncthreads();
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncol * rows) return;
+  const int i = idx / rows, r = idx % rows;
+  double s = 0;
+  for (int k = 0; k < ncol; ++k)
+    if (w[k] != 0.0) s += V[k * ncol + i] * A[k * rows + r] * w[k];
+  Qp[idx] = s;
+}
+
+void launch_pinv(spm_handle* h) {
+  const int rows = 8 * h->per.m, ncol = 2 * h->per.M;
+  const int npair = ncol / 2;
+  int G = 1;
+  while (G * 2 * npair <= 1024 && G < 64) G *= 2;
+  const int nt = G * npair;
+  k_jacobi<<<1, nt, 0, h->stream>>>(rows, ncol, h->per.Q, h->per.svd_a, h->per.svd_v, h->per.svd_s, 60);
+  SPM_HIP_CHECK(hipGetLastError());
+  const int n = rows * ncol;
+  // one block computes the weights; every block recomputes them (cheap, ncol <= 1024)
+  k_pinv_assemble<<<(n + 255) / 256, 256, 0, h->stream>>>(rows, ncol, h->per.svd_a, h->per.svd_v, h->per.svd_s,
+                                                          h->cfg.rcond, 3, h->per.Qp);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// ----------------------------------------------------------------------------
+// Wall discrepancy (step 2), telescoped: at a point x_L of L,
+//   u_near(x_L+e1) - u_near(x_L) = sum_j sum_{n=-1..1} [G(x_L, y_j - 2e1 + n e2) - G(x_L, y_j + e1 + n e2)] f_j
+// and on D with the roles of e1, e2 exchanged; the same with G^t(.; n_wall).
+// Grid (chunks, 2m): block (c, w) sums its source chunk for wall point w; partials
+// disc[c][w][4] = (du1, du2, dT1, dT2) are summed in fixed order by k_xi.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __restrict__ wx,
+                                              const double* __restrict__ wy, const double* __restrict__ x,
+                                              const double* __restrict__ y, const double* __restrict__ f1,
+                                              const double* __restrict__ f2, int64_t chunk,
+                                              double* __restrict__ disc) {
+  __shared__ double sc[16];
+  const int wpt = blockIdx.y;
+  const bool onD = wpt >= L.m;
+  const double x0 = wx[wpt], y0 = wy[wpt];
+  const double nx = onD ? L.nDx : L.nLx, ny = onD ? L.nDy : L.nLy;
+  // far column/row (-2 along the wall-normal lattice vector) minus the near one (+1)
+  const double ax = onD ? L.e2x : L.e1x, ay = onD ? L.e2y : L.e1y;   // across the wall pair
+  const double bx = onD ? L.e1x : L.e2x, by = onD ? L.e1y : L.e2y;   // along the wall
+  const int64_t j0 = blockIdx.x * chunk;
+  const int64_t j1 = (j0 + chunk < N) ? j0 + chunk : N;
+  double u1 = 0, u2 = 0, t1 = 0, t2 = 0;
+  for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
+    const double yj = x[j], zj = y[j], g1 = f1[j], g2 = f2[j];
+    for (int n = -1; n <= 1; ++n) {
+      const double fx = yj - 2.0 * ax + n * bx, fy = zj - 2.0 * ay + n * by;
+      const double cx = yj + ax + n * bx, cy = zj + ay + n * by;
+      double v1 = 0, v2 = 0, w1 = 0, w2 = 0;
+      stokeslet_uv(x0 - fx, y0 - fy, g1, g2, L.inv4pimu, v1, v2);
+      stokeslet_uv(x0 - cx, y0 - cy, g1, g2, L.inv4pimu, w1, w2);
+      u1 += v1 - w1;
+      u2 += v2 - w2;
+      double p1 = 0, p2 = 0, q1 = 0, q2 = 0;
+      traction_uv(x0 - fx, y0 - fy, nx, ny, g1, g2, p1, p2);
+      traction_uv(x0 - cx, y0 - cy, nx, ny, g1, g2, q1, q2);
+      t1 += p1 - q1;
+      t2 += p2 - q2;
+    }
+  }
+  u1 = block_sum(u1, sc);
+  u2 = block_sum(u2, sc);
+  t1 = block_sum(t1, sc);
+  t2 = block_sum(t2, sc);
+  if (threadIdx.x == 0) {
+    double* o = disc + ((int64_t)blockIdx.x * 2 * L.m + wpt) * 4;
+    o[0] = u1;
+    o[1] = u2;
+    o[2] = t1;
+    o[3] = t2;
+  }
+}
+
+void launch_disc(spm_handle* h) {
+  const Lat L = lattice_args(h);
+  const int64_t N = h->geo.N;
+  const int nc = h->wk.nchunk_disc;
+  const int64_t chunk = (N + nc - 1) / nc;
+  dim3 grid((unsigned)nc, (unsigned)(2 * L.m));
+  k_disc<<<grid, 256, 0, h->stream>>>(N, L, h->per.wx, h->per.wy, h->geo.x, h->geo.y, h->wk.f1, h->wk.f2, chunk,
+                                      h->wk.disc);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// One block: g = sum of chunk partials, F = sum of per-particle forces, xi = Q^+ (g0 - g).
+__global__ void k_xi(Lat L, int nchunk, int No, const double* __restrict__ disc, const double* __restrict__ pF,
+                     const double* __restrict__ Qp, double* __restrict__ xi) {
+  __shared__ double gt[8 * 256];
+  __shared__ double Fs[2];
+  const int m = L.m, M = L.M;
+  if (threadIdx.x == 0) {
+    double F1 = 0, F2 = 0;
+    for (int q = 0; q < No; ++q) {
+      F1 += pF[4 * q + 0];
+      F2 += pF[4 * q + 1];
+    }
+    Fs[0] = F1;
+    Fs[1] = F2;
+  }
+  __syncthreads();
+  const double l1 = sqrt(L.e1x * L.e1x + L.e1y * L.e1y), l2 = sqrt(L.e2x * L.e2x + L.e2y * L.e2y);
+  for (int wpt = threadIdx.x; wpt < 2 * m; wpt += blockDim.x) {
+    double s[4] = {0, 0, 0, 0};
+    for (int c = 0; c < nchunk; ++c)
+      for (int k = 0; k < 4; ++k) s[k] += disc[((int64_t)c * 2 * m + wpt) * 4 + k];
+    const bool onD = wpt >= m;
+    const int q = onD ? wpt - m : wpt;
+    const int base = onD ? 4 * m : 0;
+    const double l = onD ? l1 : l2;
+    gt[base + 0 * m + q] = 0.0 - s[0];
+    gt[base + 1 * m + q] = 0.0 - s[1];
+    gt[base + 2 * m + q] = -Fs[0] / (2.0 * l) - s[2];
+    gt[base + 3 * m + q] = -Fs[1] / (2.0 * l) - s[3];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 2 * M; i += blockDim.x) {
+    double s = 0;
+    for (int r = 0; r < 8 * m; ++r) s += Qp[(int64_t)i * 8 * m + r] * gt[r];
+    xi[i] = s;
+  }
+}
+
+void launch_xi(spm_handle* h) {
+  const Lat L = lattice_args(h);
+  k_xi<<<1, 256, 0, h->stream>>>(L, h->wk.nchunk_disc, h->geo.No, h->wk.disc, h->wk.pF, h->per.Qp, h->wk.xi);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// ----------------------------------------------------------------------------
+// Combine: T_i = sum of near-sum split partials + self term + proxy correction.
+// Self term (limit of the smooth kernel on the curve): -(kappa/2pi) tau (tau . w sigma).
+// Proxy correction (step 4): sum_p G^t(x_i, y_p; n_i) xi_p.
+// ----------------------------------------------------------------------------
+__global__ void k_combine(int64_t N, int S, const double* __restrict__ Tpart, Geo g, const double* __restrict__ sigma,
+                          int M, const double* __restrict__ px, const double* __restrict__ py,
+                          const double* __restrict__ xi, int with_extra, double* __restrict__ T) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double t1 = 0, t2 = 0;
+  for (int k = 0; k < S; ++k) {
+    t1 += Tpart[k * 2 * N + i];
+    t2 += Tpart[k * 2 * N + N + i];
+  }
+  if (with_extra) {
+    const double w = g.w[i], tx = g.tx[i], ty = g.ty[i];
+    const double tf = tx * w * sigma[i] + ty * w * sigma[N + i];
+    const double ks = -(g.kap[i] / (2.0 * kPi)) * tf;
+    t1 += ks * tx;
+    t2 += ks * ty;
+    const double xx = g.x[i], yy = g.y[i], nx = g.nx[i], ny = g.ny[i];
+    double c1 = 0, c2 = 0;
+    for (int p = 0; p < M; ++p) traction_uv(xx - px[p], yy - py[p], nx, ny, xi[p], xi[M + p], c1, c2);
+    t1 += c1;
+    t2 += c2;
+  }
+  T[i] = t1;
+  T[N + i] = t2;
+}
+
+void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr) {
+  const int64_t N = h->geo.N;
+  k_combine<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, h->wk.splits, h->wk.Tpart, h->geo, sigma, h->per.M,
+                                                                h->per.px, h->per.py, h->wk.xi,
+                                                                with_self_corr ? 1 : 0, h->wk.T);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace spm

@@ -1,0 +1,304 @@
+"""Thin Python binding of libspm.so (the C ABI in include/spm.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels. PyTorch provides device memory (through the allocator callbacks given to
+``spm_create``, so the library's workspace lives in torch's caching allocator) and
+the stream (torch's current stream). The binding fails loudly if the library is
+missing; there is no CPU fallback.
+
+Function names mirror the C ABI; ``Solver`` wraps a handle for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libspm.so")
+
+SPM_OK, SPM_EINVAL, SPM_EOVERLAP, SPM_ENOCONV, SPM_EHIP, SPM_ENOMEM, SPM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+SPM_FP64, SPM_FP32, SPM_FP32_IR = 0, 1, 2
+_ERRNAMES = {-1: "SPM_EINVAL", -2: "SPM_EOVERLAP", -3: "SPM_ENOCONV", -4: "SPM_EHIP", -5: "SPM_ENOMEM",
+             -6: "SPM_ESTATE"}
+
+
+class spm_config(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("gamma", ctypes.c_double), ("M", ctypes.c_int32),
+                ("R_proxy", ctypes.c_double), ("m_wall", ctypes.c_int32), ("close_factor", ctypes.c_double),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("inner_tol", ctypes.c_double), ("min_gap", ctypes.c_double), ("rcond", ctypes.c_double)]
+
+
+class spm_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("fp64_matvecs", ctypes.c_int32),
+                ("fp32_matvecs", ctypes.c_int32), ("n_close_pairs", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("seconds_setup", ctypes.c_double), ("seconds_solve", ctypes.c_double),
+                ("seconds_readout", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+_lib = None
+
+
+class SpmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libspm.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: run paper_1912_04501_amd.build.build() (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    d = ctypes.POINTER(ctypes.c_double)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "spm_default_config": (None, [ctypes.POINTER(spm_config)]),
+        "spm_create": (ctypes.c_int, [ctypes.POINTER(P), ctypes.POINTER(spm_config), P, ALLOC_FN, FREE_FN, P]),
+        "spm_destroy": (None, [P]),
+        "spm_last_error": (ctypes.c_char_p, [P]),
+        "spm_set_lattice": (ctypes.c_int, [P, d, d, d]),
+        "spm_set_ellipses": (ctypes.c_int, [P, ctypes.c_int32, d, d, d, d, i32]),
+        "spm_num_nodes": (ctypes.c_int, [P, i64]),
+        "spm_num_particles": (ctypes.c_int, [P, i32]),
+        "spm_get_nodes": (ctypes.c_int, [P, P, P, P, P, P]),
+        "spm_get_centers": (ctypes.c_int, [P, d]),
+        "spm_apply": (ctypes.c_int, [P, P, P, ctypes.c_int32]),
+        "spm_rhs": (ctypes.c_int, [P, P]),
+        "spm_solve": (ctypes.c_int, [P, P, P, P, P, P, ctypes.POINTER(spm_solve_info)]),
+        "spm_velocities": (ctypes.c_int, [P, P, P, P]),
+        "spm_effective_viscosity": (ctypes.c_int, [P, P, P]),
+        "spm_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_int32, d, d, d, d,
+                                    ctypes.POINTER(spm_solve_info)]),
+        "spm_near_traction": (ctypes.c_int, [P, P, P, ctypes.c_int32]),
+        "spm_close_correction": (ctypes.c_int, [P, P, P, ctypes.c_int32]),
+        "spm_proxy_strengths": (ctypes.c_int, [P, P, P]),
+        "spm_close_pairs": (ctypes.c_int, [P, i64, i32, i32, i32, ctypes.c_int64]),
+        "spm_proxy_pinv": (ctypes.c_int, [P, d]),
+        "spm_proxy_svd": (ctypes.c_int, [P, d, d, i32]),
+        "spm_profile": (ctypes.c_int, [P, ctypes.c_int32]),
+        "spm_profile_read": (ctypes.c_int, [P, ctypes.c_int32, d, i64, d]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def default_config(**kw) -> spm_config:
+    c = spm_config()
+    lib().spm_default_config(ctypes.byref(c))
+    for k, v in kw.items():
+        if not hasattr(c, k):
+            raise KeyError(k)
+        setattr(c, k, v)
+    return c
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One handle of the C ABI; device memory from torch, kernels on torch's current stream."""
+
+    def __init__(self, device="cuda", **cfg):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required (no CPU fallback)")
+        self.device = torch.device(device)
+        self.cfg = default_config(**cfg)
+        self._blocks = {}
+        self._stream = torch.cuda.current_stream(self.device)
+
+        def _alloc(nbytes, stream, ctx):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            self._blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, stream, ctx):
+            self._blocks.pop(ptr, None)
+
+        self._alloc_cb = ALLOC_FN(_alloc)
+        self._free_cb = FREE_FN(_free)
+        h = ctypes.c_void_p()
+        rc = lib().spm_create(ctypes.byref(h), ctypes.byref(self.cfg), ctypes.c_void_p(self._stream.cuda_stream),
+                              self._alloc_cb, self._free_cb, None)
+        if rc != 0:
+            raise SpmError(rc, "spm_create failed (bad config?)")
+        self.h = h
+        self.N = 0
+        self.No = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().spm_destroy(self.h)
+            self.h = None
+            self._blocks.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != 0 and rc not in allow:
+            raise SpmError(rc, lib().spm_last_error(self.h).decode())
+        return rc
+
+    # --- setup -------------------------------------------------------------
+    def set_lattice(self, skew, center=(0.0, 0.0)):
+        e1 = np.array([1.0, 0.0])
+        e2 = np.array([float(skew), 1.0])
+        c = np.array(center, dtype=float)
+        self._check(lib().spm_set_lattice(self.h, _dp(e1), _dp(e2), _dp(c)))
+
+    def set_ellipses(self, centers, theta, a, b, n_nodes):
+        c = np.ascontiguousarray(np.asarray(centers, dtype=float).reshape(-1))
+        th = np.ascontiguousarray(theta, dtype=float)
+        aa = np.ascontiguousarray(a, dtype=float)
+        bb = np.ascontiguousarray(b, dtype=float)
+        nn = np.ascontiguousarray(n_nodes, dtype=np.int32)
+        self._check(lib().spm_set_ellipses(self.h, len(th), _dp(c), _dp(th), _dp(aa), _dp(bb),
+                                           nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        n = ctypes.c_int64()
+        self._check(lib().spm_num_nodes(self.h, ctypes.byref(n)))
+        self.N = int(n.value)
+        self.No = len(th)
+
+    def set_workload(self, wl):
+        self.set_lattice(wl["skew"])
+        self.set_ellipses(wl["centers"], wl["theta"], wl["a"], wl["b"], wl["n_nodes"])
+        return self
+
+    def _vec(self, n):
+        return torch.empty(int(n), dtype=torch.float64, device=self.device)
+
+    # --- calls ---------------------------------------------------------------
+    def nodes(self):
+        out = [self._vec(self.N) for _ in range(5)]
+        self._check(lib().spm_get_nodes(self.h, *[_ptr(t) for t in out]))
+        return out
+
+    def centers(self):
+        c = np.zeros(2 * self.No)
+        self._check(lib().spm_get_centers(self.h, _dp(c)))
+        return c.reshape(-1, 2)
+
+    def apply(self, sigma, precision=SPM_FP64, out=None):
+        out = self._vec(2 * self.N) if out is None else out
+        self._check(lib().spm_apply(self.h, _ptr(sigma), _ptr(out), precision))
+        return out
+
+    def rhs(self):
+        out = self._vec(2 * self.N)
+        self._check(lib().spm_rhs(self.h, _ptr(out)))
+        return out
+
+    def solve(self, sigma0=None, allow_noconv=False):
+        sig = self._vec(2 * self.N)
+        vel = self._vec(2 * self.No)
+        om = self._vec(self.No)
+        mu = self._vec(1)
+        info = spm_solve_info()
+        rc = lib().spm_solve(self.h, _ptr(sigma0), _ptr(sig), _ptr(vel), _ptr(om), _ptr(mu), ctypes.byref(info))
+        self._check(rc, allow=(SPM_ENOCONV,) if allow_noconv else ())
+        return {"sigma": sig, "vel": vel.view(-1, 2), "omega": om, "mu_eff": mu, "info": info.as_dict()}
+
+    def velocities(self, sigma):
+        vel = self._vec(2 * self.No)
+        om = self._vec(self.No)
+        self._check(lib().spm_velocities(self.h, _ptr(sigma), _ptr(vel), _ptr(om)))
+        return vel.view(-1, 2), om
+
+    def effective_viscosity(self, sigma):
+        mu = self._vec(1)
+        self._check(lib().spm_effective_viscosity(self.h, _ptr(sigma), _ptr(mu)))
+        return mu
+
+    def step(self, dt, n_steps, t, centers, theta):
+        t_io = np.array([float(t)])
+        c = np.ascontiguousarray(np.asarray(centers, dtype=float).reshape(-1)).copy()
+        th = np.ascontiguousarray(theta, dtype=float).copy()
+        mus = np.zeros(int(n_steps))
+        infos = (spm_solve_info * int(n_steps))()
+        self._check(lib().spm_step(self.h, float(dt), int(n_steps), _dp(t_io), _dp(c), _dp(th), _dp(mus), infos))
+        return {"t": float(t_io[0]), "centers": c.reshape(-1, 2), "theta": th, "mu_eff": mus,
+                "infos": [i.as_dict() for i in infos]}
+
+    # --- stage entry points ----------------------------------------------------
+    def near_traction(self, sigma, precision=SPM_FP64):
+        out = self._vec(2 * self.N)
+        self._check(lib().spm_near_traction(self.h, _ptr(sigma), _ptr(out), precision))
+        return out
+
+    def close_correction(self, sigma, precision=SPM_FP64):
+        out = self._vec(2 * self.N)
+        self._check(lib().spm_close_correction(self.h, _ptr(sigma), _ptr(out), precision))
+        return out
+
+    def proxy_strengths(self, sigma):
+        out = self._vec(2 * self.cfg.M)
+        self._check(lib().spm_proxy_strengths(self.h, _ptr(sigma), _ptr(out)))
+        return out
+
+    def close_pairs(self):
+        n = ctypes.c_int64()
+        self._check(lib().spm_close_pairs(self.h, ctypes.byref(n), None, None, None, 0))
+        k = int(n.value)
+        t = np.zeros(max(k, 1), dtype=np.int32)
+        q = np.zeros(max(k, 1), dtype=np.int32)
+        s = np.zeros(max(k, 1), dtype=np.int32)
+        ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+        self._check(lib().spm_close_pairs(self.h, ctypes.byref(n), ip(t), ip(q), ip(s), max(k, 1)))
+        return np.stack([t[:k], q[:k], s[:k]], axis=1).astype(np.int64)
+
+    def profile(self, enable=True):
+        self._check(lib().spm_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self, kernel):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        pairs = ctypes.c_double()
+        self._check(lib().spm_profile_read(self.h, int(kernel), ctypes.byref(ms), ctypes.byref(n),
+                                           ctypes.byref(pairs)))
+        return {"ms": ms.value, "launches": int(n.value), "pairs": pairs.value}
+
+    def proxy_svd(self):
+        M, m = self.cfg.M, self.cfg.m_wall
+        Q = np.zeros(2 * M * 8 * m)
+        sv = np.zeros(2 * M)
+        sw = ctypes.c_int32()
+        self._check(lib().spm_proxy_svd(self.h, _dp(Q), _dp(sv), ctypes.byref(sw)))
+        return Q.reshape(8 * m, 2 * M), sv, int(sw.value)
+
+    def proxy_pinv(self):
+        M, m = self.cfg.M, self.cfg.m_wall
+        out = np.zeros(2 * M * 8 * m)
+        self._check(lib().spm_proxy_pinv(self.h, _dp(out)))
+        return out.reshape(2 * M, 8 * m)

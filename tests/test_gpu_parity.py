@@ -1,0 +1,142 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle on the same
+seeded inputs, through the C ABI (libspm.so)."""
+import numpy as np
+import pytest
+
+from oracle import close, near, periodizer
+from oracle import operator as op
+from oracle import readout as ro
+from paper_1912_04501_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _spm():
+    from paper_1912_04501_amd import spm
+    return spm
+
+
+def _solver(wl, **cfg):
+    return _spm().Solver("cuda:0", **cfg).set_workload(wl)
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "single_ellipse_128": lambda: W.single_ellipse(),
+    "two_ellipses_gap3e-2_N128": lambda: W.two_ellipses(3e-2, n_nodes=128),
+    "two_ellipses_gap1e-2_N256_skew0.3": lambda: W.two_ellipses(1e-2, n_nodes=256, skew=0.3),
+    "random_6_phi0.3_skew_ragged": lambda: W.random_ellipses(6, 0.3, seed=5, nodes=None, target_total=700),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    wl = CASES[request.param]()
+    prob = op.make_problem(wl)
+    print(f"[case] {request.param} N={prob.N}", flush=True)
+    return request.param, wl, prob
+
+
+def test_geometry(case):
+    name, wl, prob = case
+    s = _solver(wl)
+    x, y, nx, ny, w = [_n(t) for t in s.nodes()]
+    g = prob.geom
+    assert np.abs(x - g.x[:, 0]).max() < 1e-14 and np.abs(y - g.x[:, 1]).max() < 1e-14
+    assert np.abs(nx - g.n[:, 0]).max() < 1e-14 and np.abs(ny - g.n[:, 1]).max() < 1e-14
+    assert np.abs(w - g.w).max() < 1e-15
+    assert np.abs(s.centers() - g.centers).max() < 1e-15
+
+
+def test_near_sum(case):
+    name, wl, prob = case
+    s = _solver(wl)
+    sig = W.random_density(prob.N, seed=7)
+    T = _n(s.near_traction(_t(sig)))
+    ref = op.to1(near.near_traction(prob.geom, op.to2(sig)))
+    err = np.abs(T - ref).max() / np.abs(ref).max()
+    print(f"near FP64 rel err {err:.2e}")
+    assert err < 1e-12
+    T32 = _n(s.near_traction(_t(sig), precision=_spm().SPM_FP32))
+    err32 = np.abs(T32 - ref).max() / np.abs(ref).max()
+    print(f"near FP32 rel err {err32:.2e}")
+    assert err32 < 5e-4
+
+
+def test_close_pairs_and_correction(case):
+    name, wl, prob = case
+    s = _solver(wl)
+    pairs = s.close_pairs()
+    assert pairs.shape == prob.pairs.shape and np.array_equal(pairs, prob.pairs)
+    sig = W.random_density(prob.N, seed=8)
+    dT = _n(s.close_correction(_t(sig)))
+    ref = op.to1(close.close_correction(prob.geom, op.to2(sig), prob.pairs))
+    scale = max(np.abs(ref).max(), 1e-300)
+    if len(prob.pairs):
+        err = np.abs(dT - ref).max() / scale
+        print(f"close rel err {err:.2e} over {len(prob.pairs)} pairs")
+        assert err < 1e-10
+    else:
+        assert np.abs(dT).max() == 0.0
+
+
+def test_periodizer(case):
+    name, wl, prob = case
+    s = _solver(wl)
+    Q, sv, sweeps = s.proxy_svd()
+    print(f"Q err {np.abs(Q - prob.Q).max():.2e}, Jacobi sweeps {sweeps}")
+    assert np.abs(Q - prob.Q).max() < 1e-13 * np.abs(prob.Q).max()
+    ref_sv = np.linalg.svd(prob.Q, compute_uv=False)
+    sv = np.sort(sv)[::-1]
+    print("sv rel (gpu smallest 5)", sv[-5:] / sv[0], "ref", ref_sv[-5:] / ref_sv[0])
+    assert np.abs(sv - ref_sv).max() < 1e-12 * ref_sv[0]
+    Qp = s.proxy_pinv()
+    assert np.abs(Qp - prob.Qpinv).max() < 1e-8 * np.abs(prob.Qpinv).max()
+    sig = W.random_density(prob.N, seed=9)
+    xi = _n(s.proxy_strengths(_t(sig)))
+    ref, _, _ = op.proxy_strengths(prob, op.to2(sig))
+    err = np.abs(xi - ref).max() / np.abs(ref).max()
+    print(f"xi rel err {err:.2e}")
+    assert err < 1e-9
+
+
+def test_full_operator(case):
+    name, wl, prob = case
+    s = _solver(wl)
+    sig = W.random_density(prob.N, seed=10)
+    y = _n(s.apply(_t(sig)))
+    ref = op.apply(prob, sig)
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"apply rel err {err:.2e}")
+    assert err < 1e-10
+    b = _n(s.rhs())
+    assert np.abs(b - op.rhs(prob)).max() < 1e-15
+
+
+def test_solve(case):
+    name, wl, prob = case
+    s = _solver(wl)
+    r = s.solve()
+    assert r["info"]["rel_residual"] <= 1e-10
+    x, info = op.solve(prob, tol=1e-12)
+    v, om = ro.velocities(prob, x)
+    mu = ro.mu_eff(prob, x)
+    gv, go, gm = _n(r["vel"]), _n(r["omega"]), float(r["mu_eff"].item())
+    sc_v = max(np.abs(v).max(), np.hypot(*prob.geom.e2))
+    print(f"[{name}] its {r['info']['iterations']} (oracle {info['iterations']}) "
+          f"omega err {np.abs(go - om).max():.2e} v err {np.abs(gv - v).max():.2e} mu err {abs(gm - mu):.2e}")
+    assert np.abs(go - om).max() <= 1e-9 * max(1.0, np.abs(om).max())
+    assert np.abs(gv - v).max() <= 1e-9 * sc_v
+    assert abs(gm - mu) <= 1e-9 * mu
+    # same pin: the densities agree too
+    gs = _n(r["sigma"])
+    assert np.abs(gs - x).max() <= 1e-8 * np.abs(x).max()
