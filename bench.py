@@ -96,6 +96,9 @@ def main():
     N = s.N
     pairs_per_matvec = 9.0 * N * N
     log(f"[bench] N={N} particles={s.No} close pairs={len(s.close_pairs())}")
+    t0 = time.perf_counter()
+    tune = s.autotune(None)
+    log(f"[bench] autotune {time.perf_counter() - t0:.1f}s: {tune}")
 
     for k in range(args.warmup):
         r = s.solve()
@@ -124,13 +127,15 @@ def main():
                 "frac": achieved / PEAK[dt], "traffic": None,
                 "kernel": f"k_near<{'float' if kern else 'double'}> (near-image traction sum, {dt})",
                 "avg_launch_ms": avg_ms, "launches": prof["launches"],
-                "pairs_per_launch": pairs_per_matvec}
+                "pairs_per_launch": pairs_per_matvec, "launch_shape": tune["fp32" if kern else "fp64"]}
 
     extra = {}
     if not args.no_compare:
         for name, p in (("fp64", spm.SPM_FP64), ("fp32_ir", spm.SPM_FP32_IR)):
             c = spm.Solver("cuda:0", precision=p)
             c.set_workload(wl)
+            for pr, key in ((spm.SPM_FP64, "fp64"), (spm.SPM_FP32, "fp32")):
+                c.set_launch(pr, **tune[key])
             c.solve()
             torch.cuda.synchronize()
             t1 = time.perf_counter()

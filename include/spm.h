@@ -189,6 +189,22 @@ int spm_proxy_pinv(spm_handle* h, double* pinv_host);
  * Jacobi SVD (host [2M], unsorted, may be NULL) and the number of Jacobi sweeps used. */
 int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps_host);
 
+/* ---- launch shape of the near-image sum ---- */
+
+/* Time candidate launch shapes of the near-sum kernel (block 64/128/256 threads,
+ * 1/2/4 targets per lane, 128/256/512 sources per LDS tile, source splits) on the
+ * handle's current geometry, for FP64 and FP32, and keep the fastest. cache_path
+ * (may be NULL): text file of earlier results keyed by device, N and precision;
+ * a hit skips the timing, a miss appends. best_ms_host [2] (may be NULL): the
+ * winning per-launch time (0 on a cache hit). The shape stays until N changes. */
+int spm_autotune(spm_handle* h, const char* cache_path, double* best_ms_host);
+
+/* Current near-sum launch shape {block, targets per lane, tile, splits} for
+ * precision SPM_FP64 or SPM_FP32 (host [4]); spm_set_launch overrides it
+ * (SPM_EINVAL for an unsupported shape). */
+int spm_get_launch(spm_handle* h, int32_t precision, int32_t* cfg_host);
+int spm_set_launch(spm_handle* h, int32_t precision, const int32_t* cfg_host);
+
 /* ---- measurement ---- */
 
 /* Enable (1) or disable (0) timing of the near-sum kernel with HIP events recorded

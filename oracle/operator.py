@@ -196,3 +196,29 @@ def solve(prob, tol=1e-10, maxiter=500, method="gmres", x0=None):
         x = sla.lu_solve(sla.lu_factor(A), b)
         return x, {"iterations": 0, "rel_residual": np.linalg.norm(b - A @ x) / np.linalg.norm(b)}
     return gmres(lambda v: apply(prob, v), b, tol, maxiter, x0)
+
+
+def apply_rows(prob, sigma, rows):
+    """Rows `rows` (node indices) of y = (1/2 I + K_pinned + L) sigma, without forming
+    the whole product: the same sums evaluated at the selected targets only (the pin
+    needs node 0, which is always evaluated). Returns (len(rows), 2)."""
+    g = prob.geom
+    s2 = to2(np.asarray(sigma, dtype=np.float64))
+    rows = np.asarray(rows, dtype=np.int64)
+    tgt = np.unique(np.concatenate([[0], rows]))
+    f = near.forces(g, s2)
+    from . import _clib
+    Tn = _clib.near_traction(g.x[tgt], g.n[tgt], g.x, f, g.shifts(prob.cfg.image_range), tgt)
+    tf = (g.tau[tgt] * f[tgt]).sum(1)
+    Ts = -(g.kappa[tgt] / (2.0 * np.pi) * tf)[:, None] * g.tau[tgt]
+    xi, _, _ = proxy_strengths(prob, s2)
+    Tc = periodizer.correction_traction(prob.P, xi, g.x[tgt], g.n[tgt])
+    sel = prob.pairs[np.isin(prob.pairs[:, 0], tgt)]
+    dT_full = close.close_correction(g, s2, sel, prob.cfg.image_range)
+    K = Tn + Ts + Tc + dT_full[tgt]
+    alpha = -(K[0] * g.n[0]).sum()
+    K = K + alpha * g.n[tgt]
+    L = apply_L(prob, s2)[tgt]
+    y = 0.5 * s2[tgt] + K + L
+    pos = np.searchsorted(tgt, rows)
+    return y[pos]

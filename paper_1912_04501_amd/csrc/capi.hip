@@ -1,6 +1,9 @@
 // C ABI of the solver: handle, setup, matvec pipeline, GMRES driver, readouts, time stepping.
 #include <chrono>
 #include <cmath>
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <utility>
@@ -8,6 +11,23 @@
 #include "spm_internal.h"
 
 using namespace spm;
+
+namespace spm {
+// Default near-sum launch shape: enough source splits for ~8 waves per SIMD, at
+// least 128 sources per split.
+NearConfig heuristic_near(int64_t N, int block, int tpt, int tile) {
+  NearConfig c;
+  c.block = block;
+  c.tpt = tpt;
+  c.tile = tile;
+  const int64_t nblocks = (N + block * tpt - 1) / (block * tpt);
+  const int64_t waves = nblocks * (block / 64);
+  int64_t S = (8192 + waves - 1) / waves;
+  S = std::max<int64_t>(1, std::min<int64_t>(S, std::max<int64_t>(1, N / 128)));
+  c.splits = (int32_t)S;
+  return c;
+}
+}  // namespace spm
 
 namespace {
 
@@ -70,6 +90,11 @@ void upload(spm_handle* h, void* dst, const void* src, size_t bytes) {
 }
 
 void sync(spm_handle* h) { SPM_HIP_CHECK(hipStreamSynchronize(h->stream)); }
+
+bool verbose() {
+  static const bool v = std::getenv("SPM_VERBOSE") != nullptr;
+  return v;
+}
 
 double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -184,17 +209,16 @@ void build_lattice(spm_handle* h) {
   ensure(h, h->wk.scal, 16);
 }
 
+size_t max_splits(spm_handle* h) { return (size_t)std::max(h->wk.near[0].splits, h->wk.near[1].splits); }
+
 void choose_launch(spm_handle* h) {
   const int64_t N = h->geo.N;
   Work& W = h->wk;
-  if (W.block != 64 && W.block != 128 && W.block != 256) W.block = 256;
-  if (W.tile < 16) W.tile = 256;
-  const int64_t nblocks = (N + W.block - 1) / W.block;
-  const int64_t waves = nblocks * (W.block / 64);
-  int64_t S = (8192 + waves - 1) / waves;
-  const int64_t smax = std::max<int64_t>(1, N / 128);
-  S = std::max<int64_t>(1, std::min<int64_t>(S, smax));
-  W.splits = (int32_t)S;
+  if (W.tuned && W.tuned_N != N) W.tuned = false;
+  if (!W.tuned) {
+    W.near[0] = heuristic_near(N, 256, 1, 256);
+    W.near[1] = heuristic_near(N, 256, 1, 256);
+  }
   W.nchunk_disc = (int32_t)std::max<int64_t>(1, (N + 2047) / 2048);
 }
 
@@ -206,7 +230,7 @@ void alloc_work(spm_handle* h) {
   ensure(h, W.f1f, N);
   ensure(h, W.f2f, N);
   ensure(h, W.T, 2 * N);
-  ensure(h, W.Tpart, (size_t)W.splits * 2 * N);
+  ensure(h, W.Tpart, max_splits(h) * 2 * N);
   ensure(h, W.pF, (size_t)4 * h->geo.No);
   ensure(h, W.disc, (size_t)W.nchunk_disc * 2 * h->per.m * 4);
 }
@@ -244,7 +268,7 @@ void stage_xi(spm_handle* h, const double* sigma) {
 void matvec(spm_handle* h, const double* sigma, double* out, int precision) {
   stage_xi(h, sigma);
   launch_near(h, precision);
-  launch_combine(h, sigma, true);
+  launch_combine(h, sigma, true, precision);
   if (h->cl.ntargets > 0) {
     launch_vplus(h, sigma);
     launch_close_apply(h, sigma, h->wk.T, precision);
@@ -352,21 +376,29 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, spm_solve_inf
     double rel = nonzero ? true_residual(h, bb, sigma, bnorm, info) : 1.0;
     if (!nonzero) gm_copy(h, K.tmp2, bb, n2);
     int outer = 0;
+    // inner tolerance: cfg.inner_tol, raised to half the reduction the previous
+    // refinement actually achieved (the FP32 operator error bounds what one
+    // refinement can gain; solving the inner system deeper than that is wasted)
+    double itol_next = h->cfg.inner_tol;
     while (rel > tol && outer < 40) {
-      // correction d for A d = r (r in tmp2), solved with the FP32 near sum
       ensure(h, K.d, n2);
       double* d = K.d;
       double* r = K.tmp2;
       const double rnorm = rel * bnorm;
-      double itol = h->cfg.inner_tol;
+      double itol = itol_next;
       if (tol / rel > itol) itol = 0.5 * tol / rel;
       gm_zero(h, d, n2);
-      // GMRES overwrites tmp (matvec scratch) but not tmp2 (r) except through V; copy r to V[0] happens inside
       KrylovResult kr = gmres(h, SPM_FP32, r, d, false, itol, h->cfg.max_iter, rnorm, info);
       info->iterations += kr.iterations;
       gm_axpby(h, n2, 1.0, sigma, 1.0, d, sigma);
       ++outer;
-      rel = true_residual(h, bb, sigma, bnorm, info);
+      const double rel_new = true_residual(h, bb, sigma, bnorm, info);
+      const double rho = rel_new / rel;
+      if (verbose())
+        std::fprintf(stderr, "[spm] refinement %d: inner its %d (inner tol %.1e, est %.1e) FP64 residual %.3e -> %.3e\n",
+                     outer, kr.iterations, itol, kr.est, rel, rel_new);
+      itol_next = std::min(0.1, std::max(h->cfg.inner_tol, 0.5 * rho));
+      rel = rel_new;
       if (kr.iterations >= h->cfg.max_iter && rel > tol) {
         status = SPM_ENOCONV;
         break;
@@ -400,6 +432,19 @@ void readout(spm_handle* h, const double* sigma, double* vel, double* omega, dou
 }
 
 }  // namespace
+
+namespace spm {
+void ensure_tpart(spm_handle* h, size_t splits) {
+  const size_t need = std::max(splits, max_splits(h));
+  ensure(h, h->wk.Tpart, need * 2 * h->geo.N);
+}
+void launch_prep_for_timing(spm_handle* h) {
+  // fill the force arrays from the right-hand side so the timed kernels see finite data
+  launch_rhs(h, h->kr.tmp);
+  launch_prep(h, h->kr.tmp);
+  sync(h);
+}
+}  // namespace spm
 
 // ===========================================================================
 extern "C" {
@@ -694,7 +739,7 @@ int spm_near_traction(spm_handle* h, const double* sigma, double* out, int32_t p
     if (precision != SPM_FP64 && precision != SPM_FP32) throw ApiError(SPM_EINVAL, "precision must be FP64 or FP32");
     launch_prep(h, sigma);
     launch_near(h, precision);
-    launch_near_sum_only(h, out);
+    launch_near_sum_only(h, out, precision);
     sync(h);
     return SPM_OK;
   });
@@ -828,6 +873,46 @@ int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps
     SPM_HIP_CHECK(hipMemcpyAsync(&sw, h->per.svd_s + 2 * h->per.M, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     sync(h);
     if (sweeps_host) *sweeps_host = (int32_t)sw;
+    return SPM_OK;
+  });
+}
+
+int spm_autotune(spm_handle* h, const char* cache_path, double* best_ms_host) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    autotune(h, cache_path, best_ms_host);
+    sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_get_launch(spm_handle* h, int32_t precision, int32_t* cfg_host) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!cfg_host || (precision != SPM_FP64 && precision != SPM_FP32)) throw ApiError(SPM_EINVAL, "bad arguments");
+    const NearConfig& c = h->wk.near[precision == SPM_FP64 ? 0 : 1];
+    cfg_host[0] = c.block;
+    cfg_host[1] = c.tpt;
+    cfg_host[2] = c.tile;
+    cfg_host[3] = c.splits;
+    return SPM_OK;
+  });
+}
+
+int spm_set_launch(spm_handle* h, int32_t precision, const int32_t* cfg_host) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!cfg_host || (precision != SPM_FP64 && precision != SPM_FP32)) throw ApiError(SPM_EINVAL, "bad arguments");
+    NearConfig c;
+    c.block = cfg_host[0];
+    c.tpt = cfg_host[1];
+    c.tile = cfg_host[2];
+    c.splits = cfg_host[3];
+    if (!near_config_valid(c)) throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
+    ensure_tpart(h, (size_t)c.splits);
+    h->wk.near[precision == SPM_FP64 ? 0 : 1] = c;
+    h->wk.tuned = true;
+    h->wk.tuned_N = h->geo.N;
     return SPM_OK;
   });
 }

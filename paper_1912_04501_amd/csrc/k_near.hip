@@ -16,24 +16,37 @@ struct Src {
   R y1, y2, f1, f2;
 };
 
-template <typename R, int BLOCK>
+// TPT targets per lane (i, i + BLOCK, ...) share every LDS source read. Each LDS tile is
+// summed in a fresh accumulator of the kernel's precision and then added to an FP64
+// running sum, which keeps the FP32 summation error at the level of one tile.
+template <typename R, int BLOCK, int TPT>
 __global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__ x, const R* __restrict__ y,
                                                 const R* __restrict__ nx, const R* __restrict__ ny,
                                                 const R* __restrict__ f1, const R* __restrict__ f2,
                                                 int64_t chunk, int tile, Shifts<R> sh, double* __restrict__ Tpart) {
   extern __shared__ unsigned char smem_raw[];
   Src<R>* src = reinterpret_cast<Src<R>*>(smem_raw);
-  const int64_t i = blockIdx.x * (int64_t)BLOCK + threadIdx.x;
+  const int64_t i0 = blockIdx.x * (int64_t)(BLOCK * TPT) + threadIdx.x;
   const int64_t j0 = blockIdx.y * chunk;
   const int64_t j1 = (j0 + chunk < N) ? j0 + chunk : N;
-  R xi = 0, yi = 0, nxi = 0, nyi = 0;
-  if (i < N) {
-    xi = x[i];
-    yi = y[i];
-    nxi = nx[i];
-    nyi = ny[i];
+  R xi[TPT], yi[TPT], nxi[TPT], nyi[TPT];
+  double A1[TPT], A2[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const int64_t i = i0 + t * BLOCK;
+    xi[t] = 0;
+    yi[t] = 0;
+    nxi[t] = 0;
+    nyi[t] = 0;
+    if (i < N) {
+      xi[t] = x[i];
+      yi[t] = y[i];
+      nxi[t] = nx[i];
+      nyi[t] = ny[i];
+    }
+    A1[t] = 0.0;
+    A2[t] = 0.0;
   }
-  R a1 = 0, a2 = 0;
   for (int64_t jt = j0; jt < j1; jt += tile) {
     const int cnt = (int)((jt + tile < j1) ? tile : (j1 - jt));
     __syncthreads();
@@ -46,17 +59,36 @@ __global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__
       src[k] = s;
     }
     __syncthreads();
+    R a1[TPT], a2[TPT];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      a1[t] = 0;
+      a2[t] = 0;
+    }
     for (int k = 0; k < cnt; ++k) {
       const Src<R> s = src[k];
-      const R dx = xi - s.y1, dy = yi - s.y2;
 #pragma unroll
-      for (int m = 0; m < kShifts; ++m) gt_pair(dx - sh.x[m], dy - sh.y[m], nxi, nyi, s.f1, s.f2, a1, a2);
+      for (int t = 0; t < TPT; ++t) {
+        const R dx = xi[t] - s.y1, dy = yi[t] - s.y2;
+#pragma unroll
+        for (int m = 0; m < kShifts; ++m)
+          gt_pair(dx - sh.x[m], dy - sh.y[m], nxi[t], nyi[t], s.f1, s.f2, a1[t], a2[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      A1[t] += (double)a1[t];
+      A2[t] += (double)a2[t];
     }
   }
-  if (i < N) {
-    double* out = Tpart + blockIdx.y * 2 * N;
-    out[i] = -(1.0 / kPi) * (double)a1;
-    out[N + i] = -(1.0 / kPi) * (double)a2;
+  double* out = Tpart + blockIdx.y * 2 * N;
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const int64_t i = i0 + t * BLOCK;
+    if (i < N) {
+      out[i] = -(1.0 / kPi) * A1[t];
+      out[N + i] = -(1.0 / kPi) * A2[t];
+    }
   }
 }
 
@@ -72,33 +104,40 @@ static Shifts<R> make_shifts(spm_handle* h) {
   return sh;
 }
 
+template <typename R, int BLOCK, int TPT>
+static void near_launch(spm_handle* h, const R* x, const R* y, const R* nx, const R* ny, const R* f1, const R* f2,
+                        int splits, int tile) {
+  const int64_t N = h->geo.N;
+  const int64_t chunk = (N + splits - 1) / splits;
+  const size_t lds = sizeof(Src<R>) * (size_t)tile;
+  dim3 grid((unsigned)((N + BLOCK * TPT - 1) / (BLOCK * TPT)), (unsigned)splits);
+  k_near<R, BLOCK, TPT><<<grid, BLOCK, lds, h->stream>>>(N, x, y, nx, ny, f1, f2, chunk, tile, make_shifts<R>(h),
+                                                         h->wk.Tpart);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
 template <typename R>
 static void near_dispatch(spm_handle* h, const R* x, const R* y, const R* nx, const R* ny, const R* f1,
-                          const R* f2) {
-  const int64_t N = h->geo.N;
-  const int S = h->wk.splits;
-  const int64_t chunk = (N + S - 1) / S;
-  const int tile = h->wk.tile;
-  const size_t lds = sizeof(Src<R>) * (size_t)tile;
-  const Shifts<R> sh = make_shifts<R>(h);
-  switch (h->wk.block) {
-    case 64: {
-      dim3 grid((unsigned)((N + 63) / 64), (unsigned)S);
-      k_near<R, 64><<<grid, 64, lds, h->stream>>>(N, x, y, nx, ny, f1, f2, chunk, tile, sh, h->wk.Tpart);
-      break;
-    }
-    case 128: {
-      dim3 grid((unsigned)((N + 127) / 128), (unsigned)S);
-      k_near<R, 128><<<grid, 128, lds, h->stream>>>(N, x, y, nx, ny, f1, f2, chunk, tile, sh, h->wk.Tpart);
-      break;
-    }
-    default: {
-      dim3 grid((unsigned)((N + 255) / 256), (unsigned)S);
-      k_near<R, 256><<<grid, 256, lds, h->stream>>>(N, x, y, nx, ny, f1, f2, chunk, tile, sh, h->wk.Tpart);
-      break;
-    }
+                          const R* f2, const NearConfig& c) {
+  const int key = c.block * 10 + c.tpt;
+  switch (key) {
+    case 641: near_launch<R, 64, 1>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 642: near_launch<R, 64, 2>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 644: near_launch<R, 64, 4>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 1281: near_launch<R, 128, 1>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 1282: near_launch<R, 128, 2>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 1284: near_launch<R, 128, 4>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 2561: near_launch<R, 256, 1>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 2562: near_launch<R, 256, 2>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    case 2564: near_launch<R, 256, 4>(h, x, y, nx, ny, f1, f2, c.splits, c.tile); break;
+    default: throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
   }
-  SPM_HIP_CHECK(hipGetLastError());
+}
+
+bool near_config_valid(const NearConfig& c) {
+  const bool b = c.block == 64 || c.block == 128 || c.block == 256;
+  const bool t = c.tpt == 1 || c.tpt == 2 || c.tpt == 4;
+  return b && t && c.tile >= 16 && c.tile <= 1024 && c.splits >= 1;
 }
 
 void prof_flush(spm_handle* h) {
@@ -129,9 +168,9 @@ void launch_near(spm_handle* h, int precision) {
     SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used], h->stream));
   }
   if (precision == SPM_FP64)
-    near_dispatch<double>(h, g.x, g.y, g.nx, g.ny, h->wk.f1, h->wk.f2);
+    near_dispatch<double>(h, g.x, g.y, g.nx, g.ny, h->wk.f1, h->wk.f2, h->wk.near[0]);
   else
-    near_dispatch<float>(h, g.xf, g.yf, g.nxf, g.nyf, h->wk.f1f, h->wk.f2f);
+    near_dispatch<float>(h, g.xf, g.yf, g.nxf, g.nyf, h->wk.f1f, h->wk.f2f, h->wk.near[1]);
   if (h->prof) {
     SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used + 1], h->stream));
     ++h->ev_used;
@@ -149,9 +188,10 @@ __global__ void k_sum_splits(int64_t n2, int S, const double* __restrict__ Tpart
   out[i] = s;
 }
 
-void launch_near_sum_only(spm_handle* h, double* out) {
+void launch_near_sum_only(spm_handle* h, double* out, int precision) {
   const int64_t n2 = 2 * h->geo.N;
-  k_sum_splits<<<(unsigned)((n2 + 255) / 256), 256, 0, h->stream>>>(n2, h->wk.splits, h->wk.Tpart, out);
+  const int S = h->wk.near[precision == SPM_FP64 ? 0 : 1].splits;
+  k_sum_splits<<<(unsigned)((n2 + 255) / 256), 256, 0, h->stream>>>(n2, S, h->wk.Tpart, out);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

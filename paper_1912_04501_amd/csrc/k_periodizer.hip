@@ -363,9 +363,10 @@ __global__ void k_combine(int64_t N, int S, const double* __restrict__ Tpart, Ge
   T[N + i] = t2;
 }
 
-void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr) {
+void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision) {
   const int64_t N = h->geo.N;
-  k_combine<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, h->wk.splits, h->wk.Tpart, h->geo, sigma, h->per.M,
+  const int S = h->wk.near[precision == SPM_FP64 ? 0 : 1].splits;
+  k_combine<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, S, h->wk.Tpart, h->geo, sigma, h->per.M,
                                                                 h->per.px, h->per.py, h->wk.xi,
                                                                 with_self_corr ? 1 : 0, h->wk.T);
   SPM_HIP_CHECK(hipGetLastError());

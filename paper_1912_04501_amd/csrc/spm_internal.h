@@ -144,10 +144,19 @@ struct CloseList {
   double* vp = nullptr;       // [6 N] v+ of the three densities: re0 im0 re1 im1 re2 im2 (each N)
 };
 
+// Launch shape of the near sum: block threads, targets per lane, sources per LDS
+// tile, source splits (gridDim.y). Picked by the heuristic or the autotuner.
+struct NearConfig {
+  int32_t block = 256;
+  int32_t tpt = 1;
+  int32_t tile = 256;
+  int32_t splits = 1;
+};
+
 struct Work {
-  int32_t splits = 1;         // source splits of the near sum (gridDim.y)
-  int32_t block = 256;        // near-sum block size
-  int32_t tile = 256;         // sources staged per LDS tile
+  NearConfig near[2];         // [0] FP64, [1] FP32
+  bool tuned = false;         // near[] came from the autotuner (for tuned_N nodes)
+  int64_t tuned_N = -1;
   int32_t nchunk_disc = 1;    // source chunks of the wall discrepancy
   double *f1 = nullptr, *f2 = nullptr;   // w sigma
   float *f1f = nullptr, *f2f = nullptr;
@@ -224,8 +233,11 @@ void launch_rhs(spm_handle* h, double* out);
 void launch_prep(spm_handle* h, const double* sigma);
 void launch_near(spm_handle* h, int precision);
 void prof_flush(spm_handle* h);
-void launch_near_sum_only(spm_handle* h, double* out);
-void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr);
+void launch_near_sum_only(spm_handle* h, double* out, int precision);
+bool near_config_valid(const NearConfig& c);
+void autotune(spm_handle* h, const char* cache_path, double* best_ms_out);
+double time_near(spm_handle* h, int prec, const NearConfig& c, int reps);
+void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision);
 void launch_disc(spm_handle* h);
 void launch_xi(spm_handle* h);
 void launch_build_Q(spm_handle* h);

@@ -91,6 +91,9 @@ def lib():
         "spm_close_pairs": (ctypes.c_int, [P, i64, i32, i32, i32, ctypes.c_int64]),
         "spm_proxy_pinv": (ctypes.c_int, [P, d]),
         "spm_proxy_svd": (ctypes.c_int, [P, d, d, i32]),
+        "spm_autotune": (ctypes.c_int, [P, ctypes.c_char_p, d]),
+        "spm_get_launch": (ctypes.c_int, [P, ctypes.c_int32, i32]),
+        "spm_set_launch": (ctypes.c_int, [P, ctypes.c_int32, i32]),
         "spm_profile": (ctypes.c_int, [P, ctypes.c_int32]),
         "spm_profile_read": (ctypes.c_int, [P, ctypes.c_int32, d, i64, d]),
     }
@@ -277,6 +280,22 @@ class Solver:
         ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
         self._check(lib().spm_close_pairs(self.h, ctypes.byref(n), ip(t), ip(q), ip(s), max(k, 1)))
         return np.stack([t[:k], q[:k], s[:k]], axis=1).astype(np.int64)
+
+    def autotune(self, cache_path=None):
+        ms = np.zeros(2)
+        p = None if cache_path is None else str(cache_path).encode()
+        self._check(lib().spm_autotune(self.h, p, _dp(ms)))
+        return {"fp64_ms": float(ms[0]), "fp32_ms": float(ms[1]),
+                "fp64": self.get_launch(SPM_FP64), "fp32": self.get_launch(SPM_FP32)}
+
+    def get_launch(self, precision):
+        c = np.zeros(4, dtype=np.int32)
+        self._check(lib().spm_get_launch(self.h, int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return {"block": int(c[0]), "tpt": int(c[1]), "tile": int(c[2]), "splits": int(c[3])}
+
+    def set_launch(self, precision, block, tpt, tile, splits):
+        c = np.array([block, tpt, tile, splits], dtype=np.int32)
+        self._check(lib().spm_set_launch(self.h, int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
 
     def profile(self, enable=True):
         self._check(lib().spm_profile(self.h, 1 if enable else 0))

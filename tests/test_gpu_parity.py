@@ -140,3 +140,43 @@ def test_solve(case):
     # same pin: the densities agree too
     gs = _n(r["sigma"])
     assert np.abs(gs - x).max() <= 1e-8 * np.abs(x).max()
+
+
+def test_near_sum_every_launch_shape():
+    """Every supported launch shape of the near-sum kernel gives the oracle's sum
+    (ragged particle sizes, N not a multiple of any block or tile)."""
+    spm = _spm()
+    wl = W.random_ellipses(6, 0.3, seed=5, target_total=700)
+    prob = op.make_problem(wl)
+    s = _solver(wl)
+    sig = W.random_density(prob.N, seed=11)
+    ref = op.to1(near.near_traction(prob.geom, op.to2(sig)))
+    sc = np.abs(ref).max()
+    for prec, tol in ((spm.SPM_FP64, 1e-12), (spm.SPM_FP32, 5e-4)):
+        for block in (64, 128, 256):
+            for tpt in (1, 2, 4):
+                for tile in (128, 512):
+                    for splits in (1, 3, 17):
+                        s.set_launch(prec, block, tpt, tile, splits)
+                        T = _n(s.near_traction(_t(sig), precision=prec))
+                        err = np.abs(T - ref).max() / sc
+                        assert err < tol, (prec, block, tpt, tile, splits, err)
+    with pytest.raises(spm.SpmError):
+        s.set_launch(spm.SPM_FP64, 96, 1, 128, 1)
+
+
+def test_autotune_keeps_parity(tmp_path):
+    spm = _spm()
+    wl = W.random_ellipses(6, 0.3, seed=5, target_total=700)
+    prob = op.make_problem(wl)
+    s = _solver(wl)
+    cache = tmp_path / "tune.txt"
+    r = s.autotune(str(cache))
+    print(f"[autotune] {r}")
+    assert cache.exists() and r["fp64_ms"] > 0 and r["fp32_ms"] > 0
+    r2 = _solver(wl).autotune(str(cache))          # cache hit: same shapes, no timing
+    assert r2["fp64"] == r["fp64"] and r2["fp32"] == r["fp32"] and r2["fp64_ms"] == 0.0
+    sig = W.random_density(prob.N, seed=10)
+    y = _n(s.apply(_t(sig)))
+    ref = op.apply(prob, sig)
+    assert np.abs(y - ref).max() / np.abs(ref).max() < 1e-10

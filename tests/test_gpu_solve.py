@@ -1,0 +1,173 @@
+"""GPU end-to-end tests through the C ABI: full-size workloads (sampled where the
+oracle cannot do the whole thing in seconds), FP32 iterative refinement, time
+stepping, error paths and determinism."""
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle import readout as ro
+from oracle import step as ostep
+from paper_1912_04501_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _spm():
+    from paper_1912_04501_amd import spm
+    return spm
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _t(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+@pytest.fixture(scope="module")
+def c25():
+    wl = W.ellipses_25()
+    prob = op.make_problem(wl)
+    x, info = op.solve(prob, tol=1e-12)
+    v, om = ro.velocities(prob, x)
+    print(f"[c25] N={prob.N} close pairs={len(prob.pairs)} oracle its={info['iterations']}", flush=True)
+    return wl, prob, x, v, om, ro.mu_eff(prob, x)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_25_ellipses_solve(c25, precision):
+    """25 ellipses, phi 0.3, ~5,000 nodes, min gap 1e-3. FP64: v, omega, mu_eff to 1e-9 of
+    the oracle. FP32+IR: the FP64 residual reaches 1e-10 (the target of the mixed form);
+    its refinement residual is not Krylov-minimised, so the error against the oracle is
+    larger (stated bound 1e-8; observed ~5e-9 in omega)."""
+    wl, prob, x, v, om, mu = c25
+    spm = _spm()
+    p = spm.SPM_FP64 if precision == "fp64" else spm.SPM_FP32_IR
+    s = spm.Solver("cuda:0", precision=p).set_workload(wl)
+    r = s.solve()
+    info = r["info"]
+    print(f"[c25 {precision}] {info}")
+    assert info["rel_residual"] <= 1e-10
+    if precision == "fp32_ir":
+        assert info["fp32_matvecs"] > 0 and info["refinements"] >= 1
+    gv, go, gm = _n(r["vel"]), _n(r["omega"]), float(r["mu_eff"].item())
+    sc_v = max(np.abs(v).max(), np.hypot(*prob.geom.e2))
+    print(f"omega err {np.abs(go - om).max():.2e}  v err {np.abs(gv - v).max():.2e}  mu err {abs(gm - mu):.2e}")
+    bound = 1e-9 if precision == "fp64" else 1e-8
+    assert np.abs(go - om).max() <= bound * max(1.0, np.abs(om).max())
+    assert np.abs(gv - v).max() <= bound * sc_v
+    assert abs(gm - mu) <= bound * mu
+
+
+@pytest.fixture(scope="module")
+def c200():
+    wl = W.ellipses_200()
+    prob = op.make_problem(wl)
+    print(f"[c200] N={prob.N} close pairs={len(prob.pairs)}", flush=True)
+    return wl, prob
+
+
+def test_200_ellipses_operator_sampled_rows(c200):
+    """N = 51,200 in the configuration the benchmark times: operator rows checked at
+    sampled targets (FP64) and the FP32 near sum against them (FP32 operator)."""
+    wl, prob = c200
+    spm = _spm()
+    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_IR).set_workload(wl)
+    assert np.array_equal(s.close_pairs(), prob.pairs)
+    sig = W.random_density(prob.N, seed=7)
+    rng = np.random.default_rng(3)
+    close_targets = np.unique(prob.pairs[:, 0])
+    rows = np.unique(np.concatenate([rng.choice(prob.N, 48, replace=False), rng.choice(close_targets, 16),
+                                     [0, prob.N - 1]]))
+    ref = op.apply_rows(prob, sig, rows)
+    y = op.to2(_n(s.apply(_t(sig))))[rows]
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"[c200] FP64 operator rows rel err {err:.2e}")
+    assert err < 1e-10
+    y32 = op.to2(_n(s.apply(_t(sig), precision=spm.SPM_FP32)))[rows]
+    err32 = np.abs(y32 - ref).max() / np.abs(ref).max()
+    print(f"[c200] FP32 operator rows rel err {err32:.2e}")
+    assert err32 < 1e-4
+
+
+def test_200_ellipses_solve_properties(c200):
+    """The FP32+IR solve at N = 51,200 satisfies, row-sampled through the oracle's own
+    operator, the BIE to the solver tolerance; the density is force- and torque-free
+    on every particle (Sec. 5 constraints) and mu_eff matches the oracle's functional."""
+    wl, prob = c200
+    spm = _spm()
+    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_IR).set_workload(wl)
+    r = s.solve()
+    print(f"[c200 solve] {r['info']}")
+    assert r["info"]["rel_residual"] <= 1e-10
+    x = _n(r["sigma"])
+    b = op.rhs(prob)
+    rows = np.random.default_rng(4).choice(prob.N, 64, replace=False)
+    res = op.apply_rows(prob, x, rows) - op.to2(b)[rows]
+    assert np.abs(res).max() <= 1e-8 * np.abs(b).max()
+    g = prob.geom
+    s2 = op.to2(x)
+    for i in range(g.No):
+        sl = g.particle_slice(i)
+        rel = g.x[sl] - g.centers[i]
+        F = (g.w[sl, None] * s2[sl]).sum(0)
+        tq = (g.w[sl] * (-rel[:, 1] * s2[sl, 0] + rel[:, 0] * s2[sl, 1])).sum()
+        assert np.abs(F).max() < 1e-6 and abs(tq) < 1e-6
+    assert abs(float(r["mu_eff"].item()) - ro.mu_eff(prob, x)) < 1e-12
+
+
+def test_time_stepping_matches_oracle():
+    """Forward Euler (Sec. 7) through spm_step: centres, angles and the mu_eff series."""
+    wl = W.random_ellipses(3, 0.12, seed=8, nodes=64, skew=0.45)
+    dt, n = 0.05, 4
+    c_ref, th_ref, mu_ref = ostep.euler(wl, dt, n, tol=1e-12)
+    s = _spm().Solver("cuda:0").set_workload(wl)
+    out = s.step(dt, n, 0.0, wl["centers"], wl["theta"])
+    print(f"[step] mu {out['mu_eff']} ref {mu_ref}")
+    assert abs(out["t"] - n * dt) < 1e-15
+    assert np.abs(out["mu_eff"] - mu_ref).max() < 1e-9
+    assert np.abs(out["theta"] - th_ref).max() < 1e-9
+    # centres are compared modulo the lattice (both sides wrap at every step)
+    e2 = np.array([wl["skew"] - np.floor(wl["skew"] + 0.5) + n * dt, 1.0])
+    B = np.array([[1.0, e2[0]], [0.0, 1.0]])
+    d = np.linalg.solve(B, (out["centers"] - c_ref).T).T
+    assert np.abs(d - np.round(d)).max() < 1e-9
+
+
+def test_error_paths():
+    spm = _spm()
+    s = spm.Solver("cuda:0")
+    with pytest.raises(spm.SpmError) as e:
+        s.solve()
+    assert e.value.code == spm.SPM_ESTATE
+    s.set_lattice(0.0)
+    with pytest.raises(spm.SpmError) as e:   # odd node count
+        s.set_ellipses([[0.0, 0.0]], [0.0], [0.2], [0.1], [63])
+    assert e.value.code == spm.SPM_EINVAL
+    with pytest.raises(spm.SpmError) as e:   # two overlapping ellipses
+        s.set_ellipses([[0.0, 0.0], [0.15, 0.0]], [0.0, 0.0], [0.2, 0.2], [0.1, 0.1], [64, 64])
+    assert e.value.code == spm.SPM_EOVERLAP
+    t = spm.Solver("cuda:0", min_gap=0.05)
+    t.set_lattice(0.0)
+    with pytest.raises(spm.SpmError) as e:   # closer than the requested minimum gap
+        t.set_ellipses([[-0.1, 0.0], [0.12, 0.0]], [0.0, 0.0], [0.1, 0.1], [0.05, 0.05], [64, 64])
+    assert e.value.code == spm.SPM_EOVERLAP
+    u = spm.Solver("cuda:0", max_iter=3)
+    u.set_workload(W.random_ellipses(6, 0.3, seed=5, target_total=700))
+    r = u.solve(allow_noconv=True)
+    assert r["info"]["status"] == spm.SPM_ENOCONV and r["info"]["rel_residual"] > 1e-10
+
+
+def test_deterministic():
+    """Fixed-order reductions everywhere: repeated calls are bitwise identical."""
+    wl = W.random_ellipses(6, 0.3, seed=5, target_total=700)
+    s = _spm().Solver("cuda:0").set_workload(wl)
+    sig = _t(W.random_density(s.N, seed=1))
+    a = _n(s.apply(sig))
+    b = _n(s.apply(sig))
+    assert np.array_equal(a, b)
+    r1 = s.solve()
+    r2 = s.solve()
+    assert np.array_equal(_n(r1["sigma"]), _n(r2["sigma"]))
