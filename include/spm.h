@@ -77,6 +77,8 @@ typedef struct {
   double inner_tol;     /* inner relative tolerance of SPM_FP32_IR [1e-5] */
   double min_gap;       /* reject geometries with a periodic boundary gap below this [0] */
   double rcond;         /* proxy pseudo-inverse relative cutoff [1e-14] */
+  int32_t use_graph;    /* replay one captured GMRES iteration as a HIP graph [1] */
+  int32_t poll_every;   /* GMRES iterations between convergence checks on the host [2] */
 } spm_config;
 
 typedef struct {
@@ -138,7 +140,7 @@ int spm_rhs(spm_handle* h, double* out);
 
 /* Solve the completed BIE by GMRES (cfg.precision selects FP64 or FP32_IR) and
  * read out particle velocities vel [2n] (v_x0, v_y0, ...), angular velocities
- * omega [n] and mu_eff (device scalar) - any of the three may be NULL.
+ * omega [n] and mu_eff (device, one value per cell) - any of the three may be NULL.
  * sigma0 (may be NULL) is the initial guess; sigma [2N] receives the density.
  * info (host, may be NULL). Returns SPM_ENOCONV with the last iterate if GMRES
  * does not reach cfg.tol in cfg.max_iter iterations. */
@@ -150,10 +152,11 @@ int spm_solve(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
 int spm_velocities(spm_handle* h, const double* sigma, double* vel, double* omega);
 
 /* Effective viscosity (Sec. 3 eq. mueff, evaluated by the particle-stresslet
- * identity; valid whether or not particles cross the wall D). mu_eff: device scalar. */
+ * identity; valid whether or not particles cross the wall D). mu_eff: device, one
+ * value per cell. */
 int spm_effective_viscosity(spm_handle* h, const double* sigma, double* mu_eff);
 
-/* Forward Euler time stepping (Sec. 7). t_inout (host): time on entry/exit;
+/* Forward Euler time stepping (Sec. 7) of a single-cell handle. t_inout (host): time on entry/exit;
  * the skew follows s(t) = s(0) + gamma t from the lattice set last plus the
  * elapsed time. centers_inout [2n], theta_inout [n] (host) hold the state;
  * mu_eff_series_host [n_steps] receives mu_eff(t_k); infos_host [n_steps] may be NULL. */
@@ -176,30 +179,53 @@ int spm_close_correction(spm_handle* h, const double* sigma, double* out, int32_
  * ordered all first components then all second components. */
 int spm_proxy_strengths(spm_handle* h, const double* sigma, double* xi);
 
+/* ---- ensembles of independent cells ---- */
+
+/* Replace the contents of the handle by n_cells independent unit cells, solved
+ * together (every kernel covers all cells; GMRES runs the cells in lockstep and
+ * freezes each one at its own convergence). skews_host [n_cells]: e2 = (s_c, 1) of
+ * each cell (reduced to [-1/2, 1/2)); part_offsets_host [n_cells + 1]: particles of
+ * cell c are part_offsets[c] .. part_offsets[c+1]-1 of the particle arrays (as in
+ * spm_set_ellipses); every cell is centred at the origin. 1 <= n_cells <= 1024. */
+int spm_set_cells(spm_handle* h, int32_t n_cells, const double* skews_host, const int32_t* part_offsets_host,
+                  const double* centers_host, const double* theta_host, const double* a_host,
+                  const double* b_host, const int32_t* n_nodes_host);
+
+int spm_num_cells(const spm_handle* h, int32_t* n_cells);
+
+/* Solve every cell (as spm_solve). mu_eff: device [n_cells]; infos_host [n_cells]
+ * (may be NULL); cell_latency_s_host [n_cells] (may be NULL): seconds from the start
+ * of the solve to the moment the cell met the tolerance, from the device wall clock.
+ * spm_solve on a handle with several cells behaves the same without latencies. */
+int spm_solve_batch(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
+                    spm_solve_info* infos_host, double* cell_latency_s_host);
+
 /* Number of close (target, source particle, shift) triples, and the triples
  * themselves (host arrays of length count, sorted by target, particle, shift;
  * shift index = 3 (m + 1) + (n + 1) for the image m e1 + n e2). */
 int spm_close_pairs(spm_handle* h, int64_t* count, int32_t* target_host, int32_t* particle_host,
                     int32_t* shift_host, int64_t capacity);
 
-/* The proxy least-squares pseudo-inverse Q^+ (host [2M * 8m], row-major). */
+/* The proxy least-squares pseudo-inverse Q^+ (host [n_cells * 2M * 8m], row-major per cell). */
 int spm_proxy_pinv(spm_handle* h, double* pinv_host);
 
-/* The proxy matrix Q (host [8m * 2M], row-major), the singular values of its
- * Jacobi SVD (host [2M], unsorted, may be NULL) and the number of Jacobi sweeps used. */
+/* The proxy matrix Q (host [n_cells * 8m * 2M], row-major per cell), the singular
+ * values of its Jacobi SVD (host [n_cells * 2M], unsorted, may be NULL) and the number
+ * of Jacobi sweeps used (host [n_cells], may be NULL). */
 int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps_host);
 
 /* ---- launch shape of the near-image sum ---- */
 
-/* Time candidate launch shapes of the near-sum kernel (block 64/128/256 threads,
- * 1/2/4 targets per lane, 128/256/512 sources per LDS tile, source splits) on the
- * handle's current geometry, for FP64 and FP32, and keep the fastest. cache_path
- * (may be NULL): text file of earlier results keyed by device, N and precision;
- * a hit skips the timing, a miss appends. best_ms_host [2] (may be NULL): the
- * winning per-launch time (0 on a cache hit). The shape stays until N changes. */
+/* Time candidate launch shapes of the persistent near-sum kernel (block 64/128/256
+ * threads, 1/2/4 targets per lane, 128/256/512 sources per LDS tile, three source
+ * chunk sizes) on the handle's current geometry (all cells), for FP64 and FP32,
+ * and keep the fastest. cache_path (may be NULL): text file of earlier results
+ * keyed by device, node count, cell count, pair work and precision; a hit skips the
+ * timing, a miss appends. best_ms_host [2] (may be NULL): the winning per-launch
+ * time (0 on a cache hit). The shape stays until the node count changes. */
 int spm_autotune(spm_handle* h, const char* cache_path, double* best_ms_host);
 
-/* Current near-sum launch shape {block, targets per lane, tile, splits} for
+/* Current near-sum launch shape {block, targets per lane, tile, source chunk} for
  * precision SPM_FP64 or SPM_FP32 (host [4]); spm_set_launch overrides it
  * (SPM_EINVAL for an unsupported shape). */
 int spm_get_launch(spm_handle* h, int32_t precision, int32_t* cfg_host);

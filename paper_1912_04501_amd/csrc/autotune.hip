@@ -12,7 +12,6 @@
 
 namespace spm {
 
-void ensure_tpart(spm_handle* h, size_t splits);   // capi.hip
 void launch_prep_for_timing(spm_handle* h);          // capi.hip
 
 static std::string device_name() {
@@ -27,7 +26,9 @@ static std::string device_name() {
 
 static std::string key_of(spm_handle* h, int prec) {
   std::ostringstream o;
-  o << device_name() << " N=" << h->geo.N << " prec=" << (prec == 0 ? "fp64" : "fp32");
+  double work = 0;
+  for (const auto& c : h->cells) work += (double)(c.n1 - c.n0) * (double)(c.n1 - c.n0);
+  o << device_name() << " N=" << h->geo.N << " C=" << h->geo.C << " W=" << work << " prec=" << (prec == 0 ? "fp64" : "fp32");
   return o.str();
 }
 
@@ -40,7 +41,7 @@ static bool cache_lookup(const char* path, const std::string& key, NearConfig& c
     if (bar == std::string::npos || line.substr(0, bar) != key) continue;
     std::istringstream v(line.substr(bar + 1));
     NearConfig t;
-    if (v >> t.block >> t.tpt >> t.tile >> t.splits && near_config_valid(t)) {
+    if (v >> t.block >> t.tpt >> t.tile >> t.chunk && near_config_valid(t)) {
       c = t;
       return true;
     }
@@ -51,12 +52,14 @@ static bool cache_lookup(const char* path, const std::string& key, NearConfig& c
 static void cache_store(const char* path, const std::string& key, const NearConfig& c, double ms) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << "|" << c.block << " " << c.tpt << " " << c.tile << " " << c.splits << " " << ms << "\n";
+  f << key << "|" << c.block << " " << c.tpt << " " << c.tile << " " << c.chunk << " " << ms << "\n";
 }
 
 double time_near(spm_handle* h, int prec, const NearConfig& c, int reps) {
-  NearConfig saved = h->wk.near[prec];
-  h->wk.near[prec] = c;
+  NearPlan& P = h->wk.near[prec];
+  const NearConfig saved = P.cfg;
+  P.cfg = c;
+  build_near_plan(h, prec == 0 ? SPM_FP64 : SPM_FP32);
   const bool prof = h->prof;
   h->prof = false;
   hipEvent_t a, b;
@@ -71,23 +74,23 @@ double time_near(spm_handle* h, int prec, const NearConfig& c, int reps) {
   SPM_HIP_CHECK(hipEventElapsedTime(&ms, a, b));
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
-  h->wk.near[prec] = saved;
+  P.cfg = saved;
+  build_near_plan(h, prec == 0 ? SPM_FP64 : SPM_FP32);
   h->prof = prof;
   return (double)ms / reps;
 }
 
-NearConfig heuristic_near(int64_t N, int block, int tpt, int tile);  // capi.hip
-
 void autotune(spm_handle* h, const char* cache_path, double* best_ms_out) {
-  const int64_t N = h->geo.N;
   launch_prep_for_timing(h);
+  double work = 0;
+  for (const auto& c : h->cells) work += (double)(c.n1 - c.n0) * (double)(c.n1 - c.n0);
   for (int prec = 0; prec < 2; ++prec) {
     const std::string key = key_of(h, prec);
     NearConfig best;
     double best_ms = -1.0;
     if (cache_lookup(cache_path, key, best)) {
-      ensure_tpart(h, (size_t)best.splits);
-      h->wk.near[prec] = best;
+      h->wk.near[prec].cfg = best;
+      build_near_plan(h, prec == 0 ? SPM_FP64 : SPM_FP32);
       if (best_ms_out) best_ms_out[prec] = 0.0;
       continue;
     }
@@ -95,21 +98,20 @@ void autotune(spm_handle* h, const char* cache_path, double* best_ms_out) {
     for (int block : {64, 128, 256})
       for (int tpt : {1, 2, 4})
         for (int tile : {128, 256, 512}) {
-          const NearConfig base = heuristic_near(N, block, tpt, tile);
-          for (int f : {1, 2, 4}) {
-            NearConfig c = base;
-            c.splits = std::max(1, std::min<int>(base.splits * f / 2 > 0 ? base.splits * f / 2 : 1,
-                                                 (int)std::max<int64_t>(1, N / 64)));
+          // chunks giving about 2048, 8192 and 32768 work items
+          for (double items : {2048.0, 8192.0, 32768.0}) {
+            NearConfig c;
+            c.block = block;
+            c.tpt = tpt;
+            c.tile = tile;
+            c.chunk = (int32_t)std::max(64.0, std::min(65536.0, work / ((double)block * tpt * items)));
             if (std::find_if(cand.begin(), cand.end(), [&](const NearConfig& o) {
-                  return o.block == c.block && o.tpt == c.tpt && o.tile == c.tile && o.splits == c.splits;
+                  return o.block == c.block && o.tpt == c.tpt && o.tile == c.tile && o.chunk == c.chunk;
                 }) == cand.end())
               cand.push_back(c);
           }
         }
-    size_t smax = 1;
-    for (const auto& c : cand) smax = std::max(smax, (size_t)c.splits);
-    ensure_tpart(h, smax);
-    const int reps = N > 20000 ? 2 : 5;
+    const int reps = work > 4e8 ? 2 : 5;
     for (const auto& c : cand) {
       const double ms = time_near(h, prec, c, reps);
       if (best_ms < 0 || ms < best_ms) {
@@ -117,12 +119,13 @@ void autotune(spm_handle* h, const char* cache_path, double* best_ms_out) {
         best = c;
       }
     }
-    h->wk.near[prec] = best;
+    h->wk.near[prec].cfg = best;
+    build_near_plan(h, prec == 0 ? SPM_FP64 : SPM_FP32);
     if (best_ms_out) best_ms_out[prec] = best_ms;
     cache_store(cache_path, key, best, best_ms);
   }
   h->wk.tuned = true;
-  h->wk.tuned_N = N;
+  h->wk.tuned_N = h->geo.N;
 }
 
 }  // namespace spm

@@ -1,7 +1,8 @@
-// C ABI of the solver: handle, setup, matvec pipeline, GMRES driver, readouts, time stepping.
+// C ABI of the solver: handle, setup of an ensemble of cells, matvec pipeline, GMRES
+// driver (FP64 and FP32 + FP64 iterative refinement), readouts, time stepping.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
-#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -13,18 +14,17 @@
 using namespace spm;
 
 namespace spm {
-// Default near-sum launch shape: enough source splits for ~8 waves per SIMD, at
-// least 128 sources per split.
-NearConfig heuristic_near(int64_t N, int block, int tpt, int tile) {
+// Default near-sum launch shape: 256 threads, one target per lane, 256-source tiles,
+// and a source chunk that gives about 8192 work items over the ensemble.
+NearConfig heuristic_near(spm_handle* h) {
   NearConfig c;
-  c.block = block;
-  c.tpt = tpt;
-  c.tile = tile;
-  const int64_t nblocks = (N + block * tpt - 1) / (block * tpt);
-  const int64_t waves = nblocks * (block / 64);
-  int64_t S = (8192 + waves - 1) / waves;
-  S = std::max<int64_t>(1, std::min<int64_t>(S, std::max<int64_t>(1, N / 128)));
-  c.splits = (int32_t)S;
+  c.block = 256;
+  c.tpt = 1;
+  c.tile = 256;
+  double work = 0;
+  for (const auto& cl : h->cells) work += (double)(cl.n1 - cl.n0) * (double)(cl.n1 - cl.n0);
+  const double chunk = work / (256.0 * 8192.0);
+  c.chunk = (int32_t)std::max(128.0, std::min(65536.0, chunk));
   return c;
 }
 }  // namespace spm
@@ -64,7 +64,7 @@ template <typename T>
 void ensure(spm_handle* h, T*& p, size_t count) {
   auto& cap = g_slots[h].cap;
   void** key = reinterpret_cast<void**>(&p);
-  const size_t bytes = count * sizeof(T);
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
   auto it = cap.find(key);
   if (it != cap.end() && it->second >= bytes && p) return;
   if (p) raw_free(h, p);
@@ -83,13 +83,20 @@ void free_all(spm_handle* h) {
   g_slots.erase(it);
 }
 
+void sync(spm_handle* h) { SPM_HIP_CHECK(hipStreamSynchronize(h->stream)); }
+
 // Setup-time upload from pageable host memory; waits so the source may be freed on return.
 void upload(spm_handle* h, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return;
   SPM_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->stream));
   SPM_HIP_CHECK(hipStreamSynchronize(h->stream));
 }
 
-void sync(spm_handle* h) { SPM_HIP_CHECK(hipStreamSynchronize(h->stream)); }
+void download(spm_handle* h, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return;
+  SPM_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, h->stream));
+  SPM_HIP_CHECK(hipStreamSynchronize(h->stream));
+}
 
 bool verbose() {
   static const bool v = std::getenv("SPM_VERBOSE") != nullptr;
@@ -100,7 +107,7 @@ double now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Gauss-Legendre nodes/weights on [-1, 1] by Newton iteration on P_m.
+// Gauss-Legendre nodes/weights on [-1, 1] (ascending) by Newton iteration on P_m.
 void gauss_legendre(int m, std::vector<double>& t, std::vector<double>& w) {
   t.assign(m, 0.0);
   w.assign(m, 0.0);
@@ -130,7 +137,6 @@ void gauss_legendre(int m, std::vector<double>& t, std::vector<double>& w) {
     }
     t[i] = x;
   }
-  // ascending order (-1 -> 1)
   for (int i = 0, j = m - 1; i < j; ++i, --j) {
     std::swap(t[i], t[j]);
     std::swap(w[i], w[j]);
@@ -159,67 +165,117 @@ int guarded(spm_handle* h, F&& f) {
 }
 
 void need_particles(spm_handle* h) {
-  if (!h->have_lattice || !h->have_particles) throw ApiError(SPM_ESTATE, "set the lattice and the particles first");
+  if (!h->have_particles) throw ApiError(SPM_ESTATE, "set the lattice and the particles (or the cells) first");
+}
+
+void drop_graphs(spm_handle* h) {
+  for (int k = 0; k < 2; ++k) {
+    if (h->kr.graph[k]) (void)hipGraphExecDestroy(h->kr.graph[k]);
+    if (h->kr.graph_src[k]) (void)hipGraphDestroy(h->kr.graph_src[k]);
+    h->kr.graph[k] = nullptr;
+    h->kr.graph_src[k] = nullptr;
+  }
+}
+
+template <typename T>
+T* host_scratch(spm_handle* h, size_t count) {
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  if (h->kr.host_bytes < bytes) {
+    if (h->kr.host) SPM_HIP_CHECK(hipHostFree(h->kr.host));
+    h->kr.host = nullptr;
+    SPM_HIP_CHECK(hipHostMalloc(&h->kr.host, bytes, hipHostMallocDefault));
+    h->kr.host_bytes = bytes;
+  }
+  return static_cast<T*>(h->kr.host);
 }
 
 // ---------------------------------------------------------------------------
-// lattice: walls, proxies, Q and its pseudo-inverse
+// setup
 // ---------------------------------------------------------------------------
-void build_lattice(spm_handle* h) {
+void build_periodizers(spm_handle* h) {
   Periodizer& P = h->per;
+  const int C = h->geo.C;
   P.m = h->cfg.m_wall;
   P.M = h->cfg.M;
   const int m = P.m, M = P.M;
-  ensure(h, P.wx, 2 * m);
-  ensure(h, P.wy, 2 * m);
+  ensure(h, P.wx, (size_t)C * 2 * m);
+  ensure(h, P.wy, (size_t)C * 2 * m);
   ensure(h, P.px, M);
   ensure(h, P.py, M);
-  ensure(h, P.Q, (size_t)8 * m * 2 * M);
-  ensure(h, P.Qp, (size_t)8 * m * 2 * M);
-  ensure(h, P.svd_a, (size_t)8 * m * 2 * M);
-  ensure(h, P.svd_v, (size_t)4 * M * M);
-  ensure(h, P.svd_s, (size_t)2 * M + 1);
+  ensure(h, P.Q, (size_t)C * 8 * m * 2 * M);
+  ensure(h, P.Qp, (size_t)C * 8 * m * 2 * M);
+  ensure(h, P.svd_a, (size_t)C * 8 * m * 2 * M);
+  ensure(h, P.svd_v, (size_t)C * 4 * M * M);
+  ensure(h, P.svd_s, (size_t)C * (2 * M + 1));
   std::vector<double> t, w;
   gauss_legendre(m, t, w);
-  std::vector<double> wx(2 * m), wy(2 * m), px(M), py(M);
-  for (int i = 0; i < m; ++i) {
-    const double s = 0.5 * t[i];
-    wx[i] = h->cU[0] - 0.5 * h->e1[0] + s * h->e2[0];
-    wy[i] = h->cU[1] - 0.5 * h->e1[1] + s * h->e2[1];
-    wx[m + i] = h->cU[0] - 0.5 * h->e2[0] + s * h->e1[0];
-    wy[m + i] = h->cU[1] - 0.5 * h->e2[1] + s * h->e1[1];
+  std::vector<double> wx((size_t)C * 2 * m), wy((size_t)C * 2 * m), px(M), py(M);
+  for (int c = 0; c < C; ++c) {
+    const double s = h->cells[c].skew;
+    for (int i = 0; i < m; ++i) {
+      const double u = 0.5 * t[i];
+      // L(u) = c_U - e1/2 + u e2 ; D(u) = c_U - e2/2 + u e1
+      wx[(size_t)c * 2 * m + i] = h->cU[0] - 0.5 + u * s;
+      wy[(size_t)c * 2 * m + i] = h->cU[1] + u;
+      wx[(size_t)c * 2 * m + m + i] = h->cU[0] - 0.5 * s + u;
+      wy[(size_t)c * 2 * m + m + i] = h->cU[1] - 0.5;
+    }
   }
   for (int p = 0; p < M; ++p) {
     const double th = 2.0 * kPi * p / M;
     px[p] = h->cU[0] + h->cfg.R_proxy * std::cos(th);
     py[p] = h->cU[1] + h->cfg.R_proxy * std::sin(th);
   }
-  const double l2 = std::hypot(h->e2[0], h->e2[1]);
-  P.nL[0] = h->e2[1] / l2;
-  P.nL[1] = -h->e2[0] / l2;
-  P.nD[0] = 0.0;
-  P.nD[1] = 1.0;
-  upload(h, P.wx, wx.data(), 2 * m * sizeof(double));
-  upload(h, P.wy, wy.data(), 2 * m * sizeof(double));
+  upload(h, P.wx, wx.data(), wx.size() * sizeof(double));
+  upload(h, P.wy, wy.data(), wy.size() * sizeof(double));
   upload(h, P.px, px.data(), M * sizeof(double));
   upload(h, P.py, py.data(), M * sizeof(double));
   launch_build_Q(h);
   launch_pinv(h);
-  ensure(h, h->wk.xi, (size_t)2 * M);
-  ensure(h, h->wk.scal, 16);
+  ensure(h, h->wk.xi, (size_t)C * 2 * M);
 }
 
-size_t max_splits(spm_handle* h) { return (size_t)std::max(h->wk.near[0].splits, h->wk.near[1].splits); }
-
-void choose_launch(spm_handle* h) {
-  const int64_t N = h->geo.N;
-  Work& W = h->wk;
-  if (W.tuned && W.tuned_N != N) W.tuned = false;
-  if (!W.tuned) {
-    W.near[0] = heuristic_near(N, 256, 1, 256);
-    W.near[1] = heuristic_near(N, 256, 1, 256);
+// work items of the wall discrepancy (source chunks of each cell) and the dot segments
+void build_chunks(spm_handle* h) {
+  const int C = h->geo.C;
+  std::vector<int64_t> s0, s1, n0, n1;
+  std::vector<int32_t> cc, off(C + 1, 0), sc, soff(C + 1, 0);
+  for (int c = 0; c < C; ++c) {
+    const int64_t a = h->cells[c].n0, b = h->cells[c].n1;
+    for (int64_t x = a; x < b; x += 2048) {
+      s0.push_back(x);
+      s1.push_back(std::min(b, x + 2048));
+      cc.push_back(c);
+    }
+    off[c + 1] = (int32_t)s0.size();
+    for (int64_t x = a; x < b; x += 4096) {
+      n0.push_back(x);
+      n1.push_back(std::min(b, x + 4096));
+      sc.push_back(c);
+    }
+    soff[c + 1] = (int32_t)n0.size();
   }
-  W.nchunk_disc = (int32_t)std::max<int64_t>(1, (N + 2047) / 2048);
+  Work& W = h->wk;
+  W.ndisc = (int32_t)s0.size();
+  ensure(h, W.disc_s0, s0.size());
+  ensure(h, W.disc_s1, s1.size());
+  ensure(h, W.disc_cell, cc.size());
+  ensure(h, W.disc_off, C + 1);
+  upload(h, W.disc_s0, s0.data(), s0.size() * sizeof(int64_t));
+  upload(h, W.disc_s1, s1.data(), s1.size() * sizeof(int64_t));
+  upload(h, W.disc_cell, cc.data(), cc.size() * sizeof(int32_t));
+  upload(h, W.disc_off, off.data(), off.size() * sizeof(int32_t));
+  ensure(h, W.disc, (size_t)W.ndisc * 2 * h->per.m * 4);
+  Krylov& K = h->kr;
+  K.nseg = (int32_t)n0.size();
+  ensure(h, K.seg_n0, n0.size());
+  ensure(h, K.seg_n1, n1.size());
+  ensure(h, K.seg_cell, sc.size());
+  ensure(h, K.seg_off, C + 1);
+  upload(h, K.seg_n0, n0.data(), n0.size() * sizeof(int64_t));
+  upload(h, K.seg_n1, n1.data(), n1.size() * sizeof(int64_t));
+  upload(h, K.seg_cell, sc.data(), sc.size() * sizeof(int32_t));
+  upload(h, K.seg_off, soff.data(), soff.size() * sizeof(int32_t));
 }
 
 void alloc_work(spm_handle* h) {
@@ -230,214 +286,506 @@ void alloc_work(spm_handle* h) {
   ensure(h, W.f1f, N);
   ensure(h, W.f2f, N);
   ensure(h, W.T, 2 * N);
-  ensure(h, W.Tpart, max_splits(h) * 2 * N);
   ensure(h, W.pF, (size_t)4 * h->geo.No);
-  ensure(h, W.disc, (size_t)W.nchunk_disc * 2 * h->per.m * 4);
+  ensure(h, W.scal, 16);
 }
 
 void alloc_krylov(spm_handle* h) {
   Krylov& K = h->kr;
   const int64_t n2 = 2 * h->geo.N;
-  const int kmax = std::max(1, h->cfg.max_iter);
+  const int C = h->geo.C;
+  const int kmax = std::max(2, h->cfg.max_iter);
   K.kmax = kmax;
   K.n2 = n2;
-  K.nchunk = (int32_t)std::min<int64_t>(256, std::max<int64_t>(1, n2 / 2048));
   ensure(h, K.V, (size_t)(kmax + 1) * n2);
-  ensure(h, K.H, (size_t)(kmax + 1) * kmax);
-  ensure(h, K.cs, kmax);
-  ensure(h, K.sn, kmax);
-  ensure(h, K.g, kmax + 1);
-  ensure(h, K.yv, kmax);
-  ensure(h, K.h, (size_t)2 * (kmax + 1) + 8);
-  ensure(h, K.part, (size_t)K.nchunk * (kmax + 1));
+  ensure(h, K.H, (size_t)C * kmax * (kmax + 1));
+  ensure(h, K.cs, (size_t)C * kmax);
+  ensure(h, K.sn, (size_t)C * kmax);
+  ensure(h, K.g, (size_t)C * (kmax + 1));
+  ensure(h, K.yv, (size_t)C * kmax);
+  ensure(h, K.h1, (size_t)C * (kmax + 1));
+  ensure(h, K.h2, (size_t)C * (kmax + 1));
+  ensure(h, K.nrm2, C);
+  ensure(h, K.bnorm, C);
+  ensure(h, K.tolc, C);
+  ensure(h, K.res, C);
+  ensure(h, K.active, C);
+  ensure(h, K.kdone, C);
+  ensure(h, K.mask, C);
+  ensure(h, K.stamp, C + 1);
+  ensure(h, K.jdev, 2);
+  ensure(h, K.part, (size_t)std::max(1, K.nseg) * (kmax + 1));
   ensure(h, K.tmp, n2);
   ensure(h, K.tmp2, n2);
-  ensure(h, K.res, 8);
-  if (!K.host_res) SPM_HIP_CHECK(hipHostMalloc((void**)&K.host_res, 8 * sizeof(double), hipHostMallocDefault));
+  ensure(h, K.vin, n2);
+  ensure(h, K.w, n2);
+  ensure(h, K.b, n2);
+  ensure(h, K.d, n2);
+  ensure(h, K.dots, C);
+}
+
+void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* part_off, const double* centers,
+                    const double* theta, const double* a, const double* b, const int32_t* n_nodes) {
+  if (C < 1 || C > 1024) throw ApiError(SPM_EINVAL, "number of cells must be in [1, 1024]");
+  const int n = part_off[C];
+  if (part_off[0] != 0 || n < 1) throw ApiError(SPM_EINVAL, "bad particle offsets");
+  h->have_particles = false;
+  drop_graphs(h);
+  h->cells.assign(C, CellHost());
+  h->cx.resize(n);
+  h->cy.resize(n);
+  h->th.assign(theta, theta + n);
+  h->a.assign(a, a + n);
+  h->b.assign(b, b + n);
+  h->nn.assign(n_nodes, n_nodes + n);
+  h->off.assign(n + 1, 0);
+  h->pcell.assign(n, 0);
+  for (int c = 0; c < C; ++c) {
+    CellHost& cl = h->cells[c];
+    if (part_off[c + 1] <= part_off[c]) throw ApiError(SPM_EINVAL, "every cell needs at least one particle");
+    if (!std::isfinite(skews[c])) throw ApiError(SPM_EINVAL, "bad skew");
+    cl.skew_raw = skews[c];
+    cl.skew = skews[c] - std::floor(skews[c] + 0.5);
+    cl.p0 = part_off[c];
+    cl.p1 = part_off[c + 1];
+    const double s = cl.skew;  // e1 = (1, 0), e2 = (s, 1), det = 1
+    for (int i = cl.p0; i < cl.p1; ++i) {
+      if (!(a[i] > 0) || !(b[i] > 0) || !std::isfinite(centers[2 * i]) || !std::isfinite(centers[2 * i + 1]) ||
+          !std::isfinite(theta[i]))
+        throw ApiError(SPM_EINVAL, "bad ellipse " + std::to_string(i));
+      if (n_nodes[i] < 8 || n_nodes[i] > kMaxNodesPerParticle || (n_nodes[i] & 1))
+        throw ApiError(SPM_EINVAL, "node count must be even and in [8, 512]");
+      if (std::max(a[i], b[i]) >= 0.45) throw ApiError(SPM_EINVAL, "ellipse larger than the 3x3 image rule allows");
+      // wrap: (alpha, beta) = [e1 e2]^{-1} (c - c_U), reduced to [-1/2, 1/2)
+      const double dx = centers[2 * i] - h->cU[0], dy = centers[2 * i + 1] - h->cU[1];
+      double be = dy;
+      double al = dx - s * dy;
+      al -= std::floor(al + 0.5);
+      be -= std::floor(be + 0.5);
+      h->cx[i] = h->cU[0] + al + be * s;
+      h->cy[i] = h->cU[1] + be;
+      h->off[i + 1] = h->off[i] + n_nodes[i];
+      h->pcell[i] = c;
+    }
+    cl.n0 = h->off[cl.p0];
+    cl.n1 = h->off[cl.p1];
+  }
+  Geo& g = h->geo;
+  g.No = n;
+  g.C = C;
+  g.N = h->off[n];
+  const int64_t N = g.N;
+  if (N > (int64_t)1 << 30) throw ApiError(SPM_EINVAL, "too many nodes");
+  for (double** p : {&g.x, &g.y, &g.nx, &g.ny, &g.w, &g.kap, &g.tx, &g.ty, &g.xpx, &g.xpy}) ensure(h, *p, N);
+  for (float** p : {&g.xf, &g.yf, &g.nxf, &g.nyf}) ensure(h, *p, N);
+  ensure(h, g.pid, N);
+  ensure(h, g.ncell, N);
+  for (double** p : {&g.pcx, &g.pcy, &g.pth, &g.pa, &g.pb, &g.pper}) ensure(h, *p, n);
+  ensure(h, g.poff, n + 1);
+  ensure(h, g.pn, n);
+  ensure(h, g.pcell, n);
+  ensure(h, g.cnoff, C + 1);
+  ensure(h, g.cpoff, C + 1);
+  ensure(h, g.cskew, C);
+  std::vector<int32_t> pid(N), ncell(N);
+  for (int i = 0; i < n; ++i)
+    for (int k = h->off[i]; k < h->off[i + 1]; ++k) {
+      pid[k] = i;
+      ncell[k] = h->pcell[i];
+    }
+  std::vector<int64_t> cnoff(C + 1);
+  std::vector<int32_t> cpoff(C + 1);
+  std::vector<double> cskew(C);
+  for (int c = 0; c < C; ++c) {
+    cnoff[c] = h->cells[c].n0;
+    cpoff[c] = h->cells[c].p0;
+    cskew[c] = h->cells[c].skew;
+  }
+  cnoff[C] = N;
+  cpoff[C] = n;
+  upload(h, g.pid, pid.data(), N * sizeof(int32_t));
+  upload(h, g.ncell, ncell.data(), N * sizeof(int32_t));
+  upload(h, g.pcx, h->cx.data(), n * sizeof(double));
+  upload(h, g.pcy, h->cy.data(), n * sizeof(double));
+  upload(h, g.pth, h->th.data(), n * sizeof(double));
+  upload(h, g.pa, h->a.data(), n * sizeof(double));
+  upload(h, g.pb, h->b.data(), n * sizeof(double));
+  upload(h, g.poff, h->off.data(), (n + 1) * sizeof(int32_t));
+  upload(h, g.pn, h->nn.data(), n * sizeof(int32_t));
+  upload(h, g.pcell, h->pcell.data(), n * sizeof(int32_t));
+  upload(h, g.cnoff, cnoff.data(), (C + 1) * sizeof(int64_t));
+  upload(h, g.cpoff, cpoff.data(), (C + 1) * sizeof(int32_t));
+  upload(h, g.cskew, cskew.data(), C * sizeof(double));
+  launch_geometry(h);
+  build_periodizers(h);
+  // close pairs + overlap check
+  CloseList& CL = h->cl;
+  ensure(h, CL.count, N);
+  ensure(h, CL.row, N + 1);
+  ensure(h, CL.tlist, N);
+  ensure(h, CL.dmin, N);
+  ensure(h, CL.inside, N);
+  ensure(h, CL.vp, 6 * N);
+  alloc_work(h);
+  launch_close_count(h);
+  double gap;
+  int32_t overlap;
+  launch_gap(h, &gap, &overlap);
+  h->min_gap_est = gap;
+  if (overlap || (h->cfg.min_gap > 0 && gap < h->cfg.min_gap))
+    throw ApiError(SPM_EOVERLAP, overlap ? "particles overlap" : "particles closer than min_gap");
+  int32_t total, nt;
+  launch_close_scan(h, &total, &nt);
+  CL.npairs = total;
+  CL.ntargets = nt;
+  ensure(h, CL.q, std::max<int64_t>(1, total));
+  ensure(h, CL.s, std::max<int64_t>(1, total));
+  if (total > 0) launch_close_fill(h);
+  build_chunks(h);
+  alloc_krylov(h);
+  if (h->wk.tuned && h->wk.tuned_N != N) h->wk.tuned = false;
+  if (!h->wk.tuned) {
+    h->wk.near[0].cfg = heuristic_near(h);
+    h->wk.near[1].cfg = heuristic_near(h);
+  }
+  build_near_plan(h, SPM_FP64);
+  build_near_plan(h, SPM_FP32);
+  sync(h);
+  h->have_particles = true;
 }
 
 // ---------------------------------------------------------------------------
 // operator
 // ---------------------------------------------------------------------------
-void stage_xi(spm_handle* h, const double* sigma) {
+void stage_xi(spm_handle* h, const double* sigma, bool with_active) {
   launch_prep(h, sigma);
-  launch_disc(h);
-  launch_xi(h);
+  launch_disc_impl(h, with_active);
+  launch_xi_impl(h, with_active);
 }
 
-void matvec(spm_handle* h, const double* sigma, double* out, int precision) {
-  stage_xi(h, sigma);
-  launch_near(h, precision);
+void matvec(spm_handle* h, const double* sigma, double* out, int precision, bool with_active) {
+  stage_xi(h, sigma, with_active);
+  launch_near_impl(h, precision, with_active);
   launch_combine(h, sigma, true, precision);
   if (h->cl.ntargets > 0) {
     launch_vplus(h, sigma);
-    launch_close_apply(h, sigma, h->wk.T, precision);
+    launch_close_apply_impl(h, h->wk.T, precision, with_active);
   }
   launch_assemble(h, sigma, out);
 }
 
-double host_dot(spm_handle* h, const double* a, const double* b) {
-  double* out = h->kr.res + 4;
-  gm_dot_many(h, a, 0, 1, b, out);
-  SPM_HIP_CHECK(hipMemcpyAsync(h->kr.host_res + 4, out, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  sync(h);
-  return h->kr.host_res[4];
+// one GMRES iteration of every active cell (fixed arguments: capturable)
+void iteration(spm_handle* h, int precision) {
+  Krylov& K = h->kr;
+  gm_copy_in(h);
+  matvec(h, K.vin, K.w, precision, true);
+  gm_cgs_pass(h, K.w, K.h1);
+  gm_update_j(h, K.h1, K.w);
+  gm_cgs_pass(h, K.w, K.h2);
+  gm_update_j(h, K.h2, K.w);
+  gm_dot(h, K.w, K.w, K.nrm2);
+  gm_store_next(h);
+  gm_givens(h);
 }
 
-struct KrylovResult {
-  int iterations = 0;
-  bool converged = false;
-  double est = 0.0;
+hipGraphExec_t iteration_graph(spm_handle* h, int precision) {
+  const int k = precision == SPM_FP64 ? 0 : 1;
+  Krylov& K = h->kr;
+  if (K.graph[k]) return K.graph[k];
+  if (!K.cap_stream) SPM_HIP_CHECK(hipStreamCreateWithFlags(&K.cap_stream, hipStreamNonBlocking));
+  hipStream_t saved = h->stream;
+  h->stream = K.cap_stream;
+  try {
+    SPM_HIP_CHECK(hipStreamBeginCapture(K.cap_stream, hipStreamCaptureModeThreadLocal));
+    iteration(h, precision);
+    SPM_HIP_CHECK(hipStreamEndCapture(K.cap_stream, &K.graph_src[k]));
+  } catch (...) {
+    hipGraph_t dummy = nullptr;
+    (void)hipStreamEndCapture(K.cap_stream, &dummy);
+    if (dummy) (void)hipGraphDestroy(dummy);
+    h->stream = saved;
+    throw;
+  }
+  h->stream = saved;
+  SPM_HIP_CHECK(hipGraphInstantiate(&K.graph[k], K.graph_src[k], nullptr, nullptr, 0));
+  return K.graph[k];
+}
+
+// per-cell (host) state of one solve
+struct CellStats {
+  std::vector<int32_t> its, m64, m32, refine;
+  std::vector<double> bnorm, rel;
+  explicit CellStats(int C) : its(C, 0), m64(C, 0), m32(C, 0), refine(C, 0), bnorm(C, 0), rel(C, 1) {}
 };
 
-// GMRES for A x = b (A at `precision`), x holds the initial guess if x_nonzero.
-// Stops when |g_{j+1}| <= tol * bnorm.
-KrylovResult gmres(spm_handle* h, int precision, const double* b, double* x, bool x_nonzero, double tol, int maxit,
-                   double bnorm, spm_solve_info* info) {
-  Krylov& K = h->kr;
-  const int64_t n2 = K.n2;
-  double* V = K.V;
-  double* h1 = K.h;
-  double* h2 = K.h + K.kmax + 1;
-  double* nrm2 = K.h + 2 * (K.kmax + 1);
-  KrylovResult R;
-  if (x_nonzero) {
-    matvec(h, x, K.tmp, precision);
-    if (precision == SPM_FP64) info->fp64_matvecs++; else info->fp32_matvecs++;
-    gm_axpby(h, n2, 1.0, b, -1.0, K.tmp, V);
-  } else {
-    gm_copy(h, V, b, n2);
-  }
-  gm_dot_many(h, V, 0, 1, V, nrm2);
-  gm_init(h, nrm2);
-  gm_scale_by_norm(h, nrm2, V, n2, nullptr);
-  SPM_HIP_CHECK(hipMemcpyAsync(K.host_res, nrm2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+void upload_cell_arrays(spm_handle* h, const std::vector<double>& bn, const std::vector<double>& tol,
+                        const std::vector<int32_t>& act) {
+  const int C = h->geo.C;
+  double* hb = host_scratch<double>(h, 3 * (size_t)C);
+  std::memcpy(hb, bn.data(), C * sizeof(double));
+  std::memcpy(hb + C, tol.data(), C * sizeof(double));
+  int32_t* ha = reinterpret_cast<int32_t*>(hb + 2 * C);
+  std::memcpy(ha, act.data(), C * sizeof(int32_t));
+  SPM_HIP_CHECK(hipMemcpyAsync(h->kr.bnorm, hb, C * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  SPM_HIP_CHECK(hipMemcpyAsync(h->kr.tolc, hb + C, C * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  SPM_HIP_CHECK(hipMemcpyAsync(h->kr.active, ha, C * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   sync(h);
-  const double beta = std::sqrt(K.host_res[0]);
-  R.est = beta / bnorm;
-  if (beta <= tol * bnorm) {
-    R.converged = true;
-    return R;
-  }
-  maxit = std::min(maxit, K.kmax);
-  int k = 0;
-  for (int j = 0; j < maxit; ++j) {
-    double* w = V + (int64_t)(j + 1) * n2;
-    matvec(h, V + (int64_t)j * n2, w, precision);
-    if (precision == SPM_FP64) info->fp64_matvecs++; else info->fp32_matvecs++;
-    gm_dot_many(h, V, n2, j + 1, w, h1);
-    gm_update(h, V, n2, j + 1, h1, w, -1.0);
-    gm_dot_many(h, V, n2, j + 1, w, h2);
-    gm_update(h, V, n2, j + 1, h2, w, -1.0);
-    gm_dot_many(h, w, 0, 1, w, nrm2);
-    gm_scale_by_norm(h, nrm2, w, n2, nullptr);
-    gm_givens(h, j, h1, h2, nrm2, bnorm, K.res);
-    SPM_HIP_CHECK(hipMemcpyAsync(K.host_res, K.res, 2 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    sync(h);
-    k = j + 1;
-    R.est = K.host_res[0];
-    if (!std::isfinite(R.est)) throw ApiError(SPM_EHIP, "GMRES residual is not finite");
-    if (R.est <= tol) {
-      R.converged = true;
-      break;
+}
+
+// GMRES cycle on V_0 = r for the cells in `act` (others untouched); x += correction.
+// Returns the Krylov iterations of every cell.
+std::vector<int32_t> krylov_cycle(spm_handle* h, int precision, double* x, const std::vector<double>& bn,
+                                  const std::vector<double>& tol, const std::vector<int32_t>& act, int maxit) {
+  Krylov& K = h->kr;
+  const int C = h->geo.C;
+  upload_cell_arrays(h, bn, tol, act);
+  gm_start(h);
+  int32_t* hj = host_scratch<int32_t>(h, 2);
+  download(h, hj, K.jdev, 2 * sizeof(int32_t));
+  maxit = std::max(0, std::min(maxit, K.kmax));
+  const bool graph = h->cfg.use_graph != 0 && !h->prof;
+  const int poll = std::max(1, h->cfg.poll_every);
+  int done = 0;
+  if (hj[1] > 0) {
+    hipGraphExec_t ge = graph ? iteration_graph(h, precision) : nullptr;
+    for (int it = 0; it < maxit; ++it) {
+      if (graph)
+        SPM_HIP_CHECK(hipGraphLaunch(ge, h->stream));
+      else
+        iteration(h, precision);
+      ++done;
+      if ((it + 1) % poll == 0 || it + 1 == maxit) {
+        SPM_HIP_CHECK(hipMemcpyAsync(hj, K.jdev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        sync(h);
+        if (hj[1] == 0) break;
+      }
     }
   }
-  R.iterations = k;
-  if (k > 0) {
-    gm_backsolve(h, k);
-    gm_update(h, V, n2, k, K.yv, x, 1.0);
-  }
-  return R;
+  gm_backsolve_update(h, x);
+  std::vector<int32_t> kd(C, 0);
+  int32_t* hk = host_scratch<int32_t>(h, C);
+  download(h, hk, K.kdone, C * sizeof(int32_t));
+  for (int c = 0; c < C; ++c) kd[c] = act[c] ? hk[c] : 0;
+  (void)done;
+  return kd;
 }
 
-double true_residual(spm_handle* h, const double* b, const double* x, double bnorm, spm_solve_info* info) {
+// r = b - A x per cell for the cells in act; rel_c = |r_c| / |b_c|. r goes to tmp2.
+void residual(spm_handle* h, const double* x, const std::vector<int32_t>& act, CellStats& st) {
   Krylov& K = h->kr;
-  matvec(h, x, K.tmp, SPM_FP64);
-  info->fp64_matvecs++;
-  gm_axpby(h, K.n2, 1.0, b, -1.0, K.tmp, K.tmp2);
-  return std::sqrt(host_dot(h, K.tmp2, K.tmp2)) / bnorm;
+  const int C = h->geo.C;
+  upload_cell_arrays(h, st.bnorm, std::vector<double>(C, 0.0), act);
+  matvec(h, x, K.tmp, SPM_FP64, true);
+  gm_axpby(h, K.n2, 1.0, K.b, -1.0, K.tmp, K.tmp2);
+  gm_dot(h, K.tmp2, K.tmp2, K.dots);
+  double* hd = host_scratch<double>(h, C);
+  download(h, hd, K.dots, C * sizeof(double));
+  for (int c = 0; c < C; ++c)
+    if (act[c]) {
+      st.rel[c] = std::sqrt(hd[c]) / st.bnorm[c];
+      st.m64[c] += 1;
+    }
 }
 
-int solve_impl(spm_handle* h, const double* sigma0, double* sigma, spm_solve_info* info) {
+void stamp_newly(spm_handle* h, const std::vector<int32_t>& newly) {
+  const int C = h->geo.C;
+  int32_t* hm = host_scratch<int32_t>(h, C);
+  std::memcpy(hm, newly.data(), C * sizeof(int32_t));
+  SPM_HIP_CHECK(hipMemcpyAsync(h->kr.mask, hm, C * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  gm_stamp_mask(h, h->kr.mask);
+  sync(h);
+}
+
+int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<spm_solve_info>& infos) {
   Krylov& K = h->kr;
+  const int C = h->geo.C;
   const int64_t n2 = K.n2;
-  ensure(h, K.b, n2);
-  double* bb = K.b;
-  launch_rhs(h, bb);
-  const double bnorm = std::sqrt(host_dot(h, bb, bb));
+  const double tol = h->cfg.tol;
+  CellStats st(C);
+  launch_rhs(h, K.b);
+  gm_dot(h, K.b, K.b, K.dots);
+  {
+    double* hd = host_scratch<double>(h, C);
+    download(h, hd, K.dots, C * sizeof(double));
+    for (int c = 0; c < C; ++c) st.bnorm[c] = std::sqrt(hd[c]);
+  }
+  gm_stamp_start(h);
   if (sigma0)
     gm_copy(h, sigma, sigma0, n2);
   else
     gm_zero(h, sigma, n2);
-  bool nonzero = sigma0 != nullptr;
-  const double tol = h->cfg.tol;
-  int status = SPM_OK;
-  if (h->cfg.precision == SPM_FP32_IR) {
-    double rel = nonzero ? true_residual(h, bb, sigma, bnorm, info) : 1.0;
-    if (!nonzero) gm_copy(h, K.tmp2, bb, n2);
-    int outer = 0;
-    // inner tolerance: cfg.inner_tol, raised to half the reduction the previous
-    // refinement actually achieved (the FP32 operator error bounds what one
-    // refinement can gain; solving the inner system deeper than that is wasted)
-    double itol_next = h->cfg.inner_tol;
-    while (rel > tol && outer < 40) {
-      ensure(h, K.d, n2);
-      double* d = K.d;
-      double* r = K.tmp2;
-      const double rnorm = rel * bnorm;
-      double itol = itol_next;
-      if (tol / rel > itol) itol = 0.5 * tol / rel;
-      gm_zero(h, d, n2);
-      KrylovResult kr = gmres(h, SPM_FP32, r, d, false, itol, h->cfg.max_iter, rnorm, info);
-      info->iterations += kr.iterations;
-      gm_axpby(h, n2, 1.0, sigma, 1.0, d, sigma);
-      ++outer;
-      const double rel_new = true_residual(h, bb, sigma, bnorm, info);
-      const double rho = rel_new / rel;
-      if (verbose())
-        std::fprintf(stderr, "[spm] refinement %d: inner its %d (inner tol %.1e, est %.1e) FP64 residual %.3e -> %.3e\n",
-                     outer, kr.iterations, itol, kr.est, rel, rel_new);
-      itol_next = std::min(0.1, std::max(h->cfg.inner_tol, 0.5 * rho));
-      rel = rel_new;
-      if (kr.iterations >= h->cfg.max_iter && rel > tol) {
-        status = SPM_ENOCONV;
-        break;
-      }
-    }
-    info->refinements = outer;
-    info->rel_residual = rel;
-    if (rel > tol) status = SPM_ENOCONV;
+  std::vector<int32_t> act(C, 1), conv(C, 0), newly(C, 0);
+  if (sigma0) {
+    residual(h, sigma, act, st);
   } else {
-    int used = 0;
-    double rel = 1.0;
-    for (int restart = 0; restart < 6; ++restart) {
-      KrylovResult kr = gmres(h, SPM_FP64, bb, sigma, nonzero, tol, h->cfg.max_iter - used, bnorm, info);
-      used += kr.iterations;
-      info->iterations += kr.iterations;
-      nonzero = true;
-      rel = true_residual(h, bb, sigma, bnorm, info);
-      if (rel <= tol || used >= h->cfg.max_iter) break;
-    }
-    info->rel_residual = rel;
-    if (rel > tol) status = SPM_ENOCONV;
+    gm_copy(h, K.tmp2, K.b, n2);
+    std::fill(st.rel.begin(), st.rel.end(), 1.0);
   }
-  info->status = status;
+  auto mark = [&]() {
+    bool any = false;
+    for (int c = 0; c < C; ++c) {
+      newly[c] = (!conv[c] && st.rel[c] <= tol) ? 1 : 0;
+      if (newly[c]) conv[c] = 1;
+      act[c] = (!conv[c] && st.its[c] < h->cfg.max_iter) ? 1 : 0;
+      any = any || act[c];
+    }
+    stamp_newly(h, newly);
+    return any;
+  };
+  bool any = mark();
+  if (h->cfg.precision == SPM_FP32_IR) {
+    std::vector<double> itol(C, h->cfg.inner_tol), bn(C), tl(C);
+    for (int outer = 0; outer < 40 && any; ++outer) {
+      for (int c = 0; c < C; ++c) {
+        bn[c] = st.rel[c] * st.bnorm[c];
+        tl[c] = (tol / st.rel[c] > itol[c]) ? 0.5 * tol / st.rel[c] : itol[c];
+      }
+      gm_copy(h, K.V, K.tmp2, n2);   // V_0 = r
+      gm_zero(h, K.d, n2);
+      const std::vector<int32_t> kd = krylov_cycle(h, SPM_FP32, K.d, bn, tl, act, h->cfg.max_iter);
+      gm_axpby(h, n2, 1.0, sigma, 1.0, K.d, sigma);
+      const std::vector<double> before = st.rel;
+      std::vector<int32_t> was = act;
+      for (int c = 0; c < C; ++c)
+        if (was[c]) {
+          st.its[c] += kd[c];
+          st.m32[c] += kd[c];
+          st.refine[c] += 1;
+        }
+      residual(h, sigma, was, st);
+      for (int c = 0; c < C; ++c)
+        if (was[c]) {
+          const double rho = st.rel[c] / before[c];
+          itol[c] = std::min(0.1, std::max(h->cfg.inner_tol, 0.5 * rho));
+          if (verbose())
+            std::fprintf(stderr, "[spm] cell %d refinement %d: inner its %d (inner tol %.1e) residual %.3e -> %.3e\n",
+                         c, st.refine[c], kd[c], tl[c], before[c], st.rel[c]);
+          if (kd[c] == 0 && st.rel[c] > tol) st.its[c] = h->cfg.max_iter;  // no progress possible
+        }
+      any = mark();
+    }
+  } else {
+    std::vector<double> tl(C, tol);
+    for (int restart = 0; restart < 6 && any; ++restart) {
+      gm_copy(h, K.V, K.tmp2, n2);   // V_0 = r
+      int budget = h->cfg.max_iter;
+      for (int c = 0; c < C; ++c)
+        if (act[c]) budget = std::min(budget, h->cfg.max_iter - st.its[c]);
+      const std::vector<int32_t> kd = krylov_cycle(h, SPM_FP64, sigma, st.bnorm, tl, act, std::max(1, budget));
+      std::vector<int32_t> was = act;
+      for (int c = 0; c < C; ++c)
+        if (was[c]) {
+          st.its[c] += kd[c];
+          st.m64[c] += kd[c];
+        }
+      residual(h, sigma, was, st);
+      if (verbose())
+        for (int c = 0; c < C; ++c)
+          if (was[c]) std::fprintf(stderr, "[spm] cell %d cycle %d: its %d residual %.3e\n", c, restart, kd[c], st.rel[c]);
+      any = mark();
+    }
+  }
+  int status = SPM_OK;
+  infos.assign(C, spm_solve_info{});
+  for (int c = 0; c < C; ++c) {
+    spm_solve_info& in = infos[c];
+    std::memset(&in, 0, sizeof(in));
+    in.iterations = st.its[c];
+    in.fp64_matvecs = st.m64[c];
+    in.fp32_matvecs = st.m32[c];
+    in.refinements = st.refine[c];
+    in.rel_residual = st.rel[c];
+    in.status = st.rel[c] <= tol ? SPM_OK : SPM_ENOCONV;
+    if (in.status != SPM_OK) status = SPM_ENOCONV;
+  }
   return status;
 }
 
 void readout(spm_handle* h, const double* sigma, double* vel, double* omega, double* mu_eff) {
-  stage_xi(h, sigma);
+  stage_xi(h, sigma, false);
   if (vel || omega) launch_velocities(h, vel, omega);
   if (mu_eff) launch_mu_eff(h, mu_eff);
+}
+
+int solve_api(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
+              spm_solve_info* info_out, double* latency_out) {
+  need_particles(h);
+  if (!sigma) throw ApiError(SPM_EINVAL, "null sigma");
+  const int C = h->geo.C;
+  std::vector<spm_solve_info> infos;
+  const double t0 = now();
+  const int st = solve_impl(h, sigma0, sigma, infos);
+  sync(h);
+  const double t1 = now();
+  readout(h, sigma, vel, omega, mu_eff);
+  sync(h);
+  const double t2 = now();
+  std::vector<unsigned long long> stamps(C + 1);
+  download(h, stamps.data(), h->kr.stamp, (C + 1) * sizeof(unsigned long long));
+  int32_t npairs_cell = 0;
+  (void)npairs_cell;
+  for (int c = 0; c < C; ++c) {
+    infos[c].n_close_pairs = (int32_t)h->cl.npairs;
+    infos[c].seconds_solve = t1 - t0;
+    infos[c].seconds_readout = t2 - t1;
+    if (latency_out) latency_out[c] = (double)(stamps[c] - stamps[C]) / h->wallclock_hz;
+    if (info_out) info_out[c] = infos[c];
+  }
+  if (st == SPM_ENOCONV) h->err = "GMRES did not reach the tolerance; outputs hold the last iterate";
+  return st;
 }
 
 }  // namespace
 
 namespace spm {
-void ensure_tpart(spm_handle* h, size_t splits) {
-  const size_t need = std::max(splits, max_splits(h));
-  ensure(h, h->wk.Tpart, need * 2 * h->geo.N);
+size_t max_splits_all(spm_handle* h) {
+  return (size_t)std::max(h->wk.near[0].max_splits, h->wk.near[1].max_splits);
 }
+
+// Work items of the persistent near sum for one precision: every cell's targets in
+// blocks of block*tpt, its sources in ceil(N_c / chunk) balanced splits, sorted by
+// cost (largest first).
+void build_near_plan(spm_handle* h, int precision) {
+  NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
+  if (!near_config_valid(P.cfg)) throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
+  const int C = h->geo.C;
+  std::vector<NearItem> items;
+  std::vector<int32_t> nsplit(C, 1);
+  int32_t maxs = 1;
+  const int64_t T = (int64_t)P.cfg.block * P.cfg.tpt;
+  for (int c = 0; c < C; ++c) {
+    const int64_t n0 = h->cells[c].n0, n1 = h->cells[c].n1, Nc = n1 - n0;
+    const int64_t S = std::max<int64_t>(1, (Nc + P.cfg.chunk - 1) / P.cfg.chunk);
+    const int64_t per = (Nc + S - 1) / S;
+    nsplit[c] = (int32_t)S;
+    maxs = std::max<int32_t>(maxs, (int32_t)S);
+    for (int64_t t0 = n0; t0 < n1; t0 += T)
+      for (int64_t k = 0; k < S; ++k) {
+        NearItem it;
+        it.t0 = t0;
+        it.t1 = std::min(n1, t0 + T);
+        it.s0 = n0 + k * per;
+        it.s1 = std::min(n1, it.s0 + per);
+        it.c = c;
+        it.split = (int32_t)k;
+        if (it.s1 > it.s0) items.push_back(it);
+      }
+  }
+  std::stable_sort(items.begin(), items.end(), [](const NearItem& a, const NearItem& b) {
+    return (a.t1 - a.t0) * (a.s1 - a.s0) > (b.t1 - b.t0) * (b.s1 - b.s0);
+  });
+  P.nitems = (int32_t)items.size();
+  P.max_splits = maxs;
+  ensure(h, P.items, items.size());
+  ensure(h, P.nsplit, C);
+  ensure(h, P.counter, 1);
+  upload(h, P.items, items.data(), items.size() * sizeof(NearItem));
+  upload(h, P.nsplit, nsplit.data(), C * sizeof(int32_t));
+  P.grid = 0;
+  ensure(h, h->wk.Tpart, max_splits_all(h) * 2 * h->geo.N);
+  drop_graphs(h);
+}
+
 void launch_prep_for_timing(spm_handle* h) {
   // fill the force arrays from the right-hand side so the timed kernels see finite data
   launch_rhs(h, h->kr.tmp);
@@ -463,6 +811,8 @@ void spm_default_config(spm_config* c) {
   c->inner_tol = 1e-5;
   c->min_gap = 0.0;
   c->rcond = 1e-14;
+  c->use_graph = 1;
+  c->poll_every = 2;
 }
 
 int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_fn alloc, spm_free_fn free_fn,
@@ -478,7 +828,8 @@ int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_
   const spm_config& c = h->cfg;
   if (!(c.mu > 0) || !(c.gamma > 0) || c.M < 4 || c.M > 512 || c.m_wall < 4 || c.m_wall > 256 || !(c.R_proxy > 0.75) ||
       !(c.tol > 0) || c.max_iter < 1 || c.max_iter > 5000 || c.close_factor < 0 ||
-      (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR) || !(c.inner_tol > 0 && c.inner_tol < 1)) {
+      (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR) || !(c.inner_tol > 0 && c.inner_tol < 1) ||
+      c.poll_every < 1) {
     delete h;
     return SPM_EINVAL;
   }
@@ -486,6 +837,10 @@ int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_
   h->alloc = alloc;
   h->free_fn = free_fn;
   h->alloc_ctx = ctx;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess &&
+      khz > 0)
+    h->wallclock_hz = 1e3 * (double)khz;
   *out = h;
   return SPM_OK;
 }
@@ -494,8 +849,10 @@ void spm_destroy(spm_handle* h) {
   if (!h) return;
   try {
     (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    if (h->kr.cap_stream) (void)hipStreamDestroy(h->kr.cap_stream);
     free_all(h);
-    if (h->kr.host_res) (void)hipHostFree(h->kr.host_res);
+    if (h->kr.host) (void)hipHostFree(h->kr.host);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   } catch (...) {
   }
@@ -509,17 +866,9 @@ int spm_set_lattice(spm_handle* h, const double e1[2], const double e2[2], const
     if (!e1 || !e2) throw ApiError(SPM_EINVAL, "null lattice vector");
     if (e1[0] != 1.0 || e1[1] != 0.0 || e2[1] != 1.0 || !std::isfinite(e2[0]))
       throw ApiError(SPM_EINVAL, "lattice must be e1 = (1, 0), e2 = (s, 1)");
-    h->skew_raw = e2[0];
-    const double s = e2[0] - std::floor(e2[0] + 0.5);
-    h->skew = s;
-    h->e1[0] = 1.0;
-    h->e1[1] = 0.0;
-    h->e2[0] = s;
-    h->e2[1] = 1.0;
+    h->pending_skew = e2[0];
     h->cU[0] = center ? center[0] : 0.0;
     h->cU[1] = center ? center[1] : 0.0;
-    build_lattice(h);
-    sync(h);
     h->have_lattice = true;
     h->have_particles = false;
     return SPM_OK;
@@ -531,101 +880,32 @@ int spm_set_ellipses(spm_handle* h, int32_t n, const double* centers, const doub
   return guarded(h, [&]() {
     if (!h->have_lattice) throw ApiError(SPM_ESTATE, "set the lattice first");
     if (n < 1 || !centers || !theta || !a || !b || !n_nodes) throw ApiError(SPM_EINVAL, "bad particle arrays");
-    h->cx.resize(n);
-    h->cy.resize(n);
-    h->th.assign(theta, theta + n);
-    h->a.assign(a, a + n);
-    h->b.assign(b, b + n);
-    h->nn.assign(n_nodes, n_nodes + n);
-    h->off.assign(n + 1, 0);
-    // wrap centres: (alpha, beta) = [e1 e2]^{-1} (c - c_U), reduced to [-1/2, 1/2)
-    const double det = h->e1[0] * h->e2[1] - h->e1[1] * h->e2[0];
-    for (int i = 0; i < n; ++i) {
-      if (!(a[i] > 0) || !(b[i] > 0) || !std::isfinite(centers[2 * i]) || !std::isfinite(centers[2 * i + 1]) ||
-          !std::isfinite(theta[i]))
-        throw ApiError(SPM_EINVAL, "bad ellipse " + std::to_string(i));
-      if (n_nodes[i] < 8 || n_nodes[i] > kMaxNodesPerParticle || (n_nodes[i] & 1))
-        throw ApiError(SPM_EINVAL, "node count must be even and in [8, 512]");
-      if (std::max(a[i], b[i]) >= 0.45) throw ApiError(SPM_EINVAL, "ellipse larger than the 3x3 image rule allows");
-      const double dx = centers[2 * i] - h->cU[0], dy = centers[2 * i + 1] - h->cU[1];
-      double al = (dx * h->e2[1] - dy * h->e2[0]) / det;
-      double be = (h->e1[0] * dy - h->e1[1] * dx) / det;
-      al -= std::floor(al + 0.5);
-      be -= std::floor(be + 0.5);
-      h->cx[i] = h->cU[0] + al * h->e1[0] + be * h->e2[0];
-      h->cy[i] = h->cU[1] + al * h->e1[1] + be * h->e2[1];
-      h->off[i + 1] = h->off[i] + n_nodes[i];
-    }
-    Geo& g = h->geo;
-    g.No = n;
-    g.N = h->off[n];
-    const int64_t N = g.N;
-    ensure(h, g.x, N);
-    ensure(h, g.y, N);
-    ensure(h, g.nx, N);
-    ensure(h, g.ny, N);
-    ensure(h, g.w, N);
-    ensure(h, g.kap, N);
-    ensure(h, g.tx, N);
-    ensure(h, g.ty, N);
-    ensure(h, g.xpx, N);
-    ensure(h, g.xpy, N);
-    ensure(h, g.xf, N);
-    ensure(h, g.yf, N);
-    ensure(h, g.nxf, N);
-    ensure(h, g.nyf, N);
-    ensure(h, g.pid, N);
-    ensure(h, g.pcx, n);
-    ensure(h, g.pcy, n);
-    ensure(h, g.pth, n);
-    ensure(h, g.pa, n);
-    ensure(h, g.pb, n);
-    ensure(h, g.pper, n);
-    ensure(h, g.poff, n + 1);
-    ensure(h, g.pn, n);
-    std::vector<int32_t> pid(N);
-    for (int i = 0; i < n; ++i)
-      for (int k = h->off[i]; k < h->off[i + 1]; ++k) pid[k] = i;
-    upload(h, g.pid, pid.data(), N * sizeof(int32_t));
-    upload(h, g.pcx, h->cx.data(), n * sizeof(double));
-    upload(h, g.pcy, h->cy.data(), n * sizeof(double));
-    upload(h, g.pth, h->th.data(), n * sizeof(double));
-    upload(h, g.pa, h->a.data(), n * sizeof(double));
-    upload(h, g.pb, h->b.data(), n * sizeof(double));
-    upload(h, g.poff, h->off.data(), (n + 1) * sizeof(int32_t));
-    upload(h, g.pn, h->nn.data(), n * sizeof(int32_t));
-    launch_geometry(h);
-    // close pairs + overlap check
-    CloseList& C = h->cl;
-    ensure(h, C.count, N);
-    ensure(h, C.row, N + 1);
-    ensure(h, C.tlist, N);
-    ensure(h, C.dmin, N);
-    ensure(h, C.inside, N);
-    ensure(h, C.vp, 6 * N);
-    launch_close_count(h);
-    double gap;
-    int32_t overlap;
-    launch_gap(h, &gap, &overlap);
-    h->min_gap_est = gap;
-    if (overlap || (h->cfg.min_gap > 0 && gap < h->cfg.min_gap)) {
-      h->have_particles = false;
-      throw ApiError(SPM_EOVERLAP, overlap ? "particles overlap" : "particles closer than min_gap");
-    }
-    int32_t total, nt;
-    launch_close_scan(h, &total, &nt);
-    C.npairs = total;
-    C.ntargets = nt;
-    ensure(h, C.q, std::max<int64_t>(1, total));
-    ensure(h, C.s, std::max<int64_t>(1, total));
-    if (total > 0) launch_close_fill(h);
-    choose_launch(h);
-    alloc_work(h);
-    alloc_krylov(h);
-    sync(h);
-    h->have_particles = true;
+    const int32_t off[2] = {0, n};
+    const double sk = h->pending_skew;
+    set_cells_impl(h, 1, &sk, off, centers, theta, a, b, n_nodes);
     return SPM_OK;
   });
+}
+
+int spm_set_cells(spm_handle* h, int32_t n_cells, const double* skews, const int32_t* part_offsets,
+                  const double* centers, const double* theta, const double* a, const double* b,
+                  const int32_t* n_nodes) {
+  return guarded(h, [&]() {
+    if (!skews || !part_offsets || !centers || !theta || !a || !b || !n_nodes)
+      throw ApiError(SPM_EINVAL, "null array");
+    h->cU[0] = 0.0;
+    h->cU[1] = 0.0;
+    h->have_lattice = true;
+    set_cells_impl(h, n_cells, skews, part_offsets, centers, theta, a, b, n_nodes);
+    return SPM_OK;
+  });
+}
+
+int spm_num_cells(const spm_handle* h, int32_t* C) {
+  if (!h || !C) return SPM_EINVAL;
+  if (!h->have_particles) return SPM_ESTATE;
+  *C = h->geo.C;
+  return SPM_OK;
 }
 
 int spm_num_nodes(const spm_handle* h, int64_t* N) {
@@ -673,7 +953,7 @@ int spm_apply(spm_handle* h, const double* sigma, double* out, int32_t precision
     need_particles(h);
     if (!sigma || !out) throw ApiError(SPM_EINVAL, "null vector");
     if (precision != SPM_FP64 && precision != SPM_FP32) throw ApiError(SPM_EINVAL, "precision must be FP64 or FP32");
-    matvec(h, sigma, out, precision);
+    matvec(h, sigma, out, precision, false);
     sync(h);
     return SPM_OK;
   });
@@ -691,23 +971,13 @@ int spm_rhs(spm_handle* h, double* out) {
 
 int spm_solve(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
               spm_solve_info* info_out) {
+  return guarded(h, [&]() { return solve_api(h, sigma0, sigma, vel, omega, mu_eff, info_out, nullptr); });
+}
+
+int spm_solve_batch(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
+                    spm_solve_info* infos_host, double* cell_latency_s_host) {
   return guarded(h, [&]() {
-    need_particles(h);
-    if (!sigma) throw ApiError(SPM_EINVAL, "null sigma");
-    spm_solve_info info;
-    std::memset(&info, 0, sizeof(info));
-    info.n_close_pairs = (int32_t)h->cl.npairs;
-    const double t0 = now();
-    const int st = solve_impl(h, sigma0, sigma, &info);
-    sync(h);
-    const double t1 = now();
-    readout(h, sigma, vel, omega, mu_eff);
-    sync(h);
-    info.seconds_solve = t1 - t0;
-    info.seconds_readout = now() - t1;
-    if (info_out) *info_out = info;
-    if (st == SPM_ENOCONV) h->err = "GMRES did not reach the tolerance; outputs hold the last iterate";
-    return st;
+    return solve_api(h, sigma0, sigma, vel, omega, mu_eff, infos_host, cell_latency_s_host);
   });
 }
 
@@ -765,8 +1035,9 @@ int spm_proxy_strengths(spm_handle* h, const double* sigma, double* xi) {
   return guarded(h, [&]() {
     need_particles(h);
     if (!sigma || !xi) throw ApiError(SPM_EINVAL, "null vector");
-    stage_xi(h, sigma);
-    SPM_HIP_CHECK(hipMemcpyAsync(xi, h->wk.xi, 2 * h->per.M * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+    stage_xi(h, sigma, false);
+    SPM_HIP_CHECK(hipMemcpyAsync(xi, h->wk.xi, (size_t)h->geo.C * 2 * h->per.M * sizeof(double),
+                                 hipMemcpyDeviceToDevice, h->stream));
     sync(h);
     return SPM_OK;
   });
@@ -782,12 +1053,11 @@ int spm_close_pairs(spm_handle* h, int64_t* count, int32_t* target, int32_t* par
     if (capacity < h->cl.npairs) throw ApiError(SPM_EINVAL, "capacity too small");
     const int64_t N = h->geo.N, P = h->cl.npairs;
     std::vector<int32_t> row(N + 1), q(std::max<int64_t>(P, 1)), s(std::max<int64_t>(P, 1));
-    SPM_HIP_CHECK(hipMemcpyAsync(row.data(), h->cl.row, (N + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    download(h, row.data(), h->cl.row, (N + 1) * sizeof(int32_t));
     if (P > 0) {
-      SPM_HIP_CHECK(hipMemcpyAsync(q.data(), h->cl.q, P * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-      SPM_HIP_CHECK(hipMemcpyAsync(s.data(), h->cl.s, P * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+      download(h, q.data(), h->cl.q, P * sizeof(int32_t));
+      download(h, s.data(), h->cl.s, P * sizeof(int32_t));
     }
-    sync(h);
     for (int64_t i = 0; i < N; ++i)
       for (int32_t e = row[i]; e < row[i + 1]; ++e) {
         if (target) target[e] = (int32_t)i;
@@ -800,79 +1070,26 @@ int spm_close_pairs(spm_handle* h, int64_t* count, int32_t* target, int32_t* par
 
 int spm_proxy_pinv(spm_handle* h, double* out) {
   return guarded(h, [&]() {
-    if (!h->have_lattice) throw ApiError(SPM_ESTATE, "set the lattice first");
-    if (!out) throw ApiError(SPM_EINVAL, "null output");
-    const size_t n = (size_t)8 * h->per.m * 2 * h->per.M;
-    SPM_HIP_CHECK(hipMemcpyAsync(out, h->per.Qp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    sync(h);
-    return SPM_OK;
-  });
-}
-
-int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers, double* theta,
-             double* mu_series, spm_solve_info* infos) {
-  return guarded(h, [&]() {
     need_particles(h);
-    if (!t_inout || !centers || !theta || !mu_series || n_steps < 1 || !(dt > 0))
-      throw ApiError(SPM_EINVAL, "bad step arguments");
-    const int n = h->geo.No;
-    std::vector<double> a(h->a), b(h->b);
-    std::vector<int32_t> nn(h->nn);
-    const double s0 = h->skew_raw;
-    const double t0 = *t_inout;
-    double *sig = nullptr, *vel = nullptr, *om = nullptr, *mu = nullptr;
-    const int64_t n2 = 2 * h->geo.N;
-    ensure(h, h->kr.stepbuf, n2 + 3 * n + 2);
-    double* buf = h->kr.stepbuf;
-    sig = buf;
-    vel = buf + n2;
-    om = vel + 2 * n;
-    mu = om + n;
-    std::vector<double> hv(3 * n + 1);
-    bool have_prev = false;
-    for (int k = 0; k < n_steps; ++k) {
-      const double t = k * dt;  // elapsed since entry
-      const double e1[2] = {1.0, 0.0};
-      const double e2[2] = {s0 + h->cfg.gamma * t, 1.0};
-      const double cU[2] = {h->cU[0], h->cU[1]};
-      int rc = spm_set_lattice(h, e1, e2, cU);
-      if (rc) return rc;
-      h->skew_raw = s0;  // keep the reference skew of this call
-      rc = spm_set_ellipses(h, n, centers, theta, a.data(), b.data(), nn.data());
-      if (rc) return rc;
-      spm_solve_info info;
-      rc = spm_solve(h, have_prev ? sig : nullptr, sig, vel, om, mu, &info);
-      if (rc && rc != SPM_ENOCONV) return rc;
-      have_prev = true;
-      SPM_HIP_CHECK(hipMemcpyAsync(hv.data(), vel, (3 * n + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-      sync(h);
-      mu_series[k] = hv[3 * n];
-      if (infos) infos[k] = info;
-      for (int i = 0; i < n; ++i) {
-        centers[2 * i] = h->cx[i] + dt * hv[2 * i];
-        centers[2 * i + 1] = h->cy[i] + dt * hv[2 * i + 1];
-        theta[i] += dt * hv[2 * n + i];
-      }
-      if (rc == SPM_ENOCONV) return rc;
-    }
-    *t_inout = t0 + n_steps * dt;
-    h->skew_raw = s0 + h->cfg.gamma * n_steps * dt;
+    if (!out) throw ApiError(SPM_EINVAL, "null output");
+    const size_t n = (size_t)h->geo.C * 8 * h->per.m * 2 * h->per.M;
+    download(h, out, h->per.Qp, n * sizeof(double));
     return SPM_OK;
   });
 }
 
 int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps_host) {
   return guarded(h, [&]() {
-    if (!h->have_lattice) throw ApiError(SPM_ESTATE, "set the lattice first");
-    const size_t n = (size_t)8 * h->per.m * 2 * h->per.M;
-    if (Q_host) SPM_HIP_CHECK(hipMemcpyAsync(Q_host, h->per.Q, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    if (s_host)
-      SPM_HIP_CHECK(hipMemcpyAsync(s_host, h->per.svd_s, 2 * h->per.M * sizeof(double), hipMemcpyDeviceToHost,
-                                   h->stream));
-    double sw = 0;
-    SPM_HIP_CHECK(hipMemcpyAsync(&sw, h->per.svd_s + 2 * h->per.M, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    sync(h);
-    if (sweeps_host) *sweeps_host = (int32_t)sw;
+    need_particles(h);
+    const int C = h->geo.C, M = h->per.M;
+    const size_t n = (size_t)C * 8 * h->per.m * 2 * M;
+    if (Q_host) download(h, Q_host, h->per.Q, n * sizeof(double));
+    std::vector<double> sv((size_t)C * (2 * M + 1));
+    download(h, sv.data(), h->per.svd_s, sv.size() * sizeof(double));
+    for (int c = 0; c < C; ++c) {
+      if (s_host) std::memcpy(s_host + (size_t)c * 2 * M, sv.data() + (size_t)c * (2 * M + 1), 2 * M * sizeof(double));
+      if (sweeps_host) sweeps_host[c] = (int32_t)sv[(size_t)c * (2 * M + 1) + 2 * M];
+    }
     return SPM_OK;
   });
 }
@@ -890,11 +1107,11 @@ int spm_get_launch(spm_handle* h, int32_t precision, int32_t* cfg_host) {
   return guarded(h, [&]() {
     need_particles(h);
     if (!cfg_host || (precision != SPM_FP64 && precision != SPM_FP32)) throw ApiError(SPM_EINVAL, "bad arguments");
-    const NearConfig& c = h->wk.near[precision == SPM_FP64 ? 0 : 1];
+    const NearConfig& c = h->wk.near[precision == SPM_FP64 ? 0 : 1].cfg;
     cfg_host[0] = c.block;
     cfg_host[1] = c.tpt;
     cfg_host[2] = c.tile;
-    cfg_host[3] = c.splits;
+    cfg_host[3] = c.chunk;
     return SPM_OK;
   });
 }
@@ -907,10 +1124,10 @@ int spm_set_launch(spm_handle* h, int32_t precision, const int32_t* cfg_host) {
     c.block = cfg_host[0];
     c.tpt = cfg_host[1];
     c.tile = cfg_host[2];
-    c.splits = cfg_host[3];
+    c.chunk = cfg_host[3];
     if (!near_config_valid(c)) throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
-    ensure_tpart(h, (size_t)c.splits);
-    h->wk.near[precision == SPM_FP64 ? 0 : 1] = c;
+    h->wk.near[precision == SPM_FP64 ? 0 : 1].cfg = c;
+    build_near_plan(h, precision);
     h->wk.tuned = true;
     h->wk.tuned_N = h->geo.N;
     return SPM_OK;
@@ -937,6 +1154,52 @@ int spm_profile_read(spm_handle* h, int32_t kernel, double* total_ms, int64_t* l
     if (total_ms) *total_ms = h->prof_ms[kernel];
     if (launches) *launches = h->prof_launches[kernel];
     if (pairs) *pairs = h->prof_pairs[kernel];
+    return SPM_OK;
+  });
+}
+
+int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers, double* theta,
+             double* mu_series, spm_solve_info* infos) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (h->geo.C != 1) throw ApiError(SPM_EINVAL, "time stepping runs on a single cell");
+    if (!t_inout || !centers || !theta || !mu_series || n_steps < 1 || !(dt > 0))
+      throw ApiError(SPM_EINVAL, "bad step arguments");
+    const int n = h->geo.No;
+    std::vector<double> a(h->a), b(h->b);
+    std::vector<int32_t> nn(h->nn);
+    const double s0 = h->cells[0].skew_raw;
+    const double t0 = *t_inout;
+    const int64_t n2 = 2 * h->geo.N;
+    ensure(h, h->kr.stepbuf, n2 + 3 * n + 2);
+    double* sig = h->kr.stepbuf;
+    double* vel = sig + n2;
+    double* om = vel + 2 * n;
+    double* mu = om + n;
+    std::vector<double> hv(3 * n + 1);
+    bool have_prev = false;
+    for (int k = 0; k < n_steps; ++k) {
+      const double sk = s0 + h->cfg.gamma * (k * dt);
+      const int32_t off[2] = {0, n};
+      set_cells_impl(h, 1, &sk, off, centers, theta, a.data(), b.data(), nn.data());
+      sig = h->kr.stepbuf;  // (buffers are stable: same sizes)
+      spm_solve_info info;
+      const int rc = solve_api(h, have_prev ? sig : nullptr, sig, vel, om, mu, &info, nullptr);
+      if (rc && rc != SPM_ENOCONV) return rc;
+      have_prev = true;
+      download(h, hv.data(), vel, (3 * n + 1) * sizeof(double));
+      mu_series[k] = hv[3 * n];
+      if (infos) infos[k] = info;
+      for (int i = 0; i < n; ++i) {
+        centers[2 * i] = h->cx[i] + dt * hv[2 * i];
+        centers[2 * i + 1] = h->cy[i] + dt * hv[2 * i + 1];
+        theta[i] += dt * hv[2 * n + i];
+      }
+      if (rc == SPM_ENOCONV) return rc;
+    }
+    *t_inout = t0 + n_steps * dt;
+    h->cells[0].skew_raw = s0 + h->cfg.gamma * n_steps * dt;
+    h->pending_skew = h->cells[0].skew_raw;
     return SPM_OK;
   });
 }

@@ -98,20 +98,24 @@ template <int PREC>
 __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets, Geo g,
                                                      const int32_t* __restrict__ tlist, const int32_t* __restrict__ row,
                                                      const int32_t* __restrict__ cq, const int32_t* __restrict__ cs,
-                                                     Shifts<double> sh, Shifts<float> shf,
                                                      const double* __restrict__ vp, const double* __restrict__ f1,
                                                      const double* __restrict__ f2, const float* __restrict__ f1f,
-                                                     const float* __restrict__ f2f, double* __restrict__ T) {
+                                                     const float* __restrict__ f2f, const int32_t* __restrict__ active,
+                                                     double* __restrict__ T) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (wave >= ntargets) return;
   const int i = tlist[wave];
+  const double skew = g.cskew[g.ncell[i]];
+  if (active != nullptr && active[g.ncell[i]] == 0) return;
   const double xi = g.x[i], yi = g.y[i], nxi = g.nx[i], nyi = g.ny[i];
   double dT1 = 0, dT2 = 0;
   for (int e = row[i]; e < row[i + 1]; ++e) {
     const int q = cq[e], s = cs[e];
     const int o = g.poff[q], n = g.pn[q];
-    const double zr = xi - sh.x[s], zi = yi - sh.y[s];  // target shifted instead of the image
+    const double shx = shift_x(s, skew), shy = shift_y(s);
+    const float shxf = (float)shx, shyf = (float)shy;
+    const double zr = xi - shx, zi = yi - shy;  // target shifted instead of the image
     // pass 1: den and v for the three densities; plain near-sum terms of this image
     double dr = 0, di = 0, v[6] = {0, 0, 0, 0, 0, 0};
     double p1 = 0, p2 = 0;
@@ -131,13 +135,13 @@ __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets
       if (PREC == SPM_FP64) {
         const double dx = xi - g.x[kk], dy = yi - g.y[kk];
         double a1 = 0.0, a2 = 0.0;
-        gt_pair(dx - sh.x[s], dy - sh.y[s], nxi, nyi, f1[kk], f2[kk], a1, a2);
+        gt_pair(dx - shx, dy - shy, nxi, nyi, f1[kk], f2[kk], a1, a2);
         p1 += a1;
         p2 += a2;
       } else {
         const float dx = g.xf[i] - g.xf[kk], dy = g.yf[i] - g.yf[kk];
         float a1 = 0.f, a2 = 0.f;
-        gt_pair(dx - shf.x[s], dy - shf.y[s], g.nxf[i], g.nyf[i], f1f[kk], f2f[kk], a1, a2);
+        gt_pair(dx - shxf, dy - shyf, g.nxf[i], g.nyf[i], f1f[kk], f2f[kk], a1, a2);
         p1 += (double)a1;
         p2 += (double)a2;
       }
@@ -201,33 +205,25 @@ __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets
   }
 }
 
-template <typename R>
-static Shifts<R> shifts_of(spm_handle* h) {
-  Shifts<R> sh;
-  for (int m = -1; m <= 1; ++m)
-    for (int n = -1; n <= 1; ++n) {
-      const int s = 3 * (m + 1) + (n + 1);
-      sh.x[s] = (R)((double)m * h->e1[0] + (double)n * h->e2[0]);
-      sh.y[s] = (R)((double)m * h->e1[1] + (double)n * h->e2[1]);
-    }
-  return sh;
-}
-
-void launch_close_apply(spm_handle* h, const double* sigma, double* T, int precision) {
-  (void)sigma;
+void launch_close_apply_impl(spm_handle* h, double* T, int precision, bool with_active) {
   const int nt = h->cl.ntargets;
   if (nt == 0) return;
   const int waves_per_block = 4;
   const unsigned blocks = (unsigned)((nt + waves_per_block - 1) / waves_per_block);
   if (precision == SPM_FP64)
     k_close_apply<SPM_FP64><<<blocks, 256, 0, h->stream>>>(
-        h->geo.N, nt, h->geo, h->cl.tlist, h->cl.row, h->cl.q, h->cl.s, shifts_of<double>(h), shifts_of<float>(h),
-        h->cl.vp, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f, T);
+        h->geo.N, nt, h->geo, h->cl.tlist, h->cl.row, h->cl.q, h->cl.s, h->cl.vp, h->wk.f1, h->wk.f2, h->wk.f1f,
+        h->wk.f2f, with_active ? h->kr.active : nullptr, T);
   else
     k_close_apply<SPM_FP32><<<blocks, 256, 0, h->stream>>>(
-        h->geo.N, nt, h->geo, h->cl.tlist, h->cl.row, h->cl.q, h->cl.s, shifts_of<double>(h), shifts_of<float>(h),
-        h->cl.vp, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f, T);
+        h->geo.N, nt, h->geo, h->cl.tlist, h->cl.row, h->cl.q, h->cl.s, h->cl.vp, h->wk.f1, h->wk.f2, h->wk.f1f,
+        h->wk.f2f, with_active ? h->kr.active : nullptr, T);
   SPM_HIP_CHECK(hipGetLastError());
+}
+
+void launch_close_apply(spm_handle* h, const double* sigma, double* T, int precision) {
+  (void)sigma;
+  launch_close_apply_impl(h, T, precision, false);
 }
 
 }  // namespace spm

@@ -88,24 +88,26 @@ void launch_rhs(spm_handle* h, double* out) {
 // a scan makes row pointers; pass 2 fills (q, s) in ascending (q, s) order.
 // ----------------------------------------------------------------------------
 template <bool FILL>
-__global__ void k_close_pass(int64_t N, int32_t No, Geo g, Shifts<double> sh, double factor,
-                             const int32_t* __restrict__ row, int32_t* __restrict__ count,
-                             int32_t* __restrict__ outq, int32_t* __restrict__ outs,
+__global__ void k_close_pass(int64_t N, Geo g, double factor, const int32_t* __restrict__ row,
+                             int32_t* __restrict__ count, int32_t* __restrict__ outq, int32_t* __restrict__ outs,
                              double* __restrict__ dmin, int32_t* __restrict__ inside) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
   const double xi = g.x[i], yi = g.y[i];
   const int pi = g.pid[i];
+  const int c = g.ncell[i];
+  const double skew = g.cskew[c];
   int cnt = 0;
   int64_t pos = FILL ? row[i] : 0;
   double best = 1e300;
   int ins = 0;
-  for (int q = 0; q < No; ++q) {
+  for (int q = g.cpoff[c]; q < g.cpoff[c + 1]; ++q) {
     const double lim = factor * g.pper[q] / (double)g.pn[q];
     const double reach = g.pa[q] + (lim > 0.0 ? lim : 0.0);
     for (int s = 0; s < kShifts; ++s) {
       if (q == pi && s == kZeroShift) continue;
-      const double cx = g.pcx[q] + sh.x[s], cy = g.pcy[q] + sh.y[s];
+      const double sx = shift_x(s, skew), sy = shift_y(s);
+      const double cx = g.pcx[q] + sx, cy = g.pcy[q] + sy;
       const double ddx = xi - cx, ddy = yi - cy;
       if (ddx * ddx + ddy * ddy >= reach * reach) continue;
       // inside test against the ellipse (body frame)
@@ -116,8 +118,8 @@ __global__ void k_close_pass(int64_t N, int32_t No, Geo g, Shifts<double> sh, do
       if (u * u + v * v < 1.0) ins = 1;
       double m2 = 1e300;
       for (int k = g.poff[q]; k < g.poff[q + 1]; ++k) {
-        const double rx = xi - (g.x[k] + sh.x[s]);
-        const double ry = yi - (g.y[k] + sh.y[s]);
+        const double rx = xi - (g.x[k] + sx);
+        const double ry = yi - (g.y[k] + sy);
         const double d2 = rx * rx + ry * ry;
         m2 = d2 < m2 ? d2 : m2;
       }
@@ -178,23 +180,11 @@ __global__ void k_scan(int64_t N, const int32_t* __restrict__ count, int32_t* __
   }
 }
 
-static Shifts<double> shifts64(spm_handle* h) {
-  Shifts<double> sh;
-  for (int m = -1; m <= 1; ++m)
-    for (int n = -1; n <= 1; ++n) {
-      const int s = 3 * (m + 1) + (n + 1);
-      sh.x[s] = (double)m * h->e1[0] + (double)n * h->e2[0];
-      sh.y[s] = (double)m * h->e1[1] + (double)n * h->e2[1];
-    }
-  return sh;
-}
-
 void launch_close_count(spm_handle* h) {
   const int bs = 128;
   const int64_t N = h->geo.N;
   k_close_pass<false><<<(unsigned)((N + bs - 1) / bs), bs, 0, h->stream>>>(
-      N, h->geo.No, h->geo, shifts64(h), h->cfg.close_factor, nullptr, h->cl.count, nullptr, nullptr,
-      h->cl.dmin, h->cl.inside);
+      N, h->geo, h->cfg.close_factor, nullptr, h->cl.count, nullptr, nullptr, h->cl.dmin, h->cl.inside);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -213,8 +203,7 @@ void launch_close_fill(spm_handle* h) {
   const int bs = 128;
   const int64_t N = h->geo.N;
   k_close_pass<true><<<(unsigned)((N + bs - 1) / bs), bs, 0, h->stream>>>(
-      N, h->geo.No, h->geo, shifts64(h), h->cfg.close_factor, h->cl.row, nullptr, h->cl.q, h->cl.s, nullptr,
-      nullptr);
+      N, h->geo, h->cfg.close_factor, h->cl.row, nullptr, h->cl.q, h->cl.s, nullptr, nullptr);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

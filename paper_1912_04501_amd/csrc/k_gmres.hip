@@ -1,64 +1,297 @@
-// GMRES on the device (solver of Sec. 6.2 / Sec. 8: relative residual 1e-10).
+// GMRES on the device for every cell of the ensemble (solver of Sec. 6.2 / Sec. 8:
+// relative residual 1e-10).
 //
-// Arnoldi by classical Gram-Schmidt with one reorthogonalisation pass (CGS2: two
-// block dot-product passes instead of j+1 sequential MGS steps, same stability in
-// practice); Givens rotations and the residual estimate |g_{j+1}| are updated on the
-// device by one thread; the host only reads that scalar to stop.
-// All reductions are two-phase in fixed order (chunk partials, then a per-coefficient
-// sum), so results do not depend on scheduling.
+// Cells iterate in lockstep on one iteration index j held in device memory, so the
+// kernels of one iteration have fixed arguments and can be captured once and replayed.
+// Each cell has its own Hessenberg matrix, Givens rotations, right-hand-side norm,
+// tolerance and active flag; a cell that converges freezes (its rows are skipped) and
+// records the device wall clock.
+// Arnoldi: classical Gram-Schmidt with one reorthogonalisation pass (CGS2): two block
+// dot-product passes per iteration instead of j + 1 sequential MGS steps.
+// All reductions are two-phase in fixed order (segment partials, then per-cell sums),
+// so results do not depend on scheduling.
 #include "spm_internal.h"
 
 namespace spm {
 
-// part[c * ldp + i] = sum_{r in chunk c} V[i * ld + r] * w[r],  i < cnt.  One wave per (chunk, i).
-__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ V, int64_t ld, int cnt,
-                                                     const double* __restrict__ w, int64_t n, int64_t chunk,
-                                                     double* __restrict__ part, int ldp) {
+// part[s] = sum over the nodes of segment s of a.b (both components).
+__global__ __launch_bounds__(256) void k_dot_seg(const double* __restrict__ a, const double* __restrict__ b, int64_t N,
+                                                 const int64_t* __restrict__ n0, const int64_t* __restrict__ n1,
+                                                 double* __restrict__ part) {
+  __shared__ double sc[16];
+  const int s = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t r = n0[s] + threadIdx.x; r < n1[s]; r += blockDim.x) acc += a[r] * b[r] + a[N + r] * b[N + r];
+  acc = block_sum(acc, sc);
+  if (threadIdx.x == 0) part[s] = acc;
+}
+
+__global__ void k_dot_cells(const double* __restrict__ part, const int32_t* __restrict__ seg_off, int C,
+                            double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double s = 0.0;
+  for (int k = seg_off[c]; k < seg_off[c + 1]; ++k) s += part[k];
+  out[c] = s;
+}
+
+void gm_dot(spm_handle* h, const double* a, const double* b, double* out) {
+  Krylov& K = h->kr;
+  k_dot_seg<<<K.nseg, 256, 0, h->stream>>>(a, b, h->geo.N, K.seg_n0, K.seg_n1, K.part);
+  SPM_HIP_CHECK(hipGetLastError());
+  k_dot_cells<<<(h->geo.C + 255) / 256, 256, 0, h->stream>>>(K.part, K.seg_off, h->geo.C, out);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// part[s][i] = sum over segment s of V_i . w, for i <= j; one wave per (segment, i).
+__global__ __launch_bounds__(256) void k_cgs_partial(const double* __restrict__ V, int64_t n2, int64_t N,
+                                                     const int32_t* __restrict__ jdev, const double* __restrict__ w,
+                                                     const int64_t* __restrict__ n0, const int64_t* __restrict__ n1,
+                                                     const int32_t* __restrict__ seg_cell,
+                                                     const int32_t* __restrict__ active, int ldp,
+                                                     double* __restrict__ part) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (i >= cnt) return;
-  const int64_t r0 = blockIdx.x * chunk;
-  const int64_t r1 = (r0 + chunk < n) ? r0 + chunk : n;
-  const double* vi = V + i * ld;
-  double s = 0.0;
-  for (int64_t r = r0 + lane; r < r1; r += 64) s += vi[r] * w[r];
-  s = wave_sum(s);
-  if (lane == 0) part[(int64_t)blockIdx.x * ldp + i] = s;
+  const int s = blockIdx.x;
+  if (i > jdev[0] || active[seg_cell[s]] == 0) return;
+  const double* vi = V + (int64_t)i * n2;
+  double acc = 0.0;
+  for (int64_t r = n0[s] + lane; r < n1[s]; r += 64) acc += vi[r] * w[r] + vi[N + r] * w[N + r];
+  acc = wave_sum(acc);
+  if (lane == 0) part[(int64_t)s * ldp + i] = acc;
 }
 
-__global__ void k_dot_reduce(const double* __restrict__ part, int nchunk, int ldp, int cnt, double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= cnt) return;
-  double s = 0.0;
-  for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * ldp + i];
-  out[i] = s;
+__global__ void k_cgs_reduce(const double* __restrict__ part, const int32_t* __restrict__ seg_off,
+                             const int32_t* __restrict__ jdev, const int32_t* __restrict__ active, int ldp,
+                             double* __restrict__ coef) {
+  const int c = blockIdx.x;
+  if (active[c] == 0) return;
+  const int cnt = jdev[0] + 1;
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+    double s = 0.0;
+    for (int k = seg_off[c]; k < seg_off[c + 1]; ++k) s += part[(int64_t)k * ldp + i];
+    coef[(int64_t)c * ldp + i] = s;
+  }
 }
 
-void gm_dot_many(spm_handle* h, const double* V, int64_t ld, int cnt, const double* w, double* out) {
-  Krylov& k = h->kr;
-  const int64_t n = k.n2;
-  const int nc = k.nchunk;
-  const int64_t chunk = (n + nc - 1) / nc;
-  dim3 grid((unsigned)nc, (unsigned)((cnt + 3) / 4));
-  k_dot_partial<<<grid, 256, 0, h->stream>>>(V, ld, cnt, w, n, chunk, k.part, k.kmax + 1);
+void gm_cgs_pass(spm_handle* h, const double* w, double* coef) {
+  Krylov& K = h->kr;
+  const int ldp = K.kmax + 1;
+  dim3 grid((unsigned)K.nseg, (unsigned)((ldp + 3) / 4));
+  k_cgs_partial<<<grid, 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.jdev, w, K.seg_n0, K.seg_n1, K.seg_cell,
+                                             K.active, ldp, K.part);
   SPM_HIP_CHECK(hipGetLastError());
-  k_dot_reduce<<<(cnt + 255) / 256, 256, 0, h->stream>>>(k.part, nc, k.kmax + 1, cnt, out);
+  k_cgs_reduce<<<h->geo.C, 256, 0, h->stream>>>(K.part, K.seg_off, K.jdev, K.active, ldp, coef);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-// w[r] += sign * sum_{i < cnt} V[i * ld + r] * coef[i]
-__global__ void k_update(const double* __restrict__ V, int64_t ld, int cnt, const double* __restrict__ coef,
-                         double* __restrict__ w, int64_t n, double sign) {
+// w[r] -= sum_{i <= j} V_i[r] coef[cell(r)][i] (active cells only)
+__global__ void k_update_j(const double* __restrict__ V, int64_t n2, int64_t N, const int32_t* __restrict__ jdev,
+                           const double* __restrict__ coef, int ldp, const int32_t* __restrict__ ncell,
+                           const int32_t* __restrict__ active, double* __restrict__ w) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n) return;
+  if (r >= n2) return;
+  const int c = ncell[r < N ? r : r - N];
+  if (active[c] == 0) return;
+  const int cnt = jdev[0] + 1;
+  const double* cf = coef + (int64_t)c * ldp;
   double s = 0.0;
-  for (int i = 0; i < cnt; ++i) s += V[i * ld + r] * coef[i];
-  w[r] += sign * s;
+  for (int i = 0; i < cnt; ++i) s += V[(int64_t)i * n2 + r] * cf[i];
+  w[r] -= s;
 }
 
-void gm_update(spm_handle* h, const double* V, int64_t ld, int cnt, const double* coef, double* w, double sign) {
-  const int64_t n = h->kr.n2;
-  k_update<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(V, ld, cnt, coef, w, n, sign);
+void gm_update_j(spm_handle* h, const double* coef, double* w) {
+  Krylov& K = h->kr;
+  k_update_j<<<(unsigned)((K.n2 + 255) / 256), 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.jdev, coef, K.kmax + 1,
+                                                                    h->geo.ncell, K.active, w);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// V_{j+1} = w / |w|_cell (active cells)
+__global__ void k_store_next(double* __restrict__ V, int64_t n2, int64_t N, const int32_t* __restrict__ jdev,
+                             const double* __restrict__ w, const double* __restrict__ nrm2,
+                             const int32_t* __restrict__ ncell, const int32_t* __restrict__ active) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n2) return;
+  const int c = ncell[r < N ? r : r - N];
+  if (active[c] == 0) return;
+  const double nr = sqrt(nrm2[c]);
+  V[(int64_t)(jdev[0] + 1) * n2 + r] = nr > 0.0 ? w[r] / nr : 0.0;
+}
+
+void gm_store_next(spm_handle* h) {
+  Krylov& K = h->kr;
+  k_store_next<<<(unsigned)((K.n2 + 255) / 256), 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.jdev, K.w, K.nrm2,
+                                                                      h->geo.ncell, K.active);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// One thread per cell: column j of H = h1 + h2 (CGS2), subdiagonal |w|; apply the previous
+// rotations, make rotation j, update g; res = |g_{j+1}| / bnorm; a cell whose residual
+// estimate reaches its tolerance freezes and records the wall clock. Thread 0 then
+// advances j and counts the cells still active.
+__global__ void k_givens(int C, int kmax, int32_t* __restrict__ jdev, const double* __restrict__ h1,
+                         const double* __restrict__ h2, const double* __restrict__ nrm2,
+                         const double* __restrict__ bnorm, const double* __restrict__ tolc, double* __restrict__ H,
+                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
+                         double* __restrict__ res, int32_t* __restrict__ active, int32_t* __restrict__ kdone,
+                         unsigned long long* __restrict__ stamp) {
+  __shared__ int cnt[1024];
+  const int j = jdev[0];
+  const int ldp = kmax + 1;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    if (active[c] == 0) continue;
+    double* col = H + ((int64_t)c * kmax + j) * ldp;
+    const double* a1 = h1 + (int64_t)c * ldp;
+    const double* a2 = h2 + (int64_t)c * ldp;
+    double* csc = cs + (int64_t)c * kmax;
+    double* snc = sn + (int64_t)c * kmax;
+    double* gc = g + (int64_t)c * ldp;
+    for (int i = 0; i <= j; ++i) col[i] = a1[i] + a2[i];
+    col[j + 1] = sqrt(nrm2[c]);
+    for (int i = 0; i < j; ++i) {
+      const double t = csc[i] * col[i] + snc[i] * col[i + 1];
+      col[i + 1] = -snc[i] * col[i] + csc[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double a = col[j], b = col[j + 1];
+    const double r = hypot(a, b);
+    const double cc = r > 0.0 ? a / r : 1.0, ss = r > 0.0 ? b / r : 0.0;
+    csc[j] = cc;
+    snc[j] = ss;
+    col[j] = r;
+    col[j + 1] = 0.0;
+    gc[j + 1] = -ss * gc[j];
+    gc[j] = cc * gc[j];
+    const double e = fabs(gc[j + 1]) / bnorm[c];
+    res[c] = e;
+    if (!(e > tolc[c]) || j + 1 >= kmax || r == 0.0) {   // converged, out of space, or exact (breakdown)
+      active[c] = 0;
+      kdone[c] = j + 1;
+      stamp[c] = wall_clock64();
+    }
+  }
+  __syncthreads();
+  int n = 0;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) n += active[c];
+  cnt[threadIdx.x] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < (int)blockDim.x; ++k) t += cnt[k];
+    jdev[1] = t;
+    jdev[0] = j + 1;
+  }
+}
+
+void gm_givens(spm_handle* h) {
+  Krylov& K = h->kr;
+  const int bs = h->geo.C >= 1024 ? 1024 : ((h->geo.C + 63) / 64) * 64;
+  k_givens<<<1, bs, 0, h->stream>>>(h->geo.C, K.kmax, K.jdev, K.h1, K.h2, K.nrm2, K.bnorm, K.tolc, K.H, K.cs, K.sn,
+                                    K.g, K.res, K.active, K.kdone, K.stamp);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// vin = V_j
+__global__ void k_copy_in(const double* __restrict__ V, int64_t n2, const int32_t* __restrict__ jdev,
+                          double* __restrict__ vin) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n2) return;
+  vin[r] = V[(int64_t)jdev[0] * n2 + r];
+}
+
+void gm_copy_in(spm_handle* h) {
+  Krylov& K = h->kr;
+  k_copy_in<<<(unsigned)((K.n2 + 255) / 256), 256, 0, h->stream>>>(K.V, K.n2, K.jdev, K.vin);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// Start of a Krylov cycle for r = V_0 (unnormalised, already in V): nrm2 = |r|^2 per cell.
+// Cells whose |r| is already within tolerance start inactive (kdone 0).
+__global__ void k_start(int C, int kmax, const double* __restrict__ nrm2, const double* __restrict__ bnorm,
+                        const double* __restrict__ tolc, double* __restrict__ g, int32_t* __restrict__ active,
+                        int32_t* __restrict__ kdone, double* __restrict__ res, int32_t* __restrict__ jdev) {
+  __shared__ int cnt[1024];
+  int n = 0;
+  for (int c = threadIdx.x; c < C; c += blockDim.x) {
+    const double beta = sqrt(nrm2[c]);
+    double* gc = g + (int64_t)c * (kmax + 1);
+    for (int i = 0; i <= kmax; ++i) gc[i] = 0.0;
+    gc[0] = beta;
+    const int act = (active[c] != 0) && (beta > tolc[c] * bnorm[c]);
+    active[c] = act;
+    kdone[c] = 0;
+    res[c] = beta / bnorm[c];
+    n += act;
+  }
+  cnt[threadIdx.x] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < (int)blockDim.x; ++k) t += cnt[k];
+    jdev[0] = 0;
+    jdev[1] = t;
+  }
+}
+
+__global__ void k_normalize0(double* __restrict__ V, int64_t n2, int64_t N, const double* __restrict__ nrm2,
+                             const int32_t* __restrict__ ncell) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n2) return;
+  const double nr = sqrt(nrm2[ncell[r < N ? r : r - N]]);
+  V[r] = nr > 0.0 ? V[r] / nr : 0.0;
+}
+
+// V_0 holds r; active/bnorm/tolc are set by the caller.
+void gm_start(spm_handle* h) {
+  Krylov& K = h->kr;
+  gm_dot(h, K.V, K.V, K.nrm2);
+  const int bs = h->geo.C >= 1024 ? 1024 : ((h->geo.C + 63) / 64) * 64;
+  k_start<<<1, bs, 0, h->stream>>>(h->geo.C, K.kmax, K.nrm2, K.bnorm, K.tolc, K.g, K.active, K.kdone, K.res, K.jdev);
+  SPM_HIP_CHECK(hipGetLastError());
+  k_normalize0<<<(unsigned)((K.n2 + 255) / 256), 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.nrm2, h->geo.ncell);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// y_c = R_c^{-1} g_c[0..k_c) (k_c = kdone, or j for cells still active), then
+// x[r] += sum_{i < k_c} V_i[r] y_c[i].
+__global__ void k_backsolve(int C, int kmax, const int32_t* __restrict__ jdev, const double* __restrict__ H,
+                            const double* __restrict__ g, const int32_t* __restrict__ active,
+                            int32_t* __restrict__ kdone, double* __restrict__ y) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  if (active[c] != 0) kdone[c] = jdev[0];
+  const int k = kdone[c];
+  const int ldp = kmax + 1;
+  const double* gc = g + (int64_t)c * ldp;
+  double* yc = y + (int64_t)c * kmax;
+  for (int i = k - 1; i >= 0; --i) {
+    double s = gc[i];
+    for (int q = i + 1; q < k; ++q) s -= H[((int64_t)c * kmax + q) * ldp + i] * yc[q];
+    const double d = H[((int64_t)c * kmax + i) * ldp + i];
+    yc[i] = d != 0.0 ? s / d : 0.0;
+  }
+}
+
+__global__ void k_update_x(const double* __restrict__ V, int64_t n2, int64_t N, int kmax,
+                           const int32_t* __restrict__ kdone, const double* __restrict__ y,
+                           const int32_t* __restrict__ ncell, double* __restrict__ x) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n2) return;
+  const int c = ncell[r < N ? r : r - N];
+  const int k = kdone[c];
+  const double* yc = y + (int64_t)c * kmax;
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) s += V[(int64_t)i * n2 + r] * yc[i];
+  x[r] += s;
+}
+
+void gm_backsolve_update(spm_handle* h, double* x) {
+  Krylov& K = h->kr;
+  k_backsolve<<<(h->geo.C + 63) / 64, 64, 0, h->stream>>>(h->geo.C, K.kmax, K.jdev, K.H, K.g, K.active, K.kdone, K.yv);
+  SPM_HIP_CHECK(hipGetLastError());
+  k_update_x<<<(unsigned)((K.n2 + 255) / 256), 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.kmax, K.kdone, K.yv,
+                                                                    h->geo.ncell, x);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -86,80 +319,23 @@ void gm_copy(spm_handle* h, double* dst, const double* src, int64_t n) {
 
 void gm_zero(spm_handle* h, double* dst, int64_t n) { gm_copy(h, dst, nullptr, n); }
 
-// v /= sqrt(nrm2[0]) (zero vector stays zero); norm_out[0] = sqrt(nrm2[0])
-__global__ void k_scale(const double* __restrict__ nrm2, double* __restrict__ v, int64_t n, double* __restrict__ norm_out) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const double nr = sqrt(nrm2[0]);
-  if (r == 0 && norm_out) norm_out[0] = nr;
-  if (r >= n) return;
-  v[r] = nr > 0.0 ? v[r] / nr : 0.0;
+__global__ void k_stamp_start(unsigned long long* stamp, int C) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) stamp[C] = wall_clock64();
 }
 
-void gm_scale_by_norm(spm_handle* h, const double* nrm2, double* v, int64_t n, double* norm_out) {
-  k_scale<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(nrm2, v, n, norm_out);
+void gm_stamp_start(spm_handle* h) {
+  k_stamp_start<<<1, 64, 0, h->stream>>>(h->kr.stamp, h->geo.C);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-// g = [beta, 0, ...]
-__global__ void k_init(const double* __restrict__ nrm2, double* __restrict__ g, int kmax) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i > kmax) return;
-  g[i] = (i == 0) ? sqrt(nrm2[0]) : 0.0;
+// stamp[c] = wall clock for the cells flagged in mask (convergence seen by the host)
+__global__ void k_stamp_mask(unsigned long long* stamp, const int32_t* __restrict__ mask, int C) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < C && mask[c] != 0) stamp[c] = wall_clock64();
 }
 
-void gm_init(spm_handle* h, const double* nrm2) {
-  k_init<<<(h->kr.kmax + 256) / 256, 256, 0, h->stream>>>(nrm2, h->kr.g, h->kr.kmax);
-  SPM_HIP_CHECK(hipGetLastError());
-}
-
-// Column j of H = h1 + h2 (CGS2 passes), subdiagonal sqrt(nrm2); apply the previous
-// rotations, make rotation j, update g; res[0] = |g_{j+1}| / bnorm.
-__global__ void k_givens(int j, int kmax, const double* __restrict__ h1, const double* __restrict__ h2,
-                         const double* __restrict__ nrm2, double bnorm, double* __restrict__ H, double* __restrict__ cs,
-                         double* __restrict__ sn, double* __restrict__ g, double* __restrict__ res) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double* col = H + (int64_t)j * (kmax + 1);
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  col[j + 1] = sqrt(nrm2[0]);
-  for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-    col[i] = t;
-  }
-  const double a = col[j], b = col[j + 1];
-  const double r = hypot(a, b);
-  const double c = r > 0.0 ? a / r : 1.0, s = r > 0.0 ? b / r : 0.0;
-  cs[j] = c;
-  sn[j] = s;
-  col[j] = r;
-  col[j + 1] = 0.0;
-  g[j + 1] = -s * g[j];
-  g[j] = c * g[j];
-  res[0] = fabs(g[j + 1]) / bnorm;
-  res[1] = r;
-}
-
-void gm_givens(spm_handle* h, int j, const double* h1, const double* h2, const double* nrm2, double bnorm,
-               double* res_out) {
-  Krylov& k = h->kr;
-  k_givens<<<1, 64, 0, h->stream>>>(j, k.kmax, h1, h2, nrm2, bnorm, k.H, k.cs, k.sn, k.g, res_out);
-  SPM_HIP_CHECK(hipGetLastError());
-}
-
-// y = R^{-1} g[0..k) by back substitution (R upper triangular in H).
-__global__ void k_backsolve(int k, int kmax, const double* __restrict__ H, const double* __restrict__ g,
-                            double* __restrict__ y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int i = k - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int c = i + 1; c < k; ++c) s -= H[(int64_t)c * (kmax + 1) + i] * y[c];
-    const double d = H[(int64_t)i * (kmax + 1) + i];
-    y[i] = d != 0.0 ? s / d : 0.0;
-  }
-}
-
-void gm_backsolve(spm_handle* h, int k) {
-  k_backsolve<<<1, 64, 0, h->stream>>>(k, h->kr.kmax, h->kr.H, h->kr.g, h->kr.yv);
+void gm_stamp_mask(spm_handle* h, const int32_t* mask_dev) {
+  k_stamp_mask<<<(h->geo.C + 63) / 64, 64, 0, h->stream>>>(h->kr.stamp, mask_dev, h->geo.C);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

@@ -56,7 +56,8 @@ __global__ void k_assemble(int64_t N, Geo g, const double* __restrict__ sigma, c
                            const double* __restrict__ pF, double* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const double alpha = -(T[0] * g.nx[0] + T[N] * g.ny[0]);
+  const int64_t i0 = g.cnoff[g.ncell[i]];  // pin node: the first node of the cell
+  const double alpha = -(T[i0] * g.nx[i0] + T[N + i0] * g.ny[i0]);
   const int q = g.pid[i];
   const double rx = g.x[i] - g.pcx[q], ry = g.y[i] - g.pcy[q];
   const double F1 = pF[4 * q + 0], F2 = pF[4 * q + 1], tq = pF[4 * q + 2];
@@ -70,21 +71,23 @@ void launch_assemble(spm_handle* h, const double* sigma, double* out) {
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-// Velocity and vorticity at the particle centres: one block per particle, all nodes x 9 images.
-__global__ __launch_bounds__(256) void k_velocities(int64_t N, Geo g, Shifts<double> sh, const double* __restrict__ f1,
-                                                    const double* __restrict__ f2, int M, const double* __restrict__ px,
-                                                    const double* __restrict__ py, const double* __restrict__ xi,
-                                                    double cUx, double cUy, double mu, double gamma,
-                                                    double* __restrict__ vel, double* __restrict__ omega) {
+// Velocity and vorticity at the particle centres: one block per particle, the nodes of
+// its cell x 9 images.
+__global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restrict__ f1, const double* __restrict__ f2,
+                                                    int M, const double* __restrict__ px, const double* __restrict__ py,
+                                                    const double* __restrict__ xi_all, double cUx, double cUy, double mu,
+                                                    double gamma, double* __restrict__ vel, double* __restrict__ omega) {
   __shared__ double sc[16];
   const int q = blockIdx.x;
+  const int cell = g.pcell[q];
+  const double skew = g.cskew[cell];
   const double cx = g.pcx[q], cy = g.pcy[q];
   const double k4 = 1.0 / (4.0 * kPi * mu), k2 = -1.0 / (2.0 * kPi * mu);
   double u1 = 0, u2 = 0, vo = 0;
-  for (int64_t j = threadIdx.x; j < N; j += blockDim.x) {
+  for (int64_t j = g.cnoff[cell] + threadIdx.x; j < g.cnoff[cell + 1]; j += blockDim.x) {
     const double yx = g.x[j], yy = g.y[j], a = f1[j], b = f2[j];
     for (int s = 0; s < kShifts; ++s) {
-      const double rx = cx - (yx + sh.x[s]), ry = cy - (yy + sh.y[s]);
+      const double rx = cx - (yx + shift_x(s, skew)), ry = cy - (yy + shift_y(s));
       const double r2 = rx * rx + ry * ry;
       const double ir2 = rcp64(r2);
       const double lg = -0.5 * log(r2);
@@ -98,6 +101,7 @@ __global__ __launch_bounds__(256) void k_velocities(int64_t N, Geo g, Shifts<dou
   u2 = block_sum(u2, sc);
   vo = block_sum(vo, sc);
   if (threadIdx.x == 0) {
+    const double* xi = xi_all + (int64_t)cell * 2 * M;
     double c1 = 0, c2 = 0, z1 = 0, z2 = 0, cv = 0;
     for (int p = 0; p < M; ++p) {
       const double a = xi[p], b = xi[M + p];
@@ -128,31 +132,24 @@ __global__ __launch_bounds__(256) void k_velocities(int64_t N, Geo g, Shifts<dou
 }
 
 void launch_velocities(spm_handle* h, double* vel, double* omega) {
-  Shifts<double> sh;
-  for (int m = -1; m <= 1; ++m)
-    for (int n = -1; n <= 1; ++n) {
-      const int s = 3 * (m + 1) + (n + 1);
-      sh.x[s] = (double)m * h->e1[0] + (double)n * h->e2[0];
-      sh.y[s] = (double)m * h->e1[1] + (double)n * h->e2[1];
-    }
-  k_velocities<<<h->geo.No, 256, 0, h->stream>>>(h->geo.N, h->geo, sh, h->wk.f1, h->wk.f2, h->per.M, h->per.px,
-                                                 h->per.py, h->wk.xi, h->cU[0], h->cU[1], h->cfg.mu, h->cfg.gamma,
-                                                 vel, omega);
+  k_velocities<<<h->geo.No, 256, 0, h->stream>>>(h->geo, h->wk.f1, h->wk.f2, h->per.M, h->per.px, h->per.py,
+                                                 h->wk.xi, h->cU[0], h->cU[1], h->cfg.mu, h->cfg.gamma, vel, omega);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-__global__ void k_mu_eff(int No, const double* __restrict__ pF, double mu, double gamma, double area,
+// mu_eff of every cell (|U| = |det(e1, e2)| = 1 for e1 = (1, 0), e2 = (s, 1)).
+__global__ void k_mu_eff(const int32_t* __restrict__ cpoff, const double* __restrict__ pF, double mu, double gamma,
                          double* __restrict__ out) {
   __shared__ double sc[16];
+  const int cell = blockIdx.x;
   double s = 0;
-  for (int q = threadIdx.x; q < No; q += blockDim.x) s += pF[4 * q + 3];
+  for (int q = cpoff[cell] + threadIdx.x; q < cpoff[cell + 1]; q += blockDim.x) s += pF[4 * q + 3];
   s = block_sum(s, sc);
-  if (threadIdx.x == 0) out[0] = mu - s / (2.0 * gamma * area);
+  if (threadIdx.x == 0) out[cell] = mu - s / (2.0 * gamma * 1.0);
 }
 
 void launch_mu_eff(spm_handle* h, double* mu_eff) {
-  const double area = fabs(h->e1[0] * h->e2[1] - h->e1[1] * h->e2[0]);
-  k_mu_eff<<<1, 256, 0, h->stream>>>(h->geo.No, h->wk.pF, h->cfg.mu, h->cfg.gamma, area, mu_eff);
+  k_mu_eff<<<h->geo.C, 256, 0, h->stream>>>(h->geo.cpoff, h->wk.pF, h->cfg.mu, h->cfg.gamma, mu_eff);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

@@ -31,35 +31,40 @@ __device__ __forceinline__ void traction_uv(double rx, double ry, double nx, dou
 }
 
 struct Lat {
-  double e1x, e1y, e2x, e2y;
-  double nLx, nLy, nDx, nDy;
   double inv4pimu;
   int m, M;
 };
 
 static Lat lattice_args(spm_handle* h) {
   Lat L;
-  L.e1x = h->e1[0];
-  L.e1y = h->e1[1];
-  L.e2x = h->e2[0];
-  L.e2y = h->e2[1];
-  L.nLx = h->per.nL[0];
-  L.nLy = h->per.nL[1];
-  L.nDx = h->per.nD[0];
-  L.nDy = h->per.nD[1];
   L.inv4pimu = 1.0 / (4.0 * kPi * h->cfg.mu);
   L.m = h->per.m;
   L.M = h->per.M;
   return L;
 }
 
+// Lattice of a cell: e1 = (1, 0), e2 = (skew, 1); wall normals n_L = (e2_2, -e2_1)/|e2|, n_D = (0, 1).
+struct CellLat {
+  double e2x, nLx, nLy;
+};
+__device__ __forceinline__ CellLat cell_lat(double skew) {
+  const double l2 = sqrt(skew * skew + 1.0);
+  return {skew, 1.0 / l2, -skew / l2};
+}
+
 // Q[row][col], row in [0, 8m), col = comp * M + p: the wall jumps of the field of a unit
 // force e_comp at proxy p.
-__global__ void k_build_Q(Lat L, const double* __restrict__ wx, const double* __restrict__ wy,
-                          const double* __restrict__ px, const double* __restrict__ py, double* __restrict__ Q) {
+__global__ void k_build_Q(Lat L, const double* __restrict__ cskew, const double* __restrict__ wx_all,
+                          const double* __restrict__ wy_all, const double* __restrict__ px,
+                          const double* __restrict__ py, double* __restrict__ Q_all) {
   const int m = L.m, M = L.M;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 8 * m * 2 * M) return;
+  const int cell = blockIdx.y;
+  const CellLat CL = cell_lat(cskew[cell]);
+  const double* wx = wx_all + (int64_t)cell * 2 * m;
+  const double* wy = wy_all + (int64_t)cell * 2 * m;
+  double* Q = Q_all + (int64_t)cell * 8 * m * 2 * M;
   const int row = idx / (2 * M), col = idx % (2 * M);
   const int comp = col / M, p = col % M;
   const int blk = row / m, q = row % m;       // blk: 0,1 u on L; 2,3 T on L; 4,5 u on D; 6,7 T on D
@@ -67,8 +72,8 @@ __global__ void k_build_Q(Lat L, const double* __restrict__ wx, const double* __
   const int kind = (blk % 4) / 2;              // 0 velocity, 1 traction
   const int outc = blk % 2;                    // output component
   const double x0 = wx[onD ? m + q : q], y0 = wy[onD ? m + q : q];
-  const double sx = onD ? L.e2x : L.e1x, sy = onD ? L.e2y : L.e1y;
-  const double nx = onD ? L.nDx : L.nLx, ny = onD ? L.nDy : L.nLy;
+  const double sx = onD ? CL.e2x : 1.0, sy = onD ? 1.0 : 0.0;
+  const double nx = onD ? 0.0 : CL.nLx, ny = onD ? 1.0 : CL.nLy;
   const double f1 = comp == 0 ? 1.0 : 0.0, f2 = comp == 1 ? 1.0 : 0.0;
   double a1 = 0, a2 = 0, b1 = 0, b2 = 0;
   if (kind == 0) {
@@ -84,7 +89,8 @@ __global__ void k_build_Q(Lat L, const double* __restrict__ wx, const double* __
 void launch_build_Q(spm_handle* h) {
   const Lat L = lattice_args(h);
   const int n = 8 * L.m * 2 * L.M;
-  k_build_Q<<<(n + 255) / 256, 256, 0, h->stream>>>(L, h->per.wx, h->per.wy, h->per.px, h->per.py, h->per.Q);
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)h->geo.C);
+  k_build_Q<<<grid, 256, 0, h->stream>>>(L, h->geo.cskew, h->per.wx, h->per.wy, h->per.px, h->per.py, h->per.Q);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -96,9 +102,14 @@ void launch_build_Q(spm_handle* h) {
 // gauge modes of the empty-box problem: constant velocity and pressure) and any
 // singular value below rcond * s_max are dropped:  Q^+ = sum_k v_k u_k^T / s_k.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_jacobi(int rows, int ncol, const double* __restrict__ Q,
-                                                 double* __restrict__ A, double* __restrict__ V,
-                                                 double* __restrict__ S, int max_sweeps) {
+__global__ __launch_bounds__(1024) void k_jacobi(int rows, int ncol, const double* __restrict__ Q_all,
+                                                 double* __restrict__ A_all, double* __restrict__ V_all,
+                                                 double* __restrict__ S_all, int max_sweeps) {
+  const int cell = blockIdx.x;
+  const double* Q = Q_all + (int64_t)cell * rows * ncol;
+  double* A = A_all + (int64_t)cell * rows * ncol;
+  double* V = V_all + (int64_t)cell * ncol * ncol;
+  double* S = S_all + (int64_t)cell * (ncol + 1);
   __shared__ int perm[1024];
   __shared__ double offmax[1024];
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -180,8 +191,14 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rows, int ncol, const doubl
 }
 
 // Qp[i][r] = sum_{k kept} V[k][i] A[k][r] / s_k^2  (u_k = A_k / s_k)
-__global__ void k_pinv_assemble(int rows, int ncol, const double* __restrict__ A, const double* __restrict__ V,
-                                const double* __restrict__ S, double rcond, int n_gauge, double* __restrict__ Qp) {
+__global__ void k_pinv_assemble(int rows, int ncol, const double* __restrict__ A_all,
+                                const double* __restrict__ V_all, const double* __restrict__ S_all, double rcond,
+                                int n_gauge, double* __restrict__ Qp_all) {
+  const int cell = blockIdx.y;
+  const double* A = A_all + (int64_t)cell * rows * ncol;
+  const double* V = V_all + (int64_t)cell * ncol * ncol;
+  const double* S = S_all + (int64_t)cell * (ncol + 1);
+  double* Qp = Qp_all + (int64_t)cell * rows * ncol;
   __shared__ double w[1024];
   if (threadIdx.x == 0) {
     double smax = 0;
@@ -215,12 +232,13 @@ void launch_pinv(spm_handle* h) {
   int G = 1;
   while (G * 2 * npair <= 1024 && G < 64) G *= 2;
   const int nt = G * npair;
-  k_jacobi<<<1, nt, 0, h->stream>>>(rows, ncol, h->per.Q, h->per.svd_a, h->per.svd_v, h->per.svd_s, 60);
+  k_jacobi<<<h->geo.C, nt, 0, h->stream>>>(rows, ncol, h->per.Q, h->per.svd_a, h->per.svd_v, h->per.svd_s, 60);
   SPM_HIP_CHECK(hipGetLastError());
   const int n = rows * ncol;
-  // one block computes the weights; every block recomputes them (cheap, ncol <= 1024)
-  k_pinv_assemble<<<(n + 255) / 256, 256, 0, h->stream>>>(rows, ncol, h->per.svd_a, h->per.svd_v, h->per.svd_s,
-                                                          h->cfg.rcond, 3, h->per.Qp);
+  // every block recomputes the truncation weights of its cell (cheap, ncol <= 1024)
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)h->geo.C);
+  k_pinv_assemble<<<grid, 256, 0, h->stream>>>(rows, ncol, h->per.svd_a, h->per.svd_v, h->per.svd_s, h->cfg.rcond, 3,
+                                               h->per.Qp);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -231,21 +249,26 @@ void launch_pinv(spm_handle* h) {
 // Grid (chunks, 2m): block (c, w) sums its source chunk for wall point w; partials
 // disc[c][w][4] = (du1, du2, dT1, dT2) are summed in fixed order by k_xi.
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __restrict__ wx,
-                                              const double* __restrict__ wy, const double* __restrict__ x,
-                                              const double* __restrict__ y, const double* __restrict__ f1,
-                                              const double* __restrict__ f2, int64_t chunk,
+__global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __restrict__ cskew,
+                                              const double* __restrict__ wx_all, const double* __restrict__ wy_all,
+                                              const double* __restrict__ x, const double* __restrict__ y,
+                                              const double* __restrict__ f1, const double* __restrict__ f2,
+                                              const int64_t* __restrict__ cs0, const int64_t* __restrict__ cs1,
+                                              const int32_t* __restrict__ ccell, const int32_t* __restrict__ active,
                                               double* __restrict__ disc) {
   __shared__ double sc[16];
+  const int chunk = blockIdx.x;
   const int wpt = blockIdx.y;
+  const int cell = ccell[chunk];
+  if (active != nullptr && active[cell] == 0) return;
+  const CellLat CL = cell_lat(cskew[cell]);
   const bool onD = wpt >= L.m;
-  const double x0 = wx[wpt], y0 = wy[wpt];
-  const double nx = onD ? L.nDx : L.nLx, ny = onD ? L.nDy : L.nLy;
-  // far column/row (-2 along the wall-normal lattice vector) minus the near one (+1)
-  const double ax = onD ? L.e2x : L.e1x, ay = onD ? L.e2y : L.e1y;   // across the wall pair
-  const double bx = onD ? L.e1x : L.e2x, by = onD ? L.e1y : L.e2y;   // along the wall
-  const int64_t j0 = blockIdx.x * chunk;
-  const int64_t j1 = (j0 + chunk < N) ? j0 + chunk : N;
+  const double x0 = wx_all[(int64_t)cell * 2 * L.m + wpt], y0 = wy_all[(int64_t)cell * 2 * L.m + wpt];
+  const double nx = onD ? 0.0 : CL.nLx, ny = onD ? 1.0 : CL.nLy;
+  // far column/row (-2 along the lattice vector across the wall pair) minus the near one (+1)
+  const double ax = onD ? CL.e2x : 1.0, ay = onD ? 1.0 : 0.0;   // across the wall pair
+  const double bx = onD ? 1.0 : CL.e2x, by = onD ? 0.0 : 1.0;   // along the wall
+  const int64_t j0 = cs0[chunk], j1 = cs1[chunk];
   double u1 = 0, u2 = 0, t1 = 0, t2 = 0;
   for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
     const double yj = x[j], zj = y[j], g1 = f1[j], g2 = f2[j];
@@ -269,7 +292,7 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
   t1 = block_sum(t1, sc);
   t2 = block_sum(t2, sc);
   if (threadIdx.x == 0) {
-    double* o = disc + ((int64_t)blockIdx.x * 2 * L.m + wpt) * 4;
+    double* o = disc + ((int64_t)chunk * 2 * L.m + wpt) * 4;
     o[0] = u1;
     o[1] = u2;
     o[2] = t1;
@@ -277,26 +300,32 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
   }
 }
 
-void launch_disc(spm_handle* h) {
+void launch_disc_impl(spm_handle* h, bool with_active) {
   const Lat L = lattice_args(h);
-  const int64_t N = h->geo.N;
-  const int nc = h->wk.nchunk_disc;
-  const int64_t chunk = (N + nc - 1) / nc;
-  dim3 grid((unsigned)nc, (unsigned)(2 * L.m));
-  k_disc<<<grid, 256, 0, h->stream>>>(N, L, h->per.wx, h->per.wy, h->geo.x, h->geo.y, h->wk.f1, h->wk.f2, chunk,
-                                      h->wk.disc);
+  dim3 grid((unsigned)h->wk.ndisc, (unsigned)(2 * L.m));
+  k_disc<<<grid, 256, 0, h->stream>>>(h->geo.N, L, h->geo.cskew, h->per.wx, h->per.wy, h->geo.x, h->geo.y, h->wk.f1,
+                                      h->wk.f2, h->wk.disc_s0, h->wk.disc_s1, h->wk.disc_cell,
+                                      with_active ? h->kr.active : nullptr, h->wk.disc);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-// One block: g = sum of chunk partials, F = sum of per-particle forces, xi = Q^+ (g0 - g).
-__global__ void k_xi(Lat L, int nchunk, int No, const double* __restrict__ disc, const double* __restrict__ pF,
-                     const double* __restrict__ Qp, double* __restrict__ xi) {
+void launch_disc(spm_handle* h) { launch_disc_impl(h, false); }
+
+// One block per cell: g = sum of the cell's chunk partials, F = sum of its particles'
+// forces, xi = Q^+ (g0 - g).
+__global__ void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __restrict__ disc_off,
+                     const int32_t* __restrict__ cpoff, const double* __restrict__ disc, const double* __restrict__ pF,
+                     const double* __restrict__ Qp_all, const int32_t* __restrict__ active, double* __restrict__ xi_all) {
   __shared__ double gt[8 * 256];
   __shared__ double Fs[2];
+  const int cell = blockIdx.x;
+  if (active != nullptr && active[cell] == 0) return;
   const int m = L.m, M = L.M;
+  const double* Qp = Qp_all + (int64_t)cell * 2 * M * 8 * m;
+  double* xi = xi_all + (int64_t)cell * 2 * M;
   if (threadIdx.x == 0) {
     double F1 = 0, F2 = 0;
-    for (int q = 0; q < No; ++q) {
+    for (int q = cpoff[cell]; q < cpoff[cell + 1]; ++q) {
       F1 += pF[4 * q + 0];
       F2 += pF[4 * q + 1];
     }
@@ -304,10 +333,11 @@ __global__ void k_xi(Lat L, int nchunk, int No, const double* __restrict__ disc,
     Fs[1] = F2;
   }
   __syncthreads();
-  const double l1 = sqrt(L.e1x * L.e1x + L.e1y * L.e1y), l2 = sqrt(L.e2x * L.e2x + L.e2y * L.e2y);
+  const double skew = cskew[cell];
+  const double l1 = 1.0, l2 = sqrt(skew * skew + 1.0);
   for (int wpt = threadIdx.x; wpt < 2 * m; wpt += blockDim.x) {
     double s[4] = {0, 0, 0, 0};
-    for (int c = 0; c < nchunk; ++c)
+    for (int c = disc_off[cell]; c < disc_off[cell + 1]; ++c)
       for (int k = 0; k < 4; ++k) s[k] += disc[((int64_t)c * 2 * m + wpt) * 4 + k];
     const bool onD = wpt >= m;
     const int q = onD ? wpt - m : wpt;
@@ -326,26 +356,32 @@ __global__ void k_xi(Lat L, int nchunk, int No, const double* __restrict__ disc,
   }
 }
 
-void launch_xi(spm_handle* h) {
+void launch_xi_impl(spm_handle* h, bool with_active) {
   const Lat L = lattice_args(h);
-  k_xi<<<1, 256, 0, h->stream>>>(L, h->wk.nchunk_disc, h->geo.No, h->wk.disc, h->wk.pF, h->per.Qp, h->wk.xi);
+  k_xi<<<h->geo.C, 256, 0, h->stream>>>(L, h->geo.cskew, h->wk.disc_off, h->geo.cpoff, h->wk.disc, h->wk.pF,
+                                        h->per.Qp, with_active ? h->kr.active : nullptr, h->wk.xi);
   SPM_HIP_CHECK(hipGetLastError());
 }
+
+void launch_xi(spm_handle* h) { launch_xi_impl(h, false); }
 
 // ----------------------------------------------------------------------------
 // Combine: T_i = sum of near-sum split partials + self term + proxy correction.
 // Self term (limit of the smooth kernel on the curve): -(kappa/2pi) tau (tau . w sigma).
 // Proxy correction (step 4): sum_p G^t(x_i, y_p; n_i) xi_p.
 // ----------------------------------------------------------------------------
-__global__ void k_combine(int64_t N, int S, const double* __restrict__ Tpart, Geo g, const double* __restrict__ sigma,
-                          int M, const double* __restrict__ px, const double* __restrict__ py,
-                          const double* __restrict__ xi, int with_extra, double* __restrict__ T) {
+__global__ void k_combine(int64_t N, const int32_t* __restrict__ nsplit, const double* __restrict__ Tpart, Geo g,
+                          const double* __restrict__ sigma, int M, const double* __restrict__ px,
+                          const double* __restrict__ py, const double* __restrict__ xi_all, int with_extra,
+                          double* __restrict__ T) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
+  const int cell = g.ncell[i];
+  const int S = nsplit[cell];
   double t1 = 0, t2 = 0;
   for (int k = 0; k < S; ++k) {
-    t1 += Tpart[k * 2 * N + i];
-    t2 += Tpart[k * 2 * N + N + i];
+    t1 += Tpart[(int64_t)k * 2 * N + i];
+    t2 += Tpart[(int64_t)k * 2 * N + N + i];
   }
   if (with_extra) {
     const double w = g.w[i], tx = g.tx[i], ty = g.ty[i];
@@ -354,6 +390,7 @@ __global__ void k_combine(int64_t N, int S, const double* __restrict__ Tpart, Ge
     t1 += ks * tx;
     t2 += ks * ty;
     const double xx = g.x[i], yy = g.y[i], nx = g.nx[i], ny = g.ny[i];
+    const double* xi = xi_all + (int64_t)cell * 2 * M;
     double c1 = 0, c2 = 0;
     for (int p = 0; p < M; ++p) traction_uv(xx - px[p], yy - py[p], nx, ny, xi[p], xi[M + p], c1, c2);
     t1 += c1;
@@ -365,8 +402,8 @@ __global__ void k_combine(int64_t N, int S, const double* __restrict__ Tpart, Ge
 
 void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision) {
   const int64_t N = h->geo.N;
-  const int S = h->wk.near[precision == SPM_FP64 ? 0 : 1].splits;
-  k_combine<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, S, h->wk.Tpart, h->geo, sigma, h->per.M,
+  const NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
+  k_combine<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, P.nsplit, h->wk.Tpart, h->geo, sigma, h->per.M,
                                                                 h->per.px, h->per.py, h->wk.xi,
                                                                 with_self_corr ? 1 : 0, h->wk.T);
   SPM_HIP_CHECK(hipGetLastError());

@@ -1,4 +1,9 @@
 // Internal declarations of the MI355X mobility solver (not part of the ABI).
+//
+// A handle holds C >= 1 independent unit cells (an ensemble); the single-cell calls
+// of the ABI are the case C = 1. Nodes and particles of all cells are stored
+// back to back (cell-major, then particle-major), so every kernel works on the
+// whole ensemble at once and finds a node's cell through ncell[].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,12 +21,12 @@ constexpr int kShifts = 9;   // 3x3 images m e1 + n e2, index 3 (m + 1) + (n + 1
 constexpr int kZeroShift = 4;
 constexpr int kMaxNodesPerParticle = 512;   // close-evaluation LDS staging (k_vplus) holds one curve
 
-// Image shifts as kernel arguments (land in scalar registers).
-template <typename R>
-struct Shifts {
-  R x[kShifts];
-  R y[kShifts];
-};
+// Image shift s = m e1 + n e2 of a cell with e1 = (1, 0), e2 = (skew, 1), computed the
+// same way by every kernel (the FP32 close correction needs bit-identical shifts).
+__host__ __device__ __forceinline__ double shift_x(int s, double skew) {
+  return (double)(s / 3 - 1) + (double)(s % 3 - 1) * skew;
+}
+__host__ __device__ __forceinline__ double shift_y(int s) { return (double)(s % 3 - 1); }
 
 // ----------------------------------------------------------------------------
 // One pair of the single-layer traction sum (Sec. 4.1 eq. Gt without the -1/pi,
@@ -101,34 +106,40 @@ __device__ __forceinline__ double block_sum(double v, double* scratch /* >= 16 d
 }
 
 // ----------------------------------------------------------------------------
-// Device buffers of a handle (all SoA; N nodes, No particles).
+// Device buffers of a handle (all SoA; N nodes, No particles, C cells).
 // ----------------------------------------------------------------------------
 struct Geo {
   int64_t N = 0;
   int32_t No = 0;
+  int32_t C = 0;
   // nodes, FP64
   double *x = nullptr, *y = nullptr, *nx = nullptr, *ny = nullptr, *w = nullptr, *kap = nullptr;
   double *tx = nullptr, *ty = nullptr, *xpx = nullptr, *xpy = nullptr;
   // nodes, FP32 shadows (targets and sources of the FP32 near sum)
   float *xf = nullptr, *yf = nullptr, *nxf = nullptr, *nyf = nullptr;
-  int32_t* pid = nullptr;
+  int32_t* pid = nullptr;     // [N] particle of each node
+  int32_t* ncell = nullptr;   // [N] cell of each node
   // particles
   double *pcx = nullptr, *pcy = nullptr, *pth = nullptr, *pa = nullptr, *pb = nullptr, *pper = nullptr;
   int32_t *poff = nullptr, *pn = nullptr;
+  int32_t* pcell = nullptr;   // [No] cell of each particle
+  // cells
+  int64_t* cnoff = nullptr;   // [C + 1] node offsets
+  int32_t* cpoff = nullptr;   // [C + 1] particle offsets
+  double* cskew = nullptr;    // [C] reduced skew (e2 = (skew, 1))
 };
 
 struct Periodizer {
   int32_t m = 0, M = 0;
-  double* wx = nullptr;   // [2m] wall points: L then D
+  double* wx = nullptr;     // [C x 2m] wall points: L then D
   double* wy = nullptr;
-  double* px = nullptr;   // [M] proxies
+  double* px = nullptr;     // [M] proxies (the same circle about c_U for every cell)
   double* py = nullptr;
-  double* Q = nullptr;    // [8m x 2M] row-major
-  double* Qp = nullptr;   // [2M x 8m] row-major pseudo-inverse
-  double* svd_a = nullptr;  // Jacobi workspace [8m x 2M] column-major
-  double* svd_v = nullptr;  // [2M x 2M]
-  double* svd_s = nullptr;  // [2M]
-  double nL[2] = {1, 0}, nD[2] = {0, 1};
+  double* Q = nullptr;      // [C x 8m x 2M] row-major
+  double* Qp = nullptr;     // [C x 2M x 8m] row-major pseudo-inverse
+  double* svd_a = nullptr;  // Jacobi workspace [C x 8m x 2M] column-major
+  double* svd_v = nullptr;  // [C x 2M x 2M]
+  double* svd_s = nullptr;  // [C x (2M + 1)]: singular values and the sweep count
 };
 
 struct CloseList {
@@ -145,49 +156,101 @@ struct CloseList {
 };
 
 // Launch shape of the near sum: block threads, targets per lane, sources per LDS
-// tile, source splits (gridDim.y). Picked by the heuristic or the autotuner.
+// tile, sources per split (each cell's sources are cut into ceil(N_c / chunk)
+// splits). Picked by the heuristic or the autotuner.
 struct NearConfig {
   int32_t block = 256;
   int32_t tpt = 1;
   int32_t tile = 256;
-  int32_t splits = 1;
+  int32_t chunk = 2048;
+};
+
+// One work item of the persistent near-sum kernel: targets [t0, t1) of cell c,
+// sources [s0, s1) of the same cell, written to partial slot `split`.
+struct NearItem {
+  int64_t t0, t1, s0, s1;
+  int32_t c, split;
+};
+
+struct NearPlan {
+  NearConfig cfg;
+  int32_t nitems = 0;
+  int32_t max_splits = 1;
+  NearItem* items = nullptr;  // [nitems], cost-sorted (largest first)
+  int32_t* nsplit = nullptr;  // [C] splits of each cell
+  int32_t* counter = nullptr; // [1] work-queue head
+  int32_t grid = 0;           // persistent grid size
 };
 
 struct Work {
-  NearConfig near[2];         // [0] FP64, [1] FP32
-  bool tuned = false;         // near[] came from the autotuner (for tuned_N nodes)
+  NearPlan near[2];           // [0] FP64, [1] FP32
+  bool tuned = false;         // near[].cfg came from the autotuner (for tuned_N nodes)
   int64_t tuned_N = -1;
-  int32_t nchunk_disc = 1;    // source chunks of the wall discrepancy
+  // wall discrepancy work items (source chunks of every cell)
+  int32_t ndisc = 0;
+  int64_t* disc_s0 = nullptr; // [ndisc] chunk source ranges
+  int64_t* disc_s1 = nullptr;
+  int32_t* disc_cell = nullptr;
+  int32_t* disc_off = nullptr;  // [C + 1] chunks of each cell
   double *f1 = nullptr, *f2 = nullptr;   // w sigma
   float *f1f = nullptr, *f2f = nullptr;
-  double* Tpart = nullptr;    // [splits x 2N]
+  double* Tpart = nullptr;    // [max splits x 2N]
   double* T = nullptr;        // [2N]
   double* pF = nullptr;       // [No x 4]: F1, F2, torque, stresslet
-  double* disc = nullptr;     // [nchunk x 2m x 4]
-  double* xi = nullptr;       // [2M]
+  double* disc = nullptr;     // [ndisc x 2m x 4]
+  double* xi = nullptr;       // [C x 2M]
   double* scal = nullptr;     // [16] device scalars
-  size_t tpart_cap = 0;
 };
 
+// Krylov state. Cells iterate in lockstep on one global iteration index j (kept in
+// device memory so one captured iteration can be replayed); each cell has its own
+// Hessenberg matrix, rotations, tolerance and active flag and stops on its own.
 struct Krylov {
   int32_t kmax = 0;
   int64_t n2 = 0;
   double* V = nullptr;        // [(kmax+1) x n2]
-  double* H = nullptr;        // [(kmax+1) x kmax], column j at H + j*(kmax+1)
-  double* cs = nullptr;       // [kmax]
+  double* H = nullptr;        // [C x kmax x (kmax+1)], column j of cell c at H + (c*kmax + j)*(kmax+1)
+  double* cs = nullptr;       // [C x kmax]
   double* sn = nullptr;
-  double* g = nullptr;        // [kmax+1]
-  double* yv = nullptr;       // [kmax]
-  double* h = nullptr;        // [kmax+1] CGS coefficients
-  double* part = nullptr;     // [nchunk x (kmax+1)] dot partials
+  double* g = nullptr;        // [C x (kmax+1)]
+  double* yv = nullptr;       // [C x kmax]
+  double* h1 = nullptr;       // [C x (kmax+1)] CGS pass 1 coefficients
+  double* h2 = nullptr;       // [C x (kmax+1)] pass 2
+  double* nrm2 = nullptr;     // [C]
+  double* bnorm = nullptr;    // [C] norm of this solve's right-hand side
+  double* tolc = nullptr;     // [C] stopping tolerance relative to bnorm
+  double* res = nullptr;      // [C] residual estimate |g_{j+1}| / bnorm
+  int32_t* active = nullptr;  // [C]
+  int32_t* kdone = nullptr;   // [C] Krylov iterations of each cell
+  unsigned long long* stamp = nullptr;  // [C + 1] device wall clock at convergence; [C] = solve start
+  int32_t* jdev = nullptr;    // [2]: current j, number of active cells
+  double* part = nullptr;     // [nseg x (kmax+1)] dot partials
+  int32_t nseg = 0;
+  int64_t* seg_n0 = nullptr;  // [nseg] node range of each dot segment
+  int64_t* seg_n1 = nullptr;
+  int32_t* seg_cell = nullptr;// [nseg] cell of each segment
+  int32_t* seg_off = nullptr; // [C + 1] segments of each cell
   double* tmp = nullptr;      // [n2]
   double* tmp2 = nullptr;     // [n2]
-  double* res = nullptr;      // [4] device scalars: |g_{j+1}|, norm, ...
-  double* host_res = nullptr; // pinned
+  double* vin = nullptr;      // [n2] matvec input of the current iteration
+  double* w = nullptr;        // [n2] matvec output of the current iteration
   double* b = nullptr;        // [n2] right-hand side of the current solve
   double* d = nullptr;        // [n2] refinement correction (FP32_IR)
-  double* stepbuf = nullptr;  // [n2 + 3 No + 2] state of spm_step
-  int32_t nchunk = 0;
+  double* stepbuf = nullptr;  // state of spm_step
+  double* dots = nullptr;     // [C] small per-cell reductions
+  void* host = nullptr;       // pinned host scratch
+  size_t host_bytes = 0;
+  // captured iteration graphs per precision (0: FP64, 1: FP32)
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  hipGraph_t graph_src[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+  int32_t* mask = nullptr;            // [C] scratch mask uploaded from the host
+};
+
+struct CellHost {
+  double skew_raw = 0.0, skew = 0.0;
+  int32_t p0 = 0, p1 = 0;
+  int64_t n0 = 0, n1 = 0;
 };
 
 }  // namespace spm
@@ -199,14 +262,14 @@ struct spm_handle {
   spm_free_fn free_fn = nullptr;
   void* alloc_ctx = nullptr;
   std::string err;
-  std::vector<void*> owned;   // allocations to release
 
   bool have_lattice = false, have_particles = false;
-  double e1[2] = {1, 0}, e2[2] = {0, 1}, cU[2] = {0, 0};
-  double skew = 0.0, skew_raw = 0.0;
-  // host copy of the particle table (wrapped centres)
+  double cU[2] = {0, 0};
+  double pending_skew = 0.0;          // set by spm_set_lattice for the next spm_set_ellipses
+  std::vector<spm::CellHost> cells;   // host view of the cells
+  // host copy of the particle table (wrapped centres), all cells
   std::vector<double> cx, cy, th, a, b;
-  std::vector<int32_t> nn, off;
+  std::vector<int32_t> nn, off, pcell;
 
   spm::Geo geo;
   spm::Periodizer per;
@@ -214,6 +277,7 @@ struct spm_handle {
   spm::Work wk;
   spm::Krylov kr;
   double min_gap_est = 0.0;
+  double wallclock_hz = 1e8;
 
   // opt-in kernel timing: HIP events around near-sum launches (kernel 0 = FP64, 1 = FP32)
   bool prof = false;
@@ -235,8 +299,10 @@ void launch_near(spm_handle* h, int precision);
 void prof_flush(spm_handle* h);
 void launch_near_sum_only(spm_handle* h, double* out, int precision);
 bool near_config_valid(const NearConfig& c);
+void build_near_plan(spm_handle* h, int precision);
 void autotune(spm_handle* h, const char* cache_path, double* best_ms_out);
 double time_near(spm_handle* h, int prec, const NearConfig& c, int reps);
+NearConfig heuristic_near(spm_handle* h);
 void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision);
 void launch_disc(spm_handle* h);
 void launch_xi(spm_handle* h);
@@ -252,17 +318,24 @@ void launch_velocities(spm_handle* h, double* vel, double* omega);
 void launch_mu_eff(spm_handle* h, double* mu_eff);
 void launch_gap(spm_handle* h, double* gap_host, int32_t* overlap_host);
 
-// GMRES building blocks (k_gmres.hip)
-void gm_dot_many(spm_handle* h, const double* V, int64_t ld, int cnt, const double* w, double* out);
-void gm_update(spm_handle* h, const double* V, int64_t ld, int cnt, const double* coef, double* w, double sign);
+// GMRES building blocks (k_gmres.hip); per cell, cells in lockstep
+void gm_dot(spm_handle* h, const double* a, const double* b, double* out /*[C]*/);
+void gm_cgs_pass(spm_handle* h, const double* w, double* coef);
+void gm_update_j(spm_handle* h, const double* coef, double* w);
+void gm_store_next(spm_handle* h);
+void gm_givens(spm_handle* h);
+void gm_copy_in(spm_handle* h);
+void gm_start(spm_handle* h);
+void gm_backsolve_update(spm_handle* h, double* x);
 void gm_axpby(spm_handle* h, int64_t n, double a, const double* x, double b, const double* y, double* out);
-void gm_scale_by_norm(spm_handle* h, const double* nrm2, double* v, int64_t n, double* norm_out);
-void gm_givens(spm_handle* h, int j, const double* h1, const double* h2, const double* nrm2, double bnorm,
-               double* res_out);
-void gm_backsolve(spm_handle* h, int k);
-void gm_init(spm_handle* h, const double* nrm2);
 void gm_copy(spm_handle* h, double* dst, const double* src, int64_t n);
 void gm_zero(spm_handle* h, double* dst, int64_t n);
+void gm_stamp_start(spm_handle* h);
+void gm_stamp_mask(spm_handle* h, const int32_t* mask_dev);
+void launch_disc_impl(spm_handle* h, bool with_active);
+void launch_xi_impl(spm_handle* h, bool with_active);
+void launch_near_impl(spm_handle* h, int precision, bool with_active);
+void launch_close_apply_impl(spm_handle* h, double* T, int precision, bool with_active);
 
 }  // namespace spm
 

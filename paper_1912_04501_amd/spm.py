@@ -29,7 +29,8 @@ class spm_config(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("gamma", ctypes.c_double), ("M", ctypes.c_int32),
                 ("R_proxy", ctypes.c_double), ("m_wall", ctypes.c_int32), ("close_factor", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("inner_tol", ctypes.c_double), ("min_gap", ctypes.c_double), ("rcond", ctypes.c_double)]
+                ("inner_tol", ctypes.c_double), ("min_gap", ctypes.c_double), ("rcond", ctypes.c_double),
+                ("use_graph", ctypes.c_int32), ("poll_every", ctypes.c_int32)]
 
 
 class spm_solve_info(ctypes.Structure):
@@ -91,6 +92,9 @@ def lib():
         "spm_close_pairs": (ctypes.c_int, [P, i64, i32, i32, i32, ctypes.c_int64]),
         "spm_proxy_pinv": (ctypes.c_int, [P, d]),
         "spm_proxy_svd": (ctypes.c_int, [P, d, d, i32]),
+        "spm_set_cells": (ctypes.c_int, [P, ctypes.c_int32, d, i32, d, d, d, d, i32]),
+        "spm_num_cells": (ctypes.c_int, [P, i32]),
+        "spm_solve_batch": (ctypes.c_int, [P, P, P, P, P, P, ctypes.POINTER(spm_solve_info), d]),
         "spm_autotune": (ctypes.c_int, [P, ctypes.c_char_p, d]),
         "spm_get_launch": (ctypes.c_int, [P, ctypes.c_int32, i32]),
         "spm_set_launch": (ctypes.c_int, [P, ctypes.c_int32, i32]),
@@ -193,11 +197,46 @@ class Solver:
         self._check(lib().spm_num_nodes(self.h, ctypes.byref(n)))
         self.N = int(n.value)
         self.No = len(th)
+        self.C = 1
 
     def set_workload(self, wl):
         self.set_lattice(wl["skew"])
         self.set_ellipses(wl["centers"], wl["theta"], wl["a"], wl["b"], wl["n_nodes"])
         return self
+
+    def set_cells(self, cells):
+        """An ensemble: a list of workload dicts, one per independent cell."""
+        skews = np.array([float(c["skew"]) for c in cells])
+        counts = [len(c["theta"]) for c in cells]
+        off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
+        cen = np.ascontiguousarray(np.concatenate([np.asarray(c["centers"], float) for c in cells]).reshape(-1))
+        th = np.ascontiguousarray(np.concatenate([np.asarray(c["theta"], float) for c in cells]))
+        aa = np.ascontiguousarray(np.concatenate([np.asarray(c["a"], float) for c in cells]))
+        bb = np.ascontiguousarray(np.concatenate([np.asarray(c["b"], float) for c in cells]))
+        nn = np.ascontiguousarray(np.concatenate([np.asarray(c["n_nodes"]) for c in cells]).astype(np.int32))
+        ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+        self._check(lib().spm_set_cells(self.h, len(cells), _dp(skews), ip(off), _dp(cen), _dp(th), _dp(aa), _dp(bb),
+                                        ip(nn)))
+        n = ctypes.c_int64()
+        self._check(lib().spm_num_nodes(self.h, ctypes.byref(n)))
+        self.N = int(n.value)
+        self.No = int(off[-1])
+        self.C = len(cells)
+        self.part_off = off
+        return self
+
+    def solve_batch(self, sigma0=None, allow_noconv=False):
+        C = getattr(self, "C", 1)
+        sig = self._vec(2 * self.N)
+        vel = self._vec(2 * self.No)
+        om = self._vec(self.No)
+        mu = self._vec(C)
+        infos = (spm_solve_info * C)()
+        lat = np.zeros(C)
+        rc = lib().spm_solve_batch(self.h, _ptr(sigma0), _ptr(sig), _ptr(vel), _ptr(om), _ptr(mu), infos, _dp(lat))
+        self._check(rc, allow=(SPM_ENOCONV,) if allow_noconv else ())
+        return {"sigma": sig, "vel": vel.view(-1, 2), "omega": om, "mu_eff": mu,
+                "infos": [i.as_dict() for i in infos], "latency_s": lat}
 
     def _vec(self, n):
         return torch.empty(int(n), dtype=torch.float64, device=self.device)
@@ -227,7 +266,7 @@ class Solver:
         sig = self._vec(2 * self.N)
         vel = self._vec(2 * self.No)
         om = self._vec(self.No)
-        mu = self._vec(1)
+        mu = self._vec(getattr(self, "C", 1))
         info = spm_solve_info()
         rc = lib().spm_solve(self.h, _ptr(sigma0), _ptr(sig), _ptr(vel), _ptr(om), _ptr(mu), ctypes.byref(info))
         self._check(rc, allow=(SPM_ENOCONV,) if allow_noconv else ())
@@ -266,7 +305,7 @@ class Solver:
         return out
 
     def proxy_strengths(self, sigma):
-        out = self._vec(2 * self.cfg.M)
+        out = self._vec(2 * self.cfg.M * getattr(self, "C", 1))
         self._check(lib().spm_proxy_strengths(self.h, _ptr(sigma), _ptr(out)))
         return out
 
@@ -291,10 +330,10 @@ class Solver:
     def get_launch(self, precision):
         c = np.zeros(4, dtype=np.int32)
         self._check(lib().spm_get_launch(self.h, int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
-        return {"block": int(c[0]), "tpt": int(c[1]), "tile": int(c[2]), "splits": int(c[3])}
+        return {"block": int(c[0]), "tpt": int(c[1]), "tile": int(c[2]), "chunk": int(c[3])}
 
-    def set_launch(self, precision, block, tpt, tile, splits):
-        c = np.array([block, tpt, tile, splits], dtype=np.int32)
+    def set_launch(self, precision, block, tpt, tile, chunk):
+        c = np.array([block, tpt, tile, chunk], dtype=np.int32)
         self._check(lib().spm_set_launch(self.h, int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
 
     def profile(self, enable=True):
@@ -309,15 +348,15 @@ class Solver:
         return {"ms": ms.value, "launches": int(n.value), "pairs": pairs.value}
 
     def proxy_svd(self):
-        M, m = self.cfg.M, self.cfg.m_wall
-        Q = np.zeros(2 * M * 8 * m)
-        sv = np.zeros(2 * M)
-        sw = ctypes.c_int32()
-        self._check(lib().spm_proxy_svd(self.h, _dp(Q), _dp(sv), ctypes.byref(sw)))
-        return Q.reshape(8 * m, 2 * M), sv, int(sw.value)
+        M, m, C = self.cfg.M, self.cfg.m_wall, getattr(self, "C", 1)
+        Q = np.zeros(C * 2 * M * 8 * m)
+        sv = np.zeros(C * 2 * M)
+        sw = np.zeros(C, dtype=np.int32)
+        self._check(lib().spm_proxy_svd(self.h, _dp(Q), _dp(sv), sw.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return Q.reshape(C, 8 * m, 2 * M), sv.reshape(C, 2 * M), sw
 
     def proxy_pinv(self):
-        M, m = self.cfg.M, self.cfg.m_wall
-        out = np.zeros(2 * M * 8 * m)
+        M, m, C = self.cfg.M, self.cfg.m_wall, getattr(self, "C", 1)
+        out = np.zeros(C * 2 * M * 8 * m)
         self._check(lib().spm_proxy_pinv(self.h, _dp(out)))
-        return out.reshape(2 * M, 8 * m)
+        return out.reshape(C, 2 * M, 8 * m)

@@ -1,0 +1,111 @@
+"""Ensembles of independent cells solved together (one persistent near-sum launch per
+matvec covering every cell, lockstep GMRES with per-cell convergence, captured
+iteration graph): each cell against the oracle solving it alone."""
+import numpy as np
+import pytest
+
+from oracle import operator as op
+from oracle import readout as ro
+from paper_1912_04501_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _spm():
+    from paper_1912_04501_amd import spm
+    return spm
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _cells():
+    # uneven sizes and skews; one cell is a single ellipse
+    h = W.c1_h_star()
+    cells = [W.random_ellipses(n, 0.3, seed=1000 + k, h_star=h, name=f"cell{k}")
+             for k, n in enumerate((4, 9, 6, 13))]
+    cells.append(W.single_ellipse(n_nodes=96, skew=0.37))
+    return cells
+
+
+@pytest.fixture(scope="module")
+def ensemble():
+    cells = _cells()
+    refs = []
+    for c in cells:
+        prob = op.make_problem(c)
+        x, _ = op.solve(prob, tol=1e-12)
+        v, om = ro.velocities(prob, x)
+        refs.append((prob, x, v, om, ro.mu_eff(prob, x)))
+    print(f"[ensemble] cells {len(cells)} nodes {[r[0].N for r in refs]}", flush=True)
+    return cells, refs
+
+
+@pytest.mark.parametrize("precision,graph", [("fp64", 1), ("fp64", 0), ("fp32_ir", 1)])
+def test_ensemble_matches_oracle_per_cell(ensemble, precision, graph):
+    cells, refs = ensemble
+    spm = _spm()
+    p = spm.SPM_FP64 if precision == "fp64" else spm.SPM_FP32_IR
+    s = spm.Solver("cuda:0", precision=p, use_graph=graph).set_cells(cells)
+    r = s.solve_batch()
+    off = s.part_off
+    bound = 1e-9 if precision == "fp64" else 1e-8
+    vel, om, mu = _n(r["vel"]), _n(r["omega"]), _n(r["mu_eff"])
+    for k, (prob, x, v, o, m) in enumerate(refs):
+        info = r["infos"][k]
+        assert info["status"] == 0 and info["rel_residual"] <= 1e-10, (k, info)
+        sl = slice(off[k], off[k + 1])
+        sc_v = max(np.abs(v).max(), np.hypot(*prob.geom.e2))
+        e_om = np.abs(om[sl] - o).max()
+        e_v = np.abs(vel[sl] - v).max()
+        print(f"[{precision} graph={graph}] cell {k}: its {info['iterations']} omega err {e_om:.1e} v err {e_v:.1e} "
+              f"mu err {abs(mu[k] - m):.1e} latency {r['latency_s'][k] * 1e3:.2f} ms")
+        assert e_om <= bound * max(1.0, np.abs(o).max())
+        assert e_v <= bound * sc_v
+        assert abs(mu[k] - m) <= bound * m
+        assert 0.0 < r["latency_s"][k] < 60.0
+
+
+def test_graph_replay_is_bitwise_identical(ensemble):
+    cells, _ = ensemble
+    spm = _spm()
+    a = spm.Solver("cuda:0", use_graph=1).set_cells(cells).solve_batch()
+    b = spm.Solver("cuda:0", use_graph=0).set_cells(cells).solve_batch()
+    assert np.array_equal(_n(a["sigma"]), _n(b["sigma"]))
+    assert [i["iterations"] for i in a["infos"]] == [i["iterations"] for i in b["infos"]]
+
+
+def test_ensemble_operator_is_block_diagonal(ensemble):
+    """apply() on the ensemble equals the oracle operator of every cell on its block."""
+    cells, refs = ensemble
+    spm = _spm()
+    s = spm.Solver("cuda:0").set_cells(cells)
+    N = s.N
+    sig = W.random_density(N, seed=3)
+    y = _n(s.apply(torch.as_tensor(sig, device="cuda:0")))
+    n0 = 0
+    for prob, *_ in refs:
+        n = prob.N
+        sub = np.concatenate([sig[n0:n0 + n], sig[N + n0:N + n0 + n]])
+        ref = op.apply(prob, sub)
+        got = np.concatenate([y[n0:n0 + n], y[N + n0:N + n0 + n]])
+        assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+        n0 += n
+
+
+def test_ensemble_every_launch_shape(ensemble):
+    cells, refs = ensemble
+    spm = _spm()
+    s = spm.Solver("cuda:0").set_cells(cells)
+    N = s.N
+    sig = W.random_density(N, seed=4)
+    st = torch.as_tensor(sig, device="cuda:0")
+    base = _n(s.near_traction(st))
+    for block in (64, 256):
+        for tpt in (1, 4):
+            for chunk in (50, 1000):
+                s.set_launch(spm.SPM_FP64, block, tpt, 256, chunk)
+                T = _n(s.near_traction(st))
+                assert np.abs(T - base).max() <= 1e-12 * np.abs(base).max()
