@@ -135,13 +135,13 @@ __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets
       if (PREC == SPM_FP64) {
         const double dx = xi - g.x[kk], dy = yi - g.y[kk];
         double a1 = 0.0, a2 = 0.0;
-        gt_pair(dx - shx, dy - shy, nxi, nyi, f1[kk], f2[kk], a1, a2);
+        gt_pair(dx - shx, row_terms(dy, shy, nyi, f2[kk]), nxi, f1[kk], a1, a2);
         p1 += a1;
         p2 += a2;
       } else {
         const float dx = g.xf[i] - g.xf[kk], dy = g.yf[i] - g.yf[kk];
         float a1 = 0.f, a2 = 0.f;
-        gt_pair(dx - shxf, dy - shyf, g.nxf[i], g.nyf[i], f1f[kk], f2f[kk], a1, a2);
+        gt_pair(dx - shxf, row_terms(dy, shyf, g.nyf[i], f2f[kk]), g.nxf[i], f1f[kk], a1, a2);
         p1 += (double)a1;
         p2 += (double)a2;
       }

@@ -92,8 +92,11 @@ __global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__
 #pragma unroll
         for (int t = 0; t < TPT; ++t) {
           const R dx = xi[t] - s.y1, dy = yi[t] - s.y2;
+          RowTerms<R> row[3];
 #pragma unroll
-          for (int m = 0; m < kShifts; ++m) gt_pair(dx - sx[m], dy - sy[m], nxi[t], nyi[t], s.f1, s.f2, a1[t], a2[t]);
+          for (int n = 0; n < 3; ++n) row[n] = row_terms(dy, sy[n], nyi[t], s.f2);
+#pragma unroll
+          for (int m = 0; m < kShifts; ++m) gt_pair(dx - sx[m], row[m % 3], nxi[t], s.f1, a1[t], a2[t]);
         }
       }
 #pragma unroll

@@ -29,8 +29,13 @@ __host__ __device__ __forceinline__ double shift_x(int s, double skew) {
 __host__ __device__ __forceinline__ double shift_y(int s) { return (double)(s % 3 - 1); }
 
 // ----------------------------------------------------------------------------
-// One pair of the single-layer traction sum (Sec. 4.1 eq. Gt without the -1/pi,
-// which is applied once per target):  a += r (r.n)(r.f) / |r|^4.
+// Pairs of the single-layer traction sum (Sec. 4.1 eq. Gt without the -1/pi, which
+// is applied once per target):  a += r (r.n)(r.f) / |r|^4,  r = (dx - sx, dy - sy).
+//
+// The three images of a lattice row share sy, so per source the row terms
+//   ry = dy - sy,  ry2 = ry^2 + floor,  ryn = ry n_y,  ryf = ry f_y
+// are formed once per row and every pair then costs 9 VALU operations + 1 reciprocal
+// (FP64: + 3 for the reciprocal correction).
 //
 // The self pair (r == 0) is handled without a branch: |r|^2 gets a tiny floor
 // (1e-300 in FP64, 1e-30 in FP32) far below any physical pair distance, so the
@@ -44,14 +49,34 @@ __host__ __device__ __forceinline__ double shift_y(int s) { return (double)(s % 
 // FP32 plain terms the close correction removes are bit-identical to the ones
 // the near sum added. Compile with -ffp-contract=off: only the fma() calls fuse.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ void gt_pair(double rx, double ry, double nx, double ny, double f1,
-                                        double f2, double& a1, double& a2) {
-  double r2 = fma(rx, rx, 1e-300);
-  r2 = fma(ry, ry, r2);
-  double rn = rx * nx;
-  rn = fma(ry, ny, rn);
-  double rf = rx * f1;
-  rf = fma(ry, f2, rf);
+template <typename R>
+struct RowTerms {
+  R ry, ry2, ryn, ryf;
+};
+
+__device__ __forceinline__ RowTerms<double> row_terms(double dy, double sy, double ny, double f2) {
+  RowTerms<double> t;
+  t.ry = dy - sy;
+  t.ry2 = fma(t.ry, t.ry, 1e-300);
+  t.ryn = t.ry * ny;
+  t.ryf = t.ry * f2;
+  return t;
+}
+
+__device__ __forceinline__ RowTerms<float> row_terms(float dy, float sy, float ny, float f2) {
+  RowTerms<float> t;
+  t.ry = dy - sy;
+  t.ry2 = fmaf(t.ry, t.ry, 1e-30f);
+  t.ryn = t.ry * ny;
+  t.ryf = t.ry * f2;
+  return t;
+}
+
+__device__ __forceinline__ void gt_pair(double rx, const RowTerms<double>& t, double nx, double f1, double& a1,
+                                        double& a2) {
+  const double r2 = fma(rx, rx, t.ry2);
+  const double rn = fma(rx, nx, t.ryn);
+  const double rf = fma(rx, f1, t.ryf);
   const double i0 = __builtin_amdgcn_rcp(r2);
   const double e = fma(-r2, i0, 1.0);
   const double ee = fma(e, e, e);
@@ -60,23 +85,19 @@ __device__ __forceinline__ void gt_pair(double rx, double ry, double nx, double 
   double c = p * inv;
   c = c * inv;
   a1 = fma(c, rx, a1);
-  a2 = fma(c, ry, a2);
+  a2 = fma(c, t.ry, a2);
 }
 
-__device__ __forceinline__ void gt_pair(float rx, float ry, float nx, float ny, float f1, float f2,
-                                        float& a1, float& a2) {
-  float r2 = fmaf(rx, rx, 1e-30f);
-  r2 = fmaf(ry, ry, r2);
-  float rn = rx * nx;
-  rn = fmaf(ry, ny, rn);
-  float rf = rx * f1;
-  rf = fmaf(ry, f2, rf);
+__device__ __forceinline__ void gt_pair(float rx, const RowTerms<float>& t, float nx, float f1, float& a1, float& a2) {
+  const float r2 = fmaf(rx, rx, t.ry2);
+  const float rn = fmaf(rx, nx, t.ryn);
+  const float rf = fmaf(rx, f1, t.ryf);
   const float inv = __builtin_amdgcn_rcpf(r2);
   const float p = rn * rf;
   float c = p * inv;
   c = c * inv;
   a1 = fmaf(c, rx, a1);
-  a2 = fmaf(c, ry, a2);
+  a2 = fmaf(c, t.ry, a2);
 }
 
 // Accurate FP64 reciprocal (correctly rounded division is not needed here).
