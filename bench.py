@@ -33,6 +33,32 @@ if ROOT not in sys.path:
 
 FLOP_PER_PAIR = 19
 PEAK = {"fp32": 157.3, "fp64": 78.6}   # MI355X vector ALU peaks, TFLOP/s
+COPY_BYTES = 256 << 20
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "near_sum_fp32_ellipses200_N51200_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1912_04501_amd", "csrc", f) for f in ("k_near.hip", "spm_internal.h")]
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP32 near sum from the committed counter summary, or
+    None when that summary is missing or was taken on different kernel sources."""
+    import re
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", txt)
+    t = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
 
 
 def log(*a):
@@ -73,6 +99,9 @@ def main():
     ap.add_argument("--precision", choices=["fp32_ir", "fp64"], default="fp32_ir")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed FP64-vs-FP32+IR comparison solves")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 256 MiB device copy three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
@@ -87,6 +116,13 @@ def main():
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {COPY_BYTES} bytes read and written")
     t0 = time.perf_counter()
     wl = W.ellipses_200()
     log(f"[bench] workload {wl['name']} generated in {time.perf_counter() - t0:.1f}s")
@@ -97,7 +133,7 @@ def main():
     pairs_per_matvec = 9.0 * N * N
     log(f"[bench] N={N} particles={s.No} close pairs={len(s.close_pairs())}")
     t0 = time.perf_counter()
-    tune = s.autotune(None)
+    tune = s.autotune(args.tune_cache)
     log(f"[bench] autotune {time.perf_counter() - t0:.1f}s: {tune}")
 
     for k in range(args.warmup):
@@ -124,7 +160,7 @@ def main():
     achieved = FLOP_PER_PAIR * pairs_per_matvec / (avg_ms * 1e-3) / 1e12
     dt = "fp32" if kern == 1 else "fp64"
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK[dt], "unit": "TFLOP/s",
-                "frac": achieved / PEAK[dt], "traffic": None,
+                "frac": achieved / PEAK[dt], "traffic": measured_traffic() if kern == 1 else None,
                 "kernel": f"k_near<{'float' if kern else 'double'}> (near-image traction sum, {dt})",
                 "avg_launch_ms": avg_ms, "launches": prof["launches"],
                 "pairs_per_launch": pairs_per_matvec, "launch_shape": tune["fp32" if kern else "fp64"]}
