@@ -30,10 +30,15 @@ Map of the method (citations are to the paper's sections and equations):
 * ``readout``    - particle velocities, angular velocities, effective viscosity
                    (Sec. 3 eq. RigidBodyMotion and eq. mueff)
 * ``step``       - forward Euler time stepping (Sec. 7)
+* ``precond``    - isolated-body self blocks of the completed operator and the
+                   block-diagonal right preconditioner built from them
+* ``learned``    - neighbour features, body-frame Fourier targets, the MLP
+                   (forward, back-propagation, Adam) and the learned warm start
 
 Parity unpinned (consistent by construction only): the absolute velocity gauge
-away from symmetric configurations, and the exact truncation of the proxy
-least-squares pseudo-inverse.
+away from symmetric configurations, the exact truncation of the proxy
+least-squares pseudo-inverse, and the trained network's predictions (their only
+ground truth is the solver's own density).
 """
 from .geometry import Geometry, build_geometry, reduce_skew  # noqa: F401
 from .operator import Problem, make_problem  # noqa: F401

@@ -9,10 +9,17 @@ same FP64 residual, so the network changes cost, never the answer).
   offset of its centre in the particle's body frame in units of the particle's
   semi-major axis, R(-theta_i)(c_j + s - c_i)/a_i, and (cos 2(theta_j - theta_i),
   sin 2(theta_j - theta_i)) (ellipses are symmetric under a half turn); then a_i/b_i.
-* targets (128 per particle): the body-frame density s_k = R(-theta_i) sigma_k / (mu gamma)
-  at the nodes t_k = 2 pi k / N_i as a complex sequence s1 + i s2, its discrete Fourier
-  coefficients c_m = (1/N_i) sum_k s_k exp(-i m t_k) for m = -32..31; real parts then
-  imaginary parts.
+* offset: the completed operator maps the normal field n to n/2 (the single layer
+  with density n is a pure pressure, so K n = n/2 on every curve, the pin removes
+  the value at the first node and L n = 0). A solution is therefore determined by the
+  geometry only up to a cell-wide multiple beta n that no local feature can predict:
+  the target density is sigma - beta* n with beta* = <sigma, n> / <n, n> over the
+  cell's nodes, and the warm start fits beta from its own residual r0 = b - A x0 as
+  beta = 2 <r0, n> / <n, n> (the exact minimiser of |r0 - beta A n|).
+* targets (128 per particle): the body-frame density s_k = R(-theta_i) sigma'_k / (mu gamma)
+  of sigma' = sigma - beta* n at the nodes t_k = 2 pi k / N_i as a complex sequence
+  s1 + i s2, its discrete Fourier coefficients c_m = (1/N_i) sum_k s_k exp(-i m t_k)
+  for m = -32..31; real parts then imaginary parts.
 * decode: sigma_k = mu gamma R(theta_i) sum_m c_m exp(i m t_k) (exact for densities
   whose modes lie in -32..31 when N_i >= 64).
 * MLP: 33 -> 256 -> 256 -> 256 -> 128, ReLU on the hidden layers, loss
@@ -41,7 +48,7 @@ def features(geom):
                 if j == i and si == zero:
                     continue
                 d = c[j] + s - c[i]
-                cand.append((float(np.hypot(*d)), j, si, d))
+                cand.append((float(d[0] * d[0] + d[1] * d[1]), j, si, d))
         cand.sort(key=lambda t: (t[0], t[1], t[2]))
         ct, st = np.cos(geom.theta[i]), np.sin(geom.theta[i])
         for k in range(N_NEIGH):
@@ -58,7 +65,18 @@ def _mode_index():
     return np.arange(-N_MODES // 2, N_MODES // 2)
 
 
+def remove_offset(geom, sigma2):
+    """sigma - beta* n with beta* = <sigma, n> / <n, n> over all nodes of the cell."""
+    beta = (sigma2 * geom.n).sum() / (geom.n * geom.n).sum()
+    return sigma2 - beta * geom.n
+
+
 def targets(geom, sigma2, mu=1.0, gamma=1.0):
+    return modes(geom, remove_offset(geom, sigma2), mu, gamma)
+
+
+def modes(geom, sigma2, mu=1.0, gamma=1.0):
+    """Body-frame Fourier coefficients c_m, m = -32..31, of every particle's density."""
     out = np.zeros((geom.No, N_OUT))
     m = _mode_index()
     for i in range(geom.No):
@@ -140,3 +158,20 @@ def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
             vh = state["v"][li][k] / (1 - b2 ** t)
             layer[k] = layer[k] - lr * mh / (np.sqrt(vh) + eps)
     return params
+
+
+def warm_start_from_modes(prob, modes_):
+    """x0 = decode(modes) + beta n with beta fitted to the residual of decode(modes)."""
+    from .operator import apply, rhs, to1
+    g = prob.geom
+    x0 = to1(decode(g, modes_, prob.cfg.mu, prob.cfg.gamma))
+    r0 = rhs(prob) - apply(prob, x0)
+    nv = to1(g.n)
+    beta = 2.0 * (r0 @ nv) / (nv @ nv)
+    return x0 + beta * nv
+
+
+def learned_guess(prob, params):
+    """The network's warm start: features -> MLP -> decode -> offset fit."""
+    y, _ = forward(params, features(prob.geom))
+    return warm_start_from_modes(prob, y)
