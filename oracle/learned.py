@@ -116,18 +116,33 @@ def init_params(seed=0, layers=LAYERS):
     return params
 
 
-def forward(params, x):
+def round_bf16(a):
+    """Round to bfloat16 through FP32, nearest even (the matrix-core operand format)."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _op(a, rounding):
+    return a if rounding is None else round_bf16(a)
+
+
+def forward(params, x, rounding=None):
+    """rounding="bf16" rounds both operands of every layer product to bfloat16 (the
+    products and sums stay FP64): the arithmetic of a bf16 x bf16 -> fp32 matrix unit
+    up to the order and precision of accumulation."""
     acts = [x]
     h = x
     for li, (W, b) in enumerate(params):
-        z = h @ W.T + b
+        z = _op(h, rounding) @ _op(W, rounding).T + b
         h = np.maximum(z, 0.0) if li < len(params) - 1 else z
         acts.append(h)
     return h, acts
 
 
-def loss_and_grads(params, x, t):
-    y, acts = forward(params, x)
+def loss_and_grads(params, x, t, rounding=None):
+    y, acts = forward(params, x, rounding)
     B = x.shape[0]
     d = (y - t) / B
     loss = 0.5 * ((y - t) ** 2).sum() / B
@@ -135,9 +150,9 @@ def loss_and_grads(params, x, t):
     for li in range(len(params) - 1, -1, -1):
         W, b = params[li]
         h_in = acts[li]
-        grads[li] = [d.T @ h_in, d.sum(0)]
+        grads[li] = [_op(d, rounding).T @ _op(h_in, rounding), d.sum(0)]
         if li > 0:
-            d = (d @ W) * (acts[li] > 0)
+            d = (_op(d, rounding) @ _op(W, rounding)) * (acts[li] > 0)
     return loss, grads
 
 

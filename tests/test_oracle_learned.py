@@ -224,3 +224,25 @@ def test_adam_first_step_closed_form():
     want = np.array([1.0, -2.0, 0.5]) - lr * g / (np.abs(g) + 1e-8)
     got = np.array([params[0][0][0, 0], params[0][0][0, 1], params[0][1][0]])
     assert np.abs(got - want).max() < 1e-15
+
+
+def test_round_bf16():
+    """Nearest-even rounding to 8 significand bits: representable values are kept,
+    halfway cases go to the even neighbour, others to the nearest."""
+    u = 2.0 ** -7   # spacing of bfloat16 in [1, 2)
+    vals = np.array([1.0, -3.5, 1 + u, 1 + u / 2, 1 + 3 * u / 2, 1 + 0.7 * u, 2.0 ** -130, 0.0])
+    want = np.array([1.0, -3.5, 1 + u, 1.0, 1 + 2 * u, 1 + u, 2.0 ** -130, 0.0])
+    assert np.array_equal(OL_round(vals), want)
+
+
+def OL_round(v):
+    return learned.round_bf16(v)
+
+
+def test_bf16_rounded_network_is_close_to_exact():
+    """With bf16 operands the forward pass stays within a few bf16 units of the exact one."""
+    params = learned.init_params(1)
+    x = np.random.default_rng(2).standard_normal((50, learned.N_FEAT))
+    y, _ = learned.forward(params, x)
+    yb, _ = learned.forward(params, x, rounding="bf16")
+    assert 1e-4 < np.abs(yb - y).max() / np.abs(y).max() < 3e-2
