@@ -14,8 +14,11 @@ same FP64 residual, so the network changes cost, never the answer).
   the value at the first node and L n = 0). A solution is therefore determined by the
   geometry only up to a cell-wide multiple beta n that no local feature can predict:
   the target density is sigma - beta* n with beta* = <sigma, n> / <n, n> over the
-  cell's nodes, and the warm start fits beta from its own residual r0 = b - A x0 as
-  beta = 2 <r0, n> / <n, n> (the exact minimiser of |r0 - beta A n|).
+  cell's nodes.
+* warm start: the decoded density g is scaled and given its offset by the least
+  squares fit min over (alpha, beta) of |b - alpha A g - beta n / 2|, i.e. the
+  guess alpha g + beta n with the smallest residual in that plane (never worse than
+  the zero guess, which the plane contains).
 * targets (128 per particle): the body-frame density s_k = R(-theta_i) sigma'_k / (mu gamma)
   of sigma' = sigma - beta* n at the nodes t_k = 2 pi k / N_i as a complex sequence
   s1 + i s2, its discrete Fourier coefficients c_m = (1/N_i) sum_k s_k exp(-i m t_k)
@@ -176,14 +179,17 @@ def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
 
 
 def warm_start_from_modes(prob, modes_):
-    """x0 = decode(modes) + beta n with beta fitted to the residual of decode(modes)."""
+    """x0 = alpha g + beta n, g = decode(modes), (alpha, beta) minimising
+    |b - alpha A g - beta n / 2| (A n = n / 2)."""
     from .operator import apply, rhs, to1
-    g = prob.geom
-    x0 = to1(decode(g, modes_, prob.cfg.mu, prob.cfg.gamma))
-    r0 = rhs(prob) - apply(prob, x0)
-    nv = to1(g.n)
-    beta = 2.0 * (r0 @ nv) / (nv @ nv)
-    return x0 + beta * nv
+    geo = prob.geom
+    g = to1(decode(geo, modes_, prob.cfg.mu, prob.cfg.gamma))
+    b = rhs(prob)
+    z = apply(prob, g)
+    h = 0.5 * to1(geo.n)
+    M = np.array([[z @ z, z @ h], [z @ h, h @ h]])
+    alpha, beta = np.linalg.solve(M, np.array([b @ z, b @ h]))
+    return alpha * g + beta * to1(geo.n)
 
 
 def learned_guess(prob, params):

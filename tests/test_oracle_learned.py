@@ -246,3 +246,19 @@ def test_bf16_rounded_network_is_close_to_exact():
     y, _ = learned.forward(params, x)
     yb, _ = learned.forward(params, x, rounding="bf16")
     assert 1e-4 < np.abs(yb - y).max() / np.abs(y).max() < 3e-2
+
+
+def test_warm_start_fit_is_never_worse_than_zero():
+    """The (alpha, beta) fit contains the zero guess, so any decoded density, even
+    noise, leaves a residual no larger than |b|; and it is the plane's minimiser:
+    perturbing alpha or beta raises the residual."""
+    prob = op.make_problem(W.random_ellipses(3, 0.2, seed=7, nodes=64))
+    g = prob.geom
+    b = op.rhs(prob)
+    noise = 50.0 * np.random.default_rng(0).standard_normal((g.No, learned.N_OUT))
+    x0 = learned.warm_start_from_modes(prob, noise)
+    r0 = np.linalg.norm(b - op.apply(prob, x0))
+    assert r0 <= np.linalg.norm(b) * (1 + 1e-12)
+    nv = op.to1(g.n)
+    for dx in (1e-3 * x0, 1e-3 * np.linalg.norm(x0) / np.linalg.norm(nv) * nv):
+        assert np.linalg.norm(b - op.apply(prob, x0 + dx)) > r0
