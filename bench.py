@@ -102,6 +102,9 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy three times (HBM counter calibration)")
+    ap.add_argument("--workload", choices=["ellipses200", "ensemble64", "learned"], default="ellipses200",
+                    help="ellipses200: the 200-ellipse cell (default); ensemble64: 64 independent cells in one "
+                         "launch; learned: time stepping with the trained warm-start network")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
@@ -123,6 +126,10 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 x {COPY_BYTES} bytes read and written")
+    if args.workload == "ensemble64":
+        return bench_ensemble(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     t0 = time.perf_counter()
     wl = W.ellipses_200()
     log(f"[bench] workload {wl['name']} generated in {time.perf_counter() - t0:.1f}s")
@@ -198,6 +205,155 @@ def main():
                       "precision": args.precision, "tol": 1e-10, "images": "3x3", "proxies": 32,
                       "wall_points": 24, "close_factor": 10},
            "roofline": roofline, "cpu_baseline": cpu, **extra}
+    print(json.dumps(out), flush=True)
+
+
+def percentile(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q))
+
+
+def bench_ensemble(args):
+    """64 independent cells (seeds 1000..1063, 4-50 ellipses each) solved together in
+    one persistent near-sum launch per matvec, FP32+IR, autotuned launch shape. One
+    step = one batched solve of every cell to 1e-10; value = cell solves per second;
+    per-cell latency (device wall clock from the solve start to the cell's convergence)
+    as p50 / p99 over the timed steps."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04501_amd import spm
+    from paper_1912_04501_amd import workloads as W
+    t0 = time.perf_counter()
+    cells = W.ensemble_cells(64)
+    Ns = np.array([int(np.sum(c["n_nodes"])) for c in cells])
+    log(f"[bench] 64 cells generated in {time.perf_counter() - t0:.1f}s: N_c {Ns.min()}..{Ns.max()}, "
+        f"total {Ns.sum()}, particles {sum(len(c['theta']) for c in cells)}")
+    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_IR)
+    s.set_cells(cells)
+    tune = s.autotune(args.tune_cache)
+    log(f"[bench] autotune: {tune}")
+    for k in range(args.warmup):
+        r = s.solve_batch()
+        log(f"[bench] warmup {k}: its {[i['iterations'] for i in r['infos']][:8]} ...")
+    torch.cuda.synchronize()
+    s.profile(True)
+    lat, infos = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = s.solve_batch()
+        lat.extend(r["latency_s"].tolist())
+        infos.extend(r["infos"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s.profile(False)
+    assert max(i["rel_residual"] for i in infos) <= 1e-10
+    pairs = float(9.0 * (Ns.astype(np.float64) ** 2).sum())
+    # roofline of the near-sum launch over all 64 cells (inside a solve, launches skip the
+    # cells that have converged): FP32 operator applications, HIP events on the stream
+    x = torch.randn(2 * s.N, dtype=torch.float64, device="cuda:0")
+    s.apply(x, precision=spm.SPM_FP32)
+    torch.cuda.synchronize()
+    s.profile(True)
+    for _ in range(10):
+        s.apply(x, precision=spm.SPM_FP32)
+    torch.cuda.synchronize()
+    prof = s.profile_read(1)
+    s.profile(False)
+    avg_ms = prof["ms"] / max(prof["launches"], 1)
+    pairs_per_launch = prof["pairs"] / max(prof["launches"], 1)
+    achieved = FLOP_PER_PAIR * pairs_per_launch / (avg_ms * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cells[int(np.argmax(Ns))])
+    out = {"metric": "ensemble cell solves/s (64 independent cells, FP32+IR to 1e-10 FP64 residual)",
+           "value": 64 * args.steps / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "ensemble_64_cells_phi0.3", "cells": 64, "nodes_total": int(Ns.sum()),
+                      "nodes_min": int(Ns.min()), "nodes_max": int(Ns.max()), "pairs_per_matvec": pairs,
+                      "precision": "fp32_ir", "tol": 1e-10},
+           "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99),
+                          "max": 1e3 * max(lat)},
+           "iterations": {"p50": percentile([i["iterations"] for i in infos], 50),
+                          "max": max(i["iterations"] for i in infos)},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                        "frac": achieved / PEAK["fp32"], "traffic": None,
+                        "kernel": "k_near<float> (near-image traction sum over all active cells, fp32)",
+                        "avg_launch_ms": avg_ms, "launches": prof["launches"], "pairs_per_launch": pairs_per_launch,
+                        "launch_shape": tune["fp32"]},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def bench_learned(args):
+    """Time stepping with the learned warm start. Training data: forward-Euler
+    trajectories run by the solver itself (seeds 5000..5009, 25-100 ellipses at area
+    fraction 0.3, dt 0.01, up to `--train-steps` steps each); the network is trained
+    on the device (BF16 matrix-core kernels, Adam). Evaluation: held-out trajectories
+    (seeds 6000..6002), `--eval-steps` steps each, every variant to the FP64 residual
+    1e-10: (i) FP64 from zero, (ii) FP64 from the previous step, (iii) FP32+IR from zero,
+    (iv) network warm start + block preconditioner in FP64 and in FP32+IR. value = steps
+    per second of the fastest learned variant; the others are reported beside it."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04501_amd import learned as L
+    from paper_1912_04501_amd import spm
+    from paper_1912_04501_amd import workloads as W
+    train_steps = int(os.environ.get("SPM_BENCH_TRAIN_STEPS", "200"))
+    eval_steps = int(os.environ.get("SPM_BENCH_EVAL_STEPS", "50"))
+    t0 = time.perf_counter()
+    X, T, solves = L.generate(range(5000, 5010), train_steps, log=log)
+    t_data = time.perf_counter() - t0
+    net = spm.MLP("cuda:0")
+    net.set_params(L.init_params(0))
+    t0 = time.perf_counter()
+    losses = L.train(net, X, T, epochs=30, batch=256, lr=1e-3, lr_final=1e-5, seed=0, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    Z, P, NW, B, IR = spm.SPM_X0_ZERO, spm.SPM_X0_PREVIOUS, spm.SPM_X0_NETWORK, spm.SPM_PRECOND_BLOCK, spm.SPM_FP32_IR
+    variants = [("fp64_zero", dict(x0=Z)),
+                ("fp64_previous", dict(x0=P)),
+                ("fp64_network", dict(x0=NW)),
+                ("fp64_zero_precond", dict(x0=Z, precond=B)),
+                ("fp64_network_precond", dict(x0=NW, precond=B)),
+                ("fp32ir_zero", dict(x0=Z, precision=IR)),
+                ("fp32ir_zero_precond", dict(x0=Z, precond=B, precision=IR)),
+                ("fp32ir_network_precond", dict(x0=NW, precond=B, precision=IR))]
+    res = {}
+    for name, cfg in variants:
+        its, secs, steps, res_max, fb = [], 0.0, 0, 0.0, 0
+        for sd in range(6000, 6003):
+            wl = W.trajectory_cell(sd)
+            s = spm.Solver("cuda:0", **cfg).set_workload(wl)
+            s.set_network(net)
+            s.step(0.01, 1, 0.0, wl["centers"], wl["theta"])   # warm-up (graphs, preconditioner)
+            s.set_workload(wl)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = s.step(0.01, eval_steps, 0.0, wl["centers"], wl["theta"])
+            torch.cuda.synchronize()
+            secs += time.perf_counter() - t1
+            steps += eval_steps
+            its += [i["iterations"] for i in r["infos"]]
+            res_max = max(res_max, max(i["rel_residual"] for i in r["infos"]))
+            fb += sum(i["fallback"] for i in r["infos"])
+            s.close()
+        res[name] = {"steps_per_s": steps / secs, "ms_per_step": 1e3 * secs / steps,
+                     "iterations_mean": float(np.mean(its)), "max_rel_residual": res_max, "fallbacks": fb}
+        log(f"[bench] {name}: {res[name]}")
+    best = max(("fp64_network_precond", "fp32ir_network_precond"), key=lambda k: res[k]["steps_per_s"])
+    out = {"metric": "time steps/s with the learned warm start + block preconditioner (FP64 residual 1e-10)",
+           "value": res[best]["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": 3 * eval_steps,
+           "warmup": 3, "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "bf16+f64" if best.startswith("fp64") else "bf16+f32+f64",
+           "data": "synthetic", "config": {"workload": "trajectories_25-100_ellipses_phi0.3_dt0.01",
+                                           "train_seeds": "5000-5009", "eval_seeds": "6000-6002",
+                                           "train_steps": train_steps, "eval_steps": eval_steps, "best": best},
+           "training": {"samples": int(X.shape[0]), "solves": solves, "data_s": t_data, "train_s": t_train,
+                        "adam_steps": int(len(losses)), "final_loss": float(np.mean(losses[-100:]))},
+           "variants": res, "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 

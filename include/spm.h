@@ -61,7 +61,15 @@ extern "C" {
 #define SPM_FP32 1         /* near-image sum in FP32 with FP32 accumulation; the rest FP64 */
 #define SPM_FP32_IR 2      /* solve: FP64 iterative refinement around FP32-near-sum GMRES */
 
+#define SPM_X0_ZERO 0      /* initial guess of a solve without sigma0: zero */
+#define SPM_X0_PREVIOUS 1  /* spm_step: the previous step's density (first step: zero) */
+#define SPM_X0_NETWORK 2   /* the learned warm start of the network set by spm_set_network */
+
+#define SPM_PRECOND_NONE 0
+#define SPM_PRECOND_BLOCK 1  /* right preconditioner blockdiag(B_q)^-1 of isolated-body self blocks */
+
 typedef struct spm_handle spm_handle;
+typedef struct spm_mlp spm_mlp;
 
 /* Solver configuration; spm_default_config() fills the values in brackets. */
 typedef struct {
@@ -79,6 +87,10 @@ typedef struct {
   double rcond;         /* proxy pseudo-inverse relative cutoff [1e-14] */
   int32_t use_graph;    /* replay one captured GMRES iteration as a HIP graph [1] */
   int32_t poll_every;   /* GMRES iterations between convergence checks on the host [2] */
+  int32_t x0;           /* SPM_X0_* initial guess when no sigma0 is given [SPM_X0_ZERO] */
+  int32_t precond;      /* SPM_PRECOND_* [SPM_PRECOND_NONE] */
+  int32_t learned_max_iter; /* iteration cap of a warm-started or preconditioned attempt before
+                               the plain-GMRES fallback; 0 = max_iter [0] */
 } spm_config;
 
 typedef struct {
@@ -92,6 +104,9 @@ typedef struct {
   double seconds_setup;    /* geometry, proxy pseudo-inverse, close pairs */
   double seconds_solve;
   double seconds_readout;
+  int32_t fallback;        /* 1 if the warm-started/preconditioned attempt failed and plain
+                              GMRES (zero guess, no preconditioner) produced the result */
+  int32_t first_iterations;/* iterations of that failed attempt (0 without fallback) */
 } spm_solve_info;
 
 typedef void* (*spm_alloc_fn)(size_t bytes, void* stream, void* ctx);
@@ -159,7 +174,11 @@ int spm_effective_viscosity(spm_handle* h, const double* sigma, double* mu_eff);
 /* Forward Euler time stepping (Sec. 7) of a single-cell handle. t_inout (host): time on entry/exit;
  * the skew follows s(t) = s(0) + gamma t from the lattice set last plus the
  * elapsed time. centers_inout [2n], theta_inout [n] (host) hold the state;
- * mu_eff_series_host [n_steps] receives mu_eff(t_k); infos_host [n_steps] may be NULL. */
+ * mu_eff_series_host [n_steps] receives mu_eff(t_k); infos_host [n_steps] may be NULL.
+ * The initial guess of every solve follows cfg.x0 (SPM_X0_PREVIOUS: the previous step's
+ * density). If a step fails (e.g. SPM_EOVERLAP when particles collide), the state,
+ * *t_inout and the series hold the last state reached: (t_out - t_in) / dt steps were
+ * completed, and the handle must be given particles again before further calls. */
 int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers_inout_host,
              double* theta_inout_host, double* mu_eff_series_host, spm_solve_info* infos_host);
 
@@ -172,7 +191,9 @@ int spm_near_traction(spm_handle* h, const double* sigma, double* out, int32_t p
 /* Close-evaluation correction Delta T (Sec. 6.3): barycentric traction minus the
  * plain near-sum terms over each close (target, source image) pair. out [2N].
  * precision selects which plain terms are subtracted (those of the FP64 or the
- * FP32 near sum). */
+ * FP32 near sum). For SPM_FP32 it also holds the own-curve correction: the terms
+ * between a target and the nodes of its own curve (zero shift) in FP64 minus the FP32
+ * near sum's (FP32 coordinates cannot resolve those short, nearly tangent chords). */
 int spm_close_correction(spm_handle* h, const double* sigma, double* out, int32_t precision);
 
 /* Proxy strengths xi = Q^+ (g0 - g) (Sec. 6.2 steps 2-3). xi [2M] (device),
@@ -241,6 +262,80 @@ int spm_profile(spm_handle* h, int32_t enable);
  * total_ms: summed launch durations; launches: number of launches; pairs: node-image
  * pair evaluations (9 N^2 per launch). Any output may be NULL. Synchronises. */
 int spm_profile_read(spm_handle* h, int32_t kernel, double* total_ms, int64_t* launches, double* pairs);
+
+/* ---- block preconditioner ---- */
+
+/* out = P^{-1} v with P = blockdiag(B_q): B_q is particle q's completed operator alone in
+ * free space (sigma/2 + its own traction single layer with the smooth diagonal limit of
+ * Sec. 6 + the rigid-mode completion L of Sec. 5; no pin, no images, no other particles).
+ * The blocks are built and inverted (FP64 Gauss-Jordan, stored FP32) once per particle
+ * shape (a, b, N_i) in the body frame and kept for later geometries with the same
+ * shapes; each application rotates into the body frame and back. v, out [2N]. */
+int spm_precond_apply(spm_handle* h, const double* v, double* out);
+
+/* ---- learned warm start ---- */
+
+#define SPM_MLP_IN 33          /* features per particle */
+#define SPM_MLP_HIDDEN 256     /* width of the three hidden layers */
+#define SPM_MLP_OUT 128        /* body-frame Fourier coefficients per particle (64 complex) */
+#define SPM_MLP_NPARAMS 173184 /* W0[256x33] b0 W1[256x256] b1 W2[256x256] b2 W3[128x256] b3 */
+#define SPM_MLP_BF16 0         /* matrix-core products in bfloat16, FP32 accumulation */
+#define SPM_MLP_FP32 1         /* matrix-core products in FP32 (checking mode) */
+
+/* Per-particle features [n x 33] (FP32, device): for the 8 nearest other particle images
+ * (3x3 images of the particle's own cell, its own images included, ordered by squared
+ * centre distance, then particle, then shift index) the centre offset in the particle's
+ * body frame divided by its semi-major axis and (cos, sin) of twice the angle
+ * difference; then a/b. */
+int spm_features(spm_handle* h, float* features);
+
+/* Training targets [n x 128] (FP32, device) of a density sigma [2N]: sigma minus its
+ * cell-wide normal component beta* n (beta* = <sigma, n>/<n, n> per cell), rotated into
+ * each particle's body frame, divided by mu gamma, as the discrete Fourier
+ * coefficients c_m, m = -32..31 (real parts, then imaginary parts). */
+int spm_density_modes(spm_handle* h, const double* sigma, float* modes);
+
+/* Warm start from coefficients [n x 128] (device FP32): decode to the nodes (g), then per
+ * cell sigma0 = alpha g + beta n with (alpha, beta) minimising |b - alpha A g - beta n/2|
+ * (the completed operator maps n to n/2), so the guess never has a larger residual than
+ * zero. sigma0 [2N] (device). One FP64 operator application. */
+int spm_warm_start(spm_handle* h, const float* modes, double* sigma0);
+
+/* Attach a network (borrowed: it must outlive its use; NULL detaches) for SPM_X0_NETWORK. */
+int spm_set_network(spm_handle* h, spm_mlp* net);
+
+/* features -> network (BF16) -> spm_warm_start. sigma0 [2N] (device). */
+int spm_learned_guess(spm_handle* h, double* sigma0);
+
+/* Forward Euler as spm_step, also recording for every step k the features and the
+ * training targets of the solved density (device, [n_steps x n x 33] and
+ * [n_steps x n x 128]; either may be NULL). */
+int spm_step_record(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers_inout_host,
+                    double* theta_inout_host, double* mu_eff_series_host, spm_solve_info* infos_host,
+                    float* features, float* targets);
+
+/* Network object (its own stream and allocator, as spm_create). Parameters start at zero;
+ * set them with spm_mlp_set_params (which also resets the Adam state). */
+int spm_mlp_create(spm_mlp** net, void* hip_stream, spm_alloc_fn alloc, spm_free_fn free_fn, void* alloc_ctx);
+void spm_mlp_destroy(spm_mlp* net);
+const char* spm_mlp_last_error(const spm_mlp* net);
+int spm_mlp_set_params(spm_mlp* net, const float* params);   /* device [SPM_MLP_NPARAMS] */
+int spm_mlp_get_params(spm_mlp* net, float* params);         /* device [SPM_MLP_NPARAMS] */
+
+/* y [batch x 128] = MLP(x [batch x 33]) (device FP32, row-major). */
+int spm_mlp_forward(spm_mlp* net, const float* x, int64_t batch, float* y, int32_t mode);
+
+/* Loss (1/(2 batch)) sum |y - t|^2 (host) and its gradient with respect to the packed
+ * parameters (device [SPM_MLP_NPARAMS], may be NULL). */
+int spm_mlp_loss_grad(spm_mlp* net, const float* x, const float* t, int64_t batch, int32_t mode, float* grads,
+                      double* loss_host);
+
+/* n_batches Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on minibatches
+ * of the n_samples rows of x [n_samples x 33] and t [n_samples x 128]: batch k uses the
+ * rows idx[k batch .. (k+1) batch) (device int32; SPM_EINVAL if any is out of range).
+ * losses (device [n_batches], may be NULL) receives each minibatch loss before its step. */
+int spm_mlp_train(spm_mlp* net, const float* x, const float* t, int64_t n_samples, const int32_t* idx,
+                  int32_t n_batches, int32_t batch, float lr, int32_t mode, float* losses);
 
 #ifdef __cplusplus
 }

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <utility>
 
 #include "spm_internal.h"
@@ -169,7 +170,7 @@ void need_particles(spm_handle* h) {
 }
 
 void drop_graphs(spm_handle* h) {
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < 4; ++k) {
     if (h->kr.graph[k]) (void)hipGraphExecDestroy(h->kr.graph[k]);
     if (h->kr.graph_src[k]) (void)hipGraphDestroy(h->kr.graph_src[k]);
     h->kr.graph[k] = nullptr;
@@ -321,7 +322,56 @@ void alloc_krylov(spm_handle* h) {
   ensure(h, K.w, n2);
   ensure(h, K.b, n2);
   ensure(h, K.d, n2);
+  ensure(h, K.z, n2);
+  ensure(h, K.z2, n2);
   ensure(h, K.dots, C);
+}
+
+// Learned warm start buffers and the normal field as one SoA vector.
+void alloc_learned(spm_handle* h) {
+  Learned& L = h->ln;
+  const int64_t N = h->geo.N;
+  const int C = h->geo.C, n = h->geo.No;
+  ensure(h, L.nvec, 2 * N);
+  ensure(h, L.num, C);
+  ensure(h, L.den, C);
+  ensure(h, L.fit, (size_t)7 * C);
+  ensure(h, L.feat, (size_t)n * SPM_MLP_IN);
+  ensure(h, L.modes, (size_t)n * SPM_MLP_OUT);
+  SPM_HIP_CHECK(hipMemcpyAsync(L.nvec, h->geo.nx, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  SPM_HIP_CHECK(hipMemcpyAsync(L.nvec + N, h->geo.ny, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+}
+
+// Distinct particle shapes (a, b, N) in order of first appearance; the preconditioner
+// is rebuilt (lazily) only when this list changes.
+void update_shapes(spm_handle* h) {
+  Precond& P = h->pc;
+  const int n = h->geo.No;
+  std::map<std::tuple<double, double, int32_t>, int32_t> id;
+  std::vector<double> ka, kb;
+  std::vector<int32_t> kn, ps(n);
+  for (int i = 0; i < n; ++i) {
+    const auto key = std::make_tuple(h->a[i], h->b[i], h->nn[i]);
+    auto it = id.find(key);
+    if (it == id.end()) {
+      const int32_t s = (int32_t)ka.size();
+      id.emplace(key, s);
+      ka.push_back(h->a[i]);
+      kb.push_back(h->b[i]);
+      kn.push_back(h->nn[i]);
+      ps[i] = s;
+    } else {
+      ps[i] = it->second;
+    }
+  }
+  if (ka != P.ka || kb != P.kb || kn != P.kn) {
+    P.valid = false;
+    P.ka = ka;
+    P.kb = kb;
+    P.kn = kn;
+  }
+  ensure(h, P.pshape, n);
+  upload(h, P.pshape, ps.data(), n * sizeof(int32_t));
 }
 
 void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* part_off, const double* centers,
@@ -443,6 +493,8 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   if (total > 0) launch_close_fill(h);
   build_chunks(h);
   alloc_krylov(h);
+  alloc_learned(h);
+  update_shapes(h);
   if (h->wk.tuned && h->wk.tuned_N != N) h->wk.tuned = false;
   if (!h->wk.tuned) {
     h->wk.near[0].cfg = heuristic_near(h);
@@ -471,14 +523,21 @@ void matvec(spm_handle* h, const double* sigma, double* out, int precision, bool
     launch_vplus(h, sigma);
     launch_close_apply_impl(h, h->wk.T, precision, with_active);
   }
+  if (precision == SPM_FP32) launch_self_fix(h, h->wk.T, with_active);
   launch_assemble(h, sigma, out);
 }
 
-// one GMRES iteration of every active cell (fixed arguments: capturable)
-void iteration(spm_handle* h, int precision) {
+// one GMRES iteration of every active cell (fixed arguments: capturable); with the block
+// preconditioner the operator is A P^{-1} (right preconditioning)
+void iteration(spm_handle* h, int precision, bool pc) {
   Krylov& K = h->kr;
   gm_copy_in(h);
-  matvec(h, K.vin, K.w, precision, true);
+  if (pc) {
+    launch_precond_apply(h, K.vin, K.z, true);
+    matvec(h, K.z, K.w, precision, true);
+  } else {
+    matvec(h, K.vin, K.w, precision, true);
+  }
   gm_cgs_pass(h, K.w, K.h1);
   gm_update_j(h, K.h1, K.w);
   gm_cgs_pass(h, K.w, K.h2);
@@ -488,8 +547,8 @@ void iteration(spm_handle* h, int precision) {
   gm_givens(h);
 }
 
-hipGraphExec_t iteration_graph(spm_handle* h, int precision) {
-  const int k = precision == SPM_FP64 ? 0 : 1;
+hipGraphExec_t iteration_graph(spm_handle* h, int precision, bool pc) {
+  const int k = (precision == SPM_FP64 ? 0 : 1) + (pc ? 2 : 0);
   Krylov& K = h->kr;
   if (K.graph[k]) return K.graph[k];
   if (!K.cap_stream) SPM_HIP_CHECK(hipStreamCreateWithFlags(&K.cap_stream, hipStreamNonBlocking));
@@ -497,7 +556,7 @@ hipGraphExec_t iteration_graph(spm_handle* h, int precision) {
   h->stream = K.cap_stream;
   try {
     SPM_HIP_CHECK(hipStreamBeginCapture(K.cap_stream, hipStreamCaptureModeThreadLocal));
-    iteration(h, precision);
+    iteration(h, precision, pc);
     SPM_HIP_CHECK(hipStreamEndCapture(K.cap_stream, &K.graph_src[k]));
   } catch (...) {
     hipGraph_t dummy = nullptr;
@@ -534,7 +593,7 @@ void upload_cell_arrays(spm_handle* h, const std::vector<double>& bn, const std:
 
 // GMRES cycle on V_0 = r for the cells in `act` (others untouched); x += correction.
 // Returns the Krylov iterations of every cell.
-std::vector<int32_t> krylov_cycle(spm_handle* h, int precision, double* x, const std::vector<double>& bn,
+std::vector<int32_t> krylov_cycle(spm_handle* h, int precision, bool pc, double* x, const std::vector<double>& bn,
                                   const std::vector<double>& tol, const std::vector<int32_t>& act, int maxit) {
   Krylov& K = h->kr;
   const int C = h->geo.C;
@@ -547,12 +606,12 @@ std::vector<int32_t> krylov_cycle(spm_handle* h, int precision, double* x, const
   const int poll = std::max(1, h->cfg.poll_every);
   int done = 0;
   if (hj[1] > 0) {
-    hipGraphExec_t ge = graph ? iteration_graph(h, precision) : nullptr;
+    hipGraphExec_t ge = graph ? iteration_graph(h, precision, pc) : nullptr;
     for (int it = 0; it < maxit; ++it) {
       if (graph)
         SPM_HIP_CHECK(hipGraphLaunch(ge, h->stream));
       else
-        iteration(h, precision);
+        iteration(h, precision, pc);
       ++done;
       if ((it + 1) % poll == 0 || it + 1 == maxit) {
         SPM_HIP_CHECK(hipMemcpyAsync(hj, K.jdev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
@@ -561,7 +620,15 @@ std::vector<int32_t> krylov_cycle(spm_handle* h, int precision, double* x, const
       }
     }
   }
-  gm_backsolve_update(h, x);
+  if (pc) {   // x += P^{-1} (V y)
+    gm_backsolve(h);
+    gm_zero(h, K.z2, K.n2);
+    gm_update_only(h, K.z2);
+    launch_precond_apply(h, K.z2, K.z, false);
+    gm_axpby(h, K.n2, 1.0, x, 1.0, K.z, x);
+  } else {
+    gm_backsolve_update(h, x);
+  }
   std::vector<int32_t> kd(C, 0);
   int32_t* hk = host_scratch<int32_t>(h, C);
   download(h, hk, K.kdone, C * sizeof(int32_t));
@@ -596,11 +663,47 @@ void stamp_newly(spm_handle* h, const std::vector<int32_t>& newly) {
   sync(h);
 }
 
-int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<spm_solve_info>& infos) {
+// Warm-start fit (b in K.b): with z = A g for the decoded guess g in x, per cell
+// x <- alpha g + beta n with (alpha, beta) minimising |b - alpha z - beta n/2|
+// (A n = n/2), and the residual of the result into tmp2.
+void offset_fit(spm_handle* h, double* x) {
+  Krylov& K = h->kr;
+  Learned& L = h->ln;
+  const int C = h->geo.C;
+  matvec(h, x, K.tmp, SPM_FP64, false);
+  gm_dot(h, K.tmp, K.tmp, L.fit);
+  gm_dot(h, K.tmp, L.nvec, L.fit + C);
+  gm_dot(h, L.nvec, L.nvec, L.fit + 2 * C);
+  gm_dot(h, K.b, K.tmp, L.fit + 3 * C);
+  gm_dot(h, K.b, L.nvec, L.fit + 4 * C);
+  launch_fit_guess(h, L.fit, L.fit + 5 * C);
+  launch_apply_fit(h, L.fit + 5 * C, K.b, K.tmp, x, K.tmp2);
+}
+
+// features -> network (BF16) -> decoded density in x (no offset fit)
+void network_decode(spm_handle* h, double* x) {
+  if (!h->net) throw ApiError(SPM_ESTATE, "no network set (spm_set_network)");
+  launch_features(h, h->ln.feat);
+  mlp_forward(h->net, h->stream, h->ln.feat, nullptr, h->geo.No, h->ln.modes, SPM_MLP_BF16);
+  launch_decode(h, h->ln.modes, x);
+}
+
+// How one solve attempt starts and iterates.
+struct Attempt {
+  bool network = false;   // learned warm start (when no sigma0 is given)
+  bool pc = false;        // block preconditioner
+  int max_iter = 0;
+};
+
+int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<spm_solve_info>& infos,
+               const Attempt& at) {
   Krylov& K = h->kr;
   const int C = h->geo.C;
   const int64_t n2 = K.n2;
   const double tol = h->cfg.tol;
+  const int max_iter = at.max_iter;
+  const bool pc = at.pc;
+  if (pc && !h->pc.valid) build_precond(h);
   CellStats st(C);
   launch_rhs(h, K.b);
   gm_dot(h, K.b, K.b, K.dots);
@@ -610,13 +713,25 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
     for (int c = 0; c < C; ++c) st.bnorm[c] = std::sqrt(hd[c]);
   }
   gm_stamp_start(h);
+  const bool net = !sigma0 && at.network;
   if (sigma0)
     gm_copy(h, sigma, sigma0, n2);
+  else if (net)
+    network_decode(h, sigma);
   else
     gm_zero(h, sigma, n2);
   std::vector<int32_t> act(C, 1), conv(C, 0), newly(C, 0);
   if (sigma0) {
     residual(h, sigma, act, st);
+  } else if (net) {
+    offset_fit(h, sigma);
+    gm_dot(h, K.tmp2, K.tmp2, K.dots);
+    double* hd = host_scratch<double>(h, C);
+    download(h, hd, K.dots, C * sizeof(double));
+    for (int c = 0; c < C; ++c) {
+      st.rel[c] = std::sqrt(hd[c]) / st.bnorm[c];
+      st.m64[c] += 1;
+    }
   } else {
     gm_copy(h, K.tmp2, K.b, n2);
     std::fill(st.rel.begin(), st.rel.end(), 1.0);
@@ -626,7 +741,7 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
     for (int c = 0; c < C; ++c) {
       newly[c] = (!conv[c] && st.rel[c] <= tol) ? 1 : 0;
       if (newly[c]) conv[c] = 1;
-      act[c] = (!conv[c] && st.its[c] < h->cfg.max_iter) ? 1 : 0;
+      act[c] = (!conv[c] && st.its[c] < max_iter) ? 1 : 0;
       any = any || act[c];
     }
     stamp_newly(h, newly);
@@ -642,7 +757,7 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
       }
       gm_copy(h, K.V, K.tmp2, n2);   // V_0 = r
       gm_zero(h, K.d, n2);
-      const std::vector<int32_t> kd = krylov_cycle(h, SPM_FP32, K.d, bn, tl, act, h->cfg.max_iter);
+      const std::vector<int32_t> kd = krylov_cycle(h, SPM_FP32, pc, K.d, bn, tl, act, max_iter);
       gm_axpby(h, n2, 1.0, sigma, 1.0, K.d, sigma);
       const std::vector<double> before = st.rel;
       std::vector<int32_t> was = act;
@@ -660,7 +775,7 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
           if (verbose())
             std::fprintf(stderr, "[spm] cell %d refinement %d: inner its %d (inner tol %.1e) residual %.3e -> %.3e\n",
                          c, st.refine[c], kd[c], tl[c], before[c], st.rel[c]);
-          if (kd[c] == 0 && st.rel[c] > tol) st.its[c] = h->cfg.max_iter;  // no progress possible
+          if (kd[c] == 0 && st.rel[c] > tol) st.its[c] = max_iter;  // no progress possible
         }
       any = mark();
     }
@@ -668,10 +783,10 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
     std::vector<double> tl(C, tol);
     for (int restart = 0; restart < 6 && any; ++restart) {
       gm_copy(h, K.V, K.tmp2, n2);   // V_0 = r
-      int budget = h->cfg.max_iter;
+      int budget = max_iter;
       for (int c = 0; c < C; ++c)
-        if (act[c]) budget = std::min(budget, h->cfg.max_iter - st.its[c]);
-      const std::vector<int32_t> kd = krylov_cycle(h, SPM_FP64, sigma, st.bnorm, tl, act, std::max(1, budget));
+        if (act[c]) budget = std::min(budget, max_iter - st.its[c]);
+      const std::vector<int32_t> kd = krylov_cycle(h, SPM_FP64, pc, sigma, st.bnorm, tl, act, std::max(1, budget));
       std::vector<int32_t> was = act;
       for (int c = 0; c < C; ++c)
         if (was[c]) {
@@ -714,7 +829,25 @@ int solve_api(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
   const int C = h->geo.C;
   std::vector<spm_solve_info> infos;
   const double t0 = now();
-  const int st = solve_impl(h, sigma0, sigma, infos);
+  Attempt first;
+  first.network = !sigma0 && h->cfg.x0 == SPM_X0_NETWORK;
+  first.pc = h->cfg.precond == SPM_PRECOND_BLOCK;
+  const bool special = first.network || first.pc;
+  first.max_iter = (special && h->cfg.learned_max_iter > 0) ? std::min(h->cfg.learned_max_iter, h->cfg.max_iter)
+                                                             : h->cfg.max_iter;
+  int st = solve_impl(h, sigma0, sigma, infos, first);
+  if (st == SPM_ENOCONV && special) {
+    // fallback: plain GMRES from zero without the preconditioner
+    std::vector<int32_t> first_its(C);
+    for (int c = 0; c < C; ++c) first_its[c] = infos[c].iterations;
+    Attempt plain;
+    plain.max_iter = h->cfg.max_iter;
+    st = solve_impl(h, nullptr, sigma, infos, plain);
+    for (int c = 0; c < C; ++c) {
+      infos[c].fallback = 1;
+      infos[c].first_iterations = first_its[c];
+    }
+  }
   sync(h);
   const double t1 = now();
   readout(h, sigma, vel, omega, mu_eff);
@@ -786,6 +919,21 @@ void build_near_plan(spm_handle* h, int precision) {
   drop_graphs(h);
 }
 
+void* precond_alloc(spm_handle* h, void* old, size_t bytes, size_t& cap) {
+  if (old && cap >= bytes) return old;
+  if (old) raw_free(h, old);
+  void* p = raw_alloc(h, bytes);
+  cap = bytes;
+  return p;
+}
+
+void precond_release_work(spm_handle* h) {
+  sync(h);
+  raw_free(h, h->pc.work);
+  h->pc.work = nullptr;
+  h->pc.work_cap = 0;
+}
+
 void launch_prep_for_timing(spm_handle* h) {
   // fill the force arrays from the right-hand side so the timed kernels see finite data
   launch_rhs(h, h->kr.tmp);
@@ -813,6 +961,9 @@ void spm_default_config(spm_config* c) {
   c->rcond = 1e-14;
   c->use_graph = 1;
   c->poll_every = 2;
+  c->x0 = SPM_X0_ZERO;
+  c->precond = SPM_PRECOND_NONE;
+  c->learned_max_iter = 0;
 }
 
 int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_fn alloc, spm_free_fn free_fn,
@@ -829,7 +980,8 @@ int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_
   if (!(c.mu > 0) || !(c.gamma > 0) || c.M < 4 || c.M > 512 || c.m_wall < 4 || c.m_wall > 256 || !(c.R_proxy > 0.75) ||
       !(c.tol > 0) || c.max_iter < 1 || c.max_iter > 5000 || c.close_factor < 0 ||
       (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR) || !(c.inner_tol > 0 && c.inner_tol < 1) ||
-      c.poll_every < 1) {
+      c.poll_every < 1 || c.x0 < SPM_X0_ZERO || c.x0 > SPM_X0_NETWORK ||
+      (c.precond != SPM_PRECOND_NONE && c.precond != SPM_PRECOND_BLOCK) || c.learned_max_iter < 0) {
     delete h;
     return SPM_EINVAL;
   }
@@ -852,6 +1004,8 @@ void spm_destroy(spm_handle* h) {
     drop_graphs(h);
     if (h->kr.cap_stream) (void)hipStreamDestroy(h->kr.cap_stream);
     free_all(h);
+    for (void* p : {(void*)h->pc.inv, (void*)h->pc.ioff, (void*)h->pc.work, (void*)h->pc.desc, (void*)h->pc.status})
+      raw_free(h, p);
     if (h->kr.host) (void)hipHostFree(h->kr.host);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
   } catch (...) {
@@ -1026,6 +1180,7 @@ int spm_close_correction(spm_handle* h, const double* sigma, double* out, int32_
       launch_vplus(h, sigma);
       launch_close_apply(h, sigma, out, precision);
     }
+    if (precision == SPM_FP32) launch_self_fix(h, out, false);
     sync(h);
     return SPM_OK;
   });
@@ -1158,8 +1313,8 @@ int spm_profile_read(spm_handle* h, int32_t kernel, double* total_ms, int64_t* l
   });
 }
 
-int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers, double* theta,
-             double* mu_series, spm_solve_info* infos) {
+int spm_step_record(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers, double* theta,
+                    double* mu_series, spm_solve_info* infos, float* features, float* targets) {
   return guarded(h, [&]() {
     need_particles(h);
     if (h->geo.C != 1) throw ApiError(SPM_EINVAL, "time stepping runs on a single cell");
@@ -1181,12 +1336,20 @@ int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double*
     for (int k = 0; k < n_steps; ++k) {
       const double sk = s0 + h->cfg.gamma * (k * dt);
       const int32_t off[2] = {0, n};
+      *t_inout = t0 + k * dt;   // time of the state being solved (kept if this step fails)
       set_cells_impl(h, 1, &sk, off, centers, theta, a.data(), b.data(), nn.data());
       sig = h->kr.stepbuf;  // (buffers are stable: same sizes)
       spm_solve_info info;
-      const int rc = solve_api(h, have_prev ? sig : nullptr, sig, vel, om, mu, &info, nullptr);
+      const double* guess = (h->cfg.x0 == SPM_X0_PREVIOUS && have_prev) ? sig : nullptr;
+      const int rc = solve_api(h, guess, sig, vel, om, mu, &info, nullptr);
       if (rc && rc != SPM_ENOCONV) return rc;
       have_prev = true;
+      if (features) launch_features(h, features + (int64_t)k * n * SPM_MLP_IN);
+      if (targets) {
+        gm_dot(h, sig, h->ln.nvec, h->ln.num);
+        gm_dot(h, h->ln.nvec, h->ln.nvec, h->ln.den);
+        launch_modes(h, sig, h->ln.num, h->ln.den, targets + (int64_t)k * n * SPM_MLP_OUT);
+      }
       download(h, hv.data(), vel, (3 * n + 1) * sizeof(double));
       mu_series[k] = hv[3 * n];
       if (infos) infos[k] = info;
@@ -1200,6 +1363,74 @@ int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double*
     *t_inout = t0 + n_steps * dt;
     h->cells[0].skew_raw = s0 + h->cfg.gamma * n_steps * dt;
     h->pending_skew = h->cells[0].skew_raw;
+    return SPM_OK;
+  });
+}
+
+int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers, double* theta,
+             double* mu_series, spm_solve_info* infos) {
+  return spm_step_record(h, dt, n_steps, t_inout, centers, theta, mu_series, infos, nullptr, nullptr);
+}
+
+int spm_precond_apply(spm_handle* h, const double* v, double* out) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!v || !out) throw ApiError(SPM_EINVAL, "null vector");
+    if (!h->pc.valid) build_precond(h);
+    launch_precond_apply(h, v, out, false);
+    sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_features(spm_handle* h, float* features) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!features) throw ApiError(SPM_EINVAL, "null features");
+    launch_features(h, features);
+    sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_density_modes(spm_handle* h, const double* sigma, float* modes) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!sigma || !modes) throw ApiError(SPM_EINVAL, "null argument");
+    gm_dot(h, sigma, h->ln.nvec, h->ln.num);
+    gm_dot(h, h->ln.nvec, h->ln.nvec, h->ln.den);
+    launch_modes(h, sigma, h->ln.num, h->ln.den, modes);
+    sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_warm_start(spm_handle* h, const float* modes, double* sigma0) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!modes || !sigma0) throw ApiError(SPM_EINVAL, "null argument");
+    launch_rhs(h, h->kr.b);
+    launch_decode(h, modes, sigma0);
+    offset_fit(h, sigma0);
+    sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_set_network(spm_handle* h, spm_mlp* net) {
+  if (!h) return SPM_EINVAL;
+  h->net = net;
+  return SPM_OK;
+}
+
+int spm_learned_guess(spm_handle* h, double* sigma0) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!sigma0) throw ApiError(SPM_EINVAL, "null sigma0");
+    launch_rhs(h, h->kr.b);
+    network_decode(h, sigma0);
+    offset_fit(h, sigma0);
+    sync(h);
     return SPM_OK;
   });
 }

@@ -226,4 +226,52 @@ void launch_close_apply(spm_handle* h, const double* sigma, double* T, int preci
   launch_close_apply_impl(h, T, precision, false);
 }
 
+// Own-curve terms of the FP32 near sum. For a target and the other nodes of its own
+// curve (zero shift), r = x_i - y_k is a short chord nearly tangent to the curve: FP32
+// node coordinates leave r with a relative error of about eps32 |x| / |r| and the
+// cancellation in r.n magnifies it, so these few terms (sum of N_q^2 over particles,
+// a tiny fraction of all pairs) are recomputed in FP64 and the FP32 ones, evaluated
+// with the near kernel's own per-pair arithmetic, are removed:
+//   T_i += -(1/pi) sum_{k on the curve of i} (a64(i, k) - a32(i, k)).
+// One block per particle, one thread per target.
+__global__ __launch_bounds__(256) void k_self_fix(int64_t N, Geo g, const double* __restrict__ f1,
+                                                  const double* __restrict__ f2, const float* __restrict__ f1f,
+                                                  const float* __restrict__ f2f, const int32_t* __restrict__ active,
+                                                  double* __restrict__ T) {
+  const int q = blockIdx.x;
+  if (active != nullptr && active[g.pcell[q]] == 0) return;
+  const int o = g.poff[q], n = g.pn[q];
+  for (int k0 = threadIdx.x; k0 < n; k0 += blockDim.x) {
+    const int64_t i = o + k0;
+    const double xi = g.x[i], yi = g.y[i], nxi = g.nx[i], nyi = g.ny[i];
+    const float xif = g.xf[i], yif = g.yf[i], nxif = g.nxf[i], nyif = g.nyf[i];
+    double d1 = 0.0, d2 = 0.0, e1 = 0.0, e2 = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const int64_t kk = o + k;
+      {
+        const double dx = xi - g.x[kk], dy = yi - g.y[kk];
+        double a1 = 0.0, a2 = 0.0;
+        gt_pair(dx - 0.0, row_terms(dy, 0.0, nyi, f2[kk]), nxi, f1[kk], a1, a2);
+        d1 += a1;
+        d2 += a2;
+      }
+      {
+        const float dx = xif - g.xf[kk], dy = yif - g.yf[kk];
+        float a1 = 0.f, a2 = 0.f;
+        gt_pair(dx - 0.0f, row_terms(dy, 0.0f, nyif, f2f[kk]), nxif, f1f[kk], a1, a2);
+        e1 += (double)a1;
+        e2 += (double)a2;
+      }
+    }
+    T[i] += -(1.0 / kPi) * (d1 - e1);
+    T[N + i] += -(1.0 / kPi) * (d2 - e2);
+  }
+}
+
+void launch_self_fix(spm_handle* h, double* T, bool with_active) {
+  k_self_fix<<<h->geo.No, 256, 0, h->stream>>>(h->geo.N, h->geo, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f,
+                                               with_active ? h->kr.active : nullptr, T);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
 }  // namespace spm

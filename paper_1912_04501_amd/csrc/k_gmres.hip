@@ -286,13 +286,22 @@ __global__ void k_update_x(const double* __restrict__ V, int64_t n2, int64_t N, 
   x[r] += s;
 }
 
-void gm_backsolve_update(spm_handle* h, double* x) {
+void gm_backsolve(spm_handle* h) {
   Krylov& K = h->kr;
   k_backsolve<<<(h->geo.C + 63) / 64, 64, 0, h->stream>>>(h->geo.C, K.kmax, K.jdev, K.H, K.g, K.active, K.kdone, K.yv);
   SPM_HIP_CHECK(hipGetLastError());
+}
+
+void gm_update_only(spm_handle* h, double* x) {
+  Krylov& K = h->kr;
   k_update_x<<<(unsigned)((K.n2 + 255) / 256), 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.kmax, K.kdone, K.yv,
                                                                     h->geo.ncell, x);
   SPM_HIP_CHECK(hipGetLastError());
+}
+
+void gm_backsolve_update(spm_handle* h, double* x) {
+  gm_backsolve(h);
+  gm_update_only(h, x);
 }
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,

@@ -1,0 +1,258 @@
+// Block preconditioner: inverses of the isolated-body self blocks of the completed
+// operator (Sec. 5 eq. BIEPerturbed for one body in free space, Sec. 6 Nystrom rule),
+// one per particle shape (a, b, N), in the body frame.
+//
+//   B sigma = sigma/2 + sum_{j != i} G^t(x_i, y_j; n_i) w_j sigma_j
+//             - (kappa_i / 2 pi) tau_i tau_i^T w_i sigma_i + F + x_i^perp tau,
+//   F = sum_j w_j sigma_j,  tau = sum_j w_j x_j^perp . sigma_j  (x relative to the centre).
+//
+// Unknowns and rows are ordered [sigma_1(0..n-1), sigma_2(0..n-1)] (m = 2n). The blocks are
+// assembled in FP64 next to an identity ([B | I], m x 2m, row-major), inverted by
+// Gauss-Jordan elimination with partial pivoting (one 1024-thread workgroup per shape),
+// and stored in FP32 column-major, so that applying them reads coalesced columns.
+#include "spm_internal.h"
+
+namespace spm {
+
+__device__ __forceinline__ void body_node(double a, double b, int n, int k, double& x, double& y, double& tx,
+                                          double& ty, double& w, double& kap) {
+  double s, c;
+  sincos(2.0 * kPi * (double)k / (double)n, &s, &c);
+  x = a * c;
+  y = b * s;
+  const double dx = -a * s, dy = b * c;
+  const double sp = sqrt(dx * dx + dy * dy);
+  tx = dx / sp;
+  ty = dy / sp;
+  w = 2.0 * kPi * sp / (double)n;
+  kap = a * b / (sp * sp * sp);
+}
+
+// block (row i, shape): both rows (component 1 and 2) of node i of [B | I]
+__global__ __launch_bounds__(256) void k_self_block(const ShapeDesc* __restrict__ sh, double* __restrict__ work) {
+  const ShapeDesc d = sh[blockIdx.y];
+  const int n = d.n, m = 2 * n, ld = 2 * m;
+  const int i = blockIdx.x;
+  if (i >= n) return;
+  double xi, yi, txi, tyi, wi, ki;
+  body_node(d.a, d.b, n, i, xi, yi, txi, tyi, wi, ki);
+  const double nxi = tyi, nyi = -txi;
+  double* r1 = work + d.woff + (int64_t)i * ld;         // row of component 1
+  double* r2 = work + d.woff + (int64_t)(n + i) * ld;   // row of component 2
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double xj, yj, txj, tyj, wj, kj;
+    body_node(d.a, d.b, n, j, xj, yj, txj, tyj, wj, kj);
+    double m11, m12, m21, m22;
+    if (j == i) {
+      const double c = -(ki / (2.0 * kPi)) * wi;
+      m11 = c * txi * txi;
+      m12 = c * txi * tyi;
+      m21 = m12;
+      m22 = c * tyi * tyi;
+    } else {
+      const double rx = xi - xj, ry = yi - yj;
+      const double r2 = rx * rx + ry * ry;
+      const double c = -(rx * nxi + ry * nyi) / (kPi * r2 * r2) * wj;
+      m11 = c * rx * rx;
+      m12 = c * rx * ry;
+      m21 = m12;
+      m22 = c * ry * ry;
+    }
+    // completion: net force (w_j delta_cd) and torque (perp_c(i) w_j perp_d(j)), perp = (-y, x)
+    const double pi1 = -yi, pi2 = xi, pj1 = -yj, pj2 = xj;
+    m11 += wj + pi1 * wj * pj1;
+    m12 += pi1 * wj * pj2;
+    m21 += pi2 * wj * pj1;
+    m22 += wj + pi2 * wj * pj2;
+    if (j == i) {
+      m11 += 0.5;
+      m22 += 0.5;
+    }
+    r1[j] = m11;
+    r1[n + j] = m12;
+    r2[j] = m21;
+    r2[n + j] = m22;
+  }
+  for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    r1[m + j] = (j == i) ? 1.0 : 0.0;
+    r2[m + j] = (j == n + i) ? 1.0 : 0.0;
+  }
+}
+
+// One workgroup per shape: [B | I] -> [I | B^-1] with partial pivoting.
+// status[shape] = 1 if a pivot is zero.
+__global__ __launch_bounds__(1024) void k_gauss_jordan(const ShapeDesc* __restrict__ sh, double* __restrict__ work,
+                                                       int32_t* __restrict__ status) {
+  __shared__ double prow[2 * kMaxNodesPerParticle * 2];   // pivot row, up to 2m = 2048
+  __shared__ double fcol[2 * kMaxNodesPerParticle];       // column k of every row
+  __shared__ double rv[1024];
+  __shared__ int ri[1024];
+  const ShapeDesc d = sh[blockIdx.x];
+  const int m = 2 * d.n, ld = 2 * m;
+  double* A = work + d.woff;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+  int bad = 0;
+  for (int k = 0; k < m; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + t; i < m; i += blockDim.x) {
+      const double v = fabs(A[(int64_t)i * ld + k]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    rv[t] = best;
+    ri[t] = bi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (t < o) {
+        const double v2 = rv[t + o];
+        const int i2 = ri[t + o];
+        if (v2 > rv[t] || (v2 == rv[t] && i2 < ri[t])) {
+          rv[t] = v2;
+          ri[t] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = ri[0];
+    double piv = A[(int64_t)p * ld + k];
+    if (piv == 0.0) {
+      bad = 1;
+      piv = 1.0;
+    }
+    __syncthreads();
+    // swap rows k and p, scale the pivot row, keep it in LDS
+    for (int j = t; j < ld; j += blockDim.x) {
+      const double vk = A[(int64_t)k * ld + j], vp = A[(int64_t)p * ld + j];
+      const double pr = vp / piv;
+      prow[j] = pr;
+      A[(int64_t)k * ld + j] = pr;
+      if (p != k) A[(int64_t)p * ld + j] = vk;
+    }
+    __syncthreads();
+    for (int i = t; i < m; i += blockDim.x) fcol[i] = A[(int64_t)i * ld + k];
+    __syncthreads();
+    // eliminate column k from every other row (columns left of k are already unit vectors)
+    for (int i = wave; i < m; i += nw) {
+      if (i == k) continue;
+      const double f = fcol[i];
+      double* row = A + (int64_t)i * ld;
+      for (int j = k + lane; j < ld; j += 64) row[j] -= f * prow[j];
+    }
+    __syncthreads();
+  }
+  if (t == 0) status[blockIdx.x] = bad;
+}
+
+// inv[ioff + c m + r] = (float) A[r][m + c]
+__global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* __restrict__ work,
+                                float* __restrict__ inv) {
+  const ShapeDesc d = sh[blockIdx.y];
+  const int m = 2 * d.n, ld = 2 * m;
+  const int c = blockIdx.x;
+  if (c >= m) return;
+  for (int r = threadIdx.x; r < m; r += blockDim.x)
+    inv[d.ioff + (int64_t)c * m + r] = (float)work[d.woff + (int64_t)r * ld + m + c];
+}
+
+// One block per particle: out = R (B^-1 (R^T v)) on the particle's nodes. Particles of
+// inactive cells are skipped when active is given.
+__global__ __launch_bounds__(256) void k_precond_apply(Geo g, const int32_t* __restrict__ pshape,
+                                                       const int64_t* __restrict__ ioff, const float* __restrict__ inv,
+                                                       const int32_t* __restrict__ active,
+                                                       const double* __restrict__ v, double* __restrict__ out) {
+  __shared__ double vb[2 * kMaxNodesPerParticle];
+  __shared__ double ub[2 * kMaxNodesPerParticle];
+  const int q = blockIdx.x;
+  if (active && active[g.pcell[q]] == 0) return;
+  const int n = g.pn[q], m = 2 * n;
+  const int64_t i0 = g.poff[q], N = g.N;
+  double st, ct;
+  sincos(g.pth[q], &st, &ct);
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double a = v[i0 + k], b = v[N + i0 + k];
+    vb[k] = ct * a + st * b;
+    vb[n + k] = -st * a + ct * b;
+  }
+  __syncthreads();
+  const float* M = inv + ioff[pshape[q]];
+  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < m; ++c) acc += (double)M[(int64_t)c * m + r] * vb[c];
+    ub[r] = acc;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const double a = ub[k], b = ub[n + k];
+    out[i0 + k] = ct * a - st * b;
+    out[N + i0 + k] = st * a + ct * b;
+  }
+}
+
+// Builds the inverses of the shapes listed in h->pc (host keys), in batches whose
+// [B | I] work arrays stay below ~1 GB.
+void build_precond(spm_handle* h) {
+  Precond& P = h->pc;
+  const int S = (int)P.ka.size();
+  std::vector<int64_t> ioff(S);
+  int64_t total = 0;
+  for (int s = 0; s < S; ++s) {
+    ioff[s] = total;
+    total += 4LL * P.kn[s] * P.kn[s];
+  }
+  P.inv = static_cast<float*>(precond_alloc(h, P.inv, (size_t)total * sizeof(float), P.inv_cap));
+  P.ioff = static_cast<int64_t*>(precond_alloc(h, P.ioff, (size_t)S * sizeof(int64_t), P.ioff_cap));
+  SPM_HIP_CHECK(hipMemcpyAsync(P.ioff, ioff.data(), S * sizeof(int64_t), hipMemcpyHostToDevice, h->stream));
+  const int64_t budget = (int64_t)1 << 27;   // doubles of work per batch (1 GiB)
+  int s0 = 0;
+  while (s0 < S) {
+    std::vector<ShapeDesc> batch;
+    int64_t w = 0;
+    int maxn = 0;
+    for (int s = s0; s < S; ++s) {
+      const int64_t need = 8LL * P.kn[s] * P.kn[s];   // m x 2m
+      if (!batch.empty() && w + need > budget) break;
+      ShapeDesc d;
+      d.a = P.ka[s];
+      d.b = P.kb[s];
+      d.n = P.kn[s];
+      d.pad = 0;
+      d.woff = w;
+      d.ioff = ioff[s];
+      batch.push_back(d);
+      w += need;
+      maxn = std::max(maxn, P.kn[s]);
+    }
+    const int nb = (int)batch.size();
+    P.work = static_cast<double*>(precond_alloc(h, P.work, (size_t)w * sizeof(double), P.work_cap));
+    P.desc = static_cast<ShapeDesc*>(precond_alloc(h, P.desc, (size_t)nb * sizeof(ShapeDesc), P.desc_cap));
+    P.status = static_cast<int32_t*>(precond_alloc(h, P.status, (size_t)nb * sizeof(int32_t), P.status_cap));
+    SPM_HIP_CHECK(hipMemcpyAsync(P.desc, batch.data(), nb * sizeof(ShapeDesc), hipMemcpyHostToDevice, h->stream));
+    k_self_block<<<dim3((unsigned)maxn, (unsigned)nb), 256, 0, h->stream>>>(P.desc, P.work);
+    SPM_HIP_CHECK(hipGetLastError());
+    k_gauss_jordan<<<nb, 1024, 0, h->stream>>>(P.desc, P.work, P.status);
+    SPM_HIP_CHECK(hipGetLastError());
+    k_store_inverse<<<dim3((unsigned)(2 * maxn), (unsigned)nb), 256, 0, h->stream>>>(P.desc, P.work, P.inv);
+    SPM_HIP_CHECK(hipGetLastError());
+    std::vector<int32_t> st(nb);
+    SPM_HIP_CHECK(hipMemcpyAsync(st.data(), P.status, nb * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    SPM_HIP_CHECK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < nb; ++k)
+      if (st[k]) throw ApiError(SPM_EINVAL, "singular self block");
+    s0 += nb;
+  }
+  // the work array is only needed while building
+  precond_release_work(h);
+  P.valid = true;
+}
+
+void launch_precond_apply(spm_handle* h, const double* v, double* out, bool with_active) {
+  Precond& P = h->pc;
+  k_precond_apply<<<h->geo.No, 256, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
+                                                    with_active ? h->kr.active : nullptr, v, out);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace spm

@@ -261,11 +261,53 @@ struct Krylov {
   double* dots = nullptr;     // [C] small per-cell reductions
   void* host = nullptr;       // pinned host scratch
   size_t host_bytes = 0;
-  // captured iteration graphs per precision (0: FP64, 1: FP32)
-  hipGraphExec_t graph[2] = {nullptr, nullptr};
-  hipGraph_t graph_src[2] = {nullptr, nullptr};
+  double* z = nullptr;        // [n2] preconditioned matvec input / correction
+  double* z2 = nullptr;       // [n2]
+  // captured iteration graphs: index precision (0: FP64, 1: FP32) + 2 * preconditioned
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t graph_src[4] = {nullptr, nullptr, nullptr, nullptr};
   hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
   int32_t* mask = nullptr;            // [C] scratch mask uploaded from the host
+};
+
+// Learned warm start buffers.
+struct Learned {
+  double* nvec = nullptr;     // [2N] outward normals, SoA
+  double* num = nullptr;      // [C] <r, n> (or <sigma, n>) per cell
+  double* den = nullptr;      // [C] <n, n> per cell
+  double* fit = nullptr;      // [5C] dots of the warm-start fit, then [2C] alpha, beta
+  float* feat = nullptr;      // [No x 33]
+  float* modes = nullptr;     // [No x 128]
+};
+
+// Shape of one self block being built: ellipse semi-axes, nodes, offsets of its
+// [B | I] work matrix and of its FP32 inverse.
+struct ShapeDesc {
+  double a, b;
+  int32_t n;
+  int32_t pad;
+  int64_t woff;
+  int64_t ioff;
+};
+
+// Block preconditioner: one FP32 inverse per distinct shape (a, b, N) of the current
+// particles (kept while the shapes stay the same).
+struct Precond {
+  bool valid = false;
+  std::vector<double> ka, kb;   // distinct shapes, in order of first appearance
+  std::vector<int32_t> kn;
+  int32_t* pshape = nullptr;    // [No] shape of each particle
+  size_t pshape_cap = 0;
+  int64_t* ioff = nullptr;      // [shapes] offset of each inverse
+  size_t ioff_cap = 0;
+  float* inv = nullptr;         // inverses, (2n)^2 floats each, column-major
+  size_t inv_cap = 0;
+  double* work = nullptr;       // build workspace
+  size_t work_cap = 0;
+  ShapeDesc* desc = nullptr;
+  size_t desc_cap = 0;
+  int32_t* status = nullptr;
+  size_t status_cap = 0;
 };
 
 struct CellHost {
@@ -297,6 +339,9 @@ struct spm_handle {
   spm::CloseList cl;
   spm::Work wk;
   spm::Krylov kr;
+  spm::Learned ln;
+  spm::Precond pc;
+  spm_mlp* net = nullptr;             // borrowed warm-start network
   double min_gap_est = 0.0;
   double wallclock_hz = 1e8;
 
@@ -310,7 +355,28 @@ struct spm_handle {
   double prof_pairs[2] = {0, 0};
 };
 
+// The warm-start network (k_mlp.hip): FP32 master parameters, Adam moments and the
+// activation buffers of the largest batch seen so far.
+struct spm_mlp {
+  hipStream_t stream = nullptr;
+  spm_alloc_fn alloc = nullptr;
+  spm_free_fn free_fn = nullptr;
+  void* alloc_ctx = nullptr;
+  std::string err;
+  float *params = nullptr, *grads = nullptr, *m1 = nullptr, *m2 = nullptr;   // [SPM_MLP_NPARAMS]
+  float* h[3] = {nullptr, nullptr, nullptr};   // hidden activations [cap x 256]
+  float* y = nullptr;                          // output [cap x 128]
+  float* dz[2] = {nullptr, nullptr};           // back-propagated gradients [cap x 256]
+  double* part = nullptr;                      // loss partial sums
+  double* loss = nullptr;                      // [1]
+  int32_t* flag = nullptr;                     // [1] argument check
+  int64_t cap = 0;                             // batch capacity of the buffers
+  int64_t t = 0;                               // Adam step count
+};
+
 namespace spm {
+
+void mlp_forward(spm_mlp* net, hipStream_t s, const float* x, const int32_t* xrow, int64_t B, float* y, int mode);
 
 // --- launch wrappers (defined in the k_*.hip files) --------------------------
 void launch_geometry(spm_handle* h);
@@ -334,6 +400,7 @@ void launch_close_scan(spm_handle* h, int32_t* total_host, int32_t* ntargets_hos
 void launch_close_fill(spm_handle* h);
 void launch_vplus(spm_handle* h, const double* sigma);
 void launch_close_apply(spm_handle* h, const double* sigma, double* T, int precision);
+void launch_self_fix(spm_handle* h, double* T, bool with_active);
 void launch_assemble(spm_handle* h, const double* sigma, double* out);
 void launch_velocities(spm_handle* h, double* vel, double* omega);
 void launch_mu_eff(spm_handle* h, double* mu_eff);
@@ -357,6 +424,20 @@ void launch_disc_impl(spm_handle* h, bool with_active);
 void launch_xi_impl(spm_handle* h, bool with_active);
 void launch_near_impl(spm_handle* h, int precision, bool with_active);
 void launch_close_apply_impl(spm_handle* h, double* T, int precision, bool with_active);
+
+// learned warm start (k_learned.hip) and block preconditioner (k_precond.hip)
+void launch_features(spm_handle* h, float* feat);
+void launch_modes(spm_handle* h, const double* sigma, const double* num, const double* den, float* modes);
+void launch_decode(spm_handle* h, const float* modes, double* sigma);
+void launch_add_normal(spm_handle* h, const double* num, const double* den, double f, double* x);
+void launch_fit_guess(spm_handle* h, const double* dots, double* coef);
+void launch_apply_fit(spm_handle* h, const double* coef, const double* b, const double* z, double* x, double* r);
+void build_precond(spm_handle* h);
+void launch_precond_apply(spm_handle* h, const double* v, double* out, bool with_active);
+void* precond_alloc(spm_handle* h, void* old, size_t bytes, size_t& cap);
+void precond_release_work(spm_handle* h);
+void gm_update_only(spm_handle* h, double* x);   // x += V y (after gm_backsolve)
+void gm_backsolve(spm_handle* h);
 
 }  // namespace spm
 

@@ -21,6 +21,10 @@ LIB_PATH = os.path.join(_HERE, "libspm.so")
 
 SPM_OK, SPM_EINVAL, SPM_EOVERLAP, SPM_ENOCONV, SPM_EHIP, SPM_ENOMEM, SPM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 SPM_FP64, SPM_FP32, SPM_FP32_IR = 0, 1, 2
+SPM_X0_ZERO, SPM_X0_PREVIOUS, SPM_X0_NETWORK = 0, 1, 2
+SPM_PRECOND_NONE, SPM_PRECOND_BLOCK = 0, 1
+SPM_MLP_IN, SPM_MLP_HIDDEN, SPM_MLP_OUT, SPM_MLP_NPARAMS = 33, 256, 128, 173184
+SPM_MLP_BF16, SPM_MLP_FP32 = 0, 1
 _ERRNAMES = {-1: "SPM_EINVAL", -2: "SPM_EOVERLAP", -3: "SPM_ENOCONV", -4: "SPM_EHIP", -5: "SPM_ENOMEM",
              -6: "SPM_ESTATE"}
 
@@ -30,7 +34,8 @@ class spm_config(ctypes.Structure):
                 ("R_proxy", ctypes.c_double), ("m_wall", ctypes.c_int32), ("close_factor", ctypes.c_double),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("min_gap", ctypes.c_double), ("rcond", ctypes.c_double),
-                ("use_graph", ctypes.c_int32), ("poll_every", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("x0", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("learned_max_iter", ctypes.c_int32)]
 
 
 class spm_solve_info(ctypes.Structure):
@@ -38,7 +43,8 @@ class spm_solve_info(ctypes.Structure):
                 ("fp32_matvecs", ctypes.c_int32), ("n_close_pairs", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("seconds_setup", ctypes.c_double), ("seconds_solve", ctypes.c_double),
-                ("seconds_readout", ctypes.c_double)]
+                ("seconds_readout", ctypes.c_double), ("fallback", ctypes.c_int32),
+                ("first_iterations", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,6 +106,23 @@ def lib():
         "spm_set_launch": (ctypes.c_int, [P, ctypes.c_int32, i32]),
         "spm_profile": (ctypes.c_int, [P, ctypes.c_int32]),
         "spm_profile_read": (ctypes.c_int, [P, ctypes.c_int32, d, i64, d]),
+        "spm_precond_apply": (ctypes.c_int, [P, P, P]),
+        "spm_features": (ctypes.c_int, [P, P]),
+        "spm_density_modes": (ctypes.c_int, [P, P, P]),
+        "spm_warm_start": (ctypes.c_int, [P, P, P]),
+        "spm_set_network": (ctypes.c_int, [P, P]),
+        "spm_learned_guess": (ctypes.c_int, [P, P]),
+        "spm_step_record": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_int32, d, d, d, d,
+                                           ctypes.POINTER(spm_solve_info), P, P]),
+        "spm_mlp_create": (ctypes.c_int, [ctypes.POINTER(P), P, ALLOC_FN, FREE_FN, P]),
+        "spm_mlp_destroy": (None, [P]),
+        "spm_mlp_last_error": (ctypes.c_char_p, [P]),
+        "spm_mlp_set_params": (ctypes.c_int, [P, P]),
+        "spm_mlp_get_params": (ctypes.c_int, [P, P]),
+        "spm_mlp_forward": (ctypes.c_int, [P, P, ctypes.c_int64, P, ctypes.c_int32]),
+        "spm_mlp_loss_grad": (ctypes.c_int, [P, P, P, ctypes.c_int64, ctypes.c_int32, P, d]),
+        "spm_mlp_train": (ctypes.c_int, [P, P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_float, ctypes.c_int32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -123,12 +146,106 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def _ptr(t):
+def _ptr(t, dtype=torch.float64):
     if t is None:
         return None
-    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
-        raise TypeError("expected a contiguous float64 CUDA tensor")
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _fptr(t):
+    return _ptr(t, torch.float32)
+
+
+def _iptr(t):
+    return _ptr(t, torch.int32)
+
+
+class _TorchAlloc:
+    """Allocator callbacks backed by torch's caching allocator."""
+
+    def __init__(self, device):
+        self.device = device
+        self.blocks = {}
+
+        def _alloc(nbytes, stream, ctx):
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+            self.blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def _free(ptr, stream, ctx):
+            self.blocks.pop(ptr, None)
+
+        self.alloc_cb = ALLOC_FN(_alloc)
+        self.free_cb = FREE_FN(_free)
+
+
+class MLP:
+    """The warm-start network (spm_mlp_*): parameters, forward, gradients, Adam training."""
+
+    def __init__(self, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a HIP device is required (no CPU fallback)")
+        self.device = torch.device(device)
+        self._mem = _TorchAlloc(self.device)
+        self._stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = lib().spm_mlp_create(ctypes.byref(h), ctypes.c_void_p(self._stream.cuda_stream), self._mem.alloc_cb,
+                                  self._mem.free_cb, None)
+        if rc != 0:
+            raise SpmError(rc, "spm_mlp_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().spm_mlp_destroy(self.h)
+            self.h = None
+            self._mem.blocks.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise SpmError(rc, lib().spm_mlp_last_error(self.h).decode())
+
+    def set_params(self, params):
+        p = params.to(device=self.device, dtype=torch.float32).contiguous()
+        if p.numel() != SPM_MLP_NPARAMS:
+            raise ValueError("wrong parameter count")
+        self._check(lib().spm_mlp_set_params(self.h, _fptr(p)))
+
+    def get_params(self):
+        p = torch.empty(SPM_MLP_NPARAMS, dtype=torch.float32, device=self.device)
+        self._check(lib().spm_mlp_get_params(self.h, _fptr(p)))
+        return p
+
+    def forward(self, x, mode=SPM_MLP_BF16):
+        x = x.to(device=self.device, dtype=torch.float32).contiguous()
+        y = torch.empty(x.shape[0], SPM_MLP_OUT, dtype=torch.float32, device=self.device)
+        self._check(lib().spm_mlp_forward(self.h, _fptr(x), x.shape[0], _fptr(y), int(mode)))
+        return y
+
+    def loss_grad(self, x, t, mode=SPM_MLP_BF16):
+        x = x.to(device=self.device, dtype=torch.float32).contiguous()
+        t = t.to(device=self.device, dtype=torch.float32).contiguous()
+        g = torch.empty(SPM_MLP_NPARAMS, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        self._check(lib().spm_mlp_loss_grad(self.h, _fptr(x), _fptr(t), x.shape[0], int(mode), _fptr(g),
+                                            ctypes.byref(loss)))
+        return loss.value, g
+
+    def train(self, x, t, idx, batch, lr, mode=SPM_MLP_BF16):
+        """Adam steps over the minibatches idx.view(-1, batch) (device int32)."""
+        nb = idx.numel() // batch
+        losses = torch.empty(nb, dtype=torch.float32, device=self.device)
+        self._check(lib().spm_mlp_train(self.h, _fptr(x), _fptr(t), x.shape[0], _iptr(idx), nb, int(batch),
+                                        float(lr), int(mode), _fptr(losses)))
+        return losses
 
 
 class Solver:
@@ -139,22 +256,11 @@ class Solver:
             raise RuntimeError("a HIP device is required (no CPU fallback)")
         self.device = torch.device(device)
         self.cfg = default_config(**cfg)
-        self._blocks = {}
+        self._mem = _TorchAlloc(self.device)
         self._stream = torch.cuda.current_stream(self.device)
-
-        def _alloc(nbytes, stream, ctx):
-            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
-            self._blocks[t.data_ptr()] = t
-            return t.data_ptr()
-
-        def _free(ptr, stream, ctx):
-            self._blocks.pop(ptr, None)
-
-        self._alloc_cb = ALLOC_FN(_alloc)
-        self._free_cb = FREE_FN(_free)
         h = ctypes.c_void_p()
         rc = lib().spm_create(ctypes.byref(h), ctypes.byref(self.cfg), ctypes.c_void_p(self._stream.cuda_stream),
-                              self._alloc_cb, self._free_cb, None)
+                              self._mem.alloc_cb, self._mem.free_cb, None)
         if rc != 0:
             raise SpmError(rc, "spm_create failed (bad config?)")
         self.h = h
@@ -165,7 +271,7 @@ class Solver:
         if getattr(self, "h", None):
             lib().spm_destroy(self.h)
             self.h = None
-            self._blocks.clear()
+            self._mem.blocks.clear()
 
     def __del__(self):
         try:
@@ -283,15 +389,55 @@ class Solver:
         self._check(lib().spm_effective_viscosity(self.h, _ptr(sigma), _ptr(mu)))
         return mu
 
-    def step(self, dt, n_steps, t, centers, theta):
+    def step(self, dt, n_steps, t, centers, theta, record=False):
         t_io = np.array([float(t)])
         c = np.ascontiguousarray(np.asarray(centers, dtype=float).reshape(-1)).copy()
         th = np.ascontiguousarray(theta, dtype=float).copy()
         mus = np.zeros(int(n_steps))
         infos = (spm_solve_info * int(n_steps))()
-        self._check(lib().spm_step(self.h, float(dt), int(n_steps), _dp(t_io), _dp(c), _dp(th), _dp(mus), infos))
-        return {"t": float(t_io[0]), "centers": c.reshape(-1, 2), "theta": th, "mu_eff": mus,
-                "infos": [i.as_dict() for i in infos]}
+        feat = tgt = None
+        if record:
+            feat = torch.empty(int(n_steps), self.No, SPM_MLP_IN, dtype=torch.float32, device=self.device)
+            tgt = torch.empty(int(n_steps), self.No, SPM_MLP_OUT, dtype=torch.float32, device=self.device)
+        self._check(lib().spm_step_record(self.h, float(dt), int(n_steps), _dp(t_io), _dp(c), _dp(th), _dp(mus),
+                                          infos, _fptr(feat), _fptr(tgt)))
+        out = {"t": float(t_io[0]), "centers": c.reshape(-1, 2), "theta": th, "mu_eff": mus,
+               "infos": [i.as_dict() for i in infos]}
+        if record:
+            out["features"] = feat
+            out["targets"] = tgt
+        return out
+
+    # --- block preconditioner and learned warm start ----------------------------
+    def precond_apply(self, v):
+        out = self._vec(2 * self.N)
+        self._check(lib().spm_precond_apply(self.h, _ptr(v), _ptr(out)))
+        return out
+
+    def features(self):
+        f = torch.empty(self.No, SPM_MLP_IN, dtype=torch.float32, device=self.device)
+        self._check(lib().spm_features(self.h, _fptr(f)))
+        return f
+
+    def density_modes(self, sigma):
+        m = torch.empty(self.No, SPM_MLP_OUT, dtype=torch.float32, device=self.device)
+        self._check(lib().spm_density_modes(self.h, _ptr(sigma), _fptr(m)))
+        return m
+
+    def warm_start(self, modes):
+        out = self._vec(2 * self.N)
+        m = modes.to(device=self.device, dtype=torch.float32).contiguous()
+        self._check(lib().spm_warm_start(self.h, _fptr(m), _ptr(out)))
+        return out
+
+    def set_network(self, net):
+        self._net = net
+        self._check(lib().spm_set_network(self.h, None if net is None else net.h))
+
+    def learned_guess(self):
+        out = self._vec(2 * self.N)
+        self._check(lib().spm_learned_guess(self.h, _ptr(out)))
+        return out
 
     # --- stage entry points ----------------------------------------------------
     def near_traction(self, sigma, precision=SPM_FP64):

@@ -240,6 +240,16 @@ def ensemble_cells(n_cells=64, base_seed=1000, h_star=None, lo=4, hi=50, phi=0.3
     return cells
 
 
+def trajectory_cell(seed, lo=25, hi=100, phi=0.3, h_star=None):
+    """Initial state of a time-stepping run: n ~ U{lo..hi} ellipses (from the seed) at
+    area fraction phi in an unskewed cell (s(0) = 0), node counts from the 25-ellipse
+    node density."""
+    if h_star is None:
+        h_star = c1_h_star()
+    n = int(np.random.default_rng(seed).integers(lo, hi + 1))
+    return random_ellipses(n, phi, seed, h_star=h_star, skew=0.0, name=f"trajectory{seed}")
+
+
 def two_ellipses(d, n_nodes=64, skew=0.0):
     """Semi-axes (0.25, 0.125) and (0.125, 0.25) with boundary gap d along x."""
     sep = d + 0.375

@@ -123,6 +123,21 @@ def test_full_operator(case):
     assert np.abs(b - op.rhs(prob)).max() < 1e-15
 
 
+def test_fp32_operator(case):
+    """The FP32 operator (FP32 near sum with FP32 accumulation, close pairs and own-curve
+    terms corrected in FP64, everything else FP64) against the oracle's FP64 operator.
+    Bound 1e-5 relative: u32 = 6e-8 times the largest amplification left, |x| / |r| of
+    a pair just outside the close lists (about 1/(10 h) ~ 1e2 here)."""
+    name, wl, prob = case
+    s = _solver(wl)
+    sig = W.random_density(prob.N, seed=12)
+    ref = op.apply(prob, sig)
+    y = _n(s.apply(_t(sig), precision=_spm().SPM_FP32))
+    err = np.abs(y - ref).max() / np.abs(ref).max()
+    print(f"[{name}] FP32 apply rel err {err:.2e}")
+    assert err < 1e-5
+
+
 def test_solve(case):
     name, wl, prob = case
     s = _solver(wl)
