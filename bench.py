@@ -96,7 +96,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp32_ir", "fp64"], default="fp32_ir")
+    ap.add_argument("--precision", choices=["fp32_ir", "fp32_relaxed", "fp64"], default=None,
+                    help="solver precision (default: fp32_ir for the 200-ellipse cell, fp32_relaxed for the "
+                         "ensemble)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed FP64-vs-FP32+IR comparison solves")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
@@ -106,6 +108,8 @@ def main():
                     help="ellipses200: the 200-ellipse cell (default); ensemble64: 64 independent cells in one "
                          "launch; learned: time stepping with the trained warm-start network")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = "fp32_relaxed" if args.workload == "ensemble64" else "fp32_ir"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
               file=sys.stderr)
@@ -133,7 +137,7 @@ def main():
     t0 = time.perf_counter()
     wl = W.ellipses_200()
     log(f"[bench] workload {wl['name']} generated in {time.perf_counter() - t0:.1f}s")
-    prec = spm.SPM_FP32_IR if args.precision == "fp32_ir" else spm.SPM_FP64
+    prec = {"fp32_relaxed": spm.SPM_FP32_RELAXED, "fp32_ir": spm.SPM_FP32_IR, "fp64": spm.SPM_FP64}[args.precision]
     s = spm.Solver("cuda:0", precision=prec)
     s.set_workload(wl)
     N = s.N
@@ -156,26 +160,35 @@ def main():
         infos.append(r["info"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kern = 1 if prec == spm.SPM_FP32_IR else 0
-    prof = s.profile_read(kern)
+    profs = [s.profile_read(0), s.profile_read(1)]
     s.profile(False)
     for k, i in enumerate(infos):
         log(f"[bench] step {k}: {i}")
     matvecs = sum(i["fp64_matvecs"] + i["fp32_matvecs"] for i in infos)
     value = matvecs * pairs_per_matvec / elapsed
-    avg_ms = prof["ms"] / max(prof["launches"], 1)
-    achieved = FLOP_PER_PAIR * pairs_per_matvec / (avg_ms * 1e-3) / 1e12
-    dt = "fp32" if kern == 1 else "fp64"
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK[dt], "unit": "TFLOP/s",
+
+    def roof(kern):
+        prof = profs[kern]
+        avg_ms = prof["ms"] / max(prof["launches"], 1)
+        achieved = FLOP_PER_PAIR * pairs_per_matvec / (avg_ms * 1e-3) / 1e12
+        dt = "fp32" if kern == 1 else "fp64"
+        return {"bound": "alu", "achieved": achieved, "peak": PEAK[dt], "unit": "TFLOP/s",
                 "frac": achieved / PEAK[dt], "traffic": measured_traffic() if kern == 1 else None,
                 "kernel": f"k_near<{'float' if kern else 'double'}> (near-image traction sum, {dt})",
-                "avg_launch_ms": avg_ms, "launches": prof["launches"],
+                "avg_launch_ms": avg_ms, "launches": prof["launches"], "total_ms": prof["ms"],
                 "pairs_per_launch": pairs_per_matvec, "launch_shape": tune["fp32" if kern else "fp64"]}
+
+    # the dominant kernel is the near sum of the precision that took the most time
+    kern = 0 if profs[0]["ms"] >= profs[1]["ms"] else 1
+    roofline = roof(kern)
+    other = roof(1 - kern) if profs[1 - kern]["launches"] > 0 else None
 
     extra = {}
     if not args.no_compare:
-        for name, p in (("fp64", spm.SPM_FP64), ("fp32_ir", spm.SPM_FP32_IR)):
-            c = spm.Solver("cuda:0", precision=p)
+        for name, p, pc in (("fp64", spm.SPM_FP64, 0), ("fp32_ir", spm.SPM_FP32_IR, 0),
+                            ("fp32_relaxed", spm.SPM_FP32_RELAXED, 0), ("fp64_precond", spm.SPM_FP64, 1),
+                            ("fp32_relaxed_precond", spm.SPM_FP32_RELAXED, 1)):
+            c = spm.Solver("cuda:0", precision=p, precond=pc)
             c.set_workload(wl)
             for pr, key in ((spm.SPM_FP64, "fp64"), (spm.SPM_FP32, "fp32")):
                 c.set_launch(pr, **tune[key])
@@ -200,11 +213,11 @@ def main():
     out = {"metric": "Stokes matvec pair-evals/s (whole mobility solve to 1e-10 FP64 residual)",
            "value": value, "unit": "pair-evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32+f64" if kern == 1 else "f64", "data": "synthetic",
+           "vs_baseline": None, "dtype": "f64" if prec == spm.SPM_FP64 else "f32+f64", "data": "synthetic",
            "config": {"workload": wl["name"], "N": N, "particles": s.No, "nodes_per_particle": 256,
                       "precision": args.precision, "tol": 1e-10, "images": "3x3", "proxies": 32,
                       "wall_points": 24, "close_factor": 10},
-           "roofline": roofline, "cpu_baseline": cpu, **extra}
+           "roofline": roofline, "roofline_other_precision": other, "cpu_baseline": cpu, **extra}
     print(json.dumps(out), flush=True)
 
 
@@ -229,7 +242,8 @@ def bench_ensemble(args):
     Ns = np.array([int(np.sum(c["n_nodes"])) for c in cells])
     log(f"[bench] 64 cells generated in {time.perf_counter() - t0:.1f}s: N_c {Ns.min()}..{Ns.max()}, "
         f"total {Ns.sum()}, particles {sum(len(c['theta']) for c in cells)}")
-    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_IR)
+    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_RELAXED if args.precision == "fp32_relaxed" else
+                   {"fp32_ir": spm.SPM_FP32_IR, "fp64": spm.SPM_FP64}[args.precision])
     s.set_cells(cells)
     tune = s.autotune(args.tune_cache)
     log(f"[bench] autotune: {tune}")
@@ -266,13 +280,13 @@ def bench_ensemble(args):
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(cells[int(np.argmax(Ns))])
-    out = {"metric": "ensemble cell solves/s (64 independent cells, FP32+IR to 1e-10 FP64 residual)",
+    out = {"metric": f"ensemble cell solves/s (64 independent cells, {args.precision} to 1e-10 FP64 residual)",
            "value": 64 * args.steps / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "ensemble_64_cells_phi0.3", "cells": 64, "nodes_total": int(Ns.sum()),
                       "nodes_min": int(Ns.min()), "nodes_max": int(Ns.max()), "pairs_per_matvec": pairs,
-                      "precision": "fp32_ir", "tol": 1e-10},
+                      "precision": args.precision, "tol": 1e-10},
            "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99),
                           "max": 1e3 * max(lat)},
            "iterations": {"p50": percentile([i["iterations"] for i in infos], 50),
@@ -293,8 +307,9 @@ def bench_learned(args):
     on the device (BF16 matrix-core kernels, Adam). Evaluation: held-out trajectories
     (seeds 6000..6002), `--eval-steps` steps each, every variant to the FP64 residual
     1e-10: (i) FP64 from zero, (ii) FP64 from the previous step, (iii) FP32+IR from zero,
-    (iv) network warm start + block preconditioner in FP64 and in FP32+IR. value = steps
-    per second of the fastest learned variant; the others are reported beside it."""
+    (iv) network warm start + block preconditioner in FP64, FP32+IR and relaxed FP32; each
+    of the ingredients alone beside them. value = steps per second of the fastest learned
+    variant; the others are reported beside it."""
     import numpy as np
     import torch
 
@@ -313,6 +328,7 @@ def bench_learned(args):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     Z, P, NW, B, IR = spm.SPM_X0_ZERO, spm.SPM_X0_PREVIOUS, spm.SPM_X0_NETWORK, spm.SPM_PRECOND_BLOCK, spm.SPM_FP32_IR
+    RX = spm.SPM_FP32_RELAXED
     variants = [("fp64_zero", dict(x0=Z)),
                 ("fp64_previous", dict(x0=P)),
                 ("fp64_network", dict(x0=NW)),
@@ -320,7 +336,10 @@ def bench_learned(args):
                 ("fp64_network_precond", dict(x0=NW, precond=B)),
                 ("fp32ir_zero", dict(x0=Z, precision=IR)),
                 ("fp32ir_zero_precond", dict(x0=Z, precond=B, precision=IR)),
-                ("fp32ir_network_precond", dict(x0=NW, precond=B, precision=IR))]
+                ("fp32ir_network_precond", dict(x0=NW, precond=B, precision=IR)),
+                ("fp32relaxed_zero", dict(x0=Z, precision=RX)),
+                ("fp32relaxed_zero_precond", dict(x0=Z, precond=B, precision=RX)),
+                ("fp32relaxed_network_precond", dict(x0=NW, precond=B, precision=RX))]
     res = {}
     for name, cfg in variants:
         its, secs, steps, res_max, fb = [], 0.0, 0, 0.0, 0
@@ -343,7 +362,8 @@ def bench_learned(args):
         res[name] = {"steps_per_s": steps / secs, "ms_per_step": 1e3 * secs / steps,
                      "iterations_mean": float(np.mean(its)), "max_rel_residual": res_max, "fallbacks": fb}
         log(f"[bench] {name}: {res[name]}")
-    best = max(("fp64_network_precond", "fp32ir_network_precond"), key=lambda k: res[k]["steps_per_s"])
+    best = max(("fp64_network_precond", "fp32ir_network_precond", "fp32relaxed_network_precond"),
+               key=lambda k: res[k]["steps_per_s"])
     out = {"metric": "time steps/s with the learned warm start + block preconditioner (FP64 residual 1e-10)",
            "value": res[best]["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": 3 * eval_steps,
            "warmup": 3, "ms_per_step": res[best]["ms_per_step"], "higher_is_better": True, "scaling": "weak",

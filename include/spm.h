@@ -60,6 +60,8 @@ extern "C" {
 #define SPM_FP64 0         /* every sum in FP64 */
 #define SPM_FP32 1         /* near-image sum in FP32 with FP32 accumulation; the rest FP64 */
 #define SPM_FP32_IR 2      /* solve: FP64 iterative refinement around FP32-near-sum GMRES */
+#define SPM_FP32_RELAXED 3 /* solve: one FP64 GMRES whose operator products switch to the FP32
+                              near sum once the residual estimate is below cfg.inner_tol */
 
 #define SPM_X0_ZERO 0      /* initial guess of a solve without sigma0: zero */
 #define SPM_X0_PREVIOUS 1  /* spm_step: the previous step's density (first step: zero) */
@@ -81,8 +83,9 @@ typedef struct {
   double close_factor;  /* close-evaluation threshold in node spacings [10] (Sec. 6.3 remark) */
   double tol;           /* relative residual of the solve [1e-10] */
   int32_t max_iter;     /* GMRES iteration cap per Krylov solve [500] */
-  int32_t precision;    /* SPM_FP64 or SPM_FP32_IR for spm_solve [SPM_FP64] */
-  double inner_tol;     /* inner relative tolerance of SPM_FP32_IR [1e-5] */
+  int32_t precision;    /* SPM_FP64, SPM_FP32_IR or SPM_FP32_RELAXED for spm_solve [SPM_FP64] */
+  double inner_tol;     /* SPM_FP32_IR: inner relative tolerance; SPM_FP32_RELAXED: residual
+                           estimate below which products use the FP32 near sum [1e-5] */
   double min_gap;       /* reject geometries with a periodic boundary gap below this [0] */
   double rcond;         /* proxy pseudo-inverse relative cutoff [1e-14] */
   int32_t use_graph;    /* replay one captured GMRES iteration as a HIP graph [1] */

@@ -23,7 +23,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import close, near, periodizer
+from . import close, dilated, near, periodizer
 from .geometry import Geometry, build_geometry
 
 
@@ -37,6 +37,7 @@ class Config:
     close_factor: float = 10.0
     rcond: float = 1e-14
     image_range: int = 1
+    near_set: str = "3x3"   # "3x3": 3x3 images of whole particles; "dilated": the U~ set of Sec. 4.2
 
 
 @dataclass
@@ -58,6 +59,10 @@ class Problem:
 def make_problem(wl, **kw) -> Problem:
     cfg = Config(**{**{"mu": wl.get("mu", 1.0), "gamma": wl.get("gamma", 1.0)}, **kw})
     g = build_geometry(wl)
+    if cfg.near_set not in ("3x3", "dilated"):
+        raise ValueError(cfg.near_set)
+    if cfg.near_set == "dilated" and not dilated.max_extent_ok(g, cfg.close_factor):
+        raise ValueError("particles too large for the dilated-cell near set")
     W = periodizer.walls(g, cfg.m)
     P = periodizer.proxies(g, cfg.M, cfg.R)
     Q = periodizer.build_Q(g, W, P, cfg.mu)
@@ -81,18 +86,30 @@ def proxy_strengths(prob, sigma2):
     g = prob.geom
     f = near.forces(g, sigma2)
     F = f.sum(0)
-    d = periodizer.discrepancy(g, prob.W, f, prob.cfg.mu, prob.cfg.image_range)
+    if prob.cfg.near_set == "dilated":
+        d = dilated.discrepancy(g, prob.W, f, prob.cfg.mu)
+    else:
+        d = periodizer.discrepancy(g, prob.W, f, prob.cfg.mu, prob.cfg.image_range)
     return prob.Qpinv @ (periodizer.g0_vector(g, prob.W, F) - d), d, F
+
+
+def targets(prob):
+    """Where the periodic sums are evaluated for each node: the node itself (3x3 set) or
+    the node wrapped into the cell (U~ set, whose near sum holds for targets in U)."""
+    return dilated.wrap_nodes(prob.geom) if prob.cfg.near_set == "dilated" else prob.geom.x
 
 
 def apply_K(prob, sigma2, parts=False):
     """Unpinned K sigma as (N, 2) (and its pieces if parts)."""
     g = prob.geom
-    Tn = near.near_traction(g, sigma2, prob.cfg.image_range)
+    if prob.cfg.near_set == "dilated":
+        Tn = dilated.near_traction_fast(g, sigma2)
+    else:
+        Tn = near.near_traction(g, sigma2, prob.cfg.image_range)
     Ts = near.self_term(g, sigma2)
     dT = close.close_correction(g, sigma2, prob.pairs, prob.cfg.image_range)
     xi, d, F = proxy_strengths(prob, sigma2)
-    Tc = periodizer.correction_traction(prob.P, xi, g.x, g.n)
+    Tc = periodizer.correction_traction(prob.P, xi, targets(prob), g.n)
     K = Tn + Ts + dT + Tc
     if parts:
         return K, {"near": Tn, "self": Ts, "close": dT, "corr": Tc, "xi": xi, "g": d, "F": F}

@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import _clib, near, periodizer
+from . import _clib, dilated, near, periodizer
 from .operator import proxy_strengths, to2
 
 
@@ -34,7 +34,10 @@ def velocities(prob, sigma):
     s2 = to2(np.asarray(sigma, dtype=np.float64))
     f = near.forces(g, s2)
     xi, _, _ = proxy_strengths(prob, s2)
-    un, vn = _clib.stokeslet_velocity(g.centers, g.x, f, g.shifts(prob.cfg.image_range), prob.cfg.mu)
+    if prob.cfg.near_set == "dilated":
+        un, vn = dilated.near_velocity(g, f, g.centers, prob.cfg.mu)
+    else:
+        un, vn = _clib.stokeslet_velocity(g.centers, g.x, f, g.shifts(prob.cfg.image_range), prob.cfg.mu)
     uc = periodizer.correction_velocity(prob.P, xi, g.centers, prob.cfg.mu)
     uc0 = periodizer.correction_velocity(prob.P, xi, g.cU[None, :], prob.cfg.mu)
     vc = periodizer.correction_vorticity(prob.P, xi, g.centers, prob.cfg.mu)
@@ -62,7 +65,12 @@ def mu_eff_wall(prob, sigma, nq=64):
     xq = g.cU - 0.5 * g.e2 + (0.5 * t)[:, None] * g.e1
     wq = 0.5 * wt * np.linalg.norm(g.e1)
     nD = np.repeat(np.array([[0.0, 1.0]]), nq, axis=0)
-    Tn = _clib.near_traction(xq, nD, g.x, f, g.shifts(prob.cfg.image_range))
+    if prob.cfg.near_set == "dilated":
+        _, pts, _ = dilated.image_sources(g)
+        src, _, _ = dilated.image_sources(g)
+        Tn = _clib.near_traction(xq, nD, pts, f[src], np.zeros((1, 2)))
+    else:
+        Tn = _clib.near_traction(xq, nD, g.x, f, g.shifts(prob.cfg.image_range))
     Tc = periodizer.correction_traction(prob.P, xi, xq, nD)
     T1 = Tn[:, 0] + Tc[:, 0]
     return prob.cfg.mu + (wq * T1).sum() / (prob.cfg.gamma * np.linalg.norm(g.e1))

@@ -313,7 +313,7 @@ void alloc_krylov(spm_handle* h) {
   ensure(h, K.active, C);
   ensure(h, K.kdone, C);
   ensure(h, K.mask, C);
-  ensure(h, K.stamp, C + 1);
+  ensure(h, K.stamp, C + 2);
   ensure(h, K.jdev, 2);
   ensure(h, K.part, (size_t)std::max(1, K.nseg) * (kmax + 1));
   ensure(h, K.tmp, n2);
@@ -593,30 +593,58 @@ void upload_cell_arrays(spm_handle* h, const std::vector<double>& bn, const std:
 
 // GMRES cycle on V_0 = r for the cells in `act` (others untouched); x += correction.
 // Returns the Krylov iterations of every cell.
+//
+// relax_at > 0 (FP64 cycles only): once every active cell's residual estimate is at or
+// below relax_at (relative to |b|), the remaining iterations apply the operator with the
+// FP32 near sum. In GMRES with inexact products, the error allowed in the k-th product
+// grows like tol / |r_k|, so the late iterations tolerate FP32 sums while the early
+// ones, which set the leading digits, keep FP64. *switched_at (if given) receives the
+// iteration index of the switch (-1 if none).
 std::vector<int32_t> krylov_cycle(spm_handle* h, int precision, bool pc, double* x, const std::vector<double>& bn,
-                                  const std::vector<double>& tol, const std::vector<int32_t>& act, int maxit) {
+                                  const std::vector<double>& tol, const std::vector<int32_t>& act, int maxit,
+                                  double relax_at = 0.0, int* switched_at = nullptr) {
   Krylov& K = h->kr;
   const int C = h->geo.C;
   upload_cell_arrays(h, bn, tol, act);
+  gm_stamp_cycle(h);
   gm_start(h);
-  int32_t* hj = host_scratch<int32_t>(h, 2);
+  // pinned host scratch: jdev [2], active [C], (padding to 8 bytes), res [C] doubles
+  int32_t* hj = host_scratch<int32_t>(h, 4 + 3 * (size_t)C);
+  int32_t* hact = hj + 2;
+  double* hres = reinterpret_cast<double*>(hj + 2 + C + (C & 1));
   download(h, hj, K.jdev, 2 * sizeof(int32_t));
   maxit = std::max(0, std::min(maxit, K.kmax));
   const bool graph = h->cfg.use_graph != 0 && !h->prof;
   const int poll = std::max(1, h->cfg.poll_every);
-  int done = 0;
+  int cur = precision;
+  bool relax = relax_at > 0.0 && precision == SPM_FP64;
+  if (switched_at) *switched_at = -1;
   if (hj[1] > 0) {
-    hipGraphExec_t ge = graph ? iteration_graph(h, precision, pc) : nullptr;
+    hipGraphExec_t ge = graph ? iteration_graph(h, cur, pc) : nullptr;
     for (int it = 0; it < maxit; ++it) {
       if (graph)
         SPM_HIP_CHECK(hipGraphLaunch(ge, h->stream));
       else
-        iteration(h, precision, pc);
-      ++done;
+        iteration(h, cur, pc);
       if ((it + 1) % poll == 0 || it + 1 == maxit) {
         SPM_HIP_CHECK(hipMemcpyAsync(hj, K.jdev, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+        if (relax) {
+          SPM_HIP_CHECK(hipMemcpyAsync(hact, K.active, C * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+          SPM_HIP_CHECK(hipMemcpyAsync(hres, K.res, C * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        }
         sync(h);
         if (hj[1] == 0) break;
+        if (relax) {
+          double worst = 0.0;
+          for (int c = 0; c < C; ++c)
+            if (hact[c]) worst = std::max(worst, hres[c]);
+          if (worst <= relax_at) {
+            relax = false;
+            cur = SPM_FP32;
+            if (switched_at) *switched_at = it + 1;
+            if (graph) ge = iteration_graph(h, cur, pc);
+          }
+        }
       }
     }
   }
@@ -633,7 +661,6 @@ std::vector<int32_t> krylov_cycle(spm_handle* h, int precision, bool pc, double*
   int32_t* hk = host_scratch<int32_t>(h, C);
   download(h, hk, K.kdone, C * sizeof(int32_t));
   for (int c = 0; c < C; ++c) kd[c] = act[c] ? hk[c] : 0;
-  (void)done;
   return kd;
 }
 
@@ -786,12 +813,17 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
       int budget = max_iter;
       for (int c = 0; c < C; ++c)
         if (act[c]) budget = std::min(budget, max_iter - st.its[c]);
-      const std::vector<int32_t> kd = krylov_cycle(h, SPM_FP64, pc, sigma, st.bnorm, tl, act, std::max(1, budget));
+      const double relax_at = h->cfg.precision == SPM_FP32_RELAXED ? h->cfg.inner_tol : 0.0;
+      int sw = -1;
+      const std::vector<int32_t> kd =
+          krylov_cycle(h, SPM_FP64, pc, sigma, st.bnorm, tl, act, std::max(1, budget), relax_at, &sw);
       std::vector<int32_t> was = act;
       for (int c = 0; c < C; ++c)
         if (was[c]) {
+          const int k64 = sw < 0 ? kd[c] : std::min(kd[c], sw);
           st.its[c] += kd[c];
-          st.m64[c] += kd[c];
+          st.m64[c] += k64;
+          st.m32[c] += kd[c] - k64;
         }
       residual(h, sigma, was, st);
       if (verbose())
@@ -979,7 +1011,8 @@ int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_
   const spm_config& c = h->cfg;
   if (!(c.mu > 0) || !(c.gamma > 0) || c.M < 4 || c.M > 512 || c.m_wall < 4 || c.m_wall > 256 || !(c.R_proxy > 0.75) ||
       !(c.tol > 0) || c.max_iter < 1 || c.max_iter > 5000 || c.close_factor < 0 ||
-      (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR) || !(c.inner_tol > 0 && c.inner_tol < 1) ||
+      (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR && c.precision != SPM_FP32_RELAXED) ||
+      !(c.inner_tol > 0 && c.inner_tol < 1) ||
       c.poll_every < 1 || c.x0 < SPM_X0_ZERO || c.x0 > SPM_X0_NETWORK ||
       (c.precond != SPM_PRECOND_NONE && c.precond != SPM_PRECOND_BLOCK) || c.learned_max_iter < 0) {
     delete h;

@@ -337,10 +337,22 @@ void gm_stamp_start(spm_handle* h) {
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-// stamp[c] = wall clock for the cells flagged in mask (convergence seen by the host)
+// stamp[C + 1] = wall clock at the start of a Krylov cycle
+__global__ void k_stamp_cycle(unsigned long long* stamp, int C) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) stamp[C + 1] = wall_clock64();
+}
+
+void gm_stamp_cycle(spm_handle* h) {
+  k_stamp_cycle<<<1, 64, 0, h->stream>>>(h->kr.stamp, h->geo.C);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// For the cells flagged in mask (convergence confirmed by the host after a cycle): keep the
+// stamp k_givens wrote when the cell's Krylov iteration stopped in this cycle; a cell that
+// stopped without iterating in this cycle gets the current wall clock.
 __global__ void k_stamp_mask(unsigned long long* stamp, const int32_t* __restrict__ mask, int C) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < C && mask[c] != 0) stamp[c] = wall_clock64();
+  if (c < C && mask[c] != 0 && stamp[c] < stamp[C + 1]) stamp[c] = wall_clock64();
 }
 
 void gm_stamp_mask(spm_handle* h, const int32_t* mask_dev) {

@@ -243,7 +243,8 @@ struct Krylov {
   double* res = nullptr;      // [C] residual estimate |g_{j+1}| / bnorm
   int32_t* active = nullptr;  // [C]
   int32_t* kdone = nullptr;   // [C] Krylov iterations of each cell
-  unsigned long long* stamp = nullptr;  // [C + 1] device wall clock at convergence; [C] = solve start
+  unsigned long long* stamp = nullptr;  // [C + 2] device wall clock at convergence; [C] = solve start,
+                                        // [C + 1] = start of the current Krylov cycle
   int32_t* jdev = nullptr;    // [2]: current j, number of active cells
   double* part = nullptr;     // [nseg x (kmax+1)] dot partials
   int32_t nseg = 0;
@@ -420,6 +421,7 @@ void gm_copy(spm_handle* h, double* dst, const double* src, int64_t n);
 void gm_zero(spm_handle* h, double* dst, int64_t n);
 void gm_stamp_start(spm_handle* h);
 void gm_stamp_mask(spm_handle* h, const int32_t* mask_dev);
+void gm_stamp_cycle(spm_handle* h);
 void launch_disc_impl(spm_handle* h, bool with_active);
 void launch_xi_impl(spm_handle* h, bool with_active);
 void launch_near_impl(spm_handle* h, int precision, bool with_active);

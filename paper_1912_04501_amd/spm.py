@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspm.so")
 
 SPM_OK, SPM_EINVAL, SPM_EOVERLAP, SPM_ENOCONV, SPM_EHIP, SPM_ENOMEM, SPM_ESTATE = 0, -1, -2, -3, -4, -5, -6
-SPM_FP64, SPM_FP32, SPM_FP32_IR = 0, 1, 2
+SPM_FP64, SPM_FP32, SPM_FP32_IR, SPM_FP32_RELAXED = 0, 1, 2, 3
 SPM_X0_ZERO, SPM_X0_PREVIOUS, SPM_X0_NETWORK = 0, 1, 2
 SPM_PRECOND_NONE, SPM_PRECOND_BLOCK = 0, 1
 SPM_MLP_IN, SPM_MLP_HIDDEN, SPM_MLP_OUT, SPM_MLP_NPARAMS = 33, 256, 128, 173184
