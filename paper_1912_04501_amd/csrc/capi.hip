@@ -206,7 +206,15 @@ void build_periodizers(spm_handle* h) {
   ensure(h, P.Q, (size_t)C * 8 * m * 2 * M);
   ensure(h, P.Qp, (size_t)C * 8 * m * 2 * M);
   ensure(h, P.svd_a, (size_t)C * 8 * m * 2 * M);
-  ensure(h, P.svd_v, (size_t)C * 4 * M * M);
+  {
+    // the previous V's warm-start the SVD only for the same number of cells and sizes
+    double* before = P.svd_v;
+    ensure(h, P.svd_v, (size_t)C * 4 * M * M);
+    if (P.svd_v != before || C != P.warm_C || m != P.warm_m || M != P.warm_M) P.warm_ok = false;
+    P.warm_C = C;
+    P.warm_m = m;
+    P.warm_M = M;
+  }
   ensure(h, P.svd_s, (size_t)C * (2 * M + 1));
   std::vector<double> t, w;
   gauss_legendre(m, t, w);
@@ -249,9 +257,9 @@ void build_chunks(spm_handle* h) {
       cc.push_back(c);
     }
     off[c + 1] = (int32_t)s0.size();
-    for (int64_t x = a; x < b; x += 4096) {
+    for (int64_t x = a; x < b; x += 1024) {
       n0.push_back(x);
-      n1.push_back(std::min(b, x + 4096));
+      n1.push_back(std::min(b, x + 1024));
       sc.push_back(c);
     }
     soff[c + 1] = (int32_t)n0.size();
@@ -424,6 +432,7 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   g.No = n;
   g.C = C;
   g.N = h->off[n];
+  g.nmax = *std::max_element(h->nn.begin(), h->nn.end());
   const int64_t N = g.N;
   if (N > (int64_t)1 << 30) throw ApiError(SPM_EINVAL, "too many nodes");
   for (double** p : {&g.x, &g.y, &g.nx, &g.ny, &g.w, &g.kap, &g.tx, &g.ty, &g.xpx, &g.xpy}) ensure(h, *p, N);

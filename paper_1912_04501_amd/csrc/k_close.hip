@@ -26,8 +26,8 @@ __device__ __forceinline__ cplx cinv(cplx a) {
 }
 
 // One block per particle: v+ of the three densities, written to vp[6][N].
-__global__ __launch_bounds__(256) void k_vplus(int64_t N, Geo g, const double* __restrict__ sigma,
-                                               double* __restrict__ vp) {
+__global__ __launch_bounds__(1024) void k_vplus(int64_t N, Geo g, const double* __restrict__ sigma, int L,
+                                                double* __restrict__ vp) {
   __shared__ double s_yr[kMaxNodesPerParticle], s_yi[kMaxNodesPerParticle];
   __shared__ double s_wr[kMaxNodesPerParticle], s_wi[kMaxNodesPerParticle];
   __shared__ double s_ph[6][kMaxNodesPerParticle];
@@ -58,12 +58,15 @@ __global__ __launch_bounds__(256) void k_vplus(int64_t N, Geo g, const double* _
     }
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+  // L lanes per node j: lane `sub` takes k = sub, sub + L, ...; the groups' sums are combined
+  // by a fixed butterfly
+  const int sub = threadIdx.x % L;
+  for (int j = threadIdx.x / L; j < n; j += blockDim.x / L) {
     const double yjr = s_yr[j], yji = s_yi[j];
     double acc[6] = {0, 0, 0, 0, 0, 0};
     double der[6] = {0, 0, 0, 0, 0, 0};
     const double pj[6] = {s_ph[0][j], s_ph[1][j], s_ph[2][j], s_ph[3][j], s_ph[4][j], s_ph[5][j]};
-    for (int k = 0; k < n; ++k) {
+    for (int k = sub; k < n; k += L) {
       if (k == j) continue;
       const cplx u = cmul({s_wr[k], s_wi[k]}, cinv({s_yr[k] - yjr, s_yi[k] - yji}));
       const int dm = j - k >= 0 ? j - k : j - k + n;
@@ -78,6 +81,12 @@ __global__ __launch_bounds__(256) void k_vplus(int64_t N, Geo g, const double* _
         der[2 * d + 1] += dw * s_ph[2 * d + 1][k];
       }
     }
+#pragma unroll
+    for (int d = 0; d < 6; ++d) {
+      acc[d] = group_sum(acc[d], L);
+      der[d] = group_sum(der[d], L);
+    }
+    if (sub != 0) continue;
     const int64_t i = o + j;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -89,7 +98,8 @@ __global__ __launch_bounds__(256) void k_vplus(int64_t N, Geo g, const double* _
 }
 
 void launch_vplus(spm_handle* h, const double* sigma) {
-  k_vplus<<<h->geo.No, 256, 0, h->stream>>>(h->geo.N, h->geo, sigma, h->cl.vp);
+  const int L = lanes_per_row(h->geo.nmax);
+  k_vplus<<<h->geo.No, 1024, 0, h->stream>>>(h->geo.N, h->geo, sigma, L, h->cl.vp);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -234,19 +244,20 @@ void launch_close_apply(spm_handle* h, const double* sigma, double* T, int preci
 // with the near kernel's own per-pair arithmetic, are removed:
 //   T_i += -(1/pi) sum_{k on the curve of i} (a64(i, k) - a32(i, k)).
 // One block per particle, one thread per target.
-__global__ __launch_bounds__(256) void k_self_fix(int64_t N, Geo g, const double* __restrict__ f1,
-                                                  const double* __restrict__ f2, const float* __restrict__ f1f,
-                                                  const float* __restrict__ f2f, const int32_t* __restrict__ active,
-                                                  double* __restrict__ T) {
+__global__ __launch_bounds__(1024) void k_self_fix(int64_t N, Geo g, const double* __restrict__ f1,
+                                                   const double* __restrict__ f2, const float* __restrict__ f1f,
+                                                   const float* __restrict__ f2f, const int32_t* __restrict__ active,
+                                                   int L, double* __restrict__ T) {
   const int q = blockIdx.x;
   if (active != nullptr && active[g.pcell[q]] == 0) return;
   const int o = g.poff[q], n = g.pn[q];
-  for (int k0 = threadIdx.x; k0 < n; k0 += blockDim.x) {
+  const int sub = threadIdx.x % L;
+  for (int k0 = threadIdx.x / L; k0 < n; k0 += blockDim.x / L) {
     const int64_t i = o + k0;
     const double xi = g.x[i], yi = g.y[i], nxi = g.nx[i], nyi = g.ny[i];
     const float xif = g.xf[i], yif = g.yf[i], nxif = g.nxf[i], nyif = g.nyf[i];
     double d1 = 0.0, d2 = 0.0, e1 = 0.0, e2 = 0.0;
-    for (int k = 0; k < n; ++k) {
+    for (int k = sub; k < n; k += L) {
       const int64_t kk = o + k;
       {
         const double dx = xi - g.x[kk], dy = yi - g.y[kk];
@@ -263,14 +274,17 @@ __global__ __launch_bounds__(256) void k_self_fix(int64_t N, Geo g, const double
         e2 += (double)a2;
       }
     }
-    T[i] += -(1.0 / kPi) * (d1 - e1);
-    T[N + i] += -(1.0 / kPi) * (d2 - e2);
+    const double c1 = group_sum(d1 - e1, L), c2 = group_sum(d2 - e2, L);
+    if (sub == 0) {
+      T[i] += -(1.0 / kPi) * c1;
+      T[N + i] += -(1.0 / kPi) * c2;
+    }
   }
 }
 
 void launch_self_fix(spm_handle* h, double* T, bool with_active) {
-  k_self_fix<<<h->geo.No, 256, 0, h->stream>>>(h->geo.N, h->geo, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f,
-                                               with_active ? h->kr.active : nullptr, T);
+  k_self_fix<<<h->geo.No, 1024, 0, h->stream>>>(h->geo.N, h->geo, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f,
+                                                with_active ? h->kr.active : nullptr, lanes_per_row(h->geo.nmax), T);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

@@ -102,23 +102,51 @@ void launch_build_Q(spm_handle* h) {
 // gauge modes of the empty-box problem: constant velocity and pressure) and any
 // singular value below rcond * s_max are dropped:  Q^+ = sum_k v_k u_k^T / s_k.
 // ----------------------------------------------------------------------------
+// One-sided Jacobi SVD of Q (rows x ncol) per cell, one workgroup per cell: columns of
+// A = Q V are rotated in pairs until mutually orthogonal; then s_k = |A_k|, u_k = A_k / s_k.
+// Pairs follow the circle method (column 0 fixed, the others rotate by one position per
+// round), so each round rotates ncol/2 disjoint pairs in parallel. A warm start begins from
+// the previous V of the same cell (A = Q V_prev): any orthogonal start converges to the
+// SVD, and for the slowly changing lattice of a time step it needs few sweeps.
+// LDS_RES: A and V live in LDS for the whole iteration (rows*ncol + ncol^2 <= kJacobiLds).
+constexpr int kJacobiLds = 16384;   // doubles (128 KiB)
+
+__device__ __forceinline__ int circle_col(int k, int round, int n) {
+  return k == 0 ? 0 : 1 + ((k - 1 - round) % (n - 1) + (n - 1)) % (n - 1);
+}
+
+template <bool LDS_RES>
 __global__ __launch_bounds__(1024) void k_jacobi(int rows, int ncol, const double* __restrict__ Q_all,
                                                  double* __restrict__ A_all, double* __restrict__ V_all,
-                                                 double* __restrict__ S_all, int max_sweeps) {
+                                                 double* __restrict__ S_all, int max_sweeps, int warm) {
+  __shared__ double lds[LDS_RES ? kJacobiLds : 1];
+  __shared__ double offmax[1024];
   const int cell = blockIdx.x;
   const double* Q = Q_all + (int64_t)cell * rows * ncol;
-  double* A = A_all + (int64_t)cell * rows * ncol;
-  double* V = V_all + (int64_t)cell * ncol * ncol;
+  double* Ag = A_all + (int64_t)cell * rows * ncol;
+  double* Vg = V_all + (int64_t)cell * ncol * ncol;
   double* S = S_all + (int64_t)cell * (ncol + 1);
-  __shared__ int perm[1024];
-  __shared__ double offmax[1024];
+  double* A = LDS_RES ? lds : Ag;
+  double* V = LDS_RES ? lds + rows * ncol : Vg;
   const int tid = threadIdx.x, nt = blockDim.x;
-  for (int k = tid; k < rows * ncol; k += nt) {
-    const int r = k / ncol, c = k % ncol;
-    A[c * rows + r] = Q[k];
+  // V(:, c) is stored contiguously: V[c * ncol + i]
+  if (warm) {
+    if (LDS_RES)
+      for (int k = tid; k < ncol * ncol; k += nt) V[k] = Vg[k];
+    __syncthreads();
+    for (int k = tid; k < rows * ncol; k += nt) {
+      const int c = k / rows, r = k % rows;
+      double a = 0.0;
+      for (int i = 0; i < ncol; ++i) a += Q[r * ncol + i] * V[c * ncol + i];
+      A[k] = a;
+    }
+  } else {
+    for (int k = tid; k < rows * ncol; k += nt) {
+      const int r = k / ncol, c = k % ncol;
+      A[c * rows + r] = Q[k];
+    }
+    for (int k = tid; k < ncol * ncol; k += nt) V[k] = (k / ncol == k % ncol) ? 1.0 : 0.0;
   }
-  for (int k = tid; k < ncol * ncol; k += nt) V[k] = (k / ncol == k % ncol) ? 1.0 : 0.0;
-  for (int k = tid; k < ncol; k += nt) perm[k] = k;
   __syncthreads();
   const int npair = ncol / 2;
   const int G = nt / npair;  // lanes per pair (power of two, <= 64)
@@ -128,7 +156,7 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rows, int ncol, const doubl
     double local_off = 0.0;
     for (int round = 0; round < ncol - 1; ++round) {
       if (pair < npair) {
-        const int cp = perm[pair], cq = perm[ncol - 1 - pair];
+        const int cp = circle_col(pair, round, ncol), cq = circle_col(ncol - 1 - pair, round, ncol);
         const int p = cp < cq ? cp : cq, q = cp < cq ? cq : cp;
         double al = 0, be = 0, ga = 0;
         for (int r = gl; r < rows; r += G) {
@@ -162,25 +190,20 @@ __global__ __launch_bounds__(1024) void k_jacobi(int rows, int ncol, const doubl
         }
       }
       __syncthreads();
-      // circle method: keep perm[0], rotate the rest by one
-      if (tid == 0) {
-        const int last = perm[ncol - 1];
-        for (int k = ncol - 1; k > 1; --k) perm[k] = perm[k - 1];
-        perm[1] = last;
-      }
-      __syncthreads();
     }
     offmax[tid] = local_off;
     __syncthreads();
-    if (tid == 0) {
-      double mx = 0;
-      for (int k = 0; k < nt; ++k) mx = offmax[k] > mx ? offmax[k] : mx;
-      offmax[0] = mx;
+    for (int o = nt / 2; o > 0; o >>= 1) {
+      if (tid < o) offmax[tid] = offmax[tid + o] > offmax[tid] ? offmax[tid + o] : offmax[tid];
+      __syncthreads();
     }
-    __syncthreads();
     const bool done = offmax[0] <= 1e-15;
     __syncthreads();
     if (done) break;
+  }
+  if (LDS_RES) {
+    for (int k = tid; k < rows * ncol; k += nt) Ag[k] = A[k];
+    for (int k = tid; k < ncol * ncol; k += nt) Vg[k] = V[k];
   }
   for (int c = tid; c < ncol; c += nt) {
     double s = 0;
@@ -232,8 +255,15 @@ void launch_pinv(spm_handle* h) {
   int G = 1;
   while (G * 2 * npair <= 1024 && G < 64) G *= 2;
   const int nt = G * npair;
-  k_jacobi<<<h->geo.C, nt, 0, h->stream>>>(rows, ncol, h->per.Q, h->per.svd_a, h->per.svd_v, h->per.svd_s, 60);
+  const int warm = h->per.warm_ok ? 1 : 0;
+  if ((int64_t)rows * ncol + (int64_t)ncol * ncol <= kJacobiLds)
+    k_jacobi<true><<<h->geo.C, nt, 0, h->stream>>>(rows, ncol, h->per.Q, h->per.svd_a, h->per.svd_v, h->per.svd_s,
+                                                    60, warm);
+  else
+    k_jacobi<false><<<h->geo.C, nt, 0, h->stream>>>(rows, ncol, h->per.Q, h->per.svd_a, h->per.svd_v,
+                                                     h->per.svd_s, 60, warm);
   SPM_HIP_CHECK(hipGetLastError());
+  h->per.warm_ok = true;
   const int n = rows * ncol;
   // every block recomputes the truncation weights of its cell (cheap, ncol <= 1024)
   dim3 grid((unsigned)((n + 255) / 256), (unsigned)h->geo.C);
@@ -313,7 +343,7 @@ void launch_disc(spm_handle* h) { launch_disc_impl(h, false); }
 
 // One block per cell: g = sum of the cell's chunk partials, F = sum of its particles'
 // forces, xi = Q^+ (g0 - g).
-__global__ void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __restrict__ disc_off,
+__global__ __launch_bounds__(1024) void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __restrict__ disc_off,
                      const int32_t* __restrict__ cpoff, const double* __restrict__ disc, const double* __restrict__ pF,
                      const double* __restrict__ Qp_all, const int32_t* __restrict__ active, double* __restrict__ xi_all) {
   __shared__ double gt[8 * 256];
@@ -323,14 +353,19 @@ __global__ void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __r
   const int m = L.m, M = L.M;
   const double* Qp = Qp_all + (int64_t)cell * 2 * M * 8 * m;
   double* xi = xi_all + (int64_t)cell * 2 * M;
-  if (threadIdx.x == 0) {
+  {
+    __shared__ double sc[16];
     double F1 = 0, F2 = 0;
-    for (int q = cpoff[cell]; q < cpoff[cell + 1]; ++q) {
+    for (int q = cpoff[cell] + threadIdx.x; q < cpoff[cell + 1]; q += blockDim.x) {
       F1 += pF[4 * q + 0];
       F2 += pF[4 * q + 1];
     }
-    Fs[0] = F1;
-    Fs[1] = F2;
+    F1 = block_sum(F1, sc);
+    F2 = block_sum(F2, sc);
+    if (threadIdx.x == 0) {
+      Fs[0] = F1;
+      Fs[1] = F2;
+    }
   }
   __syncthreads();
   const double skew = cskew[cell];
@@ -349,16 +384,19 @@ __global__ void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __r
     gt[base + 3 * m + q] = -Fs[1] / (2.0 * l) - s[3];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 2 * M; i += blockDim.x) {
+  // one wave per row of Q+, lanes over its 8m entries
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int i = threadIdx.x >> 6; i < 2 * M; i += nw) {
     double s = 0;
-    for (int r = 0; r < 8 * m; ++r) s += Qp[(int64_t)i * 8 * m + r] * gt[r];
-    xi[i] = s;
+    for (int r = lane; r < 8 * m; r += 64) s += Qp[(int64_t)i * 8 * m + r] * gt[r];
+    s = wave_sum(s);
+    if (lane == 0) xi[i] = s;
   }
 }
 
 void launch_xi_impl(spm_handle* h, bool with_active) {
   const Lat L = lattice_args(h);
-  k_xi<<<h->geo.C, 256, 0, h->stream>>>(L, h->geo.cskew, h->wk.disc_off, h->geo.cpoff, h->wk.disc, h->wk.pF,
+  k_xi<<<h->geo.C, 1024, 0, h->stream>>>(L, h->geo.cskew, h->wk.disc_off, h->geo.cpoff, h->wk.disc, h->wk.pF,
                                         h->per.Qp, with_active ? h->kr.active : nullptr, h->wk.xi);
   SPM_HIP_CHECK(hipGetLastError());
 }
@@ -370,31 +408,45 @@ void launch_xi(spm_handle* h) { launch_xi_impl(h, false); }
 // Self term (limit of the smooth kernel on the curve): -(kappa/2pi) tau (tau . w sigma).
 // Proxy correction (step 4): sum_p G^t(x_i, y_p; n_i) xi_p.
 // ----------------------------------------------------------------------------
-__global__ void k_combine(int64_t N, const int32_t* __restrict__ nsplit, const double* __restrict__ Tpart, Geo g,
-                          const double* __restrict__ sigma, int M, const double* __restrict__ px,
-                          const double* __restrict__ py, const double* __restrict__ xi_all, int with_extra,
-                          double* __restrict__ T) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const int cell = g.ncell[i];
+// Four lanes per target: lane l sums the splits k = l, l+4, ... and the proxies p = l, l+4,
+// ...; the four partial sums are combined by a fixed butterfly (deterministic).
+constexpr int kCombineLanes = 4;
+
+__global__ __launch_bounds__(256) void k_combine(int64_t N, const int32_t* __restrict__ nsplit,
+                                                 const double* __restrict__ Tpart, Geo g,
+                                                 const double* __restrict__ sigma, int M,
+                                                 const double* __restrict__ px, const double* __restrict__ py,
+                                                 const double* __restrict__ xi_all, int with_extra,
+                                                 double* __restrict__ T) {
+  const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = gid / kCombineLanes;
+  const int l = (int)(gid % kCombineLanes);
+  const bool live = i < N;
+  const int64_t ii = live ? i : N - 1;   // idle lanes shadow the last target so shuffles stay uniform
+  const int cell = g.ncell[ii];
   const int S = nsplit[cell];
   double t1 = 0, t2 = 0;
-  for (int k = 0; k < S; ++k) {
-    t1 += Tpart[(int64_t)k * 2 * N + i];
-    t2 += Tpart[(int64_t)k * 2 * N + N + i];
+  for (int k = l; k < S; k += kCombineLanes) {
+    t1 += Tpart[(int64_t)k * 2 * N + ii];
+    t2 += Tpart[(int64_t)k * 2 * N + N + ii];
   }
+  if (with_extra) {
+    const double xx = g.x[ii], yy = g.y[ii], nx = g.nx[ii], ny = g.ny[ii];
+    const double* xi = xi_all + (int64_t)cell * 2 * M;
+    for (int p = l; p < M; p += kCombineLanes) traction_uv(xx - px[p], yy - py[p], nx, ny, xi[p], xi[M + p], t1, t2);
+  }
+#pragma unroll
+  for (int o = kCombineLanes / 2; o > 0; o >>= 1) {
+    t1 += __shfl_xor(t1, o, kCombineLanes);
+    t2 += __shfl_xor(t2, o, kCombineLanes);
+  }
+  if (!live || l != 0) return;
   if (with_extra) {
     const double w = g.w[i], tx = g.tx[i], ty = g.ty[i];
     const double tf = tx * w * sigma[i] + ty * w * sigma[N + i];
     const double ks = -(g.kap[i] / (2.0 * kPi)) * tf;
     t1 += ks * tx;
     t2 += ks * ty;
-    const double xx = g.x[i], yy = g.y[i], nx = g.nx[i], ny = g.ny[i];
-    const double* xi = xi_all + (int64_t)cell * 2 * M;
-    double c1 = 0, c2 = 0;
-    for (int p = 0; p < M; ++p) traction_uv(xx - px[p], yy - py[p], nx, ny, xi[p], xi[M + p], c1, c2);
-    t1 += c1;
-    t2 += c2;
   }
   T[i] = t1;
   T[N + i] = t2;
@@ -403,9 +455,10 @@ __global__ void k_combine(int64_t N, const int32_t* __restrict__ nsplit, const d
 void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision) {
   const int64_t N = h->geo.N;
   const NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
-  k_combine<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, P.nsplit, h->wk.Tpart, h->geo, sigma, h->per.M,
-                                                                h->per.px, h->per.py, h->wk.xi,
-                                                                with_self_corr ? 1 : 0, h->wk.T);
+  const int64_t threads = N * kCombineLanes;
+  k_combine<<<(unsigned)((threads + 255) / 256), 256, 0, h->stream>>>(N, P.nsplit, h->wk.Tpart, h->geo, sigma,
+                                                                     h->per.M, h->per.px, h->per.py, h->wk.xi,
+                                                                     with_self_corr ? 1 : 0, h->wk.T);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

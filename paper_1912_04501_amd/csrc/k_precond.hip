@@ -159,10 +159,11 @@ __global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* 
 
 // One block per particle: out = R (B^-1 (R^T v)) on the particle's nodes. Particles of
 // inactive cells are skipped when active is given.
-__global__ __launch_bounds__(256) void k_precond_apply(Geo g, const int32_t* __restrict__ pshape,
-                                                       const int64_t* __restrict__ ioff, const float* __restrict__ inv,
-                                                       const int32_t* __restrict__ active,
-                                                       const double* __restrict__ v, double* __restrict__ out) {
+__global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __restrict__ pshape,
+                                                        const int64_t* __restrict__ ioff,
+                                                        const float* __restrict__ inv,
+                                                        const int32_t* __restrict__ active, int L,
+                                                        const double* __restrict__ v, double* __restrict__ out) {
   __shared__ double vb[2 * kMaxNodesPerParticle];
   __shared__ double ub[2 * kMaxNodesPerParticle];
   const int q = blockIdx.x;
@@ -178,10 +179,13 @@ __global__ __launch_bounds__(256) void k_precond_apply(Geo g, const int32_t* __r
   }
   __syncthreads();
   const float* M = inv + ioff[pshape[q]];
-  for (int r = threadIdx.x; r < m; r += blockDim.x) {
+  // L lanes per row, each over the columns c = sub, sub + L, ...
+  const int sub = threadIdx.x % L;
+  for (int r = threadIdx.x / L; r < m; r += blockDim.x / L) {
     double acc = 0.0;
-    for (int c = 0; c < m; ++c) acc += (double)M[(int64_t)c * m + r] * vb[c];
-    ub[r] = acc;
+    for (int c = sub; c < m; c += L) acc += (double)M[(int64_t)c * m + r] * vb[c];
+    acc = group_sum(acc, L);
+    if (sub == 0) ub[r] = acc;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -250,8 +254,9 @@ void build_precond(spm_handle* h) {
 
 void launch_precond_apply(spm_handle* h, const double* v, double* out, bool with_active) {
   Precond& P = h->pc;
-  k_precond_apply<<<h->geo.No, 256, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
-                                                    with_active ? h->kr.active : nullptr, v, out);
+  k_precond_apply<<<h->geo.No, 1024, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
+                                                     with_active ? h->kr.active : nullptr,
+                                                     lanes_per_row(2 * h->geo.nmax), v, out);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

@@ -114,6 +114,20 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Lanes that share one row of a per-particle loop: the largest power of two <= 16 with
+// n_max * lanes <= 1024 (a 1024-thread block covers a whole particle in one pass).
+inline int lanes_per_row(int nmax) {
+  int L = 1;
+  while (L < 16 && 2 * L * nmax <= 1024) L *= 2;
+  return L;
+}
+
+// Sum over the `width` lanes of a group (a power of two dividing 64), fixed butterfly order.
+__device__ __forceinline__ double group_sum(double v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
+  return v;
+}
+
 // Block sum for blockDim.x a multiple of 64 (<= 1024), deterministic; result valid in all threads.
 __device__ __forceinline__ double block_sum(double v, double* scratch /* >= 16 doubles */) {
   v = wave_sum(v);
@@ -133,6 +147,7 @@ struct Geo {
   int64_t N = 0;
   int32_t No = 0;
   int32_t C = 0;
+  int32_t nmax = 0;           // largest node count of a particle
   // nodes, FP64
   double *x = nullptr, *y = nullptr, *nx = nullptr, *ny = nullptr, *w = nullptr, *kap = nullptr;
   double *tx = nullptr, *ty = nullptr, *xpx = nullptr, *xpy = nullptr;
@@ -161,6 +176,8 @@ struct Periodizer {
   double* svd_a = nullptr;  // Jacobi workspace [C x 8m x 2M] column-major
   double* svd_v = nullptr;  // [C x 2M x 2M]
   double* svd_s = nullptr;  // [C x (2M + 1)]: singular values and the sweep count
+  bool warm_ok = false;     // svd_v holds orthogonal V's of the current shape (C, m, M): warm start
+  int32_t warm_C = -1, warm_m = -1, warm_M = -1;
 };
 
 struct CloseList {
