@@ -15,17 +15,19 @@
 using namespace spm;
 
 namespace spm {
-// Default near-sum launch shape: 256 threads, one target per lane, 256-source tiles,
-// and a source chunk that gives about 8192 work items over the ensemble.
-NearConfig heuristic_near(spm_handle* h) {
+// Default near-sum launch shape (what the autotuner picks on the 25-, 83- and 200-ellipse
+// cells): 256 threads, 256-source LDS tiles; FP64 with four targets per lane (the FP64
+// pair is ALU-heavier, so reusing each staged source for more targets pays), FP32 with one;
+// the source chunk gives about 32768 work items over the ensemble, at least 64 sources.
+NearConfig heuristic_near(spm_handle* h, int precision) {
   NearConfig c;
   c.block = 256;
-  c.tpt = 1;
+  c.tpt = precision == SPM_FP64 ? 4 : 1;
   c.tile = 256;
   double work = 0;
   for (const auto& cl : h->cells) work += (double)(cl.n1 - cl.n0) * (double)(cl.n1 - cl.n0);
-  const double chunk = work / (256.0 * 8192.0);
-  c.chunk = (int32_t)std::max(128.0, std::min(65536.0, chunk));
+  const double chunk = work / ((double)c.block * c.tpt * 32768.0);
+  c.chunk = (int32_t)std::max(64.0, std::min(65536.0, std::round(chunk)));
   return c;
 }
 }  // namespace spm
@@ -251,9 +253,9 @@ void build_chunks(spm_handle* h) {
   std::vector<int32_t> cc, off(C + 1, 0), sc, soff(C + 1, 0);
   for (int c = 0; c < C; ++c) {
     const int64_t a = h->cells[c].n0, b = h->cells[c].n1;
-    for (int64_t x = a; x < b; x += 2048) {
+    for (int64_t x = a; x < b; x += 512) {
       s0.push_back(x);
-      s1.push_back(std::min(b, x + 2048));
+      s1.push_back(std::min(b, x + 512));
       cc.push_back(c);
     }
     off[c + 1] = (int32_t)s0.size();
@@ -506,8 +508,8 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   update_shapes(h);
   if (h->wk.tuned && h->wk.tuned_N != N) h->wk.tuned = false;
   if (!h->wk.tuned) {
-    h->wk.near[0].cfg = heuristic_near(h);
-    h->wk.near[1].cfg = heuristic_near(h);
+    h->wk.near[0].cfg = heuristic_near(h, SPM_FP64);
+    h->wk.near[1].cfg = heuristic_near(h, SPM_FP32);
   }
   build_near_plan(h, SPM_FP64);
   build_near_plan(h, SPM_FP32);

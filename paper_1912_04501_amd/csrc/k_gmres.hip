@@ -85,25 +85,37 @@ void gm_cgs_pass(spm_handle* h, const double* w, double* coef) {
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-// w[r] -= sum_{i <= j} V_i[r] coef[cell(r)][i] (active cells only)
-__global__ void k_update_j(const double* __restrict__ V, int64_t n2, int64_t N, const int32_t* __restrict__ jdev,
-                           const double* __restrict__ coef, int ldp, const int32_t* __restrict__ ncell,
-                           const int32_t* __restrict__ active, double* __restrict__ w) {
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (r >= n2) return;
-  const int c = ncell[r < N ? r : r - N];
-  if (active[c] == 0) return;
-  const int cnt = jdev[0] + 1;
-  const double* cf = coef + (int64_t)c * ldp;
+// w[r] -= sum_{i <= j} V_i[r] coef[cell(r)][i] (active cells only).
+// A 256-thread block covers 64 entries r with 4 groups; group g sums the basis vectors
+// i = g, g+4, ... (coalesced over r for every i), and the four partial sums are added in
+// fixed order through LDS.
+constexpr int kUpdGroups = 4;
+
+__global__ __launch_bounds__(256) void k_update_j(const double* __restrict__ V, int64_t n2, int64_t N,
+                                                  const int32_t* __restrict__ jdev, const double* __restrict__ coef,
+                                                  int ldp, const int32_t* __restrict__ ncell,
+                                                  const int32_t* __restrict__ active, double* __restrict__ w) {
+  __shared__ double part[kUpdGroups][64];
+  const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int64_t r = blockIdx.x * (int64_t)64 + lane;
+  const bool live = r < n2;
+  const int c = live ? ncell[r < N ? r : r - N] : 0;
+  const bool act = live && active[c] != 0;
   double s = 0.0;
-  for (int i = 0; i < cnt; ++i) s += V[(int64_t)i * n2 + r] * cf[i];
-  w[r] -= s;
+  if (act) {
+    const int cnt = jdev[0] + 1;
+    const double* cf = coef + (int64_t)c * ldp;
+    for (int i = grp; i < cnt; i += kUpdGroups) s += V[(int64_t)i * n2 + r] * cf[i];
+  }
+  part[grp][lane] = s;
+  __syncthreads();
+  if (grp == 0 && act) w[r] -= (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 void gm_update_j(spm_handle* h, const double* coef, double* w) {
   Krylov& K = h->kr;
-  k_update_j<<<(unsigned)((K.n2 + 255) / 256), 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.jdev, coef, K.kmax + 1,
-                                                                    h->geo.ncell, K.active, w);
+  k_update_j<<<(unsigned)((K.n2 + 63) / 64), 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.jdev, coef, K.kmax + 1,
+                                                                  h->geo.ncell, K.active, w);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

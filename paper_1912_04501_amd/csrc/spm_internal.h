@@ -407,7 +407,7 @@ bool near_config_valid(const NearConfig& c);
 void build_near_plan(spm_handle* h, int precision);
 void autotune(spm_handle* h, const char* cache_path, double* best_ms_out);
 double time_near(spm_handle* h, int prec, const NearConfig& c, int reps);
-NearConfig heuristic_near(spm_handle* h);
+NearConfig heuristic_near(spm_handle* h, int precision);
 void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision);
 void launch_disc(spm_handle* h);
 void launch_xi(spm_handle* h);

@@ -43,15 +43,29 @@ def ensemble():
     return cells, refs
 
 
-@pytest.mark.parametrize("precision,graph", [("fp64", 1), ("fp64", 0), ("fp32_ir", 1)])
+@pytest.mark.parametrize("precision,graph", [("fp64", 1), ("fp64", 0), ("fp32_ir", 1), ("fp32_relaxed", 1)])
 def test_ensemble_matches_oracle_per_cell(ensemble, precision, graph):
+    """Every cell of the batched solve against the oracle's solve of that cell alone. The
+    mixed forms target the FP64 residual: each cell's density must leave a residual within
+    2e-10 through the oracle's operator, and the readouts may differ by up to 1e-7."""
     cells, refs = ensemble
     spm = _spm()
-    p = spm.SPM_FP64 if precision == "fp64" else spm.SPM_FP32_IR
+    p = {"fp64": spm.SPM_FP64, "fp32_ir": spm.SPM_FP32_IR, "fp32_relaxed": spm.SPM_FP32_RELAXED}[precision]
     s = spm.Solver("cuda:0", precision=p, use_graph=graph).set_cells(cells)
     r = s.solve_batch()
     off = s.part_off
-    bound = 1e-9 if precision == "fp64" else 1e-8
+    bound = 1e-9 if precision == "fp64" else 1e-7
+    if precision != "fp64":
+        sig = _n(r["sigma"])
+        n0 = 0
+        N = s.N
+        for k, (prob, x, v, o, m) in enumerate(refs):
+            n1 = n0 + prob.N
+            sk = np.concatenate([sig[n0:n1], sig[N + n0:N + n1]])
+            b = op.rhs(prob)
+            res = np.linalg.norm(b - op.apply(prob, sk)) / np.linalg.norm(b)
+            assert res <= 2e-10, (k, res)
+            n0 = n1
     vel, om, mu = _n(r["vel"]), _n(r["omega"]), _n(r["mu_eff"])
     for k, (prob, x, v, o, m) in enumerate(refs):
         info = r["infos"][k]
