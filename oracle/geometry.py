@@ -9,6 +9,12 @@
   Periodic trapezoid rule (Sec. 6): w_k = (2 pi / N_i) |x'(t_k)|.
   Tangent tau = x'/|x'|, outward normal n = (tau_2, -tau_1), curvature
   kappa = a b / |x'|^3. The perimeter centroid (Sec. 2) of an ellipse is c.
+* Star (the smooth star-shaped curves of Sec. 8 Examples 2 and 4): in the body frame
+  x(t) = r(t) (cos t, sin t), r(t) = s (1 + A cos(omega t + phi)), with the same rule,
+  tangent and normal, and the signed curvature kappa = (x' y'' - y' x'') / |x'|^3. Its
+  reference point c (the polar origin, inside the curve) carries the rigid motion; any
+  body-fixed point inside serves, since the particles are force- and torque-free.
+  For stars, ``a`` holds the largest radius s (1 + |A|) and ``b`` the smallest.
 """
 from __future__ import annotations
 
@@ -51,6 +57,8 @@ class Geometry:
     w: np.ndarray         # (N,) trapezoid weights
     kappa: np.ndarray     # (N,) curvature
     pid: np.ndarray       # (N,) particle index of each node
+    kind: np.ndarray = None    # (No,) 0 ellipse, 1 star
+    params: np.ndarray = None  # (No, 4) ellipse (a, b, 0, 0); star (s, A, omega, phi)
 
     @property
     def N(self) -> int:
@@ -87,15 +95,62 @@ def ellipse_nodes(c, theta, a, b, N):
     return x, xp, tau, n, w, kappa
 
 
+def star_nodes(c, theta, s, A, omega, phi, N):
+    t = 2.0 * np.pi * np.arange(N) / N
+    u = omega * t + phi
+    r = s * (1.0 + A * np.cos(u))
+    rp = -s * A * omega * np.sin(u)
+    rpp = -s * A * omega * omega * np.cos(u)
+    ct_, st_ = np.cos(t), np.sin(t)
+    X, Y = r * ct_, r * st_
+    Xp, Yp = rp * ct_ - r * st_, rp * st_ + r * ct_
+    Xpp = rpp * ct_ - 2.0 * rp * st_ - r * ct_
+    Ypp = rpp * st_ + 2.0 * rp * ct_ - r * st_
+    ca, sa = np.cos(theta), np.sin(theta)
+    x = np.stack([c[0] + ca * X - sa * Y, c[1] + sa * X + ca * Y], axis=1)
+    xp = np.stack([ca * Xp - sa * Yp, sa * Xp + ca * Yp], axis=1)
+    sp = np.sqrt((xp * xp).sum(1))
+    tau = xp / sp[:, None]
+    n = np.stack([tau[:, 1], -tau[:, 0]], axis=1)
+    w = 2.0 * np.pi * sp / N
+    kappa = (Xp * Ypp - Yp * Xpp) / sp ** 3
+    return x, xp, tau, n, w, kappa
+
+
+def shape_params(wl):
+    """(kind, params) of every particle; ellipses by default (params a, b)."""
+    n = len(wl["theta"])
+    if "kind" not in wl:
+        p = np.zeros((n, 4))
+        p[:, 0], p[:, 1] = wl["a"], wl["b"]
+        return np.zeros(n, dtype=np.int64), p
+    return np.asarray(wl["kind"], dtype=np.int64), np.asarray(wl["params"], dtype=float).reshape(n, 4)
+
+
+def radii(kind, p):
+    """(largest, smallest) distance from the reference point to the curve."""
+    if kind == 0:
+        return max(p[0], p[1]), min(p[0], p[1])
+    return p[0] * (1.0 + abs(p[1])), p[0] * (1.0 - abs(p[1]))
+
+
+def particle_nodes(c, theta, kind, p, N):
+    if kind == 0:
+        return ellipse_nodes(c, theta, p[0], p[1], N)
+    return star_nodes(c, theta, p[0], p[1], p[2], p[3], N)
+
+
 def build_geometry(wl) -> Geometry:
     e1, e2 = lattice(wl["skew"])
     cU = np.zeros(2)
     c = wrap_centers(np.asarray(wl["centers"], float), e1, e2, cU)
     nn = np.asarray(wl["n_nodes"], dtype=np.int64)
     offs = np.concatenate([[0], np.cumsum(nn)])
-    parts = [ellipse_nodes(c[i], float(wl["theta"][i]), float(wl["a"][i]), float(wl["b"][i]), int(nn[i]))
-             for i in range(len(nn))]
+    kind, prm = shape_params(wl)
+    th = np.asarray(wl["theta"], float)
+    parts = [particle_nodes(c[i], float(th[i]), int(kind[i]), prm[i], int(nn[i])) for i in range(len(nn))]
     x, xp, tau, n, w, kappa = (np.concatenate([p[k] for p in parts]) for k in range(6))
     pid = np.repeat(np.arange(len(nn)), nn)
-    return Geometry(e1, e2, cU, c, np.asarray(wl["theta"], float), np.asarray(wl["a"], float),
-                    np.asarray(wl["b"], float), nn, offs, x, xp, tau, n, w, kappa, pid)
+    rr = np.array([radii(int(kind[i]), prm[i]) for i in range(len(nn))]).reshape(-1, 2)
+    return Geometry(e1, e2, cU, c, th, rr[:, 0].copy(), rr[:, 1].copy(), nn, offs, x, xp, tau, n, w, kappa, pid,
+                    kind, prm)

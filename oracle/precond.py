@@ -26,17 +26,19 @@ from . import geometry
 from .kernels import traction_matrix
 
 
-def body_nodes(a, b, n):
-    """Nodes of the ellipse (a cos t, b sin t), t_k = 2 pi k / n, with the geometry
-    of the periodic trapezoid rule (Sec. 6)."""
-    x, xp, tau, nrm, w, kap = geometry.ellipse_nodes(np.zeros(2), 0.0, a, b, n)
+def body_nodes(a, b, n, kind=0, params=None):
+    """Nodes of the curve in its body frame (angle 0, reference point at the origin),
+    t_k = 2 pi k / n, with the geometry of the periodic trapezoid rule (Sec. 6): the
+    ellipse (a cos t, b sin t), or the star of the given params."""
+    p = np.array([a, b, 0.0, 0.0]) if params is None else np.asarray(params, float)
+    x, xp, tau, nrm, w, kap = geometry.particle_nodes(np.zeros(2), 0.0, kind, p, n)
     return x, tau, nrm, w, kap
 
 
-def self_block(a, b, n, complete=True):
-    """B_body (2n x 2n) of the ellipse with semi-axes a, b and n nodes (without the
-    completion L when complete is False)."""
-    x, tau, nrm, w, kap = body_nodes(a, b, n)
+def self_block(a, b, n, complete=True, kind=0, params=None):
+    """B_body (2n x 2n) of the ellipse with semi-axes a, b (or of the given shape) and n
+    nodes (without the completion L when complete is False)."""
+    x, tau, nrm, w, kap = body_nodes(a, b, n, kind, params)
     B = np.zeros((2 * n, 2 * n))
     for i in range(n):
         r = x[i] - x
@@ -67,9 +69,11 @@ def apply_inverse(geom, v):
     for q in range(geom.No):
         sl = geom.particle_slice(q)
         n = int(geom.n_nodes[q])
-        key = (float(geom.a[q]), float(geom.b[q]), n)
+        kind = 0 if geom.kind is None else int(geom.kind[q])
+        prm = np.array([geom.a[q], geom.b[q], 0.0, 0.0]) if geom.params is None else geom.params[q]
+        key = (kind, tuple(float(v) for v in prm), n)
         if key not in cache:
-            cache[key] = self_block(*key)
+            cache[key] = self_block(0.0, 0.0, n, kind=kind, params=prm)
         c, s = np.cos(geom.theta[q]), np.sin(geom.theta[q])
         v1, v2 = v[:N][sl], v[N:][sl]
         rhs = np.concatenate([c * v1 + s * v2, -s * v1 + c * v2])

@@ -259,6 +259,28 @@ def two_ellipses(d, n_nodes=64, skew=0.0):
             "n_nodes": np.array([n_nodes, n_nodes], dtype=np.int32), "mu": 1.0, "gamma": 1.0}
 
 
+def stars(centers, s, A, omega, phase=None, theta=None, n_nodes=256, skew=0.0, name="stars"):
+    """Smooth star-shaped particles r(t) = s (1 + A cos(omega t + phase)) in the body frame,
+    x = c + R(theta) r(t) (cos t, sin t)."""
+    c = np.asarray(centers, dtype=float).reshape(-1, 2)
+    n = len(c)
+    bc = lambda v: np.broadcast_to(np.asarray(v, dtype=float), (n,)).copy()  # noqa: E731
+    params = np.stack([bc(s), bc(A), bc(omega), bc(0.0 if phase is None else phase)], axis=1)
+    th = bc(0.0 if theta is None else theta)
+    return {"name": name, "skew": float(skew), "centers": c, "theta": th, "kind": np.ones(n, dtype=np.int32),
+            "params": params, "a": params[:, 0] * (1 + np.abs(params[:, 1])),
+            "b": params[:, 0] * (1 - np.abs(params[:, 1])),
+            "n_nodes": np.broadcast_to(np.asarray(n_nodes, dtype=np.int32), (n,)).copy(), "mu": 1.0, "gamma": 1.0}
+
+
+def two_stars(s=0.25, A=0.5, omega=1.0, second_theta=0.0, n_nodes=256):
+    """Two star-shaped particles of the Sec. 8 jamming examples, centred at (1/4, 1/4) and
+    (3/4, 3/4) of the unit square (here relative to the cell centre), the second turned by
+    second_theta."""
+    return stars([[-0.25, -0.25], [0.25, 0.25]], s, A, omega, theta=[0.0, second_theta], n_nodes=n_nodes,
+                 name=f"two_stars_s{s}_A{A}_w{omega:g}")
+
+
 def random_density(n_total, seed=7):
     """sigma ~ N(0, 1), SoA [sigma_1(0..N-1), sigma_2(0..N-1)]."""
     return np.random.default_rng(seed).standard_normal(2 * int(n_total))
