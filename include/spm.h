@@ -67,6 +67,11 @@ extern "C" {
 #define SPM_X0_PREVIOUS 1  /* spm_step: the previous step's density (first step: zero) */
 #define SPM_X0_NETWORK 2   /* the learned warm start of the network set by spm_set_network */
 
+#define SPM_SHAPE_ELLIPSE 0  /* params (a, b, -, -): x(t) = (a cos t, b sin t) */
+#define SPM_SHAPE_STAR 1     /* params (s, A, omega, phi): x(t) = r(t) (cos t, sin t),
+                                r(t) = s (1 + A cos(omega t + phi)), |A| < 1, integer omega >= 0
+                                (the smooth star-shaped curves of Sec. 8 Examples 2 and 4) */
+
 #define SPM_PRECOND_NONE 0
 #define SPM_PRECOND_BLOCK 1  /* right preconditioner blockdiag(B_q)^-1 of isolated-body self blocks */
 
@@ -214,6 +219,15 @@ int spm_proxy_strengths(spm_handle* h, const double* sigma, double* xi);
 int spm_set_cells(spm_handle* h, int32_t n_cells, const double* skews_host, const int32_t* part_offsets_host,
                   const double* centers_host, const double* theta_host, const double* a_host,
                   const double* b_host, const int32_t* n_nodes_host);
+
+/* As spm_set_cells for particles of any supported shape: kind_host [n] (SPM_SHAPE_*),
+ * params_host [4n] (see SPM_SHAPE_*); the curve of particle i is c_i + R(theta_i) x(t),
+ * t_k = 2 pi k / N_i, and its reference point c_i (inside the curve) carries the rigid
+ * motion (velocity and angular velocity are read there). The largest radius must stay
+ * below 0.45 (3x3 image rule). */
+int spm_set_cells_shapes(spm_handle* h, int32_t n_cells, const double* skews_host, const int32_t* part_offsets_host,
+                         const double* centers_host, const double* theta_host, const int32_t* kind_host,
+                         const double* params_host, const int32_t* n_nodes_host);
 
 int spm_num_cells(const spm_handle* h, int32_t* n_cells);
 

@@ -352,40 +352,48 @@ void alloc_learned(spm_handle* h) {
   SPM_HIP_CHECK(hipMemcpyAsync(L.nvec + N, h->geo.ny, N * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
 }
 
-// Distinct particle shapes (a, b, N) in order of first appearance; the preconditioner
-// is rebuilt (lazily) only when this list changes.
+// Distinct particle shapes (kind, parameters, N) in order of first appearance; the
+// preconditioner is rebuilt (lazily) only when this list changes.
 void update_shapes(spm_handle* h) {
   Precond& P = h->pc;
   const int n = h->geo.No;
-  std::map<std::tuple<double, double, int32_t>, int32_t> id;
-  std::vector<double> ka, kb;
-  std::vector<int32_t> kn, ps(n);
+  std::map<std::vector<double>, int32_t> id;
+  std::vector<std::vector<double>> keys;
+  std::vector<int32_t> ps(n);
   for (int i = 0; i < n; ++i) {
-    const auto key = std::make_tuple(h->a[i], h->b[i], h->nn[i]);
+    std::vector<double> key = {(double)h->kind[i], h->prm[4 * i], h->prm[4 * i + 1], h->prm[4 * i + 2],
+                               h->prm[4 * i + 3], (double)h->nn[i]};
     auto it = id.find(key);
     if (it == id.end()) {
-      const int32_t s = (int32_t)ka.size();
-      id.emplace(key, s);
-      ka.push_back(h->a[i]);
-      kb.push_back(h->b[i]);
-      kn.push_back(h->nn[i]);
-      ps[i] = s;
+      const int32_t sid = (int32_t)keys.size();
+      id.emplace(key, sid);
+      keys.push_back(key);
+      ps[i] = sid;
     } else {
       ps[i] = it->second;
     }
   }
-  if (ka != P.ka || kb != P.kb || kn != P.kn) {
+  if (keys != P.keys) {
     P.valid = false;
-    P.ka = ka;
-    P.kb = kb;
-    P.kn = kn;
+    P.keys = keys;
   }
   ensure(h, P.pshape, n);
   upload(h, P.pshape, ps.data(), n * sizeof(int32_t));
 }
 
+// Largest and smallest distance from a particle's reference point to its curve.
+void shape_radii(int32_t kind, const double* p, double& rmax, double& rmin) {
+  if (kind == SPM_SHAPE_ELLIPSE) {
+    rmax = std::max(p[0], p[1]);
+    rmin = std::min(p[0], p[1]);
+  } else {
+    rmax = p[0] * (1.0 + std::fabs(p[1]));
+    rmin = p[0] * (1.0 - std::fabs(p[1]));
+  }
+}
+
 void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* part_off, const double* centers,
-                    const double* theta, const double* a, const double* b, const int32_t* n_nodes) {
+                    const double* theta, const int32_t* kind, const double* prm, const int32_t* n_nodes) {
   if (C < 1 || C > 1024) throw ApiError(SPM_EINVAL, "number of cells must be in [1, 1024]");
   const int n = part_off[C];
   if (part_off[0] != 0 || n < 1) throw ApiError(SPM_EINVAL, "bad particle offsets");
@@ -395,8 +403,10 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   h->cx.resize(n);
   h->cy.resize(n);
   h->th.assign(theta, theta + n);
-  h->a.assign(a, a + n);
-  h->b.assign(b, b + n);
+  h->kind.assign(kind, kind + n);
+  h->prm.assign(prm, prm + 4 * (size_t)n);
+  h->a.assign(n, 0.0);
+  h->b.assign(n, 0.0);
   h->nn.assign(n_nodes, n_nodes + n);
   h->off.assign(n + 1, 0);
   h->pcell.assign(n, 0);
@@ -410,12 +420,22 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
     cl.p1 = part_off[c + 1];
     const double s = cl.skew;  // e1 = (1, 0), e2 = (s, 1), det = 1
     for (int i = cl.p0; i < cl.p1; ++i) {
-      if (!(a[i] > 0) || !(b[i] > 0) || !std::isfinite(centers[2 * i]) || !std::isfinite(centers[2 * i + 1]) ||
-          !std::isfinite(theta[i]))
-        throw ApiError(SPM_EINVAL, "bad ellipse " + std::to_string(i));
+      const double* pp = prm + 4 * (size_t)i;
+      bool ok = std::isfinite(centers[2 * i]) && std::isfinite(centers[2 * i + 1]) && std::isfinite(theta[i]);
+      if (kind[i] == SPM_SHAPE_ELLIPSE) {
+        ok = ok && pp[0] > 0 && pp[1] > 0;
+      } else if (kind[i] == SPM_SHAPE_STAR) {
+        // r(t) = s (1 + A cos(omega t + phi)) > 0, closed for integer omega
+        ok = ok && pp[0] > 0 && std::fabs(pp[1]) < 1.0 && pp[2] >= 0 && pp[2] <= 64 &&
+             pp[2] == std::floor(pp[2]) && std::isfinite(pp[3]);
+      } else {
+        ok = false;
+      }
+      if (!ok) throw ApiError(SPM_EINVAL, "bad particle " + std::to_string(i));
       if (n_nodes[i] < 8 || n_nodes[i] > kMaxNodesPerParticle || (n_nodes[i] & 1))
         throw ApiError(SPM_EINVAL, "node count must be even and in [8, 512]");
-      if (std::max(a[i], b[i]) >= 0.45) throw ApiError(SPM_EINVAL, "ellipse larger than the 3x3 image rule allows");
+      shape_radii(kind[i], pp, h->a[i], h->b[i]);
+      if (h->a[i] >= 0.45) throw ApiError(SPM_EINVAL, "particle larger than the 3x3 image rule allows");
       // wrap: (alpha, beta) = [e1 e2]^{-1} (c - c_U), reduced to [-1/2, 1/2)
       const double dx = centers[2 * i] - h->cU[0], dy = centers[2 * i + 1] - h->cU[1];
       double be = dy;
@@ -471,6 +491,10 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   upload(h, g.pth, h->th.data(), n * sizeof(double));
   upload(h, g.pa, h->a.data(), n * sizeof(double));
   upload(h, g.pb, h->b.data(), n * sizeof(double));
+  ensure(h, g.pkind, n);
+  ensure(h, g.pprm, 4 * (size_t)n);
+  upload(h, g.pkind, h->kind.data(), n * sizeof(int32_t));
+  upload(h, g.pprm, h->prm.data(), 4 * (size_t)n * sizeof(double));
   upload(h, g.poff, h->off.data(), (n + 1) * sizeof(int32_t));
   upload(h, g.pn, h->nn.data(), n * sizeof(int32_t));
   upload(h, g.pcell, h->pcell.data(), n * sizeof(int32_t));
@@ -1080,7 +1104,13 @@ int spm_set_ellipses(spm_handle* h, int32_t n, const double* centers, const doub
     if (n < 1 || !centers || !theta || !a || !b || !n_nodes) throw ApiError(SPM_EINVAL, "bad particle arrays");
     const int32_t off[2] = {0, n};
     const double sk = h->pending_skew;
-    set_cells_impl(h, 1, &sk, off, centers, theta, a, b, n_nodes);
+    std::vector<int32_t> kind(n, SPM_SHAPE_ELLIPSE);
+    std::vector<double> prm(4 * (size_t)n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      prm[4 * i] = a[i];
+      prm[4 * i + 1] = b[i];
+    }
+    set_cells_impl(h, 1, &sk, off, centers, theta, kind.data(), prm.data(), n_nodes);
     return SPM_OK;
   });
 }
@@ -1094,7 +1124,30 @@ int spm_set_cells(spm_handle* h, int32_t n_cells, const double* skews, const int
     h->cU[0] = 0.0;
     h->cU[1] = 0.0;
     h->have_lattice = true;
-    set_cells_impl(h, n_cells, skews, part_offsets, centers, theta, a, b, n_nodes);
+    if (n_cells < 1 || n_cells > 1024) throw ApiError(SPM_EINVAL, "number of cells must be in [1, 1024]");
+    const int n = part_offsets[n_cells];
+    if (n < 1) throw ApiError(SPM_EINVAL, "bad particle offsets");
+    std::vector<int32_t> kind(n, SPM_SHAPE_ELLIPSE);
+    std::vector<double> prm(4 * (size_t)n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      prm[4 * i] = a[i];
+      prm[4 * i + 1] = b[i];
+    }
+    set_cells_impl(h, n_cells, skews, part_offsets, centers, theta, kind.data(), prm.data(), n_nodes);
+    return SPM_OK;
+  });
+}
+
+int spm_set_cells_shapes(spm_handle* h, int32_t n_cells, const double* skews, const int32_t* part_offsets,
+                         const double* centers, const double* theta, const int32_t* kind, const double* params,
+                         const int32_t* n_nodes) {
+  return guarded(h, [&]() {
+    if (!skews || !part_offsets || !centers || !theta || !kind || !params || !n_nodes)
+      throw ApiError(SPM_EINVAL, "null array");
+    h->cU[0] = 0.0;
+    h->cU[1] = 0.0;
+    h->have_lattice = true;
+    set_cells_impl(h, n_cells, skews, part_offsets, centers, theta, kind, params, n_nodes);
     return SPM_OK;
   });
 }
@@ -1365,8 +1418,8 @@ int spm_step_record(spm_handle* h, double dt, int32_t n_steps, double* t_inout, 
     if (!t_inout || !centers || !theta || !mu_series || n_steps < 1 || !(dt > 0))
       throw ApiError(SPM_EINVAL, "bad step arguments");
     const int n = h->geo.No;
-    std::vector<double> a(h->a), b(h->b);
-    std::vector<int32_t> nn(h->nn);
+    std::vector<int32_t> kind(h->kind), nn(h->nn);
+    std::vector<double> prm(h->prm);
     const double s0 = h->cells[0].skew_raw;
     const double t0 = *t_inout;
     const int64_t n2 = 2 * h->geo.N;
@@ -1381,7 +1434,7 @@ int spm_step_record(spm_handle* h, double dt, int32_t n_steps, double* t_inout, 
       const double sk = s0 + h->cfg.gamma * (k * dt);
       const int32_t off[2] = {0, n};
       *t_inout = t0 + k * dt;   // time of the state being solved (kept if this step fails)
-      set_cells_impl(h, 1, &sk, off, centers, theta, a.data(), b.data(), nn.data());
+      set_cells_impl(h, 1, &sk, off, centers, theta, kind.data(), prm.data(), nn.data());
       sig = h->kr.stepbuf;  // (buffers are stable: same sizes)
       spm_solve_info info;
       const double* guess = (h->cfg.x0 == SPM_X0_PREVIOUS && have_prev) ? sig : nullptr;

@@ -3,24 +3,23 @@
 
 namespace spm {
 
-// One thread per node: ellipse x(t) = c + R(theta)(a cos t, b sin t), t = 2 pi k / N_p.
-// w = (2 pi / N_p)|x'|, tau = x'/|x'|, n = (tau_2, -tau_1), kappa = a b / |x'|^3.
+// One thread per node: x(t) = c + R(theta) x_body(t), t = 2 pi k / N_p (x_body: ellipse
+// (a cos t, b sin t) or star r(t) (cos t, sin t)). w = (2 pi / N_p)|x'|, tau = x'/|x'|,
+// n = (tau_2, -tau_1), kappa = (x' y'' - y' x'') / |x'|^3 (= a b / |x'|^3 for an ellipse).
 __global__ void k_geometry(int64_t N, const int32_t* __restrict__ pid, const int32_t* __restrict__ poff,
                            const int32_t* __restrict__ pn, const double* __restrict__ pcx,
                            const double* __restrict__ pcy, const double* __restrict__ pth,
-                           const double* __restrict__ pa, const double* __restrict__ pb, Geo g) {
+                           const int32_t* __restrict__ pkind, const double* __restrict__ pprm, Geo g) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int p = pid[i];
   const int k = (int)(i - poff[p]);
   const int n = pn[p];
   const double t = 2.0 * kPi * (double)k / (double)n;
-  double st, ct, sth, cth;
-  sincos(t, &st, &ct);
+  double px, py, dx, dy, ddx, ddy;
+  shape_point(pkind[p], pprm + 4 * (int64_t)p, t, px, py, dx, dy, ddx, ddy);
+  double sth, cth;
   sincos(pth[p], &sth, &cth);
-  const double a = pa[p], b = pb[p];
-  const double px = a * ct, py = b * st;
-  const double dx = -a * st, dy = b * ct;
   const double x = pcx[p] + (cth * px - sth * py);
   const double y = pcy[p] + (sth * px + cth * py);
   const double xpx = cth * dx - sth * dy;
@@ -36,7 +35,7 @@ __global__ void k_geometry(int64_t N, const int32_t* __restrict__ pid, const int
   g.nx[i] = ty;
   g.ny[i] = -tx;
   g.w[i] = 2.0 * kPi * sp / (double)n;
-  g.kap[i] = a * b / (sp * sp * sp);
+  g.kap[i] = (dx * ddy - dy * ddx) / (sp * sp * sp);
   g.xf[i] = (float)x;
   g.yf[i] = (float)y;
   g.nxf[i] = (float)ty;
@@ -57,7 +56,7 @@ void launch_geometry(spm_handle* h) {
   Geo& g = h->geo;
   const int bs = 256;
   k_geometry<<<(unsigned)((g.N + bs - 1) / bs), bs, 0, h->stream>>>(g.N, g.pid, g.poff, g.pn, g.pcx, g.pcy,
-                                                                    g.pth, g.pa, g.pb, g);
+                                                                    g.pth, g.pkind, g.pprm, g);
   SPM_HIP_CHECK(hipGetLastError());
   k_perimeter<<<g.No, 256, 0, h->stream>>>(g.poff, g.w, g.pper);
   SPM_HIP_CHECK(hipGetLastError());
@@ -110,12 +109,18 @@ __global__ void k_close_pass(int64_t N, Geo g, double factor, const int32_t* __r
       const double cx = g.pcx[q] + sx, cy = g.pcy[q] + sy;
       const double ddx = xi - cx, ddy = yi - cy;
       if (ddx * ddx + ddy * ddy >= reach * reach) continue;
-      // inside test against the ellipse (body frame)
+      // inside test against the curve (body frame)
       double sth, cth;
       sincos(g.pth[q], &sth, &cth);
-      const double u = (cth * ddx + sth * ddy) / g.pa[q];
-      const double v = (-sth * ddx + cth * ddy) / g.pb[q];
-      if (u * u + v * v < 1.0) ins = 1;
+      const double bu = cth * ddx + sth * ddy, bv = -sth * ddx + cth * ddy;
+      const double* pp = g.pprm + 4 * (int64_t)q;
+      if (g.pkind[q] == SPM_SHAPE_ELLIPSE) {
+        const double u = bu / pp[0], v = bv / pp[1];
+        if (u * u + v * v < 1.0) ins = 1;
+      } else {   // star-shaped about the reference point: inside when closer than r(angle)
+        const double r = pp[0] * (1.0 + pp[1] * cos(pp[2] * atan2(bv, bu) + pp[3]));
+        if (bu * bu + bv * bv < r * r) ins = 1;
+      }
       double m2 = 1e300;
       for (int k = g.poff[q]; k < g.poff[q + 1]; ++k) {
         const double rx = xi - (g.x[k] + sx);

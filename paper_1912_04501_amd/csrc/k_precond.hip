@@ -14,18 +14,16 @@
 
 namespace spm {
 
-__device__ __forceinline__ void body_node(double a, double b, int n, int k, double& x, double& y, double& tx,
-                                          double& ty, double& w, double& kap) {
-  double s, c;
-  sincos(2.0 * kPi * (double)k / (double)n, &s, &c);
-  x = a * c;
-  y = b * s;
-  const double dx = -a * s, dy = b * c;
+__device__ __forceinline__ void body_node(const ShapeDesc& d, int k, double& x, double& y, double& tx, double& ty,
+                                          double& w, double& kap) {
+  const double t = 2.0 * kPi * (double)k / (double)d.n;
+  double dx, dy, ddx, ddy;
+  shape_point(d.kind, d.p, t, x, y, dx, dy, ddx, ddy);
   const double sp = sqrt(dx * dx + dy * dy);
   tx = dx / sp;
   ty = dy / sp;
-  w = 2.0 * kPi * sp / (double)n;
-  kap = a * b / (sp * sp * sp);
+  w = 2.0 * kPi * sp / (double)d.n;
+  kap = (dx * ddy - dy * ddx) / (sp * sp * sp);
 }
 
 // block (row i, shape): both rows (component 1 and 2) of node i of [B | I]
@@ -35,13 +33,13 @@ __global__ __launch_bounds__(256) void k_self_block(const ShapeDesc* __restrict_
   const int i = blockIdx.x;
   if (i >= n) return;
   double xi, yi, txi, tyi, wi, ki;
-  body_node(d.a, d.b, n, i, xi, yi, txi, tyi, wi, ki);
+  body_node(d, i, xi, yi, txi, tyi, wi, ki);
   const double nxi = tyi, nyi = -txi;
   double* r1 = work + d.woff + (int64_t)i * ld;         // row of component 1
   double* r2 = work + d.woff + (int64_t)(n + i) * ld;   // row of component 2
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     double xj, yj, txj, tyj, wj, kj;
-    body_node(d.a, d.b, n, j, xj, yj, txj, tyj, wj, kj);
+    body_node(d, j, xj, yj, txj, tyj, wj, kj);
     double m11, m12, m21, m22;
     if (j == i) {
       const double c = -(ki / (2.0 * kPi)) * wi;
@@ -199,12 +197,13 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
 // [B | I] work arrays stay below ~1 GB.
 void build_precond(spm_handle* h) {
   Precond& P = h->pc;
-  const int S = (int)P.ka.size();
+  const int S = (int)P.keys.size();
+  auto nodes = [&](int s) { return (int32_t)P.keys[s][5]; };
   std::vector<int64_t> ioff(S);
   int64_t total = 0;
   for (int s = 0; s < S; ++s) {
     ioff[s] = total;
-    total += 4LL * P.kn[s] * P.kn[s];
+    total += 4LL * nodes(s) * nodes(s);
   }
   P.inv = static_cast<float*>(precond_alloc(h, P.inv, (size_t)total * sizeof(float), P.inv_cap));
   P.ioff = static_cast<int64_t*>(precond_alloc(h, P.ioff, (size_t)S * sizeof(int64_t), P.ioff_cap));
@@ -216,18 +215,17 @@ void build_precond(spm_handle* h) {
     int64_t w = 0;
     int maxn = 0;
     for (int s = s0; s < S; ++s) {
-      const int64_t need = 8LL * P.kn[s] * P.kn[s];   // m x 2m
+      const int64_t need = 8LL * nodes(s) * nodes(s);   // m x 2m
       if (!batch.empty() && w + need > budget) break;
       ShapeDesc d;
-      d.a = P.ka[s];
-      d.b = P.kb[s];
-      d.n = P.kn[s];
-      d.pad = 0;
+      d.kind = (int32_t)P.keys[s][0];
+      for (int k = 0; k < 4; ++k) d.p[k] = P.keys[s][1 + k];
+      d.n = nodes(s);
       d.woff = w;
       d.ioff = ioff[s];
       batch.push_back(d);
       w += need;
-      maxn = std::max(maxn, P.kn[s]);
+      maxn = std::max(maxn, nodes(s));
     }
     const int nb = (int)batch.size();
     P.work = static_cast<double*>(precond_alloc(h, P.work, (size_t)w * sizeof(double), P.work_cap));

@@ -21,6 +21,33 @@ constexpr int kShifts = 9;   // 3x3 images m e1 + n e2, index 3 (m + 1) + (n + 1
 constexpr int kZeroShift = 4;
 constexpr int kMaxNodesPerParticle = 512;   // close-evaluation LDS staging (k_vplus) holds one curve
 
+// Body-frame point of a particle curve at parameter t (SPM_SHAPE_ELLIPSE: (a cos t, b sin t);
+// SPM_SHAPE_STAR: r(t) (cos t, sin t), r = s (1 + A cos(omega t + phi))) with its first and
+// second t-derivatives.
+__host__ __device__ __forceinline__ void shape_point(int kind, const double* p, double t, double& X, double& Y,
+                                                     double& Xp, double& Yp, double& Xpp, double& Ypp) {
+  const double st = sin(t), ct = cos(t);
+  if (kind == SPM_SHAPE_ELLIPSE) {
+    X = p[0] * ct;
+    Y = p[1] * st;
+    Xp = -p[0] * st;
+    Yp = p[1] * ct;
+    Xpp = -X;
+    Ypp = -Y;
+  } else {
+    const double su = sin(p[2] * t + p[3]), cu = cos(p[2] * t + p[3]);
+    const double r = p[0] * (1.0 + p[1] * cu);
+    const double rp = -p[0] * p[1] * p[2] * su;
+    const double rpp = -p[0] * p[1] * p[2] * p[2] * cu;
+    X = r * ct;
+    Y = r * st;
+    Xp = rp * ct - r * st;
+    Yp = rp * st + r * ct;
+    Xpp = rpp * ct - 2.0 * rp * st - r * ct;
+    Ypp = rpp * st + 2.0 * rp * ct - r * st;
+  }
+}
+
 // Image shift s = m e1 + n e2 of a cell with e1 = (1, 0), e2 = (skew, 1), computed the
 // same way by every kernel (the FP32 close correction needs bit-identical shifts).
 __host__ __device__ __forceinline__ double shift_x(int s, double skew) {
@@ -156,9 +183,12 @@ struct Geo {
   int32_t* pid = nullptr;     // [N] particle of each node
   int32_t* ncell = nullptr;   // [N] cell of each node
   // particles
+  // pa, pb: largest and smallest distance from the reference point to the curve
   double *pcx = nullptr, *pcy = nullptr, *pth = nullptr, *pa = nullptr, *pb = nullptr, *pper = nullptr;
   int32_t *poff = nullptr, *pn = nullptr;
   int32_t* pcell = nullptr;   // [No] cell of each particle
+  int32_t* pkind = nullptr;   // [No] SPM_SHAPE_*
+  double* pprm = nullptr;     // [No x 4] shape parameters (ellipse a, b; star s, A, omega, phi)
   // cells
   int64_t* cnoff = nullptr;   // [C + 1] node offsets
   int32_t* cpoff = nullptr;   // [C + 1] particle offsets
@@ -301,9 +331,9 @@ struct Learned {
 // Shape of one self block being built: ellipse semi-axes, nodes, offsets of its
 // [B | I] work matrix and of its FP32 inverse.
 struct ShapeDesc {
-  double a, b;
+  double p[4];      // shape parameters
+  int32_t kind;     // SPM_SHAPE_*
   int32_t n;
-  int32_t pad;
   int64_t woff;
   int64_t ioff;
 };
@@ -312,8 +342,7 @@ struct ShapeDesc {
 // particles (kept while the shapes stay the same).
 struct Precond {
   bool valid = false;
-  std::vector<double> ka, kb;   // distinct shapes, in order of first appearance
-  std::vector<int32_t> kn;
+  std::vector<std::vector<double>> keys;   // distinct shapes {kind, p0..p3, N}, in order of first appearance
   int32_t* pshape = nullptr;    // [No] shape of each particle
   size_t pshape_cap = 0;
   int64_t* ioff = nullptr;      // [shapes] offset of each inverse
@@ -349,8 +378,9 @@ struct spm_handle {
   double pending_skew = 0.0;          // set by spm_set_lattice for the next spm_set_ellipses
   std::vector<spm::CellHost> cells;   // host view of the cells
   // host copy of the particle table (wrapped centres), all cells
-  std::vector<double> cx, cy, th, a, b;
-  std::vector<int32_t> nn, off, pcell;
+  std::vector<double> cx, cy, th, a, b;   // a, b: largest and smallest radius
+  std::vector<int32_t> nn, off, pcell, kind;
+  std::vector<double> prm;                // [4 n] shape parameters
 
   spm::Geo geo;
   spm::Periodizer per;

@@ -99,6 +99,7 @@ def lib():
         "spm_proxy_pinv": (ctypes.c_int, [P, d]),
         "spm_proxy_svd": (ctypes.c_int, [P, d, d, i32]),
         "spm_set_cells": (ctypes.c_int, [P, ctypes.c_int32, d, i32, d, d, d, d, i32]),
+        "spm_set_cells_shapes": (ctypes.c_int, [P, ctypes.c_int32, d, i32, d, d, i32, d, i32]),
         "spm_num_cells": (ctypes.c_int, [P, i32]),
         "spm_solve_batch": (ctypes.c_int, [P, P, P, P, P, P, ctypes.POINTER(spm_solve_info), d]),
         "spm_autotune": (ctypes.c_int, [P, ctypes.c_char_p, d]),
@@ -306,9 +307,23 @@ class Solver:
         self.C = 1
 
     def set_workload(self, wl):
+        if "kind" in wl:
+            self.set_cells([wl])
+            return self
         self.set_lattice(wl["skew"])
         self.set_ellipses(wl["centers"], wl["theta"], wl["a"], wl["b"], wl["n_nodes"])
         return self
+
+    @staticmethod
+    def _shape_arrays(c):
+        """(kind, params [n, 4]) of one workload: stars carry their own, ellipses (a, b, 0, 0)."""
+        n = len(c["theta"])
+        if "kind" in c:
+            return np.asarray(c["kind"], np.int32), np.asarray(c["params"], float).reshape(n, 4)
+        prm = np.zeros((n, 4))
+        prm[:, 0] = c["a"]
+        prm[:, 1] = c["b"]
+        return np.zeros(n, np.int32), prm
 
     def set_cells(self, cells):
         """An ensemble: a list of workload dicts, one per independent cell."""
@@ -317,12 +332,19 @@ class Solver:
         off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
         cen = np.ascontiguousarray(np.concatenate([np.asarray(c["centers"], float) for c in cells]).reshape(-1))
         th = np.ascontiguousarray(np.concatenate([np.asarray(c["theta"], float) for c in cells]))
-        aa = np.ascontiguousarray(np.concatenate([np.asarray(c["a"], float) for c in cells]))
-        bb = np.ascontiguousarray(np.concatenate([np.asarray(c["b"], float) for c in cells]))
         nn = np.ascontiguousarray(np.concatenate([np.asarray(c["n_nodes"]) for c in cells]).astype(np.int32))
         ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
-        self._check(lib().spm_set_cells(self.h, len(cells), _dp(skews), ip(off), _dp(cen), _dp(th), _dp(aa), _dp(bb),
-                                        ip(nn)))
+        if any("kind" in c for c in cells):
+            shapes = [self._shape_arrays(c) for c in cells]
+            kind = np.ascontiguousarray(np.concatenate([k for k, _ in shapes]).astype(np.int32))
+            prm = np.ascontiguousarray(np.concatenate([p for _, p in shapes]).reshape(-1))
+            self._check(lib().spm_set_cells_shapes(self.h, len(cells), _dp(skews), ip(off), _dp(cen), _dp(th),
+                                                   ip(kind), _dp(prm), ip(nn)))
+        else:
+            aa = np.ascontiguousarray(np.concatenate([np.asarray(c["a"], float) for c in cells]))
+            bb = np.ascontiguousarray(np.concatenate([np.asarray(c["b"], float) for c in cells]))
+            self._check(lib().spm_set_cells(self.h, len(cells), _dp(skews), ip(off), _dp(cen), _dp(th), _dp(aa),
+                                            _dp(bb), ip(nn)))
         n = ctypes.c_int64()
         self._check(lib().spm_num_nodes(self.h, ctypes.byref(n)))
         self.N = int(n.value)

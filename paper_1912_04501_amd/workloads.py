@@ -281,6 +281,20 @@ def two_stars(s=0.25, A=0.5, omega=1.0, second_theta=0.0, n_nodes=256):
                  name=f"two_stars_s{s}_A{A}_w{omega:g}")
 
 
+def star_and_ellipse(gap=2e-2, s=0.15, A=0.3, omega=3.0, n_star=192, n_ellipse=128, skew=0.2):
+    """A three-armed star (r = s (1 + A cos(omega t))) beside an ellipse with semi-axes
+    (0.2, 0.1), boundary gap `gap` along x between the star's arm tip and the ellipse's
+    vertex: a cell that mixes both particle kinds."""
+    rmax = s * (1.0 + abs(A))
+    sep = rmax + 0.2 + gap
+    c = np.array([[-sep / 2, 0.05], [sep / 2, 0.05]])
+    return {"name": f"star_and_ellipse_d{gap:g}", "skew": float(skew), "centers": c,
+            "theta": np.array([0.0, 0.0]), "kind": np.array([1, 0], dtype=np.int32),
+            "params": np.array([[s, A, omega, 0.0], [0.2, 0.1, 0.0, 0.0]]),
+            "a": np.array([rmax, 0.2]), "b": np.array([s * (1.0 - abs(A)), 0.1]),
+            "n_nodes": np.array([n_star, n_ellipse], dtype=np.int32), "mu": 1.0, "gamma": 1.0}
+
+
 def random_density(n_total, seed=7):
     """sigma ~ N(0, 1), SoA [sigma_1(0..N-1), sigma_2(0..N-1)]."""
     return np.random.default_rng(seed).standard_normal(2 * int(n_total))

@@ -35,6 +35,8 @@ CASES = {
     "two_ellipses_gap3e-2_N128": lambda: W.two_ellipses(3e-2, n_nodes=128),
     "two_ellipses_gap1e-2_N256_skew0.3": lambda: W.two_ellipses(1e-2, n_nodes=256, skew=0.3),
     "random_6_phi0.3_skew_ragged": lambda: W.random_ellipses(6, 0.3, seed=5, nodes=None, target_total=700),
+    "two_stars_N128": lambda: W.two_stars(n_nodes=128),
+    "star_and_ellipse_gap2e-2_skew0.2": lambda: W.star_and_ellipse(),
 }
 
 
