@@ -121,9 +121,21 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy three times (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["ellipses200", "ensemble64", "learned"], default="ellipses200",
+    ap.add_argument("--workload", choices=["ellipses200", "ensemble64", "learned", "jamming"],
+                    default="ellipses200",
                     help="ellipses200: the 200-ellipse cell (default); ensemble64: 64 independent cells in one "
-                         "launch; learned: time stepping with the trained warm-start network")
+                         "launch; learned: time stepping with the trained warm-start network; jamming: two "
+                         "star-shaped particles sheared into contact (Sec. 8 Examples 4 and 5)")
+    ap.add_argument("--example", type=int, choices=[4, 5], default=4, help="jamming: which of the two runs")
+    ap.add_argument("--nodes", type=int, default=2500, help="jamming: nodes per star")
+    ap.add_argument("--omega", type=int, default=4, help="jamming: arms of each star, r = s (1 + cos(omega t)/2)")
+    ap.add_argument("--full-series", action="store_true", help="jamming: every step of mu_eff(t) in the JSON line")
+    ap.add_argument("--jam-tol", type=float, default=1e-9,
+                    help="jamming: GMRES tolerance (the FP64 residual floor reaches 2e-10 at mu_eff ~ 1e5)")
+    ap.add_argument("--dt", type=float, default=5e-4, help="jamming: forward Euler step")
+    ap.add_argument("--t-end", type=float, default=None, help="jamming: last time (default 0.46 / 0.475)")
+    ap.add_argument("--window", type=float, nargs=2, default=None,
+                    help="jamming: fit window (default: the example's, and the same width before the run's end)")
     args = ap.parse_args()
     if args.precision is None:
         args.precision = "fp32_relaxed" if args.workload == "ensemble64" else "fp32_ir"
@@ -151,6 +163,8 @@ def main():
         return bench_ensemble(args)
     if args.workload == "learned":
         return bench_learned(args)
+    if args.workload == "jamming":
+        return bench_jamming(args)
     t0 = time.perf_counter()
     wl = W.ellipses_200()
     log(f"[bench] workload {wl['name']} generated in {time.perf_counter() - t0:.1f}s")
@@ -396,6 +410,127 @@ def bench_learned(args):
            "training": {"samples": int(X.shape[0]), "solves": solves, "data_s": t_data, "train_s": t_train,
                         "adam_steps": int(len(losses)), "final_loss": float(np.mean(losses[-100:]))},
            "variants": res, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+# Sec. 8: the two runs' stars, centres (1/4, 1/4) and (3/4, 3/4) of the unit cell, and the
+# fit window and published fit of mu_eff(t) ~ c |t - t*|^(-beta) (context only)
+JAMMING = {4: {"s": 0.25, "second_theta": 0.0, "t_end": 0.46, "window": (0.40, 0.44),
+               "paper": {"c": 2.187, "t_star": 0.458, "beta": 2.431}},
+           5: {"s": 0.275, "second_theta": 0.7853981633974483, "t_end": 0.475, "window": (0.40, 0.45),
+               "paper": {"c": 12.16, "t_star": 0.472, "beta": 1.31}}}
+
+
+def fit_blowup(t, mu):
+    """Nonlinear least squares of mu = c |t - t*|^(-beta) in relative residuals, t* beyond
+    the last sample; returns (c, t*, beta, relative residual 2-norm)."""
+    import numpy as np
+    from scipy.optimize import least_squares
+
+    t = np.asarray(t, float)
+    mu = np.asarray(mu, float)
+
+    def res(p):
+        c, ts, be = p
+        return (c * np.abs(ts - t) ** (-be) - mu) / mu
+
+    best = None
+    for ts0 in t[-1] + np.array([0.005, 0.02, 0.05, 0.1]):
+        for be0 in (1.0, 2.0, 3.0):
+            c0 = float(np.median(mu * np.abs(ts0 - t) ** be0))
+            r = least_squares(res, [c0, ts0, be0], bounds=([0.0, t[-1] + 1e-9, 0.0], [np.inf, 10.0, 20.0]))
+            if best is None or r.cost < best.cost:
+                best = r
+    c, ts, be = best.x
+    return float(c), float(ts), float(be), float(np.linalg.norm(best.fun) / np.sqrt(len(t)))
+
+
+def bench_jamming(args):
+    """Forward Euler of two star-shaped particles r = s (1 + cos(t)/2) in a unit cell
+    sheared at rate 1 (Sec. 7, Sec. 8 Examples 4 and 5), plain FP64 GMRES to 1e-10 every
+    step, until the particles jam: mu_eff(t) blows up and the solve or the gap check
+    stops the run. value = time steps per second; the fit of mu_eff(t) on the examples'
+    window is reported beside it with the paper's fit as context."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04501_amd import spm
+    from paper_1912_04501_amd import workloads as W
+    ex = JAMMING[args.example]
+    t_end = ex["t_end"] if args.t_end is None else args.t_end
+    wl = W.two_stars(s=ex["s"], A=0.5, omega=float(args.omega), second_theta=ex["second_theta"], n_nodes=args.nodes)
+    s = spm.Solver("cuda:0", precision=spm.SPM_FP64, max_iter=2000, tol=args.jam_tol)
+    s.set_workload(wl)
+    c, th, t = np.array(wl["centers"], float), np.array(wl["theta"], float), 0.0
+    ts, mus, its, gaps = [], [], [], []
+    n_total = int(round(t_end / args.dt))
+    chunk = 20
+    stop = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while len(mus) < n_total and stop is None:
+        n = min(chunk, n_total - len(mus))
+        try:
+            r = s.step(args.dt, n, t, c, th)
+        except spm.SpmError:
+            # replay the chunk one step at a time from its start to keep every good step
+            # (a failed step leaves the handle without particles: set the chunk's start again)
+            for _ in range(n):
+                try:
+                    s.set_workload(dict(wl, centers=c, theta=th, skew=wl["skew"] + t))
+                    r = s.step(args.dt, 1, t, c, th)
+                except spm.SpmError as e:
+                    stop = f"{e} at t = {t:.5f}"
+                    break
+                ts.append(t)
+                mus.append(float(r["mu_eff"][0]))
+                its.append(r["infos"][0]["iterations"])
+                gaps.append(r["infos"][0]["min_gap"])
+                c, th, t = r["centers"], r["theta"], r["t"]
+            break
+        ts += [t + k * args.dt for k in range(n)]
+        mus += r["mu_eff"].tolist()
+        its += [i["iterations"] for i in r["infos"]]
+        gaps += [i["min_gap"] for i in r["infos"]]
+        c, th, t = r["centers"], r["theta"], r["t"]
+        log(f"[jam] t = {t:.4f} mu_eff = {mus[-1]:.6g} its = {its[-1]} gap = {gaps[-1]:.3e}")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ts, mus = np.array(ts), np.array(mus)
+
+    def fit_on(lo, hi):
+        w = (ts >= lo - 1e-12) & (ts <= hi + 1e-12)
+        if w.sum() < 5:
+            return None
+        cf, tsf, bf, rr = fit_blowup(ts[w], mus[w])
+        return {"c": cf, "t_star": tsf, "beta": bf, "rel_residual": rr, "window": [lo, hi], "samples": int(w.sum())}
+
+    lo, hi = ex["window"] if args.window is None else args.window
+    fit = fit_on(lo, hi)
+    # the same window width ending as far before this run's last step as the paper's
+    # window ends before its t*
+    lead = ex["paper"]["t_star"] - ex["window"][1]
+    width = ex["window"][1] - ex["window"][0]
+    fit_end = fit_on(ts[-1] - lead - width, ts[-1] - lead) if len(ts) else None
+    every = 1 if args.full_series else max(1, len(ts) // 40)
+    out = {"metric": f"time steps/s (two-star jamming, Sec. 8 Example {args.example}, FP64 residual {args.jam_tol:g})",
+           "value": len(mus) / secs, "unit": "steps/s", "n_gpus": 1, "steps": len(mus), "warmup": 0,
+           "ms_per_step": 1e3 * secs / max(1, len(mus)), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"two_stars_example{args.example}", "nodes_per_star": args.nodes, "dt": args.dt,
+                      "tol": args.jam_tol,
+                      "t_end": t_end, "s": ex["s"], "A": 0.5, "omega": args.omega,
+                      "second_theta": ex["second_theta"]},
+           "stopped": stop, "t_last": float(ts[-1]) if len(ts) else 0.0,
+           "state_end": {"t": float(t), "centers": np.asarray(c).reshape(-1).tolist(),
+                         "theta": np.asarray(th).tolist()},
+           "iterations": {"first": its[0] if its else None, "last": its[-1] if its else None,
+                          "max": max(its) if its else None},
+           "mu_eff_series": [[float(a), float(b), float(g)] for a, b, g in zip(ts[::every], mus[::every],
+                                                                             gaps[::every])]
+           + ([[float(ts[-1]), float(mus[-1]), float(gaps[-1])]] if len(ts) else []),
+           "fit": fit, "fit_before_end": fit_end, "paper_fit": ex["paper"], "roofline": None,
+           "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 

@@ -73,7 +73,8 @@ extern "C" {
                                 (the smooth star-shaped curves of Sec. 8 Examples 2 and 4) */
 
 #define SPM_PRECOND_NONE 0
-#define SPM_PRECOND_BLOCK 1  /* right preconditioner blockdiag(B_q)^-1 of isolated-body self blocks */
+#define SPM_PRECOND_BLOCK 1  /* right preconditioner blockdiag(B_q)^-1 of isolated-body self blocks
+                                (particles of at most 512 nodes; SPM_EINVAL at the solve otherwise) */
 
 typedef struct spm_handle spm_handle;
 typedef struct spm_mlp spm_mlp;
@@ -115,6 +116,10 @@ typedef struct {
   int32_t fallback;        /* 1 if the warm-started/preconditioned attempt failed and plain
                               GMRES (zero guess, no preconditioner) produced the result */
   int32_t first_iterations;/* iterations of that failed attempt (0 without fallback) */
+  double min_gap;          /* smallest distance between nodes of different particles (any
+                              images, every cell of the handle): the boundary gap to within
+                              the node spacing; 1e300 when no two particles come within the
+                              close-evaluation reach */
 } spm_solve_info;
 
 typedef void* (*spm_alloc_fn)(size_t bytes, void* stream, void* ctx);
@@ -138,7 +143,7 @@ int spm_set_lattice(spm_handle* h, const double e1_host[2], const double e2_host
 
 /* Ellipses (Sec. 2 geometry; Sec. 6 periodic trapezoid rule). Host arrays of
  * length n: centres [2n] (x0, y0, x1, y1, ...), theta, semi-axes a and b, node
- * counts (even, 8 <= N_i <= 512). Centres are wrapped into the cell. Builds
+ * counts (even, 8 <= N_i <= 4096). Centres are wrapped into the cell. Builds
  * the nodes, the proxy pseudo-inverse and the close-pair list. Returns
  * SPM_EOVERLAP if two boundaries (any images) come within cfg.min_gap or
  * overlap. */
@@ -184,9 +189,12 @@ int spm_effective_viscosity(spm_handle* h, const double* sigma, double* mu_eff);
  * elapsed time. centers_inout [2n], theta_inout [n] (host) hold the state;
  * mu_eff_series_host [n_steps] receives mu_eff(t_k); infos_host [n_steps] may be NULL.
  * The initial guess of every solve follows cfg.x0 (SPM_X0_PREVIOUS: the previous step's
- * density). If a step fails (e.g. SPM_EOVERLAP when particles collide), the state,
- * *t_inout and the series hold the last state reached: (t_out - t_in) / dt steps were
- * completed, and the handle must be given particles again before further calls. */
+ * density). If a step fails (SPM_EOVERLAP when particles collide or come closer than
+ * cfg.min_gap, SPM_ENOCONV when GMRES does not converge), the state and *t_inout hold the
+ * state that step was solving: (t_out - t_in) / dt steps were completed, their series
+ * entries are set, and infos_host of the failing step holds its info after a solve. The
+ * handle is then left without particles (SPM_ESTATE until particles and lattice are
+ * given again). */
 int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double* centers_inout_host,
              double* theta_inout_host, double* mu_eff_series_host, spm_solve_info* infos_host);
 
@@ -309,7 +317,8 @@ int spm_features(spm_handle* h, float* features);
 /* Training targets [n x 128] (FP32, device) of a density sigma [2N]: sigma minus its
  * cell-wide normal component beta* n (beta* = <sigma, n>/<n, n> per cell), rotated into
  * each particle's body frame, divided by mu gamma, as the discrete Fourier
- * coefficients c_m, m = -32..31 (real parts, then imaginary parts). */
+ * coefficients c_m, m = -32..31 (real parts, then imaginary parts). Particles of at
+ * most 512 nodes (SPM_EINVAL otherwise). */
 int spm_density_modes(spm_handle* h, const double* sigma, float* modes);
 
 /* Warm start from coefficients [n x 128] (device FP32): decode to the nodes (g), then per

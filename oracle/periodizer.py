@@ -176,3 +176,52 @@ def correction_vorticity(P, xi, xt, mu):
     fx = xi_to_forces(xi)
     r = xt[:, None, :] - P[None, :, :]
     return vorticity_apply(r, fx[None], mu).sum(1)
+
+
+def proxy_data_extended(geom, W, f, mu, rng=1):
+    """g0 - g (steps 2 and 3) in extended precision (numpy longdouble: a 64-bit significand
+    on x86-64), from the same telescoped sums as `discrepancy` and `g0_vector`.
+
+    Test reference for the rounding of an FP64 evaluation: g is small against the sum of
+    its terms' sizes, and the least-squares step amplifies its rounding by |Q+| (about
+    1e6), so the accuracy of xi is set by how g and F are summed."""
+    LD = np.longdouble
+    pi = 4 * np.arctan(LD(1))
+    e1, e2 = geom.e1.astype(LD), geom.e2.astype(LD)
+    y = geom.x.astype(LD)
+    fl = np.asarray(f).astype(LD)
+    ks = [LD(k) for k in range(-rng, rng + 1)]
+
+    def field(x, nrm, shifts):
+        u = np.zeros((len(x), 2), LD)
+        t = np.zeros((len(x), 2), LD)
+        for s in shifts:
+            r = x[:, None, :] - (y[None, :, :] + s)
+            rr = (r * r).sum(-1)
+            rf = (r * fl[None]).sum(-1)
+            rn = (r * nrm[None, None, :]).sum(-1)
+            u += ((-LD(0.5) * np.log(rr))[..., None] * fl[None] + r * (rf / rr)[..., None]).sum(1)
+            t += (r * (rn * rf / (rr * rr))[..., None]).sum(1)
+        return u / (4 * pi * LD(mu)), -t / pi
+
+    out = []
+    for (x, nrm, far, near) in ((W["xL"], W["nL"], [-(rng + 1) * e1 + k * e2 for k in ks],
+                                 [rng * e1 + k * e2 for k in ks]),
+                                (W["xD"], W["nD"], [k * e1 - (rng + 1) * e2 for k in ks],
+                                 [k * e1 + rng * e2 for k in ks])):
+        xl, nl = x.astype(LD), nrm.astype(LD)
+        uf, tf = field(xl, nl, far)
+        un, tn = field(xl, nl, near)
+        du, dt = uf - un, tf - tn
+        out += [du[:, 0], du[:, 1], dt[:, 0], dt[:, 1]]
+    g = np.concatenate(out)
+    F = fl.sum(0)
+    m = W["m"]
+    g0 = np.zeros(8 * m, LD)
+    l2 = np.sqrt((e2 * e2).sum())
+    l1 = np.sqrt((e1 * e1).sum())
+    g0[2 * m:3 * m] = -F[0] / (2 * l2)
+    g0[3 * m:4 * m] = -F[1] / (2 * l2)
+    g0[6 * m:7 * m] = -F[0] / (2 * l1)
+    g0[7 * m:8 * m] = -F[1] / (2 * l1)
+    return g0 - g

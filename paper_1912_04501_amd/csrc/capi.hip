@@ -276,7 +276,7 @@ void build_chunks(spm_handle* h) {
   upload(h, W.disc_s1, s1.data(), s1.size() * sizeof(int64_t));
   upload(h, W.disc_cell, cc.data(), cc.size() * sizeof(int32_t));
   upload(h, W.disc_off, off.data(), off.size() * sizeof(int32_t));
-  ensure(h, W.disc, (size_t)W.ndisc * 2 * h->per.m * 4);
+  ensure(h, W.disc, (size_t)W.ndisc * 2 * h->per.m * 8);
   Krylov& K = h->kr;
   K.nseg = (int32_t)n0.size();
   ensure(h, K.seg_n0, n0.size());
@@ -433,7 +433,7 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
       }
       if (!ok) throw ApiError(SPM_EINVAL, "bad particle " + std::to_string(i));
       if (n_nodes[i] < 8 || n_nodes[i] > kMaxNodesPerParticle || (n_nodes[i] & 1))
-        throw ApiError(SPM_EINVAL, "node count must be even and in [8, 512]");
+        throw ApiError(SPM_EINVAL, "node count must be even and in [8, 4096]");
       shape_radii(kind[i], pp, h->a[i], h->b[i]);
       if (h->a[i] >= 0.45) throw ApiError(SPM_EINVAL, "particle larger than the 3x3 image rule allows");
       // wrap: (alpha, beta) = [e1 e2]^{-1} (c - c_U), reduced to [-1/2, 1/2)
@@ -457,7 +457,7 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   g.nmax = *std::max_element(h->nn.begin(), h->nn.end());
   const int64_t N = g.N;
   if (N > (int64_t)1 << 30) throw ApiError(SPM_EINVAL, "too many nodes");
-  for (double** p : {&g.x, &g.y, &g.nx, &g.ny, &g.w, &g.kap, &g.tx, &g.ty, &g.xpx, &g.xpy}) ensure(h, *p, N);
+  for (double** p : {&g.x, &g.y, &g.nx, &g.ny, &g.w, &g.kap, &g.tx, &g.ty, &g.xpx, &g.xpy, &g.dcot}) ensure(h, *p, N);
   for (float** p : {&g.xf, &g.yf, &g.nxf, &g.nyf}) ensure(h, *p, N);
   ensure(h, g.pid, N);
   ensure(h, g.ncell, N);
@@ -922,10 +922,9 @@ int solve_api(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
   const double t2 = now();
   std::vector<unsigned long long> stamps(C + 1);
   download(h, stamps.data(), h->kr.stamp, (C + 1) * sizeof(unsigned long long));
-  int32_t npairs_cell = 0;
-  (void)npairs_cell;
   for (int c = 0; c < C; ++c) {
     infos[c].n_close_pairs = (int32_t)h->cl.npairs;
+    infos[c].min_gap = h->min_gap_est;
     infos[c].seconds_solve = t1 - t0;
     infos[c].seconds_readout = t2 - t1;
     if (latency_out) latency_out[c] = (double)(stamps[c] - stamps[C]) / h->wallclock_hz;
@@ -1434,12 +1433,18 @@ int spm_step_record(spm_handle* h, double dt, int32_t n_steps, double* t_inout, 
       const double sk = s0 + h->cfg.gamma * (k * dt);
       const int32_t off[2] = {0, n};
       *t_inout = t0 + k * dt;   // time of the state being solved (kept if this step fails)
+      // a failure leaves the handle without particles (its lattice is the failing step's)
+      h->have_particles = false;
       set_cells_impl(h, 1, &sk, off, centers, theta, kind.data(), prm.data(), nn.data());
       sig = h->kr.stepbuf;  // (buffers are stable: same sizes)
       spm_solve_info info;
       const double* guess = (h->cfg.x0 == SPM_X0_PREVIOUS && have_prev) ? sig : nullptr;
       const int rc = solve_api(h, guess, sig, vel, om, mu, &info, nullptr);
-      if (rc && rc != SPM_ENOCONV) return rc;
+      if (infos) infos[k] = info;
+      if (rc) {   // the state stays the one solved at *t_inout
+        h->have_particles = false;
+        return rc;
+      }
       have_prev = true;
       if (features) launch_features(h, features + (int64_t)k * n * SPM_MLP_IN);
       if (targets) {
@@ -1449,13 +1454,11 @@ int spm_step_record(spm_handle* h, double dt, int32_t n_steps, double* t_inout, 
       }
       download(h, hv.data(), vel, (3 * n + 1) * sizeof(double));
       mu_series[k] = hv[3 * n];
-      if (infos) infos[k] = info;
       for (int i = 0; i < n; ++i) {
         centers[2 * i] = h->cx[i] + dt * hv[2 * i];
         centers[2 * i + 1] = h->cy[i] + dt * hv[2 * i + 1];
         theta[i] += dt * hv[2 * n + i];
       }
-      if (rc == SPM_ENOCONV) return rc;
     }
     *t_inout = t0 + n_steps * dt;
     h->cells[0].skew_raw = s0 + h->cfg.gamma * n_steps * dt;

@@ -25,81 +25,99 @@ __device__ __forceinline__ cplx cinv(cplx a) {
   return {a.re * d, -a.im * d};
 }
 
-// One block per particle: v+ of the three densities, written to vp[6][N].
+// v+ of the three densities, written to vp[6][N]. Block (q, by) takes the nodes
+// j in [by R, by R + R) of particle q (R = blockDim / L rows, L lanes per node); the source
+// nodes pass through LDS in tiles of kVplusTile. Lane `sub` of a node takes k = sub, sub + L,
+// ... (tile sizes are multiples of L) and the lanes' sums are combined by a fixed butterfly.
 __global__ __launch_bounds__(1024) void k_vplus(int64_t N, Geo g, const double* __restrict__ sigma, int L,
                                                 double* __restrict__ vp) {
-  __shared__ double s_yr[kMaxNodesPerParticle], s_yi[kMaxNodesPerParticle];
-  __shared__ double s_wr[kMaxNodesPerParticle], s_wi[kMaxNodesPerParticle];
-  __shared__ double s_ph[6][kMaxNodesPerParticle];
-  __shared__ double s_d[kMaxNodesPerParticle];
+  __shared__ double s_yr[kVplusTile], s_yi[kVplusTile];
+  __shared__ double s_wr[kVplusTile], s_wi[kVplusTile];
+  __shared__ double s_ph[6][kVplusTile];
   const int q = blockIdx.x;
   const int o = g.poff[q], n = g.pn[q];
+  const int R = blockDim.x / L;
+  const int j = blockIdx.y * R + threadIdx.x / L;
+  if (blockIdx.y * R >= n) return;   // whole block: this particle has fewer nodes
   const double cx = g.pcx[q], cy = g.pcy[q];
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const int64_t i = o + k;
-    s_yr[k] = g.x[i];
-    s_yi[k] = g.y[i];
-    // W = y' / (i n) = (y'_im - i y'_re) / n
-    s_wr[k] = g.xpy[i] / (double)n;
-    s_wi[k] = -g.xpx[i] / (double)n;
-    const double t1 = g.tx[i], t2 = g.ty[i];
-    const double sg1 = sigma[i], sg2 = sigma[N + i];
-    const double f[3] = {sg1, sg2, (g.x[i] - cx) * sg1 + (g.y[i] - cy) * sg2};
-    for (int d = 0; d < 3; ++d) {  // phi = f conj(tau)
-      s_ph[2 * d][k] = f[d] * t1;
-      s_ph[2 * d + 1][k] = -f[d] * t2;
-    }
-    // differentiation weights by distance m = k (k = 0 unused)
-    if (k > 0) {
-      const double c = cos(kPi * (double)k / (double)n) / sin(kPi * (double)k / (double)n);
-      s_d[k] = ((k & 1) ? -0.5 : 0.5) * c;
-    } else {
-      s_d[0] = 0.0;
-    }
-  }
-  __syncthreads();
-  // L lanes per node j: lane `sub` takes k = sub, sub + L, ...; the groups' sums are combined
-  // by a fixed butterfly
+  const bool own = j < n;
   const int sub = threadIdx.x % L;
-  for (int j = threadIdx.x / L; j < n; j += blockDim.x / L) {
-    const double yjr = s_yr[j], yji = s_yi[j];
-    double acc[6] = {0, 0, 0, 0, 0, 0};
-    double der[6] = {0, 0, 0, 0, 0, 0};
-    const double pj[6] = {s_ph[0][j], s_ph[1][j], s_ph[2][j], s_ph[3][j], s_ph[4][j], s_ph[5][j]};
-    for (int k = sub; k < n; k += L) {
-      if (k == j) continue;
-      const cplx u = cmul({s_wr[k], s_wi[k]}, cinv({s_yr[k] - yjr, s_yi[k] - yji}));
-      const int dm = j - k >= 0 ? j - k : j - k + n;
-      const double dw = s_d[dm];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const cplx dp = {s_ph[2 * d][k] - pj[2 * d], s_ph[2 * d + 1][k] - pj[2 * d + 1]};
-        const cplx t = cmul(dp, u);
-        acc[2 * d] += t.re;
-        acc[2 * d + 1] += t.im;
-        der[2 * d] += dw * s_ph[2 * d][k];
-        der[2 * d + 1] += dw * s_ph[2 * d + 1][k];
-      }
-    }
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      acc[d] = group_sum(acc[d], L);
-      der[d] = group_sum(der[d], L);
-    }
-    if (sub != 0) continue;
+  double yjr = 0, yji = 0, pj[6] = {0, 0, 0, 0, 0, 0};
+  if (own) {   // phi = f conj(tau) at node j
     const int64_t i = o + j;
+    yjr = g.x[i];
+    yji = g.y[i];
+    const double t1 = g.tx[i], t2 = g.ty[i], sg1 = sigma[i], sg2 = sigma[N + i];
+    const double f[3] = {sg1, sg2, (yjr - cx) * sg1 + (yji - cy) * sg2};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      // phi' / (i n) = (phi'_im - i phi'_re) / n
-      vp[(2 * d) * N + i] = acc[2 * d] + der[2 * d + 1] / (double)n;
-      vp[(2 * d + 1) * N + i] = acc[2 * d + 1] - der[2 * d] / (double)n;
+      pj[2 * d] = f[d] * t1;
+      pj[2 * d + 1] = -f[d] * t2;
     }
+  }
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double der[6] = {0, 0, 0, 0, 0, 0};
+  for (int kb = 0; kb < n; kb += kVplusTile) {
+    const int nt = min(kVplusTile, n - kb);
+    __syncthreads();   // the previous tile has been consumed
+    for (int k = threadIdx.x; k < nt; k += blockDim.x) {
+      const int64_t i = o + kb + k;
+      s_yr[k] = g.x[i];
+      s_yi[k] = g.y[i];
+      // W = y' / (i n) = (y'_im - i y'_re) / n
+      s_wr[k] = g.xpy[i] / (double)n;
+      s_wi[k] = -g.xpx[i] / (double)n;
+      const double t1 = g.tx[i], t2 = g.ty[i], sg1 = sigma[i], sg2 = sigma[N + i];
+      const double f[3] = {sg1, sg2, (g.x[i] - cx) * sg1 + (g.y[i] - cy) * sg2};
+      for (int d = 0; d < 3; ++d) {
+        s_ph[2 * d][k] = f[d] * t1;
+        s_ph[2 * d + 1][k] = -f[d] * t2;
+      }
+    }
+    __syncthreads();
+    if (own) {
+      for (int kk = sub; kk < nt; kk += L) {
+        const int k = kb + kk;
+        if (k == j) continue;
+        const cplx u = cmul({s_wr[kk], s_wi[kk]}, cinv({s_yr[kk] - yjr, s_yi[kk] - yji}));
+        const int dm = j - k >= 0 ? j - k : j - k + n;
+        const double dw = g.dcot[o + dm];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const cplx dp = {s_ph[2 * d][kk] - pj[2 * d], s_ph[2 * d + 1][kk] - pj[2 * d + 1]};
+          const cplx t = cmul(dp, u);
+          acc[2 * d] += t.re;
+          acc[2 * d + 1] += t.im;
+          der[2 * d] += dw * s_ph[2 * d][kk];
+          der[2 * d + 1] += dw * s_ph[2 * d + 1][kk];
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 6; ++d) {
+    acc[d] = group_sum(acc[d], L);
+    der[d] = group_sum(der[d], L);
+  }
+  if (!own || sub != 0) return;
+  const int64_t i = o + j;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    // phi' / (i n) = (phi'_im - i phi'_re) / n
+    vp[(2 * d) * N + i] = acc[2 * d] + der[2 * d + 1] / (double)n;
+    vp[(2 * d + 1) * N + i] = acc[2 * d + 1] - der[2 * d] / (double)n;
   }
 }
 
+// Lanes per node of k_vplus: enough rows for the largest curve in one 1024-thread block
+// while curves fit one block; above that, 16 lanes and more blocks per particle.
+inline int vplus_lanes(int nmax) { return nmax <= kVplusTile ? lanes_per_row(nmax) : 16; }
+
 void launch_vplus(spm_handle* h, const double* sigma) {
-  const int L = lanes_per_row(h->geo.nmax);
-  k_vplus<<<h->geo.No, 1024, 0, h->stream>>>(h->geo.N, h->geo, sigma, L, h->cl.vp);
+  const int L = vplus_lanes(h->geo.nmax);
+  const int R = 1024 / L;
+  const dim3 grid((unsigned)h->geo.No, (unsigned)((h->geo.nmax + R - 1) / R));
+  k_vplus<<<grid, 1024, 0, h->stream>>>(h->geo.N, h->geo, sigma, L, h->cl.vp);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

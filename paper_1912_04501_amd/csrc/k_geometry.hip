@@ -36,6 +36,9 @@ __global__ void k_geometry(int64_t N, const int32_t* __restrict__ pid, const int
   g.ny[i] = -tx;
   g.w[i] = 2.0 * kPi * sp / (double)n;
   g.kap[i] = (dx * ddy - dy * ddx) / (sp * sp * sp);
+  // spectral derivative weight at index distance k (N_p even): (1/2) (-1)^k cot(k pi / N_p), 0 at k = 0
+  g.dcot[i] = k > 0 ? ((k & 1) ? -0.5 : 0.5) * (cos(kPi * (double)k / (double)n) / sin(kPi * (double)k / (double)n))
+                    : 0.0;
   g.xf[i] = (float)x;
   g.yf[i] = (float)y;
   g.nxf[i] = (float)ty;

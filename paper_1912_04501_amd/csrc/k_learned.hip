@@ -100,7 +100,7 @@ __device__ __forceinline__ void twiddle(int m, int k, int n, double& c, double& 
 __global__ __launch_bounds__(128) void k_modes(Geo g, const double* __restrict__ sigma,
                                                const double* __restrict__ num, const double* __restrict__ den,
                                                double inv_mg, float* __restrict__ modes) {
-  __shared__ double s1[kMaxNodesPerParticle], s2[kMaxNodesPerParticle];
+  __shared__ double s1[kMaxNodesStaged], s2[kMaxNodesStaged];
   const int q = blockIdx.x;
   const int64_t i0 = g.poff[q];
   const int n = g.pn[q];
@@ -130,6 +130,8 @@ __global__ __launch_bounds__(128) void k_modes(Geo g, const double* __restrict__
 }
 
 void launch_modes(spm_handle* h, const double* sigma, const double* num, const double* den, float* modes) {
+  if (h->geo.nmax > kMaxNodesStaged)
+    throw ApiError(SPM_EINVAL, "density modes need at most " + std::to_string(kMaxNodesStaged) + " nodes per particle");
   k_modes<<<h->geo.No, 128, 0, h->stream>>>(h->geo, sigma, num, den, 1.0 / (h->cfg.mu * h->cfg.gamma), modes);
   SPM_HIP_CHECK(hipGetLastError());
 }

@@ -17,10 +17,11 @@ __global__ __launch_bounds__(256) void k_prep(int64_t N, Geo g, const double* __
                                               double* __restrict__ f1, double* __restrict__ f2,
                                               float* __restrict__ f1f, float* __restrict__ f2f,
                                               double* __restrict__ pF) {
-  __shared__ double sc[16];
+  __shared__ double sc[32];
   const int q = blockIdx.x;
   const double cx = g.pcx[q], cy = g.pcy[q];
-  double F1 = 0, F2 = 0, tq = 0, st = 0;
+  dd F1 = {0, 0}, F2 = {0, 0};   // the net force is small against its terms and feeds the proxy solve
+  double tq = 0, st = 0;
   for (int64_t i = g.poff[q] + threadIdx.x; i < g.poff[q + 1]; i += blockDim.x) {
     const double w = g.w[i], s1 = sigma[i], s2 = sigma[N + i];
     const double a = w * s1, b = w * s2;
@@ -29,18 +30,18 @@ __global__ __launch_bounds__(256) void k_prep(int64_t N, Geo g, const double* __
     f1f[i] = (float)a;
     f2f[i] = (float)b;
     const double rx = g.x[i] - cx, ry = g.y[i] - cy;
-    F1 += a;
-    F2 += b;
+    F1 = dd_add_d(F1, a);
+    F2 = dd_add_d(F2, b);
     tq += -ry * a + rx * b;
     st += rx * b + ry * a;
   }
-  F1 = block_sum(F1, sc);
-  F2 = block_sum(F2, sc);
+  F1 = dd_block_sum(F1, sc);
+  F2 = dd_block_sum(F2, sc);
   tq = block_sum(tq, sc);
   st = block_sum(st, sc);
   if (threadIdx.x == 0) {
-    pF[4 * q + 0] = F1;
-    pF[4 * q + 1] = F2;
+    pF[4 * q + 0] = F1.hi + F1.lo;
+    pF[4 * q + 1] = F2.hi + F2.lo;
     pF[4 * q + 2] = tq;
     pF[4 * q + 3] = st;
   }

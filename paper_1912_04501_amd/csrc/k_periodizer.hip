@@ -276,8 +276,10 @@ void launch_pinv(spm_handle* h) {
 // Wall discrepancy (step 2), telescoped: at a point x_L of L,
 //   u_near(x_L+e1) - u_near(x_L) = sum_j sum_{n=-1..1} [G(x_L, y_j - 2e1 + n e2) - G(x_L, y_j + e1 + n e2)] f_j
 // and on D with the roles of e1, e2 exchanged; the same with G^t(.; n_wall).
-// Grid (chunks, 2m): block (c, w) sums its source chunk for wall point w; partials
-// disc[c][w][4] = (du1, du2, dT1, dT2) are summed in fixed order by k_xi.
+// Grid (chunks, 2m): block (c, w) sums its source chunk for wall point w in double-double
+// (the result is small against the sum of the terms' sizes and Q+ amplifies its rounding);
+// partials disc[c][w][8] = (du1, du2, dT1, dT2) hi parts then lo parts, summed in fixed
+// order by k_xi.
 // ----------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __restrict__ cskew,
                                               const double* __restrict__ wx_all, const double* __restrict__ wy_all,
@@ -286,7 +288,7 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
                                               const int64_t* __restrict__ cs0, const int64_t* __restrict__ cs1,
                                               const int32_t* __restrict__ ccell, const int32_t* __restrict__ active,
                                               double* __restrict__ disc) {
-  __shared__ double sc[16];
+  __shared__ double sc[32];
   const int chunk = blockIdx.x;
   const int wpt = blockIdx.y;
   const int cell = ccell[chunk];
@@ -299,7 +301,7 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
   const double ax = onD ? CL.e2x : 1.0, ay = onD ? 1.0 : 0.0;   // across the wall pair
   const double bx = onD ? 1.0 : CL.e2x, by = onD ? 0.0 : 1.0;   // along the wall
   const int64_t j0 = cs0[chunk], j1 = cs1[chunk];
-  double u1 = 0, u2 = 0, t1 = 0, t2 = 0;
+  dd u1 = {0, 0}, u2 = {0, 0}, t1 = {0, 0}, t2 = {0, 0};
   for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
     const double yj = x[j], zj = y[j], g1 = f1[j], g2 = f2[j];
     for (int n = -1; n <= 1; ++n) {
@@ -308,25 +310,29 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
       double v1 = 0, v2 = 0, w1 = 0, w2 = 0;
       stokeslet_uv(x0 - fx, y0 - fy, g1, g2, L.inv4pimu, v1, v2);
       stokeslet_uv(x0 - cx, y0 - cy, g1, g2, L.inv4pimu, w1, w2);
-      u1 += v1 - w1;
-      u2 += v2 - w2;
+      u1 = dd_add_d(dd_add_d(u1, v1), -w1);
+      u2 = dd_add_d(dd_add_d(u2, v2), -w2);
       double p1 = 0, p2 = 0, q1 = 0, q2 = 0;
       traction_uv(x0 - fx, y0 - fy, nx, ny, g1, g2, p1, p2);
       traction_uv(x0 - cx, y0 - cy, nx, ny, g1, g2, q1, q2);
-      t1 += p1 - q1;
-      t2 += p2 - q2;
+      t1 = dd_add_d(dd_add_d(t1, p1), -q1);
+      t2 = dd_add_d(dd_add_d(t2, p2), -q2);
     }
   }
-  u1 = block_sum(u1, sc);
-  u2 = block_sum(u2, sc);
-  t1 = block_sum(t1, sc);
-  t2 = block_sum(t2, sc);
+  u1 = dd_block_sum(u1, sc);
+  u2 = dd_block_sum(u2, sc);
+  t1 = dd_block_sum(t1, sc);
+  t2 = dd_block_sum(t2, sc);
   if (threadIdx.x == 0) {
-    double* o = disc + ((int64_t)chunk * 2 * L.m + wpt) * 4;
-    o[0] = u1;
-    o[1] = u2;
-    o[2] = t1;
-    o[3] = t2;
+    double* o = disc + ((int64_t)chunk * 2 * L.m + wpt) * 8;
+    o[0] = u1.hi;
+    o[1] = u2.hi;
+    o[2] = t1.hi;
+    o[3] = t2.hi;
+    o[4] = u1.lo;
+    o[5] = u2.lo;
+    o[6] = t1.lo;
+    o[7] = t2.lo;
   }
 }
 
@@ -354,43 +360,46 @@ __global__ __launch_bounds__(1024) void k_xi(Lat L, const double* __restrict__ c
   const double* Qp = Qp_all + (int64_t)cell * 2 * M * 8 * m;
   double* xi = xi_all + (int64_t)cell * 2 * M;
   {
-    __shared__ double sc[16];
-    double F1 = 0, F2 = 0;
+    __shared__ double sc[32];
+    dd F1 = {0, 0}, F2 = {0, 0};
     for (int q = cpoff[cell] + threadIdx.x; q < cpoff[cell + 1]; q += blockDim.x) {
-      F1 += pF[4 * q + 0];
-      F2 += pF[4 * q + 1];
+      F1 = dd_add_d(F1, pF[4 * q + 0]);
+      F2 = dd_add_d(F2, pF[4 * q + 1]);
     }
-    F1 = block_sum(F1, sc);
-    F2 = block_sum(F2, sc);
+    F1 = dd_block_sum(F1, sc);
+    F2 = dd_block_sum(F2, sc);
     if (threadIdx.x == 0) {
-      Fs[0] = F1;
-      Fs[1] = F2;
+      Fs[0] = F1.hi + F1.lo;
+      Fs[1] = F2.hi + F2.lo;
     }
   }
   __syncthreads();
   const double skew = cskew[cell];
   const double l1 = 1.0, l2 = sqrt(skew * skew + 1.0);
   for (int wpt = threadIdx.x; wpt < 2 * m; wpt += blockDim.x) {
-    double s[4] = {0, 0, 0, 0};
-    for (int c = disc_off[cell]; c < disc_off[cell + 1]; ++c)
-      for (int k = 0; k < 4; ++k) s[k] += disc[((int64_t)c * 2 * m + wpt) * 4 + k];
+    dd s[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (int c = disc_off[cell]; c < disc_off[cell + 1]; ++c) {
+      const double* o = disc + ((int64_t)c * 2 * m + wpt) * 8;
+      for (int k = 0; k < 4; ++k) s[k] = dd_add(s[k], dd{o[k], o[4 + k]});
+    }
     const bool onD = wpt >= m;
     const int q = onD ? wpt - m : wpt;
     const int base = onD ? 4 * m : 0;
     const double l = onD ? l1 : l2;
-    gt[base + 0 * m + q] = 0.0 - s[0];
-    gt[base + 1 * m + q] = 0.0 - s[1];
-    gt[base + 2 * m + q] = -Fs[0] / (2.0 * l) - s[2];
-    gt[base + 3 * m + q] = -Fs[1] / (2.0 * l) - s[3];
+    const double g0[4] = {0.0, 0.0, -Fs[0] / (2.0 * l), -Fs[1] / (2.0 * l)};
+    for (int k = 0; k < 4; ++k) {   // g0 - g, rounded once
+      const dd v = dd_add(dd{g0[k], 0.0}, dd{-s[k].hi, -s[k].lo});
+      gt[base + k * m + q] = v.hi + v.lo;
+    }
   }
   __syncthreads();
-  // one wave per row of Q+, lanes over its 8m entries
+  // one wave per row of Q+, lanes over its 8m entries; compensated dot product
   const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int i = threadIdx.x >> 6; i < 2 * M; i += nw) {
-    double s = 0;
-    for (int r = lane; r < 8 * m; r += 64) s += Qp[(int64_t)i * 8 * m + r] * gt[r];
-    s = wave_sum(s);
-    if (lane == 0) xi[i] = s;
+    dd s = {0, 0};
+    for (int r = lane; r < 8 * m; r += 64) s = dd_fma(s, Qp[(int64_t)i * 8 * m + r], gt[r]);
+    s = dd_wave_sum(s);
+    if (lane == 0) xi[i] = s.hi + s.lo;
   }
 }
 

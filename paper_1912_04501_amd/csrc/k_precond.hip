@@ -81,8 +81,8 @@ __global__ __launch_bounds__(256) void k_self_block(const ShapeDesc* __restrict_
 // status[shape] = 1 if a pivot is zero.
 __global__ __launch_bounds__(1024) void k_gauss_jordan(const ShapeDesc* __restrict__ sh, double* __restrict__ work,
                                                        int32_t* __restrict__ status) {
-  __shared__ double prow[2 * kMaxNodesPerParticle * 2];   // pivot row, up to 2m = 2048
-  __shared__ double fcol[2 * kMaxNodesPerParticle];       // column k of every row
+  __shared__ double prow[2 * kMaxNodesStaged * 2];   // pivot row, up to 2m = 2048
+  __shared__ double fcol[2 * kMaxNodesStaged];       // column k of every row
   __shared__ double rv[1024];
   __shared__ int ri[1024];
   const ShapeDesc d = sh[blockIdx.x];
@@ -162,8 +162,8 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
                                                         const float* __restrict__ inv,
                                                         const int32_t* __restrict__ active, int L,
                                                         const double* __restrict__ v, double* __restrict__ out) {
-  __shared__ double vb[2 * kMaxNodesPerParticle];
-  __shared__ double ub[2 * kMaxNodesPerParticle];
+  __shared__ double vb[2 * kMaxNodesStaged];
+  __shared__ double ub[2 * kMaxNodesStaged];
   const int q = blockIdx.x;
   if (active && active[g.pcell[q]] == 0) return;
   const int n = g.pn[q], m = 2 * n;
@@ -197,6 +197,9 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
 // [B | I] work arrays stay below ~1 GB.
 void build_precond(spm_handle* h) {
   Precond& P = h->pc;
+  if (h->geo.nmax > kMaxNodesStaged)
+    throw ApiError(SPM_EINVAL, "the block preconditioner needs at most " + std::to_string(kMaxNodesStaged) +
+                                   " nodes per particle");
   const int S = (int)P.keys.size();
   auto nodes = [&](int s) { return (int32_t)P.keys[s][5]; };
   std::vector<int64_t> ioff(S);
@@ -252,6 +255,9 @@ void build_precond(spm_handle* h) {
 
 void launch_precond_apply(spm_handle* h, const double* v, double* out, bool with_active) {
   Precond& P = h->pc;
+  if (h->geo.nmax > kMaxNodesStaged)
+    throw ApiError(SPM_EINVAL, "the block preconditioner needs at most " + std::to_string(kMaxNodesStaged) +
+                                   " nodes per particle");
   k_precond_apply<<<h->geo.No, 1024, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
                                                      with_active ? h->kr.active : nullptr,
                                                      lanes_per_row(2 * h->geo.nmax), v, out);

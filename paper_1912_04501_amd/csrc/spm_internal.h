@@ -19,7 +19,9 @@ namespace spm {
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kShifts = 9;   // 3x3 images m e1 + n e2, index 3 (m + 1) + (n + 1)
 constexpr int kZeroShift = 4;
-constexpr int kMaxNodesPerParticle = 512;   // close-evaluation LDS staging (k_vplus) holds one curve
+constexpr int kMaxNodesPerParticle = 4096;  // nodes of one particle curve
+constexpr int kMaxNodesStaged = 512;        // curves held whole in LDS: block preconditioner, density modes
+constexpr int kVplusTile = 512;             // source nodes per LDS stage of the close-evaluation boundary values
 
 // Body-frame point of a particle curve at parameter t (SPM_SHAPE_ELLIPSE: (a cos t, b sin t);
 // SPM_SHAPE_STAR: r(t) (cos t, sin t), r = s (1 + A cos(omega t + phi))) with its first and
@@ -167,6 +169,52 @@ __device__ __forceinline__ double block_sum(double v, double* scratch /* >= 16 d
   return t;
 }
 
+// Double-double accumulation (error-free transformations, Knuth's two-sum and an FMA
+// two-product): a sum carried as an unevaluated hi + lo pair keeps the rounding error of
+// every addition. Used where a small result is the sum of many larger terms and an
+// ill-conditioned step follows (the wall discrepancy, then the proxy least squares).
+struct dd {
+  double hi, lo;
+};
+__device__ __forceinline__ dd dd_add_d(dd a, double b) {
+  const double s = a.hi + b, bb = s - a.hi;
+  const double e = ((a.hi - (s - bb)) + (b - bb)) + a.lo;
+  const double h = s + e;
+  return {h, e - (h - s)};
+}
+__device__ __forceinline__ dd dd_add(dd a, dd b) {
+  const double s = a.hi + b.hi, bb = s - a.hi;
+  const double e = ((a.hi - (s - bb)) + (b.hi - bb)) + (a.lo + b.lo);
+  const double h = s + e;
+  return {h, e - (h - s)};
+}
+__device__ __forceinline__ dd dd_fma(dd acc, double a, double b) {   // acc + a b
+  const double p = a * b;
+  const double pe = fma(a, b, -p);
+  dd r = dd_add_d(acc, p);
+  return dd_add_d(r, pe);
+}
+// Wave sum of pairs by a xor butterfly (dd_add is symmetric, so every lane ends equal).
+__device__ __forceinline__ dd dd_wave_sum(dd v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = dd_add(v, dd{__shfl_xor(v.hi, o, 64), __shfl_xor(v.lo, o, 64)});
+  return v;
+}
+// Block sum of pairs for blockDim.x a multiple of 64 (<= 1024); result valid in all threads.
+__device__ __forceinline__ dd dd_block_sum(dd v, double* scratch /* >= 32 doubles */) {
+  v = dd_wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    scratch[2 * wid] = v.hi;
+    scratch[2 * wid + 1] = v.lo;
+  }
+  __syncthreads();
+  dd t = {0.0, 0.0};
+  for (int k = 0; k < nw; ++k) t = dd_add(t, dd{scratch[2 * k], scratch[2 * k + 1]});
+  return t;
+}
+
 // ----------------------------------------------------------------------------
 // Device buffers of a handle (all SoA; N nodes, No particles, C cells).
 // ----------------------------------------------------------------------------
@@ -177,6 +225,7 @@ struct Geo {
   int32_t nmax = 0;           // largest node count of a particle
   // nodes, FP64
   double *x = nullptr, *y = nullptr, *nx = nullptr, *ny = nullptr, *w = nullptr, *kap = nullptr;
+  double* dcot = nullptr;     // [N] spectral differentiation weights of the particle's own N_q, by distance
   double *tx = nullptr, *ty = nullptr, *xpx = nullptr, *xpy = nullptr;
   // nodes, FP32 shadows (targets and sources of the FP32 near sum)
   float *xf = nullptr, *yf = nullptr, *nxf = nullptr, *nyf = nullptr;

@@ -44,7 +44,7 @@ class spm_solve_info(ctypes.Structure):
                 ("refinements", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("seconds_setup", ctypes.c_double), ("seconds_solve", ctypes.c_double),
                 ("seconds_readout", ctypes.c_double), ("fallback", ctypes.c_int32),
-                ("first_iterations", ctypes.c_int32)]
+                ("first_iterations", ctypes.c_int32), ("min_gap", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

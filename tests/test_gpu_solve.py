@@ -170,6 +170,30 @@ def test_error_paths():
     assert r["info"]["status"] == spm.SPM_ENOCONV and r["info"]["rel_residual"] > 1e-10
 
 
+def test_step_failure_keeps_state():
+    """A step whose solve fails (here GMRES capped at 3 iterations) leaves the state and
+    the time at the state it was solving and the handle without particles; after the
+    particles are set again the handle steps normally."""
+    spm = _spm()
+    wl = W.random_ellipses(3, 0.12, seed=8, nodes=64, skew=0.45)
+    s = spm.Solver("cuda:0", max_iter=3).set_workload(wl)
+    c0 = np.asarray(wl["centers"], float).reshape(-1).copy()
+    th0 = np.asarray(wl["theta"], float).copy()
+    t_io, c, th = np.array([0.25]), c0.copy(), th0.copy()
+    mus = np.zeros(2)
+    infos = (spm.spm_solve_info * 2)()
+    rc = spm.lib().spm_step(s.h, 0.01, 2, spm._dp(t_io), spm._dp(c), spm._dp(th), spm._dp(mus), infos)
+    assert rc == spm.SPM_ENOCONV
+    assert t_io[0] == 0.25 and np.array_equal(c, c0) and np.array_equal(th, th0)
+    assert infos[0].status == spm.SPM_ENOCONV and infos[0].iterations == 3
+    with pytest.raises(spm.SpmError) as e:
+        s.solve()
+    assert e.value.code == spm.SPM_ESTATE
+    u = spm.Solver("cuda:0").set_workload(wl)
+    out = u.step(0.01, 2, 0.0, wl["centers"], wl["theta"])
+    assert all(i["status"] == 0 for i in out["infos"]) and abs(out["t"] - 0.02) < 1e-15
+
+
 def test_deterministic():
     """Fixed-order reductions everywhere: repeated calls are bitwise identical."""
     wl = W.random_ellipses(6, 0.3, seed=5, target_total=700)

@@ -98,6 +98,29 @@ def test_discrepancy_is_consistent():
     assert np.abs(Wt @ prob.Q).max() < 1e-6 * np.abs(prob.Q).max()
 
 
+def test_extended_proxy_data():
+    """The extended-precision g0 - g (the test reference for the rounding of the FP64
+    sums) equals the FP64 evaluation up to FP64 rounding, satisfies the consistency
+    conditions W^T (g0 - g) = 0 far more tightly, and does not depend on the order of
+    the sources."""
+    prob = op.make_problem(W.random_ellipses(5, 0.3, seed=4, nodes=64, skew=0.3))
+    g = prob.geom
+    f = near.forces(g, 30.0 * np.random.default_rng(5).standard_normal((g.N, 2)))
+    F = f.sum(0)
+    v64 = periodizer.g0_vector(g, prob.W, F) - periodizer.discrepancy(g, prob.W, f, prob.cfg.mu)
+    vx = periodizer.proxy_data_extended(g, prob.W, f, prob.cfg.mu)
+    assert vx.dtype == np.longdouble
+    assert np.abs(v64 - vx.astype(float)).max() < 1e-13 * np.abs(v64).max()
+    Wt = periodizer.consistency_W(g, prob.W)
+    assert float(np.abs(Wt.astype(np.longdouble) @ vx).max()) < 1e-15 * np.abs(F).max()
+    perm = np.random.default_rng(1).permutation(g.N)
+
+    class _Perm:
+        e1, e2, x = g.e1, g.e2, g.x[perm]
+    vp = periodizer.proxy_data_extended(_Perm, prob.W, f[perm], prob.cfg.mu)
+    assert float(np.abs(vp - vx).max()) < 1e-16 * np.abs(v64).max()
+
+
 class _Cell:
     def __init__(self, e2):
         self.e1 = np.array([1.0, 0.0])
