@@ -176,7 +176,10 @@ int spm_solve(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
               double* mu_eff, spm_solve_info* info_host);
 
 /* Velocities and angular velocities of the rigid particles for a given density
- * (Sec. 3 eq. RigidBodyMotion, read at the centroids). vel [2n], omega [n]. */
+ * (Sec. 3 eq. RigidBodyMotion, read at the centroids). vel [2n], omega [n]. The
+ * velocity is defined up to one constant per cell; it is fixed so that the
+ * area-weighted mean of v_i - u0(c_i) over the cell's particles is zero (a gauge that
+ * does not depend on where the particles sit in the cell). */
 int spm_velocities(spm_handle* h, const double* sigma, double* vel, double* omega);
 
 /* Effective viscosity (Sec. 3 eq. mueff, evaluated by the particle-stresslet

@@ -134,6 +134,21 @@ def radii(kind, p):
     return p[0] * (1.0 + abs(p[1])), p[0] * (1.0 - abs(p[1]))
 
 
+def areas(geom):
+    """Area of every particle from its shape: pi a b for an ellipse; for a star
+    r = s (1 + A cos(omega t + phi)) with integer omega >= 1, (1/2) int r^2 dt =
+    pi s^2 (1 + A^2 / 2)."""
+    out = np.zeros(geom.No)
+    for i in range(geom.No):
+        if geom.kind is None or int(geom.kind[i]) == 0:
+            p = (geom.a[i], geom.b[i]) if geom.params is None else geom.params[i][:2]
+            out[i] = np.pi * p[0] * p[1]
+        else:
+            s, A = geom.params[i][0], geom.params[i][1]
+            out[i] = np.pi * s * s * (1.0 + 0.5 * A * A)
+    return out
+
+
 def particle_nodes(c, theta, kind, p, N):
     if kind == 0:
         return ellipse_nodes(c, theta, p[0], p[1], N)

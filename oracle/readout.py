@@ -8,8 +8,17 @@ traction vanish, Sec. 5), so both are read at the centroid c_i:
     omega_i = (1/2) [vort_near(c_i) + vort_corr(c_i)] - gamma/2
 
 u is defined only up to a constant velocity (Sec. 3 nullspace lemma; Sec. 4.2,
-G_per up to a constant); differencing u_corr against the cell centre fixes that
-gauge, and omega is gauge-free. u0 = (gamma x_2, 0) has vorticity -gamma.
+G_per up to a constant), and the expression above fixes it at the value the near sum
+takes at the cell centre, which depends on where the particles sit relative to c_U.
+Moving every particle by the same vector is a symmetry of the periodic problem, so the
+velocities are reported in the gauge that does not depend on that position: the
+area-weighted mean over the particles of the disturbance v_i - u0(c_i) is zero,
+
+    v_i <- v_i - sum_k |Omega_k| (v_k - u0(c_k)) / sum_k |Omega_k|.
+
+(Under the fixed-point gauge a stiff configuration drifts as a whole with a speed that
+depends on its position, and forward Euler amplifies that drift.) omega is gauge-free.
+u0 = (gamma x_2, 0) has vorticity -gamma.
 
 Effective viscosity. eq. (mueff) integrates the shear traction through the
 bottom wall D. The particle-stresslet form used here equals it by the force
@@ -25,7 +34,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import _clib, dilated, near, periodizer
+from . import _clib, dilated, geometry, near, periodizer
 from .operator import proxy_strengths, to2
 
 
@@ -43,6 +52,8 @@ def velocities(prob, sigma):
     vc = periodizer.correction_vorticity(prob.P, xi, g.centers, prob.cfg.mu)
     u0 = np.stack([prob.cfg.gamma * g.centers[:, 1], np.zeros(g.No)], axis=1)
     v = u0 + un + uc - uc0
+    area = geometry.areas(g)
+    v = v - (area[:, None] * (v - u0)).sum(0) / area.sum()
     omega = 0.5 * (vn + vc) - 0.5 * prob.cfg.gamma
     return v, omega
 

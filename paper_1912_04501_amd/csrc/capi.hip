@@ -461,7 +461,7 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   for (float** p : {&g.xf, &g.yf, &g.nxf, &g.nyf}) ensure(h, *p, N);
   ensure(h, g.pid, N);
   ensure(h, g.ncell, N);
-  for (double** p : {&g.pcx, &g.pcy, &g.pth, &g.pa, &g.pb, &g.pper}) ensure(h, *p, n);
+  for (double** p : {&g.pcx, &g.pcy, &g.pth, &g.pa, &g.pb, &g.pper, &g.parea}) ensure(h, *p, n);
   ensure(h, g.poff, n + 1);
   ensure(h, g.pn, n);
   ensure(h, g.pcell, n);

@@ -45,14 +45,23 @@ __global__ void k_geometry(int64_t N, const int32_t* __restrict__ pid, const int
   g.nyf[i] = (float)(-tx);
 }
 
-// Perimeter of every particle (sum of its trapezoid weights), one block per particle.
-__global__ void k_perimeter(const int32_t* __restrict__ poff, const double* __restrict__ w, double* per) {
+// Perimeter of every particle (sum of its trapezoid weights) and its area by the
+// boundary quadrature (1/2) sum ((x - c) y' - (y - c) x') (2 pi / N_p), one block per particle.
+__global__ void k_perimeter(const int32_t* __restrict__ poff, Geo g, double* per, double* area) {
   __shared__ double sc[16];
   const int p = blockIdx.x;
-  double s = 0.0;
-  for (int k = poff[p] + threadIdx.x; k < poff[p + 1]; k += blockDim.x) s += w[k];
+  const double cx = g.pcx[p], cy = g.pcy[p];
+  double s = 0.0, a = 0.0;
+  for (int k = poff[p] + threadIdx.x; k < poff[p + 1]; k += blockDim.x) {
+    s += g.w[k];
+    a += (g.x[k] - cx) * g.xpy[k] - (g.y[k] - cy) * g.xpx[k];
+  }
   s = block_sum(s, sc);
-  if (threadIdx.x == 0) per[p] = s;
+  a = block_sum(a, sc);
+  if (threadIdx.x == 0) {
+    per[p] = s;
+    area[p] = a * kPi / (double)(poff[p + 1] - poff[p]);
+  }
 }
 
 void launch_geometry(spm_handle* h) {
@@ -61,7 +70,7 @@ void launch_geometry(spm_handle* h) {
   k_geometry<<<(unsigned)((g.N + bs - 1) / bs), bs, 0, h->stream>>>(g.N, g.pid, g.poff, g.pn, g.pcx, g.pcy,
                                                                     g.pth, g.pkind, g.pprm, g);
   SPM_HIP_CHECK(hipGetLastError());
-  k_perimeter<<<g.No, 256, 0, h->stream>>>(g.poff, g.w, g.pper);
+  k_perimeter<<<g.No, 256, 0, h->stream>>>(g.poff, g, g.pper, g.parea);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

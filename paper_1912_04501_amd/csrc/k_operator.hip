@@ -5,7 +5,8 @@
 // assemble: y = sigma/2 + T + alpha n + L sigma,  alpha = -(T(x0) . n0)   (Sec. 5 eq. BIEPerturbed;
 //           Sec. 6.2 pressure pin with x0 the first node of the first particle),
 //           L_q sigma (x) = F_q + (x - c_q)^perp tau_q.
-// readout:  v_q = u0(c_q) + u_near(c_q) + u_corr(c_q) - u_corr(c_U);
+// readout:  v_q = u0(c_q) + u_near(c_q) + u_corr(c_q) - u_corr(c_U), then the constant that makes
+//           the area-weighted mean of v_q - u0(c_q) over the cell zero is removed;
 //           omega_q = (vort_near(c_q) + vort_corr(c_q))/2 - gamma/2   (Sec. 3 eq. RigidBodyMotion).
 //           mu_eff = mu - sum_q stresslet_q / (2 gamma |U|)           (Sec. 3 eq. mueff via the
 //           cell force balance: the traction on a particle is -sigma).
@@ -132,10 +133,39 @@ __global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restr
   }
 }
 
+// Velocity gauge, one block per cell: subtract the area-weighted mean disturbance
+// sum_q |Omega_q| (v_q - u0(c_q)) / sum_q |Omega_q| from every velocity of the cell, so the
+// reported velocities do not depend on where the particles sit relative to the cell
+// centre (a uniform translation of all particles is a symmetry of the periodic problem).
+__global__ __launch_bounds__(256) void k_velocity_gauge(const int32_t* __restrict__ cpoff,
+                                                        const double* __restrict__ pcy,
+                                                        const double* __restrict__ parea, double gamma,
+                                                        double* __restrict__ vel) {
+  __shared__ double sc[16];
+  const int c = blockIdx.x;
+  double a = 0, m1 = 0, m2 = 0;
+  for (int q = cpoff[c] + threadIdx.x; q < cpoff[c + 1]; q += blockDim.x) {
+    a += parea[q];
+    m1 += parea[q] * (vel[2 * q] - gamma * pcy[q]);
+    m2 += parea[q] * vel[2 * q + 1];
+  }
+  a = block_sum(a, sc);
+  m1 = block_sum(m1, sc) / a;
+  m2 = block_sum(m2, sc) / a;
+  for (int q = cpoff[c] + threadIdx.x; q < cpoff[c + 1]; q += blockDim.x) {
+    vel[2 * q] -= m1;
+    vel[2 * q + 1] -= m2;
+  }
+}
+
 void launch_velocities(spm_handle* h, double* vel, double* omega) {
   k_velocities<<<h->geo.No, 256, 0, h->stream>>>(h->geo, h->wk.f1, h->wk.f2, h->per.M, h->per.px, h->per.py,
                                                  h->wk.xi, h->cU[0], h->cU[1], h->cfg.mu, h->cfg.gamma, vel, omega);
   SPM_HIP_CHECK(hipGetLastError());
+  if (vel) {
+    k_velocity_gauge<<<h->geo.C, 256, 0, h->stream>>>(h->geo.cpoff, h->geo.pcy, h->geo.parea, h->cfg.gamma, vel);
+    SPM_HIP_CHECK(hipGetLastError());
+  }
 }
 
 // mu_eff of every cell (|U| = |det(e1, e2)| = 1 for e1 = (1, 0), e2 = (s, 1)).

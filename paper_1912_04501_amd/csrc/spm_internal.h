@@ -234,6 +234,7 @@ struct Geo {
   // particles
   // pa, pb: largest and smallest distance from the reference point to the curve
   double *pcx = nullptr, *pcy = nullptr, *pth = nullptr, *pa = nullptr, *pb = nullptr, *pper = nullptr;
+  double* parea = nullptr;    // [No] particle areas (boundary quadrature of (1/2) x ^ dx)
   int32_t *poff = nullptr, *pn = nullptr;
   int32_t* pcell = nullptr;   // [No] cell of each particle
   int32_t* pkind = nullptr;   // [No] SPM_SHAPE_*

@@ -70,3 +70,17 @@ def test_two_stars_shift_invariance():
     v2, o2 = ro.velocities(p2, x2)
     assert np.abs(o1 - o2).max() < 5e-6
     assert abs(ro.mu_eff(p1, x1) - ro.mu_eff(p2, x2)) < 5e-6
+
+
+def test_particle_areas_match_greens_theorem():
+    """Closed-form areas (pi a b; pi s^2 (1 + A^2/2) for the stars) against the
+    spectrally accurate boundary integral (1/2) sum (x y' - y x') (2 pi / N)."""
+    from oracle.geometry import areas, build_geometry
+    for wl in (W.star_and_ellipse(), W.two_stars(omega=4.0, n_nodes=256), W.random_ellipses(4, 0.2, seed=3, nodes=64)):
+        g = build_geometry(wl)
+        ref = areas(g)
+        for i in range(g.No):
+            sl = g.particle_slice(i)
+            rel = g.x[sl] - g.centers[i]
+            quad = 0.5 * (rel[:, 0] * g.xp[sl, 1] - rel[:, 1] * g.xp[sl, 0]).sum() * 2.0 * np.pi / g.n_nodes[i]
+            assert abs(quad - ref[i]) < 1e-13 * ref[i]
