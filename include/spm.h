@@ -182,6 +182,19 @@ int spm_solve(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
  * does not depend on where the particles sit in the cell). */
 int spm_velocities(spm_handle* h, const double* sigma, double* vel, double* omega);
 
+/* Flow velocity and pressure at points x (Sec. 3; Sec. 5 representations of u and p; the
+ * quasi-static solver of Sec. 7 returns u(x) and p(x)). sigma [2N] (device): a solved
+ * density. xt, yt [n_targets] (device): any points (the disturbance is periodic; the
+ * total velocity includes u0 = (gamma x_2, 0)). u [2 n_targets] (device): u_1 of every
+ * target, then u_2, in the velocity gauge of spm_velocities. p [n_targets] (device): the
+ * pressure of the representation (defined up to one constant), NaN inside particles,
+ * where u is the particle's rigid motion. Points within close_factor * h of a curve use
+ * the Laplace decomposition of the single layer with the barycentric rule of Sec. 6.3
+ * (no slip is met to the discretisation error however close). Single-cell handles;
+ * 0 <= n_targets <= 2^28. */
+int spm_eval_field(spm_handle* h, const double* sigma, int64_t n_targets, const double* xt, const double* yt,
+                   double* u, double* p);
+
 /* Effective viscosity (Sec. 3 eq. mueff, evaluated by the particle-stresslet
  * identity; valid whether or not particles cross the wall D). mu_eff: device, one
  * value per cell. */

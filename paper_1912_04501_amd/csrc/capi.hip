@@ -299,6 +299,7 @@ void alloc_work(spm_handle* h) {
   ensure(h, W.T, 2 * N);
   ensure(h, W.pF, (size_t)4 * h->geo.No);
   ensure(h, W.scal, 16);
+  ensure(h, W.gauge, (size_t)2 * h->geo.C);
 }
 
 void alloc_krylov(spm_handle* h) {
@@ -1236,6 +1237,29 @@ int spm_velocities(spm_handle* h, const double* sigma, double* vel, double* omeg
     need_particles(h);
     if (!sigma) throw ApiError(SPM_EINVAL, "null sigma");
     readout(h, sigma, vel, omega, nullptr);
+    sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_eval_field(spm_handle* h, const double* sigma, int64_t n_targets, const double* xt, const double* yt,
+                   double* u, double* p) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (h->geo.C != 1) throw ApiError(SPM_EINVAL, "field evaluation runs on a single-cell handle");
+    if (!sigma || n_targets < 0 || n_targets > ((int64_t)1 << 28) ||
+        (n_targets > 0 && (!xt || !yt || !u || !p)))
+      throw ApiError(SPM_EINVAL, "bad field arguments");
+    if (n_targets == 0) return SPM_OK;
+    Field& F = h->fd;
+    ensure(h, F.iw, (size_t)h->geo.N);
+    ensure(h, F.hp, 4 * (size_t)h->geo.N);
+    ensure(h, F.vel, 2 * (size_t)h->geo.No);
+    ensure(h, F.om, (size_t)h->geo.No);
+    stage_xi(h, sigma, false);              // f = w sigma, net forces, proxy strengths
+    launch_velocities(h, F.vel, F.om);      // rigid motions and the velocity gauge
+    launch_vplus(h, sigma);                 // boundary values of the Cauchy integrals
+    launch_field(h, n_targets, xt, yt, u, p);
     sync(h);
     return SPM_OK;
   });

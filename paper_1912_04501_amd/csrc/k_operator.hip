@@ -140,7 +140,7 @@ __global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restr
 __global__ __launch_bounds__(256) void k_velocity_gauge(const int32_t* __restrict__ cpoff,
                                                         const double* __restrict__ pcy,
                                                         const double* __restrict__ parea, double gamma,
-                                                        double* __restrict__ vel) {
+                                                        double* __restrict__ vel, double* __restrict__ gauge) {
   __shared__ double sc[16];
   const int c = blockIdx.x;
   double a = 0, m1 = 0, m2 = 0;
@@ -156,6 +156,10 @@ __global__ __launch_bounds__(256) void k_velocity_gauge(const int32_t* __restric
     vel[2 * q] -= m1;
     vel[2 * q + 1] -= m2;
   }
+  if (threadIdx.x == 0) {
+    gauge[2 * c] = m1;
+    gauge[2 * c + 1] = m2;
+  }
 }
 
 void launch_velocities(spm_handle* h, double* vel, double* omega) {
@@ -163,7 +167,8 @@ void launch_velocities(spm_handle* h, double* vel, double* omega) {
                                                  h->wk.xi, h->cU[0], h->cU[1], h->cfg.mu, h->cfg.gamma, vel, omega);
   SPM_HIP_CHECK(hipGetLastError());
   if (vel) {
-    k_velocity_gauge<<<h->geo.C, 256, 0, h->stream>>>(h->geo.cpoff, h->geo.pcy, h->geo.parea, h->cfg.gamma, vel);
+    k_velocity_gauge<<<h->geo.C, 256, 0, h->stream>>>(h->geo.cpoff, h->geo.pcy, h->geo.parea, h->cfg.gamma, vel,
+                                                      h->wk.gauge);
     SPM_HIP_CHECK(hipGetLastError());
   }
 }

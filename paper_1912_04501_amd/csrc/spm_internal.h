@@ -315,9 +315,18 @@ struct Work {
   double* Tpart = nullptr;    // [max splits x 2N]
   double* T = nullptr;        // [2N]
   double* pF = nullptr;       // [No x 4]: F1, F2, torque, stresslet
-  double* disc = nullptr;     // [ndisc x 2m x 4]
+  double* disc = nullptr;     // [ndisc x 2m x 8] (double-double partials)
   double* xi = nullptr;       // [C x 2M]
   double* scal = nullptr;     // [16] device scalars
+  double* gauge = nullptr;    // [C x 2] velocity constant removed by the readout gauge
+};
+
+// Flow-field evaluation at points of the fluid.
+struct Field {
+  double* iw = nullptr;       // [N] spectral antiderivative weights of each particle's own N_q, by distance
+  double* hp = nullptr;       // [4N] H+ of sigma_1, sigma_2 (re, im): boundary values of the log potential part
+  double* vel = nullptr;      // [2 No] readout velocities (gauged)
+  double* om = nullptr;       // [No]
 };
 
 // Krylov state. Cells iterate in lockstep on one global iteration index j (kept in
@@ -436,6 +445,7 @@ struct spm_handle {
   spm::Periodizer per;
   spm::CloseList cl;
   spm::Work wk;
+  spm::Field fd;
   spm::Krylov kr;
   spm::Learned ln;
   spm::Precond pc;
@@ -477,6 +487,7 @@ namespace spm {
 void mlp_forward(spm_mlp* net, hipStream_t s, const float* x, const int32_t* xrow, int64_t B, float* y, int mode);
 
 // --- launch wrappers (defined in the k_*.hip files) --------------------------
+void launch_field(spm_handle* h, int64_t n_targets, const double* xt, const double* yt, double* u, double* p);
 void launch_geometry(spm_handle* h);
 void launch_rhs(spm_handle* h, double* out);
 void launch_prep(spm_handle* h, const double* sigma);

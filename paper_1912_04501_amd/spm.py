@@ -100,6 +100,7 @@ def lib():
         "spm_proxy_svd": (ctypes.c_int, [P, d, d, i32]),
         "spm_set_cells": (ctypes.c_int, [P, ctypes.c_int32, d, i32, d, d, d, d, i32]),
         "spm_set_cells_shapes": (ctypes.c_int, [P, ctypes.c_int32, d, i32, d, d, i32, d, i32]),
+        "spm_eval_field": (ctypes.c_int, [P, P, ctypes.c_int64, P, P, P, P]),
         "spm_num_cells": (ctypes.c_int, [P, i32]),
         "spm_solve_batch": (ctypes.c_int, [P, P, P, P, P, P, ctypes.POINTER(spm_solve_info), d]),
         "spm_autotune": (ctypes.c_int, [P, ctypes.c_char_p, d]),
@@ -405,6 +406,18 @@ class Solver:
         om = self._vec(self.No)
         self._check(lib().spm_velocities(self.h, _ptr(sigma), _ptr(vel), _ptr(om)))
         return vel.view(-1, 2), om
+
+    def eval_field(self, sigma, targets):
+        """Flow velocity [n, 2] and pressure [n] at targets [n, 2] (array-like) for a solved density."""
+        pts = torch.as_tensor(np.ascontiguousarray(np.asarray(targets, dtype=np.float64).reshape(-1, 2)),
+                              device=self.device)
+        xt = pts[:, 0].contiguous()
+        yt = pts[:, 1].contiguous()
+        n = int(xt.numel())
+        u = self._vec(2 * n)
+        p = self._vec(n)
+        self._check(lib().spm_eval_field(self.h, _ptr(sigma), n, _ptr(xt), _ptr(yt), _ptr(u), _ptr(p)))
+        return torch.stack([u[:n], u[n:]], dim=1), p
 
     def effective_viscosity(self, sigma):
         mu = self._vec(1)

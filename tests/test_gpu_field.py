@@ -1,0 +1,71 @@
+"""Flow velocity and pressure at points of the fluid (spm_eval_field) against the oracle's
+field on the same density: far points (plain rule), points approaching the curves along
+their normals down to 1e-4 (the device's Laplace-decomposition barycentric rule against
+the oracle's refined trapezoid rule on the exact curve), points inside particles (rigid
+motion) and periodic copies outside the cell."""
+import numpy as np
+import pytest
+
+from oracle import field as ofield
+from oracle import operator as op
+from paper_1912_04501_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "two_ellipses_gap2e-2_N256_skew0.2": lambda: W.two_ellipses(2e-2, n_nodes=256, skew=0.2),
+    "star_and_ellipse_gap2e-2_N384_256_skew0.2": lambda: W.star_and_ellipse(n_star=384, n_ellipse=256),
+}
+
+
+def _targets(prob):
+    g = prob.geom
+    rng = np.random.default_rng(4)
+    pts = [rng.uniform(-0.5, 0.5, size=(24, 2)) @ np.stack([g.e1, g.e2])]      # anywhere in the cell
+    for i0 in (7, 60, g.offsets[1] + 30):
+        d = np.array([1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4])
+        pts.append(g.x[i0][None] + d[:, None] * g.n[i0][None])                 # towards a boundary point
+    pts.append(g.centers + 0.05 * np.array([[1.0, 0.3]]))                        # inside the particles
+    pts = np.concatenate(pts)
+    return np.concatenate([pts, pts[:10] + 2 * g.e1 - g.e2])                     # periodic copies
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_field_matches_oracle(name):
+    from paper_1912_04501_amd import spm
+    wl = CASES[name]()
+    prob = op.make_problem(wl)
+    s = spm.Solver("cuda:0").set_workload(wl)
+    r = s.solve()
+    sig = r["sigma"]
+    pts = _targets(prob)
+    print(f"[field {name}] {len(pts)} targets", flush=True)
+    u, p = s.eval_field(sig, pts)
+    u, p = u.cpu().numpy(), p.cpu().numpy()
+    uo, po = ofield.field(prob, sig.cpu().numpy(), pts)
+    inside = np.isnan(po)
+    assert np.array_equal(np.isnan(p), inside)
+    su = np.abs(uo).max()
+    eu = np.abs(u - uo).max(axis=1) / su
+    ep = np.abs(p - po)[~inside] / np.abs(po[~inside]).max()
+    print(f"[field {name}] u err max {eu.max():.2e} (inside {eu[inside].max():.2e}), p err max {ep.max():.2e}",
+          flush=True)
+    # the two close rules converge to the same layer potential as the density is resolved:
+    # 1e-11 here (on the star at 192 nodes they still differ by 2e-8 at 1e-4 from the curve)
+    assert eu.max() < 1e-10
+    assert ep.max() < 1e-10
+
+
+def test_field_arguments():
+    from paper_1912_04501_amd import spm
+    wl = W.two_ellipses(3e-2, n_nodes=64)
+    s = spm.Solver("cuda:0").set_workload(wl)
+    sig = s.solve()["sigma"]
+    u, p = s.eval_field(sig, np.zeros((0, 2)))
+    assert u.shape == (0, 2) and p.shape == (0,)
+    e = spm.Solver("cuda:0").set_cells([wl, wl])
+    with pytest.raises(spm.SpmError) as err:
+        e.eval_field(torch.zeros(2 * e.N, dtype=torch.float64, device="cuda:0"), np.zeros((3, 2)))
+    assert err.value.code == spm.SPM_EINVAL
