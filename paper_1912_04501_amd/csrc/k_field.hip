@@ -66,22 +66,24 @@ __global__ __launch_bounds__(256) void k_hplus(int64_t N, Geo g, const double* _
   const double* vim = vp + (int64_t)(2 * d + 1) * N;
   double* hre = hp + (int64_t)(2 * d) * N;
   double* him = hp + (int64_t)(2 * d + 1) * N;
-  // antiderivative of g_k = y'_k H'+_k, H'+ = -2 pi i v+ - Q / (y - c)
-  auto gk = [&](int k) -> zc {
+  // g_k = y'_k H'+_k, H'+ = -2 pi i v+ - Q / (y - c), staged in LDS; then its antiderivative
+  __shared__ double gre[kMaxNodesPerParticle], gim[kMaxNodesPerParticle];
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
     const int64_t i = o + k;
     const zc dv = {2.0 * kPi * vim[i], -2.0 * kPi * vre[i]};
     const zc qc = zinv({g.x[i] - cx, g.y[i] - cy});
-    const zc hd = {dv.re - Q * qc.re, dv.im - Q * qc.im};
-    return zmul({g.xpx[i], g.xpy[i]}, hd);
-  };
+    const zc gv = zmul({g.xpx[i], g.xpy[i]}, {dv.re - Q * qc.re, dv.im - Q * qc.im});
+    gre[k] = gv.re;
+    gim[k] = gv.im;
+  }
+  __syncthreads();
   for (int j = threadIdx.x; j < n; j += blockDim.x) {
     double ar = 0.0, ai = 0.0;
     for (int k = 0; k < n; ++k) {
       const int l = j - k >= 0 ? j - k : j - k + n;
       const double w = iw[o + l];
-      const zc gv = gk(k);
-      ar += w * gv.re;
-      ai += w * gv.im;
+      ar += w * gre[k];
+      ai += w * gim[k];
     }
     hre[o + j] = ar;
     him[o + j] = ai;
