@@ -85,3 +85,30 @@ def test_star_shape_checks():
     with pytest.raises(spm.SpmError) as e:
         spm.Solver("cuda:0").set_workload(wl)
     assert e.value.code == spm.SPM_EOVERLAP
+
+
+def test_star_cells_in_one_ensemble():
+    """Cells of stars, of ellipses and of both kinds solved together (one launch per
+    product, per-cell convergence) against the oracle solving each cell alone."""
+    from oracle import operator as op
+    from oracle import readout as ro
+    spm = _spm()
+    cells = [W.two_stars(n_nodes=128), W.star_and_ellipse(), W.random_ellipses(5, 0.3, seed=1004, nodes=64),
+             W.stars([[0.1, -0.2]], 0.2, 0.3, 3, theta=0.4, n_nodes=96, skew=-0.3)]
+    s = spm.Solver("cuda:0").set_cells(cells)
+    r = s.solve_batch()
+    vel, om, mu = _n(r["vel"]), _n(r["omega"]), _n(r["mu_eff"])
+    off = s.part_off
+    for k, wl in enumerate(cells):
+        prob = op.make_problem(wl)
+        x, _ = op.solve(prob, tol=1e-12)
+        v, o = ro.velocities(prob, x)
+        m = ro.mu_eff(prob, x)
+        sl = slice(off[k], off[k + 1])
+        sc_v = max(np.abs(v).max(), np.hypot(*prob.geom.e2))
+        print(f"[star ensemble] cell {k}: its {r['infos'][k]['iterations']} omega err {np.abs(om[sl] - o).max():.1e} "
+              f"mu err {abs(mu[k] - m):.1e}", flush=True)
+        assert r["infos"][k]["rel_residual"] <= 1e-10
+        assert np.abs(om[sl] - o).max() <= 1e-9 * max(1.0, np.abs(o).max())
+        assert np.abs(vel[sl] - v).max() <= 1e-9 * sc_v
+        assert abs(mu[k] - m) <= 1e-9 * m
