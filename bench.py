@@ -130,6 +130,7 @@ def main():
     ap.add_argument("--nodes", type=int, default=2500, help="jamming: nodes per star")
     ap.add_argument("--omega", type=int, default=4, help="jamming: arms of each star, r = s (1 + cos(omega t)/2)")
     ap.add_argument("--full-series", action="store_true", help="jamming: every step of mu_eff(t) in the JSON line")
+    ap.add_argument("--no-tune", action="store_true", help="jamming: keep the heuristic near-sum launch shapes")
     ap.add_argument("--jam-tol", type=float, default=None,
                     help="jamming: GMRES tolerance (default 1e-9 for Example 4, 1e-8 for Example 5: near contact "
                          "the FP64 residual floor of the operator reaches 2e-10 at mu_eff ~ 1e5 and 1e-9 at gaps "
@@ -220,7 +221,7 @@ def main():
     if not args.no_compare:
         for name, p, pc in (("fp64", spm.SPM_FP64, 0), ("fp32_ir", spm.SPM_FP32_IR, 0),
                             ("fp32_relaxed", spm.SPM_FP32_RELAXED, 0), ("fp64_precond", spm.SPM_FP64, 1),
-                            ("fp32_relaxed_precond", spm.SPM_FP32_RELAXED, 1)):
+                            ("fp32_ir_precond", spm.SPM_FP32_IR, 1), ("fp32_relaxed_precond", spm.SPM_FP32_RELAXED, 1)):
             c = spm.Solver("cuda:0", precision=p, precond=pc)
             c.set_workload(wl)
             for pr, key in ((spm.SPM_FP64, "fp64"), (spm.SPM_FP32, "fp32")):
@@ -465,6 +466,10 @@ def bench_jamming(args):
     wl = W.two_stars(s=ex["s"], A=0.5, omega=float(args.omega), second_theta=ex["second_theta"], n_nodes=args.nodes)
     s = spm.Solver("cuda:0", precision=spm.SPM_FP64, max_iter=2000, tol=args.jam_tol)
     s.set_workload(wl)
+    tuned = None
+    if not args.no_tune:   # launch shapes for this node count; they persist while N is unchanged
+        tuned = s.autotune(args.tune_cache)
+        log(f"[jam] autotuned near sum: {tuned}")
     c, th, t = np.array(wl["centers"], float), np.array(wl["theta"], float), 0.0
     ts, mus, its, gaps = [], [], [], []
     n_total = int(round(t_end / args.dt))
@@ -522,7 +527,7 @@ def bench_jamming(args):
            "ms_per_step": 1e3 * secs / max(1, len(mus)), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"two_stars_example{args.example}", "nodes_per_star": args.nodes, "dt": args.dt,
-                      "tol": args.jam_tol,
+                      "tol": args.jam_tol, "autotuned": tuned is not None,
                       "t_end": t_end, "s": ex["s"], "A": 0.5, "omega": args.omega,
                       "second_theta": ex["second_theta"]},
            "stopped": stop, "t_last": float(ts[-1]) if len(ts) else 0.0,

@@ -61,7 +61,7 @@ extern "C" {
 #define SPM_FP32 1         /* near-image sum in FP32 with FP32 accumulation; the rest FP64 */
 #define SPM_FP32_IR 2      /* solve: FP64 iterative refinement around FP32-near-sum GMRES */
 #define SPM_FP32_RELAXED 3 /* solve: one FP64 GMRES whose operator products switch to the FP32
-                              near sum once the residual estimate is below cfg.inner_tol */
+                              near sum once the residual estimate is below cfg.relax_tol */
 
 #define SPM_X0_ZERO 0      /* initial guess of a solve without sigma0: zero */
 #define SPM_X0_PREVIOUS 1  /* spm_step: the previous step's density (first step: zero) */
@@ -90,8 +90,8 @@ typedef struct {
   double tol;           /* relative residual of the solve [1e-10] */
   int32_t max_iter;     /* GMRES iteration cap per Krylov solve [500] */
   int32_t precision;    /* SPM_FP64, SPM_FP32_IR or SPM_FP32_RELAXED for spm_solve [SPM_FP64] */
-  double inner_tol;     /* SPM_FP32_IR: inner relative tolerance; SPM_FP32_RELAXED: residual
-                           estimate below which products use the FP32 near sum [1e-5] */
+  double inner_tol;     /* SPM_FP32_IR: relative tolerance of the first inner solve; 0 = 3e-3 with
+                           the block preconditioner, 1e-4 without [0] */
   double min_gap;       /* reject geometries with a periodic boundary gap below this [0] */
   double rcond;         /* proxy pseudo-inverse relative cutoff [1e-14] */
   int32_t use_graph;    /* replay one captured GMRES iteration as a HIP graph [1] */
@@ -100,6 +100,8 @@ typedef struct {
   int32_t precond;      /* SPM_PRECOND_* [SPM_PRECOND_NONE] */
   int32_t learned_max_iter; /* iteration cap of a warm-started or preconditioned attempt before
                                the plain-GMRES fallback; 0 = max_iter [0] */
+  double relax_tol;     /* SPM_FP32_RELAXED: residual estimate below which products use the FP32
+                           near sum [1e-5] */
 } spm_config;
 
 typedef struct {

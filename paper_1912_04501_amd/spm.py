@@ -35,7 +35,7 @@ class spm_config(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("min_gap", ctypes.c_double), ("rcond", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("x0", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("learned_max_iter", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("learned_max_iter", ctypes.c_int32), ("relax_tol", ctypes.c_double)]
 
 
 class spm_solve_info(ctypes.Structure):
