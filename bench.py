@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--precision", choices=["fp32_ir", "fp32_relaxed", "fp64"], default=None,
                     help="solver precision (default: fp32_ir for the 200-ellipse cell, fp32_relaxed for the "
                          "ensemble)")
+    ap.add_argument("--precond", choices=["none", "block"], default=None,
+                    help="ensemble64: right block preconditioner (default: block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed FP64-vs-FP32+IR comparison solves")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
@@ -142,6 +144,8 @@ def main():
     args = ap.parse_args()
     if args.precision is None:
         args.precision = "fp32_relaxed" if args.workload == "ensemble64" else "fp32_ir"
+    if args.precond is None:
+        args.precond = "block" if args.workload == "ensemble64" else "none"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
               file=sys.stderr)
@@ -262,7 +266,8 @@ def percentile(v, q):
 
 def bench_ensemble(args):
     """64 independent cells (seeds 1000..1063, 4-50 ellipses each) solved together in
-    one persistent near-sum launch per matvec, FP32+IR, autotuned launch shape. One
+    one persistent near-sum launch per matvec (relaxed FP32 by default, --precision and
+    --precond choose the solver), autotuned launch shape. One
     step = one batched solve of every cell to 1e-10; value = cell solves per second;
     per-cell latency (device wall clock from the solve start to the cell's convergence)
     as p50 / p99 over the timed steps."""
@@ -277,7 +282,8 @@ def bench_ensemble(args):
     log(f"[bench] 64 cells generated in {time.perf_counter() - t0:.1f}s: N_c {Ns.min()}..{Ns.max()}, "
         f"total {Ns.sum()}, particles {sum(len(c['theta']) for c in cells)}")
     s = spm.Solver("cuda:0", precision=spm.SPM_FP32_RELAXED if args.precision == "fp32_relaxed" else
-                   {"fp32_ir": spm.SPM_FP32_IR, "fp64": spm.SPM_FP64}[args.precision])
+                   {"fp32_ir": spm.SPM_FP32_IR, "fp64": spm.SPM_FP64}[args.precision],
+                   precond=spm.SPM_PRECOND_BLOCK if args.precond == "block" else spm.SPM_PRECOND_NONE)
     s.set_cells(cells)
     tune = s.autotune(args.tune_cache)
     log(f"[bench] autotune: {tune}")
@@ -319,13 +325,14 @@ def bench_ensemble(args):
         mv = np.array([i["fp64_matvecs"] + i["fp32_matvecs"] for i in infos[:len(cells)]], dtype=np.float64)
         cpu["solves_per_s_near_only"] = len(cells) / float((9.0 * Ns.astype(np.float64) ** 2 * mv).sum()
                                                            / cpu["value"])
-    out = {"metric": f"ensemble cell solves/s (64 independent cells, {args.precision} to 1e-10 FP64 residual)",
+    out = {"metric": f"ensemble cell solves/s (64 independent cells, {args.precision}"
+                     f"{' + block preconditioner' if args.precond == 'block' else ''} to 1e-10 FP64 residual)",
            "value": 64 * args.steps / elapsed, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
            "config": {"workload": "ensemble_64_cells_phi0.3", "cells": 64, "nodes_total": int(Ns.sum()),
                       "nodes_min": int(Ns.min()), "nodes_max": int(Ns.max()), "pairs_per_matvec": pairs,
-                      "precision": args.precision, "tol": 1e-10},
+                      "precision": args.precision, "precond": args.precond, "tol": 1e-10},
            "latency_ms": {"p50": 1e3 * percentile(lat, 50), "p99": 1e3 * percentile(lat, 99),
                           "max": 1e3 * max(lat)},
            "iterations": {"p50": percentile([i["iterations"] for i in infos], 50),
