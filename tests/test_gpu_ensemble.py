@@ -123,3 +123,39 @@ def test_ensemble_every_launch_shape(ensemble):
                 s.set_launch(spm.SPM_FP64, block, tpt, 256, chunk)
                 T = _n(s.near_traction(st))
                 assert np.abs(T - base).max() <= 1e-12 * np.abs(base).max()
+
+
+def test_full_64_cell_ensemble_sampled_cells():
+    """The 64-cell ensemble at full size, solved as the bench solves it (relaxed FP32 with
+    the block preconditioner, autotuned launch shapes): every cell meets the FP64 residual,
+    and the three smallest cells (sampled outputs the oracle can afford one by one) match
+    the oracle's solves of those cells alone: residual through the oracle's operator within
+    2e-10 and readouts within 1e-7 (the mixed-form bound)."""
+    spm = _spm()
+    cells = W.ensemble_cells(64)
+    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_RELAXED, precond=spm.SPM_PRECOND_BLOCK).set_cells(cells)
+    s.autotune()
+    r = s.solve_batch()
+    assert all(i["status"] == 0 and i["rel_residual"] <= 1e-10 for i in r["infos"])
+    sig, vel, om, mu = _n(r["sigma"]), _n(r["vel"]), _n(r["omega"]), _n(r["mu_eff"])
+    N = s.N
+    off = s.part_off
+    sizes = [int(np.sum(c["n_nodes"])) for c in cells]
+    starts = np.concatenate([[0], np.cumsum(sizes)])
+    for k in np.argsort(sizes)[:3]:
+        prob = op.make_problem(cells[k])
+        n0, n1 = starts[k], starts[k + 1]
+        sk = np.concatenate([sig[n0:n1], sig[N + n0:N + n1]])
+        b = op.rhs(prob)
+        res = np.linalg.norm(b - op.apply(prob, sk)) / np.linalg.norm(b)
+        x, _ = op.solve(prob, tol=1e-12)
+        v, o = ro.velocities(prob, x)
+        m = ro.mu_eff(prob, x)
+        sl = slice(off[k], off[k + 1])
+        sc_v = max(np.abs(v).max(), np.hypot(*prob.geom.e2))
+        print(f"[ensemble64] cell {k} (N {sizes[k]}): oracle residual {res:.1e} omega err {np.abs(om[sl] - o).max():.1e} "
+              f"mu err {abs(mu[k] - m):.1e}", flush=True)
+        assert res <= 2e-10
+        assert np.abs(om[sl] - o).max() <= 1e-7 * max(1.0, np.abs(o).max())
+        assert np.abs(vel[sl] - v).max() <= 1e-7 * sc_v
+        assert abs(mu[k] - m) <= 1e-7 * m
