@@ -328,3 +328,23 @@ def test_trained_network_gain():
         out[name] = (r0, r["info"]["iterations"])
         print(f"[gain] {name:9s} initial residual {r0:.3e}  GMRES iterations {r['info']['iterations']}")
     assert out["trained"][0] < out["untrained"][0] <= 1.0 + 1e-9
+
+
+def test_trajectory_cell_full_size_steps():
+    """A held-out trajectory cell at full size (seed 6002: 70 ellipses, 8,792 nodes) stepped
+    as the bench steps it (relaxed FP32 with the block preconditioner, dt = 0.01): every
+    step meets the FP64 residual, and the density of a solve at the final state leaves a
+    residual within 2e-10 through the oracle's own operator."""
+    spm = _spm()
+    wl = W.trajectory_cell(6002)
+    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_RELAXED, precond=spm.SPM_PRECOND_BLOCK).set_workload(wl)
+    out = s.step(0.01, 3, 0.0, wl["centers"], wl["theta"])
+    assert all(i["status"] == 0 and i["rel_residual"] <= 1e-10 for i in out["infos"])
+    w2 = dict(wl, centers=out["centers"], theta=out["theta"], skew=wl["skew"] + out["t"])
+    s.set_workload(w2)
+    r = s.solve()
+    prob = op.make_problem(w2)
+    b = op.rhs(prob)
+    res = np.linalg.norm(b - op.apply(prob, _n(r["sigma"]))) / np.linalg.norm(b)
+    print(f"[trajectory 6002] its {[i['iterations'] for i in out['infos']]} oracle residual {res:.1e}", flush=True)
+    assert res <= 2e-10
