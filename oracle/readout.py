@@ -29,6 +29,30 @@ particle i is -int sigma_i, and the cell-averaged shear stress gives
 
 |U| = |det(e1, e2)|. ``mu_eff_wall`` evaluates eq. (mueff) directly with
 Gauss-Legendre on D; it is valid only when no particle comes near D.
+
+``mu_eff_contour`` is the contour-deformation form of eq. (mueff) (Sec. 7, the
+proposition on efficient evaluation of the effective viscosity), re-derived for the
+near set used here (3x3 images of whole particles, centres wrapped into U). The force
+through a curve C joining D's end points around the particles is
+int_C T = int_C T_near + int_D T_corr, and by translation invariance of G^t
+
+    int_C T_near = sum_q sum_{n=-1,0,1} J_q(-n),   J_q(a) = int over l + a e2 of S^t_{Gamma_q}[sigma],
+
+where l = (C - e1) u C u (C + e1) runs three cells along e1 and only the unshifted
+curve Gamma_q is a source. Gauss' law (Sec. 4.1 lemma on net quantities, the exterior
+traction of a single layer integrates to -int sigma) on the region between l + a e2 and
+l + b e2, closed by the two straight sides through the corners p0 - e1 + k e2 and
+p0 + 2 e1 + k e2 (p0 = c_U - e1/2 - e2/2, outward normals), gives
+J(b) - J(a) + sides(a, b) = -(force of Gamma_q if it lies between them). With C taken
+so that every particle lies in the deformed copy of the cell that holds its centre, the
+strips (-1, 0) and (1, 2) hold no source, so
+
+    int_C T_near = sum_q [2 J_q(-1) + J_q(2) - sides_q(-1, 0) + sides_q(1, 2)],
+
+and J(-1), J(2) may be taken on the straight lines D - e2, D + 2 e2. Every target is
+at least about half a cell (less the particle radius) from its source curve, so
+Gauss-Legendre with m nodes per cell edge and the plain trapezoid rule on the curves
+suffice, however the particles sit on D; the correction part is smooth on D.
 """
 from __future__ import annotations
 
@@ -85,3 +109,48 @@ def mu_eff_wall(prob, sigma, nq=64):
     Tc = periodizer.correction_traction(prob.P, xi, xq, nD)
     T1 = Tn[:, 0] + Tc[:, 0]
     return prob.cfg.mu + (wq * T1).sum() / (prob.cfg.gamma * np.linalg.norm(g.e1))
+
+
+def contour_points(geom, m):
+    """Quadrature of the deformed contour: points [10 m, 2], normals [10 m, 2] and
+    signed weights [10 m] (J(-1) twice, J(2) once, the four straight sides with the signs
+    of the Gauss-law balance), then the points, normals and weights of D [m]."""
+    t, wt = periodizer.gauss_legendre(m)
+    t, w = 0.5 * t, 0.5 * wt
+    e1, e2 = geom.e1, geom.e2
+    l1, l2 = np.linalg.norm(e1), np.linalg.norm(e2)
+    p0 = geom.cU - 0.5 * e1 - 0.5 * e2
+    nh = np.array([-e1[1], e1[0]]) / l1       # left normal of e1: (0, 1) on D
+    nv = np.array([e2[1], -e2[0]]) / l2       # right normal of e2: outward on the right side
+    pts, nrm, wts = [], [], []
+    for a, coef in ((-1, 2.0), (2, 1.0)):
+        for k in (-1, 0, 1):
+            pts.append(p0 + a * e2 + (k + 0.5 + t)[:, None] * e1)
+            nrm.append(np.tile(nh, (m, 1)))
+            wts.append(coef * w * l1)
+    for corner, coef in ((p0 + 2 * e1 - e2, -1.0), (p0 - e1 - e2, 1.0), (p0 + 2 * e1 + e2, 1.0), (p0 - e1 + e2, -1.0)):
+        pts.append(corner + (0.5 + t)[:, None] * e2)
+        nrm.append(np.tile(nv, (m, 1)))
+        wts.append(coef * w * l2)
+    xD = p0 + (0.5 + t)[:, None] * e1
+    return (np.concatenate(pts), np.concatenate(nrm), np.concatenate(wts),
+            xD, np.tile(nh, (m, 1)), w * l1)
+
+
+def mu_eff_contour(prob, sigma, m=16, xi=None):
+    """eq. (mueff) by contour deformation (module docstring); valid whether or not
+    particles cross D. 3x3 near set only. xi: proxy strengths to use instead of the
+    ones this density gives (to separate the proxy solve from the rest in comparisons)."""
+    if prob.cfg.near_set != "3x3" or prob.cfg.image_range != 1:
+        raise NotImplementedError("contour form derived for the 3x3 near set")
+    g = prob.geom
+    s2 = to2(np.asarray(sigma, dtype=np.float64))
+    f = near.forces(g, s2)
+    if xi is None:
+        xi, _, _ = proxy_strengths(prob, s2)
+    pts, nrm, wts, xD, nD, wD = contour_points(g, m)
+    Tn = _clib.near_traction(pts, nrm, g.x, f, np.zeros((1, 2)))
+    Tc = periodizer.correction_traction(prob.P, xi, xD, nD)
+    F = (wts[:, None] * Tn).sum(0) + (wD[:, None] * Tc).sum(0)
+    l1 = np.linalg.norm(g.e1)
+    return prob.cfg.mu + (g.e1 / l1) @ F / (prob.cfg.gamma * l1)
