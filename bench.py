@@ -4,8 +4,9 @@
 Workload: 200 random ellipses at area fraction 0.4, 256 nodes each (N = 51,200),
 seed 2 (the large-cell configuration on which node-pair evaluations per second are
 quoted). One step = one complete mobility solve from a zero initial guess to an FP64
-relative residual of 1e-10 (matvecs + GMRES + readout of v, omega, mu_eff), with the
-geometry already resident in HBM. Default precision: FP32 near sums inside FP64
+relative residual of 1e-10 (matvecs + GMRES + readout of v, omega, mu_eff), then
+mu_eff once more by contour deformation (valid with particles across the wall D), with
+the geometry already resident in HBM. Default precision: FP32 near sums inside FP64
 iterative refinement; --precision fp64 times plain FP64 GMRES.
 
 value = node-image pair evaluations (9 N^2 per matvec, all matvecs of the step) per
@@ -187,6 +188,7 @@ def main():
 
     for k in range(args.warmup):
         r = s.solve()
+        s.effective_viscosity_contour(r["sigma"])
         log(f"[bench] warmup {k}: {r['info']}")
     torch.cuda.synchronize()
     s.profile(True)
@@ -195,6 +197,7 @@ def main():
     infos = []
     for k in range(args.steps):
         r = s.solve()
+        mu_c = s.effective_viscosity_contour(r["sigma"])
         infos.append(r["info"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -255,7 +258,8 @@ def main():
            "config": {"workload": wl["name"], "N": N, "particles": s.No, "nodes_per_particle": 256,
                       "precision": args.precision, "tol": 1e-10, "images": "3x3", "proxies": 32,
                       "wall_points": 24, "close_factor": 10},
-           "roofline": roofline, "roofline_other_precision": other, "cpu_baseline": cpu, **extra}
+           "roofline": roofline, "roofline_other_precision": other, "cpu_baseline": cpu,
+           "mu_eff": {"stresslet": float(r["mu_eff"][0]), "contour": float(mu_c[0])}, **extra}
     print(json.dumps(out), flush=True)
 
 

@@ -72,6 +72,10 @@ extern "C" {
                                 r(t) = s (1 + A cos(omega t + phi)), |A| < 1, integer omega >= 0
                                 (the smooth star-shaped curves of Sec. 8 Examples 2 and 4) */
 
+#define SPM_NEAR_DIRECT 0  /* near-image sum: tiled direct N-body kernels (FP64 or FP32) */
+#define SPM_NEAR_FMM 1     /* near-image sum: fast multipole method in FP64 (Sec. 6.2 remark: the
+                              paper evaluates this sum with an FMM); single-cell handles, SPM_FP64 */
+
 #define SPM_PRECOND_NONE 0
 #define SPM_PRECOND_BLOCK 1  /* right preconditioner blockdiag(B_q)^-1 of isolated-body self blocks
                                 (particles of at most 512 nodes; SPM_EINVAL at the solve otherwise) */
@@ -102,6 +106,11 @@ typedef struct {
                                the plain-GMRES fallback; 0 = max_iter [0] */
   double relax_tol;     /* SPM_FP32_RELAXED: residual estimate below which products use the FP32
                            near sum [1e-5] */
+  int32_t near_method;  /* SPM_NEAR_DIRECT or SPM_NEAR_FMM [SPM_NEAR_DIRECT]; SPM_NEAR_FMM needs
+                           precision SPM_FP64 (SPM_EINVAL at spm_create) and one cell (SPM_EINVAL
+                           when more cells are set) */
+  int32_t fmm_order;    /* SPM_NEAR_FMM: terms of each multipole and local expansion, 8..64;
+                           0 = 40 (relative error of the near sum about 1e-14) [0] */
 } spm_config;
 
 typedef struct {
@@ -202,6 +211,15 @@ int spm_eval_field(spm_handle* h, const double* sigma, int64_t n_targets, const 
  * value per cell. */
 int spm_effective_viscosity(spm_handle* h, const double* sigma, double* mu_eff);
 
+/* Effective viscosity by contour deformation (Sec. 7, efficient evaluation of the
+ * effective viscosity), derived for this library's 3x3 near set: the shear force of
+ * eq. mueff is carried from D to straight lines and segments that are about half a cell
+ * or more from every source curve (D - e2, D + 2 e2 and four lattice-edge segments three
+ * cells apart), plus the smooth proxy correction on D; valid whether or not particles
+ * cross D. Gauss-Legendre with m nodes per cell edge (m = 0 selects 16; 4 <= m <= 128,
+ * else SPM_EINVAL). sigma: device [2N] (SoA). mu_eff: device, one value per cell. */
+int spm_effective_viscosity_contour(spm_handle* h, const double* sigma, int32_t m, double* mu_eff);
+
 /* Forward Euler time stepping (Sec. 7) of a single-cell handle. t_inout (host): time on entry/exit;
  * the skew follows s(t) = s(0) + gamma t from the lattice set last plus the
  * elapsed time. centers_inout [2n], theta_inout [n] (host) hold the state;
@@ -221,6 +239,11 @@ int spm_step(spm_handle* h, double dt, int32_t n_steps, double* t_inout, double*
 /* Near-image traction sum T_near(x_i) = sum_j sum_{s in S9} G^t(x_i, y_j + s; n_i) w_j sigma_j,
  * self pair skipped (Sec. 4.2 G_near; 3x3 images per particle). out [2N]. */
 int spm_near_traction(spm_handle* h, const double* sigma, double* out, int32_t precision);
+
+/* With SPM_NEAR_FMM: the quadtree of the current geometry (levels below the root box, expansion
+ * terms) and the work of one near sum (direct pairs of neighbouring leaves, multipole-to-local
+ * translations). Host outputs, any may be NULL. SPM_ESTATE without an FMM plan. */
+int spm_fmm_stats(spm_handle* h, int32_t* levels, int32_t* order, double* p2p_pairs, double* m2l_translations);
 
 /* Close-evaluation correction Delta T (Sec. 6.3): barycentric traction minus the
  * plain near-sum terms over each close (target, source image) pair. out [2N].

@@ -12,7 +12,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["k_geometry.hip", "k_near.hip", "k_periodizer.hip", "k_close.hip", "k_operator.hip", "k_gmres.hip",
-           "k_mlp.hip", "k_learned.hip", "k_precond.hip", "k_field.hip", "autotune.hip", "capi.hip"]
+           "k_mlp.hip", "k_learned.hip", "k_precond.hip", "k_field.hip", "k_fmm.hip", "autotune.hip", "capi.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",
          # packed FP32 VALU forms are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

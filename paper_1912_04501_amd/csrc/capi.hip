@@ -538,6 +538,7 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   }
   build_near_plan(h, SPM_FP64);
   build_near_plan(h, SPM_FP32);
+  if (h->cfg.near_method == SPM_NEAR_FMM) build_fmm_plan(h);
   sync(h);
   h->have_particles = true;
 }
@@ -552,8 +553,12 @@ void stage_xi(spm_handle* h, const double* sigma, bool with_active) {
 }
 
 void matvec(spm_handle* h, const double* sigma, double* out, int precision, bool with_active) {
+  if (h->fmm.on) precision = SPM_FP64;     // the FMM sum is FP64: FP64 close and self terms
   stage_xi(h, sigma, with_active);
-  launch_near_impl(h, precision, with_active);
+  if (h->fmm.on)
+    launch_fmm(h, h->wk.Tpart);
+  else
+    launch_near_impl(h, precision, with_active);
   launch_combine(h, sigma, true, precision);
   if (h->cl.ntargets > 0) {
     launch_vplus(h, sigma);
@@ -941,6 +946,209 @@ int solve_api(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
 }  // namespace
 
 namespace spm {
+namespace {
+inline int64_t fmm_box_off(int l) { return (((int64_t)1 << (2 * l)) - 1) / 3; }
+
+// Counts of a leaf grid summed into every level: out[box_off(l) + iy 2^l + ix], levels 0..L.
+std::vector<int64_t> fmm_levels(const std::vector<int64_t>& leaf, int L) {
+  std::vector<int64_t> out(fmm_box_off(L + 1), 0);
+  std::copy(leaf.begin(), leaf.end(), out.begin() + fmm_box_off(L));
+  for (int l = L - 1; l >= 0; --l) {
+    const int n = 1 << l;
+    for (int iy = 0; iy < n; ++iy)
+      for (int ix = 0; ix < n; ++ix) {
+        int64_t v = 0;
+        for (int ch = 0; ch < 4; ++ch)
+          v += out[fmm_box_off(l + 1) + (int64_t)(2 * iy + (ch >> 1)) * (2 * n) + (2 * ix + (ch & 1))];
+        out[fmm_box_off(l) + (int64_t)iy * n + ix] = v;
+      }
+  }
+  return out;
+}
+
+// Direct pairs of the leaves and multipole-to-local translations of one evaluation.
+std::pair<double, double> fmm_work(const std::vector<int64_t>& bs, const std::vector<int64_t>& bt, int L) {
+  double p2p = 0, m2l = 0;
+  const int nL = 1 << L;
+  for (int iy = 0; iy < nL; ++iy)
+    for (int ix = 0; ix < nL; ++ix) {
+      const int64_t t = bt[fmm_box_off(L) + (int64_t)iy * nL + ix];
+      if (!t) continue;
+      int64_t s = 0;
+      for (int jy = std::max(iy - 1, 0); jy <= std::min(iy + 1, nL - 1); ++jy)
+        for (int jx = std::max(ix - 1, 0); jx <= std::min(ix + 1, nL - 1); ++jx)
+          s += bs[fmm_box_off(L) + (int64_t)jy * nL + jx];
+      p2p += (double)t * (double)s;
+    }
+  for (int l = 2; l <= L; ++l) {
+    const int n = 1 << l, np = n >> 1;
+    for (int iy = 0; iy < n; ++iy)
+      for (int ix = 0; ix < n; ++ix) {
+        if (!bt[fmm_box_off(l) + (int64_t)iy * n + ix]) continue;
+        for (int qy = std::max((iy >> 1) - 1, 0); qy <= std::min((iy >> 1) + 1, np - 1); ++qy)
+          for (int qx = std::max((ix >> 1) - 1, 0); qx <= std::min((ix >> 1) + 1, np - 1); ++qx)
+            for (int ch = 0; ch < 4; ++ch) {
+              const int bx = 2 * qx + (ch & 1), by = 2 * qy + (ch >> 1);
+              if (std::abs(bx - ix) <= 1 && std::abs(by - iy) <= 1) continue;
+              if (bs[fmm_box_off(l) + (int64_t)by * n + bx]) m2l += 1;
+            }
+      }
+  }
+  return {p2p, m2l};
+}
+}  // namespace
+
+// Quadtree of the FMM near sum for the current geometry (one cell): the root box holds the 9 N
+// image sources (node + m e1 + n e2 with the shifts of the direct sum, so the target's own node is
+// the source at zero distance); the leaf level minimises an operation count (direct pairs at
+// ~25 flop against multipole-to-local translations at ~12 p^2 flop); sources and targets are
+// sorted by leaf; box lists of every pass are uploaded with the expansion buffers.
+void build_fmm_plan(spm_handle* h) {
+  FmmPlan& F = h->fmm;
+  F.on = false;
+  const Geo& g = h->geo;
+  const int64_t N = g.N;
+  if (g.C != 1) throw ApiError(SPM_EINVAL, "the FMM near sum runs on single-cell handles");
+  if (9 * N >= ((int64_t)1 << 31)) throw ApiError(SPM_EINVAL, "too many nodes for the FMM");
+  const int p = h->cfg.fmm_order > 0 ? h->cfg.fmm_order : 40;
+  std::vector<double> x(N), y(N);
+  download(h, x.data(), g.x, N * sizeof(double));
+  download(h, y.data(), g.y, N * sizeof(double));
+  const double skew = h->cells[0].skew;
+  const int64_t ns = 9 * N;
+  std::vector<double> sx(ns), sy(ns);
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  for (int s = 0; s < kShifts; ++s) {
+    const double dx = shift_x(s, skew), dy = shift_y(s);
+    for (int64_t j = 0; j < N; ++j) {
+      const double a = x[j] + dx, b = y[j] + dy;
+      sx[s * N + j] = a;
+      sy[s * N + j] = b;
+      xmin = std::min(xmin, a);
+      xmax = std::max(xmax, a);
+      ymin = std::min(ymin, b);
+      ymax = std::max(ymax, b);
+    }
+  }
+  const double D0 = std::max(xmax - xmin, ymax - ymin) * (1.0 + 1e-6) + 1e-12;
+  const double c0x = 0.5 * (xmin + xmax), c0y = 0.5 * (ymin + ymax);
+  auto leaf_of = [&](double a, double b, int L) -> int64_t {
+    const int n = 1 << L;
+    const int ix = std::min(std::max((int)std::floor((a - (c0x - 0.5 * D0)) / D0 * n), 0), n - 1);
+    const int iy = std::min(std::max((int)std::floor((b - (c0y - 0.5 * D0)) / D0 * n), 0), n - 1);
+    return (int64_t)iy * n + ix;
+  };
+  const int64_t ctr = 4 * N;   // shift index 4 is m = n = 0: the targets themselves
+  int bestL = 2;
+  double best = 1e300, best_p2p = 0, best_m2l = 0;
+  for (int L = 2; L <= 10; ++L) {
+    std::vector<int64_t> cs((int64_t)1 << (2 * L), 0), ct((int64_t)1 << (2 * L), 0);
+    for (int64_t k = 0; k < ns; ++k) cs[leaf_of(sx[k], sy[k], L)]++;
+    for (int64_t j = 0; j < N; ++j) ct[leaf_of(sx[ctr + j], sy[ctr + j], L)]++;
+    const auto w = fmm_work(fmm_levels(cs, L), fmm_levels(ct, L), L);
+    const double cost = 25.0 * w.first + 12.0 * p * p * w.second;
+    if (cost < best) {
+      best = cost;
+      bestL = L;
+      best_p2p = w.first;
+      best_m2l = w.second;
+    } else if (L > bestL + 1) {
+      break;
+    }
+  }
+  const int L = bestL;
+  const int64_t nl = (int64_t)1 << (2 * L);
+  // counting sort of the sources and of the targets by leaf
+  std::vector<int64_t> cs(nl, 0), ct(nl, 0);
+  std::vector<int64_t> lf(ns);
+  for (int64_t k = 0; k < ns; ++k) cs[lf[k] = leaf_of(sx[k], sy[k], L)]++;
+  for (int64_t j = 0; j < N; ++j) ct[lf[ctr + j]]++;
+  std::vector<int32_t> leaf_s(nl + 1, 0), leaf_t(nl + 1, 0);
+  for (int64_t b = 0; b < nl; ++b) {
+    leaf_s[b + 1] = leaf_s[b] + (int32_t)cs[b];
+    leaf_t[b + 1] = leaf_t[b] + (int32_t)ct[b];
+  }
+  std::vector<double> ssx(ns), ssy(ns);
+  std::vector<int32_t> ssj(ns), tperm(N), tleaf(N);
+  {
+    std::vector<int32_t> fill(leaf_s.begin(), leaf_s.end() - 1);
+    for (int64_t k = 0; k < ns; ++k) {
+      const int32_t d = fill[lf[k]]++;
+      ssx[d] = sx[k];
+      ssy[d] = sy[k];
+      ssj[d] = (int32_t)(k % N);
+    }
+    std::vector<int32_t> tf(leaf_t.begin(), leaf_t.end() - 1);
+    for (int64_t j = 0; j < N; ++j) {
+      const int32_t d = tf[lf[ctr + j]]++;
+      tperm[d] = (int32_t)j;
+      tleaf[d] = (int32_t)lf[ctr + j];
+    }
+  }
+  const std::vector<int64_t> bs = fmm_levels(cs, L), bt = fmm_levels(ct, L);
+  const int64_t nbox = fmm_box_off(L + 1);
+  std::vector<int32_t> bsrc(nbox);
+  for (int64_t b = 0; b < nbox; ++b) bsrc[b] = (int32_t)std::min<int64_t>(bs[b], INT32_MAX);
+  // box lists: P2M (leaves with sources), M2M levels L-1..2, M2L (target boxes of levels 2..L),
+  // L2L levels 3..L
+  std::vector<int32_t> lists;
+  F.seg.assign(1, 0);
+  auto push_level = [&](int l, const std::vector<int64_t>& cnt) {
+    for (int64_t b = fmm_box_off(l); b < fmm_box_off(l + 1); ++b)
+      if (cnt[b]) lists.push_back((int32_t)b);
+  };
+  push_level(L, bs);
+  F.seg.push_back((int64_t)lists.size());
+  for (int l = L - 1; l >= 2; --l) {
+    push_level(l, bs);
+    F.seg.push_back((int64_t)lists.size());
+  }
+  for (int l = 2; l <= L; ++l) push_level(l, bt);
+  F.seg.push_back((int64_t)lists.size());
+  for (int l = 3; l <= L; ++l) {
+    push_level(l, bt);
+    F.seg.push_back((int64_t)lists.size());
+  }
+  std::vector<double> fact(2 * p);
+  fact[0] = 1.0;
+  for (int k = 1; k < 2 * p; ++k) fact[k] = fact[k - 1] * k;
+  ensure(h, F.sx, ns);
+  ensure(h, F.sy, ns);
+  ensure(h, F.sj, ns);
+  ensure(h, F.fs1, ns);
+  ensure(h, F.fs2, ns);
+  ensure(h, F.leaf_s, nl + 1);
+  ensure(h, F.tperm, N);
+  ensure(h, F.tleaf, N);
+  ensure(h, F.bsrc, nbox);
+  ensure(h, F.lists, lists.size());
+  ensure(h, F.fact, 2 * p);
+  ensure(h, F.Mx, (size_t)nbox * 3 * p * 2);
+  ensure(h, F.Lx, (size_t)nbox * 3 * p * 2);
+  ensure(h, F.nsplit1, 1);
+  upload(h, F.sx, ssx.data(), ns * sizeof(double));
+  upload(h, F.sy, ssy.data(), ns * sizeof(double));
+  upload(h, F.sj, ssj.data(), ns * sizeof(int32_t));
+  upload(h, F.leaf_s, leaf_s.data(), (nl + 1) * sizeof(int32_t));
+  upload(h, F.tperm, tperm.data(), N * sizeof(int32_t));
+  upload(h, F.tleaf, tleaf.data(), N * sizeof(int32_t));
+  upload(h, F.bsrc, bsrc.data(), nbox * sizeof(int32_t));
+  upload(h, F.lists, lists.data(), lists.size() * sizeof(int32_t));
+  upload(h, F.fact, fact.data(), fact.size() * sizeof(double));
+  const int32_t one = 1;
+  upload(h, F.nsplit1, &one, sizeof(int32_t));
+  F.p = p;
+  F.L = L;
+  F.D0 = D0;
+  F.c0x = c0x;
+  F.c0y = c0y;
+  F.nsrc = ns;
+  F.p2p_pairs = best_p2p;
+  F.m2l = best_m2l;
+  F.on = true;
+  drop_graphs(h);
+}
+
 size_t max_splits_all(spm_handle* h) {
   return (size_t)std::max(h->wk.near[0].max_splits, h->wk.near[1].max_splits);
 }
@@ -1028,6 +1236,8 @@ void spm_default_config(spm_config* c) {
   c->precision = SPM_FP64;
   c->inner_tol = 0.0;
   c->relax_tol = 1e-5;
+  c->near_method = SPM_NEAR_DIRECT;
+  c->fmm_order = 0;
   c->min_gap = 0.0;
   c->rcond = 1e-14;
   c->use_graph = 1;
@@ -1053,7 +1263,10 @@ int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_
       (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR && c.precision != SPM_FP32_RELAXED) ||
       !(c.inner_tol >= 0 && c.inner_tol < 1) || !(c.relax_tol > 0 && c.relax_tol < 1) ||
       c.poll_every < 1 || c.x0 < SPM_X0_ZERO || c.x0 > SPM_X0_NETWORK ||
-      (c.precond != SPM_PRECOND_NONE && c.precond != SPM_PRECOND_BLOCK) || c.learned_max_iter < 0) {
+      (c.precond != SPM_PRECOND_NONE && c.precond != SPM_PRECOND_BLOCK) || c.learned_max_iter < 0 ||
+      (c.near_method != SPM_NEAR_DIRECT && c.near_method != SPM_NEAR_FMM) ||
+      (c.near_method == SPM_NEAR_FMM && c.precision != SPM_FP64) ||
+      (c.fmm_order != 0 && (c.fmm_order < 8 || c.fmm_order > 64))) {
     delete h;
     return SPM_EINVAL;
   }
@@ -1280,15 +1493,51 @@ int spm_effective_viscosity(spm_handle* h, const double* sigma, double* mu_eff) 
   });
 }
 
+int spm_effective_viscosity_contour(spm_handle* h, const double* sigma, int32_t m, double* mu_eff) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!sigma || !mu_eff) throw ApiError(SPM_EINVAL, "null pointer");
+    if (m == 0) m = 16;
+    if (m < 4 || m > 128) throw ApiError(SPM_EINVAL, "contour quadrature order outside [4, 128]");
+    std::vector<double> t, w;
+    gauss_legendre(m, t, w);
+    t.insert(t.end(), w.begin(), w.end());
+    ensure(h, h->wk.contour_gl, (size_t)2 * m);
+    ensure(h, h->wk.contour, (size_t)h->geo.C * 11 * m);
+    SPM_HIP_CHECK(hipMemcpyAsync(h->wk.contour_gl, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice,
+                                 h->stream));
+    stage_xi(h, sigma, false);              // f = w sigma, proxy strengths of every cell
+    launch_mu_eff_contour(h, m, mu_eff);
+    sync(h);                                // also keeps t alive until its copy has run
+    return SPM_OK;
+  });
+}
+
 int spm_near_traction(spm_handle* h, const double* sigma, double* out, int32_t precision) {
   return guarded(h, [&]() {
     need_particles(h);
     if (!sigma || !out) throw ApiError(SPM_EINVAL, "null vector");
     if (precision != SPM_FP64 && precision != SPM_FP32) throw ApiError(SPM_EINVAL, "precision must be FP64 or FP32");
     launch_prep(h, sigma);
-    launch_near(h, precision);
-    launch_near_sum_only(h, out, precision);
+    if (h->fmm.on) {
+      launch_fmm(h, out);
+    } else {
+      launch_near(h, precision);
+      launch_near_sum_only(h, out, precision);
+    }
     sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_fmm_stats(spm_handle* h, int32_t* levels, int32_t* order, double* p2p_pairs, double* m2l_translations) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!h->fmm.on) throw ApiError(SPM_ESTATE, "no FMM plan (near_method is not SPM_NEAR_FMM)");
+    if (levels) *levels = h->fmm.L;
+    if (order) *order = h->fmm.p;
+    if (p2p_pairs) *p2p_pairs = h->fmm.p2p_pairs;
+    if (m2l_translations) *m2l_translations = h->fmm.m2l;
     return SPM_OK;
   });
 }

@@ -1,0 +1,362 @@
+// Fast multipole evaluation of the near-image traction sum (FP64, one cell).
+//
+// The paper evaluates the near sum from the image sources to the nodes with an FMM (Sec. 6.2,
+// remark on the cost; Sec. 8 runs at tolerances 1e-9 to 1e-12). Here it is a complex-variable FMM
+// on a uniform quadtree. With z the target, n its unit normal and r = z - z_j (complex), the
+// traction kernel of eq. Gt applied to f_j = w_j sigma_j splits into Cauchy sums:
+//
+//   (r.n)(r.f) r / |r|^4 = n f / (4 r) + (conj(n) f + n conj(f)) / (4 conj(r)) + conj(n) conj(f) r / (4 conj(r)^2),
+//   T(z) = -(1/4pi) [ 2 n Re A(z) + conj(n) conj(B(z) + C'(z) - conj(z) A'(z)) ],
+//   A = sum_j f_j / (z - z_j),  B = sum_j conj(f_j) / (z - z_j),  C = sum_j f_j conj(z_j) / (z - z_j).
+//
+// C is carried about the centre c of every box, C_c = sum_j f_j conj(z_j - c) / (z - z_j) = C - conj(c) A,
+// so that no expansion holds the large factor conj(z_j): moving an expansion from centre c to c'
+// adds conj(c - c') times the moved A expansion, and at the target C' - conj(z) A' = C_c' - conj(z - c) A'.
+//
+// Expansions are scaled by the box side h: multipole a_k = sum_j q_j ((z_j - c)/h)^k, so that
+// sum_j q_j / (z - z_j) = (1/h) sum_k a_k (h / (z - c))^(k+1); local L_l with
+// sum_j q_j / (z - z_j) = sum_l L_l ((z - c)/h)^l. Translations (binomial sums) use factorial
+// tables:
+//   M2M (child c' to parent c, t = (c' - c)/h_P): a_k = k! sum_{m<=k} (a'_m 2^-m / m!) (t^(k-m) / (k-m)!)
+//   M2L (source c_s to target c_t, rho = h / (c_t - c_s)):
+//       L_l = (-1)^l rho^(l+1) / (h l!) sum_k (k + l)! (a_k rho^k / k!)
+//   L2L (parent c to child c', t = (c' - c)/h_P): L'_m = (2^-m / m!) sum_{l>=m} (L_l l!) (t^(l-m) / (l-m)!)
+// Interaction lists are the usual ones (children of the parent's neighbours that are not
+// neighbours); leaves evaluate their 3x3 neighbourhood directly, skipping the pair at zero
+// distance (the target's own node). Every pass is deterministic: one wavefront per box, lanes over
+// expansion terms, fixed loop orders.
+#include "spm_internal.h"
+
+namespace spm {
+namespace {
+
+struct cx {
+  double r, i;
+};
+__device__ __forceinline__ cx operator+(cx a, cx b) { return {a.r + b.r, a.i + b.i}; }
+__device__ __forceinline__ cx operator-(cx a, cx b) { return {a.r - b.r, a.i - b.i}; }
+__device__ __forceinline__ cx operator*(cx a, cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cx operator*(cx a, double s) { return {a.r * s, a.i * s}; }
+__device__ __forceinline__ cx conj(cx a) { return {a.r, -a.i}; }
+__device__ __forceinline__ cx cdiv(cx a, cx b) {
+  const double d = b.r * b.r + b.i * b.i;
+  return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
+}
+__device__ __forceinline__ cx cpow(cx w, int k) {   // binary powering, k >= 0
+  cx r = {1.0, 0.0};
+  while (k) {
+    if (k & 1) r = r * w;
+    w = w * w;
+    k >>= 1;
+  }
+  return r;
+}
+
+__host__ __device__ __forceinline__ int64_t box_off(int l) { return (((int64_t)1 << (2 * l)) - 1) / 3; }
+
+struct FmmArgs {
+  int p, L;
+  double D0, c0x, c0y;
+  const double *sx, *sy, *fs1, *fs2;
+  const int32_t *leaf_s, *bsrc;
+  const double* fact;
+  cx *Mx, *Lx;                     // [box][3][p]
+};
+
+__device__ __forceinline__ cx box_center(const FmmArgs& a, int l, int64_t loc) {
+  const int n = 1 << l;
+  const double h = a.D0 / n;
+  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  return {a.c0x - 0.5 * a.D0 + (ix + 0.5) * h, a.c0y - 0.5 * a.D0 + (iy + 0.5) * h};
+}
+
+__global__ __launch_bounds__(256) void k_fmm_gather(int64_t ns, const int32_t* __restrict__ sj,
+                                                    const double* __restrict__ f1, const double* __restrict__ f2,
+                                                    double* __restrict__ fs1, double* __restrict__ fs2) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= ns) return;
+  const int32_t j = sj[k];
+  fs1[k] = f1[j];
+  fs2[k] = f2[j];
+}
+
+// multipoles of the leaves with sources; lane k holds term k
+__global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __restrict__ list) {
+  const int64_t gid = list[blockIdx.x];
+  const int64_t loc = gid - box_off(a.L);
+  const cx c = box_center(a, a.L, loc);
+  const double ih = (double)(1 << a.L) / a.D0;
+  const int k = threadIdx.x;
+  cx A = {0, 0}, B = {0, 0}, C = {0, 0};
+  const int32_t s0 = a.leaf_s[loc], s1 = a.leaf_s[loc + 1];
+  if (k < a.p) {
+    for (int32_t j = s0; j < s1; ++j) {
+      const cx d = {a.sx[j] - c.r, a.sy[j] - c.i};
+      const cx q = {a.fs1[j], a.fs2[j]};
+      const cx wk = cpow(d * ih, k);
+      const cx qw = q * wk;
+      A = A + qw;
+      B = B + conj(q) * wk;
+      C = C + qw * conj(d);
+    }
+    cx* out = a.Mx + gid * 3 * a.p;
+    out[k] = A;
+    out[a.p + k] = B;
+    out[2 * a.p + k] = C;
+  }
+}
+
+// multipoles of level l from their children at level l + 1
+__global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t* __restrict__ list) {
+  __shared__ cx ac[3][64];
+  __shared__ cx tp[64];
+  const int64_t gid = list[blockIdx.x];
+  const int64_t loc = gid - box_off(l);
+  const int n = 1 << l;
+  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const cx c = box_center(a, l, loc);
+  const double ihP = (double)n / a.D0;
+  const int k = threadIdx.x, p = a.p;
+  cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
+  for (int ch = 0; ch < 4; ++ch) {
+    const int64_t cloc = (int64_t)(2 * iy + (ch >> 1)) * (2 * n) + (2 * ix + (ch & 1));
+    const int64_t cgid = box_off(l + 1) + cloc;
+    if (a.bsrc[cgid] == 0) continue;     // the same for every lane
+    const cx cc = box_center(a, l + 1, cloc);
+    const cx d = cc - c;
+    __syncthreads();
+    if (k < p) {
+      const cx* m = a.Mx + cgid * 3 * p;
+      const double s = ldexp(1.0, -k) / a.fact[k];
+      ac[0][k] = m[k] * s;
+      ac[1][k] = m[p + k] * s;
+      ac[2][k] = m[2 * p + k] * s;
+      tp[k] = cpow(d * ihP, k) * (1.0 / a.fact[k]);
+    }
+    __syncthreads();
+    if (k < p) {
+      cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
+      for (int m = 0; m <= k; ++m) {
+        const cx t = tp[k - m];
+        sA = sA + ac[0][m] * t;
+        sB = sB + ac[1][m] * t;
+        sC = sC + ac[2][m] * t;
+      }
+      const double fk = a.fact[k];
+      sA = sA * fk;
+      oA = oA + sA;
+      oB = oB + sB * fk;
+      oC = oC + sC * fk + conj(d) * sA;
+    }
+  }
+  if (k < p) {
+    cx* out = a.Mx + gid * 3 * p;
+    out[k] = oA;
+    out[p + k] = oB;
+    out[2 * p + k] = oC;
+  }
+}
+
+// local expansions from the interaction lists, every level in one launch (written, not added)
+__global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __restrict__ list) {
+  __shared__ cx bs[3][64];
+  const int64_t gid = list[blockIdx.x];
+  int l = 2;
+  while (l < a.L && gid >= box_off(l + 1)) ++l;
+  const int64_t loc = gid - box_off(l);
+  const int n = 1 << l;
+  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const cx c = box_center(a, l, loc);
+  const double h = a.D0 / n;
+  const int k = threadIdx.x, p = a.p;
+  const int px = ix >> 1, py = iy >> 1, np = n >> 1;
+  cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
+  for (int qy = max(py - 1, 0); qy <= min(py + 1, np - 1); ++qy) {
+    for (int qx = max(px - 1, 0); qx <= min(px + 1, np - 1); ++qx) {
+      for (int ch = 0; ch < 4; ++ch) {
+        const int bx = 2 * qx + (ch & 1), by = 2 * qy + (ch >> 1);
+        if (abs(bx - ix) <= 1 && abs(by - iy) <= 1) continue;
+        const int64_t sloc = (int64_t)by * n + bx;
+        const int64_t sgid = box_off(l) + sloc;
+        if (a.bsrc[sgid] == 0) continue;
+        const cx cs = box_center(a, l, sloc);
+        const cx rho = cdiv({h, 0.0}, c - cs);
+        __syncthreads();
+        const cx rk = cpow(rho, k);
+        if (k < p) {
+          const cx* m = a.Mx + sgid * 3 * p;
+          const cx s = rk * (1.0 / a.fact[k]);
+          bs[0][k] = m[k] * s;
+          bs[1][k] = m[p + k] * s;
+          bs[2][k] = m[2 * p + k] * s;
+        }
+        __syncthreads();
+        if (k < p) {
+          cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
+          for (int m = 0; m < p; ++m) {
+            const double fm = a.fact[m + k];
+            sA = sA + bs[0][m] * fm;
+            sB = sB + bs[1][m] * fm;
+            sC = sC + bs[2][m] * fm;
+          }
+          const cx g = rk * rho * (((k & 1) ? -1.0 : 1.0) / (h * a.fact[k]));
+          sA = sA * g;
+          oA = oA + sA;
+          oB = oB + sB * g;
+          oC = oC + sC * g + conj(cs - c) * sA;
+        }
+      }
+    }
+  }
+  if (k < p) {
+    cx* out = a.Lx + gid * 3 * p;
+    out[k] = oA;
+    out[p + k] = oB;
+    out[2 * p + k] = oC;
+  }
+}
+
+// adds the parent's local expansion (level l - 1) to the boxes of level l
+__global__ __launch_bounds__(64) void k_fmm_l2l(FmmArgs a, int l, const int32_t* __restrict__ list) {
+  __shared__ cx al[3][64];
+  __shared__ cx tp[64];
+  const int64_t gid = list[blockIdx.x];
+  const int64_t loc = gid - box_off(l);
+  const int n = 1 << l;
+  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const cx c = box_center(a, l, loc);
+  const int64_t ploc = (int64_t)(iy >> 1) * (n >> 1) + (ix >> 1);
+  const int64_t pgid = box_off(l - 1) + ploc;
+  const cx cp = box_center(a, l - 1, ploc);
+  const double ihP = (double)(n >> 1) / a.D0;
+  const int k = threadIdx.x, p = a.p;
+  const cx d = c - cp;
+  if (k < p) {
+    const cx* m = a.Lx + pgid * 3 * p;
+    const double f = a.fact[k];
+    al[0][k] = m[k] * f;
+    al[1][k] = m[p + k] * f;
+    al[2][k] = m[2 * p + k] * f;
+    tp[k] = cpow(d * ihP, k) * (1.0 / f);
+  }
+  __syncthreads();
+  if (k < p) {
+    cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
+    for (int j = k; j < p; ++j) {
+      const cx t = tp[j - k];
+      sA = sA + al[0][j] * t;
+      sB = sB + al[1][j] * t;
+      sC = sC + al[2][j] * t;
+    }
+    const double s = ldexp(1.0, -k) / a.fact[k];
+    sA = sA * s;
+    cx* out = a.Lx + gid * 3 * p;
+    out[k] = out[k] + sA;
+    out[p + k] = out[p + k] + sB * s;
+    out[2 * p + k] = out[2 * p + k] + sC * s + conj(cp - c) * sA;
+  }
+}
+
+// one thread per target (sorted by leaf): local expansion plus the direct sum over the 3x3
+// neighbour leaves
+__global__ __launch_bounds__(256) void k_fmm_eval(FmmArgs a, int64_t N, const int32_t* __restrict__ tperm,
+                                                  const int32_t* __restrict__ tleaf, Geo g,
+                                                  double* __restrict__ out) {
+  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= N) return;
+  const int64_t i = tperm[t];
+  const int64_t loc = tleaf[t];
+  const int n = 1 << a.L;
+  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const cx c = box_center(a, a.L, loc);
+  const double h = a.D0 / n;
+  const double x = g.x[i], y = g.y[i], nx = g.nx[i], ny = g.ny[i];
+  const cx dz = {x - c.r, y - c.i};
+  const cx u = dz * (1.0 / h);
+  const cx* Le = a.Lx + (box_off(a.L) + loc) * 3 * a.p;
+  const int p = a.p;
+  cx A = {0, 0}, B = {0, 0}, Ad = {0, 0}, Cd = {0, 0};
+  for (int k = p - 1; k >= 1; --k) {
+    A = A * u + Le[k];
+    B = B * u + Le[p + k];
+    Ad = Ad * u + Le[k] * (double)k;
+    Cd = Cd * u + Le[2 * p + k] * (double)k;
+  }
+  A = A * u + Le[0];
+  B = B * u + Le[p];
+  const cx E = (Cd - conj(dz) * Ad) * (1.0 / h);
+  const cx BE = B + E;
+  const double k4 = -1.0 / (4.0 * kPi);
+  double t1 = k4 * (2.0 * nx * A.r + (nx * BE.r - ny * BE.i));
+  double t2 = k4 * (2.0 * ny * A.r - (nx * BE.i + ny * BE.r));
+  double d1 = 0.0, d2 = 0.0;
+  for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
+    for (int jx = max(ix - 1, 0); jx <= min(ix + 1, n - 1); ++jx) {
+      const int64_t nl = (int64_t)jy * n + jx;
+      const int32_t s1 = a.leaf_s[nl + 1];
+      for (int32_t j = a.leaf_s[nl]; j < s1; ++j) {
+        const double rx = x - a.sx[j], ry = y - a.sy[j];
+        const double r2 = rx * rx + ry * ry;
+        if (r2 == 0.0) continue;           // the target's own node
+        const double cf = (rx * nx + ry * ny) * (rx * a.fs1[j] + ry * a.fs2[j]) / (r2 * r2);
+        d1 += cf * rx;
+        d2 += cf * ry;
+      }
+    }
+  }
+  out[i] = t1 - d1 / kPi;
+  out[N + i] = t2 - d2 / kPi;
+}
+
+FmmArgs args(spm_handle* h) {
+  const FmmPlan& F = h->fmm;
+  FmmArgs a;
+  a.p = F.p;
+  a.L = F.L;
+  a.D0 = F.D0;
+  a.c0x = F.c0x;
+  a.c0y = F.c0y;
+  a.sx = F.sx;
+  a.sy = F.sy;
+  a.fs1 = F.fs1;
+  a.fs2 = F.fs2;
+  a.leaf_s = F.leaf_s;
+  a.bsrc = F.bsrc;
+  a.fact = F.fact;
+  a.Mx = reinterpret_cast<cx*>(F.Mx);
+  a.Lx = reinterpret_cast<cx*>(F.Lx);
+  return a;
+}
+
+}  // namespace
+
+void launch_fmm(spm_handle* h, double* out) {
+  const FmmPlan& F = h->fmm;
+  const FmmArgs a = args(h);
+  const int L = F.L;
+  auto n_of = [&](int s) { return (unsigned)(F.seg[s + 1] - F.seg[s]); };
+  auto list = [&](int s) { return F.lists + F.seg[s]; };
+  k_fmm_gather<<<(unsigned)((F.nsrc + 255) / 256), 256, 0, h->stream>>>(F.nsrc, F.sj, h->wk.f1, h->wk.f2, F.fs1,
+                                                                         F.fs2);
+  SPM_HIP_CHECK(hipGetLastError());
+  int s = 0;
+  if (n_of(s)) k_fmm_p2m<<<n_of(s), 64, 0, h->stream>>>(a, list(s));
+  SPM_HIP_CHECK(hipGetLastError());
+  ++s;
+  for (int l = L - 1; l >= 2; --l, ++s) {
+    if (n_of(s)) k_fmm_m2m<<<n_of(s), 64, 0, h->stream>>>(a, l, list(s));
+    SPM_HIP_CHECK(hipGetLastError());
+  }
+  if (n_of(s)) k_fmm_m2l<<<n_of(s), 64, 0, h->stream>>>(a, list(s));
+  SPM_HIP_CHECK(hipGetLastError());
+  ++s;
+  for (int l = 3; l <= L; ++l, ++s) {
+    if (n_of(s)) k_fmm_l2l<<<n_of(s), 64, 0, h->stream>>>(a, l, list(s));
+    SPM_HIP_CHECK(hipGetLastError());
+  }
+  const int64_t N = h->geo.N;
+  k_fmm_eval<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(a, N, F.tperm, F.tleaf, h->geo, out);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace spm

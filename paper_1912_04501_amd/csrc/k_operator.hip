@@ -10,6 +10,17 @@
 //           omega_q = (vort_near(c_q) + vort_corr(c_q))/2 - gamma/2   (Sec. 3 eq. RigidBodyMotion).
 //           mu_eff = mu - sum_q stresslet_q / (2 gamma |U|)           (Sec. 3 eq. mueff via the
 //           cell force balance: the traction on a particle is -sigma).
+// contour:  mu_eff by contour deformation (Sec. 7, efficient evaluation of the effective
+//           viscosity) for the 3x3 near set: the force through a curve C joining D's end points
+//           around the particles is, by translation invariance of G^t and Gauss' law on the
+//           strips between shifted copies of three cells of C,
+//             sum_q [2 J_q(-1) + J_q(2) - W_q(p0 + 2e1 - e2) + W_q(p0 - e1 - e2)
+//                                       + W_q(p0 + 2e1 + e2) - W_q(p0 - e1 + e2)] + int_D T_corr,
+//           J_q(a): the single-layer traction of the unshifted curve q on the straight line from
+//           p0 - e1 + a e2 to p0 + 2e1 + a e2 (normal (0, 1)); W_q(P): on the segment from P to
+//           P + e2 (normal e2 turned clockwise); p0 = c_U - e1/2 - e2/2. Every such target is
+//           about half a cell or more from its sources, so m Gauss-Legendre nodes per cell edge
+//           and the trapezoid rule on the curves are accurate wherever the particles sit.
 #include "spm_internal.h"
 
 namespace spm {
@@ -186,6 +197,90 @@ __global__ void k_mu_eff(const int32_t* __restrict__ cpoff, const double* __rest
 
 void launch_mu_eff(spm_handle* h, double* mu_eff) {
   k_mu_eff<<<h->geo.C, 256, 0, h->stream>>>(h->geo.cpoff, h->wk.pF, h->cfg.mu, h->cfg.gamma, mu_eff);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+// One block per quadrature point (blockIdx.x < 11 m) of cell blockIdx.y: segments 0-2 carry
+// J(-1) (weight 2), 3-5 J(2), 6-9 the four sides, 10 the correction on D. Writes the weighted
+// shear component of the traction at the point.
+__global__ __launch_bounds__(256) void k_contour_points(Geo g, const double* __restrict__ f1,
+                                                        const double* __restrict__ f2, int M,
+                                                        const double* __restrict__ px,
+                                                        const double* __restrict__ py,
+                                                        const double* __restrict__ xi_all, double cUx, double cUy,
+                                                        int m, const double* __restrict__ gl,
+                                                        double* __restrict__ part) {
+  __shared__ double sc[16];
+  const int cell = blockIdx.y;
+  const int seg = blockIdx.x / m, k = blockIdx.x % m;
+  const double skew = g.cskew[cell];
+  const double l2 = sqrt(1.0 + skew * skew);
+  const double t = 0.5 * gl[k], w = 0.5 * gl[m + k];
+  const double p0x = cUx - 0.5 - 0.5 * skew, p0y = cUy - 0.5;
+  double xq, yq, nxq, nyq, wq;
+  if (seg < 6) {                               // lines D - e2 (twice) and D + 2 e2, three cells each
+    const double a = seg < 3 ? -1.0 : 2.0;
+    const double s = (double)(seg % 3 - 1) + 0.5 + t;
+    xq = p0x + a * skew + s;
+    yq = p0y + a;
+    nxq = 0.0;
+    nyq = 1.0;
+    wq = (seg < 3 ? 2.0 : 1.0) * w;
+  } else if (seg < 10) {                       // sides from corner P to P + e2
+    const double cm[4] = {2.0, -1.0, 2.0, -1.0}, cn[4] = {-1.0, -1.0, 1.0, 1.0}, sg[4] = {-1.0, 1.0, 1.0, -1.0};
+    const int i = seg - 6;
+    const double s = 0.5 + t;
+    xq = p0x + cm[i] + (cn[i] + s) * skew;
+    yq = p0y + cn[i] + s;
+    nxq = 1.0 / l2;
+    nyq = -skew / l2;
+    wq = sg[i] * w * l2;
+  } else {                                     // D, correction field
+    xq = p0x + 0.5 + t;
+    yq = p0y;
+    nxq = 0.0;
+    nyq = 1.0;
+    wq = w;
+  }
+  double T1 = 0.0;
+  if (seg < 10) {
+    for (int64_t j = g.cnoff[cell] + threadIdx.x; j < g.cnoff[cell + 1]; j += blockDim.x) {
+      const double rx = xq - g.x[j], ry = yq - g.y[j];
+      const double r2 = rx * rx + ry * ry;
+      const double rn = rx * nxq + ry * nyq, rf = rx * f1[j] + ry * f2[j];
+      T1 += rx * rn * rf / (r2 * r2);
+    }
+  } else {
+    const double* xi = xi_all + (int64_t)cell * 2 * M;
+    for (int p = threadIdx.x; p < M; p += blockDim.x) {
+      const double rx = xq - px[p], ry = yq - py[p];
+      const double r2 = rx * rx + ry * ry;
+      const double rn = rx * nxq + ry * nyq, rf = rx * xi[p] + ry * xi[M + p];
+      T1 += rx * rn * rf / (r2 * r2);
+    }
+  }
+  T1 = block_sum(T1, sc);
+  if (threadIdx.x == 0) part[(int64_t)cell * 11 * m + blockIdx.x] = -wq * T1 / kPi;
+}
+
+// mu_eff = mu + (force through C) . e1 / (gamma |e1|), |e1| = 1; fixed summation order.
+__global__ void k_contour_sum(int m, const double* __restrict__ part, double mu, double gamma,
+                              double* __restrict__ out) {
+  __shared__ double sc[16];
+  const int cell = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < 11 * m; i += blockDim.x) s += part[(int64_t)cell * 11 * m + i];
+  s = block_sum(s, sc);
+  if (threadIdx.x == 0) out[cell] = mu + s / gamma;
+}
+
+void launch_mu_eff_contour(spm_handle* h, int m, double* mu_eff) {
+  const Geo& g = h->geo;
+  k_contour_points<<<dim3(11 * m, g.C), 256, 0, h->stream>>>(g, h->wk.f1, h->wk.f2, h->per.M, h->per.px,
+                                                             h->per.py, h->wk.xi, h->cU[0], h->cU[1], m,
+                                                             h->wk.contour_gl, h->wk.contour);
+  SPM_HIP_CHECK(hipGetLastError());
+  k_contour_sum<<<g.C, 256, 0, h->stream>>>(m, h->wk.contour, h->cfg.mu, h->cfg.gamma, mu_eff);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

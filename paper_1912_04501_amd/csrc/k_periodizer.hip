@@ -465,7 +465,8 @@ void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int
   const int64_t N = h->geo.N;
   const NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
   const int64_t threads = N * kCombineLanes;
-  k_combine<<<(unsigned)((threads + 255) / 256), 256, 0, h->stream>>>(N, P.nsplit, h->wk.Tpart, h->geo, sigma,
+  const int32_t* nsplit = h->fmm.on ? h->fmm.nsplit1 : P.nsplit;   // the FMM writes one partial
+  k_combine<<<(unsigned)((threads + 255) / 256), 256, 0, h->stream>>>(N, nsplit, h->wk.Tpart, h->geo, sigma,
                                                                      h->per.M, h->per.px, h->per.py, h->wk.xi,
                                                                      with_self_corr ? 1 : 0, h->wk.T);
   SPM_HIP_CHECK(hipGetLastError());

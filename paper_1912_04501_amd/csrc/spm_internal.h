@@ -319,6 +319,30 @@ struct Work {
   double* xi = nullptr;       // [C x 2M]
   double* scal = nullptr;     // [16] device scalars
   double* gauge = nullptr;    // [C x 2] velocity constant removed by the readout gauge
+  double* contour = nullptr;  // [C x 11 m] point terms of the contour-deformation mu_eff
+  double* contour_gl = nullptr;  // [2 m] Gauss-Legendre nodes and weights on [-1, 1]
+};
+
+// Fast multipole evaluation of the near-image sum (one cell, FP64): a uniform quadtree over
+// the 9 N image sources, complex multipole and local expansions of p terms (k_fmm.hip).
+struct FmmPlan {
+  bool on = false;
+  int32_t p = 0, L = 0;                   // expansion terms; leaf level (root box = level 0)
+  double D0 = 0, c0x = 0, c0y = 0;        // root box side and centre
+  int64_t nsrc = 0;                       // 9 N
+  double *sx = nullptr, *sy = nullptr;    // [9N] image sources sorted by leaf
+  int32_t* sj = nullptr;                  // [9N] node of each sorted source
+  double *fs1 = nullptr, *fs2 = nullptr;  // [9N] w sigma in sorted order
+  int32_t* leaf_s = nullptr;              // [4^L + 1] source offsets of the leaves
+  int32_t* tperm = nullptr;               // [N] nodes sorted by leaf
+  int32_t* tleaf = nullptr;               // [N] leaf of each sorted target
+  int32_t* bsrc = nullptr;                // [boxes of all levels] sources in each box
+  int32_t* lists = nullptr;               // box lists of the passes (global box ids)
+  std::vector<int64_t> seg;               // list segments: P2M, M2M levels L-1..2, M2L, L2L levels 3..L
+  double* fact = nullptr;                 // [2p] factorials
+  double *Mx = nullptr, *Lx = nullptr;    // [boxes x 3 x p] complex multipole / local expansions
+  int32_t* nsplit1 = nullptr;             // [1] = 1: the combine step reads one partial
+  double p2p_pairs = 0, m2l = 0;          // work of one evaluation
 };
 
 // Flow-field evaluation at points of the fluid.
@@ -446,6 +470,7 @@ struct spm_handle {
   spm::CloseList cl;
   spm::Work wk;
   spm::Field fd;
+  spm::FmmPlan fmm;
   spm::Krylov kr;
   spm::Learned ln;
   spm::Precond pc;
@@ -513,6 +538,10 @@ void launch_self_fix(spm_handle* h, double* T, bool with_active);
 void launch_assemble(spm_handle* h, const double* sigma, double* out);
 void launch_velocities(spm_handle* h, double* vel, double* omega);
 void launch_mu_eff(spm_handle* h, double* mu_eff);
+void launch_mu_eff_contour(spm_handle* h, int m, double* mu_eff);
+// FMM near sum (k_fmm.hip): plan from the device node positions; evaluation into out [2N]
+void build_fmm_plan(spm_handle* h);
+void launch_fmm(spm_handle* h, double* out);
 void launch_gap(spm_handle* h, double* gap_host, int32_t* overlap_host);
 
 // GMRES building blocks (k_gmres.hip); per cell, cells in lockstep

@@ -23,6 +23,7 @@ SPM_OK, SPM_EINVAL, SPM_EOVERLAP, SPM_ENOCONV, SPM_EHIP, SPM_ENOMEM, SPM_ESTATE 
 SPM_FP64, SPM_FP32, SPM_FP32_IR, SPM_FP32_RELAXED = 0, 1, 2, 3
 SPM_X0_ZERO, SPM_X0_PREVIOUS, SPM_X0_NETWORK = 0, 1, 2
 SPM_PRECOND_NONE, SPM_PRECOND_BLOCK = 0, 1
+SPM_NEAR_DIRECT, SPM_NEAR_FMM = 0, 1
 SPM_MLP_IN, SPM_MLP_HIDDEN, SPM_MLP_OUT, SPM_MLP_NPARAMS = 33, 256, 128, 173184
 SPM_MLP_BF16, SPM_MLP_FP32 = 0, 1
 _ERRNAMES = {-1: "SPM_EINVAL", -2: "SPM_EOVERLAP", -3: "SPM_ENOCONV", -4: "SPM_EHIP", -5: "SPM_ENOMEM",
@@ -35,7 +36,8 @@ class spm_config(ctypes.Structure):
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("inner_tol", ctypes.c_double), ("min_gap", ctypes.c_double), ("rcond", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("x0", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("learned_max_iter", ctypes.c_int32), ("relax_tol", ctypes.c_double)]
+                ("precond", ctypes.c_int32), ("learned_max_iter", ctypes.c_int32), ("relax_tol", ctypes.c_double),
+                ("near_method", ctypes.c_int32), ("fmm_order", ctypes.c_int32)]
 
 
 class spm_solve_info(ctypes.Structure):
@@ -90,6 +92,8 @@ def lib():
         "spm_solve": (ctypes.c_int, [P, P, P, P, P, P, ctypes.POINTER(spm_solve_info)]),
         "spm_velocities": (ctypes.c_int, [P, P, P, P]),
         "spm_effective_viscosity": (ctypes.c_int, [P, P, P]),
+        "spm_effective_viscosity_contour": (ctypes.c_int, [P, P, ctypes.c_int32, P]),
+        "spm_fmm_stats": (ctypes.c_int, [P, P, P, P, P]),
         "spm_step": (ctypes.c_int, [P, ctypes.c_double, ctypes.c_int32, d, d, d, d,
                                     ctypes.POINTER(spm_solve_info)]),
         "spm_near_traction": (ctypes.c_int, [P, P, P, ctypes.c_int32]),
@@ -268,6 +272,7 @@ class Solver:
         self.h = h
         self.N = 0
         self.No = 0
+        self.C = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -420,8 +425,21 @@ class Solver:
         return torch.stack([u[:n], u[n:]], dim=1), p
 
     def effective_viscosity(self, sigma):
-        mu = self._vec(1)
+        mu = self._vec(self.C)
         self._check(lib().spm_effective_viscosity(self.h, _ptr(sigma), _ptr(mu)))
+        return mu
+
+    def fmm_stats(self):
+        """Quadtree of the FMM near sum: levels, expansion terms, direct pairs, M2L translations."""
+        lv, od = ctypes.c_int32(), ctypes.c_int32()
+        pp, ml = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().spm_fmm_stats(self.h, ctypes.byref(lv), ctypes.byref(od), ctypes.byref(pp), ctypes.byref(ml)))
+        return {"levels": lv.value, "order": od.value, "p2p_pairs": pp.value, "m2l": ml.value}
+
+    def effective_viscosity_contour(self, sigma, m=0):
+        """mu_eff of every cell by contour deformation; m Gauss-Legendre nodes per cell edge (0: 16)."""
+        mu = self._vec(self.C)
+        self._check(lib().spm_effective_viscosity_contour(self.h, _ptr(sigma), int(m), _ptr(mu)))
         return mu
 
     def step(self, dt, n_steps, t, centers, theta, record=False):

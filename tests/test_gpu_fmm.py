@@ -1,0 +1,131 @@
+"""Fast multipole near sum (SPM_NEAR_FMM) against the oracle's direct near-image sum (the
+definition, Sec. 4.2 G_near with 3x3 images per particle), and solves with it against the
+oracle's solve. The FMM is an approximation of that sum: with p expansion terms and
+interaction boxes one box apart the truncation error is bounded by about
+(sqrt(2)/2 / (2 - sqrt(2)/2))^p = 0.547^p of the sum of the far contributions (p = 16:
+6e-5) and is typically far smaller (p = 40: 1e-14 to 2e-13 of the largest traction). The
+bounds are 1e-4 at p = 16 and 1e-12 at p = 40."""
+import numpy as np
+import pytest
+
+from oracle import _clib, geometry, near
+from oracle import operator as op
+from oracle import readout as ro
+from paper_1912_04501_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CASES = {
+    "random_25_phi0.3_seed1": lambda: W.random_ellipses(25, 0.3, seed=1),
+    "single_ellipse_skew0.37": lambda: W.single_ellipse(n_nodes=96, skew=0.37, center=(0.2, 0.44)),
+    "two_stars_s0.25_A0.5_w4": lambda: W.two_stars(omega=4.0),
+    "star_and_ellipse_gap2e-2": lambda: W.star_and_ellipse(),
+}
+
+
+def _n(t):
+    return t.detach().cpu().numpy()
+
+
+def _fmm(wl, order=0, **kw):
+    from paper_1912_04501_amd import spm
+    return spm.Solver("cuda:0", near_method=spm.SPM_NEAR_FMM, fmm_order=order, **kw).set_workload(wl)
+
+
+def _oracle_near(g, sig, rows=None):
+    f = near.forces(g, op.to2(sig))
+    if rows is None:
+        return _clib.near_traction(g.x, g.n, g.x, f, g.shifts(1), np.arange(g.N))
+    return _clib.near_traction(g.x[rows], g.n[rows], g.x, f, g.shifts(1), rows)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("order,bound", [(40, 1e-12), (16, 1e-4)])
+def test_fmm_near_sum_matches_oracle(name, order, bound):
+    wl = CASES[name]()
+    g = geometry.build_geometry(wl)
+    s = _fmm(wl, order)
+    st = s.fmm_stats()
+    print(f"[fmm {name} p={order}] N {g.N} levels {st['levels']} direct pairs {st['p2p_pairs']:.3g} "
+          f"M2L {st['m2l']:.3g}", flush=True)
+    assert st["order"] == order
+    sig = W.random_density(g.N, seed=5)
+    T = _n(s.near_traction(torch.as_tensor(sig, device="cuda:0")))
+    ref = _oracle_near(g, sig)
+    dev = np.stack([T[:g.N], T[g.N:]], axis=1)
+    err = np.abs(dev - ref).max() / np.abs(ref).max()
+    print(f"[fmm {name} p={order}] rel err {err:.2e}", flush=True)
+    assert err < bound
+
+
+def test_fmm_near_sum_200_ellipses_sampled():
+    """The 200-ellipse, 51,200-node cell: 3,000 sampled targets against the oracle."""
+    wl = W.ellipses_200()
+    g = geometry.build_geometry(wl)
+    s = _fmm(wl)
+    st = s.fmm_stats()
+    print(f"[fmm 200 ellipses] levels {st['levels']} direct pairs {st['p2p_pairs']:.3g} M2L {st['m2l']:.3g}",
+          flush=True)
+    sig = W.random_density(g.N, seed=6)
+    T = _n(s.near_traction(torch.as_tensor(sig, device="cuda:0")))
+    rows = np.sort(np.random.default_rng(2).choice(g.N, 3000, replace=False))
+    ref = _oracle_near(g, sig, rows)
+    dev = np.stack([T[rows], T[g.N + rows]], axis=1)
+    err = np.abs(dev - ref).max() / np.abs(ref).max()
+    print(f"[fmm 200 ellipses] rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("name", ["random_25_phi0.3_seed1", "two_stars_s0.25_A0.5_w4"])
+def test_fmm_solve_matches_oracle(name):
+    wl = CASES[name]()
+    prob = op.make_problem(wl)
+    x, _ = op.solve(prob, tol=1e-12)
+    v, om = ro.velocities(prob, x)
+    mu = ro.mu_eff(prob, x)
+    r = _fmm(wl).solve()
+    info = r["info"]
+    assert info["status"] == 0 and info["rel_residual"] <= 1e-10
+    sig = _n(r["sigma"])
+    b = op.rhs(prob)
+    res = np.linalg.norm(b - op.apply(prob, sig)) / np.linalg.norm(b)
+    e_om = np.abs(_n(r["omega"]) - om).max()
+    e_v = np.abs(_n(r["vel"]) - v).max()
+    e_mu = abs(_n(r["mu_eff"])[0] - mu)
+    print(f"[fmm solve {name}] its {info['iterations']} residual via oracle {res:.1e} omega {e_om:.1e} "
+          f"v {e_v:.1e} mu {e_mu:.1e}", flush=True)
+    assert res < 2e-10
+    sc = max(1.0, np.abs(om).max())
+    assert e_om < 1e-8 * sc and e_v < 1e-8 * max(1.0, np.abs(v).max()) and e_mu < 1e-8 * max(1.0, abs(mu))
+
+
+def test_fmm_steps_match_direct():
+    """Forward Euler with the FMM (plan rebuilt every step) against the direct FP64 sum."""
+    from paper_1912_04501_amd import spm
+    wl = W.random_ellipses(6, 0.25, seed=3, nodes=128)
+    out = []
+    for method in (spm.SPM_NEAR_DIRECT, spm.SPM_NEAR_FMM):
+        s = spm.Solver("cuda:0", near_method=method).set_workload(wl)
+        o = s.step(0.01, 5, 0.0, wl["centers"], wl["theta"])
+        out.append(o)
+    c0, c1 = np.asarray(out[0]["centers"]), np.asarray(out[1]["centers"])
+    m0, m1 = np.asarray(out[0]["mu_eff"]), np.asarray(out[1]["mu_eff"])
+    print(f"[fmm steps] centre diff {np.abs(c0 - c1).max():.1e} mu diff {np.abs(m0 - m1).max():.1e}", flush=True)
+    assert np.abs(c0 - c1).max() < 1e-9 and np.abs(m0 - m1).max() < 1e-9
+
+
+def test_fmm_arguments():
+    from paper_1912_04501_amd import spm
+    wl = W.single_ellipse(n_nodes=64)
+    with pytest.raises(spm.SpmError):
+        spm.Solver("cuda:0", near_method=spm.SPM_NEAR_FMM, precision=spm.SPM_FP32_IR)
+    with pytest.raises(spm.SpmError):
+        spm.Solver("cuda:0", near_method=spm.SPM_NEAR_FMM, fmm_order=7)
+    with pytest.raises(spm.SpmError) as err:
+        spm.Solver("cuda:0", near_method=spm.SPM_NEAR_FMM).set_cells([wl, wl])
+    assert err.value.code == spm.SPM_EINVAL
+    with pytest.raises(spm.SpmError) as err:
+        spm.Solver("cuda:0").set_workload(wl).fmm_stats()
+    assert err.value.code == spm.SPM_ESTATE
