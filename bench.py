@@ -124,11 +124,15 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy three times (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["ellipses200", "ensemble64", "learned", "jamming"],
+    ap.add_argument("--workload", choices=["ellipses200", "ensemble64", "learned", "jamming", "islands"],
                     default="ellipses200",
                     help="ellipses200: the 200-ellipse cell (default); ensemble64: 64 independent cells in one "
                          "launch; learned: time stepping with the trained warm-start network; jamming: two "
-                         "star-shaped particles sheared into contact (Sec. 8 Examples 4 and 5)")
+                         "star-shaped particles sheared into contact (Sec. 8 Examples 4 and 5); islands: K random "
+                         "star-shaped islands of 350 nodes (Sec. 8 Example 2 scale) with the FMM near sum")
+    ap.add_argument("--islands", default="100,250,500,1000", help="islands: the island counts K")
+    ap.add_argument("--direct-max", type=int, default=250,
+                    help="islands: largest K also solved with the direct FP32 near sum")
     ap.add_argument("--example", type=int, choices=[4, 5], default=4, help="jamming: which of the two runs")
     ap.add_argument("--nodes", type=int, default=2500, help="jamming: nodes per star")
     ap.add_argument("--omega", type=int, default=4, help="jamming: arms of each star, r = s (1 + cos(omega t)/2)")
@@ -173,6 +177,8 @@ def main():
         return bench_learned(args)
     if args.workload == "jamming":
         return bench_jamming(args)
+    if args.workload == "islands":
+        return bench_islands(args)
     t0 = time.perf_counter()
     wl = W.ellipses_200()
     log(f"[bench] workload {wl['name']} generated in {time.perf_counter() - t0:.1f}s")
@@ -226,10 +232,12 @@ def main():
 
     extra = {}
     if not args.no_compare:
-        for name, p, pc in (("fp64", spm.SPM_FP64, 0), ("fp32_ir", spm.SPM_FP32_IR, 0),
-                            ("fp32_relaxed", spm.SPM_FP32_RELAXED, 0), ("fp64_precond", spm.SPM_FP64, 1),
-                            ("fp32_ir_precond", spm.SPM_FP32_IR, 1), ("fp32_relaxed_precond", spm.SPM_FP32_RELAXED, 1)):
-            c = spm.Solver("cuda:0", precision=p, precond=pc)
+        for name, p, pc, nm in (("fp64", spm.SPM_FP64, 0, 0), ("fp32_ir", spm.SPM_FP32_IR, 0, 0),
+                                ("fp32_relaxed", spm.SPM_FP32_RELAXED, 0, 0), ("fp64_precond", spm.SPM_FP64, 1, 0),
+                                ("fp32_ir_precond", spm.SPM_FP32_IR, 1, 0),
+                                ("fp32_relaxed_precond", spm.SPM_FP32_RELAXED, 1, 0),
+                                ("fmm_fp64_precond", spm.SPM_FP64, 1, spm.SPM_NEAR_FMM)):
+            c = spm.Solver("cuda:0", precision=p, precond=pc, near_method=nm)
             c.set_workload(wl)
             for pr, key in ((spm.SPM_FP64, "fp64"), (spm.SPM_FP32, "fp32")):
                 c.set_launch(pr, **tune[key])
@@ -347,6 +355,114 @@ def bench_ensemble(args):
                         "avg_launch_ms": avg_ms, "launches": prof["launches"], "pairs_per_launch": pairs_per_launch,
                         "launch_shape": tune["fp32"]},
            "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def bench_islands(args):
+    """Random star-shaped islands at the scale of Sec. 8 Example 2 (K islands of 350 nodes,
+    N = 350 K, area fraction 0.2, seed 1): complete FP64 mobility solves to 1e-10 with the FMM
+    near sum (40 terms) and the block preconditioner. One step = one solve of the largest K;
+    value = solves per second. Every K also reports the FMM near-sum kernels (HIP events) and
+    one launch of the direct FP32 and FP64 near sums; K <= --direct-max also the best direct
+    solve (FP32 + iterative refinement with the block preconditioner)."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04501_amd import spm
+    from paper_1912_04501_amd import workloads as W
+    Ks = [int(k) for k in args.islands.split(",")]
+    series = []
+    last = None
+    for K in Ks:
+        t0 = time.perf_counter()
+        wl = W.random_stars(K, 0.2, 1)
+        N = int(np.sum(wl["n_nodes"]))
+        s = spm.Solver("cuda:0", precision=spm.SPM_FP64, precond=spm.SPM_PRECOND_BLOCK, near_method=spm.SPM_NEAR_FMM)
+        s.set_workload(wl)
+        st = s.fmm_stats()
+        log(f"[islands] K {K} N {N}: setup {time.perf_counter() - t0:.1f}s, FMM {st}")
+        for _ in range(args.warmup):
+            r = s.solve()
+        torch.cuda.synchronize()
+        s.profile(True)
+        t1 = time.perf_counter()
+        infos = []
+        for _ in range(args.steps):
+            r = s.solve()
+            infos.append(r["info"])
+        torch.cuda.synchronize()
+        solve_s = (time.perf_counter() - t1) / args.steps
+        ev = {k: s.profile_read(k) for k in (2, 3)}
+        s.profile(False)
+        assert max(i["rel_residual"] for i in infos) <= 1e-10, infos
+        # one FMM near sum in isolation (all of its kernels, CUDA events on torch's stream)
+        x = torch.randn(2 * N, dtype=torch.float64, device="cuda:0")
+        s.near_traction(x)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            s.near_traction(x)
+        e1.record()
+        torch.cuda.synchronize()
+        fmm_ms = e0.elapsed_time(e1) / 5
+        mu_c = float(s.effective_viscosity_contour(r["sigma"])[0])
+        entry = {"K": K, "N": N, "fmm_levels": st["levels"], "fmm_order": st["order"],
+                 "fmm_direct_pairs": st["p2p_pairs"], "fmm_m2l": st["m2l"], "solve_s": solve_s,
+                 "iterations": infos[-1]["iterations"], "rel_residual": infos[-1]["rel_residual"],
+                 "mu_eff": float(r["mu_eff"][0]), "mu_eff_contour": mu_c,
+                 "fmm_near_sum_ms": fmm_ms,
+                 "fmm_eval_kernel_ms": ev[2]["ms"] / max(ev[2]["launches"], 1),
+                 "fmm_m2l_kernel_ms": ev[3]["ms"] / max(ev[3]["launches"], 1)}
+        s.close()
+        d = spm.Solver("cuda:0", precision=spm.SPM_FP32_IR, precond=spm.SPM_PRECOND_BLOCK)
+        d.set_workload(wl)
+        d.profile(True)
+        for pr in (spm.SPM_FP32, spm.SPM_FP64):
+            d.near_traction(x, precision=pr)
+        torch.cuda.synchronize()
+        entry["direct_fp32_near_sum_ms"] = d.profile_read(1)["ms"]
+        entry["direct_fp64_near_sum_ms"] = d.profile_read(0)["ms"]
+        d.profile(False)
+        if K <= args.direct_max:
+            d.solve()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rd = d.solve()
+            torch.cuda.synchronize()
+            entry["direct_fp32_ir_precond_solve_s"] = time.perf_counter() - t1
+            entry["direct_iterations"] = rd["info"]["iterations"]
+            entry["direct_mu_eff"] = float(rd["mu_eff"][0])
+        d.close()
+        log(f"[islands] {entry}")
+        series.append(entry)
+        last = (wl, entry, ev, st, infos)
+    wl, entry, ev, st, infos = last
+    # dominant FMM kernel over the timed solves
+    flops = {2: FLOP_PER_PAIR * st["p2p_pairs"] + 32.0 * st["order"] * entry["N"],
+             3: 12.0 * st["order"] ** 2 * st["m2l"]}
+    kern = 2 if ev[2]["ms"] >= ev[3]["ms"] else 3
+    avg_ms = ev[kern]["ms"] / max(ev[kern]["launches"], 1)
+    achieved = flops[kern] / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": achieved / PEAK["fp64"], "traffic": None,
+                "kernel": "k_fmm_eval (local expansions + direct pairs of neighbouring leaves, fp64)" if kern == 2
+                else "k_fmm_m2l (multipole-to-local translations, fp64)",
+                "avg_launch_ms": avg_ms, "launches": ev[kern]["launches"],
+                "flop_per_launch": flops[kern]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline([wl])
+        mv = infos[-1]["fp64_matvecs"] + infos[-1]["fp32_matvecs"]
+        cpu["solves_per_s_near_only"] = cpu["value"] / (9.0 * entry["N"] ** 2 * mv)
+    out = {"metric": f"mobility solves/s, {entry['K']} star-shaped islands, N = {entry['N']} (FMM near sum, FP64, "
+                     "residual 1e-10)",
+           "value": 1.0 / entry["solve_s"], "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * entry["solve_s"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": wl["name"], "K": entry["K"], "N": entry["N"], "nodes_per_island": 350,
+                      "area_fraction": 0.2, "near_sum": "fmm", "fmm_order": st["order"], "precond": "block",
+                      "tol": 1e-10},
+           "roofline": roofline, "cpu_baseline": cpu, "series": series}
     print(json.dumps(out), flush=True)
 
 

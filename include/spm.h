@@ -320,13 +320,15 @@ int spm_set_launch(spm_handle* h, int32_t precision, const int32_t* cfg_host);
 
 /* ---- measurement ---- */
 
-/* Enable (1) or disable (0) timing of the near-sum kernel with HIP events recorded
+/* Enable (1) or disable (0) timing of the near-sum kernels with HIP events recorded
  * on the handle's stream around every launch; resets the counters. */
 int spm_profile(spm_handle* h, int32_t enable);
 
-/* Totals since spm_profile(h, 1): kernel 0 = FP64 near sum, 1 = FP32 near sum.
- * total_ms: summed launch durations; launches: number of launches; pairs: node-image
- * pair evaluations (9 N^2 per launch). Any output may be NULL. Synchronises. */
+/* Totals since spm_profile(h, 1): kernel 0 = FP64 near sum, 1 = FP32 near sum (pairs: node-image
+ * pair evaluations, 9 N^2 per launch); with SPM_NEAR_FMM, 2 = the FMM's target evaluation kernel
+ * (local expansions and the direct pairs of neighbouring leaves; pairs: those direct pairs) and
+ * 3 = its multipole-to-local kernel (pairs: translations). total_ms: summed launch durations;
+ * launches: number of launches. Any output may be NULL. Synchronises. */
 int spm_profile_read(spm_handle* h, int32_t kernel, double* total_ms, int64_t* launches, double* pairs);
 
 /* ---- block preconditioner ---- */

@@ -1666,7 +1666,7 @@ int spm_profile(spm_handle* h, int32_t enable) {
   return guarded(h, [&]() {
     prof_flush(h);
     h->prof = enable != 0;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 4; ++k) {
       h->prof_ms[k] = 0;
       h->prof_launches[k] = 0;
       h->prof_pairs[k] = 0;
@@ -1677,7 +1677,7 @@ int spm_profile(spm_handle* h, int32_t enable) {
 
 int spm_profile_read(spm_handle* h, int32_t kernel, double* total_ms, int64_t* launches, double* pairs) {
   return guarded(h, [&]() {
-    if (kernel < 0 || kernel > 1) throw ApiError(SPM_EINVAL, "kernel id must be 0 (FP64 near sum) or 1 (FP32)");
+    if (kernel < 0 || kernel > 3) throw ApiError(SPM_EINVAL, "kernel id must be in [0, 3]");
     prof_flush(h);
     if (total_ms) *total_ms = h->prof_ms[kernel];
     if (launches) *launches = h->prof_launches[kernel];

@@ -328,6 +328,29 @@ FmmArgs args(spm_handle* h) {
   return a;
 }
 
+// HIP events around one kernel (kind 2: evaluation, 3: M2L) when timing is on
+void prof_mark(spm_handle* h, int kind, bool start, double work) {
+  if (!h->prof) return;
+  if (start) {
+    if (h->ev_used * 2 + 2 > h->ev_pool.size()) {
+      if (h->ev_pool.size() >= 512) prof_flush(h);
+      while (h->ev_used * 2 + 2 > h->ev_pool.size()) {
+        hipEvent_t e;
+        SPM_HIP_CHECK(hipEventCreate(&e));
+        h->ev_pool.push_back(e);
+      }
+    }
+    if (h->ev_kind.size() < h->ev_pool.size() / 2) h->ev_kind.resize(h->ev_pool.size() / 2);
+    h->ev_kind[h->ev_used] = kind;
+    SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used], h->stream));
+  } else {
+    SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used + 1], h->stream));
+    ++h->ev_used;
+    h->prof_launches[kind] += 1;
+    h->prof_pairs[kind] += work;
+  }
+}
+
 }  // namespace
 
 void launch_fmm(spm_handle* h, double* out) {
@@ -347,16 +370,20 @@ void launch_fmm(spm_handle* h, double* out) {
     if (n_of(s)) k_fmm_m2m<<<n_of(s), 64, 0, h->stream>>>(a, l, list(s));
     SPM_HIP_CHECK(hipGetLastError());
   }
+  prof_mark(h, 3, true, 0);
   if (n_of(s)) k_fmm_m2l<<<n_of(s), 64, 0, h->stream>>>(a, list(s));
   SPM_HIP_CHECK(hipGetLastError());
+  prof_mark(h, 3, false, F.m2l);
   ++s;
   for (int l = 3; l <= L; ++l, ++s) {
     if (n_of(s)) k_fmm_l2l<<<n_of(s), 64, 0, h->stream>>>(a, l, list(s));
     SPM_HIP_CHECK(hipGetLastError());
   }
   const int64_t N = h->geo.N;
+  prof_mark(h, 2, true, 0);
   k_fmm_eval<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(a, N, F.tperm, F.tleaf, h->geo, out);
   SPM_HIP_CHECK(hipGetLastError());
+  prof_mark(h, 2, false, F.p2p_pairs);
 }
 
 }  // namespace spm

@@ -478,14 +478,14 @@ struct spm_handle {
   double min_gap_est = 0.0;
   double wallclock_hz = 1e8;
 
-  // opt-in kernel timing: HIP events around near-sum launches (kernel 0 = FP64, 1 = FP32)
+  // opt-in kernel timing: HIP events around near-sum launches (kernel 0 = FP64, 1 = FP32; FMM: 2 = evaluation, 3 = M2L)
   bool prof = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_kind;      // kernel id of each recorded start/stop pair
   size_t ev_used = 0;            // pairs recorded since the last flush
-  double prof_ms[2] = {0, 0};
-  int64_t prof_launches[2] = {0, 0};
-  double prof_pairs[2] = {0, 0};
+  double prof_ms[4] = {0, 0, 0, 0};
+  int64_t prof_launches[4] = {0, 0, 0, 0};
+  double prof_pairs[4] = {0, 0, 0, 0};
 };
 
 // The warm-start network (k_mlp.hip): FP32 master parameters, Adam moments and the

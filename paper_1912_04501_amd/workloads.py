@@ -295,6 +295,37 @@ def star_and_ellipse(gap=2e-2, s=0.15, A=0.3, omega=3.0, n_star=192, n_ellipse=1
             "n_nodes": np.array([n_star, n_ellipse], dtype=np.int32), "mu": 1.0, "gamma": 1.0}
 
 
+def random_stars(n, phi, seed, n_nodes=350, A=0.3, omega=5, min_gap=None, skew=0.0, name=None):
+    """n star-shaped "islands" r(t) = s (1 + A cos(omega t + phase)) of one size at area
+    fraction phi (area pi s^2 (1 + A^2/2) each), random centres, turns and phases, n_nodes
+    nodes each (Sec. 8 Example 2 uses 350). Centres are placed by random sequential addition
+    with bounding circles of radius s (1 + A) kept min_gap apart (default s/5) over the 3x3
+    periodic images."""
+    rng = np.random.default_rng(seed)
+    s_ = math.sqrt(phi / (n * math.pi * (1.0 + 0.5 * A * A)))
+    R = s_ * (1.0 + A)
+    gap = 0.2 * s_ if min_gap is None else min_gap
+    e1, e2 = np.array([1.0, 0.0]), np.array([skew, 1.0])
+    shifts = np.array([m * e1 + k * e2 for m in (-1, 0, 1) for k in (-1, 0, 1)])
+    cs = np.zeros((0, 2))
+    for _ in range(n):
+        for _try in range(200000):
+            al, be = rng.uniform(-0.5, 0.5, size=2)
+            c = al * e1 + be * e2
+            if len(cs):
+                d = np.linalg.norm((cs[:, None, :] + shifts[None]) - c, axis=2).min()
+                if d < 2 * R + gap:
+                    continue
+            if np.linalg.norm(shifts[[0, 1, 2, 3, 5, 6, 7, 8]], axis=1).min() < 2 * R + gap:
+                raise ValueError("islands larger than the cell")
+            cs = np.vstack([cs, c])
+            break
+        else:
+            raise ValueError("could not place the islands")
+    return stars(cs, s_, A, omega, phase=rng.uniform(0, 2 * math.pi, n), theta=rng.uniform(0, 2 * math.pi, n),
+                 n_nodes=n_nodes, skew=skew, name=name or f"islands_{n}_phi{phi}_N{n * n_nodes}")
+
+
 def random_density(n_total, seed=7):
     """sigma ~ N(0, 1), SoA [sigma_1(0..N-1), sigma_2(0..N-1)]."""
     return np.random.default_rng(seed).standard_normal(2 * int(n_total))
