@@ -1069,7 +1069,7 @@ void build_fmm_plan(spm_handle* h) {
     leaf_t[b + 1] = leaf_t[b] + (int32_t)ct[b];
   }
   std::vector<double> ssx(ns), ssy(ns);
-  std::vector<int32_t> ssj(ns), tperm(N), tleaf(N);
+  std::vector<int32_t> ssj(ns), tperm(N);
   {
     std::vector<int32_t> fill(leaf_s.begin(), leaf_s.end() - 1);
     for (int64_t k = 0; k < ns; ++k) {
@@ -1082,7 +1082,6 @@ void build_fmm_plan(spm_handle* h) {
     for (int64_t j = 0; j < N; ++j) {
       const int32_t d = tf[lf[ctr + j]]++;
       tperm[d] = (int32_t)j;
-      tleaf[d] = (int32_t)lf[ctr + j];
     }
   }
   const std::vector<int64_t> bs = fmm_levels(cs, L), bt = fmm_levels(ct, L);
@@ -1090,7 +1089,7 @@ void build_fmm_plan(spm_handle* h) {
   std::vector<int32_t> bsrc(nbox);
   for (int64_t b = 0; b < nbox; ++b) bsrc[b] = (int32_t)std::min<int64_t>(bs[b], INT32_MAX);
   // box lists: P2M (leaves with sources), M2M levels L-1..2, M2L (target boxes of levels 2..L),
-  // L2L levels 3..L
+  // L2L levels 3..L, evaluation (leaves with targets)
   std::vector<int32_t> lists;
   F.seg.assign(1, 0);
   auto push_level = [&](int l, const std::vector<int64_t>& cnt) {
@@ -1109,6 +1108,8 @@ void build_fmm_plan(spm_handle* h) {
     push_level(l, bt);
     F.seg.push_back((int64_t)lists.size());
   }
+  push_level(L, bt);
+  F.seg.push_back((int64_t)lists.size());
   std::vector<double> fact(2 * p);
   fact[0] = 1.0;
   for (int k = 1; k < 2 * p; ++k) fact[k] = fact[k - 1] * k;
@@ -1119,7 +1120,7 @@ void build_fmm_plan(spm_handle* h) {
   ensure(h, F.fs2, ns);
   ensure(h, F.leaf_s, nl + 1);
   ensure(h, F.tperm, N);
-  ensure(h, F.tleaf, N);
+  ensure(h, F.leaf_t, nl + 1);
   ensure(h, F.bsrc, nbox);
   ensure(h, F.lists, lists.size());
   ensure(h, F.fact, 2 * p);
@@ -1131,7 +1132,7 @@ void build_fmm_plan(spm_handle* h) {
   upload(h, F.sj, ssj.data(), ns * sizeof(int32_t));
   upload(h, F.leaf_s, leaf_s.data(), (nl + 1) * sizeof(int32_t));
   upload(h, F.tperm, tperm.data(), N * sizeof(int32_t));
-  upload(h, F.tleaf, tleaf.data(), N * sizeof(int32_t));
+  upload(h, F.leaf_t, leaf_t.data(), (nl + 1) * sizeof(int32_t));
   upload(h, F.bsrc, bsrc.data(), nbox * sizeof(int32_t));
   upload(h, F.lists, lists.data(), lists.size() * sizeof(int32_t));
   upload(h, F.fact, fact.data(), fact.size() * sizeof(double));

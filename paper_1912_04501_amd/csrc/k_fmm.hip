@@ -80,8 +80,12 @@ __global__ __launch_bounds__(256) void k_fmm_gather(int64_t ns, const int32_t* _
   fs2[k] = f2[j];
 }
 
-// multipoles of the leaves with sources; lane k holds term k
+// multipoles of the leaves with sources; lane k holds term k. Sources go four at a time: lanes
+// 16 s + i build source s's power table (w^i and w^(8 i), i < 8) in LDS, then term k takes
+// w^k = w^(8 (k >> 3)) w^(k & 7) with one product instead of a powering chain.
 __global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __restrict__ list) {
+  __shared__ cx tab[4][16];
+  __shared__ cx qs[4], ds[4];
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(a.L);
   const cx c = box_center(a, a.L, loc);
@@ -89,16 +93,33 @@ __global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __rest
   const int k = threadIdx.x;
   cx A = {0, 0}, B = {0, 0}, C = {0, 0};
   const int32_t s0 = a.leaf_s[loc], s1 = a.leaf_s[loc + 1];
-  if (k < a.p) {
-    for (int32_t j = s0; j < s1; ++j) {
+  for (int32_t j0 = s0; j0 < s1; j0 += 4) {
+    const int sl = k >> 4, i = k & 15;
+    const int32_t j = j0 + sl;
+    if (j < s1) {
       const cx d = {a.sx[j] - c.r, a.sy[j] - c.i};
-      const cx q = {a.fs1[j], a.fs2[j]};
-      const cx wk = cpow(d * ih, k);
-      const cx qw = q * wk;
-      A = A + qw;
-      B = B + conj(q) * wk;
-      C = C + qw * conj(d);
+      const cx w = d * ih;
+      tab[sl][i] = i < 8 ? cpow(w, i) : cpow(w, 8 * (i - 8));
+      if (i == 0) {
+        qs[sl] = {a.fs1[j], a.fs2[j]};
+        ds[sl] = conj(d);
+      }
     }
+    __syncthreads();
+    if (k < a.p) {
+      const int ns = min(4, (int)(s1 - j0));
+      for (int t = 0; t < ns; ++t) {
+        const cx wk = tab[t][8 + (k >> 3)] * tab[t][k & 7];
+        const cx q = qs[t];
+        const cx qw = q * wk;
+        A = A + qw;
+        B = B + conj(q) * wk;
+        C = C + qw * ds[t];
+      }
+    }
+    __syncthreads();
+  }
+  if (k < a.p) {
     cx* out = a.Mx + gid * 3 * a.p;
     out[k] = A;
     out[a.p + k] = B;
@@ -257,55 +278,88 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(FmmArgs a, int l, const int32_t*
   }
 }
 
-// one thread per target (sorted by leaf): local expansion plus the direct sum over the 3x3
-// neighbour leaves
-__global__ __launch_bounds__(256) void k_fmm_eval(FmmArgs a, int64_t N, const int32_t* __restrict__ tperm,
-                                                  const int32_t* __restrict__ tleaf, Geo g,
-                                                  double* __restrict__ out) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (t >= N) return;
-  const int64_t i = tperm[t];
-  const int64_t loc = tleaf[t];
+// one wavefront per target leaf: the leaf's targets (64 at a time) each take 64 / n_t lanes, which
+// split the direct sum over the 3x3 neighbour leaves (sources in three contiguous rows of the sorted
+// order, staged through LDS 64 at a time) and are summed in a fixed order; then the local expansion
+__global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int32_t* __restrict__ list,
+                                                 const int32_t* __restrict__ leaf_t,
+                                                 const int32_t* __restrict__ tperm, Geo g,
+                                                 double* __restrict__ out) {
+  __shared__ double shx[64], shy[64], sf1[64], sf2[64];
+  __shared__ double red1[64], red2[64];
+  const int64_t gid = list[blockIdx.x];
+  const int64_t loc = gid - box_off(a.L);
   const int n = 1 << a.L;
   const int ix = (int)(loc % n), iy = (int)(loc / n);
   const cx c = box_center(a, a.L, loc);
   const double h = a.D0 / n;
-  const double x = g.x[i], y = g.y[i], nx = g.nx[i], ny = g.ny[i];
-  const cx dz = {x - c.r, y - c.i};
-  const cx u = dz * (1.0 / h);
-  const cx* Le = a.Lx + (box_off(a.L) + loc) * 3 * a.p;
+  const cx* Le = a.Lx + gid * 3 * a.p;
   const int p = a.p;
-  cx A = {0, 0}, B = {0, 0}, Ad = {0, 0}, Cd = {0, 0};
-  for (int k = p - 1; k >= 1; --k) {
-    A = A * u + Le[k];
-    B = B * u + Le[p + k];
-    Ad = Ad * u + Le[k] * (double)k;
-    Cd = Cd * u + Le[2 * p + k] * (double)k;
-  }
-  A = A * u + Le[0];
-  B = B * u + Le[p];
-  const cx E = (Cd - conj(dz) * Ad) * (1.0 / h);
-  const cx BE = B + E;
-  const double k4 = -1.0 / (4.0 * kPi);
-  double t1 = k4 * (2.0 * nx * A.r + (nx * BE.r - ny * BE.i));
-  double t2 = k4 * (2.0 * ny * A.r - (nx * BE.i + ny * BE.r));
-  double d1 = 0.0, d2 = 0.0;
-  for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
-    for (int jx = max(ix - 1, 0); jx <= min(ix + 1, n - 1); ++jx) {
-      const int64_t nl = (int64_t)jy * n + jx;
-      const int32_t s1 = a.leaf_s[nl + 1];
-      for (int32_t j = a.leaf_s[nl]; j < s1; ++j) {
-        const double rx = x - a.sx[j], ry = y - a.sy[j];
-        const double r2 = rx * rx + ry * ry;
-        if (r2 == 0.0) continue;           // the target's own node
-        const double cf = (rx * nx + ry * ny) * (rx * a.fs1[j] + ry * a.fs2[j]) / (r2 * r2);
-        d1 += cf * rx;
-        d2 += cf * ry;
+  const int lane = threadIdx.x;
+  const int32_t t0 = leaf_t[loc], t1 = leaf_t[loc + 1];
+  for (int32_t tb = t0; tb < t1; tb += 64) {
+    const int nt = min(64, (int)(t1 - tb));
+    const int S = 64 / nt;                 // lanes per target
+    const int tl = lane % nt, r = lane / nt;
+    const bool act = r < S;
+    const int64_t i = tperm[tb + tl];
+    const double x = g.x[i], y = g.y[i], nx = g.nx[i], ny = g.ny[i];
+    double d1 = 0.0, d2 = 0.0;
+    for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
+      const int32_t r0 = a.leaf_s[(int64_t)jy * n + max(ix - 1, 0)];
+      const int32_t r1 = a.leaf_s[(int64_t)jy * n + min(ix + 1, n - 1) + 1];
+      for (int32_t sb = r0; sb < r1; sb += 64) {
+        const int32_t j = sb + lane;
+        __syncthreads();
+        if (j < r1) {
+          shx[lane] = a.sx[j];
+          shy[lane] = a.sy[j];
+          sf1[lane] = a.fs1[j];
+          sf2[lane] = a.fs2[j];
+        }
+        __syncthreads();
+        const int m = min(64, (int)(r1 - sb));
+        if (act) {
+          for (int q = r; q < m; q += S) {
+            const double rx = x - shx[q], ry = y - shy[q];
+            const double r2 = rx * rx + ry * ry;
+            if (r2 == 0.0) continue;       // the target's own node
+            const double ir2 = rcp64(r2);
+            const double cf = (rx * nx + ry * ny) * (rx * sf1[q] + ry * sf2[q]) * (ir2 * ir2);
+            d1 += cf * rx;
+            d2 += cf * ry;
+          }
+        }
       }
     }
+    __syncthreads();
+    red1[lane] = act ? d1 : 0.0;
+    red2[lane] = act ? d2 : 0.0;
+    __syncthreads();
+    if (lane < nt) {
+      double e1 = 0.0, e2 = 0.0;
+      for (int q = 0; q < S; ++q) {
+        e1 += red1[q * nt + lane];
+        e2 += red2[q * nt + lane];
+      }
+      const cx dz = {x - c.r, y - c.i};
+      const cx u = dz * (1.0 / h);
+      cx A = {0, 0}, B = {0, 0}, Ad = {0, 0}, Cd = {0, 0};
+      for (int k = p - 1; k >= 1; --k) {
+        A = A * u + Le[k];
+        B = B * u + Le[p + k];
+        Ad = Ad * u + Le[k] * (double)k;
+        Cd = Cd * u + Le[2 * p + k] * (double)k;
+      }
+      A = A * u + Le[0];
+      B = B * u + Le[p];
+      const cx E = (Cd - conj(dz) * Ad) * (1.0 / h);
+      const cx BE = B + E;
+      const double k4 = -1.0 / (4.0 * kPi);
+      out[i] = k4 * (2.0 * nx * A.r + (nx * BE.r - ny * BE.i)) - e1 / kPi;
+      out[N + i] = k4 * (2.0 * ny * A.r - (nx * BE.i + ny * BE.r)) - e2 / kPi;
+    }
   }
-  out[i] = t1 - d1 / kPi;
-  out[N + i] = t2 - d2 / kPi;
 }
 
 FmmArgs args(spm_handle* h) {
@@ -381,7 +435,7 @@ void launch_fmm(spm_handle* h, double* out) {
   }
   const int64_t N = h->geo.N;
   prof_mark(h, 2, true, 0);
-  k_fmm_eval<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(a, N, F.tperm, F.tleaf, h->geo, out);
+  if (n_of(s)) k_fmm_eval<<<n_of(s), 64, 0, h->stream>>>(a, N, list(s), F.leaf_t, F.tperm, h->geo, out);
   SPM_HIP_CHECK(hipGetLastError());
   prof_mark(h, 2, false, F.p2p_pairs);
 }

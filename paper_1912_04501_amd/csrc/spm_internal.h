@@ -335,10 +335,11 @@ struct FmmPlan {
   double *fs1 = nullptr, *fs2 = nullptr;  // [9N] w sigma in sorted order
   int32_t* leaf_s = nullptr;              // [4^L + 1] source offsets of the leaves
   int32_t* tperm = nullptr;               // [N] nodes sorted by leaf
-  int32_t* tleaf = nullptr;               // [N] leaf of each sorted target
+  int32_t* leaf_t = nullptr;              // [4^L + 1] target offsets of the leaves
   int32_t* bsrc = nullptr;                // [boxes of all levels] sources in each box
   int32_t* lists = nullptr;               // box lists of the passes (global box ids)
-  std::vector<int64_t> seg;               // list segments: P2M, M2M levels L-1..2, M2L, L2L levels 3..L
+  std::vector<int64_t> seg;               // list segments: P2M, M2M levels L-1..2, M2L, L2L levels 3..L,
+                                          // target leaves
   double* fact = nullptr;                 // [2p] factorials
   double *Mx = nullptr, *Lx = nullptr;    // [boxes x 3 x p] complex multipole / local expansions
   int32_t* nsplit1 = nullptr;             // [1] = 1: the combine step reads one partial
