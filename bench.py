@@ -6,8 +6,10 @@ seed 2 (the large-cell configuration on which node-pair evaluations per second a
 quoted). One step = one complete mobility solve from a zero initial guess to an FP64
 relative residual of 1e-10 (matvecs + GMRES + readout of v, omega, mu_eff), then
 mu_eff once more by contour deformation (valid with particles across the wall D), with
-the geometry already resident in HBM. Default precision: FP32 near sums inside FP64
-iterative refinement; --precision fp64 times plain FP64 GMRES.
+the geometry already resident in HBM. Default solver: FP32 near sums inside FP64
+iterative refinement with the right block preconditioner (the fastest variant at this
+residual); --precision and --precond choose others, and the untimed comparison solves
+report plain FP64 GMRES, the other mixed forms and the FMM near sum beside it.
 
 value = node-image pair evaluations (9 N^2 per matvec, all matvecs of the step) per
 second of wall time over the timed steps.
@@ -118,7 +120,7 @@ def main():
                     help="solver precision (default: fp32_ir for the 200-ellipse cell, fp32_relaxed for the "
                          "ensemble)")
     ap.add_argument("--precond", choices=["none", "block"], default=None,
-                    help="ensemble64: right block preconditioner (default: block)")
+                    help="ellipses200 and ensemble64: right block preconditioner (default: block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed FP64-vs-FP32+IR comparison solves")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
@@ -150,7 +152,7 @@ def main():
     if args.precision is None:
         args.precision = "fp32_relaxed" if args.workload == "ensemble64" else "fp32_ir"
     if args.precond is None:
-        args.precond = "block" if args.workload == "ensemble64" else "none"
+        args.precond = "block" if args.workload in ("ensemble64", "ellipses200") else "none"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
               file=sys.stderr)
@@ -183,7 +185,8 @@ def main():
     wl = W.ellipses_200()
     log(f"[bench] workload {wl['name']} generated in {time.perf_counter() - t0:.1f}s")
     prec = {"fp32_relaxed": spm.SPM_FP32_RELAXED, "fp32_ir": spm.SPM_FP32_IR, "fp64": spm.SPM_FP64}[args.precision]
-    s = spm.Solver("cuda:0", precision=prec)
+    s = spm.Solver("cuda:0", precision=prec,
+                   precond=spm.SPM_PRECOND_BLOCK if args.precond == "block" else spm.SPM_PRECOND_NONE)
     s.set_workload(wl)
     N = s.N
     pairs_per_matvec = 9.0 * N * N
@@ -264,7 +267,8 @@ def main():
            "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64" if prec == spm.SPM_FP64 else "f32+f64", "data": "synthetic",
            "config": {"workload": wl["name"], "N": N, "particles": s.No, "nodes_per_particle": 256,
-                      "precision": args.precision, "tol": 1e-10, "images": "3x3", "proxies": 32,
+                      "precision": args.precision, "precond": args.precond, "tol": 1e-10, "images": "3x3",
+                      "proxies": 32,
                       "wall_points": 24, "close_factor": 10},
            "roofline": roofline, "roofline_other_precision": other, "cpu_baseline": cpu,
            "mu_eff": {"stresslet": float(r["mu_eff"][0]), "contour": float(mu_c[0])}, **extra}
