@@ -78,6 +78,25 @@ def test_fmm_near_sum_200_ellipses_sampled():
     assert err < 1e-12
 
 
+def test_fmm_near_sum_1000_islands_sampled():
+    """1000 star-shaped islands, N = 350,000 (the islands benchmark's largest cell, 8 levels):
+    1,000 sampled targets against the oracle's direct sum over all 3,150,000 image sources."""
+    wl = W.random_stars(1000, 0.2, 1)
+    g = geometry.build_geometry(wl)
+    s = _fmm(wl)
+    st = s.fmm_stats()
+    print(f"[fmm islands] N {g.N} levels {st['levels']} direct pairs {st['p2p_pairs']:.3g} M2L {st['m2l']:.3g}",
+          flush=True)
+    sig = W.random_density(g.N, seed=8)
+    T = _n(s.near_traction(torch.as_tensor(sig, device="cuda:0")))
+    rows = np.sort(np.random.default_rng(3).choice(g.N, 1000, replace=False))
+    ref = _oracle_near(g, sig, rows)
+    dev = np.stack([T[rows], T[g.N + rows]], axis=1)
+    err = np.abs(dev - ref).max() / np.abs(ref).max()
+    print(f"[fmm islands] rel err {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
 @pytest.mark.parametrize("name", ["random_25_phi0.3_seed1", "two_stars_s0.25_A0.5_w4"])
 def test_fmm_solve_matches_oracle(name):
     wl = CASES[name]()
