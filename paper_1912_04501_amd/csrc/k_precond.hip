@@ -156,14 +156,16 @@ __global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* 
 }
 
 // One block per particle: out = R (B^-1 (R^T v)) on the particle's nodes. Particles of
-// inactive cells are skipped when active is given.
+// inactive cells are skipped when active is given. The inverse is column-major, so the block
+// splits into S = blockDim / m column groups whose lanes run over consecutive rows: every load of
+// a column slice is contiguous. The S partial rows are summed in a fixed order.
 __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __restrict__ pshape,
                                                         const int64_t* __restrict__ ioff,
                                                         const float* __restrict__ inv,
-                                                        const int32_t* __restrict__ active, int L,
+                                                        const int32_t* __restrict__ active,
                                                         const double* __restrict__ v, double* __restrict__ out) {
   __shared__ double vb[2 * kMaxNodesStaged];
-  __shared__ double ub[2 * kMaxNodesStaged];
+  __shared__ double part[1024];
   const int q = blockIdx.x;
   if (active && active[g.pcell[q]] == 0) return;
   const int n = g.pn[q], m = 2 * n;
@@ -177,17 +179,20 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
   }
   __syncthreads();
   const float* M = inv + ioff[pshape[q]];
-  // L lanes per row, each over the columns c = sub, sub + L, ...
-  const int sub = threadIdx.x % L;
-  for (int r = threadIdx.x / L; r < m; r += blockDim.x / L) {
+  const int S = max(1, (int)blockDim.x / m);   // column groups (m <= 2 kMaxNodesStaged = blockDim)
+  const int grp = threadIdx.x / m, r = threadIdx.x % m;
+  if (grp < S) {
     double acc = 0.0;
-    for (int c = sub; c < m; c += L) acc += (double)M[(int64_t)c * m + r] * vb[c];
-    acc = group_sum(acc, L);
-    if (sub == 0) ub[r] = acc;
+    for (int c = grp; c < m; c += S) acc += (double)M[(int64_t)c * m + r] * vb[c];
+    part[grp * m + r] = acc;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < n; k += blockDim.x) {
-    const double a = ub[k], b = ub[n + k];
+    double a = 0.0, b = 0.0;
+    for (int s = 0; s < S; ++s) {
+      a += part[s * m + k];
+      b += part[s * m + n + k];
+    }
     out[i0 + k] = ct * a - st * b;
     out[N + i0 + k] = st * a + ct * b;
   }
@@ -259,8 +264,7 @@ void launch_precond_apply(spm_handle* h, const double* v, double* out, bool with
     throw ApiError(SPM_EINVAL, "the block preconditioner needs at most " + std::to_string(kMaxNodesStaged) +
                                    " nodes per particle");
   k_precond_apply<<<h->geo.No, 1024, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
-                                                     with_active ? h->kr.active : nullptr,
-                                                     lanes_per_row(2 * h->geo.nmax), v, out);
+                                                     with_active ? h->kr.active : nullptr, v, out);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
