@@ -22,8 +22,8 @@
 //       L_l = (-1)^l rho^(l+1) / (h l!) sum_k (k + l)! (a_k rho^k / k!)
 //   L2L (parent c to child c', t = (c' - c)/h_P): L'_m = (2^-m / m!) sum_{l>=m} (L_l l!) (t^(l-m) / (l-m)!)
 // Interaction lists are the usual ones (children of the parent's neighbours that are not
-// neighbours); leaves evaluate their 3x3 neighbourhood directly, skipping the pair at zero
-// distance (the target's own node). Every pass is deterministic: one wavefront per box, lanes over
+// neighbours); leaves evaluate their 3x3 neighbourhood directly, where the pair at zero
+// distance (the target's own node) adds nothing. Every pass is deterministic: one wavefront per box, lanes over
 // expansion terms, fixed loop orders.
 #include "spm_internal.h"
 
@@ -80,12 +80,13 @@ __global__ __launch_bounds__(256) void k_fmm_gather(int64_t ns, const int32_t* _
   fs2[k] = f2[j];
 }
 
-// multipoles of the leaves with sources; lane k holds term k. Sources go four at a time: lanes
-// 16 s + i build source s's power table (w^i and w^(8 i), i < 8) in LDS, then term k takes
-// w^k = w^(8 (k >> 3)) w^(k & 7) with one product instead of a powering chain.
+// multipoles of the leaves with sources; lane k holds term k. Sources go 32 at a time: lane t
+// builds source t's power table in LDS (w^i and w^(8 i), i < 8, by repeated products), then term
+// k takes w^k = w^(8 (k >> 3)) w^(k & 7) with one product.
+constexpr int kP2mGroup = 32;
 __global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __restrict__ list) {
-  __shared__ cx tab[4][16];
-  __shared__ cx qs[4], ds[4];
+  __shared__ cx tab[kP2mGroup][16];
+  __shared__ cx qs[kP2mGroup], ds[kP2mGroup];
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(a.L);
   const cx c = box_center(a, a.L, loc);
@@ -93,21 +94,28 @@ __global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __rest
   const int k = threadIdx.x;
   cx A = {0, 0}, B = {0, 0}, C = {0, 0};
   const int32_t s0 = a.leaf_s[loc], s1 = a.leaf_s[loc + 1];
-  for (int32_t j0 = s0; j0 < s1; j0 += 4) {
-    const int sl = k >> 4, i = k & 15;
-    const int32_t j = j0 + sl;
-    if (j < s1) {
+  for (int32_t j0 = s0; j0 < s1; j0 += kP2mGroup) {
+    const int32_t j = j0 + k;
+    if (k < kP2mGroup && j < s1) {
       const cx d = {a.sx[j] - c.r, a.sy[j] - c.i};
       const cx w = d * ih;
-      tab[sl][i] = i < 8 ? cpow(w, i) : cpow(w, 8 * (i - 8));
-      if (i == 0) {
-        qs[sl] = {a.fs1[j], a.fs2[j]};
-        ds[sl] = conj(d);
+      cx pw = {1.0, 0.0};
+      for (int i = 0; i < 8; ++i) {
+        tab[k][i] = pw;
+        pw = pw * w;
       }
+      const cx w8 = pw;
+      pw = {1.0, 0.0};
+      for (int i = 0; i < 8; ++i) {
+        tab[k][8 + i] = pw;
+        pw = pw * w8;
+      }
+      qs[k] = {a.fs1[j], a.fs2[j]};
+      ds[k] = conj(d);
     }
     __syncthreads();
     if (k < a.p) {
-      const int ns = min(4, (int)(s1 - j0));
+      const int ns = min(kP2mGroup, (int)(s1 - j0));
       for (int t = 0; t < ns; ++t) {
         const cx wk = tab[t][8 + (k >> 3)] * tab[t][k & 7];
         const cx q = qs[t];
@@ -322,10 +330,9 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
         if (act) {
           for (int q = r; q < m; q += S) {
             const double rx = x - shx[q], ry = y - shy[q];
-            const double r2 = rx * rx + ry * ry;
-            if (r2 == 0.0) continue;       // the target's own node
-            const double ir2 = rcp64(r2);
-            const double cf = (rx * nx + ry * ny) * (rx * sf1[q] + ry * sf2[q]) * (ir2 * ir2);
+            // the target's own node (r = 0): the floor keeps 1/|r|^2 finite and (r.n)(r.f) = 0
+            const double ir2 = rcp64(fmax(rx * rx + ry * ry, 1e-300));
+            const double cf = (((rx * nx + ry * ny) * (rx * sf1[q] + ry * sf2[q])) * ir2) * ir2;
             d1 += cf * rx;
             d2 += cf * ry;
           }
