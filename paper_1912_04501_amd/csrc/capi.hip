@@ -1127,6 +1127,7 @@ void build_fmm_plan(spm_handle* h) {
   ensure(h, F.Mx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.Lx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.nsplit1, 1);
+  ensure(h, F.vnear, 3 * (size_t)g.No);
   upload(h, F.sx, ssx.data(), ns * sizeof(double));
   upload(h, F.sy, ssy.data(), ns * sizeof(double));
   upload(h, F.sj, ssj.data(), ns * sizeof(int32_t));

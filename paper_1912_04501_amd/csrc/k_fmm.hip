@@ -369,6 +369,84 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
   }
 }
 
+// Velocity and vorticity of the near-image sum at the particle centres (the readout's u_near,
+// vort_near) from the multipoles of the current density: one wavefront per particle walks the
+// quadtree like the FMM does (the interaction list of the centre's box at every level, evaluated
+// from the boxes' multipoles at the centre itself, then the 3x3 leaves around it directly). With
+// r = z - z_j, the Stokeslet of eq. Gv is G f = (1/4pi mu) [ -f log|r| + f/2 + conj(f) r / (2 conj(r)) ],
+// so a box contributes -(1/2)(Phi + conj(Psi)) with Phi = sum f log r, Psi = sum conj(f) log r
+// (log multipoles built from the same power sums as A and B), F_box / 2, and
+// conj((conj(z) - conj(c)) A - C_c) / 2; the vorticity is -(1/2pi mu) Im A.
+__global__ __launch_bounds__(64) void k_fmm_velocities(FmmArgs a, Geo g, double mu, double* __restrict__ near3) {
+  const int q = blockIdx.x;
+  const int k = threadIdx.x, p = a.p;
+  const double zx = g.pcx[q], zy = g.pcy[q];
+  const int nL = 1 << a.L;
+  const int ixL = min(max((int)floor((zx - (a.c0x - 0.5 * a.D0)) / a.D0 * nL), 0), nL - 1);
+  const int iyL = min(max((int)floor((zy - (a.c0y - 0.5 * a.D0)) / a.D0 * nL), 0), nL - 1);
+  cx sA = {0, 0}, sE = {0, 0}, sLog = {0, 0}, sF = {0, 0};
+  for (int l = 2; l <= a.L; ++l) {
+    const int n = 1 << l, np = n >> 1;
+    const int ix = ixL >> (a.L - l), iy = iyL >> (a.L - l);
+    const double h = a.D0 / n;
+    for (int qy = max((iy >> 1) - 1, 0); qy <= min((iy >> 1) + 1, np - 1); ++qy) {
+      for (int qx = max((ix >> 1) - 1, 0); qx <= min((ix >> 1) + 1, np - 1); ++qx) {
+        for (int ch = 0; ch < 4; ++ch) {
+          const int bx = 2 * qx + (ch & 1), by = 2 * qy + (ch >> 1);
+          if (abs(bx - ix) <= 1 && abs(by - iy) <= 1) continue;
+          const int64_t sloc = (int64_t)by * n + bx;
+          const int64_t sgid = box_off(l) + sloc;
+          if (a.bsrc[sgid] == 0) continue;
+          if (k >= p) continue;
+          const cx cs = box_center(a, l, sloc);
+          const cx d = {zx - cs.r, zy - cs.i};
+          const cx iw = cdiv({h, 0.0}, d);           // h / (z - c_s)
+          const cx pk = cpow(iw, k);                  // iw^k
+          const cx pk1 = pk * iw;                     // iw^(k+1)
+          const cx* m = a.Mx + sgid * 3 * p;
+          const cx am = m[k], bm = m[p + k], cm = m[2 * p + k];
+          const cx tA = am * pk1 * (1.0 / h);
+          sA = sA + tA;
+          sE = sE + conj(d) * tA - cm * pk1 * (1.0 / h);
+          if (k == 0) {
+            const cx lg = {0.5 * log(d.r * d.r + d.i * d.i), atan2(d.i, d.r)};
+            sLog = sLog + (am * lg + conj(bm * lg)) * 0.5;
+            sF = sF + am;
+          } else {
+            sLog = sLog - (am * pk + conj(bm * pk)) * (0.5 / k);
+          }
+        }
+      }
+    }
+  }
+  const double k4 = 1.0 / (4.0 * kPi * mu), k2 = -1.0 / (2.0 * kPi * mu);
+  double u1 = k4 * (-sLog.r + 0.5 * sF.r + 0.5 * sE.r);
+  double u2 = k4 * (-sLog.i + 0.5 * sF.i - 0.5 * sE.i);
+  double vo = k2 * sA.i;
+  for (int jy = max(iyL - 1, 0); jy <= min(iyL + 1, nL - 1); ++jy) {
+    const int32_t r0 = a.leaf_s[(int64_t)jy * nL + max(ixL - 1, 0)];
+    const int32_t r1 = a.leaf_s[(int64_t)jy * nL + min(ixL + 1, nL - 1) + 1];
+    for (int32_t j = r0 + k; j < r1; j += 64) {
+      const double rx = zx - a.sx[j], ry = zy - a.sy[j], fa = a.fs1[j], fb = a.fs2[j];
+      const double r2 = rx * rx + ry * ry;
+      const double ir2 = rcp64(r2);
+      const double lg = -0.5 * log(r2);
+      const double rf = (rx * fa + ry * fb) * ir2;
+      u1 += k4 * (lg * fa + rx * rf);
+      u2 += k4 * (lg * fb + ry * rf);
+      vo += k2 * (rx * fb - ry * fa) * ir2;
+    }
+  }
+  u1 = wave_sum(u1);
+  u2 = wave_sum(u2);
+  vo = wave_sum(vo);
+  if (k == 0) {
+    near3[3 * q] = u1;
+    near3[3 * q + 1] = u2;
+    near3[3 * q + 2] = vo;
+  }
+}
+
 FmmArgs args(spm_handle* h) {
   const FmmPlan& F = h->fmm;
   FmmArgs a;
@@ -412,12 +490,11 @@ void prof_mark(spm_handle* h, int kind, bool start, double work) {
   }
 }
 
-}  // namespace
-
-void launch_fmm(spm_handle* h, double* out) {
+// gather w sigma into the sorted order, multipoles of the leaves, then of every coarser level
+// down to 2; returns the index of the next list segment (M2L)
+int launch_fmm_upward(spm_handle* h) {
   const FmmPlan& F = h->fmm;
   const FmmArgs a = args(h);
-  const int L = F.L;
   auto n_of = [&](int s) { return (unsigned)(F.seg[s + 1] - F.seg[s]); };
   auto list = [&](int s) { return F.lists + F.seg[s]; };
   k_fmm_gather<<<(unsigned)((F.nsrc + 255) / 256), 256, 0, h->stream>>>(F.nsrc, F.sj, h->wk.f1, h->wk.f2, F.fs1,
@@ -427,10 +504,28 @@ void launch_fmm(spm_handle* h, double* out) {
   if (n_of(s)) k_fmm_p2m<<<n_of(s), 64, 0, h->stream>>>(a, list(s));
   SPM_HIP_CHECK(hipGetLastError());
   ++s;
-  for (int l = L - 1; l >= 2; --l, ++s) {
+  for (int l = F.L - 1; l >= 2; --l, ++s) {
     if (n_of(s)) k_fmm_m2m<<<n_of(s), 64, 0, h->stream>>>(a, l, list(s));
     SPM_HIP_CHECK(hipGetLastError());
   }
+  return s;
+}
+
+}  // namespace
+
+void launch_fmm_velocities(spm_handle* h, double* near3) {
+  launch_fmm_upward(h);
+  k_fmm_velocities<<<h->geo.No, 64, 0, h->stream>>>(args(h), h->geo, h->cfg.mu, near3);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+void launch_fmm(spm_handle* h, double* out) {
+  const FmmPlan& F = h->fmm;
+  const FmmArgs a = args(h);
+  const int L = F.L;
+  auto n_of = [&](int s) { return (unsigned)(F.seg[s + 1] - F.seg[s]); };
+  auto list = [&](int s) { return F.lists + F.seg[s]; };
+  int s = launch_fmm_upward(h);
   prof_mark(h, 3, true, 0);
   if (n_of(s)) k_fmm_m2l<<<n_of(s), 64, 0, h->stream>>>(a, list(s));
   SPM_HIP_CHECK(hipGetLastError());

@@ -5,7 +5,8 @@
 // assemble: y = sigma/2 + T + alpha n + L sigma,  alpha = -(T(x0) . n0)   (Sec. 5 eq. BIEPerturbed;
 //           Sec. 6.2 pressure pin with x0 the first node of the first particle),
 //           L_q sigma (x) = F_q + (x - c_q)^perp tau_q.
-// readout:  v_q = u0(c_q) + u_near(c_q) + u_corr(c_q) - u_corr(c_U), then the constant that makes
+// readout:  v_q = u0(c_q) + u_near(c_q) + u_corr(c_q) - u_corr(c_U) (u_near by the FMM's tree when the
+//           FMM near sum is on), then the constant that makes
 //           the area-weighted mean of v_q - u0(c_q) over the cell zero is removed;
 //           omega_q = (vort_near(c_q) + vort_corr(c_q))/2 - gamma/2   (Sec. 3 eq. RigidBodyMotion).
 //           mu_eff = mu - sum_q stresslet_q / (2 gamma |U|)           (Sec. 3 eq. mueff via the
@@ -85,11 +86,12 @@ void launch_assemble(spm_handle* h, const double* sigma, double* out) {
 }
 
 // Velocity and vorticity at the particle centres: one block per particle, the nodes of
-// its cell x 9 images.
+// its cell x 9 images (or, when near3 is given, the near-image part computed by the FMM).
 __global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restrict__ f1, const double* __restrict__ f2,
                                                     int M, const double* __restrict__ px, const double* __restrict__ py,
                                                     const double* __restrict__ xi_all, double cUx, double cUy, double mu,
-                                                    double gamma, double* __restrict__ vel, double* __restrict__ omega) {
+                                                    double gamma, const double* __restrict__ near3,
+                                                    double* __restrict__ vel, double* __restrict__ omega) {
   __shared__ double sc[16];
   const int q = blockIdx.x;
   const int cell = g.pcell[q];
@@ -97,7 +99,8 @@ __global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restr
   const double cx = g.pcx[q], cy = g.pcy[q];
   const double k4 = 1.0 / (4.0 * kPi * mu), k2 = -1.0 / (2.0 * kPi * mu);
   double u1 = 0, u2 = 0, vo = 0;
-  for (int64_t j = g.cnoff[cell] + threadIdx.x; j < g.cnoff[cell + 1]; j += blockDim.x) {
+  const int64_t j_end = near3 ? g.cnoff[cell] : g.cnoff[cell + 1];
+  for (int64_t j = g.cnoff[cell] + threadIdx.x; j < j_end; j += blockDim.x) {
     const double yx = g.x[j], yy = g.y[j], a = f1[j], b = f2[j];
     for (int s = 0; s < kShifts; ++s) {
       const double rx = cx - (yx + shift_x(s, skew)), ry = cy - (yy + shift_y(s));
@@ -113,6 +116,11 @@ __global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restr
   u1 = block_sum(u1, sc);
   u2 = block_sum(u2, sc);
   vo = block_sum(vo, sc);
+  if (near3) {
+    u1 = near3[3 * q];
+    u2 = near3[3 * q + 1];
+    vo = near3[3 * q + 2];
+  }
   if (threadIdx.x == 0) {
     const double* xi = xi_all + (int64_t)cell * 2 * M;
     double c1 = 0, c2 = 0, z1 = 0, z2 = 0, cv = 0;
@@ -174,8 +182,14 @@ __global__ __launch_bounds__(256) void k_velocity_gauge(const int32_t* __restric
 }
 
 void launch_velocities(spm_handle* h, double* vel, double* omega) {
+  const double* near3 = nullptr;
+  if (h->fmm.on) {                      // near-image part by the FMM's tree (w sigma is staged)
+    launch_fmm_velocities(h, h->fmm.vnear);
+    near3 = h->fmm.vnear;
+  }
   k_velocities<<<h->geo.No, 256, 0, h->stream>>>(h->geo, h->wk.f1, h->wk.f2, h->per.M, h->per.px, h->per.py,
-                                                 h->wk.xi, h->cU[0], h->cU[1], h->cfg.mu, h->cfg.gamma, vel, omega);
+                                                 h->wk.xi, h->cU[0], h->cU[1], h->cfg.mu, h->cfg.gamma, near3, vel,
+                                                 omega);
   SPM_HIP_CHECK(hipGetLastError());
   if (vel) {
     k_velocity_gauge<<<h->geo.C, 256, 0, h->stream>>>(h->geo.cpoff, h->geo.pcy, h->geo.parea, h->cfg.gamma, vel,

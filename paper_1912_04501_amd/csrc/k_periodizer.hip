@@ -376,25 +376,29 @@ __global__ __launch_bounds__(1024) void k_xi(Lat L, const double* __restrict__ c
   __syncthreads();
   const double skew = cskew[cell];
   const double l1 = 1.0, l2 = sqrt(skew * skew + 1.0);
-  for (int wpt = threadIdx.x; wpt < 2 * m; wpt += blockDim.x) {
+  // one wave per wall point, lanes over the source chunks, then a fixed butterfly
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  for (int wpt = threadIdx.x >> 6; wpt < 2 * m; wpt += nw) {
     dd s[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-    for (int c = disc_off[cell]; c < disc_off[cell + 1]; ++c) {
+    for (int c = disc_off[cell] + lane; c < disc_off[cell + 1]; c += 64) {
       const double* o = disc + ((int64_t)c * 2 * m + wpt) * 8;
       for (int k = 0; k < 4; ++k) s[k] = dd_add(s[k], dd{o[k], o[4 + k]});
     }
-    const bool onD = wpt >= m;
-    const int q = onD ? wpt - m : wpt;
-    const int base = onD ? 4 * m : 0;
-    const double l = onD ? l1 : l2;
-    const double g0[4] = {0.0, 0.0, -Fs[0] / (2.0 * l), -Fs[1] / (2.0 * l)};
-    for (int k = 0; k < 4; ++k) {   // g0 - g, rounded once
-      const dd v = dd_add(dd{g0[k], 0.0}, dd{-s[k].hi, -s[k].lo});
-      gt[base + k * m + q] = v.hi + v.lo;
+    for (int k = 0; k < 4; ++k) s[k] = dd_wave_sum(s[k]);
+    if (lane == 0) {
+      const bool onD = wpt >= m;
+      const int q = onD ? wpt - m : wpt;
+      const int base = onD ? 4 * m : 0;
+      const double l = onD ? l1 : l2;
+      const double g0[4] = {0.0, 0.0, -Fs[0] / (2.0 * l), -Fs[1] / (2.0 * l)};
+      for (int k = 0; k < 4; ++k) {   // g0 - g, rounded once
+        const dd v = dd_add(dd{g0[k], 0.0}, dd{-s[k].hi, -s[k].lo});
+        gt[base + k * m + q] = v.hi + v.lo;
+      }
     }
   }
   __syncthreads();
   // one wave per row of Q+, lanes over its 8m entries; compensated dot product
-  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
   for (int i = threadIdx.x >> 6; i < 2 * M; i += nw) {
     dd s = {0, 0};
     for (int r = lane; r < 8 * m; r += 64) s = dd_fma(s, Qp[(int64_t)i * 8 * m + r], gt[r]);

@@ -343,6 +343,7 @@ struct FmmPlan {
   double* fact = nullptr;                 // [2p] factorials
   double *Mx = nullptr, *Lx = nullptr;    // [boxes x 3 x p] complex multipole / local expansions
   int32_t* nsplit1 = nullptr;             // [1] = 1: the combine step reads one partial
+  double* vnear = nullptr;                // [3 No] near-image velocity and vorticity at the centres
   double p2p_pairs = 0, m2l = 0;          // work of one evaluation
 };
 
@@ -543,6 +544,7 @@ void launch_mu_eff_contour(spm_handle* h, int m, double* mu_eff);
 // FMM near sum (k_fmm.hip): plan from the device node positions; evaluation into out [2N]
 void build_fmm_plan(spm_handle* h);
 void launch_fmm(spm_handle* h, double* out);
+void launch_fmm_velocities(spm_handle* h, double* near3);
 void launch_gap(spm_handle* h, double* gap_host, int32_t* overlap_host);
 
 // GMRES building blocks (k_gmres.hip); per cell, cells in lockstep
