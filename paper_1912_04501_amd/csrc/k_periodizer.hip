@@ -310,13 +310,15 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
       double v1 = 0, v2 = 0, w1 = 0, w2 = 0;
       stokeslet_uv(x0 - fx, y0 - fy, g1, g2, L.inv4pimu, v1, v2);
       stokeslet_uv(x0 - cx, y0 - cy, g1, g2, L.inv4pimu, w1, w2);
-      u1 = dd_add_d(dd_add_d(u1, v1), -w1);
-      u2 = dd_add_d(dd_add_d(u2, v2), -w2);
+      // the far-minus-near difference of one source is rounded once (an error of the size
+      // of its own evaluation error); the running sums are double-double
+      u1 = dd_add_d(u1, v1 - w1);
+      u2 = dd_add_d(u2, v2 - w2);
       double p1 = 0, p2 = 0, q1 = 0, q2 = 0;
       traction_uv(x0 - fx, y0 - fy, nx, ny, g1, g2, p1, p2);
       traction_uv(x0 - cx, y0 - cy, nx, ny, g1, g2, q1, q2);
-      t1 = dd_add_d(dd_add_d(t1, p1), -q1);
-      t2 = dd_add_d(dd_add_d(t2, p2), -q2);
+      t1 = dd_add_d(t1, p1 - q1);
+      t2 = dd_add_d(t2, p2 - q2);
     }
   }
   u1 = dd_block_sum(u1, sc);
