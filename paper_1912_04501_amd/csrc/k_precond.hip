@@ -155,20 +155,26 @@ __global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* 
     inv[d.ioff + (int64_t)c * m + r] = (float)work[d.woff + (int64_t)r * ld + m + c];
 }
 
-// One block per particle: out = R (B^-1 (R^T v)) on the particle's nodes. Particles of
-// inactive cells are skipped when active is given. The inverse is column-major, so the block
-// splits into S = blockDim / m column groups whose lanes run over consecutive rows: every load of
-// a column slice is contiguous. The S partial rows are summed in a fixed order.
+// Blocks (particle, row segment): out = R (B^-1 (R^T v)) on the particle's nodes, segment y
+// producing nodes [y nk, (y + 1) nk) (rows k and n + k of the 2n x 2n inverse, nk = ceil(n / R)),
+// so that small particle counts still spread over the chip. Particles of inactive cells are
+// skipped when active is given. The inverse is column-major: the block's rows form two contiguous
+// ranges, split into S = blockDim / (2 nk) column groups whose lanes run over consecutive rows, so
+// every load is contiguous; the S partial rows are summed in a fixed order.
 __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __restrict__ pshape,
                                                         const int64_t* __restrict__ ioff,
                                                         const float* __restrict__ inv,
-                                                        const int32_t* __restrict__ active,
+                                                        const int32_t* __restrict__ active, int R,
                                                         const double* __restrict__ v, double* __restrict__ out) {
   __shared__ double vb[2 * kMaxNodesStaged];
   __shared__ double part[1024];
   const int q = blockIdx.x;
   if (active && active[g.pcell[q]] == 0) return;
   const int n = g.pn[q], m = 2 * n;
+  const int nk = (n + R - 1) / R;
+  const int k0 = blockIdx.y * nk;
+  if (k0 >= n) return;
+  const int kn = min(nk, n - k0);
   const int64_t i0 = g.poff[q], N = g.N;
   double st, ct;
   sincos(g.pth[q], &st, &ct);
@@ -179,22 +185,25 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
   }
   __syncthreads();
   const float* M = inv + ioff[pshape[q]];
-  const int S = max(1, (int)blockDim.x / m);   // column groups (m <= 2 kMaxNodesStaged = blockDim)
-  const int grp = threadIdx.x / m, r = threadIdx.x % m;
-  if (grp < S) {
+  const int rows = 2 * nk;
+  const int S = max(1, (int)blockDim.x / rows);
+  const int grp = threadIdx.x / rows, rr = threadIdx.x % rows;
+  const int lk = rr < nk ? rr : rr - nk;                // node within the segment
+  if (grp < S && lk < kn) {
+    const int r = (rr < nk ? 0 : n) + k0 + lk;          // row of the inverse
     double acc = 0.0;
     for (int c = grp; c < m; c += S) acc += (double)M[(int64_t)c * m + r] * vb[c];
-    part[grp * m + r] = acc;
+    part[grp * rows + rr] = acc;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+  for (int k = threadIdx.x; k < kn; k += blockDim.x) {
     double a = 0.0, b = 0.0;
     for (int s = 0; s < S; ++s) {
-      a += part[s * m + k];
-      b += part[s * m + n + k];
+      a += part[s * rows + k];
+      b += part[s * rows + nk + k];
     }
-    out[i0 + k] = ct * a - st * b;
-    out[N + i0 + k] = st * a + ct * b;
+    out[i0 + k0 + k] = ct * a - st * b;
+    out[N + i0 + k0 + k] = st * a + ct * b;
   }
 }
 
@@ -263,8 +272,10 @@ void launch_precond_apply(spm_handle* h, const double* v, double* out, bool with
   if (h->geo.nmax > kMaxNodesStaged)
     throw ApiError(SPM_EINVAL, "the block preconditioner needs at most " + std::to_string(kMaxNodesStaged) +
                                    " nodes per particle");
-  k_precond_apply<<<h->geo.No, 1024, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
-                                                     with_active ? h->kr.active : nullptr, v, out);
+  // row segments per particle: about 1,024 blocks in all, at most 8 per particle
+  const int R = std::max(1, std::min({8, (1024 + h->geo.No - 1) / h->geo.No, h->geo.nmax}));
+  k_precond_apply<<<dim3(h->geo.No, R), 1024, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
+                                                              with_active ? h->kr.active : nullptr, R, v, out);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
