@@ -378,13 +378,16 @@ def bench_islands(args):
     series = []
     last = None
     for K in Ks:
-        t0 = time.perf_counter()
         wl = W.random_stars(K, 0.2, 1)
         N = int(np.sum(wl["n_nodes"]))
         s = spm.Solver("cuda:0", precision=spm.SPM_FP64, precond=spm.SPM_PRECOND_BLOCK, near_method=spm.SPM_NEAR_FMM)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         s.set_workload(wl)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
         st = s.fmm_stats()
-        log(f"[islands] K {K} N {N}: setup {time.perf_counter() - t0:.1f}s, FMM {st}")
+        log(f"[islands] K {K} N {N}: geometry set-up {setup_s:.3f}s, FMM {st}")
         for _ in range(args.warmup):
             r = s.solve()
         torch.cuda.synchronize()
@@ -410,7 +413,7 @@ def bench_islands(args):
         torch.cuda.synchronize()
         fmm_ms = e0.elapsed_time(e1) / 5
         mu_c = float(s.effective_viscosity_contour(r["sigma"])[0])
-        entry = {"K": K, "N": N, "fmm_levels": st["levels"], "fmm_order": st["order"],
+        entry = {"K": K, "N": N, "setup_s": setup_s, "fmm_levels": st["levels"], "fmm_order": st["order"],
                  "fmm_direct_pairs": st["p2p_pairs"], "fmm_m2l": st["m2l"], "solve_s": solve_s,
                  "iterations": infos[-1]["iterations"], "rel_residual": infos[-1]["rel_residual"],
                  "mu_eff": float(r["mu_eff"][0]), "mu_eff_contour": mu_c,

@@ -309,7 +309,8 @@ int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps
  * and keep the fastest. cache_path (may be NULL): text file of earlier results
  * keyed by device, node count, cell count, pair work and precision; a hit skips the
  * timing, a miss appends. best_ms_host [2] (may be NULL): the winning per-launch
- * time (0 on a cache hit). The shape stays until the node count changes. */
+ * time (0 on a cache hit). The shape stays until the node count changes. SPM_ESTATE on an
+ * SPM_NEAR_FMM handle, which plans no direct near-sum launches. */
 int spm_autotune(spm_handle* h, const char* cache_path, double* best_ms_host);
 
 /* Current near-sum launch shape {block, targets per lane, tile, source chunk} for

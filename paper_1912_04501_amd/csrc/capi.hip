@@ -400,6 +400,14 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   if (part_off[0] != 0 || n < 1) throw ApiError(SPM_EINVAL, "bad particle offsets");
   h->have_particles = false;
   drop_graphs(h);
+  double tmark = now();
+  auto mark = [&](const char* what) {      // set-up phase times with SPM_VERBOSE
+    if (!verbose()) return;
+    sync(h);
+    const double t = now();
+    std::fprintf(stderr, "[spm] set-up %s %.1f ms\n", what, 1e3 * (t - tmark));
+    tmark = t;
+  };
   h->cells.assign(C, CellHost());
   h->cx.resize(n);
   h->cy.resize(n);
@@ -503,7 +511,9 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   upload(h, g.cpoff, cpoff.data(), (C + 1) * sizeof(int32_t));
   upload(h, g.cskew, cskew.data(), C * sizeof(double));
   launch_geometry(h);
+  mark("geometry");
   build_periodizers(h);
+  mark("periodizers");
   // close pairs + overlap check
   CloseList& CL = h->cl;
   ensure(h, CL.count, N);
@@ -527,18 +537,24 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   ensure(h, CL.q, std::max<int64_t>(1, total));
   ensure(h, CL.s, std::max<int64_t>(1, total));
   if (total > 0) launch_close_fill(h);
+  mark("close pairs");
   build_chunks(h);
   alloc_krylov(h);
   alloc_learned(h);
   update_shapes(h);
+  mark("work arrays");
   if (h->wk.tuned && h->wk.tuned_N != N) h->wk.tuned = false;
   if (!h->wk.tuned) {
     h->wk.near[0].cfg = heuristic_near(h, SPM_FP64);
     h->wk.near[1].cfg = heuristic_near(h, SPM_FP32);
   }
-  build_near_plan(h, SPM_FP64);
-  build_near_plan(h, SPM_FP32);
-  if (h->cfg.near_method == SPM_NEAR_FMM) build_fmm_plan(h);
+  if (h->cfg.near_method == SPM_NEAR_FMM) {
+    build_fmm_plan(h);    // the direct kernels are not planned (their work lists grow like N^2)
+  } else {
+    build_near_plan(h, SPM_FP64);
+    build_near_plan(h, SPM_FP32);
+  }
+  mark("near-sum plans");
   sync(h);
   h->have_particles = true;
 }
@@ -1039,21 +1055,29 @@ void build_fmm_plan(spm_handle* h) {
     return (int64_t)iy * n + ix;
   };
   const int64_t ctr = 4 * N;   // shift index 4 is m = n = 0: the targets themselves
-  int bestL = 2;
+  // leaf level: bin once at the finest candidate level; every coarser tree is an aggregate of it
+  // (same root box). Candidates bracket about 60 image sources per leaf.
+  const int Lg = (int)std::lround(std::log((double)ns / 60.0) / std::log(4.0));
+  const int Llo = std::max(2, std::min(9, Lg - 1)), Lhi = std::min(10, std::max(Llo, Lg + 1));
+  std::vector<int64_t> bs_all, bt_all;
+  {
+    const int64_t nlh = (int64_t)1 << (2 * Lhi);
+    std::vector<int64_t> cs(nlh, 0), ct(nlh, 0);
+    for (int64_t k = 0; k < ns; ++k) cs[leaf_of(sx[k], sy[k], Lhi)]++;
+    for (int64_t j = 0; j < N; ++j) ct[leaf_of(sx[ctr + j], sy[ctr + j], Lhi)]++;
+    bs_all = fmm_levels(cs, Lhi);
+    bt_all = fmm_levels(ct, Lhi);
+  }
+  int bestL = Llo;
   double best = 1e300, best_p2p = 0, best_m2l = 0;
-  for (int L = 2; L <= 10; ++L) {
-    std::vector<int64_t> cs((int64_t)1 << (2 * L), 0), ct((int64_t)1 << (2 * L), 0);
-    for (int64_t k = 0; k < ns; ++k) cs[leaf_of(sx[k], sy[k], L)]++;
-    for (int64_t j = 0; j < N; ++j) ct[leaf_of(sx[ctr + j], sy[ctr + j], L)]++;
-    const auto w = fmm_work(fmm_levels(cs, L), fmm_levels(ct, L), L);
+  for (int L = Llo; L <= Lhi; ++L) {
+    const auto w = fmm_work(bs_all, bt_all, L);
     const double cost = 25.0 * w.first + 12.0 * p * p * w.second;
     if (cost < best) {
       best = cost;
       bestL = L;
       best_p2p = w.first;
       best_m2l = w.second;
-    } else if (L > bestL + 1) {
-      break;
     }
   }
   const int L = bestL;
@@ -1128,6 +1152,7 @@ void build_fmm_plan(spm_handle* h) {
   ensure(h, F.Lx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.nsplit1, 1);
   ensure(h, F.vnear, 3 * (size_t)g.No);
+  ensure(h, h->wk.Tpart, 2 * (size_t)N);
   upload(h, F.sx, ssx.data(), ns * sizeof(double));
   upload(h, F.sy, ssy.data(), ns * sizeof(double));
   upload(h, F.sj, ssj.data(), ns * sizeof(int32_t));
@@ -1627,6 +1652,7 @@ int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps
 int spm_autotune(spm_handle* h, const char* cache_path, double* best_ms_host) {
   return guarded(h, [&]() {
     need_particles(h);
+    if (h->fmm.on) throw ApiError(SPM_ESTATE, "the FMM near sum has no direct launch shapes to tune");
     autotune(h, cache_path, best_ms_host);
     sync(h);
     return SPM_OK;
@@ -1657,7 +1683,7 @@ int spm_set_launch(spm_handle* h, int32_t precision, const int32_t* cfg_host) {
     c.chunk = cfg_host[3];
     if (!near_config_valid(c)) throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
     h->wk.near[precision == SPM_FP64 ? 0 : 1].cfg = c;
-    build_near_plan(h, precision);
+    if (!h->fmm.on) build_near_plan(h, precision);   // an FMM handle only keeps the shape
     h->wk.tuned = true;
     h->wk.tuned_N = h->geo.N;
     return SPM_OK;

@@ -166,3 +166,6 @@ def test_fmm_arguments():
     with pytest.raises(spm.SpmError) as err:
         spm.Solver("cuda:0").set_workload(wl).fmm_stats()
     assert err.value.code == spm.SPM_ESTATE
+    with pytest.raises(spm.SpmError) as err:
+        _fmm(wl).autotune()
+    assert err.value.code == spm.SPM_ESTATE
