@@ -38,6 +38,11 @@ __device__ __forceinline__ cx operator-(cx a, cx b) { return {a.r - b.r, a.i - b
 __device__ __forceinline__ cx operator*(cx a, cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
 __device__ __forceinline__ cx operator*(cx a, double s) { return {a.r * s, a.i * s}; }
 __device__ __forceinline__ cx conj(cx a) { return {a.r, -a.i}; }
+// acc + a b and acc + a s with fused multiply-adds (the library builds without contraction)
+__device__ __forceinline__ cx cmac(cx acc, cx a, cx b) {
+  return {fma(a.r, b.r, fma(-a.i, b.i, acc.r)), fma(a.r, b.i, fma(a.i, b.r, acc.i))};
+}
+__device__ __forceinline__ cx cmac(cx acc, cx a, double s) { return {fma(a.r, s, acc.r), fma(a.i, s, acc.i)}; }
 __device__ __forceinline__ cx cdiv(cx a, cx b) {
   const double d = b.r * b.r + b.i * b.i;
   return {(a.r * b.r + a.i * b.i) / d, (a.i * b.r - a.r * b.i) / d};
@@ -66,7 +71,7 @@ struct FmmArgs {
 __device__ __forceinline__ cx box_center(const FmmArgs& a, int l, int64_t loc) {
   const int n = 1 << l;
   const double h = a.D0 / n;
-  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> l);
   return {a.c0x - 0.5 * a.D0 + (ix + 0.5) * h, a.c0y - 0.5 * a.D0 + (iy + 0.5) * h};
 }
 
@@ -121,8 +126,8 @@ __global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __rest
         const cx q = qs[t];
         const cx qw = q * wk;
         A = A + qw;
-        B = B + conj(q) * wk;
-        C = C + qw * ds[t];
+        B = cmac(B, conj(q), wk);
+        C = cmac(C, qw, ds[t]);
       }
     }
     __syncthreads();
@@ -135,50 +140,52 @@ __global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __rest
   }
 }
 
-// multipoles of level l from their children at level l + 1
+// multipoles of level l from their children at level l + 1; the four children are staged in LDS
+// in one phase (their loads overlap)
 __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t* __restrict__ list) {
-  __shared__ cx ac[3][64];
-  __shared__ cx tp[64];
+  __shared__ cx ac[4][3][64];
+  __shared__ cx tp[4][64];
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(l);
   const int n = 1 << l;
-  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> l);
   const cx c = box_center(a, l, loc);
   const double ihP = (double)n / a.D0;
   const int k = threadIdx.x, p = a.p;
-  cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
+  bool has[4];
+  cx dch[4];
   for (int ch = 0; ch < 4; ++ch) {
     const int64_t cloc = (int64_t)(2 * iy + (ch >> 1)) * (2 * n) + (2 * ix + (ch & 1));
     const int64_t cgid = box_off(l + 1) + cloc;
-    if (a.bsrc[cgid] == 0) continue;     // the same for every lane
-    const cx cc = box_center(a, l + 1, cloc);
-    const cx d = cc - c;
-    __syncthreads();
-    if (k < p) {
+    has[ch] = a.bsrc[cgid] != 0;
+    dch[ch] = box_center(a, l + 1, cloc) - c;
+    if (has[ch] && k < p) {
       const cx* m = a.Mx + cgid * 3 * p;
-      const double s = ldexp(1.0, -k) / a.fact[k];
-      ac[0][k] = m[k] * s;
-      ac[1][k] = m[p + k] * s;
-      ac[2][k] = m[2 * p + k] * s;
-      tp[k] = cpow(d * ihP, k) * (1.0 / a.fact[k]);
+      const double sc = ldexp(1.0, -k) / a.fact[k];
+      ac[ch][0][k] = m[k] * sc;
+      ac[ch][1][k] = m[p + k] * sc;
+      ac[ch][2][k] = m[2 * p + k] * sc;
+      tp[ch][k] = cpow(dch[ch] * ihP, k) * (1.0 / a.fact[k]);
     }
-    __syncthreads();
-    if (k < p) {
+  }
+  __syncthreads();
+  if (k < p) {
+    cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
+    const double fk = a.fact[k];
+    for (int ch = 0; ch < 4; ++ch) {
+      if (!has[ch]) continue;
       cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
       for (int m = 0; m <= k; ++m) {
-        const cx t = tp[k - m];
-        sA = sA + ac[0][m] * t;
-        sB = sB + ac[1][m] * t;
-        sC = sC + ac[2][m] * t;
+        const cx t = tp[ch][k - m];
+        sA = cmac(sA, ac[ch][0][m], t);
+        sB = cmac(sB, ac[ch][1][m], t);
+        sC = cmac(sC, ac[ch][2][m], t);
       }
-      const double fk = a.fact[k];
       sA = sA * fk;
       oA = oA + sA;
       oB = oB + sB * fk;
-      oC = oC + sC * fk + conj(d) * sA;
+      oC = oC + sC * fk + conj(dch[ch]) * sA;
     }
-  }
-  if (k < p) {
     cx* out = a.Mx + gid * 3 * p;
     out[k] = oA;
     out[p + k] = oB;
@@ -186,55 +193,79 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
   }
 }
 
-// local expansions from the interaction lists, every level in one launch (written, not added)
+// local expansions from the interaction lists, every level in one launch (written, not added).
+// The list (at most 27 source boxes with sources) is formed first; the next box's multipole is
+// loaded into registers while the current one is summed.
 __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __restrict__ list) {
   __shared__ cx bs[3][64];
+  __shared__ double fs[128];
+  __shared__ int64_t srcs[27];
+  __shared__ int nsrc;
   const int64_t gid = list[blockIdx.x];
   int l = 2;
   while (l < a.L && gid >= box_off(l + 1)) ++l;
   const int64_t loc = gid - box_off(l);
   const int n = 1 << l;
-  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> l);
   const cx c = box_center(a, l, loc);
   const double h = a.D0 / n;
   const int k = threadIdx.x, p = a.p;
-  const int px = ix >> 1, py = iy >> 1, np = n >> 1;
+  for (int i = k; i < 2 * p; i += 64) fs[i] = a.fact[i];
+  if (k == 0) {
+    const int px = ix >> 1, py = iy >> 1, np = n >> 1;
+    int cnt = 0;
+    for (int qy = max(py - 1, 0); qy <= min(py + 1, np - 1); ++qy)
+      for (int qx = max(px - 1, 0); qx <= min(px + 1, np - 1); ++qx)
+        for (int ch = 0; ch < 4; ++ch) {
+          const int bx = 2 * qx + (ch & 1), by = 2 * qy + (ch >> 1);
+          if (abs(bx - ix) <= 1 && abs(by - iy) <= 1) continue;
+          const int64_t sloc = (int64_t)by * n + bx;
+          if (a.bsrc[box_off(l) + sloc] != 0) srcs[cnt++] = sloc;
+        }
+    nsrc = cnt;
+  }
+  __syncthreads();
+  const int ns = nsrc;
   cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
-  for (int qy = max(py - 1, 0); qy <= min(py + 1, np - 1); ++qy) {
-    for (int qx = max(px - 1, 0); qx <= min(px + 1, np - 1); ++qx) {
-      for (int ch = 0; ch < 4; ++ch) {
-        const int bx = 2 * qx + (ch & 1), by = 2 * qy + (ch >> 1);
-        if (abs(bx - ix) <= 1 && abs(by - iy) <= 1) continue;
-        const int64_t sloc = (int64_t)by * n + bx;
-        const int64_t sgid = box_off(l) + sloc;
-        if (a.bsrc[sgid] == 0) continue;
-        const cx cs = box_center(a, l, sloc);
-        const cx rho = cdiv({h, 0.0}, c - cs);
-        __syncthreads();
-        const cx rk = cpow(rho, k);
-        if (k < p) {
-          const cx* m = a.Mx + sgid * 3 * p;
-          const cx s = rk * (1.0 / a.fact[k]);
-          bs[0][k] = m[k] * s;
-          bs[1][k] = m[p + k] * s;
-          bs[2][k] = m[2 * p + k] * s;
-        }
-        __syncthreads();
-        if (k < p) {
-          cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
-          for (int m = 0; m < p; ++m) {
-            const double fm = a.fact[m + k];
-            sA = sA + bs[0][m] * fm;
-            sB = sB + bs[1][m] * fm;
-            sC = sC + bs[2][m] * fm;
-          }
-          const cx g = rk * rho * (((k & 1) ? -1.0 : 1.0) / (h * a.fact[k]));
-          sA = sA * g;
-          oA = oA + sA;
-          oB = oB + sB * g;
-          oC = oC + sC * g + conj(cs - c) * sA;
-        }
+  cx nA = {0, 0}, nB = {0, 0}, nC = {0, 0};
+  if (ns > 0 && k < p) {
+    const cx* m = a.Mx + (box_off(l) + srcs[0]) * 3 * p;
+    nA = m[k];
+    nB = m[p + k];
+    nC = m[2 * p + k];
+  }
+  for (int i = 0; i < ns; ++i) {
+    const int64_t sloc = srcs[i];
+    const cx cs = box_center(a, l, sloc);
+    const cx rho = cdiv({h, 0.0}, c - cs);
+    const cx rk = cpow(rho, k);
+    __syncthreads();                       // the previous box's sums are done with bs
+    if (k < p) {
+      const cx sc = rk * (1.0 / fs[k]);
+      bs[0][k] = nA * sc;
+      bs[1][k] = nB * sc;
+      bs[2][k] = nC * sc;
+    }
+    __syncthreads();
+    if (i + 1 < ns && k < p) {             // prefetch the next box's multipole
+      const cx* m = a.Mx + (box_off(l) + srcs[i + 1]) * 3 * p;
+      nA = m[k];
+      nB = m[p + k];
+      nC = m[2 * p + k];
+    }
+    if (k < p) {
+      cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
+      for (int m = 0; m < p; ++m) {
+        const double fm = fs[m + k];
+        sA = cmac(sA, bs[0][m], fm);
+        sB = cmac(sB, bs[1][m], fm);
+        sC = cmac(sC, bs[2][m], fm);
       }
+      const cx g = rk * rho * (((k & 1) ? -1.0 : 1.0) / (h * fs[k]));
+      sA = sA * g;
+      oA = oA + sA;
+      oB = oB + sB * g;
+      oC = oC + sC * g + conj(cs - c) * sA;
     }
   }
   if (k < p) {
@@ -252,7 +283,7 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(FmmArgs a, int l, const int32_t*
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(l);
   const int n = 1 << l;
-  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> l);
   const cx c = box_center(a, l, loc);
   const int64_t ploc = (int64_t)(iy >> 1) * (n >> 1) + (ix >> 1);
   const int64_t pgid = box_off(l - 1) + ploc;
@@ -273,9 +304,9 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(FmmArgs a, int l, const int32_t*
     cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
     for (int j = k; j < p; ++j) {
       const cx t = tp[j - k];
-      sA = sA + al[0][j] * t;
-      sB = sB + al[1][j] * t;
-      sC = sC + al[2][j] * t;
+      sA = cmac(sA, al[0][j], t);
+      sB = cmac(sB, al[1][j], t);
+      sC = cmac(sC, al[2][j], t);
     }
     const double s = ldexp(1.0, -k) / a.fact[k];
     sA = sA * s;
@@ -298,7 +329,7 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(a.L);
   const int n = 1 << a.L;
-  const int ix = (int)(loc % n), iy = (int)(loc / n);
+  const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> a.L);
   const cx c = box_center(a, a.L, loc);
   const double h = a.D0 / n;
   const cx* Le = a.Lx + gid * 3 * a.p;
@@ -331,10 +362,10 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
           for (int q = r; q < m; q += S) {
             const double rx = x - shx[q], ry = y - shy[q];
             // the target's own node (r = 0): the floor keeps 1/|r|^2 finite and (r.n)(r.f) = 0
-            const double ir2 = rcp64(fmax(rx * rx + ry * ry, 1e-300));
-            const double cf = (((rx * nx + ry * ny) * (rx * sf1[q] + ry * sf2[q])) * ir2) * ir2;
-            d1 += cf * rx;
-            d2 += cf * ry;
+            const double ir2 = rcp64(fmax(fma(rx, rx, ry * ry), 1e-300));
+            const double cf = ((fma(rx, nx, ry * ny) * fma(rx, sf1[q], ry * sf2[q])) * ir2) * ir2;
+            d1 = fma(cf, rx, d1);
+            d2 = fma(cf, ry, d2);
           }
         }
       }
@@ -353,13 +384,13 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
       const cx u = dz * (1.0 / h);
       cx A = {0, 0}, B = {0, 0}, Ad = {0, 0}, Cd = {0, 0};
       for (int k = p - 1; k >= 1; --k) {
-        A = A * u + Le[k];
-        B = B * u + Le[p + k];
-        Ad = Ad * u + Le[k] * (double)k;
-        Cd = Cd * u + Le[2 * p + k] * (double)k;
+        A = cmac(Le[k], A, u);
+        B = cmac(Le[p + k], B, u);
+        Ad = cmac(Le[k] * (double)k, Ad, u);
+        Cd = cmac(Le[2 * p + k] * (double)k, Cd, u);
       }
-      A = A * u + Le[0];
-      B = B * u + Le[p];
+      A = cmac(Le[0], A, u);
+      B = cmac(Le[p], B, u);
       const cx E = (Cd - conj(dz) * Ad) * (1.0 / h);
       const cx BE = B + E;
       const double k4 = -1.0 / (4.0 * kPi);
