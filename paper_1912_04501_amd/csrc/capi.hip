@@ -537,6 +537,8 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   ensure(h, CL.q, std::max<int64_t>(1, total));
   ensure(h, CL.s, std::max<int64_t>(1, total));
   if (total > 0) launch_close_fill(h);
+  ensure(h, CL.qsrc, (size_t)h->geo.No);
+  launch_close_sources(h);
   mark("close pairs");
   build_chunks(h);
   alloc_krylov(h);
@@ -577,7 +579,7 @@ void matvec(spm_handle* h, const double* sigma, double* out, int precision, bool
     launch_near_impl(h, precision, with_active);
   launch_combine(h, sigma, true, precision);
   if (h->cl.ntargets > 0) {
-    launch_vplus(h, sigma);
+    launch_vplus(h, sigma, false);
     launch_close_apply_impl(h, h->wk.T, precision, with_active);
   }
   if (precision == SPM_FP32) launch_self_fix(h, h->wk.T, with_active);
@@ -1502,7 +1504,7 @@ int spm_eval_field(spm_handle* h, const double* sigma, int64_t n_targets, const 
     ensure(h, F.om, (size_t)h->geo.No);
     stage_xi(h, sigma, false);              // f = w sigma, net forces, proxy strengths
     launch_velocities(h, F.vel, F.om);      // rigid motions and the velocity gauge
-    launch_vplus(h, sigma);                 // boundary values of the Cauchy integrals
+    launch_vplus(h, sigma, true);           // boundary values of the Cauchy integrals
     launch_field(h, n_targets, xt, yt, u, p);
     sync(h);
     return SPM_OK;
@@ -1577,7 +1579,7 @@ int spm_close_correction(spm_handle* h, const double* sigma, double* out, int32_
     launch_prep(h, sigma);
     gm_zero(h, out, 2 * h->geo.N);
     if (h->cl.ntargets > 0) {
-      launch_vplus(h, sigma);
+      launch_vplus(h, sigma, false);
       launch_close_apply(h, sigma, out, precision);
     }
     if (precision == SPM_FP32) launch_self_fix(h, out, false);

@@ -224,6 +224,27 @@ void launch_close_fill(spm_handle* h) {
   SPM_HIP_CHECK(hipGetLastError());
 }
 
+// flags of the particles that are the source of at least one close pair
+__global__ void k_close_sources(int32_t No, int64_t npairs, const int32_t* __restrict__ q, int32_t* __restrict__ flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < No) flag[i] = 0;
+}
+__global__ void k_close_sources_mark(int64_t npairs, const int32_t* __restrict__ q, int32_t* __restrict__ flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < npairs) flag[q[i]] = 1;   // every writer stores the same value
+}
+
+void launch_close_sources(spm_handle* h) {
+  const int32_t No = h->geo.No;
+  k_close_sources<<<(unsigned)((No + 255) / 256), 256, 0, h->stream>>>(No, h->cl.npairs, h->cl.q, h->cl.qsrc);
+  SPM_HIP_CHECK(hipGetLastError());
+  if (h->cl.npairs > 0) {
+    k_close_sources_mark<<<(unsigned)((h->cl.npairs + 255) / 256), 256, 0, h->stream>>>(h->cl.npairs, h->cl.q,
+                                                                                       h->cl.qsrc);
+    SPM_HIP_CHECK(hipGetLastError());
+  }
+}
+
 // min over nodes of dmin, max of inside, one block
 __global__ void k_gap_reduce(int64_t N, const double* __restrict__ dmin, const int32_t* __restrict__ inside,
                              double* out) {

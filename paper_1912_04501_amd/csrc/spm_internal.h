@@ -271,6 +271,7 @@ struct CloseList {
   double* dmin = nullptr;     // [N] min node distance to other particles (gap estimate)
   int32_t* inside = nullptr;  // [N] 1 if the node lies inside another particle
   double* vp = nullptr;       // [6 N] v+ of the three densities: re0 im0 re1 im1 re2 im2 (each N)
+  int32_t* qsrc = nullptr;    // [No] 1 if the particle is the source of a close pair (the operator needs its v+)
 };
 
 // Launch shape of the near sum: block threads, targets per lane, sources per LDS
@@ -534,7 +535,8 @@ void launch_pinv(spm_handle* h);
 void launch_close_count(spm_handle* h);
 void launch_close_scan(spm_handle* h, int32_t* total_host, int32_t* ntargets_host);
 void launch_close_fill(spm_handle* h);
-void launch_vplus(spm_handle* h, const double* sigma);
+void launch_vplus(spm_handle* h, const double* sigma, bool all_particles);
+void launch_close_sources(spm_handle* h);
 void launch_close_apply(spm_handle* h, const double* sigma, double* T, int precision);
 void launch_self_fix(spm_handle* h, double* T, bool with_active);
 void launch_assemble(spm_handle* h, const double* sigma, double* out);
