@@ -28,7 +28,11 @@ Map of the method (citations are to the paper's sections and equations):
                    (Sec. 5 eq. BIEPerturbed, Sec. 6.2 pressure-correction remark),
                    dense assembly, LU and GMRES
 * ``readout``    - particle velocities, angular velocities, effective viscosity
-                   (Sec. 3 eq. RigidBodyMotion and eq. mueff)
+                   (Sec. 3 eq. RigidBodyMotion and eq. mueff), also by contour
+                   deformation (Sec. 7, re-derived for the 3x3 near set)
+* ``field``      - flow velocity and pressure at points of the fluid (Sec. 3,
+                   Sec. 5 representations), near curves by a refined trapezoid rule
+* ``dilated``    - the paper's own per-node near set in the dilated cell (Sec. 4.2)
 * ``step``       - forward Euler time stepping (Sec. 7)
 * ``precond``    - isolated-body self blocks of the completed operator and the
                    block-diagonal right preconditioner built from them
