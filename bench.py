@@ -413,13 +413,23 @@ def bench_islands(args):
         torch.cuda.synchronize()
         fmm_ms = e0.elapsed_time(e1) / 5
         mu_c = float(s.effective_viscosity_contour(r["sigma"])[0])
+        # flow field on a 100 x 100 grid over the cell (velocity and pressure)
+        g1 = np.linspace(-0.5, 0.5, 100, endpoint=False) + 0.005
+        grid = np.stack(np.meshgrid(g1, g1), axis=-1).reshape(-1, 2)
+        s.eval_field(r["sigma"], grid)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.eval_field(r["sigma"], grid)
+        torch.cuda.synchronize()
+        field_s = time.perf_counter() - t1
         entry = {"K": K, "N": N, "setup_s": setup_s, "fmm_levels": st["levels"], "fmm_order": st["order"],
                  "fmm_direct_pairs": st["p2p_pairs"], "fmm_m2l": st["m2l"], "solve_s": solve_s,
                  "iterations": infos[-1]["iterations"], "rel_residual": infos[-1]["rel_residual"],
                  "mu_eff": float(r["mu_eff"][0]), "mu_eff_contour": mu_c,
                  "fmm_near_sum_ms": fmm_ms,
                  "fmm_eval_kernel_ms": ev[2]["ms"] / max(ev[2]["launches"], 1),
-                 "fmm_m2l_kernel_ms": ev[3]["ms"] / max(ev[3]["launches"], 1)}
+                 "fmm_m2l_kernel_ms": ev[3]["ms"] / max(ev[3]["launches"], 1),
+                 "field_grid_100x100_s": field_s}
         s.close()
         d = spm.Solver("cuda:0", precision=spm.SPM_FP32_IR, precond=spm.SPM_PRECOND_BLOCK)
         d.set_workload(wl)
@@ -439,6 +449,12 @@ def bench_islands(args):
             entry["direct_fp32_ir_precond_solve_s"] = time.perf_counter() - t1
             entry["direct_iterations"] = rd["info"]["iterations"]
             entry["direct_mu_eff"] = float(rd["mu_eff"][0])
+            d.eval_field(rd["sigma"], grid)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            d.eval_field(rd["sigma"], grid)
+            torch.cuda.synchronize()
+            entry["direct_field_grid_100x100_s"] = time.perf_counter() - t1
         d.close()
         log(f"[islands] {entry}")
         series.append(entry)

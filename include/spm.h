@@ -201,7 +201,9 @@ int spm_velocities(spm_handle* h, const double* sigma, double* vel, double* omeg
  * pressure of the representation (defined up to one constant), NaN inside particles,
  * where u is the particle's rigid motion. Points within close_factor * h of a curve use
  * the Laplace decomposition of the single layer with the barycentric rule of Sec. 6.3
- * (no slip is met to the discretisation error however close). Single-cell handles;
+ * (no slip is met to the discretisation error however close). With SPM_NEAR_FMM the
+ * near-image sums at the points (and at the particle centres for the readout) come from
+ * the FMM's quadtree instead of a direct sum over all images. Single-cell handles;
  * 0 <= n_targets <= 2^28. */
 int spm_eval_field(spm_handle* h, const double* sigma, int64_t n_targets, const double* xt, const double* yt,
                    double* u, double* p);

@@ -124,6 +124,7 @@ struct FieldArgs {
   int M;
   const double *vel, *om, *gauge;
   double mu, gamma, cUx, cUy, close_factor;
+  int plain_given;            // u, p already hold the near-image plain sums (FMM tree walk)
   double *u, *p;
 };
 
@@ -180,7 +181,12 @@ __global__ __launch_bounds__(256) void k_field(FieldArgs A) {
   }
   // near images (plain rule) and the proxy correction
   double u1 = 0, u2 = 0, pr = 0;
-  for (int64_t j = lane; j < A.N; j += 64) {
+  if (A.plain_given && lane == 0) {
+    u1 = A.u[t];
+    u2 = A.u[A.nt + t];
+    pr = A.p[t];
+  }
+  for (int64_t j = A.plain_given ? A.N : lane; j < A.N; j += 64) {
     const double yx = g.x[j], yy = g.y[j], a = A.f1[j], b = A.f2[j];
     for (int s = 0; s < kShifts; ++s)
       stokeslet_up(xw - (yx + shift_x(s, skew)), yw - (yy + shift_y(s)), a, b, k4, u1, u2, pr);
@@ -312,6 +318,11 @@ void launch_field(spm_handle* h, int64_t n_targets, const double* xt, const doub
   A.close_factor = h->cfg.close_factor;
   A.u = u;
   A.p = p;
+  A.plain_given = 0;
+  if (h->fmm.on) {           // near-image plain sums by the FMM's tree walk
+    launch_fmm_points(h, n_targets, xt, yt, u, p);
+    A.plain_given = 1;
+  }
   const int64_t blocks = (n_targets * 64 + 255) / 256;
   k_field<<<(unsigned)blocks, 256, 0, h->stream>>>(A);
   SPM_HIP_CHECK(hipGetLastError());

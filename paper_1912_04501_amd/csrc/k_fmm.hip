@@ -408,10 +408,14 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
 // so a box contributes -(1/2)(Phi + conj(Psi)) with Phi = sum f log r, Psi = sum conj(f) log r
 // (log multipoles built from the same power sums as A and B), F_box / 2, and
 // conj((conj(z) - conj(c)) A - C_c) / 2; the vorticity is -(1/2pi mu) Im A.
-__global__ __launch_bounds__(64) void k_fmm_velocities(FmmArgs a, Geo g, double mu, double* __restrict__ near3) {
-  const int q = blockIdx.x;
-  const int k = threadIdx.x, p = a.p;
-  const double zx = g.pcx[q], zy = g.pcy[q];
+// Per-lane partial sums of the near-image velocity, vorticity and pressure (G^p of eq. Gp:
+// (r.f) / (2 pi |r|^2) = Re(f / r) / (2 pi), so the boxes contribute Re A / (2 pi)) at the point z
+// (inside the root box); the caller sums the lanes.
+struct Pt4 {
+  double u1, u2, vo, pr;
+};
+__device__ Pt4 fmm_point(const FmmArgs& a, double zx, double zy, double mu) {
+  const int k = threadIdx.x & 63, p = a.p;
   const int nL = 1 << a.L;
   const int ixL = min(max((int)floor((zx - (a.c0x - 0.5 * a.D0)) / a.D0 * nL), 0), nL - 1);
   const int iyL = min(max((int)floor((zy - (a.c0y - 0.5 * a.D0)) / a.D0 * nL), 0), nL - 1);
@@ -451,9 +455,11 @@ __global__ __launch_bounds__(64) void k_fmm_velocities(FmmArgs a, Geo g, double 
     }
   }
   const double k4 = 1.0 / (4.0 * kPi * mu), k2 = -1.0 / (2.0 * kPi * mu);
-  double u1 = k4 * (-sLog.r + 0.5 * sF.r + 0.5 * sE.r);
-  double u2 = k4 * (-sLog.i + 0.5 * sF.i - 0.5 * sE.i);
-  double vo = k2 * sA.i;
+  Pt4 o;
+  o.u1 = k4 * (-sLog.r + 0.5 * sF.r + 0.5 * sE.r);
+  o.u2 = k4 * (-sLog.i + 0.5 * sF.i - 0.5 * sE.i);
+  o.vo = k2 * sA.i;
+  o.pr = sA.r * (0.5 / kPi);
   for (int jy = max(iyL - 1, 0); jy <= min(iyL + 1, nL - 1); ++jy) {
     const int32_t r0 = a.leaf_s[(int64_t)jy * nL + max(ixL - 1, 0)];
     const int32_t r1 = a.leaf_s[(int64_t)jy * nL + min(ixL + 1, nL - 1) + 1];
@@ -463,18 +469,48 @@ __global__ __launch_bounds__(64) void k_fmm_velocities(FmmArgs a, Geo g, double 
       const double ir2 = rcp64(r2);
       const double lg = -0.5 * log(r2);
       const double rf = (rx * fa + ry * fb) * ir2;
-      u1 += k4 * (lg * fa + rx * rf);
-      u2 += k4 * (lg * fb + ry * rf);
-      vo += k2 * (rx * fb - ry * fa) * ir2;
+      o.u1 += k4 * (lg * fa + rx * rf);
+      o.u2 += k4 * (lg * fb + ry * rf);
+      o.vo += k2 * (rx * fb - ry * fa) * ir2;
+      o.pr += rf * (0.5 / kPi);
     }
   }
-  u1 = wave_sum(u1);
-  u2 = wave_sum(u2);
-  vo = wave_sum(vo);
-  if (k == 0) {
-    near3[3 * q] = u1;
-    near3[3 * q + 1] = u2;
-    near3[3 * q + 2] = vo;
+  return o;
+}
+
+__global__ __launch_bounds__(64) void k_fmm_velocities(FmmArgs a, Geo g, double mu, double* __restrict__ near3) {
+  const int q = blockIdx.x;
+  Pt4 o = fmm_point(a, g.pcx[q], g.pcy[q], mu);
+  o.u1 = wave_sum(o.u1);
+  o.u2 = wave_sum(o.u2);
+  o.vo = wave_sum(o.vo);
+  if (threadIdx.x == 0) {
+    near3[3 * q] = o.u1;
+    near3[3 * q + 1] = o.u2;
+    near3[3 * q + 2] = o.vo;
+  }
+}
+
+// Near-image velocity and pressure at field points (one wavefront each), at the point's periodic
+// copy in U computed exactly as the field kernel computes it: u [2 nt] and p [nt] receive them
+// and the field kernel adds the rest.
+__global__ __launch_bounds__(64) void k_fmm_points(FmmArgs a, Geo g, double mu, double cUx, double cUy, int64_t nt,
+                                                   const double* __restrict__ xt, const double* __restrict__ yt,
+                                                   double* __restrict__ u, double* __restrict__ p) {
+  const int64_t t = blockIdx.x;
+  const double skew = g.cskew[0];
+  const double x = xt[t], y = yt[t];
+  const double be = y - cUy, al = (x - cUx) - skew * be;
+  const double ka = floor(al + 0.5), kb = floor(be + 0.5);
+  const double xw = x - ka - kb * skew, yw = y - kb;
+  Pt4 o = fmm_point(a, xw, yw, mu);
+  o.u1 = wave_sum(o.u1);
+  o.u2 = wave_sum(o.u2);
+  o.pr = wave_sum(o.pr);
+  if (threadIdx.x == 0) {
+    u[t] = o.u1;
+    u[nt + t] = o.u2;
+    p[t] = o.pr;
   }
 }
 
@@ -543,6 +579,12 @@ int launch_fmm_upward(spm_handle* h) {
 }
 
 }  // namespace
+
+void launch_fmm_points(spm_handle* h, int64_t nt, const double* xt, const double* yt, double* u, double* p) {
+  launch_fmm_upward(h);
+  k_fmm_points<<<(unsigned)nt, 64, 0, h->stream>>>(args(h), h->geo, h->cfg.mu, h->cU[0], h->cU[1], nt, xt, yt, u, p);
+  SPM_HIP_CHECK(hipGetLastError());
+}
 
 void launch_fmm_velocities(spm_handle* h, double* near3) {
   launch_fmm_upward(h);

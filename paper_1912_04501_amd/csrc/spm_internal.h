@@ -547,6 +547,7 @@ void launch_mu_eff_contour(spm_handle* h, int m, double* mu_eff);
 void build_fmm_plan(spm_handle* h);
 void launch_fmm(spm_handle* h, double* out);
 void launch_fmm_velocities(spm_handle* h, double* near3);
+void launch_fmm_points(spm_handle* h, int64_t nt, const double* xt, const double* yt, double* u, double* p);
 void launch_gap(spm_handle* h, double* gap_host, int32_t* overlap_host);
 
 // GMRES building blocks (k_gmres.hip); per cell, cells in lockstep
