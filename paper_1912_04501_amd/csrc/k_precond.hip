@@ -156,25 +156,26 @@ __global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* 
 }
 
 // Blocks (particle, row segment): out = R (B^-1 (R^T v)) on the particle's nodes, segment y
-// producing nodes [y nk, (y + 1) nk) (rows k and n + k of the 2n x 2n inverse, nk = ceil(n / R)),
-// so that small particle counts still spread over the chip. Particles of inactive cells are
-// skipped when active is given. The inverse is column-major: the block's rows form two contiguous
-// ranges, split into S = blockDim / (2 nk) column groups whose lanes run over consecutive rows, so
-// every load is contiguous; the S partial rows are summed in a fixed order.
+// producing nodes [y nk, (y + 1) nk) (rows k and n + k of the 2n x 2n inverse, nk = ceil(n / R)
+// rounded up to even), so that small particle counts still spread over the chip. Particles of
+// inactive cells are skipped when active is given. The inverse is column-major and n is even, so
+// the block's rows form two contiguous ranges of even length read as pairs (8-byte loads); they are
+// split into S = blockDim / nk column groups whose lanes run over consecutive row pairs. The S
+// partial rows are summed in a fixed order.
 __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __restrict__ pshape,
                                                         const int64_t* __restrict__ ioff,
                                                         const float* __restrict__ inv,
                                                         const int32_t* __restrict__ active, int R,
                                                         const double* __restrict__ v, double* __restrict__ out) {
   __shared__ double vb[2 * kMaxNodesStaged];
-  __shared__ double part[1024];
+  __shared__ double part[2048];
   const int q = blockIdx.x;
   if (active && active[g.pcell[q]] == 0) return;
   const int n = g.pn[q], m = 2 * n;
-  const int nk = (n + R - 1) / R;
+  const int nk = 2 * ((n + 2 * R - 1) / (2 * R));
   const int k0 = blockIdx.y * nk;
   if (k0 >= n) return;
-  const int kn = min(nk, n - k0);
+  const int kn = min(nk, n - k0);            // even: n and k0 are
   const int64_t i0 = g.poff[q], N = g.N;
   double st, ct;
   sincos(g.pth[q], &st, &ct);
@@ -184,23 +185,29 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
     vb[n + k] = -st * a + ct * b;
   }
   __syncthreads();
-  const float* M = inv + ioff[pshape[q]];
-  const int rows = 2 * nk;
-  const int S = max(1, (int)blockDim.x / rows);
-  const int grp = threadIdx.x / rows, rr = threadIdx.x % rows;
-  const int lk = rr < nk ? rr : rr - nk;                // node within the segment
+  const float2* M2 = reinterpret_cast<const float2*>(inv + ioff[pshape[q]]);
+  const int pairs = nk;                      // row pairs of the block: nk / 2 per range, two ranges
+  const int S = max(1, (int)blockDim.x / pairs);
+  const int grp = threadIdx.x / pairs, rp = threadIdx.x % pairs;
+  const int half = nk / 2;
+  const int lk = 2 * (rp < half ? rp : rp - half);   // first node of the pair within the segment
   if (grp < S && lk < kn) {
-    const int r = (rr < nk ? 0 : n) + k0 + lk;          // row of the inverse
-    double acc = 0.0;
-    for (int c = grp; c < m; c += S) acc += (double)M[(int64_t)c * m + r] * vb[c];
-    part[grp * rows + rr] = acc;
+    const int r = (rp < half ? 0 : n) + k0 + lk;       // even row of the inverse
+    double a0 = 0.0, a1 = 0.0;
+    for (int c = grp; c < m; c += S) {
+      const float2 w = M2[((int64_t)c * m + r) >> 1];
+      a0 = fma((double)w.x, vb[c], a0);
+      a1 = fma((double)w.y, vb[c], a1);
+    }
+    part[grp * 2 * pairs + 2 * rp] = a0;
+    part[grp * 2 * pairs + 2 * rp + 1] = a1;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < kn; k += blockDim.x) {
     double a = 0.0, b = 0.0;
     for (int s = 0; s < S; ++s) {
-      a += part[s * rows + k];
-      b += part[s * rows + nk + k];
+      a += part[s * 2 * pairs + k];
+      b += part[s * 2 * pairs + nk + k];
     }
     out[i0 + k0 + k] = ct * a - st * b;
     out[N + i0 + k0 + k] = st * a + ct * b;
