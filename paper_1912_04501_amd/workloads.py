@@ -14,7 +14,7 @@ A workload is a dict::
 Geometry conventions follow the paper's setup (Sec. 2): lattice vectors
 e1 = (1, 0), e2 = (gamma t, 1); an ellipse is x(t) = c + R(theta) (a cos t, b sin t).
 
-Recipes (stated in DESIGN.md as well):
+Recipes:
 
 * ``single_ellipse``: one ellipse a=0.2, b=0.1, theta=0 at the cell centre,
   skew 0, N=128 nodes.
