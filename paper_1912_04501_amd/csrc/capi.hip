@@ -1029,6 +1029,13 @@ void build_fmm_plan(spm_handle* h) {
   if (g.C != 1) throw ApiError(SPM_EINVAL, "the FMM near sum runs on single-cell handles");
   if (9 * N >= ((int64_t)1 << 31)) throw ApiError(SPM_EINVAL, "too many nodes for the FMM");
   const int p = h->cfg.fmm_order > 0 ? h->cfg.fmm_order : 40;
+  double tm = now();
+  auto mark = [&](const char* what) {      // phase times with SPM_VERBOSE
+    if (!verbose()) return;
+    const double t = now();
+    std::fprintf(stderr, "[spm]   quadtree %s %.1f ms\n", what, 1e3 * (t - tm));
+    tm = t;
+  };
   std::vector<double> x(N), y(N);
   download(h, x.data(), g.x, N * sizeof(double));
   download(h, y.data(), g.y, N * sizeof(double));
@@ -1048,6 +1055,7 @@ void build_fmm_plan(spm_handle* h) {
       ymax = std::max(ymax, b);
     }
   }
+  mark("images");
   const double D0 = std::max(xmax - xmin, ymax - ymin) * (1.0 + 1e-6) + 1e-12;
   const double c0x = 0.5 * (xmin + xmax), c0y = 0.5 * (ymin + ymax);
   auto leaf_of = [&](double a, double b, int L) -> int64_t {
@@ -1070,6 +1078,7 @@ void build_fmm_plan(spm_handle* h) {
     bs_all = fmm_levels(cs, Lhi);
     bt_all = fmm_levels(ct, Lhi);
   }
+  mark("binning");
   int bestL = Llo;
   double best = 1e300, best_p2p = 0, best_m2l = 0;
   for (int L = Llo; L <= Lhi; ++L) {
@@ -1082,6 +1091,7 @@ void build_fmm_plan(spm_handle* h) {
       best_m2l = w.second;
     }
   }
+  mark("level choice");
   const int L = bestL;
   const int64_t nl = (int64_t)1 << (2 * L);
   // counting sort of the sources and of the targets by leaf
@@ -1110,6 +1120,7 @@ void build_fmm_plan(spm_handle* h) {
       tperm[d] = (int32_t)j;
     }
   }
+  mark("sort");
   const std::vector<int64_t> bs = fmm_levels(cs, L), bt = fmm_levels(ct, L);
   const int64_t nbox = fmm_box_off(L + 1);
   std::vector<int32_t> bsrc(nbox);
@@ -1136,6 +1147,7 @@ void build_fmm_plan(spm_handle* h) {
   }
   push_level(L, bt);
   F.seg.push_back((int64_t)lists.size());
+  mark("lists");
   std::vector<double> fact(2 * p);
   fact[0] = 1.0;
   for (int k = 1; k < 2 * p; ++k) fact[k] = fact[k - 1] * k;
@@ -1166,6 +1178,7 @@ void build_fmm_plan(spm_handle* h) {
   upload(h, F.fact, fact.data(), fact.size() * sizeof(double));
   const int32_t one = 1;
   upload(h, F.nsplit1, &one, sizeof(int32_t));
+  mark("upload");
   F.p = p;
   F.L = L;
   F.D0 = D0;
