@@ -6,7 +6,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <thread>
 #include <tuple>
 #include <utility>
 
@@ -1041,40 +1043,67 @@ void build_fmm_plan(spm_handle* h) {
   download(h, y.data(), g.y, N * sizeof(double));
   const double skew = h->cells[0].skew;
   const int64_t ns = 9 * N;
-  std::vector<double> sx(ns), sy(ns);
-  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-  for (int s = 0; s < kShifts; ++s) {
-    const double dx = shift_x(s, skew), dy = shift_y(s);
-    for (int64_t j = 0; j < N; ++j) {
-      const double a = x[j] + dx, b = y[j] + dy;
-      sx[s * N + j] = a;
-      sy[s * N + j] = b;
-      xmin = std::min(xmin, a);
-      xmax = std::max(xmax, a);
-      ymin = std::min(ymin, b);
-      ymax = std::max(ymax, b);
+  // host threads over contiguous index ranges (results do not depend on their number)
+  const int T = (int)std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::max(1u, std::thread::hardware_concurrency()),
+                                                             ns / 65536 + 1}));
+  auto par = [&](int64_t n, const std::function<void(int64_t, int64_t, int)>& f) {
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) {
+      const int64_t a = n * t / T, b = n * (t + 1) / T;
+      th.emplace_back(f, a, b, t);
     }
+    for (auto& x : th) x.join();
+  };
+  std::vector<double> sx(ns), sy(ns);
+  std::vector<double> mm(4 * T);
+  par(ns, [&](int64_t a, int64_t b, int t) {
+    double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    for (int64_t k = a; k < b; ++k) {
+      const int sh = (int)(k / N);
+      const int64_t j = k - sh * N;
+      const double u = x[j] + shift_x(sh, skew), v = y[j] + shift_y(sh);
+      sx[k] = u;
+      sy[k] = v;
+      x0 = std::min(x0, u);
+      x1 = std::max(x1, u);
+      y0 = std::min(y0, v);
+      y1 = std::max(y1, v);
+    }
+    mm[4 * t] = x0;
+    mm[4 * t + 1] = x1;
+    mm[4 * t + 2] = y0;
+    mm[4 * t + 3] = y1;
+  });
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  for (int t = 0; t < T; ++t) {
+    xmin = std::min(xmin, mm[4 * t]);
+    xmax = std::max(xmax, mm[4 * t + 1]);
+    ymin = std::min(ymin, mm[4 * t + 2]);
+    ymax = std::max(ymax, mm[4 * t + 3]);
   }
   mark("images");
   const double D0 = std::max(xmax - xmin, ymax - ymin) * (1.0 + 1e-6) + 1e-12;
   const double c0x = 0.5 * (xmin + xmax), c0y = 0.5 * (ymin + ymax);
-  auto leaf_of = [&](double a, double b, int L) -> int64_t {
-    const int n = 1 << L;
-    const int ix = std::min(std::max((int)std::floor((a - (c0x - 0.5 * D0)) / D0 * n), 0), n - 1);
-    const int iy = std::min(std::max((int)std::floor((b - (c0y - 0.5 * D0)) / D0 * n), 0), n - 1);
-    return (int64_t)iy * n + ix;
-  };
   const int64_t ctr = 4 * N;   // shift index 4 is m = n = 0: the targets themselves
   // leaf level: bin once at the finest candidate level; every coarser tree is an aggregate of it
-  // (same root box). Candidates bracket about 60 image sources per leaf.
+  // (same root box, and a box index at level L is the finest index shifted right). Candidates
+  // bracket about 60 image sources per leaf.
   const int Lg = (int)std::lround(std::log((double)ns / 60.0) / std::log(4.0));
   const int Llo = std::max(2, std::min(9, Lg - 1)), Lhi = std::min(10, std::max(Llo, Lg + 1));
+  const int nh = 1 << Lhi;
+  std::vector<int32_t> ixh(ns), iyh(ns);   // finest-level box coordinates of every source
+  par(ns, [&](int64_t a, int64_t b, int) {
+    for (int64_t k = a; k < b; ++k) {
+      ixh[k] = std::min(std::max((int)std::floor((sx[k] - (c0x - 0.5 * D0)) / D0 * nh), 0), nh - 1);
+      iyh[k] = std::min(std::max((int)std::floor((sy[k] - (c0y - 0.5 * D0)) / D0 * nh), 0), nh - 1);
+    }
+  });
   std::vector<int64_t> bs_all, bt_all;
   {
-    const int64_t nlh = (int64_t)1 << (2 * Lhi);
+    const int64_t nlh = (int64_t)nh * nh;
     std::vector<int64_t> cs(nlh, 0), ct(nlh, 0);
-    for (int64_t k = 0; k < ns; ++k) cs[leaf_of(sx[k], sy[k], Lhi)]++;
-    for (int64_t j = 0; j < N; ++j) ct[leaf_of(sx[ctr + j], sy[ctr + j], Lhi)]++;
+    for (int64_t k = 0; k < ns; ++k) cs[(int64_t)iyh[k] * nh + ixh[k]]++;
+    for (int64_t j = ctr; j < ctr + N; ++j) ct[(int64_t)iyh[j] * nh + ixh[j]]++;
     bs_all = fmm_levels(cs, Lhi);
     bt_all = fmm_levels(ct, Lhi);
   }
@@ -1094,31 +1123,45 @@ void build_fmm_plan(spm_handle* h) {
   mark("level choice");
   const int L = bestL;
   const int64_t nl = (int64_t)1 << (2 * L);
-  // counting sort of the sources and of the targets by leaf
+  const int dsh = Lhi - L;
+  auto leaf = [&](int64_t k) -> int64_t { return ((int64_t)(iyh[k] >> dsh) << L) + (ixh[k] >> dsh); };
+  // stable counting sort of the sources by leaf: per-thread histograms over contiguous ranges, so
+  // within a leaf the sources keep their index order whatever the number of threads
   std::vector<int64_t> cs(nl, 0), ct(nl, 0);
-  std::vector<int64_t> lf(ns);
-  for (int64_t k = 0; k < ns; ++k) cs[lf[k] = leaf_of(sx[k], sy[k], L)]++;
-  for (int64_t j = 0; j < N; ++j) ct[lf[ctr + j]]++;
+  std::vector<std::vector<int32_t>> hist(T, std::vector<int32_t>(nl, 0));
+  par(ns, [&](int64_t a, int64_t b, int t) {
+    for (int64_t k = a; k < b; ++k) hist[t][leaf(k)]++;
+  });
+  for (int t = 0; t < T; ++t)
+    for (int64_t b = 0; b < nl; ++b) cs[b] += hist[t][b];
+  for (int64_t j = ctr; j < ctr + N; ++j) ct[leaf(j)]++;
   std::vector<int32_t> leaf_s(nl + 1, 0), leaf_t(nl + 1, 0);
   for (int64_t b = 0; b < nl; ++b) {
     leaf_s[b + 1] = leaf_s[b] + (int32_t)cs[b];
     leaf_t[b + 1] = leaf_t[b] + (int32_t)ct[b];
   }
+  for (int64_t b = 0; b < nl; ++b) {       // hist[t][b] becomes thread t's first slot in leaf b
+    int32_t run = leaf_s[b];
+    for (int t = 0; t < T; ++t) {
+      const int32_t c = hist[t][b];
+      hist[t][b] = run;
+      run += c;
+    }
+  }
   std::vector<double> ssx(ns), ssy(ns);
   std::vector<int32_t> ssj(ns), tperm(N);
-  {
-    std::vector<int32_t> fill(leaf_s.begin(), leaf_s.end() - 1);
-    for (int64_t k = 0; k < ns; ++k) {
-      const int32_t d = fill[lf[k]]++;
+  par(ns, [&](int64_t a, int64_t b, int t) {
+    std::vector<int32_t>& fill = hist[t];
+    for (int64_t k = a; k < b; ++k) {
+      const int32_t d = fill[leaf(k)]++;
       ssx[d] = sx[k];
       ssy[d] = sy[k];
       ssj[d] = (int32_t)(k % N);
     }
+  });
+  {
     std::vector<int32_t> tf(leaf_t.begin(), leaf_t.end() - 1);
-    for (int64_t j = 0; j < N; ++j) {
-      const int32_t d = tf[lf[ctr + j]]++;
-      tperm[d] = (int32_t)j;
-    }
+    for (int64_t j = 0; j < N; ++j) tperm[tf[leaf(ctr + j)]++] = (int32_t)j;
   }
   mark("sort");
   const std::vector<int64_t> bs = fmm_levels(cs, L), bt = fmm_levels(ct, L);
