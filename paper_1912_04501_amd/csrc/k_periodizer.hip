@@ -21,6 +21,17 @@ __device__ __forceinline__ void stokeslet_uv(double rx, double ry, double f1, do
   u2 += inv4pimu * (lg * f2 + ry * rf);
 }
 
+// G(r_a) f - G(r_b) f with the two logarithms taken as one: -log|r_a| + log|r_b| = -(1/2) log(|r_a|^2 / |r_b|^2).
+__device__ __forceinline__ void stokeslet_diff_uv(double ax, double ay, double bx, double by, double f1, double f2,
+                                                  double inv4pimu, double& d1, double& d2) {
+  const double a2 = ax * ax + ay * ay, b2 = bx * bx + by * by;
+  const double ia2 = rcp64(a2), ib2 = rcp64(b2);
+  const double lg = -0.5 * log(a2 * ib2);
+  const double af = (ax * f1 + ay * f2) * ia2, bf = (bx * f1 + by * f2) * ib2;
+  d1 = inv4pimu * (lg * f1 + (ax * af - bx * bf));
+  d2 = inv4pimu * (lg * f2 + (ay * af - by * bf));
+}
+
 __device__ __forceinline__ void traction_uv(double rx, double ry, double nx, double ny, double f1, double f2,
                                             double& t1, double& t2) {
   const double r2 = rx * rx + ry * ry;
@@ -307,13 +318,12 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
     for (int n = -1; n <= 1; ++n) {
       const double fx = yj - 2.0 * ax + n * bx, fy = zj - 2.0 * ay + n * by;
       const double cx = yj + ax + n * bx, cy = zj + ay + n * by;
-      double v1 = 0, v2 = 0, w1 = 0, w2 = 0;
-      stokeslet_uv(x0 - fx, y0 - fy, g1, g2, L.inv4pimu, v1, v2);
-      stokeslet_uv(x0 - cx, y0 - cy, g1, g2, L.inv4pimu, w1, w2);
-      // the far-minus-near difference of one source is rounded once (an error of the size
-      // of its own evaluation error); the running sums are double-double
-      u1 = dd_add_d(u1, v1 - w1);
-      u2 = dd_add_d(u2, v2 - w2);
+      // the far-minus-near difference of one source is formed directly (one logarithm of the
+      // ratio of squared distances) and rounded once; the running sums are double-double
+      double v1, v2;
+      stokeslet_diff_uv(x0 - fx, y0 - fy, x0 - cx, y0 - cy, g1, g2, L.inv4pimu, v1, v2);
+      u1 = dd_add_d(u1, v1);
+      u2 = dd_add_d(u2, v2);
       double p1 = 0, p2 = 0, q1 = 0, q2 = 0;
       traction_uv(x0 - fx, y0 - fy, nx, ny, g1, g2, p1, p2);
       traction_uv(x0 - cx, y0 - cy, nx, ny, g1, g2, q1, q2);
