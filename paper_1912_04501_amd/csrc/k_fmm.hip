@@ -35,7 +35,7 @@ struct cx {
 };
 __device__ __forceinline__ cx operator+(cx a, cx b) { return {a.r + b.r, a.i + b.i}; }
 __device__ __forceinline__ cx operator-(cx a, cx b) { return {a.r - b.r, a.i - b.i}; }
-__device__ __forceinline__ cx operator*(cx a, cx b) { return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r}; }
+__device__ __forceinline__ cx operator*(cx a, cx b) { return {fma(a.r, b.r, -a.i * b.i), fma(a.r, b.i, a.i * b.r)}; }
 __device__ __forceinline__ cx operator*(cx a, double s) { return {a.r * s, a.i * s}; }
 __device__ __forceinline__ cx conj(cx a) { return {a.r, -a.i}; }
 // acc + a b and acc + a s with fused multiply-adds (the library builds without contraction)
