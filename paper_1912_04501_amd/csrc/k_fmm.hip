@@ -317,15 +317,18 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(FmmArgs a, int l, const int32_t*
   }
 }
 
-// one wavefront per target leaf: the leaf's targets (64 at a time) each take 64 / n_t lanes, which
-// split the direct sum over the 3x3 neighbour leaves (sources in three contiguous rows of the sorted
-// order, staged through LDS 64 at a time) and are summed in a fixed order; then the local expansion
-__global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int32_t* __restrict__ list,
-                                                 const int32_t* __restrict__ leaf_t,
-                                                 const int32_t* __restrict__ tperm, Geo g,
-                                                 double* __restrict__ out) {
-  __shared__ double shx[64], shy[64], sf1[64], sf2[64];
-  __shared__ double red1[64], red2[64];
+// three wavefronts per target leaf: the sources of the 3x3 neighbour leaves (three contiguous rows
+// of the sorted order, taken as one list) are staged through LDS 192 at a time and each wave takes
+// a third of every chunk; within a wave the leaf's targets (64 at a time) take 64 / n_t lanes each.
+// The wave and lane partial sums are added in a fixed order, then wave 0 adds the local expansion.
+constexpr int kEvalWaves = 3;
+__global__ __launch_bounds__(64 * kEvalWaves) void k_fmm_eval(FmmArgs a, int64_t N, const int32_t* __restrict__ list,
+                                                              const int32_t* __restrict__ leaf_t,
+                                                              const int32_t* __restrict__ tperm, Geo g,
+                                                              double* __restrict__ out) {
+  constexpr int B = 64 * kEvalWaves;
+  __shared__ double shx[B], shy[B], sf1[B], sf2[B];
+  __shared__ double red1[kEvalWaves][64], red2[kEvalWaves][64];
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(a.L);
   const int n = 1 << a.L;
@@ -334,65 +337,79 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
   const double h = a.D0 / n;
   const cx* Le = a.Lx + gid * 3 * a.p;
   const int p = a.p;
-  const int lane = threadIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // the neighbour rows as one list of up to three ranges
+  int32_t rb[3], rl[3];
+  int nr = 0;
+  int32_t total = 0;
+  for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
+    rb[nr] = a.leaf_s[(int64_t)jy * n + max(ix - 1, 0)];
+    rl[nr] = a.leaf_s[(int64_t)jy * n + min(ix + 1, n - 1) + 1] - rb[nr];
+    total += rl[nr];
+    ++nr;
+  }
   const int32_t t0 = leaf_t[loc], t1 = leaf_t[loc + 1];
   for (int32_t tb = t0; tb < t1; tb += 64) {
     const int nt = min(64, (int)(t1 - tb));
-    const int S = 64 / nt;                 // lanes per target
+    const int S = 64 / nt;                 // lanes per target within a wave
     const int tl = lane % nt, r = lane / nt;
     const bool act = r < S;
     const int64_t i = tperm[tb + tl];
     const double x = g.x[i], y = g.y[i], nx = g.nx[i], ny = g.ny[i];
     double d1 = 0.0, d2 = 0.0;
-    for (int jy = max(iy - 1, 0); jy <= min(iy + 1, n - 1); ++jy) {
-      const int32_t r0 = a.leaf_s[(int64_t)jy * n + max(ix - 1, 0)];
-      const int32_t r1 = a.leaf_s[(int64_t)jy * n + min(ix + 1, n - 1) + 1];
-      for (int32_t sb = r0; sb < r1; sb += 64) {
-        const int32_t j = sb + lane;
-        __syncthreads();
-        if (j < r1) {
-          shx[lane] = a.sx[j];
-          shy[lane] = a.sy[j];
-          sf1[lane] = a.fs1[j];
-          sf2[lane] = a.fs2[j];
+    for (int32_t cb = 0; cb < total; cb += B) {
+      __syncthreads();
+      const int32_t q = cb + (int32_t)threadIdx.x;
+      if (q < total) {
+        int32_t j = q, k = 0;
+        while (j >= rl[k]) {
+          j -= rl[k];
+          ++k;
         }
-        __syncthreads();
-        const int m = min(64, (int)(r1 - sb));
-        if (act) {
-          for (int q = r; q < m; q += S) {
-            const double rx = x - shx[q], ry = y - shy[q];
-            // the target's own node (r = 0): the floor keeps 1/|r|^2 finite and (r.n)(r.f) = 0
-            const double ir2 = rcp64(fmax(fma(rx, rx, ry * ry), 1e-300));
-            const double cf = ((fma(rx, nx, ry * ny) * fma(rx, sf1[q], ry * sf2[q])) * ir2) * ir2;
-            d1 = fma(cf, rx, d1);
-            d2 = fma(cf, ry, d2);
-          }
+        j += rb[k];
+        shx[threadIdx.x] = a.sx[j];
+        shy[threadIdx.x] = a.sy[j];
+        sf1[threadIdx.x] = a.fs1[j];
+        sf2[threadIdx.x] = a.fs2[j];
+      }
+      __syncthreads();
+      const int m = min(B, (int)(total - cb));
+      const int q1 = min(m, 64 * (w + 1));
+      if (act) {
+        for (int qq = 64 * w + r; qq < q1; qq += S) {
+          const double rx = x - shx[qq], ry = y - shy[qq];
+          // the target's own node (r = 0): the floor keeps 1/|r|^2 finite and (r.n)(r.f) = 0
+          const double ir2 = rcp64(fmax(fma(rx, rx, ry * ry), 1e-300));
+          const double cf = ((fma(rx, nx, ry * ny) * fma(rx, sf1[qq], ry * sf2[qq])) * ir2) * ir2;
+          d1 = fma(cf, rx, d1);
+          d2 = fma(cf, ry, d2);
         }
       }
     }
     __syncthreads();
-    red1[lane] = act ? d1 : 0.0;
-    red2[lane] = act ? d2 : 0.0;
+    red1[w][lane] = act ? d1 : 0.0;
+    red2[w][lane] = act ? d2 : 0.0;
     __syncthreads();
-    if (lane < nt) {
+    if (w == 0 && lane < nt) {
       double e1 = 0.0, e2 = 0.0;
-      for (int q = 0; q < S; ++q) {
-        e1 += red1[q * nt + lane];
-        e2 += red2[q * nt + lane];
-      }
+      for (int ww = 0; ww < kEvalWaves; ++ww)
+        for (int sl = 0; sl < S; ++sl) {
+          e1 += red1[ww][sl * nt + lane];
+          e2 += red2[ww][sl * nt + lane];
+        }
       const cx dz = {x - c.r, y - c.i};
       const cx u = dz * (1.0 / h);
-      cx A = {0, 0}, B = {0, 0}, Ad = {0, 0}, Cd = {0, 0};
+      cx A = {0, 0}, Bv = {0, 0}, Ad = {0, 0}, Cd = {0, 0};
       for (int k = p - 1; k >= 1; --k) {
         A = cmac(Le[k], A, u);
-        B = cmac(Le[p + k], B, u);
+        Bv = cmac(Le[p + k], Bv, u);
         Ad = cmac(Le[k] * (double)k, Ad, u);
         Cd = cmac(Le[2 * p + k] * (double)k, Cd, u);
       }
       A = cmac(Le[0], A, u);
-      B = cmac(Le[p], B, u);
+      Bv = cmac(Le[p], Bv, u);
       const cx E = (Cd - conj(dz) * Ad) * (1.0 / h);
-      const cx BE = B + E;
+      const cx BE = Bv + E;
       const double k4 = -1.0 / (4.0 * kPi);
       out[i] = k4 * (2.0 * nx * A.r + (nx * BE.r - ny * BE.i)) - e1 / kPi;
       out[N + i] = k4 * (2.0 * ny * A.r - (nx * BE.i + ny * BE.r)) - e2 / kPi;
@@ -400,14 +417,6 @@ __global__ __launch_bounds__(64) void k_fmm_eval(FmmArgs a, int64_t N, const int
   }
 }
 
-// Velocity and vorticity of the near-image sum at the particle centres (the readout's u_near,
-// vort_near) from the multipoles of the current density: one wavefront per particle walks the
-// quadtree like the FMM does (the interaction list of the centre's box at every level, evaluated
-// from the boxes' multipoles at the centre itself, then the 3x3 leaves around it directly). With
-// r = z - z_j, the Stokeslet of eq. Gv is G f = (1/4pi mu) [ -f log|r| + f/2 + conj(f) r / (2 conj(r)) ],
-// so a box contributes -(1/2)(Phi + conj(Psi)) with Phi = sum f log r, Psi = sum conj(f) log r
-// (log multipoles built from the same power sums as A and B), F_box / 2, and
-// conj((conj(z) - conj(c)) A - C_c) / 2; the vorticity is -(1/2pi mu) Im A.
 // Per-lane partial sums of the near-image velocity, vorticity and pressure (G^p of eq. Gp:
 // (r.f) / (2 pi |r|^2) = Re(f / r) / (2 pi), so the boxes contribute Re A / (2 pi)) at the point z
 // (inside the root box); the caller sums the lanes.
@@ -610,7 +619,7 @@ void launch_fmm(spm_handle* h, double* out) {
   }
   const int64_t N = h->geo.N;
   prof_mark(h, 2, true, 0);
-  if (n_of(s)) k_fmm_eval<<<n_of(s), 64, 0, h->stream>>>(a, N, list(s), F.leaf_t, F.tperm, h->geo, out);
+  if (n_of(s)) k_fmm_eval<<<n_of(s), 64 * kEvalWaves, 0, h->stream>>>(a, N, list(s), F.leaf_t, F.tperm, h->geo, out);
   SPM_HIP_CHECK(hipGetLastError());
   prof_mark(h, 2, false, F.p2p_pairs);
 }
