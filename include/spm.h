@@ -4,15 +4,15 @@
  * Method: Wang, Nazockdast & Barnett, "An integral equation method for the
  * simulation of doubly-periodic suspensions of rigid bodies in a shearing viscous
  * flow" (arXiv:1912.04501). The library solves the quasi-static mobility problem
- * of Sec. 3 for rigid ellipses in a sheared, skewed unit cell through the
- * completed second-kind BIE of Sec. 5 (eq. BIEPerturbed):
+ * of Sec. 3 for rigid ellipses and smooth star-shaped particles in a sheared,
+ * skewed unit cell through the completed second-kind BIE of Sec. 5 (eq. BIEPerturbed):
  *
  *     (1/2 I + K + L) sigma = -T(u0, p0) = -mu gamma (n_2, n_1),
  *
  * where K is the traction of the periodic single-layer potential, applied as a
- * 3x3 near-image sum + exterior barycentric close correction + proxy-Stokeslet
- * periodizing correction (Sec. 4.2, Sec. 6.1-6.3), with the pressure pin of the
- * Sec. 6.2 remark, and L the rigid-mode completion of Sec. 5.
+ * 3x3 near-image sum (direct, or by a fast multipole method) + exterior barycentric
+ * close correction + proxy-Stokeslet periodizing correction (Sec. 4.2, Sec. 6.1-6.3),
+ * with the pressure pin of the Sec. 6.2 remark, and L the rigid-mode completion of Sec. 5.
  *
  * Conventions (all calls):
  *  - Lattice e1 = (1, 0), e2 = (s, 1) (Sec. 2, Sec. 7); the skew s is reduced to
@@ -22,8 +22,9 @@
  *    particle-major: the nodes of particle 0 first.
  *  - Densities and node-vectors are SoA FP64: v[0..N-1] first components,
  *    v[N..2N-1] second components.
- *  - Background flow u0 = (gamma x_2, 0). Velocities are reported in the gauge
- *    where the proxy (periodizing) field vanishes at the cell centre; omega is
+ *  - Background flow u0 = (gamma x_2, 0). Velocities are defined up to one constant
+ *    per cell; they are reported in the gauge where the area-weighted mean of
+ *    v_i - u0(c_i) over the cell's particles is zero (see spm_velocities); omega is
  *    gauge-free.
  *
  * Memory and streams: every array argument is a DEVICE pointer on the handle's
