@@ -60,6 +60,23 @@ def test_fmm_near_sum_matches_oracle(name, order, bound):
     assert err < bound
 
 
+@pytest.mark.parametrize("order,bound", [(8, 5e-2), (64, 1e-12)])
+def test_fmm_order_limits(order, bound):
+    """The smallest and largest expansion orders (8: worst-case rate 0.547^8 = 8e-3 of the far
+    contributions; 64: the 127! factorial table and 64-lane expansions) on a skewed 25-ellipse cell."""
+    wl = W.random_ellipses(25, 0.3, seed=7, skew=-0.47)
+    g = geometry.build_geometry(wl)
+    s = _fmm(wl, order)
+    assert s.fmm_stats()["order"] == order
+    sig = W.random_density(g.N, seed=12)
+    T = _n(s.near_traction(torch.as_tensor(sig, device="cuda:0")))
+    ref = _oracle_near(g, sig)
+    dev = np.stack([T[:g.N], T[g.N:]], axis=1)
+    err = np.abs(dev - ref).max() / np.abs(ref).max()
+    print(f"[fmm order {order}] rel err {err:.2e}", flush=True)
+    assert err < bound
+
+
 def test_fmm_near_sum_200_ellipses_sampled():
     """The 200-ellipse, 51,200-node cell: 3,000 sampled targets against the oracle."""
     wl = W.ellipses_200()
