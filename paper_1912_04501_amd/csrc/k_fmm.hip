@@ -23,8 +23,8 @@
 //   L2L (parent c to child c', t = (c' - c)/h_P): L'_m = (2^-m / m!) sum_{l>=m} (L_l l!) (t^(l-m) / (l-m)!)
 // Interaction lists are the usual ones (children of the parent's neighbours that are not
 // neighbours); leaves evaluate their 3x3 neighbourhood directly, where the pair at zero
-// distance (the target's own node) adds nothing. Every pass is deterministic: one wavefront per box, lanes over
-// expansion terms, fixed loop orders.
+// distance (the target's own node) adds nothing. Every pass is deterministic: one wavefront per box (three per
+// leaf in the evaluation), lanes over expansion terms, fixed loop orders.
 #include "spm_internal.h"
 
 namespace spm {
