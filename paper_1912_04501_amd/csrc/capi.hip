@@ -1058,16 +1058,23 @@ void build_fmm_plan(spm_handle* h) {
   std::vector<double> mm(4 * T);
   par(ns, [&](int64_t a, int64_t b, int t) {
     double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+    int sh = (int)(a / N);                 // source k is image sh of node j = k - sh N
+    int64_t j = a - sh * N;
+    double ox = shift_x(sh, skew), oy = shift_y(sh);
     for (int64_t k = a; k < b; ++k) {
-      const int sh = (int)(k / N);
-      const int64_t j = k - sh * N;
-      const double u = x[j] + shift_x(sh, skew), v = y[j] + shift_y(sh);
+      const double u = x[j] + ox, v = y[j] + oy;
       sx[k] = u;
       sy[k] = v;
       x0 = std::min(x0, u);
       x1 = std::max(x1, u);
       y0 = std::min(y0, v);
       y1 = std::max(y1, v);
+      if (++j == N && sh < 8) {
+        j = 0;
+        ++sh;
+        ox = shift_x(sh, skew);
+        oy = shift_y(sh);
+      }
     }
     mm[4 * t] = x0;
     mm[4 * t + 1] = x1;
@@ -1092,17 +1099,19 @@ void build_fmm_plan(spm_handle* h) {
   const int Llo = std::max(2, std::min(9, Lg - 1)), Lhi = std::min(10, std::max(Llo, Lg + 1));
   const int nh = 1 << Lhi;
   std::vector<int32_t> ixh(ns), iyh(ns);   // finest-level box coordinates of every source
-  par(ns, [&](int64_t a, int64_t b, int) {
-    for (int64_t k = a; k < b; ++k) {
-      ixh[k] = std::min(std::max((int)std::floor((sx[k] - (c0x - 0.5 * D0)) / D0 * nh), 0), nh - 1);
-      iyh[k] = std::min(std::max((int)std::floor((sy[k] - (c0y - 0.5 * D0)) / D0 * nh), 0), nh - 1);
-    }
-  });
   std::vector<int64_t> bs_all, bt_all;
   {
     const int64_t nlh = (int64_t)nh * nh;
     std::vector<int64_t> cs(nlh, 0), ct(nlh, 0);
-    for (int64_t k = 0; k < ns; ++k) cs[(int64_t)iyh[k] * nh + ixh[k]]++;
+    par(ns, [&](int64_t a, int64_t b, int) {
+      for (int64_t k = a; k < b; ++k) {
+        const int ix = std::min(std::max((int)std::floor((sx[k] - (c0x - 0.5 * D0)) / D0 * nh), 0), nh - 1);
+        const int iy = std::min(std::max((int)std::floor((sy[k] - (c0y - 0.5 * D0)) / D0 * nh), 0), nh - 1);
+        ixh[k] = ix;
+        iyh[k] = iy;
+        __atomic_fetch_add(&cs[(int64_t)iy * nh + ix], (int64_t)1, __ATOMIC_RELAXED);   // counts only
+      }
+    });
     for (int64_t j = ctr; j < ctr + N; ++j) ct[(int64_t)iyh[j] * nh + ixh[j]]++;
     bs_all = fmm_levels(cs, Lhi);
     bt_all = fmm_levels(ct, Lhi);
@@ -1152,11 +1161,13 @@ void build_fmm_plan(spm_handle* h) {
   std::vector<int32_t> ssj(ns), tperm(N);
   par(ns, [&](int64_t a, int64_t b, int t) {
     std::vector<int32_t>& fill = hist[t];
+    int64_t j = a % N;                     // node of source k
     for (int64_t k = a; k < b; ++k) {
       const int32_t d = fill[leaf(k)]++;
       ssx[d] = sx[k];
       ssy[d] = sy[k];
-      ssj[d] = (int32_t)(k % N);
+      ssj[d] = (int32_t)j;
+      if (++j == N) j = 0;
     }
   });
   {

@@ -205,3 +205,24 @@ def test_fmm_arguments():
     with pytest.raises(spm.SpmError) as err:
         _fmm(wl).autotune()
     assert err.value.code == spm.SPM_ESTATE
+
+
+@pytest.mark.parametrize("name", ["random_25_phi0.3_seed1", "two_stars_s0.25_A0.5_w4"])
+def test_fmm_handle_contour_mu_eff(name):
+    """The contour-deformation effective viscosity on an FMM handle (its wall discrepancy and proxy
+    strengths come from the FMM handle's own source order) against the oracle's contour sums on
+    the same density and strengths (1e-12) and against a direct handle (1e-10)."""
+    from paper_1912_04501_amd import spm
+    wl = CASES[name]()
+    prob = op.make_problem(wl)
+    d = spm.Solver("cuda:0").set_workload(wl)
+    f = _fmm(wl)
+    sig = d.solve()["sigma"]
+    mu_f = _n(f.effective_viscosity_contour(sig))[0]
+    mu_d = _n(d.effective_viscosity_contour(sig))[0]
+    xi = _n(f.proxy_strengths(sig))
+    a = ro.mu_eff_contour(prob, _n(sig), xi=xi)
+    print(f"[fmm contour {name}] FMM handle {mu_f:.15f} oracle (same xi) err {abs(mu_f - a):.1e} direct handle "
+          f"diff {abs(mu_f - mu_d):.1e}", flush=True)
+    assert abs(mu_f - a) < 1e-12
+    assert abs(mu_f - mu_d) < 1e-10 * max(1.0, abs(mu_d))
