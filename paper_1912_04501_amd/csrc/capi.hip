@@ -8,6 +8,7 @@
 #include <cstring>
 #include <functional>
 #include <map>
+#include <memory>
 #include <thread>
 #include <tuple>
 #include <utility>
@@ -1023,6 +1024,17 @@ std::pair<double, double> fmm_work(const std::vector<int64_t>& bs, const std::ve
 // the source at zero distance); the leaf level minimises an operation count (direct pairs at
 // ~25 flop against multipole-to-local translations at ~12 p^2 flop); sources and targets are
 // sorted by leaf; box lists of every pass are uploaded with the expansion buffers.
+// Host array left uninitialised: its pages are first touched by the threads that fill it (a
+// std::vector would zero them all on one thread first).
+template <class T>
+struct HostArray {
+  std::unique_ptr<T[]> p;
+  explicit HostArray(size_t n) : p(new T[n]) {}
+  T& operator[](size_t i) { return p[i]; }
+  const T& operator[](size_t i) const { return p[i]; }
+  T* data() { return p.get(); }
+};
+
 void build_fmm_plan(spm_handle* h) {
   FmmPlan& F = h->fmm;
   F.on = false;
@@ -1054,7 +1066,7 @@ void build_fmm_plan(spm_handle* h) {
     }
     for (auto& x : th) x.join();
   };
-  std::vector<double> sx(ns), sy(ns);
+  HostArray<double> sx(ns), sy(ns);       // every entry written below
   std::vector<double> mm(4 * T);
   par(ns, [&](int64_t a, int64_t b, int t) {
     double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
@@ -1098,7 +1110,7 @@ void build_fmm_plan(spm_handle* h) {
   const int Lg = (int)std::lround(std::log((double)ns / 60.0) / std::log(4.0));
   const int Llo = std::max(2, std::min(9, Lg - 1)), Lhi = std::min(10, std::max(Llo, Lg + 1));
   const int nh = 1 << Lhi;
-  std::vector<int32_t> ixh(ns), iyh(ns);   // finest-level box coordinates of every source
+  HostArray<int32_t> ixh(ns), iyh(ns);     // finest-level box coordinates of every source
   std::vector<int64_t> bs_all, bt_all;
   {
     const int64_t nlh = (int64_t)nh * nh;
@@ -1157,8 +1169,9 @@ void build_fmm_plan(spm_handle* h) {
       run += c;
     }
   }
-  std::vector<double> ssx(ns), ssy(ns);
-  std::vector<int32_t> ssj(ns), tperm(N);
+  HostArray<double> ssx(ns), ssy(ns);     // the scatter below writes every slot once
+  HostArray<int32_t> ssj(ns);
+  std::vector<int32_t> tperm(N);
   par(ns, [&](int64_t a, int64_t b, int t) {
     std::vector<int32_t>& fill = hist[t];
     int64_t j = a % N;                     // node of source k
