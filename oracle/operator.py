@@ -218,7 +218,9 @@ def solve(prob, tol=1e-10, maxiter=500, method="gmres", x0=None):
 def apply_rows(prob, sigma, rows):
     """Rows `rows` (node indices) of y = (1/2 I + K_pinned + L) sigma, without forming
     the whole product: the same sums evaluated at the selected targets only (the pin
-    needs node 0, which is always evaluated). Returns (len(rows), 2)."""
+    needs node 0, which is always evaluated). Returns (len(rows), 2). 3x3 near set only."""
+    if prob.cfg.near_set != "3x3":
+        raise ValueError("apply_rows evaluates the 3x3 near set only")
     g = prob.geom
     s2 = to2(np.asarray(sigma, dtype=np.float64))
     rows = np.asarray(rows, dtype=np.int64)

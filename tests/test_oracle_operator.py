@@ -314,3 +314,34 @@ def test_operator_nullspace_structure():
     assert sB[-6:].max() < 1e-6 * sB[0]
     assert sB[-7] > 1e-3 * sB[0]
     assert sA[-1] > 1e-3 * sA[0]
+
+
+@pytest.mark.parametrize("case", ["two_ellipses_gap1e-3_skew", "star_ellipse_gap5e-3", "six_ellipses_skewed"])
+def test_apply_rows_equals_full_product(case):
+    """apply_rows evaluates the operator of Sec. 5 (eq. BIEPerturbed) at selected targets
+    only: its own self term, close pairs picked by target, the pin through node 0 (Sec. 6.2
+    remark). Every selected row must equal the same row of the full product, for row sets
+    with and without node 0, unsorted and with repeats."""
+    if case == "two_ellipses_gap1e-3_skew":
+        wl = W.two_ellipses(1e-3, n_nodes=128, skew=0.3)
+    elif case == "star_ellipse_gap5e-3":
+        wl = W.star_and_ellipse(gap=5e-3, n_star=192, n_ellipse=128, skew=0.2)
+    else:
+        wl = W.random_ellipses(6, 0.3, 3, nodes=64)
+    prob = op.make_problem(wl)
+    assert len(prob.pairs) > 0
+    rng = np.random.default_rng(11)
+    sigma = rng.standard_normal(2 * prob.N)
+    full = op.to2(op.apply(prob, sigma))
+    scale = np.abs(full).max()
+    close_targets = np.unique(prob.pairs[:, 0])
+    row_sets = [
+        np.array([0, 1, prob.N - 1]),
+        np.sort(rng.choice(np.arange(1, prob.N), 40, replace=False)),       # without node 0
+        np.concatenate([close_targets[:30], [0], close_targets[:5]]),       # close targets, repeats
+        rng.permutation(prob.N)[:25],                                        # unsorted
+    ]
+    for rows in row_sets:
+        got = op.apply_rows(prob, sigma, rows)
+        assert got.shape == (len(rows), 2)
+        assert np.abs(got - full[rows]).max() <= 1e-14 * scale, (case, rows[:5])
