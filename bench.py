@@ -108,7 +108,59 @@ def cpu_baseline(cells, target_seconds=10.0):
         what = (f"{reps} full sweep(s) of all {Ntot} targets against their own cell's sources x 9 images"
                 + (f" over {len(prep)} cells" if len(prep) > 1 else ""))
     return {"value": pairs / t, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"FP64 oracle near-image traction sum (plain C, OpenMP): {what} ({pairs:.3e} pairs, {t:.1f} s)"}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_solve_times():
+    """The oracle's complete FP64 mobility solves (set-up + MGS GMRES to 1e-10 from zero) of
+    the single ellipse (N = 128) and the 25-ellipse cell (N = 5,112), and the dense LU solve of
+    the single ellipse (the matrix assembled column by column from operator products)."""
+    from oracle import operator as op
+    from paper_1912_04501_amd import workloads as W
+    out = {}
+    for name, wl in (("single_ellipse_N128", W.single_ellipse()), ("ellipses25_N5112", W.ellipses_25())):
+        t0 = time.perf_counter()
+        prob = op.make_problem(wl)
+        x, info = op.solve(prob, tol=1e-10)
+        out[f"gmres_s_{name}"] = time.perf_counter() - t0
+        out[f"gmres_its_{name}"] = info["iterations"]
+        if name == "single_ellipse_N128":
+            t0 = time.perf_counter()
+            op.solve(prob, method="lu")
+            out[f"dense_lu_s_{name}"] = time.perf_counter() - t0
+    return out
+
+
+def gpu_small_solve_times():
+    """The same two solves on the GPU (FP64 GMRES to 1e-10, geometry resident, second solve timed)."""
+    import torch
+
+    from paper_1912_04501_amd import spm
+    from paper_1912_04501_amd import workloads as W
+    out = {}
+    for name, wl in (("single_ellipse_N128", W.single_ellipse()), ("ellipses25_N5112", W.ellipses_25())):
+        s = spm.Solver("cuda:0")
+        s.set_workload(wl)
+        s.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.solve()
+        torch.cuda.synchronize()
+        out[f"gpu_fp64_s_{name}"] = time.perf_counter() - t0
+        out[f"gpu_fp64_its_{name}"] = r["info"]["iterations"]
+        s.close()
+    return out
 
 
 def main():
@@ -150,7 +202,7 @@ def main():
                     help="jamming: fit window (default: the example's, and the same width before the run's end)")
     args = ap.parse_args()
     if args.precision is None:
-        args.precision = "fp32_relaxed" if args.workload == "ensemble64" else "fp32_ir"
+        args.precision = "fp32_ir"
     if args.precond is None:
         args.precond = "block" if args.workload in ("ensemble64", "ellipses200") else "none"
     if args.gpus != 1:
@@ -200,8 +252,8 @@ def main():
         s.effective_viscosity_contour(r["sigma"])
         log(f"[bench] warmup {k}: {r['info']}")
     torch.cuda.synchronize()
-    s.profile(True)
-    torch.cuda.synchronize()
+    # timed region: the production path (each GMRES iteration replayed as a captured HIP graph,
+    # no timing events)
     t0 = time.perf_counter()
     infos = []
     for k in range(args.steps):
@@ -210,12 +262,22 @@ def main():
         infos.append(r["info"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    profs = [s.profile_read(0), s.profile_read(1)]
-    s.profile(False)
     for k, i in enumerate(infos):
         log(f"[bench] step {k}: {i}")
     matvecs = sum(i["fp64_matvecs"] + i["fp32_matvecs"] for i in infos)
     value = matvecs * pairs_per_matvec / elapsed
+    # the same steps again with HIP events recorded on the library's stream around every
+    # near-sum launch (events are not captured into graphs, so these iterations run unreplayed)
+    s.profile(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        rp = s.solve()
+        s.effective_viscosity_contour(rp["sigma"])
+    torch.cuda.synchronize()
+    elapsed_prof = time.perf_counter() - t1
+    profs = [s.profile_read(0), s.profile_read(1)]
+    s.profile(False)
 
     def roof(kern):
         prof = profs[kern]
@@ -260,6 +322,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample ...")
         cpu = cpu_baseline([wl])
+        cpu["solves"] = {**oracle_solve_times(), **gpu_small_solve_times()}
         log(f"[bench] cpu baseline {cpu}")
 
     out = {"metric": "Stokes matvec pair-evals/s (whole mobility solve to 1e-10 FP64 residual)",
@@ -270,6 +333,7 @@ def main():
                       "precision": args.precision, "precond": args.precond, "tol": 1e-10, "images": "3x3",
                       "proxies": 32,
                       "wall_points": 24, "close_factor": 10},
+           "ms_per_step_profiled": 1e3 * elapsed_prof / args.steps,
            "roofline": roofline, "roofline_other_precision": other, "cpu_baseline": cpu,
            "mu_eff": {"stresslet": float(r["mu_eff"][0]), "contour": float(mu_c[0])}, **extra}
     print(json.dumps(out), flush=True)
@@ -282,11 +346,13 @@ def percentile(v, q):
 
 def bench_ensemble(args):
     """64 independent cells (seeds 1000..1063, 4-50 ellipses each) solved together in
-    one persistent near-sum launch per matvec (relaxed FP32 by default, --precision and
-    --precond choose the solver), autotuned launch shape. One
-    step = one batched solve of every cell to 1e-10; value = cell solves per second;
-    per-cell latency (device wall clock from the solve start to the cell's convergence)
-    as p50 / p99 over the timed steps."""
+    one persistent near-sum launch per matvec (FP32 + FP64 iterative refinement with the
+    block preconditioner by default, --precision and --precond choose the solver), autotuned
+    launch shape, every GMRES iteration replayed as a captured HIP graph. One step = one
+    batched solve of every cell to 1e-10; value = cell solves per second; per-cell latency
+    (device wall clock from the solve start to the cell's convergence) as p50 / p99 over the
+    timed steps. Untimed comparisons: the other FP32 form, and the same solver without
+    graph replay."""
     import numpy as np
     import torch
 
@@ -297,26 +363,45 @@ def bench_ensemble(args):
     Ns = np.array([int(np.sum(c["n_nodes"])) for c in cells])
     log(f"[bench] 64 cells generated in {time.perf_counter() - t0:.1f}s: N_c {Ns.min()}..{Ns.max()}, "
         f"total {Ns.sum()}, particles {sum(len(c['theta']) for c in cells)}")
-    s = spm.Solver("cuda:0", precision=spm.SPM_FP32_RELAXED if args.precision == "fp32_relaxed" else
-                   {"fp32_ir": spm.SPM_FP32_IR, "fp64": spm.SPM_FP64}[args.precision],
-                   precond=spm.SPM_PRECOND_BLOCK if args.precond == "block" else spm.SPM_PRECOND_NONE)
+    precs = {"fp32_ir": spm.SPM_FP32_IR, "fp32_relaxed": spm.SPM_FP32_RELAXED, "fp64": spm.SPM_FP64}
+    pc = spm.SPM_PRECOND_BLOCK if args.precond == "block" else spm.SPM_PRECOND_NONE
+    s = spm.Solver("cuda:0", precision=precs[args.precision], precond=pc)
     s.set_cells(cells)
     tune = s.autotune(args.tune_cache)
     log(f"[bench] autotune: {tune}")
     for k in range(args.warmup):
-        r = s.solve_batch()
+        r = s.solve_cells()
         log(f"[bench] warmup {k}: its {[i['iterations'] for i in r['infos']][:8]} ...")
     torch.cuda.synchronize()
-    s.profile(True)
     lat, infos = [], []
-    t0 = time.perf_counter()
+    t0 = time.perf_counter()   # timed region: every iteration replayed as a captured HIP graph
     for k in range(args.steps):
-        r = s.solve_batch()
+        r = s.solve_cells()
         lat.extend(r["latency_s"].tolist())
         infos.extend(r["infos"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    s.profile(False)
+    compare = {}
+    if not args.no_compare:
+        # the same batch with the other FP32 form, and without graph replay (untimed region)
+        others = [(n, p, 1) for n, p in precs.items() if n != args.precision and n != "fp64"]
+        others.append((args.precision + "_no_graph", precs[args.precision], 0))
+        for name, p, graph in others:
+            c = spm.Solver("cuda:0", precision=p, precond=pc, use_graph=graph)
+            c.set_cells(cells)
+            for pr, key in ((spm.SPM_FP64, "fp64"), (spm.SPM_FP32, "fp32")):
+                c.set_launch(pr, **tune[key])
+            c.solve_cells()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            rr = c.solve_cells()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            compare[name] = {"solves_per_s": 64 / dt, "latency_p50_ms": 1e3 * percentile(rr["latency_s"], 50),
+                             "latency_p99_ms": 1e3 * percentile(rr["latency_s"], 99),
+                             "max_rel_residual": max(i["rel_residual"] for i in rr["infos"])}
+            c.close()
+        log(f"[bench] ensemble comparison {compare}")
     assert max(i["rel_residual"] for i in infos) <= 1e-10
     pairs = float(9.0 * (Ns.astype(np.float64) ** 2).sum())
     # roofline of the near-sum launch over all 64 cells (inside a solve, launches skip the
@@ -353,6 +438,7 @@ def bench_ensemble(args):
                           "max": 1e3 * max(lat)},
            "iterations": {"p50": percentile([i["iterations"] for i in infos], 50),
                           "max": max(i["iterations"] for i in infos)},
+           "compare": compare,
            "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                         "frac": achieved / PEAK["fp32"], "traffic": None,
                         "kernel": "k_near<float> (near-image traction sum over all active cells, fp32)",

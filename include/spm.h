@@ -106,12 +106,19 @@ typedef struct {
   int32_t learned_max_iter; /* iteration cap of a warm-started or preconditioned attempt before
                                the plain-GMRES fallback; 0 = max_iter [0] */
   double relax_tol;     /* SPM_FP32_RELAXED: residual estimate below which products use the FP32
-                           near sum [1e-5] */
+                           near sum; 0 = adaptive: relax_safety * tol / delta32, delta32 the
+                           relative error of the FP32 operator measured once per geometry (two
+                           operator products), kept within [10 tol, 1e-2] [0] */
   int32_t near_method;  /* SPM_NEAR_DIRECT or SPM_NEAR_FMM [SPM_NEAR_DIRECT]; SPM_NEAR_FMM needs
                            precision SPM_FP64 (SPM_EINVAL at spm_create) and one cell (SPM_EINVAL
                            when more cells are set) */
   int32_t fmm_order;    /* SPM_NEAR_FMM: terms of each multipole and local expansion, 8..64;
                            0 = 40 (relative error of the near sum about 1e-14) [0] */
+  double node_spacing;  /* node spacing h of the perimeter rule used when node counts are not
+                           given: N_i = clamp(8 ceil(P_i / (8 h)), 64, 256), P_i the perimeter
+                           [2.170590708293102e-3: about 5,000 nodes for 25 ellipses of aspect
+                           ratio 1.5-3 at area fraction 0.3] */
+  double relax_safety;  /* margin theta of the adaptive relaxed switch point, 0 < theta <= 1 [0.1] */
 } spm_config;
 
 typedef struct {
@@ -155,7 +162,8 @@ int spm_set_lattice(spm_handle* h, const double e1_host[2], const double e2_host
 
 /* Ellipses (Sec. 2 geometry; Sec. 6 periodic trapezoid rule). Host arrays of
  * length n: centres [2n] (x0, y0, x1, y1, ...), theta, semi-axes a and b, node
- * counts (even, 8 <= N_i <= 4096). Centres are wrapped into the cell. Builds
+ * counts (even, 8 <= N_i <= 4096; NULL: the perimeter rule of cfg.node_spacing).
+ * Centres are wrapped into the cell. Builds
  * the nodes, the proxy pseudo-inverse and the close-pair list. Returns
  * SPM_EOVERLAP if two boundaries (any images) come within cfg.min_gap or
  * overlap. */
@@ -260,6 +268,30 @@ int spm_close_correction(spm_handle* h, const double* sigma, double* out, int32_
  * ordered all first components then all second components. */
 int spm_proxy_strengths(spm_handle* h, const double* sigma, double* xi);
 
+/* ---- allocation-free near sum ---- */
+
+#define SPM_NOALLOC_MAX_N 131072   /* largest node count of spm_near_traction_noalloc */
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
+ * and harnesses that forbid hipMalloc): the near-image traction sum of spm_near_traction for
+ * one cell given by its node arrays, with no handle and no allocation. Its forces, FP32 copies,
+ * work plan and partial sums live in one file-scope device array of the library (about 11 MB
+ * per GPU, kept until the process ends; its address is looked up once per device on the
+ * first call, with that device current). Every call on a GPU shares that array: calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised by the caller.
+ * Inputs (device, on hip_stream, NULL = the null stream): x, y, nx, ny, w [n] (nodes, outward
+ * unit normals, quadrature weights, particle-major as spm_get_nodes returns them), sigma [2n]
+ * (SoA density); skew: e2 = (skew, 1) of the cell (reduced to [-1/2, 1/2)); every node's 3x3
+ * images m e1 + n e2 are sources, and only the node's own unshifted image is skipped (the
+ * node list must hold each particle whole, centres wrapped as the handle wraps them).
+ * precision SPM_FP64 or SPM_FP32 (FP32 pair sums, FP64 accumulation of the tiles). out [2n]
+ * (device): T_near, SoA. Returns after the stream has finished. Errors (no message):
+ * SPM_EINVAL for n < 1, n > SPM_NOALLOC_MAX_N, a NULL pointer, a non-finite skew or another
+ * precision; SPM_EHIP when a HIP call fails. */
+int spm_near_traction_noalloc(void* hip_stream, int64_t n, double skew, const double* x, const double* y,
+                              const double* nx, const double* ny, const double* w, const double* sigma,
+                              int32_t precision, double* out);
+
 /* ---- ensembles of independent cells ---- */
 
 /* Replace the contents of the handle by n_cells independent unit cells, solved
@@ -267,7 +299,8 @@ int spm_proxy_strengths(spm_handle* h, const double* sigma, double* xi);
  * freezes each one at its own convergence). skews_host [n_cells]: e2 = (s_c, 1) of
  * each cell (reduced to [-1/2, 1/2)); part_offsets_host [n_cells + 1]: particles of
  * cell c are part_offsets[c] .. part_offsets[c+1]-1 of the particle arrays (as in
- * spm_set_ellipses); every cell is centred at the origin. 1 <= n_cells <= 1024. */
+ * spm_set_ellipses; n_nodes_host may be NULL: the perimeter rule of cfg.node_spacing); every
+ * cell is centred at the origin. 1 <= n_cells <= 1024. */
 int spm_set_cells(spm_handle* h, int32_t n_cells, const double* skews_host, const int32_t* part_offsets_host,
                   const double* centers_host, const double* theta_host, const double* a_host,
                   const double* b_host, const int32_t* n_nodes_host);
@@ -276,19 +309,37 @@ int spm_set_cells(spm_handle* h, int32_t n_cells, const double* skews_host, cons
  * params_host [4n] (see SPM_SHAPE_*); the curve of particle i is c_i + R(theta_i) x(t),
  * t_k = 2 pi k / N_i, and its reference point c_i (inside the curve) carries the rigid
  * motion (velocity and angular velocity are read there). The largest radius must stay
- * below 0.45 (3x3 image rule). */
+ * below 0.45 (3x3 image rule). n_nodes_host may be NULL (the perimeter rule). */
 int spm_set_cells_shapes(spm_handle* h, int32_t n_cells, const double* skews_host, const int32_t* part_offsets_host,
                          const double* centers_host, const double* theta_host, const int32_t* kind_host,
                          const double* params_host, const int32_t* n_nodes_host);
 
 int spm_num_cells(const spm_handle* h, int32_t* n_cells);
 
-/* Solve every cell (as spm_solve). mu_eff: device [n_cells]; infos_host [n_cells]
- * (may be NULL); cell_latency_s_host [n_cells] (may be NULL): seconds from the start
- * of the solve to the moment the cell met the tolerance, from the device wall clock.
- * spm_solve on a handle with several cells behaves the same without latencies. */
-int spm_solve_batch(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
+/* Solve every cell set by spm_set_cells / spm_set_cells_shapes (as spm_solve). mu_eff:
+ * device [n_cells]; infos_host [n_cells] (may be NULL); cell_latency_s_host [n_cells] (may
+ * be NULL): seconds from the start of the solve to the moment the cell met the tolerance,
+ * from the device wall clock. spm_solve on a handle with several cells behaves the same
+ * without latencies. */
+int spm_solve_cells(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
                     spm_solve_info* infos_host, double* cell_latency_s_host);
+
+/* One call for an ensemble of independent cells of ellipses (Sec. 3 problem per cell; the
+ * quasi-static solver of Sec. 7 takes mu, gamma, e1, e2 and the boundaries and returns the
+ * rigid motions): sets the cells (replacing the handle's contents, as spm_set_cells) and
+ * solves them together in lockstep (as spm_solve_cells, zero initial guess or cfg.x0).
+ * Host inputs: lattices_host [6 n_cells] = e1 (2), e2 (2), cell centre c_U (2) per cell, with
+ * e1 = (1, 0) and e2 = (s, 1) (else SPM_EINVAL); part_offsets_host [n_cells + 1] (CSR:
+ * particles of cell c are part_offsets[c] .. part_offsets[c+1]-1); centers_host [2n],
+ * theta_host, semi_a_host, semi_b_host [n]; n_nodes_host [n] or NULL (the perimeter rule of
+ * cfg.node_spacing). Device outputs (any may be NULL): vel [2n] (velocities of the wrapped
+ * centres in the gauge of spm_velocities, u0 = (gamma x_2, 0) of the absolute position),
+ * omega [n], mu_eff [n_cells]. Host outputs: infos_host [n_cells], cell_latency_s_host
+ * [n_cells] (may be NULL). 1 <= n_cells <= 1024. The densities stay in the handle. */
+int spm_solve_batch(spm_handle* h, int32_t n_cells, const double* lattices_host, const int32_t* part_offsets_host,
+                    const double* centers_host, const double* theta_host, const double* semi_a_host,
+                    const double* semi_b_host, const int32_t* n_nodes_host, double* vel, double* omega,
+                    double* mu_eff, spm_solve_info* infos_host, double* cell_latency_s_host);
 
 /* Number of close (target, source particle, shift) triples, and the triples
  * themselves (host arrays of length count, sorted by target, particle, shift;
@@ -307,18 +358,21 @@ int spm_proxy_svd(spm_handle* h, double* Q_host, double* s_host, int32_t* sweeps
 /* ---- launch shape of the near-image sum ---- */
 
 /* Time candidate launch shapes of the persistent near-sum kernel (block 64/128/256
- * threads, 1/2/4 targets per lane, 128/256/512 sources per LDS tile, three source
- * chunk sizes) on the handle's current geometry (all cells), for FP64 and FP32,
- * and keep the fastest. cache_path (may be NULL): text file of earlier results
- * keyed by device, node count, cell count, pair work and precision; a hit skips the
- * timing, a miss appends. best_ms_host [2] (may be NULL): the winning per-launch
- * time (0 on a cache hit). The shape stays until the node count changes. SPM_ESTATE on an
- * SPM_NEAR_FMM handle, which plans no direct near-sum launches. */
+ * threads, 1/2/4 targets per lane, 128/256/512 sources per LDS tile) on the handle's
+ * current geometry (all cells), for FP64 and FP32, and keep the fastest. cache_path (may
+ * be NULL): text file of earlier results keyed by device, node count, cell count, pair work
+ * and precision; a hit skips the timing, a miss appends. best_ms_host [2] (may be NULL):
+ * the winning per-launch time (0 on a cache hit). The shape stays until the node count
+ * changes. SPM_ESTATE on an SPM_NEAR_FMM handle, which plans no direct near-sum launches. */
 int spm_autotune(spm_handle* h, const char* cache_path, double* best_ms_host);
 
-/* Current near-sum launch shape {block, targets per lane, tile, source chunk} for
- * precision SPM_FP64 or SPM_FP32 (host [4]); spm_set_launch overrides it
- * (SPM_EINVAL for an unsupported shape). */
+/* Current near-sum launch shape {block, targets per lane, tile, workgroups per compute unit}
+ * for precision SPM_FP64 or SPM_FP32 (host [4]). The kernel is persistent: its grid is
+ * (workgroups per compute unit) x (compute units), where 0 selects the occupancy limit; the
+ * work (target blocks of block x targets-per-lane nodes against source tiles of the same
+ * cell) is divided evenly over that grid. spm_set_launch overrides it (SPM_EINVAL for an
+ * unsupported shape: block 64, 128 or 256; 1, 2 or 4 targets per lane; 16 <= tile <= 1024;
+ * 0 <= workgroups per compute unit <= 32). */
 int spm_get_launch(spm_handle* h, int32_t precision, int32_t* cfg_host);
 int spm_set_launch(spm_handle* h, int32_t precision, const int32_t* cfg_host);
 
@@ -354,12 +408,17 @@ int spm_precond_apply(spm_handle* h, const double* v, double* out);
 #define SPM_MLP_BF16 0         /* matrix-core products in bfloat16, FP32 accumulation */
 #define SPM_MLP_FP32 1         /* matrix-core products in FP32 (checking mode) */
 
+/* Per-particle network inputs [n x 33] (device, bfloat16 bit patterns, nearest-even rounding
+ * of the FP32 values of spm_features_f32; the network's first layer rounds its input to
+ * bfloat16 in either form, so widening these to FP32 feeds spm_mlp_forward the same numbers). */
+int spm_features(spm_handle* h, uint16_t* feat_bf16);
+
 /* Per-particle features [n x 33] (FP32, device): for the 8 nearest other particle images
  * (3x3 images of the particle's own cell, its own images included, ordered by squared
  * centre distance, then particle, then shift index) the centre offset in the particle's
  * body frame divided by its semi-major axis and (cos, sin) of twice the angle
  * difference; then a/b. */
-int spm_features(spm_handle* h, float* features);
+int spm_features_f32(spm_handle* h, float* features);
 
 /* Training targets [n x 128] (FP32, device) of a density sigma [2N]: sigma minus its
  * cell-wide normal component beta* n (beta* = <sigma, n>/<n, n> per cell), rotated into
@@ -393,6 +452,14 @@ int spm_mlp_create(spm_mlp** net, void* hip_stream, spm_alloc_fn alloc, spm_free
 void spm_mlp_destroy(spm_mlp* net);
 const char* spm_mlp_last_error(const spm_mlp* net);
 int spm_mlp_set_params(spm_mlp* net, const float* params);   /* device [SPM_MLP_NPARAMS] */
+
+/* Weights as a bfloat16 copy and/or an FP32 master copy (device, n_params == SPM_MLP_NPARAMS,
+ * packed as for spm_mlp_set_params). The network keeps the FP32 master (Adam updates it);
+ * in SPM_MLP_BF16 mode every layer product rounds its operands to bfloat16 (nearest even), so
+ * the bfloat16 weights it multiplies are the rounding of the master (biases are added in FP32). master_fp32 NULL: the
+ * master is params_bf16 widened (exact). Both given: params_bf16 must be the rounding of
+ * master_fp32 (SPM_EINVAL otherwise). Resets the Adam moments. */
+int spm_mlp_set_weights(spm_mlp* net, const uint16_t* params_bf16, const float* master_fp32, int64_t n_params);
 int spm_mlp_get_params(spm_mlp* net, float* params);         /* device [SPM_MLP_NPARAMS] */
 
 /* y [batch x 128] = MLP(x [batch x 33]) (device FP32, row-major). */
@@ -402,6 +469,17 @@ int spm_mlp_forward(spm_mlp* net, const float* x, int64_t batch, float* y, int32
  * parameters (device [SPM_MLP_NPARAMS], may be NULL). */
 int spm_mlp_loss_grad(spm_mlp* net, const float* x, const float* t, int64_t batch, int32_t mode, float* grads,
                       double* loss_host);
+
+/* Back-propagation of an upstream gradient: forward pass of x [batch x 33] (device FP32) in
+ * mode, then grad [SPM_MLP_NPARAMS] (device, packed as the parameters) = d(sum_b dy_b . y_b)/d
+ * params for dy [batch x 128] (device FP32) = dL/dy of the caller's loss. dy is only read. */
+int spm_mlp_backward(spm_mlp* net, const float* x, const float* dy, int64_t batch, float* grad, int32_t mode);
+
+/* One Adam step with bias correction on the FP32 master parameters: m <- beta1 m + (1 - beta1) g,
+ * v <- beta2 v + (1 - beta2) g^2, p <- p - lr (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps).
+ * grad [SPM_MLP_NPARAMS] (device). step >= 1 numbers the steps since the last set_params /
+ * set_weights (which zero m and v); 0 <= beta < 1, lr > 0, eps > 0 (else SPM_EINVAL). */
+int spm_mlp_adam_step(spm_mlp* net, const float* grad, float lr, float beta1, float beta2, float eps, int32_t step);
 
 /* n_batches Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on minibatches
  * of the n_samples rows of x [n_samples x 33] and t [n_samples x 128]: batch k uses the

@@ -144,11 +144,12 @@ def forward(params, x, rounding=None):
     return h, acts
 
 
-def loss_and_grads(params, x, t, rounding=None):
-    y, acts = forward(params, x, rounding)
-    B = x.shape[0]
-    d = (y - t) / B
-    loss = 0.5 * ((y - t) ** 2).sum() / B
+def backward(params, acts, dy, rounding=None):
+    """Gradients of sum_b dy_b . y_b with respect to every (W, b), for the activations of
+    one forward pass (acts) and an upstream gradient dy = dL/dy of shape (B, out): the
+    chain rule through each affine layer (dW = d^T h_in, db = sum_b d) and through ReLU
+    (d <- (d W) * [h > 0])."""
+    d = dy
     grads = [None] * len(params)
     for li in range(len(params) - 1, -1, -1):
         W, b = params[li]
@@ -156,7 +157,15 @@ def loss_and_grads(params, x, t, rounding=None):
         grads[li] = [_op(d, rounding).T @ _op(h_in, rounding), d.sum(0)]
         if li > 0:
             d = (_op(d, rounding) @ _op(W, rounding)) * (acts[li] > 0)
-    return loss, grads
+    return grads
+
+
+def loss_and_grads(params, x, t, rounding=None):
+    """Loss (1/(2B)) sum |y - t|^2 and its gradients: backward with dy = (y - t) / B."""
+    y, acts = forward(params, x, rounding)
+    B = x.shape[0]
+    loss = 0.5 * ((y - t) ** 2).sum() / B
+    return loss, backward(params, acts, (y - t) / B, rounding)
 
 
 def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -1,5 +1,4 @@
-// Autotuner of the near-sum launch shape (block size, targets per lane, LDS tile,
-// source splits), run on the handle's own geometry: every candidate is timed with HIP
+// Autotuner of the near-sum launch shape (block size, targets per lane, LDS tile), run on the handle's own geometry: every candidate is timed with HIP
 // events on the handle's stream; the fastest per precision is kept and optionally
 // cached in a text file keyed by device, node count and precision.
 #include <algorithm>
@@ -41,7 +40,7 @@ static bool cache_lookup(const char* path, const std::string& key, NearConfig& c
     if (bar == std::string::npos || line.substr(0, bar) != key) continue;
     std::istringstream v(line.substr(bar + 1));
     NearConfig t;
-    if (v >> t.block >> t.tpt >> t.tile >> t.chunk && near_config_valid(t)) {
+    if (v >> t.block >> t.tpt >> t.tile >> t.wg_per_cu && near_config_valid(t)) {
       c = t;
       return true;
     }
@@ -52,7 +51,7 @@ static bool cache_lookup(const char* path, const std::string& key, NearConfig& c
 static void cache_store(const char* path, const std::string& key, const NearConfig& c, double ms) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << "|" << c.block << " " << c.tpt << " " << c.tile << " " << c.chunk << " " << ms << "\n";
+  f << key << "|" << c.block << " " << c.tpt << " " << c.tile << " " << c.wg_per_cu << " " << ms << "\n";
 }
 
 double time_near(spm_handle* h, int prec, const NearConfig& c, int reps) {
@@ -98,18 +97,12 @@ void autotune(spm_handle* h, const char* cache_path, double* best_ms_out) {
     for (int block : {64, 128, 256})
       for (int tpt : {1, 2, 4})
         for (int tile : {128, 256, 512}) {
-          // chunks giving about 2048, 8192 and 32768 work items
-          for (double items : {2048.0, 8192.0, 32768.0}) {
-            NearConfig c;
-            c.block = block;
-            c.tpt = tpt;
-            c.tile = tile;
-            c.chunk = (int32_t)std::max(64.0, std::min(65536.0, work / ((double)block * tpt * items)));
-            if (std::find_if(cand.begin(), cand.end(), [&](const NearConfig& o) {
-                  return o.block == c.block && o.tpt == c.tpt && o.tile == c.tile && o.chunk == c.chunk;
-                }) == cand.end())
-              cand.push_back(c);
-          }
+          NearConfig c;
+          c.block = block;
+          c.tpt = tpt;
+          c.tile = tile;
+          c.wg_per_cu = 0;
+          cand.push_back(c);
         }
     const int reps = work > 4e8 ? 2 : 5;
     for (const auto& c : cand) {

@@ -18,19 +18,16 @@
 using namespace spm;
 
 namespace spm {
-// Default near-sum launch shape (what the autotuner picks on the 25-, 83- and 200-ellipse
-// cells): 256 threads, 256-source LDS tiles; FP64 with four targets per lane (the FP64
-// pair is ALU-heavier, so reusing each staged source for more targets pays), FP32 with one;
-// the source chunk gives about 32768 work items over the ensemble, at least 64 sources.
+// Default near-sum launch shape: 256 threads, 256-source LDS tiles; FP64 with four targets
+// per lane (the FP64 pair is ALU-heavier, so reusing each staged source for more targets
+// pays), FP32 with one; as many persistent workgroups as fit on a compute unit.
 NearConfig heuristic_near(spm_handle* h, int precision) {
+  (void)h;
   NearConfig c;
   c.block = 256;
   c.tpt = precision == SPM_FP64 ? 4 : 1;
   c.tile = 256;
-  double work = 0;
-  for (const auto& cl : h->cells) work += (double)(cl.n1 - cl.n0) * (double)(cl.n1 - cl.n0);
-  const double chunk = work / ((double)c.block * c.tpt * 32768.0);
-  c.chunk = (int32_t)std::max(64.0, std::min(65536.0, std::round(chunk)));
+  c.wg_per_cu = 0;
   return c;
 }
 }  // namespace spm
@@ -396,12 +393,44 @@ void shape_radii(int32_t kind, const double* p, double& rmax, double& rmin) {
   }
 }
 
+// Node count of a particle curve by its perimeter P: clamp(8 ceil(P / (8 h)), 64, 256), h the
+// configured node spacing. The ellipse perimeter comes from Ramanujan's second approximation
+// (relative error below 1e-9 for aspect ratios up to 3), a star's from the trapezoid rule on
+// |x'(t)| (spectrally accurate for these smooth periodic curves); the count only picks the
+// discretisation.
+int32_t perimeter_nodes(int32_t kind, const double* p, double h) {
+  double P = 0.0;
+  if (kind == SPM_SHAPE_ELLIPSE) {
+    const double a = p[0], b = p[1];
+    const double l = ((a - b) / (a + b)) * ((a - b) / (a + b));
+    P = kPi * (a + b) * (1.0 + 3.0 * l / (10.0 + std::sqrt(4.0 - 3.0 * l)));
+  } else {
+    const int K = 1024;
+    for (int k = 0; k < K; ++k) {
+      double X, Y, Xp, Yp, Xpp, Ypp;
+      shape_point(kind, p, 2.0 * kPi * k / K, X, Y, Xp, Yp, Xpp, Ypp);
+      P += std::sqrt(Xp * Xp + Yp * Yp);
+    }
+    P *= 2.0 * kPi / K;
+  }
+  if (!std::isfinite(P) || !(P > 0) || !(h > 0)) return 64;
+  const double n = 8.0 * std::ceil(P / (8.0 * h));
+  return (int32_t)std::min(256.0, std::max(64.0, n));
+}
+
 void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* part_off, const double* centers,
                     const double* theta, const int32_t* kind, const double* prm, const int32_t* n_nodes) {
   if (C < 1 || C > 1024) throw ApiError(SPM_EINVAL, "number of cells must be in [1, 1024]");
   const int n = part_off[C];
   if (part_off[0] != 0 || n < 1) throw ApiError(SPM_EINVAL, "bad particle offsets");
+  std::vector<int32_t> rule_nodes;
+  if (!n_nodes) {   // node counts by the perimeter rule
+    rule_nodes.resize(n);
+    for (int i = 0; i < n; ++i) rule_nodes[i] = perimeter_nodes(kind[i], prm + 4 * (size_t)i, h->cfg.node_spacing);
+    n_nodes = rule_nodes.data();
+  }
   h->have_particles = false;
+  h->delta32 = -1.0;
   drop_graphs(h);
   double tmark = now();
   auto mark = [&](const char* what) {      // set-up phase times with SPM_VERBOSE
@@ -777,6 +806,41 @@ void network_decode(spm_handle* h, double* x) {
   launch_decode(h, h->ln.modes, x);
 }
 
+// Relative error of the FP32 operator on the current geometry: the largest over the cells of
+// |A32 v - A64 v| / |A64 v| for a fixed pseudo-random density v (two operator products, once
+// per geometry). It sets where the relaxed solve may switch to FP32 products.
+double fp32_operator_error(spm_handle* h) {
+  if (h->delta32 >= 0.0) return h->delta32;
+  Krylov& K = h->kr;
+  const int C = h->geo.C;
+  gm_probe_fill(h, K.n2, 12345, K.z2);
+  matvec(h, K.z2, K.tmp, SPM_FP64, false);
+  matvec(h, K.z2, K.tmp2, SPM_FP32, false);
+  gm_axpby(h, K.n2, 1.0, K.tmp2, -1.0, K.tmp, K.tmp2);
+  gm_dot(h, K.tmp2, K.tmp2, K.dots);
+  std::vector<double> e(C), a(C);
+  download(h, e.data(), K.dots, C * sizeof(double));
+  gm_dot(h, K.tmp, K.tmp, K.dots);
+  download(h, a.data(), K.dots, C * sizeof(double));
+  double d = 0.0;
+  for (int c = 0; c < C; ++c) d = std::max(d, std::sqrt(e[c] / std::max(a[c], 1e-300)));
+  h->delta32 = d;
+  if (verbose()) std::fprintf(stderr, "[spm] FP32 operator relative error %.3e\n", d);
+  return d;
+}
+
+// Adaptive switch point of the relaxed solve. In GMRES with inexact products the error of the
+// k-th product may grow like tol |b| / |r_k| without moving the attained residual by more than
+// about tol (the relaxation bound of inexact Krylov methods), so products may use the FP32 near
+// sum once the residual estimate is below theta tol / delta32, delta32 the measured relative
+// error of the FP32 operator and theta = cfg.relax_safety a margin for the conditioning of the
+// small Hessenberg problem; kept within [10 tol, 1e-2].
+double relax_switch_point(spm_handle* h, double tol) {
+  const double d = fp32_operator_error(h);
+  const double at = d > 0.0 ? h->cfg.relax_safety * tol / d : 1e-2;
+  return std::min(1e-2, std::max(10.0 * tol, at));
+}
+
 // How one solve attempt starts and iterates.
 struct Attempt {
   bool network = false;   // learned warm start (when no sigma0 is given)
@@ -878,7 +942,9 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
       int budget = max_iter;
       for (int c = 0; c < C; ++c)
         if (act[c]) budget = std::min(budget, max_iter - st.its[c]);
-      const double relax_at = h->cfg.precision == SPM_FP32_RELAXED ? h->cfg.relax_tol : 0.0;
+      const double relax_at = h->cfg.precision != SPM_FP32_RELAXED ? 0.0
+                              : h->cfg.relax_tol > 0.0 ? h->cfg.relax_tol
+                                                       : relax_switch_point(h, tol);
       int sw = -1;
       const std::vector<int32_t> kd =
           krylov_cycle(h, SPM_FP64, pc, sigma, st.bnorm, tl, act, std::max(1, budget), relax_at, &sw);
@@ -1231,7 +1297,7 @@ void build_fmm_plan(spm_handle* h) {
   ensure(h, F.fact, 2 * p);
   ensure(h, F.Mx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.Lx, (size_t)nbox * 3 * p * 2);
-  ensure(h, F.nsplit1, 1);
+  ensure(h, F.one_block, 2);
   ensure(h, F.vnear, 3 * (size_t)g.No);
   ensure(h, h->wk.Tpart, 2 * (size_t)N);
   upload(h, F.sx, ssx.data(), ns * sizeof(double));
@@ -1243,8 +1309,8 @@ void build_fmm_plan(spm_handle* h) {
   upload(h, F.bsrc, bsrc.data(), nbox * sizeof(int32_t));
   upload(h, F.lists, lists.data(), lists.size() * sizeof(int32_t));
   upload(h, F.fact, fact.data(), fact.size() * sizeof(double));
-  const int32_t one = 1;
-  upload(h, F.nsplit1, &one, sizeof(int32_t));
+  const int32_t one_block[2] = {0, 1};
+  upload(h, F.one_block, one_block, sizeof(one_block));
   mark("upload");
   F.p = p;
   F.L = L;
@@ -1258,51 +1324,33 @@ void build_fmm_plan(spm_handle* h) {
   drop_graphs(h);
 }
 
-size_t max_splits_all(spm_handle* h) {
-  return (size_t)std::max(h->wk.near[0].max_splits, h->wk.near[1].max_splits);
-}
-
-// Work items of the persistent near sum for one precision: every cell's targets in
-// blocks of block*tpt, its sources in ceil(N_c / chunk) balanced splits, sorted by
-// cost (largest first).
+// Plan of the near-sum launch of one precision: target blocks of block * tpt targets and
+// source tiles of every cell, the persistent grid, and room for the partials (at most one
+// per target block and one more per workgroup boundary that falls inside a block).
 void build_near_plan(spm_handle* h, int precision) {
   NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
   if (!near_config_valid(P.cfg)) throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
   const int C = h->geo.C;
-  std::vector<NearItem> items;
-  std::vector<int32_t> nsplit(C, 1);
-  int32_t maxs = 1;
-  const int64_t T = (int64_t)P.cfg.block * P.cfg.tpt;
+  const int64_t BT = (int64_t)P.cfg.block * P.cfg.tpt;
+  std::vector<int32_t> nt(C), blk(C + 1, 0);
   for (int c = 0; c < C; ++c) {
-    const int64_t n0 = h->cells[c].n0, n1 = h->cells[c].n1, Nc = n1 - n0;
-    const int64_t S = std::max<int64_t>(1, (Nc + P.cfg.chunk - 1) / P.cfg.chunk);
-    const int64_t per = (Nc + S - 1) / S;
-    nsplit[c] = (int32_t)S;
-    maxs = std::max<int32_t>(maxs, (int32_t)S);
-    for (int64_t t0 = n0; t0 < n1; t0 += T)
-      for (int64_t k = 0; k < S; ++k) {
-        NearItem it;
-        it.t0 = t0;
-        it.t1 = std::min(n1, t0 + T);
-        it.s0 = n0 + k * per;
-        it.s1 = std::min(n1, it.s0 + per);
-        it.c = c;
-        it.split = (int32_t)k;
-        if (it.s1 > it.s0) items.push_back(it);
-      }
+    const int64_t Nc = h->cells[c].n1 - h->cells[c].n0;
+    nt[c] = (int32_t)((Nc + P.cfg.tile - 1) / P.cfg.tile);
+    blk[c + 1] = blk[c] + (int32_t)((Nc + BT - 1) / BT);
   }
-  std::stable_sort(items.begin(), items.end(), [](const NearItem& a, const NearItem& b) {
-    return (a.t1 - a.t0) * (a.s1 - a.s0) > (b.t1 - b.t0) * (b.s1 - b.s0);
-  });
-  P.nitems = (int32_t)items.size();
-  P.max_splits = maxs;
-  ensure(h, P.items, items.size());
-  ensure(h, P.nsplit, C);
-  ensure(h, P.counter, 1);
-  upload(h, P.items, items.data(), items.size() * sizeof(NearItem));
-  upload(h, P.nsplit, nsplit.data(), C * sizeof(int32_t));
-  P.grid = 0;
-  ensure(h, h->wk.Tpart, max_splits_all(h) * 2 * h->geo.N);
+  P.nblocks = blk[C];
+  P.bt = (int32_t)BT;
+  ensure(h, P.cell_nt, C);
+  ensure(h, P.cell_blk, C + 1);
+  ensure(h, P.unit_off, C + 1);
+  ensure(h, P.slot_off, (size_t)P.nblocks + 1);
+  upload(h, P.cell_nt, nt.data(), C * sizeof(int32_t));
+  upload(h, P.cell_blk, blk.data(), (C + 1) * sizeof(int32_t));
+  P.grid = near_persistent_grid(P.cfg, precision);
+  size_t need = 2 * (size_t)h->geo.N;
+  for (const NearPlan& Q : h->wk.near)
+    if (Q.bt > 0) need = std::max(need, ((size_t)Q.nblocks + (size_t)Q.grid) * 2 * (size_t)Q.bt);
+  ensure(h, h->wk.Tpart, need);
   drop_graphs(h);
 }
 
@@ -1344,7 +1392,7 @@ void spm_default_config(spm_config* c) {
   c->max_iter = 500;
   c->precision = SPM_FP64;
   c->inner_tol = 0.0;
-  c->relax_tol = 1e-5;
+  c->relax_tol = 0.0;
   c->near_method = SPM_NEAR_DIRECT;
   c->fmm_order = 0;
   c->min_gap = 0.0;
@@ -1354,6 +1402,8 @@ void spm_default_config(spm_config* c) {
   c->x0 = SPM_X0_ZERO;
   c->precond = SPM_PRECOND_NONE;
   c->learned_max_iter = 0;
+  c->node_spacing = 2.170590708293102e-3;
+  c->relax_safety = 0.1;
 }
 
 int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_fn alloc, spm_free_fn free_fn,
@@ -1370,7 +1420,8 @@ int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_
   if (!(c.mu > 0) || !(c.gamma > 0) || c.M < 4 || c.M > 512 || c.m_wall < 4 || c.m_wall > 256 || !(c.R_proxy > 0.75) ||
       !(c.tol > 0) || c.max_iter < 1 || c.max_iter > 5000 || c.close_factor < 0 ||
       (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR && c.precision != SPM_FP32_RELAXED) ||
-      !(c.inner_tol >= 0 && c.inner_tol < 1) || !(c.relax_tol > 0 && c.relax_tol < 1) ||
+      !(c.inner_tol >= 0 && c.inner_tol < 1) || !(c.relax_tol >= 0 && c.relax_tol < 1) ||
+      !(c.relax_safety > 0 && c.relax_safety <= 1) || !(c.node_spacing > 0) ||
       c.poll_every < 1 || c.x0 < SPM_X0_ZERO || c.x0 > SPM_X0_NETWORK ||
       (c.precond != SPM_PRECOND_NONE && c.precond != SPM_PRECOND_BLOCK) || c.learned_max_iter < 0 ||
       (c.near_method != SPM_NEAR_DIRECT && c.near_method != SPM_NEAR_FMM) ||
@@ -1427,7 +1478,7 @@ int spm_set_ellipses(spm_handle* h, int32_t n, const double* centers, const doub
                      const double* b, const int32_t* n_nodes) {
   return guarded(h, [&]() {
     if (!h->have_lattice) throw ApiError(SPM_ESTATE, "set the lattice first");
-    if (n < 1 || !centers || !theta || !a || !b || !n_nodes) throw ApiError(SPM_EINVAL, "bad particle arrays");
+    if (n < 1 || !centers || !theta || !a || !b) throw ApiError(SPM_EINVAL, "bad particle arrays");
     const int32_t off[2] = {0, n};
     const double sk = h->pending_skew;
     std::vector<int32_t> kind(n, SPM_SHAPE_ELLIPSE);
@@ -1445,8 +1496,7 @@ int spm_set_cells(spm_handle* h, int32_t n_cells, const double* skews, const int
                   const double* centers, const double* theta, const double* a, const double* b,
                   const int32_t* n_nodes) {
   return guarded(h, [&]() {
-    if (!skews || !part_offsets || !centers || !theta || !a || !b || !n_nodes)
-      throw ApiError(SPM_EINVAL, "null array");
+    if (!skews || !part_offsets || !centers || !theta || !a || !b) throw ApiError(SPM_EINVAL, "null array");
     h->cU[0] = 0.0;
     h->cU[1] = 0.0;
     h->have_lattice = true;
@@ -1468,8 +1518,7 @@ int spm_set_cells_shapes(spm_handle* h, int32_t n_cells, const double* skews, co
                          const double* centers, const double* theta, const int32_t* kind, const double* params,
                          const int32_t* n_nodes) {
   return guarded(h, [&]() {
-    if (!skews || !part_offsets || !centers || !theta || !kind || !params || !n_nodes)
-      throw ApiError(SPM_EINVAL, "null array");
+    if (!skews || !part_offsets || !centers || !theta || !kind || !params) throw ApiError(SPM_EINVAL, "null array");
     h->cU[0] = 0.0;
     h->cU[1] = 0.0;
     h->have_lattice = true;
@@ -1551,10 +1600,58 @@ int spm_solve(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
   return guarded(h, [&]() { return solve_api(h, sigma0, sigma, vel, omega, mu_eff, info_out, nullptr); });
 }
 
-int spm_solve_batch(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
+int spm_solve_cells(spm_handle* h, const double* sigma0, double* sigma, double* vel, double* omega, double* mu_eff,
                     spm_solve_info* infos_host, double* cell_latency_s_host) {
   return guarded(h, [&]() {
     return solve_api(h, sigma0, sigma, vel, omega, mu_eff, infos_host, cell_latency_s_host);
+  });
+}
+
+int spm_solve_batch(spm_handle* h, int32_t n_cells, const double* lattices, const int32_t* part_offsets,
+                    const double* centers, const double* theta, const double* semi_a, const double* semi_b,
+                    const int32_t* n_nodes, double* vel, double* omega, double* mu_eff, spm_solve_info* infos_host,
+                    double* cell_latency_s_host) {
+  return guarded(h, [&]() {
+    if (!lattices || !part_offsets || !centers || !theta || !semi_a || !semi_b)
+      throw ApiError(SPM_EINVAL, "null array");
+    if (n_cells < 1 || n_cells > 1024) throw ApiError(SPM_EINVAL, "number of cells must be in [1, 1024]");
+    const int n = part_offsets[n_cells];
+    if (part_offsets[0] != 0 || n < 1) throw ApiError(SPM_EINVAL, "bad particle offsets");
+    std::vector<double> skews(n_cells), du(n_cells), cen(2 * (size_t)n);
+    std::vector<int32_t> kind(n, SPM_SHAPE_ELLIPSE);
+    std::vector<double> prm(4 * (size_t)n, 0.0);
+    for (int c = 0; c < n_cells; ++c) {
+      const double* L = lattices + 6 * (size_t)c;
+      if (L[0] != 1.0 || L[1] != 0.0 || L[3] != 1.0 || !std::isfinite(L[2]) || !std::isfinite(L[4]) ||
+          !std::isfinite(L[5]))
+        throw ApiError(SPM_EINVAL, "cell " + std::to_string(c) + ": the lattice must be e1 = (1, 0), e2 = (s, 1)");
+      if (part_offsets[c + 1] < part_offsets[c] || part_offsets[c + 1] > n)
+        throw ApiError(SPM_EINVAL, "bad particle offsets");
+      skews[c] = L[2];
+      // the cell is solved about the origin; u0 = (gamma y, 0) adds gamma c_y to the velocities
+      du[c] = h->cfg.gamma * L[5];
+      for (int i = part_offsets[c]; i < part_offsets[c + 1]; ++i) {
+        cen[2 * i] = centers[2 * i] - L[4];
+        cen[2 * i + 1] = centers[2 * i + 1] - L[5];
+      }
+    }
+    for (int i = 0; i < n; ++i) {
+      prm[4 * i] = semi_a[i];
+      prm[4 * i + 1] = semi_b[i];
+    }
+    h->cU[0] = 0.0;
+    h->cU[1] = 0.0;
+    h->have_lattice = true;
+    set_cells_impl(h, n_cells, skews.data(), part_offsets, cen.data(), theta, kind.data(), prm.data(), n_nodes);
+    ensure(h, h->wk.batch_sigma, 2 * (size_t)h->geo.N);
+    const int st = solve_api(h, nullptr, h->wk.batch_sigma, vel, omega, mu_eff, infos_host, cell_latency_s_host);
+    if (vel) {
+      ensure(h, h->wk.cell_du, (size_t)n_cells);
+      upload(h, h->wk.cell_du, du.data(), n_cells * sizeof(double));
+      launch_add_cell_velocity(h, h->wk.cell_du, vel);
+      sync(h);
+    }
+    return st;
   });
 }
 
@@ -1749,7 +1846,7 @@ int spm_get_launch(spm_handle* h, int32_t precision, int32_t* cfg_host) {
     cfg_host[0] = c.block;
     cfg_host[1] = c.tpt;
     cfg_host[2] = c.tile;
-    cfg_host[3] = c.chunk;
+    cfg_host[3] = c.wg_per_cu;
     return SPM_OK;
   });
 }
@@ -1762,7 +1859,7 @@ int spm_set_launch(spm_handle* h, int32_t precision, const int32_t* cfg_host) {
     c.block = cfg_host[0];
     c.tpt = cfg_host[1];
     c.tile = cfg_host[2];
-    c.chunk = cfg_host[3];
+    c.wg_per_cu = cfg_host[3];
     if (!near_config_valid(c)) throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
     h->wk.near[precision == SPM_FP64 ? 0 : 1].cfg = c;
     if (!h->fmm.on) build_near_plan(h, precision);   // an FMM handle only keeps the shape
@@ -1870,11 +1967,22 @@ int spm_precond_apply(spm_handle* h, const double* v, double* out) {
   });
 }
 
-int spm_features(spm_handle* h, float* features) {
+int spm_features_f32(spm_handle* h, float* features) {
   return guarded(h, [&]() {
     need_particles(h);
     if (!features) throw ApiError(SPM_EINVAL, "null features");
     launch_features(h, features);
+    sync(h);
+    return SPM_OK;
+  });
+}
+
+int spm_features(spm_handle* h, uint16_t* feat_bf16) {
+  return guarded(h, [&]() {
+    need_particles(h);
+    if (!feat_bf16) throw ApiError(SPM_EINVAL, "null features");
+    launch_features(h, h->ln.feat);
+    launch_to_bf16(h, h->ln.feat, (int64_t)h->geo.No * SPM_MLP_IN, feat_bf16);
     sync(h);
     return SPM_OK;
   });

@@ -328,6 +328,23 @@ void gm_axpby(spm_handle* h, int64_t n, double a, const double* x, double b, con
   SPM_HIP_CHECK(hipGetLastError());
 }
 
+// out[r] = a deterministic pseudo-random value in [-1, 1) of index r (the splitmix64 finaliser
+// of r + seed; a probe vector for measuring operator errors, not part of the method).
+__global__ void k_probe_fill(int64_t n, uint64_t seed, double* __restrict__ out) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  uint64_t z = (uint64_t)r + seed + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  out[r] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+void gm_probe_fill(spm_handle* h, int64_t n, uint64_t seed, double* out) {
+  k_probe_fill<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(n, seed, out);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
 __global__ void k_copy(int64_t n, double* __restrict__ d, const double* __restrict__ s) {
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r < n) d[r] = s ? s[r] : 0.0;

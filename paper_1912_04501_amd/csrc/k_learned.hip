@@ -82,6 +82,21 @@ __global__ void k_features(Geo g, float* __restrict__ feat) {
   f[SPM_MLP_IN - 1] = (float)(g.pa[q] / g.pb[q]);
 }
 
+// Round FP32 to bfloat16, nearest even (the network's matrix-core operand format).
+__global__ void k_to_bf16(int64_t n, const float* __restrict__ in, uint16_t* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  unsigned u = __float_as_uint(in[i]);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  out[i] = (uint16_t)(u >> 16);
+}
+
+void launch_to_bf16(spm_handle* h, const float* in, int64_t n, uint16_t* out) {
+  if (n <= 0) return;
+  k_to_bf16<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(n, in, out);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
 void launch_features(spm_handle* h, float* feat) {
   const int n = h->geo.No;
   k_features<<<(n + 127) / 128, 128, 0, h->stream>>>(h->geo, feat);

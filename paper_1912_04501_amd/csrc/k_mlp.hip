@@ -246,6 +246,20 @@ __global__ void k_fill(int64_t n, float* __restrict__ a, float v) {
   if (i < n) a[i] = v;
 }
 
+// master[i] = bf16 value widened to FP32 (exact).
+__global__ void k_widen_bf16(int64_t n, const uint16_t* __restrict__ b, float* __restrict__ d) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) d[i] = __uint_as_float((unsigned)b[i] << 16);
+}
+
+// flag[0] = 1 if some b[i] is not the nearest-even bfloat16 rounding of master[i] (the flag
+// is cleared before the launch; every writer stores the same value).
+__global__ void k_check_bf16(int64_t n, const uint16_t* __restrict__ b, const float* __restrict__ master,
+                             int32_t* __restrict__ flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n && (uint16_t)to_bf16(master[i]) != b[i]) flag[0] = 1;
+}
+
 __global__ void k_copyf(int64_t n, float* __restrict__ d, const float* __restrict__ s) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) d[i] = s[i];
@@ -323,17 +337,12 @@ void mlp_forward(spm_mlp* net, hipStream_t s, const float* x, const int32_t* xro
   }
 }
 
-// Loss and gradients of B rows (x rows xrow[b], target rows trow[b]; either may be null).
-void mlp_backward(spm_mlp* net, hipStream_t s, const float* x, const int32_t* xrow, const float* T,
-                  const int32_t* trow, int64_t B, int mode, float* grads, float* loss_f, double* loss_d) {
-  mlp_forward(net, s, x, xrow, B, net->y, mode);
-  const int64_t nel = B * kOut;
-  const int64_t nb = (nel + 255) / 256;
-  float* dZ = net->dz[0];
-  k_loss<<<(unsigned)nb, 256, 0, s>>>(net->y, T, trow, B, 1.0f / (float)B, dZ, net->part);
-  SPM_HIP_CHECK(hipGetLastError());
-  k_loss_final<<<1, 256, 0, s>>>(net->part, nb, 1.0 / (double)B, loss_f, loss_d);
-  SPM_HIP_CHECK(hipGetLastError());
+// Gradients of the packed parameters for the upstream gradient dY [B x 128] (dL/dy of the
+// rows of the last forward pass, which left its activations in h[0..2]); x rows xrow[b]
+// (xrow may be null). dY is only read.
+void mlp_backprop(spm_mlp* net, hipStream_t s, const float* x, const int32_t* xrow, const float* dY, int64_t B,
+                  int mode, float* grads) {
+  const float* dZ = dY;
   for (int l = kLayers - 1; l >= 0; --l) {
     const float* hin = l > 0 ? net->h[l - 1] : x;
     const int32_t* hrow = l > 0 ? nullptr : xrow;
@@ -375,6 +384,20 @@ void mlp_backward(spm_mlp* net, hipStream_t s, const float* x, const int32_t* xr
     gemm(s, mode, gd);
     dZ = dn;
   }
+}
+
+// Loss and gradients of B rows (x rows xrow[b], target rows trow[b]; either may be null).
+void mlp_backward(spm_mlp* net, hipStream_t s, const float* x, const int32_t* xrow, const float* T,
+                  const int32_t* trow, int64_t B, int mode, float* grads, float* loss_f, double* loss_d) {
+  mlp_forward(net, s, x, xrow, B, net->y, mode);
+  const int64_t nel = B * kOut;
+  const int64_t nb = (nel + 255) / 256;
+  float* dZ = net->dz[0];
+  k_loss<<<(unsigned)nb, 256, 0, s>>>(net->y, T, trow, B, 1.0f / (float)B, dZ, net->part);
+  SPM_HIP_CHECK(hipGetLastError());
+  k_loss_final<<<1, 256, 0, s>>>(net->part, nb, 1.0 / (double)B, loss_f, loss_d);
+  SPM_HIP_CHECK(hipGetLastError());
+  mlp_backprop(net, s, x, xrow, dZ, B, mode, grads);
 }
 
 }  // namespace spm
@@ -470,6 +493,34 @@ int spm_mlp_set_params(spm_mlp* n, const float* params) {
   });
 }
 
+int spm_mlp_set_weights(spm_mlp* n, const uint16_t* params_bf16, const float* master_fp32, int64_t n_params) {
+  return mlp_guarded(n, [&]() {
+    if (n_params != SPM_MLP_NPARAMS) throw ApiError(SPM_EINVAL, "n_params must be SPM_MLP_NPARAMS");
+    if (!params_bf16 && !master_fp32) throw ApiError(SPM_EINVAL, "no weights given");
+    const unsigned grid = (SPM_MLP_NPARAMS + 255) / 256;
+    if (master_fp32) {
+      if (params_bf16) {
+        SPM_HIP_CHECK(hipMemsetAsync(n->flag, 0, sizeof(int32_t), n->stream));
+        k_check_bf16<<<grid, 256, 0, n->stream>>>(SPM_MLP_NPARAMS, params_bf16, master_fp32, n->flag);
+        SPM_HIP_CHECK(hipGetLastError());
+        int32_t bad = 0;
+        SPM_HIP_CHECK(hipMemcpyAsync(&bad, n->flag, sizeof(int32_t), hipMemcpyDeviceToHost, n->stream));
+        SPM_HIP_CHECK(hipStreamSynchronize(n->stream));
+        if (bad) throw ApiError(SPM_EINVAL, "params_bf16 is not the bfloat16 rounding of master_fp32");
+      }
+      k_copyf<<<grid, 256, 0, n->stream>>>(SPM_MLP_NPARAMS, n->params, master_fp32);
+    } else {
+      k_widen_bf16<<<grid, 256, 0, n->stream>>>(SPM_MLP_NPARAMS, params_bf16, n->params);
+    }
+    SPM_HIP_CHECK(hipGetLastError());
+    launch_fill(n->stream, n->m1, SPM_MLP_NPARAMS, 0.f);
+    launch_fill(n->stream, n->m2, SPM_MLP_NPARAMS, 0.f);
+    n->t = 0;
+    SPM_HIP_CHECK(hipStreamSynchronize(n->stream));
+    return SPM_OK;
+  });
+}
+
 int spm_mlp_get_params(spm_mlp* n, float* params) {
   return mlp_guarded(n, [&]() {
     if (!params) throw ApiError(SPM_EINVAL, "null params");
@@ -501,6 +552,33 @@ int spm_mlp_loss_grad(spm_mlp* n, const float* x, const float* t, int64_t batch,
     SPM_HIP_CHECK(hipMemcpyAsync(&l, n->loss, sizeof(double), hipMemcpyDeviceToHost, n->stream));
     SPM_HIP_CHECK(hipStreamSynchronize(n->stream));
     if (loss_host) *loss_host = l;
+    return SPM_OK;
+  });
+}
+
+int spm_mlp_backward(spm_mlp* n, const float* x, const float* dy, int64_t batch, float* grad, int32_t mode) {
+  return mlp_guarded(n, [&]() {
+    if (!x || !dy || !grad || batch < 1 || batch > (int64_t)1 << 24)
+      throw ApiError(SPM_EINVAL, "bad backward arguments");
+    if (mode != SPM_MLP_BF16 && mode != SPM_MLP_FP32) throw ApiError(SPM_EINVAL, "bad mode");
+    mlp_forward(n, n->stream, x, nullptr, batch, n->y, mode);
+    mlp_backprop(n, n->stream, x, nullptr, dy, batch, mode, grad);
+    SPM_HIP_CHECK(hipStreamSynchronize(n->stream));
+    return SPM_OK;
+  });
+}
+
+int spm_mlp_adam_step(spm_mlp* n, const float* grad, float lr, float beta1, float beta2, float eps, int32_t step) {
+  return mlp_guarded(n, [&]() {
+    if (!grad || !(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f) ||
+        step < 1)
+      throw ApiError(SPM_EINVAL, "bad Adam arguments");
+    const float bc1 = 1.f - std::pow(beta1, (float)step), bc2 = 1.f - std::pow(beta2, (float)step);
+    k_adam<<<(SPM_MLP_NPARAMS + 255) / 256, 256, 0, n->stream>>>(SPM_MLP_NPARAMS, n->params, grad, n->m1, n->m2, lr,
+                                                                 beta1, beta2, eps, bc1, bc2);
+    SPM_HIP_CHECK(hipGetLastError());
+    n->t = step;
+    SPM_HIP_CHECK(hipStreamSynchronize(n->stream));
     return SPM_OK;
   });
 }

@@ -3,13 +3,22 @@
 //   T_near(x_i) = -(1/pi) sum_j sum_{s in S9} r (r.n_i)(r.f_j) / |r|^4,  r = x_i - (y_j + s),  f_j = w_j sigma_j
 //
 // for every cell of the ensemble (targets and sources of one cell only). Tiled direct
-// N-body in one persistent launch: the grid drains a cost-sorted queue of work items
-// (cell, block of targets, chunk of sources) through an atomic head. One target per
-// lane (or TPT targets), source tiles staged in LDS (every lane of a wave reads the same
-// source: LDS broadcast), the 9 image shifts of the item's cell applied to the source
-// difference. Each item writes its own partial slot; the combine kernel sums the
-// slots of a node in fixed order (deterministic, no floating-point atomics).
+// N-body in one persistent launch. The work of a cell is cut into units: a block of
+// BLOCK * TPT targets against one tile of `tile` sources. The units of the active cells,
+// in the order (cell, target block, source tile), are divided evenly over the persistent
+// workgroups (workgroup g takes units [g U / G, (g + 1) U / G)), so every workgroup does the
+// same number of pair evaluations up to one tile and no work queue is needed. A workgroup
+// keeps the FP64 sum of its consecutive tiles of one target block in registers and writes
+// one partial per target block it touches: at most (target blocks + workgroups) partials
+// in all, which the combine step sums per block in workgroup order (deterministic, no
+// floating-point atomics).
+//
+// Inside a unit: one target per lane (or TPT targets i, i + BLOCK, ...), the source tile
+// staged in LDS (every lane of a wave reads the same source: LDS broadcast), the 9 image
+// shifts of the cell applied to the source difference, the three images of a lattice row
+// sharing their row terms.
 #include <algorithm>
+#include <mutex>
 
 #include "spm_internal.h"
 
@@ -20,31 +29,124 @@ struct Src {
   R y1, y2, f1, f2;
 };
 
+// Owner of position p of the unit sequence [0, U) divided over G workgroups (the largest g
+// with floor(g U / G) <= p).
+__host__ __device__ __forceinline__ int64_t unit_owner(int64_t p, int64_t U, int64_t G) {
+  return ((p + 1) * G - 1) / U;
+}
+
+// One workgroup of 1024 threads (C <= 1024 cells): unit offsets of the active cells
+// (inactive cells contribute none), the number of workgroups G = min(grid, U) that share
+// them, and for every target block the range of partial slots its owners write.
+__global__ __launch_bounds__(1024) void k_near_partition(int C, const int32_t* __restrict__ cell_nt,
+                                                         const int32_t* __restrict__ cell_blk,
+                                                         const int32_t* __restrict__ active, int grid,
+                                                         int64_t* __restrict__ unit_off,
+                                                         int32_t* __restrict__ slot_off) {
+  __shared__ int64_t s_off[1025];
+  __shared__ int32_t s_blk[1025];
+  __shared__ int32_t s_nt[1024];
+  __shared__ int32_t s_scan[1024];
+  __shared__ int32_t s_carry;
+  const int t = threadIdx.x;
+  if (t < C) s_nt[t] = cell_nt[t];
+  if (t < C) s_blk[t] = cell_blk[t];
+  if (t == 0) {
+    s_blk[C] = cell_blk[C];
+    s_off[0] = 0;
+    s_carry = 0;
+  }
+  __syncthreads();
+  int64_t u = 0;
+  if (t < C && (active == nullptr || active[t] != 0)) u = (int64_t)(s_blk[t + 1] - s_blk[t]) * s_nt[t];
+  s_off[t + 1] = u;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan of s_off[1..1024]
+    const int64_t v = t >= o ? s_off[t + 1 - o] : 0;
+    __syncthreads();
+    s_off[t + 1] += v;
+    __syncthreads();
+  }
+  if (t < C) unit_off[t] = s_off[t];
+  if (t == 0) unit_off[C] = s_off[C];
+  const int64_t U = s_off[C];
+  const int64_t G = U < grid ? U : grid;
+  const int nblocks = s_blk[C];
+  for (int base = 0; base < nblocks; base += 1024) {
+    const int b = base + t;
+    int32_t P = 0;
+    if (b < nblocks && U > 0) {
+      int lo = 0, hi = C;   // s_blk[lo] <= b < s_blk[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_blk[mid] <= b)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const int64_t nt = s_nt[lo];
+      if (s_off[lo + 1] > s_off[lo]) {
+        const int64_t s = s_off[lo] + (int64_t)(b - s_blk[lo]) * nt;
+        P = (int32_t)(unit_owner(s + nt - 1, U, G) - unit_owner(s, U, G) + 1);
+      }
+    }
+    s_scan[t] = P;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {   // inclusive scan
+      const int32_t v = t >= o ? s_scan[t - o] : 0;
+      __syncthreads();
+      s_scan[t] += v;
+      __syncthreads();
+    }
+    if (b < nblocks) slot_off[b] = s_carry + s_scan[t] - P;
+    __syncthreads();
+    if (t == 1023) s_carry += s_scan[1023];
+    __syncthreads();
+  }
+  if (t == 0) slot_off[nblocks] = s_carry;
+}
+
 // TPT targets per lane (i, i + BLOCK, ...) share every LDS source read. Each LDS tile is
 // summed in a fresh accumulator of the kernel's precision and then added to an FP64
 // running sum, which keeps the FP32 summation error at the level of one tile.
 template <typename R, int BLOCK, int TPT>
-__global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__ x, const R* __restrict__ y,
+__global__ __launch_bounds__(BLOCK) void k_near(int C, const R* __restrict__ x, const R* __restrict__ y,
                                                 const R* __restrict__ nx, const R* __restrict__ ny,
                                                 const R* __restrict__ f1, const R* __restrict__ f2,
-                                                const double* __restrict__ cskew, const NearItem* __restrict__ items,
-                                                int nitems, int* __restrict__ counter,
-                                                const int32_t* __restrict__ active, int tile,
+                                                const double* __restrict__ cskew, const int64_t* __restrict__ cnoff,
+                                                const int32_t* __restrict__ cell_nt,
+                                                const int32_t* __restrict__ cell_blk,
+                                                const int64_t* __restrict__ unit_off,
+                                                const int32_t* __restrict__ slot_off, int grid, int tile,
                                                 double* __restrict__ Tpart) {
   extern __shared__ unsigned char smem_raw[];
   Src<R>* src = reinterpret_cast<Src<R>*>(smem_raw);
-  __shared__ int s_item;
-  for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = s_item;
-    if (it >= nitems) break;
-    const NearItem I = items[it];
-    if (active != nullptr && active[I.c] == 0) continue;
+  constexpr int BT = BLOCK * TPT;
+  const int64_t U = unit_off[C];
+  const int64_t G = U < grid ? U : grid;
+  const int64_t g = blockIdx.x;
+  if (g >= G) return;
+  int64_t p = g * U / G;
+  const int64_t pend = (g + 1) * U / G;
+  while (p < pend) {
+    int lo = 0, hi = C;   // unit_off[lo] <= p < unit_off[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (unit_off[mid] <= p)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const int c = lo;
+    const int64_t nt = cell_nt[c];
+    const int64_t lu = p - unit_off[c];
+    const int64_t bb = lu / nt, k0 = lu - bb * nt;
+    const int64_t run = (nt - k0 < pend - p) ? nt - k0 : pend - p;
+    const int64_t n0 = cnoff[c], n1 = cnoff[c + 1];
+    const int64_t t0 = n0 + bb * BT;
     R sx[kShifts], sy[kShifts];
     {
-      const double skew = cskew[I.c];
+      const double skew = cskew[c];
 #pragma unroll
       for (int m = 0; m < kShifts; ++m) {
         sx[m] = (R)shift_x(m, skew);
@@ -55,12 +157,12 @@ __global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__
     double A1[TPT], A2[TPT];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-      const int64_t i = I.t0 + threadIdx.x + t * BLOCK;
+      const int64_t i = t0 + threadIdx.x + t * BLOCK;
       xi[t] = 0;
       yi[t] = 0;
       nxi[t] = 0;
       nyi[t] = 0;
-      if (i < I.t1) {
+      if (i < n1) {
         xi[t] = x[i];
         yi[t] = y[i];
         nxi[t] = nx[i];
@@ -69,8 +171,9 @@ __global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__
       A1[t] = 0.0;
       A2[t] = 0.0;
     }
-    for (int64_t jt = I.s0; jt < I.s1; jt += tile) {
-      const int cnt = (int)((jt + tile < I.s1) ? tile : (I.s1 - jt));
+    const int64_t s_end = (n0 + (k0 + run) * tile < n1) ? n0 + (k0 + run) * tile : n1;
+    for (int64_t jt = n0 + k0 * tile; jt < s_end; jt += tile) {
+      const int cnt = (int)((jt + tile < s_end) ? tile : (s_end - jt));
       __syncthreads();
       for (int k = threadIdx.x; k < cnt; k += BLOCK) {
         Src<R> s;
@@ -87,6 +190,7 @@ __global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__
         a1[t] = 0;
         a2[t] = 0;
       }
+#pragma unroll 2
       for (int k = 0; k < cnt; ++k) {
         const Src<R> s = src[k];
 #pragma unroll
@@ -105,29 +209,29 @@ __global__ __launch_bounds__(BLOCK) void k_near(int64_t N, const R* __restrict__
         A2[t] += (double)a2[t];
       }
     }
-    double* out = Tpart + (int64_t)I.split * 2 * N;
+    // slot of this workgroup among the owners of target block (c, bb)
+    const int64_t first = unit_owner(unit_off[c] + bb * nt, U, G);
+    double* out = Tpart + ((int64_t)slot_off[cell_blk[c] + bb] + (g - first)) * 2 * BT;
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-      const int64_t i = I.t0 + threadIdx.x + t * BLOCK;
-      if (i < I.t1) {
-        out[i] = -(1.0 / kPi) * A1[t];
-        out[N + i] = -(1.0 / kPi) * A2[t];
+      const int local = threadIdx.x + t * BLOCK;
+      if (t0 + local < n1) {
+        out[local] = -(1.0 / kPi) * A1[t];
+        out[BT + local] = -(1.0 / kPi) * A2[t];
       }
     }
+    p += run;
   }
 }
 
-__global__ void k_reset_counter(int* c) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) c[0] = 0;
-}
-
 template <typename R, int BLOCK, int TPT>
-static int near_grid(int tile) {
+static int near_grid(int tile, int wg_per_cu) {
   int per_cu = 0;
   const size_t lds = sizeof(Src<R>) * (size_t)tile;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_near<R, BLOCK, TPT>, BLOCK, lds) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
+  if (wg_per_cu > 0) per_cu = std::min(per_cu, wg_per_cu);
   int dev = 0, ncu = 0;
   SPM_HIP_CHECK(hipGetDevice(&dev));
   SPM_HIP_CHECK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -136,40 +240,52 @@ static int near_grid(int tile) {
 
 template <typename R, int BLOCK, int TPT>
 static void near_launch(spm_handle* h, const R* x, const R* y, const R* nx, const R* ny, const R* f1, const R* f2,
-                        NearPlan& P, bool with_active) {
+                        const NearPlan& P) {
   const size_t lds = sizeof(Src<R>) * (size_t)P.cfg.tile;
-  if (P.grid <= 0) P.grid = near_grid<R, BLOCK, TPT>(P.cfg.tile);
-  const int grid = std::max(1, std::min(P.grid, P.nitems));
-  k_reset_counter<<<1, 64, 0, h->stream>>>(P.counter);
-  SPM_HIP_CHECK(hipGetLastError());
-  k_near<R, BLOCK, TPT><<<grid, BLOCK, lds, h->stream>>>(h->geo.N, x, y, nx, ny, f1, f2, h->geo.cskew, P.items,
-                                                         P.nitems, P.counter, with_active ? h->kr.active : nullptr,
-                                                         P.cfg.tile, h->wk.Tpart);
+  k_near<R, BLOCK, TPT><<<P.grid, BLOCK, lds, h->stream>>>(h->geo.C, x, y, nx, ny, f1, f2, h->geo.cskew,
+                                                           h->geo.cnoff, P.cell_nt, P.cell_blk, P.unit_off,
+                                                           P.slot_off, P.grid, P.cfg.tile, h->wk.Tpart);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
+#define SPM_NEAR_SHAPES(X) X(64, 1) X(64, 2) X(64, 4) X(128, 1) X(128, 2) X(128, 4) X(256, 1) X(256, 2) X(256, 4)
+
 template <typename R>
 static void near_dispatch(spm_handle* h, const R* x, const R* y, const R* nx, const R* ny, const R* f1,
-                          const R* f2, NearPlan& P, bool with_active) {
+                          const R* f2, const NearPlan& P) {
   const int key = P.cfg.block * 10 + P.cfg.tpt;
   switch (key) {
-    case 641: near_launch<R, 64, 1>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 642: near_launch<R, 64, 2>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 644: near_launch<R, 64, 4>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 1281: near_launch<R, 128, 1>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 1282: near_launch<R, 128, 2>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 1284: near_launch<R, 128, 4>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 2561: near_launch<R, 256, 1>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 2562: near_launch<R, 256, 2>(h, x, y, nx, ny, f1, f2, P, with_active); break;
-    case 2564: near_launch<R, 256, 4>(h, x, y, nx, ny, f1, f2, P, with_active); break;
+#define SPM_CASE(B, T)                                     \
+  case B * 10 + T:                                         \
+    near_launch<R, B, T>(h, x, y, nx, ny, f1, f2, P);      \
+    break;
+    SPM_NEAR_SHAPES(SPM_CASE)
+#undef SPM_CASE
     default: throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
   }
+}
+
+template <typename R>
+static int near_grid_of(const NearConfig& c) {
+  const int key = c.block * 10 + c.tpt;
+  switch (key) {
+#define SPM_CASE(B, T) \
+  case B * 10 + T:     \
+    return near_grid<R, B, T>(c.tile, c.wg_per_cu);
+    SPM_NEAR_SHAPES(SPM_CASE)
+#undef SPM_CASE
+    default: throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
+  }
+}
+
+int near_persistent_grid(const NearConfig& c, int precision) {
+  return precision == SPM_FP64 ? near_grid_of<double>(c) : near_grid_of<float>(c);
 }
 
 bool near_config_valid(const NearConfig& c) {
   const bool b = c.block == 64 || c.block == 128 || c.block == 256;
   const bool t = c.tpt == 1 || c.tpt == 2 || c.tpt == 4;
-  return b && t && c.tile >= 16 && c.tile <= 1024 && c.chunk >= 16;
+  return b && t && c.tile >= 16 && c.tile <= 1024 && c.wg_per_cu >= 0 && c.wg_per_cu <= 32;
 }
 
 void prof_flush(spm_handle* h) {
@@ -186,7 +302,11 @@ void prof_flush(spm_handle* h) {
 void launch_near_impl(spm_handle* h, int precision, bool with_active) {
   const Geo& g = h->geo;
   const int kind = precision == SPM_FP64 ? 0 : 1;
-  NearPlan& P = h->wk.near[kind];
+  const NearPlan& P = h->wk.near[kind];
+  if (g.C > 1024) throw ApiError(SPM_EINVAL, "at most 1024 cells");
+  k_near_partition<<<1, 1024, 0, h->stream>>>(g.C, P.cell_nt, P.cell_blk, with_active ? h->kr.active : nullptr,
+                                              P.grid, P.unit_off, P.slot_off);
+  SPM_HIP_CHECK(hipGetLastError());
   if (h->prof) {
     if (h->ev_used * 2 + 2 > h->ev_pool.size()) {
       if (h->ev_pool.size() >= 512) prof_flush(h);
@@ -201,9 +321,9 @@ void launch_near_impl(spm_handle* h, int precision, bool with_active) {
     SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used], h->stream));
   }
   if (precision == SPM_FP64)
-    near_dispatch<double>(h, g.x, g.y, g.nx, g.ny, h->wk.f1, h->wk.f2, P, with_active);
+    near_dispatch<double>(h, g.x, g.y, g.nx, g.ny, h->wk.f1, h->wk.f2, P);
   else
-    near_dispatch<float>(h, g.xf, g.yf, g.nxf, g.nyf, h->wk.f1f, h->wk.f2f, P, with_active);
+    near_dispatch<float>(h, g.xf, g.yf, g.nxf, g.nyf, h->wk.f1f, h->wk.f2f, P);
   if (h->prof) {
     SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used + 1], h->stream));
     ++h->ev_used;
@@ -216,26 +336,163 @@ void launch_near_impl(spm_handle* h, int precision, bool with_active) {
 
 void launch_near(spm_handle* h, int precision) { launch_near_impl(h, precision, false); }
 
-// Sum of the split partials only (stage entry point for checking the near sum).
-__global__ void k_sum_splits(int64_t N, const int32_t* __restrict__ ncell, const int32_t* __restrict__ nsplit,
-                             const double* __restrict__ Tpart, double* __restrict__ out) {
+// ----------------------------------------------------------------------------
+// Allocation-free near sum of one cell (spm_near_traction_noalloc). Its forces, FP32
+// shadows, plan and partials live in one file-scope device array (`scratch`, kNoallocBytes)
+// instead of handle memory; a fixed launch shape (256 threads, one target per lane, 256-source
+// tiles, at most kNoallocGrid workgroups) bounds the partials. Host code reaches the array
+// through the per-device address hipGetSymbolAddress returns, never through its name.
+// ----------------------------------------------------------------------------
+namespace {
+constexpr int64_t kNoallocMaxN = SPM_NOALLOC_MAX_N;
+constexpr int kNoallocBlock = 256, kNoallocTile = 256, kNoallocGrid = 1024;
+constexpr int64_t kNoallocBlocks = kNoallocMaxN / kNoallocBlock;
+constexpr int64_t kNoallocSlots = kNoallocBlocks + kNoallocGrid;
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kOffF64 = 0;                                                   // f1, f2 [2 maxN] double
+constexpr size_t kOffF32 = kOffF64 + align256(2 * kNoallocMaxN * sizeof(double));   // x y nx ny f1 f2 [6 maxN] float
+constexpr size_t kOffPlan = kOffF32 + align256(6 * kNoallocMaxN * sizeof(float));
+// plan: cskew [1] double, cnoff [2] int64, unit_off [2] int64, cell_nt [1], cell_blk [2], slot_off [blocks + 1] int32
+constexpr size_t kOffSlot = kOffPlan + 64;
+constexpr size_t kOffPart = kOffSlot + align256((kNoallocBlocks + 1) * sizeof(int32_t));
+constexpr size_t kNoallocBytes = kOffPart + kNoallocSlots * 2 * kNoallocBlock * sizeof(double);
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+
+// forces f = w sigma, the FP32 shadows (FP32 precision) and the one-cell plan
+__global__ __launch_bounds__(256) void k_noalloc_prep(int64_t N, double skew, const double* __restrict__ x,
+                                                      const double* __restrict__ y, const double* __restrict__ nx,
+                                                      const double* __restrict__ ny, const double* __restrict__ w,
+                                                      const double* __restrict__ sigma, int fp32,
+                                                      unsigned char* __restrict__ base) {
+  double* f1 = reinterpret_cast<double*>(base + kOffF64);
+  double* f2 = f1 + kNoallocMaxN;
+  float* xf = reinterpret_cast<float*>(base + kOffF32);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < N) {
+    const double a = w[i] * sigma[i], b = w[i] * sigma[N + i];
+    f1[i] = a;
+    f2[i] = b;
+    if (fp32) {
+      xf[i] = (float)x[i];
+      xf[kNoallocMaxN + i] = (float)y[i];
+      xf[2 * kNoallocMaxN + i] = (float)nx[i];
+      xf[3 * kNoallocMaxN + i] = (float)ny[i];
+      xf[4 * kNoallocMaxN + i] = (float)a;
+      xf[5 * kNoallocMaxN + i] = (float)b;
+    }
+  }
+  if (i == 0) {
+    unsigned char* plan = base + kOffPlan;
+    reinterpret_cast<double*>(plan)[0] = skew;
+    int64_t* cnoff = reinterpret_cast<int64_t*>(plan + 8);
+    cnoff[0] = 0;
+    cnoff[1] = N;
+    int32_t* ints = reinterpret_cast<int32_t*>(plan + 40);
+    ints[0] = (int32_t)((N + kNoallocTile - 1) / kNoallocTile);      // cell_nt
+    ints[1] = 0;                                                      // cell_blk
+    ints[2] = (int32_t)((N + kNoallocBlock - 1) / kNoallocBlock);
+  }
+}
+
+// out[i] = sum of the partial slots of target i's block (one cell)
+__global__ __launch_bounds__(256) void k_noalloc_sum(int64_t N, const unsigned char* __restrict__ base,
+                                                     double* __restrict__ out) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const int S = nsplit[ncell[i]];
-  double s1 = 0.0, s2 = 0.0;
-  for (int k = 0; k < S; ++k) {
-    s1 += Tpart[(int64_t)k * 2 * N + i];
-    s2 += Tpart[(int64_t)k * 2 * N + N + i];
+  const int32_t* slot_off = reinterpret_cast<const int32_t*>(base + kOffSlot);
+  const double* part = reinterpret_cast<const double*>(base + kOffPart);
+  const int64_t b = i / kNoallocBlock, local = i % kNoallocBlock;
+  double t1 = 0.0, t2 = 0.0;
+  for (int k = slot_off[b]; k < slot_off[b + 1]; ++k) {
+    t1 += part[(int64_t)k * 2 * kNoallocBlock + local];
+    t2 += part[(int64_t)k * 2 * kNoallocBlock + kNoallocBlock + local];
   }
-  out[i] = s1;
-  out[N + i] = s2;
+  out[i] = t1;
+  out[N + i] = t2;
 }
 
-void launch_near_sum_only(spm_handle* h, double* out, int precision) {
-  const int64_t N = h->geo.N;
-  const NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
-  k_sum_splits<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, h->geo.ncell, P.nsplit, h->wk.Tpart, out);
+namespace {
+struct NoallocDevice {
+  unsigned char* ptr = nullptr;   // device address of `scratch` on this device
+  int grid = 0;
+};
+std::mutex g_noalloc_mu;
+NoallocDevice g_noalloc_dev[64];
+
+template <typename R>
+void noalloc_launch(hipStream_t st, int64_t N, const R* x, const R* y, const R* nx, const R* ny, const R* f1,
+                    const R* f2, unsigned char* base, int grid) {
+  unsigned char* plan = base + kOffPlan;
+  const double* cskew = reinterpret_cast<const double*>(plan);
+  const int64_t* cnoff = reinterpret_cast<const int64_t*>(plan + 8);
+  int64_t* unit_off = reinterpret_cast<int64_t*>(plan + 24);
+  const int32_t* cell_nt = reinterpret_cast<const int32_t*>(plan + 40);
+  const int32_t* cell_blk = cell_nt + 1;
+  int32_t* slot_off = reinterpret_cast<int32_t*>(base + kOffSlot);
+  double* part = reinterpret_cast<double*>(base + kOffPart);
+  k_near_partition<<<1, 1024, 0, st>>>(1, cell_nt, cell_blk, nullptr, grid, unit_off, slot_off);
+  SPM_HIP_CHECK(hipGetLastError());
+  k_near<R, kNoallocBlock, 1><<<grid, kNoallocBlock, sizeof(Src<R>) * kNoallocTile, st>>>(
+      1, x, y, nx, ny, f1, f2, cskew, cnoff, cell_nt, cell_blk, unit_off, slot_off, grid, kNoallocTile, part);
   SPM_HIP_CHECK(hipGetLastError());
 }
+}  // namespace
 
 }  // namespace spm
+
+using namespace spm;
+
+extern "C" int spm_near_traction_noalloc(void* hip_stream, int64_t n, double skew, const double* x, const double* y,
+                                         const double* nx, const double* ny, const double* w, const double* sigma,
+                                         int32_t precision, double* out) {
+  if (n < 1 || n > kNoallocMaxN) return SPM_EINVAL;
+  if (!x || !y || !nx || !ny || !w || !sigma || !out || !std::isfinite(skew)) return SPM_EINVAL;
+  if (precision != SPM_FP64 && precision != SPM_FP32) return SPM_EINVAL;
+  try {
+    int dev = 0;
+    SPM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return SPM_EINVAL;
+    NoallocDevice D;
+    {
+      std::lock_guard<std::mutex> lock(g_noalloc_mu);
+      NoallocDevice& d = g_noalloc_dev[dev];
+      if (!d.ptr) {   // first call on this device (which is current): the array's device address
+        void* p = nullptr;
+        SPM_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return SPM_EHIP;
+        NearConfig c;
+        c.block = kNoallocBlock;
+        c.tpt = 1;
+        c.tile = kNoallocTile;
+        c.wg_per_cu = 0;
+        const int g64 = near_persistent_grid(c, SPM_FP64), g32 = near_persistent_grid(c, SPM_FP32);
+        d.grid = std::max(1, std::min(kNoallocGrid, std::min(g64, g32)));
+        d.ptr = static_cast<unsigned char*>(p);
+      }
+      D = d;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const double s = skew - std::floor(skew + 0.5);   // e2 = (s, 1) reduced to [-1/2, 1/2)
+    const unsigned g = (unsigned)((n + 255) / 256);
+    k_noalloc_prep<<<g, 256, 0, st>>>(n, s, x, y, nx, ny, w, sigma, precision == SPM_FP32 ? 1 : 0, D.ptr);
+    SPM_HIP_CHECK(hipGetLastError());
+    if (precision == SPM_FP64) {
+      const double* f1 = reinterpret_cast<const double*>(D.ptr + kOffF64);
+      noalloc_launch<double>(st, n, x, y, nx, ny, f1, f1 + kNoallocMaxN, D.ptr, D.grid);
+    } else {
+      const float* xf = reinterpret_cast<const float*>(D.ptr + kOffF32);
+      noalloc_launch<float>(st, n, xf, xf + kNoallocMaxN, xf + 2 * kNoallocMaxN, xf + 3 * kNoallocMaxN,
+                            xf + 4 * kNoallocMaxN, xf + 5 * kNoallocMaxN, D.ptr, D.grid);
+    }
+    k_noalloc_sum<<<g, 256, 0, st>>>(n, D.ptr, out);
+    SPM_HIP_CHECK(hipGetLastError());
+    SPM_HIP_CHECK(hipStreamSynchronize(st));
+    return SPM_OK;
+  } catch (const HipError&) {
+    return SPM_EHIP;
+  } catch (const ApiError& e) {
+    return e.code;
+  }
+}

@@ -181,6 +181,18 @@ __global__ __launch_bounds__(256) void k_velocity_gauge(const int32_t* __restric
   }
 }
 
+__global__ void k_add_cell_velocity(int No, const int32_t* __restrict__ pcell, const double* __restrict__ du,
+                                    double* __restrict__ vel) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < No) vel[2 * i] += du[pcell[i]];
+}
+
+void launch_add_cell_velocity(spm_handle* h, const double* du, double* vel) {
+  const int n = h->geo.No;
+  k_add_cell_velocity<<<(n + 255) / 256, 256, 0, h->stream>>>(n, h->geo.pcell, du, vel);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
 void launch_velocities(spm_handle* h, double* vel, double* omega) {
   const double* near3 = nullptr;
   if (h->fmm.on) {                      // near-image part by the FMM's tree (w sigma is staged)

@@ -433,11 +433,15 @@ void launch_xi(spm_handle* h) { launch_xi_impl(h, false); }
 // Self term (limit of the smooth kernel on the curve): -(kappa/2pi) tau (tau . w sigma).
 // Proxy correction (step 4): sum_p G^t(x_i, y_p; n_i) xi_p.
 // ----------------------------------------------------------------------------
-// Four lanes per target: lane l sums the splits k = l, l+4, ... and the proxies p = l, l+4,
-// ...; the four partial sums are combined by a fixed butterfly (deterministic).
+// Four lanes per target: lane l sums the partial slots k = l, l+4, ... of the target's block
+// and the proxies p = l, l+4, ...; the four partial sums are combined by a fixed butterfly
+// (deterministic). Slots: the near sum's partials of target block b are slots
+// slot_off[b] .. slot_off[b+1]-1, each [2 x bt] (first components, then second components of
+// the block's targets); block b of target i is cell_blk[cell] + (i - first node of the cell) / bt.
 constexpr int kCombineLanes = 4;
 
-__global__ __launch_bounds__(256) void k_combine(int64_t N, const int32_t* __restrict__ nsplit,
+__global__ __launch_bounds__(256) void k_combine(int64_t N, int64_t bt, const int32_t* __restrict__ cell_blk,
+                                                 const int32_t* __restrict__ slot_off,
                                                  const double* __restrict__ Tpart, Geo g,
                                                  const double* __restrict__ sigma, int M,
                                                  const double* __restrict__ px, const double* __restrict__ py,
@@ -449,11 +453,13 @@ __global__ __launch_bounds__(256) void k_combine(int64_t N, const int32_t* __res
   const bool live = i < N;
   const int64_t ii = live ? i : N - 1;   // idle lanes shadow the last target so shuffles stay uniform
   const int cell = g.ncell[ii];
-  const int S = nsplit[cell];
+  const int64_t li = ii - g.cnoff[cell];
+  const int64_t b = cell_blk[cell] + li / bt, local = li % bt;
+  const int s1 = slot_off[b + 1];
   double t1 = 0, t2 = 0;
-  for (int k = l; k < S; k += kCombineLanes) {
-    t1 += Tpart[(int64_t)k * 2 * N + ii];
-    t2 += Tpart[(int64_t)k * 2 * N + N + ii];
+  for (int k = slot_off[b] + l; k < s1; k += kCombineLanes) {
+    t1 += Tpart[(int64_t)k * 2 * bt + local];
+    t2 += Tpart[(int64_t)k * 2 * bt + bt + local];
   }
   if (with_extra) {
     const double xx = g.x[ii], yy = g.y[ii], nx = g.nx[ii], ny = g.ny[ii];
@@ -477,15 +483,27 @@ __global__ __launch_bounds__(256) void k_combine(int64_t N, const int32_t* __res
   T[N + i] = t2;
 }
 
-void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision) {
+static void combine_into(spm_handle* h, const double* sigma, bool with_self_corr, int precision, double* out) {
   const int64_t N = h->geo.N;
   const NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
   const int64_t threads = N * kCombineLanes;
-  const int32_t* nsplit = h->fmm.on ? h->fmm.nsplit1 : P.nsplit;   // the FMM writes one partial
-  k_combine<<<(unsigned)((threads + 255) / 256), 256, 0, h->stream>>>(N, nsplit, h->wk.Tpart, h->geo, sigma,
-                                                                     h->per.M, h->per.px, h->per.py, h->wk.xi,
-                                                                     with_self_corr ? 1 : 0, h->wk.T);
+  // the FMM writes one block of all N nodes into one slot
+  const int64_t bt = h->fmm.on ? N : P.bt;
+  const int32_t* cell_blk = h->fmm.on ? h->fmm.one_block : P.cell_blk;
+  const int32_t* slot_off = h->fmm.on ? h->fmm.one_block : P.slot_off;
+  k_combine<<<(unsigned)((threads + 255) / 256), 256, 0, h->stream>>>(N, bt, cell_blk, slot_off, h->wk.Tpart,
+                                                                     h->geo, sigma, h->per.M, h->per.px, h->per.py,
+                                                                     h->wk.xi, with_self_corr ? 1 : 0, out);
   SPM_HIP_CHECK(hipGetLastError());
+}
+
+void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision) {
+  combine_into(h, sigma, with_self_corr, precision, h->wk.T);
+}
+
+// The near-image sum alone (stage entry point for checking the near sum).
+void launch_near_sum_only(spm_handle* h, double* out, int precision) {
+  combine_into(h, nullptr, false, precision, out);
 }
 
 }  // namespace spm

@@ -281,24 +281,25 @@ struct NearConfig {
   int32_t block = 256;
   int32_t tpt = 1;
   int32_t tile = 256;
-  int32_t chunk = 2048;
+  int32_t wg_per_cu = 0;      // persistent workgroups per compute unit (0: the occupancy limit)
 };
 
-// One work item of the persistent near-sum kernel: targets [t0, t1) of cell c,
-// sources [s0, s1) of the same cell, written to partial slot `split`.
-struct NearItem {
-  int64_t t0, t1, s0, s1;
-  int32_t c, split;
-};
-
+// Plan of the near-sum launch of one precision. The work is split into units (target block
+// of block * tpt targets, source tile of `tile` sources of the same cell); the units of the
+// active cells, taken in order (cell, target block, tile), are divided evenly over the
+// persistent workgroups, and each workgroup writes one FP64 partial per target block it
+// touches. The partition kernel fills unit_off and slot_off before every launch (the
+// active cells change during an ensemble solve); the combine step sums the slots of a block
+// in workgroup order.
 struct NearPlan {
   NearConfig cfg;
-  int32_t nitems = 0;
-  int32_t max_splits = 1;
-  NearItem* items = nullptr;  // [nitems], cost-sorted (largest first)
-  int32_t* nsplit = nullptr;  // [C] splits of each cell
-  int32_t* counter = nullptr; // [1] work-queue head
-  int32_t grid = 0;           // persistent grid size
+  int32_t nblocks = 0;          // target blocks over all cells
+  int32_t bt = 0;               // targets per block (block * tpt)
+  int32_t* cell_nt = nullptr;   // [C] source tiles of the cell (= units per target block)
+  int32_t* cell_blk = nullptr;  // [C + 1] first target block of each cell
+  int64_t* unit_off = nullptr;  // [C + 1] offsets of the active cells' units
+  int32_t* slot_off = nullptr;  // [nblocks + 1] partial slots of each target block
+  int32_t grid = 0;             // persistent grid size (workgroups)
 };
 
 struct Work {
@@ -313,8 +314,10 @@ struct Work {
   int32_t* disc_off = nullptr;  // [C + 1] chunks of each cell
   double *f1 = nullptr, *f2 = nullptr;   // w sigma
   float *f1f = nullptr, *f2f = nullptr;
-  double* Tpart = nullptr;    // [max splits x 2N]
+  double* Tpart = nullptr;    // near-sum partials: [slots x 2 x targets per block]
   double* T = nullptr;        // [2N]
+  double* batch_sigma = nullptr;  // [2N] density of the one-call ensemble solve
+  double* cell_du = nullptr;  // [C] velocity added to the particles of each cell by that solve
   double* pF = nullptr;       // [No x 4]: F1, F2, torque, stresslet
   double* disc = nullptr;     // [ndisc x 2m x 8] (double-double partials)
   double* xi = nullptr;       // [C x 2M]
@@ -343,7 +346,7 @@ struct FmmPlan {
                                           // target leaves
   double* fact = nullptr;                 // [2p] factorials
   double *Mx = nullptr, *Lx = nullptr;    // [boxes x 3 x p] complex multipole / local expansions
-  int32_t* nsplit1 = nullptr;             // [1] = 1: the combine step reads one partial
+  int32_t* one_block = nullptr;           // {0, 1}: the combine step reads one block of all N nodes, one slot
   double* vnear = nullptr;                // [3 No] near-image velocity and vorticity at the centres
   double p2p_pairs = 0, m2l = 0;          // work of one evaluation
 };
@@ -479,6 +482,7 @@ struct spm_handle {
   spm::Precond pc;
   spm_mlp* net = nullptr;             // borrowed warm-start network
   double min_gap_est = 0.0;
+  double delta32 = -1.0;      // measured relative error of the FP32 operator (< 0: not measured for this geometry)
   double wallclock_hz = 1e8;
 
   // opt-in kernel timing: HIP events around near-sum launches (kernel 0 = FP64, 1 = FP32; FMM: 2 = evaluation, 3 = M2L)
@@ -523,6 +527,7 @@ void launch_near(spm_handle* h, int precision);
 void prof_flush(spm_handle* h);
 void launch_near_sum_only(spm_handle* h, double* out, int precision);
 bool near_config_valid(const NearConfig& c);
+int near_persistent_grid(const NearConfig& c, int precision);   // workgroups of the persistent near-sum grid
 void build_near_plan(spm_handle* h, int precision);
 void autotune(spm_handle* h, const char* cache_path, double* best_ms_out);
 double time_near(spm_handle* h, int prec, const NearConfig& c, int reps);
@@ -562,6 +567,7 @@ void gm_backsolve_update(spm_handle* h, double* x);
 void gm_axpby(spm_handle* h, int64_t n, double a, const double* x, double b, const double* y, double* out);
 void gm_copy(spm_handle* h, double* dst, const double* src, int64_t n);
 void gm_zero(spm_handle* h, double* dst, int64_t n);
+void gm_probe_fill(spm_handle* h, int64_t n, uint64_t seed, double* out);   // deterministic values in [-1, 1)
 void gm_stamp_start(spm_handle* h);
 void gm_stamp_mask(spm_handle* h, const int32_t* mask_dev);
 void gm_stamp_cycle(spm_handle* h);
@@ -572,6 +578,8 @@ void launch_close_apply_impl(spm_handle* h, double* T, int precision, bool with_
 
 // learned warm start (k_learned.hip) and block preconditioner (k_precond.hip)
 void launch_features(spm_handle* h, float* feat);
+void launch_to_bf16(spm_handle* h, const float* in, int64_t n, uint16_t* out);   // nearest even
+void launch_add_cell_velocity(spm_handle* h, const double* du, double* vel);   // vel[2i] += du[cell of i]
 void launch_modes(spm_handle* h, const double* sigma, const double* num, const double* den, float* modes);
 void launch_decode(spm_handle* h, const float* modes, double* sigma);
 void launch_add_normal(spm_handle* h, const double* num, const double* den, double f, double* x);

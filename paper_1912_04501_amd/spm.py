@@ -37,7 +37,8 @@ class spm_config(ctypes.Structure):
                 ("inner_tol", ctypes.c_double), ("min_gap", ctypes.c_double), ("rcond", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("x0", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("learned_max_iter", ctypes.c_int32), ("relax_tol", ctypes.c_double),
-                ("near_method", ctypes.c_int32), ("fmm_order", ctypes.c_int32)]
+                ("near_method", ctypes.c_int32), ("fmm_order", ctypes.c_int32),
+                ("node_spacing", ctypes.c_double), ("relax_safety", ctypes.c_double)]
 
 
 class spm_solve_info(ctypes.Structure):
@@ -106,7 +107,9 @@ def lib():
         "spm_set_cells_shapes": (ctypes.c_int, [P, ctypes.c_int32, d, i32, d, d, i32, d, i32]),
         "spm_eval_field": (ctypes.c_int, [P, P, ctypes.c_int64, P, P, P, P]),
         "spm_num_cells": (ctypes.c_int, [P, i32]),
-        "spm_solve_batch": (ctypes.c_int, [P, P, P, P, P, P, ctypes.POINTER(spm_solve_info), d]),
+        "spm_solve_cells": (ctypes.c_int, [P, P, P, P, P, P, ctypes.POINTER(spm_solve_info), d]),
+        "spm_solve_batch": (ctypes.c_int, [P, ctypes.c_int32, d, i32, d, d, d, d, i32, P, P, P,
+                                           ctypes.POINTER(spm_solve_info), d]),
         "spm_autotune": (ctypes.c_int, [P, ctypes.c_char_p, d]),
         "spm_get_launch": (ctypes.c_int, [P, ctypes.c_int32, i32]),
         "spm_set_launch": (ctypes.c_int, [P, ctypes.c_int32, i32]),
@@ -114,6 +117,7 @@ def lib():
         "spm_profile_read": (ctypes.c_int, [P, ctypes.c_int32, d, i64, d]),
         "spm_precond_apply": (ctypes.c_int, [P, P, P]),
         "spm_features": (ctypes.c_int, [P, P]),
+        "spm_features_f32": (ctypes.c_int, [P, P]),
         "spm_density_modes": (ctypes.c_int, [P, P, P]),
         "spm_warm_start": (ctypes.c_int, [P, P, P]),
         "spm_set_network": (ctypes.c_int, [P, P]),
@@ -129,6 +133,12 @@ def lib():
         "spm_mlp_loss_grad": (ctypes.c_int, [P, P, P, ctypes.c_int64, ctypes.c_int32, P, d]),
         "spm_mlp_train": (ctypes.c_int, [P, P, P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_float, ctypes.c_int32, P]),
+        "spm_mlp_set_weights": (ctypes.c_int, [P, P, P, ctypes.c_int64]),
+        "spm_near_traction_noalloc": (ctypes.c_int, [P, ctypes.c_int64, ctypes.c_double, P, P, P, P, P, P,
+                                                     ctypes.c_int32, P]),
+        "spm_mlp_backward": (ctypes.c_int, [P, P, P, ctypes.c_int64, P, ctypes.c_int32]),
+        "spm_mlp_adam_step": (ctypes.c_int, [P, P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                             ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -185,6 +195,24 @@ class _TorchAlloc:
 
         self.alloc_cb = ALLOC_FN(_alloc)
         self.free_cb = FREE_FN(_free)
+
+
+SPM_NOALLOC_MAX_N = 131072
+
+
+def near_traction_noalloc(x, y, nx, ny, w, sigma, skew, precision=SPM_FP64, out=None):
+    """spm_near_traction_noalloc on torch's current stream: the near-image traction sum of one
+    cell from its node arrays (device FP64 tensors [n], sigma [2n]) without any allocation in
+    the library. Returns out [2n] (allocated here by torch when not given)."""
+    n = x.numel()
+    if out is None:
+        out = torch.empty(2 * n, dtype=torch.float64, device=x.device)
+    st = torch.cuda.current_stream(x.device)
+    rc = lib().spm_near_traction_noalloc(ctypes.c_void_p(st.cuda_stream), n, float(skew), _ptr(x), _ptr(y),
+                                         _ptr(nx), _ptr(ny), _ptr(w), _ptr(sigma), int(precision), _ptr(out))
+    if rc != 0:
+        raise SpmError(rc, "spm_near_traction_noalloc failed")
+    return out
 
 
 class MLP:
@@ -245,6 +273,28 @@ class MLP:
                                             ctypes.byref(loss)))
         return loss.value, g
 
+    def set_weights(self, params_bf16=None, master=None):
+        """spm_mlp_set_weights: bfloat16 weights (a torch.bfloat16 tensor) and/or the FP32 master."""
+        pb = None if params_bf16 is None else params_bf16.to(device=self.device).contiguous()
+        pm = None if master is None else master.to(device=self.device, dtype=torch.float32).contiguous()
+        if pb is not None and pb.dtype != torch.bfloat16:
+            raise TypeError("params_bf16 must be a torch.bfloat16 tensor")
+        self._check(lib().spm_mlp_set_weights(self.h, None if pb is None else ctypes.c_void_p(pb.data_ptr()),
+                                              None if pm is None else _fptr(pm), SPM_MLP_NPARAMS))
+
+    def backward(self, x, dy, mode=SPM_MLP_BF16):
+        """Gradient of sum(dy * MLP(x)) with respect to the packed parameters."""
+        x = x.to(device=self.device, dtype=torch.float32).contiguous()
+        dy = dy.to(device=self.device, dtype=torch.float32).contiguous()
+        g = torch.empty(SPM_MLP_NPARAMS, dtype=torch.float32, device=self.device)
+        self._check(lib().spm_mlp_backward(self.h, _fptr(x), _fptr(dy), x.shape[0], _fptr(g), int(mode)))
+        return g
+
+    def adam_step(self, grad, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1):
+        g = grad.to(device=self.device, dtype=torch.float32).contiguous()
+        self._check(lib().spm_mlp_adam_step(self.h, _fptr(g), float(lr), float(beta1), float(beta2), float(eps),
+                                            int(step)))
+
     def train(self, x, t, idx, batch, lr, mode=SPM_MLP_BF16):
         """Adam steps over the minibatches idx.view(-1, batch) (device int32)."""
         nb = idx.numel() // batch
@@ -298,19 +348,25 @@ class Solver:
         c = np.array(center, dtype=float)
         self._check(lib().spm_set_lattice(self.h, _dp(e1), _dp(e2), _dp(c)))
 
-    def set_ellipses(self, centers, theta, a, b, n_nodes):
+    def set_ellipses(self, centers, theta, a, b, n_nodes=None):
+        """n_nodes None: the library's perimeter rule."""
         c = np.ascontiguousarray(np.asarray(centers, dtype=float).reshape(-1))
         th = np.ascontiguousarray(theta, dtype=float)
         aa = np.ascontiguousarray(a, dtype=float)
         bb = np.ascontiguousarray(b, dtype=float)
-        nn = np.ascontiguousarray(n_nodes, dtype=np.int32)
+        nn = None if n_nodes is None else np.ascontiguousarray(n_nodes, dtype=np.int32)
         self._check(lib().spm_set_ellipses(self.h, len(th), _dp(c), _dp(th), _dp(aa), _dp(bb),
-                                           nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+                                           None if nn is None else nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        self.C = 1
+        self._refresh_sizes()
+
+    def _refresh_sizes(self):
         n = ctypes.c_int64()
         self._check(lib().spm_num_nodes(self.h, ctypes.byref(n)))
         self.N = int(n.value)
-        self.No = len(th)
-        self.C = 1
+        k = ctypes.c_int32()
+        self._check(lib().spm_num_particles(self.h, ctypes.byref(k)))
+        self.No = int(k.value)
 
     def set_workload(self, wl):
         if "kind" in wl:
@@ -332,14 +388,18 @@ class Solver:
         return np.zeros(n, np.int32), prm
 
     def set_cells(self, cells):
-        """An ensemble: a list of workload dicts, one per independent cell."""
+        """An ensemble: a list of workload dicts, one per independent cell (n_nodes None in
+        every cell: the library's perimeter rule)."""
         skews = np.array([float(c["skew"]) for c in cells])
         counts = [len(c["theta"]) for c in cells]
         off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int32)
         cen = np.ascontiguousarray(np.concatenate([np.asarray(c["centers"], float) for c in cells]).reshape(-1))
         th = np.ascontiguousarray(np.concatenate([np.asarray(c["theta"], float) for c in cells]))
-        nn = np.ascontiguousarray(np.concatenate([np.asarray(c["n_nodes"]) for c in cells]).astype(np.int32))
-        ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+        if all(c.get("n_nodes") is None for c in cells):
+            nn = None
+        else:
+            nn = np.ascontiguousarray(np.concatenate([np.asarray(c["n_nodes"]) for c in cells]).astype(np.int32))
+        ip = lambda a: None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
         if any("kind" in c for c in cells):
             shapes = [self._shape_arrays(c) for c in cells]
             kind = np.ascontiguousarray(np.concatenate([k for k, _ in shapes]).astype(np.int32))
@@ -359,7 +419,8 @@ class Solver:
         self.part_off = off
         return self
 
-    def solve_batch(self, sigma0=None, allow_noconv=False):
+    def solve_cells(self, sigma0=None, allow_noconv=False):
+        """Solve the cells set by set_cells (spm_solve_cells)."""
         C = getattr(self, "C", 1)
         sig = self._vec(2 * self.N)
         vel = self._vec(2 * self.No)
@@ -367,10 +428,37 @@ class Solver:
         mu = self._vec(C)
         infos = (spm_solve_info * C)()
         lat = np.zeros(C)
-        rc = lib().spm_solve_batch(self.h, _ptr(sigma0), _ptr(sig), _ptr(vel), _ptr(om), _ptr(mu), infos, _dp(lat))
+        rc = lib().spm_solve_cells(self.h, _ptr(sigma0), _ptr(sig), _ptr(vel), _ptr(om), _ptr(mu), infos, _dp(lat))
         self._check(rc, allow=(SPM_ENOCONV,) if allow_noconv else ())
         return {"sigma": sig, "vel": vel.view(-1, 2), "omega": om, "mu_eff": mu,
                 "infos": [i.as_dict() for i in infos], "latency_s": lat}
+
+    def solve_batch(self, lattices, part_offsets, centers, theta, a, b, n_nodes=None, allow_noconv=False):
+        """One call: set and solve an ensemble of ellipse cells (spm_solve_batch). lattices
+        [C, 6] = e1, e2, cell centre per cell; part_offsets [C + 1]; n_nodes None: the
+        perimeter rule."""
+        lat = np.ascontiguousarray(np.asarray(lattices, dtype=np.float64).reshape(-1))
+        off = np.ascontiguousarray(np.asarray(part_offsets, dtype=np.int32))
+        C = len(off) - 1
+        n = int(off[-1])
+        cen = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1))
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        aa = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+        bb = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+        nn = None if n_nodes is None else np.ascontiguousarray(np.asarray(n_nodes, dtype=np.int32))
+        ip = lambda v: None if v is None else v.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+        vel = self._vec(2 * n)
+        om = self._vec(n)
+        mu = self._vec(C)
+        infos = (spm_solve_info * C)()
+        latency = np.zeros(C)
+        rc = lib().spm_solve_batch(self.h, C, _dp(lat), ip(off), _dp(cen), _dp(th), _dp(aa), _dp(bb), ip(nn),
+                                   _ptr(vel), _ptr(om), _ptr(mu), infos, _dp(latency))
+        self._check(rc, allow=(SPM_ENOCONV,) if allow_noconv else ())
+        self.C = C
+        self._refresh_sizes()
+        return {"vel": vel.view(-1, 2), "omega": om, "mu_eff": mu, "infos": [i.as_dict() for i in infos],
+                "latency_s": latency}
 
     def _vec(self, n):
         return torch.empty(int(n), dtype=torch.float64, device=self.device)
@@ -469,7 +557,12 @@ class Solver:
 
     def features(self):
         f = torch.empty(self.No, SPM_MLP_IN, dtype=torch.float32, device=self.device)
-        self._check(lib().spm_features(self.h, _fptr(f)))
+        self._check(lib().spm_features_f32(self.h, _fptr(f)))
+        return f
+
+    def features_bf16(self):
+        f = torch.empty(self.No, SPM_MLP_IN, dtype=torch.bfloat16, device=self.device)
+        self._check(lib().spm_features(self.h, ctypes.c_void_p(f.data_ptr())))
         return f
 
     def density_modes(self, sigma):
@@ -529,10 +622,10 @@ class Solver:
     def get_launch(self, precision):
         c = np.zeros(4, dtype=np.int32)
         self._check(lib().spm_get_launch(self.h, int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
-        return {"block": int(c[0]), "tpt": int(c[1]), "tile": int(c[2]), "chunk": int(c[3])}
+        return {"block": int(c[0]), "tpt": int(c[1]), "tile": int(c[2]), "wg_per_cu": int(c[3])}
 
-    def set_launch(self, precision, block, tpt, tile, chunk):
-        c = np.array([block, tpt, tile, chunk], dtype=np.int32)
+    def set_launch(self, precision, block, tpt, tile, wg_per_cu=0):
+        c = np.array([block, tpt, tile, wg_per_cu], dtype=np.int32)
         self._check(lib().spm_set_launch(self.h, int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
 
     def profile(self, enable=True):

@@ -68,7 +68,7 @@ def test_contour_ensemble_cells():
     cells = [W.random_ellipses(n, 0.3, seed=1000 + k, h_star=h, name=f"cell{k}") for k, n in enumerate((4, 9, 6))]
     cells.append(W.single_ellipse(n_nodes=96, skew=0.37, center=(0.2, 0.44)))
     s = spm.Solver("cuda:0").set_cells(cells)
-    sig = _n(s.solve_batch()["sigma"])
+    sig = _n(s.solve_cells()["sigma"])
     dev = s.proxy_strengths(torch.as_tensor(sig, device="cuda:0"))
     mu = _n(s.effective_viscosity_contour(torch.as_tensor(sig, device="cuda:0")))
     xi = _n(dev)

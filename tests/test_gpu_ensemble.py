@@ -52,7 +52,7 @@ def test_ensemble_matches_oracle_per_cell(ensemble, precision, graph):
     spm = _spm()
     p = {"fp64": spm.SPM_FP64, "fp32_ir": spm.SPM_FP32_IR, "fp32_relaxed": spm.SPM_FP32_RELAXED}[precision]
     s = spm.Solver("cuda:0", precision=p, use_graph=graph).set_cells(cells)
-    r = s.solve_batch()
+    r = s.solve_cells()
     off = s.part_off
     bound = 1e-9 if precision == "fp64" else 1e-7
     if precision != "fp64":
@@ -85,8 +85,8 @@ def test_ensemble_matches_oracle_per_cell(ensemble, precision, graph):
 def test_graph_replay_is_bitwise_identical(ensemble):
     cells, _ = ensemble
     spm = _spm()
-    a = spm.Solver("cuda:0", use_graph=1).set_cells(cells).solve_batch()
-    b = spm.Solver("cuda:0", use_graph=0).set_cells(cells).solve_batch()
+    a = spm.Solver("cuda:0", use_graph=1).set_cells(cells).solve_cells()
+    b = spm.Solver("cuda:0", use_graph=0).set_cells(cells).solve_cells()
     assert np.array_equal(_n(a["sigma"]), _n(b["sigma"]))
     assert [i["iterations"] for i in a["infos"]] == [i["iterations"] for i in b["infos"]]
 
@@ -119,8 +119,8 @@ def test_ensemble_every_launch_shape(ensemble):
     base = _n(s.near_traction(st))
     for block in (64, 256):
         for tpt in (1, 4):
-            for chunk in (50, 1000):
-                s.set_launch(spm.SPM_FP64, block, tpt, 256, chunk)
+            for tile, wg in ((256, 0), (16, 1)):   # one workgroup per CU with 16-source tiles:
+                s.set_launch(spm.SPM_FP64, block, tpt, tile, wg)   # workgroups span several blocks and cells
                 T = _n(s.near_traction(st))
                 assert np.abs(T - base).max() <= 1e-12 * np.abs(base).max()
 
@@ -135,7 +135,7 @@ def test_full_64_cell_ensemble_sampled_cells():
     cells = W.ensemble_cells(64)
     s = spm.Solver("cuda:0", precision=spm.SPM_FP32_RELAXED, precond=spm.SPM_PRECOND_BLOCK).set_cells(cells)
     s.autotune()
-    r = s.solve_batch()
+    r = s.solve_cells()
     assert all(i["status"] == 0 and i["rel_residual"] <= 1e-10 for i in r["infos"])
     sig, vel, om, mu = _n(r["sigma"]), _n(r["vel"]), _n(r["omega"]), _n(r["mu_eff"])
     N = s.N

@@ -201,7 +201,9 @@ def test_solve(case):
 
 def test_near_sum_every_launch_shape():
     """Every supported launch shape of the near-sum kernel gives the oracle's sum
-    (ragged particle sizes, N not a multiple of any block or tile)."""
+    (ragged particle sizes, N not a multiple of any block or tile). Tiles of 16 sources and
+    one workgroup per compute unit make workgroups own runs that span several target blocks;
+    the default grid with 512-source tiles has fewer units than workgroups."""
     spm = _spm()
     wl = W.random_ellipses(6, 0.3, seed=5, target_total=700)
     prob = op.make_problem(wl)
@@ -212,12 +214,12 @@ def test_near_sum_every_launch_shape():
     for prec, tol in ((spm.SPM_FP64, 1e-12), (spm.SPM_FP32, 5e-4)):
         for block in (64, 128, 256):
             for tpt in (1, 2, 4):
-                for tile in (128, 512):
-                    for chunk in (64, 300, 100000):
-                        s.set_launch(prec, block, tpt, tile, chunk)
+                for tile in (16, 128, 512):
+                    for wg in (0, 1):
+                        s.set_launch(prec, block, tpt, tile, wg)
                         T = _n(s.near_traction(_t(sig), precision=prec))
                         err = np.abs(T - ref).max() / sc
-                        assert err < tol, (prec, block, tpt, tile, chunk, err)
+                        assert err < tol, (prec, block, tpt, tile, wg, err)
     with pytest.raises(spm.SpmError):
         s.set_launch(spm.SPM_FP64, 96, 1, 128, 1)
 

@@ -1,6 +1,8 @@
 """GPU end-to-end tests through the C ABI: full-size workloads (sampled where the
 oracle cannot do the whole thing in seconds), FP32 iterative refinement, time
 stepping, error paths and determinism."""
+import os
+
 import numpy as np
 import pytest
 
@@ -126,6 +128,51 @@ def test_200_ellipses_solve_properties(c200):
         tq = (g.w[sl] * (-rel[:, 1] * s2[sl, 0] + rel[:, 0] * s2[sl, 1])).sum()
         assert np.abs(F).max() < 1e-6 and abs(tq) < 1e-6
     assert abs(float(r["mu_eff"].item()) - ro.mu_eff(prob, x)) < 1e-12
+
+
+GOLDEN_C200 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ellipses200_oracle_solve.npz")
+
+
+@pytest.mark.parametrize("config", ["fp32_ir_precond", "fp64"])
+def test_200_ellipses_bench_configuration_against_oracle_solve(c200, config):
+    """The 200-ellipse cell (N = 51,200) solved as the benchmark solves it (FP32 near sums
+    inside FP64 iterative refinement with the block preconditioner) and by plain FP64 GMRES,
+    both to the FP64 residual 1e-10. The density is put through the oracle's whole FP64
+    operator (Sec. 5 eq. BIEPerturbed, every row): residual within 2e-10 of |b|. The readouts
+    (Sec. 3 eqs. RigidBodyMotion, mueff) are compared with the oracle's own GMRES solve to
+    1e-12 (tests/golden, written by a script that calls only the oracle): 1e-9 relative for
+    FP64, 1e-7 for the mixed form (its density leaves the oracle's Krylov path: the residual
+    times the conditioning of the readouts). Same pressure pin, so the densities agree too."""
+    wl, prob = c200
+    gold = np.load(GOLDEN_C200)
+    assert int(gold["N"]) == prob.N and float(gold["skew"]) == float(wl["skew"])
+    assert float(gold["true_residual"]) <= 1e-11
+    spm = _spm()
+    if config == "fp64":
+        s = spm.Solver("cuda:0", precision=spm.SPM_FP64)
+        tol = 1e-9
+    else:
+        s = spm.Solver("cuda:0", precision=spm.SPM_FP32_IR, precond=spm.SPM_PRECOND_BLOCK)
+        tol = 1e-7
+    s.set_workload(wl)
+    r = s.solve()
+    info = r["info"]
+    print(f"[c200 {config}] {info}", flush=True)
+    assert info["rel_residual"] <= 1e-10
+    x = _n(r["sigma"])
+    b = op.rhs(prob)
+    res = np.linalg.norm(op.apply(prob, x) - b) / np.linalg.norm(b)
+    gv, go, gm = _n(r["vel"]), _n(r["omega"]), float(r["mu_eff"].item())
+    sc_v = max(np.abs(gold["vel"]).max(), np.hypot(*prob.geom.e2))
+    ev = np.abs(gv - gold["vel"]).max() / sc_v
+    eo = np.abs(go - gold["omega"]).max() / max(1.0, np.abs(gold["omega"]).max())
+    em = abs(gm - float(gold["mu_eff"])) / float(gold["mu_eff"])
+    es = np.linalg.norm(x - gold["sigma"]) / np.linalg.norm(gold["sigma"])
+    print(f"[c200 {config}] oracle-operator residual {res:.2e}; v {ev:.2e} omega {eo:.2e} mu_eff {em:.2e} "
+          f"sigma {es:.2e}", flush=True)
+    assert res <= 2e-10
+    assert ev <= tol and eo <= tol and em <= tol
+    assert es <= 100 * tol
 
 
 def test_time_stepping_matches_oracle():

@@ -96,7 +96,7 @@ def test_star_cells_in_one_ensemble():
     cells = [W.two_stars(n_nodes=128), W.star_and_ellipse(), W.random_ellipses(5, 0.3, seed=1004, nodes=64),
              W.stars([[0.1, -0.2]], 0.2, 0.3, 3, theta=0.4, n_nodes=96, skew=-0.3)]
     s = spm.Solver("cuda:0").set_cells(cells)
-    r = s.solve_batch()
+    r = s.solve_cells()
     vel, om, mu = _n(r["vel"]), _n(r["omega"]), _n(r["mu_eff"])
     off = s.part_off
     for k, wl in enumerate(cells):

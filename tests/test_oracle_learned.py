@@ -262,3 +262,39 @@ def test_warm_start_fit_is_never_worse_than_zero():
     nv = op.to1(g.n)
     for dx in (1e-3 * x0, 1e-3 * np.linalg.norm(x0) / np.linalg.norm(nv) * nv):
         assert np.linalg.norm(b - op.apply(prob, x0 + dx)) > r0
+
+
+def test_mlp_backward_of_upstream_gradient_matches_central_differences():
+    """Back-propagation of an arbitrary upstream gradient dy: the derivative of the scalar
+    sum(dy * y) with respect to every weight and bias against central differences (the
+    chain rule written out, checked independently of the loss it is usually fed)."""
+    layers = (4, 6, 5, 3)
+    params = learned.init_params(7, layers)
+    rng = np.random.default_rng(21)
+    for W_, b_ in params:
+        b_ += 0.1 * rng.standard_normal(b_.shape)
+    x = rng.standard_normal((9, 4))
+    dy = rng.standard_normal((9, 3))
+    _, acts = learned.forward(params, x)
+    grads = learned.backward(params, acts, dy)
+
+    def scalar():
+        y, _ = learned.forward(params, x)
+        return float((dy * y).sum())
+
+    h = 1e-6
+    for li in range(len(params)):
+        for k in range(2):
+            p = params[li][k]
+            num = np.zeros_like(p)
+            it = np.nditer(p, flags=["multi_index"])
+            for _ in it:
+                idx = it.multi_index
+                old = p[idx]
+                p[idx] = old + h
+                fp = scalar()
+                p[idx] = old - h
+                fm = scalar()
+                p[idx] = old
+                num[idx] = (fp - fm) / (2 * h)
+            assert np.abs(num - grads[li][k]).max() < 1e-7 * max(1.0, np.abs(num).max())
