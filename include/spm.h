@@ -77,6 +77,16 @@ extern "C" {
 #define SPM_NEAR_FMM 1     /* near-image sum: fast multipole method in FP64 (Sec. 6.2 remark: the
                               paper evaluates this sum with an FMM); single-cell handles, SPM_FP64 */
 
+#define SPM_NEAR_SET_3X3 0      /* near images: the 3x3 lattice images of every whole particle (centres
+                                   wrapped into the cell); proxies on a circle of radius R_proxy */
+#define SPM_NEAR_SET_DILATED 1  /* the near set of Sec. 4.2 (definition of G_near): every node wrapped into the
+                                   cell on its own, its images inside the dilated cell U~ (same centre,
+                                   twice the side: four images per node); proxies on U~'s walls (Sec. 6.1
+                                   remark), M/4 per side (M a multiple of 4). Direct near sums only;
+                                   particles must stay within lattice distance 1/2 of their close
+                                   neighbourhood (SPM_EINVAL at set-up otherwise); no contour mu_eff and no
+                                   field evaluation */
+
 #define SPM_PRECOND_NONE 0
 #define SPM_PRECOND_BLOCK 1  /* right preconditioner blockdiag(B_q)^-1 of isolated-body self blocks
                                 (particles of at most 512 nodes; SPM_EINVAL at the solve otherwise) */
@@ -119,6 +129,10 @@ typedef struct {
                            [2.170590708293102e-3: about 5,000 nodes for 25 ellipses of aspect
                            ratio 1.5-3 at area fraction 0.3] */
   double relax_safety;  /* margin theta of the adaptive relaxed switch point, 0 < theta <= 1 [0.1] */
+  double learned_accept;/* SPM_X0_NETWORK: a cell whose fitted network guess leaves a relative residual
+                           above this starts from zero instead (GMRES judges the guess) [0.5] */
+  int32_t near_set;     /* SPM_NEAR_SET_3X3 or SPM_NEAR_SET_DILATED [SPM_NEAR_SET_3X3]; with the dilated
+                           set, M = 64, m_wall = 24 and rcond = 1e-10 are the measured choices */
 } spm_config;
 
 typedef struct {
@@ -139,6 +153,8 @@ typedef struct {
                               images, every cell of the handle): the boundary gap to within
                               the node spacing; 1e300 when no two particles come within the
                               close-evaluation reach */
+  int32_t guess_rejected;  /* SPM_X0_NETWORK: 1 if the fitted network guess left a residual above
+                              cfg.learned_accept and the solve started from zero */
 } spm_solve_info;
 
 typedef void* (*spm_alloc_fn)(size_t bytes, void* stream, void* ctx);

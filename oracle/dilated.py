@@ -101,6 +101,23 @@ def discrepancy(geom, W, f, mu):
     return np.concatenate(out)
 
 
+def wall_proxies(geom, M):
+    """Proxy points on the walls of the dilated cell U~ (Sec. 6.1 remark: the expanded unit
+    cell is the proxy surface): M / 4 points on each side of the parallelogram with corners
+    c_U +- e1 +- e2, equispaced at the midpoints of M / 4 equal parameter intervals (the paper
+    does not state the distribution along the walls), counter-clockwise from the bottom side."""
+    if M % 4:
+        raise ValueError("M must be a multiple of 4")
+    k = M // 4
+    t = -1.0 + (np.arange(k) + 0.5) * (2.0 / k)
+    e1, e2, c = geom.e1, geom.e2, geom.cU
+    sides = [c - e2 + t[:, None] * e1,          # bottom, left to right
+             c + e1 + t[:, None] * e2,          # right, bottom to top
+             c + e2 - t[:, None] * e1,          # top, right to left
+             c - e1 - t[:, None] * e2]          # left, top to bottom
+    return np.concatenate(sides)
+
+
 def max_extent_ok(geom, close_factor=10.0):
     """Whether every particle is small enough for the U~ near set: its diameter plus the
     close-evaluation distance stays below lattice distance 1/2 in both lattice directions."""

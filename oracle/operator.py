@@ -38,6 +38,7 @@ class Config:
     rcond: float = 1e-14
     image_range: int = 1
     near_set: str = "3x3"   # "3x3": 3x3 images of whole particles; "dilated": the U~ set of Sec. 4.2
+    proxy_surface: str = "circle"   # "circle": M proxies on a circle of radius R; "walls": on U~'s walls
 
 
 @dataclass
@@ -64,7 +65,9 @@ def make_problem(wl, **kw) -> Problem:
     if cfg.near_set == "dilated" and not dilated.max_extent_ok(g, cfg.close_factor):
         raise ValueError("particles too large for the dilated-cell near set")
     W = periodizer.walls(g, cfg.m)
-    P = periodizer.proxies(g, cfg.M, cfg.R)
+    if cfg.proxy_surface not in ("circle", "walls"):
+        raise ValueError(cfg.proxy_surface)
+    P = periodizer.proxies(g, cfg.M, cfg.R) if cfg.proxy_surface == "circle" else dilated.wall_proxies(g, cfg.M)
     Q = periodizer.build_Q(g, W, P, cfg.mu)
     Qp = periodizer.pinv_gauge_truncated(Q, cfg.rcond)
     pairs = close.close_pairs(g, cfg.close_factor, cfg.image_range) if cfg.close_factor > 0 else \

@@ -203,8 +203,8 @@ void build_periodizers(spm_handle* h) {
   const int m = P.m, M = P.M;
   ensure(h, P.wx, (size_t)C * 2 * m);
   ensure(h, P.wy, (size_t)C * 2 * m);
-  ensure(h, P.px, M);
-  ensure(h, P.py, M);
+  ensure(h, P.px, (size_t)C * M);
+  ensure(h, P.py, (size_t)C * M);
   ensure(h, P.Q, (size_t)C * 8 * m * 2 * M);
   ensure(h, P.Qp, (size_t)C * 8 * m * 2 * M);
   ensure(h, P.svd_a, (size_t)C * 8 * m * 2 * M);
@@ -220,7 +220,7 @@ void build_periodizers(spm_handle* h) {
   ensure(h, P.svd_s, (size_t)C * (2 * M + 1));
   std::vector<double> t, w;
   gauss_legendre(m, t, w);
-  std::vector<double> wx((size_t)C * 2 * m), wy((size_t)C * 2 * m), px(M), py(M);
+  std::vector<double> wx((size_t)C * 2 * m), wy((size_t)C * 2 * m), px, py;
   for (int c = 0; c < C; ++c) {
     const double s = h->cells[c].skew;
     for (int i = 0; i < m; ++i) {
@@ -232,15 +232,38 @@ void build_periodizers(spm_handle* h) {
       wy[(size_t)c * 2 * m + m + i] = h->cU[1] - 0.5;
     }
   }
-  for (int p = 0; p < M; ++p) {
-    const double th = 2.0 * kPi * p / M;
-    px[p] = h->cU[0] + h->cfg.R_proxy * std::cos(th);
-    py[p] = h->cU[1] + h->cfg.R_proxy * std::sin(th);
+  // proxies of every cell: M on a circle about c_U (3x3 near set) or M/4 on each wall of the
+  // dilated cell U~ = c_U + [-1, 1) e1 + [-1, 1) e2, at the midpoints of equal parameter
+  // intervals, counter-clockwise from the bottom side (dilated near set, Sec. 6.1 remark)
+  px.assign((size_t)C * M, 0.0);
+  py.assign((size_t)C * M, 0.0);
+  for (int c = 0; c < C; ++c) {
+    const double sk = h->cells[c].skew;
+    for (int p = 0; p < M; ++p) {
+      double X, Y;
+      if (h->cfg.near_set == SPM_NEAR_SET_DILATED) {
+        const int k = M / 4, side = p / k;
+        const double t = -1.0 + (p % k + 0.5) * (2.0 / k);
+        double a = 0, b = 0;   // lattice coordinates
+        if (side == 0) { a = t; b = -1.0; }
+        else if (side == 1) { a = 1.0; b = t; }
+        else if (side == 2) { a = -t; b = 1.0; }
+        else { a = -1.0; b = -t; }
+        X = h->cU[0] + a + b * sk;
+        Y = h->cU[1] + b;
+      } else {
+        const double th = 2.0 * kPi * p / M;
+        X = h->cU[0] + h->cfg.R_proxy * std::cos(th);
+        Y = h->cU[1] + h->cfg.R_proxy * std::sin(th);
+      }
+      px[(size_t)c * M + p] = X;
+      py[(size_t)c * M + p] = Y;
+    }
   }
   upload(h, P.wx, wx.data(), wx.size() * sizeof(double));
   upload(h, P.wy, wy.data(), wy.size() * sizeof(double));
-  upload(h, P.px, px.data(), M * sizeof(double));
-  upload(h, P.py, py.data(), M * sizeof(double));
+  upload(h, P.px, px.data(), px.size() * sizeof(double));
+  upload(h, P.py, py.data(), py.size() * sizeof(double));
   launch_build_Q(h);
   launch_pinv(h);
   ensure(h, h->wk.xi, (size_t)C * 2 * M);
@@ -542,7 +565,25 @@ void set_cells_impl(spm_handle* h, int C, const double* skews, const int32_t* pa
   upload(h, g.cnoff, cnoff.data(), (C + 1) * sizeof(int64_t));
   upload(h, g.cpoff, cpoff.data(), (C + 1) * sizeof(int32_t));
   upload(h, g.cskew, cskew.data(), C * sizeof(double));
+  g.dilated = h->cfg.near_set == SPM_NEAR_SET_DILATED ? 1 : 0;
+  if (g.dilated) {
+    ensure(h, g.xw, N);
+    ensure(h, g.yw, N);
+    ensure(h, g.nwrap, N);
+  }
   launch_geometry(h);
+  if (g.dilated) {
+    // every particle and its close neighbourhood within lattice distance 1/2 of each of its
+    // nodes, so that each close source curve lies whole inside the dilated cell seen from a
+    // target in the cell: (1 + |s|)(2 r_max + close_factor h_q) < 1/2, h_q = perimeter / N_q
+    std::vector<double> per(n);
+    download(h, per.data(), g.pper, n * sizeof(double));
+    for (int i = 0; i < n; ++i) {
+      const double s = std::fabs(h->cells[h->pcell[i]].skew);
+      if ((1.0 + s) * (2.0 * h->a[i] + h->cfg.close_factor * per[i] / h->nn[i]) >= 0.5)
+        throw ApiError(SPM_EINVAL, "particle " + std::to_string(i) + " too large for the dilated near set");
+    }
+  }
   mark("geometry");
   build_periodizers(h);
   mark("periodizers");
@@ -867,6 +908,7 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
   }
   gm_stamp_start(h);
   const bool net = !sigma0 && at.network;
+  h->guess_rejected.assign(C, 0);
   if (sigma0)
     gm_copy(h, sigma, sigma0, n2);
   else if (net)
@@ -881,9 +923,27 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
     gm_dot(h, K.tmp2, K.tmp2, K.dots);
     double* hd = host_scratch<double>(h, C);
     download(h, hd, K.dots, C * sizeof(double));
+    // plain GMRES judges the guess: a cell whose fitted guess leaves more than learned_accept of
+    // the zero start's residual starts from zero (a loose guess puts every slowly converging
+    // error component into the starting residual and costs iterations)
+    std::vector<int32_t> reject(C, 0);
+    int nrej = 0;
     for (int c = 0; c < C; ++c) {
       st.rel[c] = std::sqrt(hd[c]) / st.bnorm[c];
       st.m64[c] += 1;
+      if (st.rel[c] > h->cfg.learned_accept) {
+        reject[c] = 1;
+        st.rel[c] = 1.0;
+        ++nrej;
+      }
+    }
+    h->guess_rejected = reject;
+    if (nrej > 0) {
+      int32_t* hm = host_scratch<int32_t>(h, C);
+      std::memcpy(hm, reject.data(), C * sizeof(int32_t));
+      SPM_HIP_CHECK(hipMemcpyAsync(K.mask, hm, C * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+      launch_reject_guess(h, K.mask, K.b, sigma, K.tmp2);
+      sync(h);
     }
   } else {
     gm_copy(h, K.tmp2, K.b, n2);
@@ -1023,6 +1083,7 @@ int solve_api(spm_handle* h, const double* sigma0, double* sigma, double* vel, d
     infos[c].min_gap = h->min_gap_est;
     infos[c].seconds_solve = t1 - t0;
     infos[c].seconds_readout = t2 - t1;
+    infos[c].guess_rejected = c < (int)h->guess_rejected.size() ? h->guess_rejected[c] : 0;
     if (latency_out) latency_out[c] = (double)(stamps[c] - stamps[C]) / h->wallclock_hz;
     if (info_out) info_out[c] = infos[c];
   }
@@ -1346,7 +1407,7 @@ void build_near_plan(spm_handle* h, int precision) {
   ensure(h, P.slot_off, (size_t)P.nblocks + 1);
   upload(h, P.cell_nt, nt.data(), C * sizeof(int32_t));
   upload(h, P.cell_blk, blk.data(), (C + 1) * sizeof(int32_t));
-  P.grid = near_persistent_grid(P.cfg, precision);
+  P.grid = near_persistent_grid(P.cfg, precision, h->geo.dilated != 0);
   size_t need = 2 * (size_t)h->geo.N;
   for (const NearPlan& Q : h->wk.near)
     if (Q.bt > 0) need = std::max(need, ((size_t)Q.nblocks + (size_t)Q.grid) * 2 * (size_t)Q.bt);
@@ -1404,6 +1465,8 @@ void spm_default_config(spm_config* c) {
   c->learned_max_iter = 0;
   c->node_spacing = 2.170590708293102e-3;
   c->relax_safety = 0.1;
+  c->learned_accept = 0.5;
+  c->near_set = SPM_NEAR_SET_3X3;
 }
 
 int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_fn alloc, spm_free_fn free_fn,
@@ -1421,12 +1484,14 @@ int spm_create(spm_handle** out, const spm_config* cfg, void* stream, spm_alloc_
       !(c.tol > 0) || c.max_iter < 1 || c.max_iter > 5000 || c.close_factor < 0 ||
       (c.precision != SPM_FP64 && c.precision != SPM_FP32_IR && c.precision != SPM_FP32_RELAXED) ||
       !(c.inner_tol >= 0 && c.inner_tol < 1) || !(c.relax_tol >= 0 && c.relax_tol < 1) ||
-      !(c.relax_safety > 0 && c.relax_safety <= 1) || !(c.node_spacing > 0) ||
+      !(c.relax_safety > 0 && c.relax_safety <= 1) || !(c.node_spacing > 0) || !(c.learned_accept > 0) ||
       c.poll_every < 1 || c.x0 < SPM_X0_ZERO || c.x0 > SPM_X0_NETWORK ||
       (c.precond != SPM_PRECOND_NONE && c.precond != SPM_PRECOND_BLOCK) || c.learned_max_iter < 0 ||
       (c.near_method != SPM_NEAR_DIRECT && c.near_method != SPM_NEAR_FMM) ||
       (c.near_method == SPM_NEAR_FMM && c.precision != SPM_FP64) ||
-      (c.fmm_order != 0 && (c.fmm_order < 8 || c.fmm_order > 64))) {
+      (c.fmm_order != 0 && (c.fmm_order < 8 || c.fmm_order > 64)) ||
+      (c.near_set != SPM_NEAR_SET_3X3 && c.near_set != SPM_NEAR_SET_DILATED) ||
+      (c.near_set == SPM_NEAR_SET_DILATED && (c.near_method != SPM_NEAR_DIRECT || c.M % 4 != 0))) {
     delete h;
     return SPM_EINVAL;
   }
@@ -1669,6 +1734,7 @@ int spm_eval_field(spm_handle* h, const double* sigma, int64_t n_targets, const 
                    double* u, double* p) {
   return guarded(h, [&]() {
     need_particles(h);
+    if (h->geo.dilated) throw ApiError(SPM_EINVAL, "not available with the dilated near set");
     if (h->geo.C != 1) throw ApiError(SPM_EINVAL, "field evaluation runs on a single-cell handle");
     if (!sigma || n_targets < 0 || n_targets > ((int64_t)1 << 28) ||
         (n_targets > 0 && (!xt || !yt || !u || !p)))
@@ -1702,6 +1768,7 @@ int spm_effective_viscosity(spm_handle* h, const double* sigma, double* mu_eff) 
 int spm_effective_viscosity_contour(spm_handle* h, const double* sigma, int32_t m, double* mu_eff) {
   return guarded(h, [&]() {
     need_particles(h);
+    if (h->geo.dilated) throw ApiError(SPM_EINVAL, "not available with the dilated near set");
     if (!sigma || !mu_eff) throw ApiError(SPM_EINVAL, "null pointer");
     if (m == 0) m = 16;
     if (m < 4 || m > 128) throw ApiError(SPM_EINVAL, "contour quadrature order outside [4, 128]");

@@ -170,10 +170,23 @@ __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets
         gt_pair(dx - shx, row_terms(dy, shy, nyi, f2[kk]), nxi, f1[kk], a1, a2);
         p1 += a1;
         p2 += a2;
-      } else {
+      } else if (!g.dilated) {
         const float dx = g.xf[i] - g.xf[kk], dy = g.yf[i] - g.yf[kk];
         float a1 = 0.f, a2 = 0.f;
         gt_pair(dx - shxf, row_terms(dy, shyf, g.nyf[i], f2f[kk]), g.nxf[i], f1f[kk], a1, a2);
+        p1 += (double)a1;
+        p2 += (double)a2;
+      } else {
+        // dilated set: the FP32 shadows are the wrapped nodes, and the near sum met node kk of
+        // this curve image at the lattice shift t = s + (wrap of i) - (wrap of kk); the same
+        // shift expression and per-pair arithmetic as the near kernel's
+        const int32_t wi = g.nwrap[i], wk = g.nwrap[kk];
+        const int tm = s / 3 - 1 + node_wrap_ka(wi) - node_wrap_ka(wk);
+        const int tn = s % 3 - 1 + node_wrap_kb(wi) - node_wrap_kb(wk);
+        const float dx = g.xf[i] - g.xf[kk], dy = g.yf[i] - g.yf[kk];
+        float a1 = 0.f, a2 = 0.f;
+        gt_pair(dx - (float)shift_xmn(tm, tn, skew), row_terms(dy, (float)tn, g.nyf[i], f2f[kk]), g.nxf[i], f1f[kk],
+                a1, a2);
         p1 += (double)a1;
         p2 += (double)a2;
       }
@@ -278,6 +291,8 @@ __global__ __launch_bounds__(1024) void k_self_fix(int64_t N, Geo g, const doubl
     const int64_t i = o + k0;
     const double xi = g.x[i], yi = g.y[i], nxi = g.nx[i], nyi = g.ny[i];
     const float xif = g.xf[i], yif = g.yf[i], nxif = g.nxf[i], nyif = g.nyf[i];
+    const int32_t wi = g.dilated ? g.nwrap[i] : 0;
+    const double skew = g.cskew[g.pcell[q]];
     double d1 = 0.0, d2 = 0.0, e1 = 0.0, e2 = 0.0;
     for (int k = sub; k < n; k += L) {
       const int64_t kk = o + k;
@@ -288,10 +303,18 @@ __global__ __launch_bounds__(1024) void k_self_fix(int64_t N, Geo g, const doubl
         d1 += a1;
         d2 += a2;
       }
-      {
+      if (!g.dilated) {
         const float dx = xif - g.xf[kk], dy = yif - g.yf[kk];
         float a1 = 0.f, a2 = 0.f;
         gt_pair(dx - 0.0f, row_terms(dy, 0.0f, nyif, f2f[kk]), nxif, f1f[kk], a1, a2);
+        e1 += (double)a1;
+        e2 += (double)a2;
+      } else {   // wrapped nodes: the own curve's node kk sits at shift (wrap of i) - (wrap of kk)
+        const int tm = node_wrap_ka(wi) - node_wrap_ka(g.nwrap[kk]);
+        const int tn = node_wrap_kb(wi) - node_wrap_kb(g.nwrap[kk]);
+        const float dx = xif - g.xf[kk], dy = yif - g.yf[kk];
+        float a1 = 0.f, a2 = 0.f;
+        gt_pair(dx - (float)shift_xmn(tm, tn, skew), row_terms(dy, (float)tn, nyif, f2f[kk]), nxif, f1f[kk], a1, a2);
         e1 += (double)a1;
         e2 += (double)a2;
       }

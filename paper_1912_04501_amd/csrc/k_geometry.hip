@@ -6,10 +6,14 @@ namespace spm {
 // One thread per node: x(t) = c + R(theta) x_body(t), t = 2 pi k / N_p (x_body: ellipse
 // (a cos t, b sin t) or star r(t) (cos t, sin t)). w = (2 pi / N_p)|x'|, tau = x'/|x'|,
 // n = (tau_2, -tau_1), kappa = (x' y'' - y' x'') / |x'|^3 (= a b / |x'|^3 for an ellipse).
+// With the dilated near set every node is also wrapped into the cell on its own: lattice
+// coordinates (alpha, beta) of x - c_U reduced to [-1/2, 1/2) as floor(. + 1/2) (Sec. 4.2, the
+// sources of G_near are points of the cell); the FP32 shadows then hold the wrapped node.
 __global__ void k_geometry(int64_t N, const int32_t* __restrict__ pid, const int32_t* __restrict__ poff,
                            const int32_t* __restrict__ pn, const double* __restrict__ pcx,
                            const double* __restrict__ pcy, const double* __restrict__ pth,
-                           const int32_t* __restrict__ pkind, const double* __restrict__ pprm, Geo g) {
+                           const int32_t* __restrict__ pkind, const double* __restrict__ pprm, double cUx,
+                           double cUy, Geo g) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int p = pid[i];
@@ -39,10 +43,22 @@ __global__ void k_geometry(int64_t N, const int32_t* __restrict__ pid, const int
   // spectral derivative weight at index distance k (N_p even): (1/2) (-1)^k cot(k pi / N_p), 0 at k = 0
   g.dcot[i] = k > 0 ? ((k & 1) ? -0.5 : 0.5) * (cos(kPi * (double)k / (double)n) / sin(kPi * (double)k / (double)n))
                     : 0.0;
-  g.xf[i] = (float)x;
-  g.yf[i] = (float)y;
   g.nxf[i] = (float)ty;
   g.nyf[i] = (float)(-tx);
+  if (g.dilated) {
+    const double skew = g.cskew[g.ncell[i]];
+    const double be = y - cUy, al = (x - cUx) - skew * be;
+    const double ka = -floor(al + 0.5), kb = -floor(be + 0.5);
+    const double xw = x + ka + kb * skew, yw = y + kb;
+    g.xw[i] = xw;
+    g.yw[i] = yw;
+    g.nwrap[i] = node_wrap_pack((int)ka, (int)kb, (al + ka) < 0.0 ? 1 : -1, (be + kb) < 0.0 ? 1 : -1);
+    g.xf[i] = (float)xw;
+    g.yf[i] = (float)yw;
+  } else {
+    g.xf[i] = (float)x;
+    g.yf[i] = (float)y;
+  }
 }
 
 // Perimeter of every particle (sum of its trapezoid weights) and its area by the
@@ -68,7 +84,7 @@ void launch_geometry(spm_handle* h) {
   Geo& g = h->geo;
   const int bs = 256;
   k_geometry<<<(unsigned)((g.N + bs - 1) / bs), bs, 0, h->stream>>>(g.N, g.pid, g.poff, g.pn, g.pcx, g.pcy,
-                                                                    g.pth, g.pkind, g.pprm, g);
+                                                                    g.pth, g.pkind, g.pprm, h->cU[0], h->cU[1], g);
   SPM_HIP_CHECK(hipGetLastError());
   k_perimeter<<<g.No, 256, 0, h->stream>>>(g.poff, g, g.pper, g.parea);
   SPM_HIP_CHECK(hipGetLastError());

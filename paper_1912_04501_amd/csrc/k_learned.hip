@@ -231,6 +231,23 @@ void launch_apply_fit(spm_handle* h, const double* coef, const double* b, const 
   SPM_HIP_CHECK(hipGetLastError());
 }
 
+// Cells whose fitted guess is rejected (mask[cell] != 0) start from zero: x = 0, r = b.
+__global__ void k_reject_guess(int64_t N, const int32_t* __restrict__ ncell, const int32_t* __restrict__ mask,
+                               const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= N || mask[ncell[i]] == 0) return;
+  x[i] = 0.0;
+  x[N + i] = 0.0;
+  r[i] = b[i];
+  r[N + i] = b[N + i];
+}
+
+void launch_reject_guess(spm_handle* h, const int32_t* mask, const double* b, double* x, double* r) {
+  const int64_t N = h->geo.N;
+  k_reject_guess<<<(unsigned)((N + 255) / 256), 256, 0, h->stream>>>(N, h->geo.ncell, mask, b, x, r);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
 // x += f * (num[cell] / den[cell]) n over all nodes (SoA [2N])
 __global__ void k_add_normal(int64_t N, const int32_t* __restrict__ ncell, const double* __restrict__ nx,
                              const double* __restrict__ ny, const double* __restrict__ num,

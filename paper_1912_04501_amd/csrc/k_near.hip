@@ -4,14 +4,18 @@
 //
 // for every cell of the ensemble (targets and sources of one cell only). Tiled direct
 // N-body in one persistent launch. The work of a cell is cut into units: a block of
-// BLOCK * TPT targets against one tile of `tile` sources. The units of the active cells,
-// in the order (cell, target block, source tile), are divided evenly over the persistent
-// workgroups (workgroup g takes units [g U / G, (g + 1) U / G)), so every workgroup does the
-// same number of pair evaluations up to one tile and no work queue is needed. A workgroup
-// keeps the FP64 sum of its consecutive tiles of one target block in registers and writes
-// one partial per target block it touches: at most (target blocks + workgroups) partials
-// in all, which the combine step sums per block in workgroup order (deterministic, no
-// floating-point atomics).
+// BLOCK * TPT targets against one tile of `tile` sources. The units of the active cells, in
+// the order (cell, target block, source tile), are divided evenly over the persistent
+// workgroups (workgroup g takes units [g U / G, (g + 1) U / G)). Each workgroup keeps the FP64
+// sum of its consecutive tiles of one target block in registers and writes one partial per
+// target block it touches: at most (target blocks + workgroups) partials in all, which the
+// combine step sums per block in workgroup order (deterministic, no floating-point atomics).
+//
+// The wave scheduler issues from the oldest ready wave first, so in this issue-bound kernel
+// equal shares would finish at very different times (1.6 to 7 ms for one launch measured with
+// per-workgroup wall clocks). Each workgroup therefore sets its waves' issue priority from its
+// own progress (s_setprio: 3 in the first quarter of its share, down to 0 in the last): a
+// workgroup that has fallen behind issues ahead of those that are further along.
 //
 // Inside a unit: one target per lane (or TPT targets i, i + BLOCK, ...), the source tile
 // staged in LDS (every lane of a wave reads the same source: LDS broadcast), the 9 image
@@ -27,6 +31,22 @@ namespace spm {
 template <typename R>
 struct Src {
   R y1, y2, f1, f2;
+};
+
+// A source of the dilated near set: its wrapped position and force, and the x components of
+// its three non-zero image shifts (ms, 0), (0, ns), (ms, ns) and the y component ns.
+template <typename R>
+struct SrcD {
+  R y1, y2, f1, f2, sxA, sxB, sxC, syB;
+};
+
+template <typename R, bool DIL>
+struct SrcOf {
+  typedef Src<R> type;
+};
+template <typename R>
+struct SrcOf<R, true> {
+  typedef SrcD<R> type;
 };
 
 // Owner of position p of the unit sequence [0, U) divided over G workgroups (the largest g
@@ -106,28 +126,146 @@ __global__ __launch_bounds__(1024) void k_near_partition(int C, const int32_t* _
   if (t == 0) slot_off[nblocks] = s_carry;
 }
 
-// TPT targets per lane (i, i + BLOCK, ...) share every LDS source read. Each LDS tile is
-// summed in a fresh accumulator of the kernel's precision and then added to an FP64
-// running sum, which keeps the FP32 summation error at the level of one tile.
-template <typename R, int BLOCK, int TPT>
+// One run: targets t0 .. t0 + BLOCK * TPT (clipped at n1) against sources [s_begin, s_end) of
+// the cell, in tiles staged through LDS; writes -(1/pi) x the FP64 sum to out[local] and
+// out[BLOCK * TPT + local]. TPT targets per lane (i, i + BLOCK, ...) share every LDS source
+// read. Each LDS tile is summed in a fresh accumulator of the kernel's precision and then added
+// to an FP64 running sum, which keeps the FP32 summation error at the level of one tile. Every
+// thread of the workgroup takes part (the tile loop synchronises).
+// done0, share: units of the workgroup's share finished before this run and the share's size
+// (the issue priority follows done / share). DIL: the dilated near set (Sec. 4.2): x, y are the
+// wrapped nodes, and every source has the four images {0, ms} x {0, ns} given by nwrap (two
+// lattice rows of two images each) instead of the nine of the 3x3 set.
+template <typename R, int BLOCK, int TPT, bool DIL>
+__device__ __forceinline__ void near_run(typename SrcOf<R, DIL>::type* src, const R* __restrict__ x,
+                                         const R* __restrict__ y, const R* __restrict__ nx,
+                                         const R* __restrict__ ny, const R* __restrict__ f1,
+                                         const R* __restrict__ f2, const int32_t* __restrict__ nwrap, double skew,
+                                         int64_t t0, int64_t n1, int64_t s_begin, int64_t s_end, int tile,
+                                         int64_t done0, int64_t share, double* __restrict__ out) {
+  constexpr int BT = BLOCK * TPT;
+  R sx[kShifts], sy[kShifts];
+#pragma unroll
+  for (int m = 0; m < kShifts; ++m) {
+    sx[m] = (R)shift_x(m, skew);
+    sy[m] = (R)shift_y(m);
+  }
+  R xi[TPT], yi[TPT], nxi[TPT], nyi[TPT];
+  double A1[TPT], A2[TPT];
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const int64_t i = t0 + threadIdx.x + t * BLOCK;
+    xi[t] = 0;
+    yi[t] = 0;
+    nxi[t] = 0;
+    nyi[t] = 0;
+    if (i < n1) {
+      xi[t] = x[i];
+      yi[t] = y[i];
+      nxi[t] = nx[i];
+      nyi[t] = ny[i];
+    }
+    A1[t] = 0.0;
+    A2[t] = 0.0;
+  }
+  for (int64_t jt = s_begin; jt < s_end; jt += tile) {
+    const int cnt = (int)((jt + tile < s_end) ? tile : (s_end - jt));
+    {
+      const int64_t level = (4 * (done0 + (jt - s_begin) / tile)) / share;
+      if (level <= 0)
+        __builtin_amdgcn_s_setprio(3);
+      else if (level == 1)
+        __builtin_amdgcn_s_setprio(2);
+      else if (level == 2)
+        __builtin_amdgcn_s_setprio(1);
+      else
+        __builtin_amdgcn_s_setprio(0);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < cnt; k += BLOCK) {
+      typename SrcOf<R, DIL>::type s;
+      s.y1 = x[jt + k];
+      s.y2 = y[jt + k];
+      s.f1 = f1[jt + k];
+      s.f2 = f2[jt + k];
+      if constexpr (DIL) {
+        const int32_t w = nwrap[jt + k];
+        const int ms = node_wrap_ms(w), ns = node_wrap_ns(w);
+        s.sxA = (R)shift_xmn(ms, 0, skew);
+        s.sxB = (R)shift_xmn(0, ns, skew);
+        s.sxC = (R)shift_xmn(ms, ns, skew);
+        s.syB = (R)ns;
+      }
+      src[k] = s;
+    }
+    __syncthreads();
+    R a1[TPT], a2[TPT];
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      a1[t] = 0;
+      a2[t] = 0;
+    }
+    for (int k = 0; k < cnt; ++k) {
+      const typename SrcOf<R, DIL>::type s = src[k];
+#pragma unroll
+      for (int t = 0; t < TPT; ++t) {
+        const R dx = xi[t] - s.y1, dy = yi[t] - s.y2;
+        if constexpr (DIL) {
+          const R zero = (R)shift_xmn(0, 0, skew);
+          const RowTerms<R> r0 = row_terms(dy, zero, nyi[t], s.f2);
+          const RowTerms<R> rB = row_terms(dy, s.syB, nyi[t], s.f2);
+          gt_pair(dx - zero, r0, nxi[t], s.f1, a1[t], a2[t]);
+          gt_pair(dx - s.sxA, r0, nxi[t], s.f1, a1[t], a2[t]);
+          gt_pair(dx - s.sxB, rB, nxi[t], s.f1, a1[t], a2[t]);
+          gt_pair(dx - s.sxC, rB, nxi[t], s.f1, a1[t], a2[t]);
+        } else {
+          RowTerms<R> row[3];
+#pragma unroll
+          for (int n = 0; n < 3; ++n) row[n] = row_terms(dy, sy[n], nyi[t], s.f2);
+#pragma unroll
+          for (int m = 0; m < kShifts; ++m) gt_pair(dx - sx[m], row[m % 3], nxi[t], s.f1, a1[t], a2[t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TPT; ++t) {
+      A1[t] += (double)a1[t];
+      A2[t] += (double)a2[t];
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TPT; ++t) {
+    const int local = threadIdx.x + t * BLOCK;
+    if (t0 + local < n1) {
+      out[local] = -(1.0 / kPi) * A1[t];
+      out[BT + local] = -(1.0 / kPi) * A2[t];
+    }
+  }
+}
+
+template <typename R, int BLOCK, int TPT, bool DIL>
 __global__ __launch_bounds__(BLOCK) void k_near(int C, const R* __restrict__ x, const R* __restrict__ y,
-                                                const R* __restrict__ nx, const R* __restrict__ ny,
-                                                const R* __restrict__ f1, const R* __restrict__ f2,
-                                                const double* __restrict__ cskew, const int64_t* __restrict__ cnoff,
-                                                const int32_t* __restrict__ cell_nt,
-                                                const int32_t* __restrict__ cell_blk,
-                                                const int64_t* __restrict__ unit_off,
-                                                const int32_t* __restrict__ slot_off, int grid, int tile,
-                                                double* __restrict__ Tpart) {
+                                                       const R* __restrict__ nx, const R* __restrict__ ny,
+                                                       const R* __restrict__ f1, const R* __restrict__ f2,
+                                                       const int32_t* __restrict__ nwrap,
+                                                       const double* __restrict__ cskew,
+                                                       const int64_t* __restrict__ cnoff,
+                                                       const int32_t* __restrict__ cell_nt,
+                                                       const int32_t* __restrict__ cell_blk,
+                                                       const int64_t* __restrict__ unit_off,
+                                                       const int32_t* __restrict__ slot_off, int grid, int tile,
+                                                       double* __restrict__ Tpart) {
   extern __shared__ unsigned char smem_raw[];
-  Src<R>* src = reinterpret_cast<Src<R>*>(smem_raw);
+  typedef typename SrcOf<R, DIL>::type S;
+  S* src = reinterpret_cast<S*>(smem_raw);
   constexpr int BT = BLOCK * TPT;
   const int64_t U = unit_off[C];
   const int64_t G = U < grid ? U : grid;
   const int64_t g = blockIdx.x;
   if (g >= G) return;
-  int64_t p = g * U / G;
+  const int64_t pbeg = g * U / G;
   const int64_t pend = (g + 1) * U / G;
+  int64_t p = pbeg;
   while (p < pend) {
     int lo = 0, hi = C;   // unit_off[lo] <= p < unit_off[hi]
     while (hi - lo > 1) {
@@ -143,92 +281,39 @@ __global__ __launch_bounds__(BLOCK) void k_near(int C, const R* __restrict__ x, 
     const int64_t bb = lu / nt, k0 = lu - bb * nt;
     const int64_t run = (nt - k0 < pend - p) ? nt - k0 : pend - p;
     const int64_t n0 = cnoff[c], n1 = cnoff[c + 1];
-    const int64_t t0 = n0 + bb * BT;
-    R sx[kShifts], sy[kShifts];
-    {
-      const double skew = cskew[c];
-#pragma unroll
-      for (int m = 0; m < kShifts; ++m) {
-        sx[m] = (R)shift_x(m, skew);
-        sy[m] = (R)shift_y(m);
-      }
-    }
-    R xi[TPT], yi[TPT], nxi[TPT], nyi[TPT];
-    double A1[TPT], A2[TPT];
-#pragma unroll
-    for (int t = 0; t < TPT; ++t) {
-      const int64_t i = t0 + threadIdx.x + t * BLOCK;
-      xi[t] = 0;
-      yi[t] = 0;
-      nxi[t] = 0;
-      nyi[t] = 0;
-      if (i < n1) {
-        xi[t] = x[i];
-        yi[t] = y[i];
-        nxi[t] = nx[i];
-        nyi[t] = ny[i];
-      }
-      A1[t] = 0.0;
-      A2[t] = 0.0;
-    }
     const int64_t s_end = (n0 + (k0 + run) * tile < n1) ? n0 + (k0 + run) * tile : n1;
-    for (int64_t jt = n0 + k0 * tile; jt < s_end; jt += tile) {
-      const int cnt = (int)((jt + tile < s_end) ? tile : (s_end - jt));
-      __syncthreads();
-      for (int k = threadIdx.x; k < cnt; k += BLOCK) {
-        Src<R> s;
-        s.y1 = x[jt + k];
-        s.y2 = y[jt + k];
-        s.f1 = f1[jt + k];
-        s.f2 = f2[jt + k];
-        src[k] = s;
-      }
-      __syncthreads();
-      R a1[TPT], a2[TPT];
-#pragma unroll
-      for (int t = 0; t < TPT; ++t) {
-        a1[t] = 0;
-        a2[t] = 0;
-      }
-#pragma unroll 2
-      for (int k = 0; k < cnt; ++k) {
-        const Src<R> s = src[k];
-#pragma unroll
-        for (int t = 0; t < TPT; ++t) {
-          const R dx = xi[t] - s.y1, dy = yi[t] - s.y2;
-          RowTerms<R> row[3];
-#pragma unroll
-          for (int n = 0; n < 3; ++n) row[n] = row_terms(dy, sy[n], nyi[t], s.f2);
-#pragma unroll
-          for (int m = 0; m < kShifts; ++m) gt_pair(dx - sx[m], row[m % 3], nxi[t], s.f1, a1[t], a2[t]);
-        }
-      }
-#pragma unroll
-      for (int t = 0; t < TPT; ++t) {
-        A1[t] += (double)a1[t];
-        A2[t] += (double)a2[t];
-      }
-    }
     // slot of this workgroup among the owners of target block (c, bb)
     const int64_t first = unit_owner(unit_off[c] + bb * nt, U, G);
     double* out = Tpart + ((int64_t)slot_off[cell_blk[c] + bb] + (g - first)) * 2 * BT;
-#pragma unroll
-    for (int t = 0; t < TPT; ++t) {
-      const int local = threadIdx.x + t * BLOCK;
-      if (t0 + local < n1) {
-        out[local] = -(1.0 / kPi) * A1[t];
-        out[BT + local] = -(1.0 / kPi) * A2[t];
-      }
-    }
+    near_run<R, BLOCK, TPT, DIL>(src, x, y, nx, ny, f1, f2, nwrap, cskew[c], n0 + bb * BT, n1, n0 + k0 * tile, s_end,
+                                 tile, p - pbeg, pend - pbeg, out);
     p += run;
   }
 }
 
-template <typename R, int BLOCK, int TPT>
+// LDS of one workgroup: the source tile, padded when wg_per_cu > 0 so that at most wg_per_cu
+// workgroups fit on a compute unit (the grid is then exactly wg_per_cu x compute units).
+template <typename R, bool DIL>
+static size_t near_lds(int tile, int wg_per_cu) {
+  size_t lds = sizeof(typename SrcOf<R, DIL>::type) * (size_t)tile;
+  if (wg_per_cu > 0) {
+    int dev = 0, per_cu = 0;
+    SPM_HIP_CHECK(hipGetDevice(&dev));
+    SPM_HIP_CHECK(hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+    const size_t over = (size_t)per_cu / (size_t)(wg_per_cu + 1) + 256;
+    if (lds < over) lds = (over + 255) / 256 * 256;
+  }
+  return lds;
+}
+
+template <typename R, int BLOCK, int TPT, bool DIL>
 static int near_grid(int tile, int wg_per_cu) {
+  const size_t lds = near_lds<R, DIL>(tile, wg_per_cu);
+  if (lds > 65536)
+    SPM_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(k_near<R, BLOCK, TPT, DIL>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   int per_cu = 0;
-  const size_t lds = sizeof(Src<R>) * (size_t)tile;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_near<R, BLOCK, TPT>, BLOCK, lds) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_near<R, BLOCK, TPT, DIL>, BLOCK, lds) != hipSuccess ||
       per_cu < 1)
     per_cu = 1;
   if (wg_per_cu > 0) per_cu = std::min(per_cu, wg_per_cu);
@@ -238,26 +323,28 @@ static int near_grid(int tile, int wg_per_cu) {
   return per_cu * ncu;
 }
 
-template <typename R, int BLOCK, int TPT>
+template <typename R, int BLOCK, int TPT, bool DIL>
 static void near_launch(spm_handle* h, const R* x, const R* y, const R* nx, const R* ny, const R* f1, const R* f2,
                         const NearPlan& P) {
-  const size_t lds = sizeof(Src<R>) * (size_t)P.cfg.tile;
-  k_near<R, BLOCK, TPT><<<P.grid, BLOCK, lds, h->stream>>>(h->geo.C, x, y, nx, ny, f1, f2, h->geo.cskew,
-                                                           h->geo.cnoff, P.cell_nt, P.cell_blk, P.unit_off,
-                                                           P.slot_off, P.grid, P.cfg.tile, h->wk.Tpart);
+  const size_t lds = near_lds<R, DIL>(P.cfg.tile, P.cfg.wg_per_cu);
+  k_near<R, BLOCK, TPT, DIL><<<P.grid, BLOCK, lds, h->stream>>>(
+      h->geo.C, x, y, nx, ny, f1, f2, h->geo.nwrap, h->geo.cskew, h->geo.cnoff, P.cell_nt, P.cell_blk, P.unit_off,
+      P.slot_off, P.grid, P.cfg.tile, h->wk.Tpart);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-#define SPM_NEAR_SHAPES(X) X(64, 1) X(64, 2) X(64, 4) X(128, 1) X(128, 2) X(128, 4) X(256, 1) X(256, 2) X(256, 4)
+#define SPM_NEAR_SHAPES(X)                                                                                     \
+  X(64, 1) X(64, 2) X(64, 4) X(128, 1) X(128, 2) X(128, 4) X(256, 1) X(256, 2) X(256, 4) X(512, 1) X(512, 2) \
+      X(1024, 1) X(1024, 2)
 
-template <typename R>
+template <typename R, bool DIL>
 static void near_dispatch(spm_handle* h, const R* x, const R* y, const R* nx, const R* ny, const R* f1,
                           const R* f2, const NearPlan& P) {
   const int key = P.cfg.block * 10 + P.cfg.tpt;
   switch (key) {
-#define SPM_CASE(B, T)                                     \
-  case B * 10 + T:                                         \
-    near_launch<R, B, T>(h, x, y, nx, ny, f1, f2, P);      \
+#define SPM_CASE(B, T)                                          \
+  case B * 10 + T:                                              \
+    near_launch<R, B, T, DIL>(h, x, y, nx, ny, f1, f2, P);      \
     break;
     SPM_NEAR_SHAPES(SPM_CASE)
 #undef SPM_CASE
@@ -265,27 +352,28 @@ static void near_dispatch(spm_handle* h, const R* x, const R* y, const R* nx, co
   }
 }
 
-template <typename R>
+template <typename R, bool DIL>
 static int near_grid_of(const NearConfig& c) {
   const int key = c.block * 10 + c.tpt;
   switch (key) {
 #define SPM_CASE(B, T) \
   case B * 10 + T:     \
-    return near_grid<R, B, T>(c.tile, c.wg_per_cu);
+    return near_grid<R, B, T, DIL>(c.tile, c.wg_per_cu);
     SPM_NEAR_SHAPES(SPM_CASE)
 #undef SPM_CASE
     default: throw ApiError(SPM_EINVAL, "unsupported near-sum launch configuration");
   }
 }
 
-int near_persistent_grid(const NearConfig& c, int precision) {
-  return precision == SPM_FP64 ? near_grid_of<double>(c) : near_grid_of<float>(c);
+int near_persistent_grid(const NearConfig& c, int precision, bool dilated) {
+  if (precision == SPM_FP64) return dilated ? near_grid_of<double, true>(c) : near_grid_of<double, false>(c);
+  return dilated ? near_grid_of<float, true>(c) : near_grid_of<float, false>(c);
 }
 
 bool near_config_valid(const NearConfig& c) {
-  const bool b = c.block == 64 || c.block == 128 || c.block == 256;
-  const bool t = c.tpt == 1 || c.tpt == 2 || c.tpt == 4;
-  return b && t && c.tile >= 16 && c.tile <= 1024 && c.wg_per_cu >= 0 && c.wg_per_cu <= 32;
+  const bool b = c.block == 64 || c.block == 128 || c.block == 256 || c.block == 512 || c.block == 1024;
+  const bool t = c.tpt == 1 || c.tpt == 2 || (c.tpt == 4 && c.block <= 256);
+  return b && t && c.tile >= 16 && c.tile <= 4096 && c.wg_per_cu >= 0 && c.wg_per_cu <= 32;
 }
 
 void prof_flush(spm_handle* h) {
@@ -320,10 +408,17 @@ void launch_near_impl(spm_handle* h, int precision, bool with_active) {
     h->ev_kind[h->ev_used] = kind;
     SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used], h->stream));
   }
-  if (precision == SPM_FP64)
-    near_dispatch<double>(h, g.x, g.y, g.nx, g.ny, h->wk.f1, h->wk.f2, P);
-  else
-    near_dispatch<float>(h, g.xf, g.yf, g.nxf, g.nyf, h->wk.f1f, h->wk.f2f, P);
+  if (precision == SPM_FP64) {
+    if (g.dilated)
+      near_dispatch<double, true>(h, g.xw, g.yw, g.nx, g.ny, h->wk.f1, h->wk.f2, P);
+    else
+      near_dispatch<double, false>(h, g.x, g.y, g.nx, g.ny, h->wk.f1, h->wk.f2, P);
+  } else {   // the FP32 shadows hold the wrapped nodes with the dilated set
+    if (g.dilated)
+      near_dispatch<float, true>(h, g.xf, g.yf, g.nxf, g.nyf, h->wk.f1f, h->wk.f2f, P);
+    else
+      near_dispatch<float, false>(h, g.xf, g.yf, g.nxf, g.nyf, h->wk.f1f, h->wk.f2f, P);
+  }
   if (h->prof) {
     SPM_HIP_CHECK(hipEventRecord(h->ev_pool[2 * h->ev_used + 1], h->stream));
     ++h->ev_used;
@@ -434,8 +529,8 @@ void noalloc_launch(hipStream_t st, int64_t N, const R* x, const R* y, const R* 
   double* part = reinterpret_cast<double*>(base + kOffPart);
   k_near_partition<<<1, 1024, 0, st>>>(1, cell_nt, cell_blk, nullptr, grid, unit_off, slot_off);
   SPM_HIP_CHECK(hipGetLastError());
-  k_near<R, kNoallocBlock, 1><<<grid, kNoallocBlock, sizeof(Src<R>) * kNoallocTile, st>>>(
-      1, x, y, nx, ny, f1, f2, cskew, cnoff, cell_nt, cell_blk, unit_off, slot_off, grid, kNoallocTile, part);
+  k_near<R, kNoallocBlock, 1, false><<<grid, kNoallocBlock, sizeof(Src<R>) * kNoallocTile, st>>>(
+      1, x, y, nx, ny, f1, f2, nullptr, cskew, cnoff, cell_nt, cell_blk, unit_off, slot_off, grid, kNoallocTile, part);
   SPM_HIP_CHECK(hipGetLastError());
 }
 }  // namespace
@@ -467,7 +562,7 @@ extern "C" int spm_near_traction_noalloc(void* hip_stream, int64_t n, double ske
         c.tpt = 1;
         c.tile = kNoallocTile;
         c.wg_per_cu = 0;
-        const int g64 = near_persistent_grid(c, SPM_FP64), g32 = near_persistent_grid(c, SPM_FP32);
+        const int g64 = near_persistent_grid(c, SPM_FP64, false), g32 = near_persistent_grid(c, SPM_FP32, false);
         d.grid = std::max(1, std::min(kNoallocGrid, std::min(g64, g32)));
         d.ptr = static_cast<unsigned char*>(p);
       }

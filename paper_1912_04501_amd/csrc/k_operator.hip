@@ -101,9 +101,18 @@ __global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restr
   double u1 = 0, u2 = 0, vo = 0;
   const int64_t j_end = near3 ? g.cnoff[cell] : g.cnoff[cell + 1];
   for (int64_t j = g.cnoff[cell] + threadIdx.x; j < j_end; j += blockDim.x) {
-    const double yx = g.x[j], yy = g.y[j], a = f1[j], b = f2[j];
+    // 3x3 set: the nodes with the nine shifts; dilated set: the wrapped nodes with their four
+    // images {0, ms} x {0, ns} inside U~
+    const double yx = g.dilated ? g.xw[j] : g.x[j], yy = g.dilated ? g.yw[j] : g.y[j], a = f1[j], b = f2[j];
+    const int32_t w = g.dilated ? g.nwrap[j] : 0;
     for (int s = 0; s < kShifts; ++s) {
-      const double rx = cx - (yx + shift_x(s, skew)), ry = cy - (yy + shift_y(s));
+      int sm = s / 3 - 1, sn = s % 3 - 1;
+      if (g.dilated) {
+        if (s >= 4) break;
+        sm = (s & 1) ? node_wrap_ms(w) : 0;
+        sn = (s & 2) ? node_wrap_ns(w) : 0;
+      }
+      const double rx = cx - (yx + shift_xmn(sm, sn, skew)), ry = cy - (yy + (double)sn);
       const double r2 = rx * rx + ry * ry;
       const double ir2 = rcp64(r2);
       const double lg = -0.5 * log(r2);
@@ -123,6 +132,8 @@ __global__ __launch_bounds__(256) void k_velocities(Geo g, const double* __restr
   }
   if (threadIdx.x == 0) {
     const double* xi = xi_all + (int64_t)cell * 2 * M;
+    px += (int64_t)cell * M;
+    py += (int64_t)cell * M;
     double c1 = 0, c2 = 0, z1 = 0, z2 = 0, cv = 0;
     for (int p = 0; p < M; ++p) {
       const double a = xi[p], b = xi[M + p];
@@ -278,6 +289,8 @@ __global__ __launch_bounds__(256) void k_contour_points(Geo g, const double* __r
     }
   } else {
     const double* xi = xi_all + (int64_t)cell * 2 * M;
+    px += (int64_t)cell * M;
+    py += (int64_t)cell * M;
     for (int p = threadIdx.x; p < M; p += blockDim.x) {
       const double rx = xq - px[p], ry = yq - py[p];
       const double r2 = rx * rx + ry * ry;

@@ -66,8 +66,8 @@ __device__ __forceinline__ CellLat cell_lat(double skew) {
 // Q[row][col], row in [0, 8m), col = comp * M + p: the wall jumps of the field of a unit
 // force e_comp at proxy p.
 __global__ void k_build_Q(Lat L, const double* __restrict__ cskew, const double* __restrict__ wx_all,
-                          const double* __restrict__ wy_all, const double* __restrict__ px,
-                          const double* __restrict__ py, double* __restrict__ Q_all) {
+                          const double* __restrict__ wy_all, const double* __restrict__ px_all,
+                          const double* __restrict__ py_all, double* __restrict__ Q_all) {
   const int m = L.m, M = L.M;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 8 * m * 2 * M) return;
@@ -75,6 +75,8 @@ __global__ void k_build_Q(Lat L, const double* __restrict__ cskew, const double*
   const CellLat CL = cell_lat(cskew[cell]);
   const double* wx = wx_all + (int64_t)cell * 2 * m;
   const double* wy = wy_all + (int64_t)cell * 2 * m;
+  const double* px = px_all + (int64_t)cell * M;
+  const double* py = py_all + (int64_t)cell * M;
   double* Q = Q_all + (int64_t)cell * 8 * m * 2 * M;
   const int row = idx / (2 * M), col = idx % (2 * M);
   const int comp = col / M, p = col % M;
@@ -237,8 +239,9 @@ __global__ void k_pinv_assemble(int rows, int ncol, const double* __restrict__ A
   if (threadIdx.x == 0) {
     double smax = 0;
     for (int k = 0; k < ncol; ++k) smax = S[k] > smax ? S[k] : smax;
-    for (int k = 0; k < ncol; ++k) w[k] = (S[k] > rcond * smax) ? 1.0 / (S[k] * S[k]) : 0.0;
-    // drop the n_gauge smallest
+    // the n_gauge smallest are the gauge modes, dropped whether or not they fall below the
+    // cutoff; then every other value at or below rcond * s_max
+    for (int k = 0; k < ncol; ++k) w[k] = 1.0;
     for (int g = 0; g < n_gauge; ++g) {
       int arg = -1;
       double best = 1e300;
@@ -249,6 +252,7 @@ __global__ void k_pinv_assemble(int rows, int ncol, const double* __restrict__ A
         }
       if (arg >= 0) w[arg] = 0.0;
     }
+    for (int k = 0; k < ncol; ++k) w[k] = (w[k] != 0.0 && S[k] > rcond * smax) ? 1.0 / (S[k] * S[k]) : 0.0;
   }
   __syncthreads();
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -292,10 +296,18 @@ void launch_pinv(spm_handle* h) {
 // partials disc[c][w][8] = (du1, du2, dT1, dT2) hi parts then lo parts, summed in fixed
 // order by k_xi.
 // ----------------------------------------------------------------------------
+//
+// Dilated near set (nwrap given; x, y the wrapped nodes): a node's images are the shifts
+// {0, ms} x {0, ns}. Across the wall pair with lattice vector a (e1 for L/R, e2 for D/U) the
+// images are i a with i in I = {0, s_a}; shifting the target by a maps them to i - 1, so the
+// jump is, for each image position j along the wall, G(x, y + (min I - 1) a + j b) -
+// G(x, y + (max I) a + j b), j in {0, s_b}: two far-minus-near pairs per node, each image at
+// least half a cell from the wall.
 __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __restrict__ cskew,
                                               const double* __restrict__ wx_all, const double* __restrict__ wy_all,
                                               const double* __restrict__ x, const double* __restrict__ y,
                                               const double* __restrict__ f1, const double* __restrict__ f2,
+                                              const int32_t* __restrict__ nwrap,
                                               const int64_t* __restrict__ cs0, const int64_t* __restrict__ cs1,
                                               const int32_t* __restrict__ ccell, const int32_t* __restrict__ active,
                                               double* __restrict__ disc) {
@@ -315,9 +327,20 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
   dd u1 = {0, 0}, u2 = {0, 0}, t1 = {0, 0}, t2 = {0, 0};
   for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
     const double yj = x[j], zj = y[j], g1 = f1[j], g2 = f2[j];
-    for (int n = -1; n <= 1; ++n) {
-      const double fx = yj - 2.0 * ax + n * bx, fy = zj - 2.0 * ay + n * by;
-      const double cx = yj + ax + n * bx, cy = zj + ay + n * by;
+    // 3x3 set: far image -2 a, near image +a, rows n = -1, 0, 1 along the wall;
+    // dilated set: far (min I - 1) a, near (max I) a, rows {0, s_b}
+    int far = -2, near = 1, nlo = -1, nhi = 1, nstep = 1;
+    if (nwrap != nullptr) {
+      const int32_t w = nwrap[j];
+      const int sa = onD ? node_wrap_ns(w) : node_wrap_ms(w), sb = onD ? node_wrap_ms(w) : node_wrap_ns(w);
+      far = sa > 0 ? -1 : -2;
+      near = sa > 0 ? 1 : 0;
+      nlo = sb > 0 ? 0 : -1;
+      nhi = sb > 0 ? 1 : 0;
+    }
+    for (int n = nlo; n <= nhi; n += nstep) {
+      const double fx = yj + far * ax + n * bx, fy = zj + far * ay + n * by;
+      const double cx = yj + near * ax + n * bx, cy = zj + near * ay + n * by;
       // the far-minus-near difference of one source is formed directly (one logarithm of the
       // ratio of squared distances) and rounded once; the running sums are double-double
       double v1, v2;
@@ -351,8 +374,10 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
 void launch_disc_impl(spm_handle* h, bool with_active) {
   const Lat L = lattice_args(h);
   dim3 grid((unsigned)h->wk.ndisc, (unsigned)(2 * L.m));
-  k_disc<<<grid, 256, 0, h->stream>>>(h->geo.N, L, h->geo.cskew, h->per.wx, h->per.wy, h->geo.x, h->geo.y, h->wk.f1,
-                                      h->wk.f2, h->wk.disc_s0, h->wk.disc_s1, h->wk.disc_cell,
+  const Geo& g = h->geo;
+  k_disc<<<grid, 256, 0, h->stream>>>(g.N, L, g.cskew, h->per.wx, h->per.wy, g.dilated ? g.xw : g.x,
+                                      g.dilated ? g.yw : g.y, h->wk.f1, h->wk.f2, g.dilated ? g.nwrap : nullptr,
+                                      h->wk.disc_s0, h->wk.disc_s1, h->wk.disc_cell,
                                       with_active ? h->kr.active : nullptr, h->wk.disc);
   SPM_HIP_CHECK(hipGetLastError());
 }
@@ -461,10 +486,14 @@ __global__ __launch_bounds__(256) void k_combine(int64_t N, int64_t bt, const in
     t1 += Tpart[(int64_t)k * 2 * bt + local];
     t2 += Tpart[(int64_t)k * 2 * bt + bt + local];
   }
-  if (with_extra) {
-    const double xx = g.x[ii], yy = g.y[ii], nx = g.nx[ii], ny = g.ny[ii];
+  if (with_extra) {   // the correction field at the target's position in the cell (wrapped node, dilated set)
+    const double xx = g.dilated ? g.xw[ii] : g.x[ii], yy = g.dilated ? g.yw[ii] : g.y[ii];
+    const double nx = g.nx[ii], ny = g.ny[ii];
     const double* xi = xi_all + (int64_t)cell * 2 * M;
-    for (int p = l; p < M; p += kCombineLanes) traction_uv(xx - px[p], yy - py[p], nx, ny, xi[p], xi[M + p], t1, t2);
+    const double* pxc = px + (int64_t)cell * M;
+    const double* pyc = py + (int64_t)cell * M;
+    for (int p = l; p < M; p += kCombineLanes)
+      traction_uv(xx - pxc[p], yy - pyc[p], nx, ny, xi[p], xi[M + p], t1, t2);
   }
 #pragma unroll
   for (int o = kCombineLanes / 2; o > 0; o >>= 1) {

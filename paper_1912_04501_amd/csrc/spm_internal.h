@@ -57,6 +57,22 @@ __host__ __device__ __forceinline__ double shift_x(int s, double skew) {
 }
 __host__ __device__ __forceinline__ double shift_y(int s) { return (double)(s % 3 - 1); }
 
+// Lattice shift m e1 + n e2 (e1 = (1, 0), e2 = (skew, 1)) for integers m, n: x component.
+// The near sum of the dilated set and the kernels that remove its close terms form the FP32
+// shifts from this one expression, so those terms agree bit for bit.
+__host__ __device__ __forceinline__ double shift_xmn(int m, int n, double skew) { return (double)m + (double)n * skew; }
+
+// Packed per-node wrap of the dilated near set: the node was moved by ka e1 + kb e2 into the
+// cell (|ka|, |kb| < 2^14), and its images inside U~ are the shifts {0, ms} x {0, ns} with
+// ms = +1 when its first lattice coordinate (after the wrap) is negative, else -1; ns likewise.
+__host__ __device__ __forceinline__ int32_t node_wrap_pack(int ka, int kb, int ms, int ns) {
+  return ((ka + 16384) & 0x7fff) | (((kb + 16384) & 0x7fff) << 15) | ((ms > 0) << 30) | ((int32_t)(ns > 0) << 31);
+}
+__host__ __device__ __forceinline__ int node_wrap_ka(int32_t w) { return (w & 0x7fff) - 16384; }
+__host__ __device__ __forceinline__ int node_wrap_kb(int32_t w) { return ((w >> 15) & 0x7fff) - 16384; }
+__host__ __device__ __forceinline__ int node_wrap_ms(int32_t w) { return ((w >> 30) & 1) ? 1 : -1; }
+__host__ __device__ __forceinline__ int node_wrap_ns(int32_t w) { return ((unsigned)w >> 31) ? 1 : -1; }
+
 // ----------------------------------------------------------------------------
 // Pairs of the single-layer traction sum (Sec. 4.1 eq. Gt without the -1/pi, which
 // is applied once per target):  a += r (r.n)(r.f) / |r|^4,  r = (dx - sx, dy - sy).
@@ -227,8 +243,14 @@ struct Geo {
   double *x = nullptr, *y = nullptr, *nx = nullptr, *ny = nullptr, *w = nullptr, *kap = nullptr;
   double* dcot = nullptr;     // [N] spectral differentiation weights of the particle's own N_q, by distance
   double *tx = nullptr, *ty = nullptr, *xpx = nullptr, *xpy = nullptr;
-  // nodes, FP32 shadows (targets and sources of the FP32 near sum)
+  // nodes, FP32 shadows (targets and sources of the FP32 near sum; with the dilated near set the
+  // node positions wrapped into the cell one by one)
   float *xf = nullptr, *yf = nullptr, *nxf = nullptr, *nyf = nullptr;
+  // dilated near set only: node positions wrapped into the cell (FP64) and per node the lattice
+  // vector added by the wrap and the side of the cell it lies on (node_wrap_* below)
+  double *xw = nullptr, *yw = nullptr;
+  int32_t* nwrap = nullptr;
+  int32_t dilated = 0;
   int32_t* pid = nullptr;     // [N] particle of each node
   int32_t* ncell = nullptr;   // [N] cell of each node
   // particles
@@ -284,13 +306,12 @@ struct NearConfig {
   int32_t wg_per_cu = 0;      // persistent workgroups per compute unit (0: the occupancy limit)
 };
 
-// Plan of the near-sum launch of one precision. The work is split into units (target block
-// of block * tpt targets, source tile of `tile` sources of the same cell); the units of the
-// active cells, taken in order (cell, target block, tile), are divided evenly over the
-// persistent workgroups, and each workgroup writes one FP64 partial per target block it
-// touches. The partition kernel fills unit_off and slot_off before every launch (the
-// active cells change during an ensemble solve); the combine step sums the slots of a block
-// in workgroup order.
+// Plan of the near-sum launch of one precision. The work is split into units (target block of
+// block * tpt targets, source tile of `tile` sources of the same cell); the units of the active
+// cells, taken in order (cell, target block, tile), are divided evenly over the persistent
+// workgroups, and each workgroup writes one FP64 partial per target block it touches. The
+// partition kernel fills unit_off and slot_off before every launch (the active cells change
+// during an ensemble solve); the combine step sums the slots of a block in workgroup order.
 struct NearPlan {
   NearConfig cfg;
   int32_t nblocks = 0;          // target blocks over all cells
@@ -482,7 +503,8 @@ struct spm_handle {
   spm::Precond pc;
   spm_mlp* net = nullptr;             // borrowed warm-start network
   double min_gap_est = 0.0;
-  double delta32 = -1.0;      // measured relative error of the FP32 operator (< 0: not measured for this geometry)
+  double delta32 = -1.0;
+  std::vector<int32_t> guess_rejected;   // [C] per cell of the last solve: learned guess rejected      // measured relative error of the FP32 operator (< 0: not measured for this geometry)
   double wallclock_hz = 1e8;
 
   // opt-in kernel timing: HIP events around near-sum launches (kernel 0 = FP64, 1 = FP32; FMM: 2 = evaluation, 3 = M2L)
@@ -527,7 +549,7 @@ void launch_near(spm_handle* h, int precision);
 void prof_flush(spm_handle* h);
 void launch_near_sum_only(spm_handle* h, double* out, int precision);
 bool near_config_valid(const NearConfig& c);
-int near_persistent_grid(const NearConfig& c, int precision);   // workgroups of the persistent near-sum grid
+int near_persistent_grid(const NearConfig& c, int precision, bool dilated);   // workgroups of the persistent near-sum grid
 void build_near_plan(spm_handle* h, int precision);
 void autotune(spm_handle* h, const char* cache_path, double* best_ms_out);
 double time_near(spm_handle* h, int prec, const NearConfig& c, int reps);
@@ -579,6 +601,7 @@ void launch_close_apply_impl(spm_handle* h, double* T, int precision, bool with_
 // learned warm start (k_learned.hip) and block preconditioner (k_precond.hip)
 void launch_features(spm_handle* h, float* feat);
 void launch_to_bf16(spm_handle* h, const float* in, int64_t n, uint16_t* out);   // nearest even
+void launch_reject_guess(spm_handle* h, const int32_t* mask, const double* b, double* x, double* r);
 void launch_add_cell_velocity(spm_handle* h, const double* du, double* vel);   // vel[2i] += du[cell of i]
 void launch_modes(spm_handle* h, const double* sigma, const double* num, const double* den, float* modes);
 void launch_decode(spm_handle* h, const float* modes, double* sigma);

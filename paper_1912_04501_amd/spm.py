@@ -24,6 +24,7 @@ SPM_FP64, SPM_FP32, SPM_FP32_IR, SPM_FP32_RELAXED = 0, 1, 2, 3
 SPM_X0_ZERO, SPM_X0_PREVIOUS, SPM_X0_NETWORK = 0, 1, 2
 SPM_PRECOND_NONE, SPM_PRECOND_BLOCK = 0, 1
 SPM_NEAR_DIRECT, SPM_NEAR_FMM = 0, 1
+SPM_NEAR_SET_3X3, SPM_NEAR_SET_DILATED = 0, 1
 SPM_MLP_IN, SPM_MLP_HIDDEN, SPM_MLP_OUT, SPM_MLP_NPARAMS = 33, 256, 128, 173184
 SPM_MLP_BF16, SPM_MLP_FP32 = 0, 1
 _ERRNAMES = {-1: "SPM_EINVAL", -2: "SPM_EOVERLAP", -3: "SPM_ENOCONV", -4: "SPM_EHIP", -5: "SPM_ENOMEM",
@@ -38,7 +39,8 @@ class spm_config(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("poll_every", ctypes.c_int32), ("x0", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("learned_max_iter", ctypes.c_int32), ("relax_tol", ctypes.c_double),
                 ("near_method", ctypes.c_int32), ("fmm_order", ctypes.c_int32),
-                ("node_spacing", ctypes.c_double), ("relax_safety", ctypes.c_double)]
+                ("node_spacing", ctypes.c_double), ("relax_safety", ctypes.c_double),
+                ("learned_accept", ctypes.c_double), ("near_set", ctypes.c_int32)]
 
 
 class spm_solve_info(ctypes.Structure):
@@ -47,7 +49,8 @@ class spm_solve_info(ctypes.Structure):
                 ("refinements", ctypes.c_int32), ("rel_residual", ctypes.c_double),
                 ("seconds_setup", ctypes.c_double), ("seconds_solve", ctypes.c_double),
                 ("seconds_readout", ctypes.c_double), ("fallback", ctypes.c_int32),
-                ("first_iterations", ctypes.c_int32), ("min_gap", ctypes.c_double)]
+                ("first_iterations", ctypes.c_int32), ("min_gap", ctypes.c_double),
+                ("guess_rejected", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -294,11 +294,18 @@ def test_step_record():
 def test_trained_network_gain():
     """Train the network on the solver's own trajectories (two 10-20 ellipse cells,
     20 steps each) with the device kernels, then on a held-out cell compare the method
-    with and without it: the trained network's warm start must leave a smaller initial
-    residual than the untrained network's, and neither may exceed the zero start's (the
-    fitted guess contains it); the iteration counts of the solves started from each are
-    reported (in this operator a nearby initial guess does not shorten GMRES: the
-    right-hand side itself is a favourable starting vector)."""
+    with and without it, at the same FP64 residual 1e-10.
+
+    What the network gains is measured, not assumed. Its fitted warm start never leaves a
+    larger residual than the zero start (the fit contains zero), and training lowers it
+    below the untrained network's. Started from that guess, GMRES nevertheless needs more
+    iterations than from zero (in this operator GMRES from the right-hand side itself
+    converges superlinearly, and a loose guess puts every slowly converging error component
+    into the starting residual), so plain GMRES judges the guess: a cell whose fitted guess
+    leaves more than learned_accept (0.5) of the zero start's residual starts from zero. The
+    test asserts that the judged learned solve takes no more iterations than the zero start,
+    and records what the unjudged one costs."""
+    import time
     spm = _spm()
     from paper_1912_04501_amd import learned as L
     X, T, solves = L.generate([7100, 7101], 20, lo=10, hi=20)
@@ -314,8 +321,10 @@ def test_trained_network_gain():
     assert final < 0.6 * data_ms
     wl = W.trajectory_cell(7200, lo=10, hi=20)
     out = {}
-    for name, n in [("zero", None), ("untrained", untrained), ("trained", net)]:
-        s = spm.Solver("cuda:0", x0=spm.SPM_X0_ZERO if n is None else spm.SPM_X0_NETWORK).set_workload(wl)
+    for name, n, accept in [("zero", None, 0.5), ("untrained", untrained, 1e9), ("trained", net, 1e9),
+                            ("trained_judged", net, 0.5)]:
+        s = spm.Solver("cuda:0", x0=spm.SPM_X0_ZERO if n is None else spm.SPM_X0_NETWORK,
+                       learned_accept=accept).set_workload(wl)
         b = s.rhs()
         if n is not None:
             s.set_network(n)
@@ -323,11 +332,22 @@ def test_trained_network_gain():
             r0 = float(torch.linalg.norm(b - s.apply(x0)) / torch.linalg.norm(b))
         else:
             r0 = 1.0
+        s.solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         r = s.solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
         assert r["info"]["rel_residual"] <= 1e-10
-        out[name] = (r0, r["info"]["iterations"])
-        print(f"[gain] {name:9s} initial residual {r0:.3e}  GMRES iterations {r['info']['iterations']}")
+        out[name] = (r0, r["info"]["iterations"], dt, r["info"]["guess_rejected"])
+        print(f"[gain] {name:14s} initial residual {r0:.3e}  GMRES iterations {r['info']['iterations']}  "
+              f"solve {1e3 * dt:.1f} ms  guess rejected {r['info']['guess_rejected']}")
     assert out["trained"][0] < out["untrained"][0] <= 1.0 + 1e-9
+    print(f"[gain] unjudged trained network vs zero start: iterations x{out['trained'][1] / out['zero'][1]:.2f}, "
+          f"time x{out['trained'][2] / out['zero'][2]:.2f}")
+    judged = out["trained_judged"]
+    assert judged[1] <= out["zero"][1]
+    assert judged[3] == (1 if out["trained"][0] > 0.5 else 0)
 
 
 def test_trajectory_cell_full_size_steps():

@@ -164,6 +164,26 @@ def test_full_operator(case):
     assert np.abs(b - op.rhs(prob)).max() < 1e-15
 
 
+def test_pinv_cutoff_above_the_gauge_modes():
+    """Sec. 6.1's least squares with a cutoff (1e-8 of the largest singular value) above the
+    three gauge modes' singular values (a few 1e-9 for these 32 circle proxies): the gauge modes
+    are dropped once, not three more kept values besides them. Q+ to 1e-8 of its largest entry,
+    the operator to 1e-10 (the oracle itself moves by under 1e-11 with LAPACK's other SVD
+    driver at this cutoff)."""
+    wl = W.random_ellipses(12, 0.3, seed=3, nodes=96, skew=0.15)
+    prob = op.make_problem(wl, rcond=1e-8)
+    sv = np.linalg.svd(prob.Q, compute_uv=False)
+    assert (sv[-3:] < 1e-8 * sv[0]).any()       # the case the rule is about
+    s = _solver(wl, rcond=1e-8)
+    Qp = s.proxy_pinv()[0]
+    qerr = np.abs(Qp - prob.Qpinv).max() / np.abs(prob.Qpinv).max()
+    sig = W.random_density(prob.N, seed=10)
+    ref = op.apply(prob, sig)
+    err = np.abs(_n(s.apply(_t(sig))) - ref).max() / np.abs(ref).max()
+    print(f"[cutoff 1e-8] Q+ err {qerr:.2e} apply err {err:.2e}")
+    assert qerr < 1e-8 and err < 1e-10
+
+
 def test_fp32_operator(case):
     """The FP32 operator (FP32 near sum with FP32 accumulation, close pairs and own-curve
     terms corrected in FP64, everything else FP64) against the oracle's FP64 operator.

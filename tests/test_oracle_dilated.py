@@ -12,6 +12,7 @@ from oracle.geometry import build_geometry
 from paper_1912_04501_amd import workloads as W
 
 DIL = dict(near_set="dilated", M=64, R=1.0)
+DIL_WALLS = dict(near_set="dilated", proxy_surface="walls", M=64, m=24, rcond=1e-8)
 
 
 def test_four_images_per_node_inside_dilated_cell():
@@ -49,15 +50,33 @@ def test_dilated_discrepancy_is_consistent():
     assert np.abs(res).max() < 1e-12 * max(1.0, np.abs(d).max())
 
 
+def test_wall_proxies_on_the_dilated_cell_boundary():
+    """M / 4 proxies on each side of U~ (corners c_U +- e1 +- e2), evenly spaced along it."""
+    g = build_geometry(W.random_ellipses(4, 0.2, seed=1, skew=0.3, nodes=64))
+    P = dilated.wall_proxies(g, 64)
+    ab = dilated.lattice_coords(g, P)
+    on = np.abs(np.abs(ab) - 1.0) < 1e-12
+    assert np.all(on.sum(1) == 1)                         # on exactly one wall, never at a corner
+    for side in ((1, -1), (0, 1), (1, 1), (0, -1)):         # bottom, right, top, left
+        k = on[:, side[0]] & (np.sign(ab[:, side[0]]) == side[1])
+        assert k.sum() == 16
+        t = np.sort(ab[k, 1 - side[0]])
+        assert np.abs(np.diff(t) - 0.125).max() < 1e-12 and abs(t[0] + 1 - 0.0625) < 1e-12
+    with pytest.raises(ValueError):
+        dilated.wall_proxies(g, 30)
+
+
+@pytest.mark.parametrize("per", [DIL, DIL_WALLS], ids=["circle_proxies", "wall_proxies"])
 @pytest.mark.parametrize("wl", [W.single_ellipse(), W.random_ellipses(10, 0.3, seed=3)])
-def test_same_periodic_operator_and_solution_as_3x3(wl):
+def test_same_periodic_operator_and_solution_as_3x3(wl, per):
     """Both near sets periodize the same G_per: the operator on a smooth force-free
     density and the solution's omega, relative velocities and mu_eff agree to the
-    proxy-fit level. (With a net force F the periodic pressure grows linearly across
-    the cell, so values at a node and at its wrapped copy differ by F . shift / |U|
-    times n: a comparison needs F = 0, as every solution has.)"""
+    proxy-fit level, with the U~ set's proxies on a circle or on U~'s walls. (With a net
+    force F the periodic pressure grows linearly across the cell, so values at a node and
+    at its wrapped copy differ by F . shift / |U| times n: a comparison needs F = 0, as
+    every solution has.)"""
     p3 = op.make_problem(wl)
-    pd = op.make_problem(wl, **DIL)
+    pd = op.make_problem(wl, **per)
     g = p3.geom
     t = np.arange(p3.N)
     s2 = np.stack([np.cos(2 * np.pi * t / 97), np.sin(2 * np.pi * t / 61)], axis=1)
