@@ -297,12 +297,20 @@ def main():
 
     extra = {}
     if not args.no_compare:
-        for name, p, pc, nm in (("fp64", spm.SPM_FP64, 0, 0), ("fp32_ir", spm.SPM_FP32_IR, 0, 0),
-                                ("fp32_relaxed", spm.SPM_FP32_RELAXED, 0, 0), ("fp64_precond", spm.SPM_FP64, 1, 0),
-                                ("fp32_ir_precond", spm.SPM_FP32_IR, 1, 0),
-                                ("fp32_relaxed_precond", spm.SPM_FP32_RELAXED, 1, 0),
-                                ("fmm_fp64_precond", spm.SPM_FP64, 1, spm.SPM_NEAR_FMM)):
-            c = spm.Solver("cuda:0", precision=p, precond=pc, near_method=nm)
+        # the paper's own near set (four images of every wrapped node, 4 N^2 pairs per matvec)
+        # with 64 proxies on the dilated cell's walls, at two pseudo-inverse cutoffs
+        dil = dict(near_set=spm.SPM_NEAR_SET_DILATED, M=64, m_wall=24)
+        for name, cfg in (("fp64", dict(precision=spm.SPM_FP64)), ("fp32_ir", dict(precision=spm.SPM_FP32_IR)),
+                          ("fp32_relaxed", dict(precision=spm.SPM_FP32_RELAXED)),
+                          ("fp64_precond", dict(precision=spm.SPM_FP64, precond=1)),
+                          ("fp32_ir_precond", dict(precision=spm.SPM_FP32_IR, precond=1)),
+                          ("fp32_relaxed_precond", dict(precision=spm.SPM_FP32_RELAXED, precond=1)),
+                          ("fmm_fp64_precond", dict(precision=spm.SPM_FP64, precond=1, near_method=spm.SPM_NEAR_FMM)),
+                          ("dilated_fp64_precond", dict(precision=spm.SPM_FP64, precond=1, rcond=1e-8, **dil)),
+                          ("dilated_fp32_ir_precond", dict(precision=spm.SPM_FP32_IR, precond=1, rcond=1e-8, **dil)),
+                          ("dilated_fp32_ir_precond_rcond1e-10",
+                           dict(precision=spm.SPM_FP32_IR, precond=1, rcond=1e-10, **dil))):
+            c = spm.Solver("cuda:0", **cfg)
             c.set_workload(wl)
             for pr, key in ((spm.SPM_FP64, "fp64"), (spm.SPM_FP32, "fp32")):
                 c.set_launch(pr, **tune[key])
@@ -315,6 +323,8 @@ def main():
             extra[f"solve_info_{name}"] = {k: rr["info"][k] for k in ("iterations", "fp64_matvecs", "fp32_matvecs",
                                                                        "refinements", "rel_residual")}
             extra[f"mu_eff_{name}"] = float(rr["mu_eff"].item())
+            if name.startswith("dilated"):
+                extra[f"pairs_per_matvec_{name}"] = 4.0 * N * N
             c.close()
         log(f"[bench] comparison {extra}")
 

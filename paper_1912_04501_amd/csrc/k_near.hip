@@ -210,11 +210,13 @@ __device__ __forceinline__ void near_run(typename SrcOf<R, DIL>::type* src, cons
 #pragma unroll
       for (int t = 0; t < TPT; ++t) {
         const R dx = xi[t] - s.y1, dy = yi[t] - s.y2;
+        // The unshifted image takes dx and dy as they are: its shift (R)shift_xmn(0, 0, skew) is
+        // +0 for every skew and x - (+0) == x bit for bit, so the kernels that remove close and
+        // own-curve terms with this arithmetic still match it exactly.
         if constexpr (DIL) {
-          const R zero = (R)shift_xmn(0, 0, skew);
-          const RowTerms<R> r0 = row_terms(dy, zero, nyi[t], s.f2);
+          const RowTerms<R> r0 = row_terms(dy, (R)0, nyi[t], s.f2);
           const RowTerms<R> rB = row_terms(dy, s.syB, nyi[t], s.f2);
-          gt_pair(dx - zero, r0, nxi[t], s.f1, a1[t], a2[t]);
+          gt_pair(dx, r0, nxi[t], s.f1, a1[t], a2[t]);
           gt_pair(dx - s.sxA, r0, nxi[t], s.f1, a1[t], a2[t]);
           gt_pair(dx - s.sxB, rB, nxi[t], s.f1, a1[t], a2[t]);
           gt_pair(dx - s.sxC, rB, nxi[t], s.f1, a1[t], a2[t]);
@@ -223,7 +225,8 @@ __device__ __forceinline__ void near_run(typename SrcOf<R, DIL>::type* src, cons
 #pragma unroll
           for (int n = 0; n < 3; ++n) row[n] = row_terms(dy, sy[n], nyi[t], s.f2);
 #pragma unroll
-          for (int m = 0; m < kShifts; ++m) gt_pair(dx - sx[m], row[m % 3], nxi[t], s.f1, a1[t], a2[t]);
+          for (int m = 0; m < kShifts; ++m)
+            gt_pair(m == kShifts / 2 ? dx : dx - sx[m], row[m % 3], nxi[t], s.f1, a1[t], a2[t]);
         }
       }
     }
