@@ -122,17 +122,28 @@ def cpu_model():
     return "unknown"
 
 
-def oracle_solve_times():
+def oracle_solve_times(with_c2=False):
     """The oracle's complete FP64 mobility solves (set-up + MGS GMRES to 1e-10 from zero) of
     the single ellipse (N = 128) and the 25-ellipse cell (N = 5,112), and the dense LU solve of
-    the single ellipse (the matrix assembled column by column from operator products)."""
+    the single ellipse (the matrix assembled column by column from operator products); with
+    with_c2 also the 200-ellipse cell (N = 51,200; minutes on the host's cores)."""
     from oracle import operator as op
     from paper_1912_04501_amd import workloads as W
     out = {}
-    for name, wl in (("single_ellipse_N128", W.single_ellipse()), ("ellipses25_N5112", W.ellipses_25())):
+    cases = [("single_ellipse_N128", W.single_ellipse()), ("ellipses25_N5112", W.ellipses_25())]
+    if with_c2:
+        cases.append(("ellipses200_N51200", W.ellipses_200()))
+    for name, wl in cases:
         t0 = time.perf_counter()
         prob = op.make_problem(wl)
-        x, info = op.solve(prob, tol=1e-10)
+        count = [0]
+
+        def product(v, prob=prob, count=count, name=name):
+            count[0] += 1
+            if count[0] % 10 == 0:
+                log(f"[bench] oracle solve {name}: {count[0]} operator products, {time.perf_counter() - t0:.0f}s")
+            return op.apply(prob, v)
+        x, info = op.gmres(product, op.rhs(prob), tol=1e-10)
         out[f"gmres_s_{name}"] = time.perf_counter() - t0
         out[f"gmres_its_{name}"] = info["iterations"]
         if name == "single_ellipse_N128":
@@ -175,6 +186,8 @@ def main():
                     help="ellipses200 and ensemble64: right block preconditioner (default: block)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the untimed FP64-vs-FP32+IR comparison solves")
+    ap.add_argument("--oracle-c2", action="store_true",
+                    help="cpu_baseline also times the oracle's whole solve of the 200-ellipse cell (minutes)")
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy three times (HBM counter calibration)")
@@ -332,7 +345,7 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample ...")
         cpu = cpu_baseline([wl])
-        cpu["solves"] = {**oracle_solve_times(), **gpu_small_solve_times()}
+        cpu["solves"] = {**oracle_solve_times(args.oracle_c2), **gpu_small_solve_times()}
         log(f"[bench] cpu baseline {cpu}")
 
     out = {"metric": "Stokes matvec pair-evals/s (whole mobility solve to 1e-10 FP64 residual)",

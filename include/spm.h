@@ -128,7 +128,7 @@ typedef struct {
                            given: N_i = clamp(8 ceil(P_i / (8 h)), 64, 256), P_i the perimeter
                            [2.170590708293102e-3: about 5,000 nodes for 25 ellipses of aspect
                            ratio 1.5-3 at area fraction 0.3] */
-  double relax_safety;  /* margin theta of the adaptive relaxed switch point, 0 < theta <= 1 [0.1] */
+  double relax_safety;  /* margin theta of the adaptive relaxed switch point, 0 < theta <= 1 [0.01] */
   double learned_accept;/* SPM_X0_NETWORK: a cell whose fitted network guess leaves a relative residual
                            above this starts from zero instead (GMRES judges the guess) [0.5] */
   int32_t near_set;     /* SPM_NEAR_SET_3X3 or SPM_NEAR_SET_DILATED [SPM_NEAR_SET_3X3]; with the dilated
@@ -291,7 +291,7 @@ int spm_proxy_strengths(spm_handle* h, const double* sigma, double* xi);
 /* For callers that cannot allocate device memory (code under HIP graph capture, serving loops
  * and harnesses that forbid hipMalloc): the near-image traction sum of spm_near_traction for
  * one cell given by its node arrays, with no handle and no allocation. Its forces, FP32 copies,
- * work plan and partial sums live in one file-scope device array of the library (about 11 MB
+ * work plan and partial sums live in one file-scope device array of the library (about 16 MB
  * per GPU, kept until the process ends; its address is looked up once per device on the
  * first call, with that device current). Every call on a GPU shares that array: calls that
  * overlap on one GPU (other streams or threads) race and must be serialised by the caller.

@@ -21,12 +21,17 @@ namespace spm {
 // Default near-sum launch shape: 256 threads, 256-source LDS tiles; FP64 with four targets
 // per lane (the FP64 pair is ALU-heavier, so reusing each staged source for more targets
 // pays), FP32 with one; as many persistent workgroups as fit on a compute unit.
+// Launch shape of the near sum before (or without) autotuning: one target per lane in blocks of
+// 64 against tiles of 128 sources in both precisions. Small blocks and tiles give many units
+// (target block, source tile) for the persistent grid to share out even at a few thousand nodes,
+// and at N = 51,200 this shape is within 1% of the autotuner's best in either precision.
 NearConfig heuristic_near(spm_handle* h, int precision) {
   (void)h;
+  (void)precision;
   NearConfig c;
-  c.block = 256;
-  c.tpt = precision == SPM_FP64 ? 4 : 1;
-  c.tile = 256;
+  c.block = 64;
+  c.tpt = 1;
+  c.tile = 128;
   c.wg_per_cu = 0;
   return c;
 }
@@ -875,7 +880,9 @@ double fp32_operator_error(spm_handle* h) {
 // about tol (the relaxation bound of inexact Krylov methods), so products may use the FP32 near
 // sum once the residual estimate is below theta tol / delta32, delta32 the measured relative
 // error of the FP32 operator and theta = cfg.relax_safety a margin for the conditioning of the
-// small Hessenberg problem; kept within [10 tol, 1e-2].
+// small Hessenberg problem; kept within [10 tol, 1e-2]. theta = 0.01 by default: of 0.003 to 0.1
+// it was the fastest on a 51,200-node cell and on forward-Euler steps of 9,000-node cells (a
+// larger theta switches so early that the solve needs a second cycle).
 double relax_switch_point(spm_handle* h, double tol) {
   const double d = fp32_operator_error(h);
   const double at = d > 0.0 ? h->cfg.relax_safety * tol / d : 1e-2;
@@ -1464,7 +1471,7 @@ void spm_default_config(spm_config* c) {
   c->precond = SPM_PRECOND_NONE;
   c->learned_max_iter = 0;
   c->node_spacing = 2.170590708293102e-3;
-  c->relax_safety = 0.1;
+  c->relax_safety = 0.01;
   c->learned_accept = 0.5;
   c->near_set = SPM_NEAR_SET_3X3;
 }

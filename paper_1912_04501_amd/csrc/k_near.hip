@@ -437,13 +437,14 @@ void launch_near(spm_handle* h, int precision) { launch_near_impl(h, precision, 
 // ----------------------------------------------------------------------------
 // Allocation-free near sum of one cell (spm_near_traction_noalloc). Its forces, FP32
 // shadows, plan and partials live in one file-scope device array (`scratch`, kNoallocBytes)
-// instead of handle memory; a fixed launch shape (256 threads, one target per lane, 256-source
-// tiles, at most kNoallocGrid workgroups) bounds the partials. Host code reaches the array
+// instead of handle memory; a fixed launch shape, the handle's default one (64 threads, one target
+// per lane, 128-source tiles, so that both entry points round the FP32 tile sums alike), and at
+// most kNoallocGrid workgroups bound the partials. Host code reaches the array
 // through the per-device address hipGetSymbolAddress returns, never through its name.
 // ----------------------------------------------------------------------------
 namespace {
 constexpr int64_t kNoallocMaxN = SPM_NOALLOC_MAX_N;
-constexpr int kNoallocBlock = 256, kNoallocTile = 256, kNoallocGrid = 1024;
+constexpr int kNoallocBlock = 64, kNoallocTile = 128, kNoallocGrid = 8192;
 constexpr int64_t kNoallocBlocks = kNoallocMaxN / kNoallocBlock;
 constexpr int64_t kNoallocSlots = kNoallocBlocks + kNoallocGrid;
 constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
