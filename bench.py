@@ -775,7 +775,10 @@ def bench_jamming(args):
                 its.append(r["infos"][0]["iterations"])
                 gaps.append(r["infos"][0]["min_gap"])
                 c, th, t = r["centers"], r["theta"], r["t"]
-            break
+            if stop is None:   # every step of the chunk converged one at a time: go on
+                s.set_workload(dict(wl, centers=c, theta=th, skew=wl["skew"] + t))
+                log(f"[jam] t = {t:.4f} mu_eff = {mus[-1]:.6g} its = {its[-1]} gap = {gaps[-1]:.3e} (steps taken singly)")
+            continue
         ts += [t + k * args.dt for k in range(n)]
         mus += r["mu_eff"].tolist()
         its += [i["iterations"] for i in r["infos"]]

@@ -7,9 +7,9 @@
 //   F = sum_j w_j sigma_j,  tau = sum_j w_j x_j^perp . sigma_j  (x relative to the centre).
 //
 // Unknowns and rows are ordered [sigma_1(0..n-1), sigma_2(0..n-1)] (m = 2n). The blocks are
-// assembled in FP64 next to an identity ([B | I], m x 2m, row-major), inverted by
-// Gauss-Jordan elimination with partial pivoting (one 1024-thread workgroup per shape),
-// and stored in FP32 column-major, so that applying them reads coalesced columns.
+// assembled in FP64 (m x m, row-major), inverted in place by blocked Gauss-Jordan elimination
+// with partial pivoting (one 1024-thread workgroup per shape), and stored in FP32 column-major,
+// so that applying them reads coalesced columns.
 #include "spm_internal.h"
 
 namespace spm {
@@ -26,10 +26,10 @@ __device__ __forceinline__ void body_node(const ShapeDesc& d, int k, double& x, 
   kap = (dx * ddy - dy * ddx) / (sp * sp * sp);
 }
 
-// block (row i, shape): both rows (component 1 and 2) of node i of [B | I]
+// block (row i, shape): both rows (component 1 and 2) of node i of B
 __global__ __launch_bounds__(256) void k_self_block(const ShapeDesc* __restrict__ sh, double* __restrict__ work) {
   const ShapeDesc d = sh[blockIdx.y];
-  const int n = d.n, m = 2 * n, ld = 2 * m;
+  const int n = d.n, m = 2 * n, ld = m;
   const int i = blockIdx.x;
   if (i >= n) return;
   double xi, yi, txi, tyi, wi, ki;
@@ -71,88 +71,164 @@ __global__ __launch_bounds__(256) void k_self_block(const ShapeDesc* __restrict_
     r2[j] = m21;
     r2[n + j] = m22;
   }
-  for (int j = threadIdx.x; j < m; j += blockDim.x) {
-    r1[m + j] = (j == i) ? 1.0 : 0.0;
-    r2[m + j] = (j == n + i) ? 1.0 : 0.0;
-  }
 }
 
-// One workgroup per shape: [B | I] -> [I | B^-1] with partial pivoting.
-// status[shape] = 1 if a pivot is zero.
+// One workgroup per shape: B (m x m, row-major) -> X = (P B)^-1 in place, P the row
+// permutation of partial pivoting (perm[i] = the row of B that ends at row i, stored after the
+// matrix); B^-1 = X P, i.e. column i of X is column perm[i] of B^-1. status[shape] = 1 if a
+// pivot is zero.
+//
+// Blocked Gauss-Jordan: the columns are taken in panels of kGJPanel. Within a panel each pivot
+// column is eliminated from every row on the panel's columns only: rows swap whole (their pending
+// updates travel with them), the pivot row is scaled, and the pivot column is replaced by its
+// column of the inverse (1/piv at the pivot, -a_ik/piv elsewhere). The panel's composite
+// elementary transform E is the identity with the pivot columns replaced by the panel P, so the
+// other columns T are then updated in one pass: T_i += P_i T_R for the non-pivot rows i and
+// T_R = P_R T_R for the pivot rows R (T_R read before it is overwritten). One pass over the
+// matrix per panel instead of one per pivot.
+constexpr int kGJPanel = 32;
+constexpr int kGJRowChunk = 128;
+
 __global__ __launch_bounds__(1024) void k_gauss_jordan(const ShapeDesc* __restrict__ sh, double* __restrict__ work,
                                                        int32_t* __restrict__ status) {
-  __shared__ double prow[2 * kMaxNodesStaged * 2];   // pivot row, up to 2m = 2048
-  __shared__ double fcol[2 * kMaxNodesStaged];       // column k of every row
+  constexpr int PB = kGJPanel, RC = kGJRowChunk;
+  __shared__ double Pl[RC * PB];                   // panel rows of one row chunk
+  __shared__ double fcol[2 * kMaxNodesStaged];     // pivot column, every row
+  __shared__ double prow[PB];                      // scaled pivot row, panel columns
   __shared__ double rv[1024];
   __shared__ int ri[1024];
   const ShapeDesc d = sh[blockIdx.x];
-  const int m = 2 * d.n, ld = 2 * m;
+  const int m = 2 * d.n;
   double* A = work + d.woff;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, nw = blockDim.x >> 6;
+  int32_t* perm = reinterpret_cast<int32_t*>(A + (int64_t)m * m);
+  const int t = threadIdx.x, T = blockDim.x;
+  for (int i = t; i < m; i += T) perm[i] = i;
   int bad = 0;
-  for (int k = 0; k < m; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + t; i < m; i += blockDim.x) {
-      const double v = fabs(A[(int64_t)i * ld + k]);
-      if (v > best) {
-        best = v;
-        bi = i;
+  for (int kb = 0; kb < m; kb += PB) {
+    const int ke = min(kb + PB, m), pw = ke - kb;
+    // ---- panel ----
+    for (int k = kb; k < ke; ++k) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + t; i < m; i += T) {
+        const double v = fabs(A[(int64_t)i * m + k]);
+        if (v > best) {
+          best = v;
+          bi = i;
+        }
       }
-    }
-    rv[t] = best;
-    ri[t] = bi;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-      if (t < o) {
-        const double v2 = rv[t + o];
-        const int i2 = ri[t + o];
-        if (v2 > rv[t] || (v2 == rv[t] && i2 < ri[t])) {
-          rv[t] = v2;
-          ri[t] = i2;
+      rv[t] = best;
+      ri[t] = bi;
+      __syncthreads();
+      for (int o = T / 2; o > 0; o >>= 1) {
+        if (t < o) {
+          const double v2 = rv[t + o];
+          const int i2 = ri[t + o];
+          if (v2 > rv[t] || (v2 == rv[t] && i2 < ri[t])) {
+            rv[t] = v2;
+            ri[t] = i2;
+          }
+        }
+        __syncthreads();
+      }
+      const int p = ri[0];
+      double piv = A[(int64_t)p * m + k];
+      if (piv == 0.0) {
+        bad = 1;
+        piv = 1.0;
+      }
+      __syncthreads();   // every thread has read ri[0] and the pivot before the rows move
+      if (p != k) {
+        for (int j = t; j < m; j += T) {
+          const double a = A[(int64_t)k * m + j];
+          A[(int64_t)k * m + j] = A[(int64_t)p * m + j];
+          A[(int64_t)p * m + j] = a;
+        }
+        if (t == 0) {
+          const int32_t q = perm[k];
+          perm[k] = perm[p];
+          perm[p] = q;
         }
       }
       __syncthreads();
+      for (int i = t; i < m; i += T) fcol[i] = A[(int64_t)i * m + k];
+      if (t < pw) prow[t] = (kb + t == k) ? 1.0 / piv : A[(int64_t)k * m + kb + t] / piv;
+      __syncthreads();
+      for (int e = t; e < m * pw; e += T) {
+        const int i = e / pw, jj = e - i * pw;
+        double* a = A + (int64_t)i * m + kb + jj;
+        if (i == k)
+          *a = prow[jj];
+        else if (kb + jj == k)
+          *a = -fcol[i] / piv;
+        else
+          *a = fma(-fcol[i], prow[jj], *a);
+      }
+      __syncthreads();
     }
-    const int p = ri[0];
-    double piv = A[(int64_t)p * ld + k];
-    if (piv == 0.0) {
-      bad = 1;
-      piv = 1.0;
-    }
-    __syncthreads();
-    // swap rows k and p, scale the pivot row, keep it in LDS
-    for (int j = t; j < ld; j += blockDim.x) {
-      const double vk = A[(int64_t)k * ld + j], vp = A[(int64_t)p * ld + j];
-      const double pr = vp / piv;
-      prow[j] = pr;
-      A[(int64_t)k * ld + j] = pr;
-      if (p != k) A[(int64_t)p * ld + j] = vk;
-    }
-    __syncthreads();
-    for (int i = t; i < m; i += blockDim.x) fcol[i] = A[(int64_t)i * ld + k];
-    __syncthreads();
-    // eliminate column k from every other row (columns left of k are already unit vectors)
-    for (int i = wave; i < m; i += nw) {
-      if (i == k) continue;
-      const double f = fcol[i];
-      double* row = A + (int64_t)i * ld;
-      for (int j = k + lane; j < ld; j += 64) row[j] -= f * prow[j];
+    // ---- the other columns: j in [0, kb) and [ke, m), at most one per thread (m <= 1024) ----
+    const int nJ = m - pw;
+    if (nJ > 0) {
+      const int CT = min(T, (nJ + 63) / 64 * 64);   // column threads
+      const int G = T / CT;                          // row groups
+      const int cg = t % CT, g = t / CT;
+      const bool col = g < G && cg < nJ;
+      const int j = cg < kb ? cg : cg + pw;
+      double tr[PB];
+#pragma unroll
+      for (int r = 0; r < PB; ++r) tr[r] = (col && r < pw) ? A[(int64_t)(kb + r) * m + j] : 0.0;
+      // non-pivot rows, in chunks of RC rows whose panel entries pass through LDS
+      for (int i0 = 0; i0 < m; i0 += RC) {
+        const int ie = min(i0 + RC, m);
+        __syncthreads();
+        for (int e = t; e < (ie - i0) * PB; e += T) {
+          const int ii = e / PB, r = e - ii * PB;
+          Pl[e] = r < pw ? A[(int64_t)(i0 + ii) * m + kb + r] : 0.0;
+        }
+        __syncthreads();
+        if (col) {
+          for (int i = i0 + g; i < ie; i += G) {
+            if (i >= kb && i < ke) continue;
+            double acc = A[(int64_t)i * m + j];
+            const double* pr = Pl + (i - i0) * PB;
+#pragma unroll
+            for (int r = 0; r < PB; ++r) acc = fma(pr[r], tr[r], acc);
+            A[(int64_t)i * m + j] = acc;
+          }
+        }
+      }
+      // pivot rows: T_R = P_R T_R (the old T_R is in tr)
+      __syncthreads();
+      for (int e = t; e < PB * PB; e += T) {
+        const int q = e / PB, r = e - q * PB;
+        Pl[e] = (q < pw && r < pw) ? A[(int64_t)(kb + q) * m + kb + r] : 0.0;
+      }
+      __syncthreads();
+      if (col) {
+        for (int q = g; q < pw; q += G) {
+          double acc = 0.0;
+#pragma unroll
+          for (int r = 0; r < PB; ++r) acc = fma(Pl[q * PB + r], tr[r], acc);
+          A[(int64_t)(kb + q) * m + j] = acc;
+        }
+      }
     }
     __syncthreads();
   }
   if (t == 0) status[blockIdx.x] = bad;
 }
 
-// inv[ioff + c m + r] = (float) A[r][m + c]
+// inv[ioff + perm[i] m + r] = (float) X[r][i]: column i of X is column perm[i] of B^-1
 __global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* __restrict__ work,
                                 float* __restrict__ inv) {
   const ShapeDesc d = sh[blockIdx.y];
-  const int m = 2 * d.n, ld = 2 * m;
-  const int c = blockIdx.x;
-  if (c >= m) return;
-  for (int r = threadIdx.x; r < m; r += blockDim.x)
-    inv[d.ioff + (int64_t)c * m + r] = (float)work[d.woff + (int64_t)r * ld + m + c];
+  const int m = 2 * d.n;
+  const int i = blockIdx.x;
+  if (i >= m) return;
+  const double* X = work + d.woff;
+  const int32_t* perm = reinterpret_cast<const int32_t*>(X + (int64_t)m * m);
+  const int64_t c = perm[i];
+  for (int r = threadIdx.x; r < m; r += blockDim.x) inv[d.ioff + c * m + r] = (float)X[(int64_t)r * m + i];
 }
 
 // Blocks (particle, row segment): out = R (B^-1 (R^T v)) on the particle's nodes, segment y
@@ -239,7 +315,7 @@ void build_precond(spm_handle* h) {
     int64_t w = 0;
     int maxn = 0;
     for (int s = s0; s < S; ++s) {
-      const int64_t need = 8LL * nodes(s) * nodes(s);   // m x 2m
+      const int64_t need = 4LL * nodes(s) * nodes(s) + nodes(s);   // m x m doubles, then m int32 (perm)
       if (!batch.empty() && w + need > budget) break;
       ShapeDesc d;
       d.kind = (int32_t)P.keys[s][0];
