@@ -26,20 +26,23 @@ __global__ __launch_bounds__(256) void k_dot_seg(const double* __restrict__ a, c
   if (threadIdx.x == 0) part[s] = acc;
 }
 
-__global__ void k_dot_cells(const double* __restrict__ part, const int32_t* __restrict__ seg_off, int C,
-                            double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per cell: lanes take the cell's segment partials k = lane, lane + 64, ..., then a
+// fixed butterfly.
+__global__ __launch_bounds__(256) void k_dot_cells(const double* __restrict__ part, const int32_t* __restrict__ seg_off,
+                                                   int C, double* __restrict__ out) {
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (c >= C) return;
   double s = 0.0;
-  for (int k = seg_off[c]; k < seg_off[c + 1]; ++k) s += part[k];
-  out[c] = s;
+  for (int k = seg_off[c] + lane; k < seg_off[c + 1]; k += 64) s += part[k];
+  s = wave_sum(s);
+  if (lane == 0) out[c] = s;
 }
 
 void gm_dot(spm_handle* h, const double* a, const double* b, double* out) {
   Krylov& K = h->kr;
   k_dot_seg<<<K.nseg, 256, 0, h->stream>>>(a, b, h->geo.N, K.seg_n0, K.seg_n1, K.part);
   SPM_HIP_CHECK(hipGetLastError());
-  k_dot_cells<<<(h->geo.C + 255) / 256, 256, 0, h->stream>>>(K.part, K.seg_off, h->geo.C, out);
+  k_dot_cells<<<(h->geo.C + 3) / 4, 256, 0, h->stream>>>(K.part, K.seg_off, h->geo.C, out);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -61,17 +64,19 @@ __global__ __launch_bounds__(256) void k_cgs_partial(const double* __restrict__ 
   if (lane == 0) part[(int64_t)s * ldp + i] = acc;
 }
 
-__global__ void k_cgs_reduce(const double* __restrict__ part, const int32_t* __restrict__ seg_off,
-                             const int32_t* __restrict__ jdev, const int32_t* __restrict__ active, int ldp,
-                             double* __restrict__ coef) {
+// coef[c][i] = sum of the cell's segment partials part[k][i]: one wave per (cell, i), lanes over
+// the segments k = lane, lane + 64, ..., then a fixed butterfly.
+__global__ __launch_bounds__(256) void k_cgs_reduce(const double* __restrict__ part, const int32_t* __restrict__ seg_off,
+                                                    const int32_t* __restrict__ jdev,
+                                                    const int32_t* __restrict__ active, int ldp,
+                                                    double* __restrict__ coef) {
   const int c = blockIdx.x;
-  if (active[c] == 0) return;
-  const int cnt = jdev[0] + 1;
-  for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-    double s = 0.0;
-    for (int k = seg_off[c]; k < seg_off[c + 1]; ++k) s += part[(int64_t)k * ldp + i];
-    coef[(int64_t)c * ldp + i] = s;
-  }
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (active[c] == 0 || i > jdev[0]) return;
+  double s = 0.0;
+  for (int k = seg_off[c] + lane; k < seg_off[c + 1]; k += 64) s += part[(int64_t)k * ldp + i];
+  s = wave_sum(s);
+  if (lane == 0) coef[(int64_t)c * ldp + i] = s;
 }
 
 void gm_cgs_pass(spm_handle* h, const double* w, double* coef) {
@@ -81,7 +86,8 @@ void gm_cgs_pass(spm_handle* h, const double* w, double* coef) {
   k_cgs_partial<<<grid, 256, 0, h->stream>>>(K.V, K.n2, h->geo.N, K.jdev, w, K.seg_n0, K.seg_n1, K.seg_cell,
                                              K.active, ldp, K.part);
   SPM_HIP_CHECK(hipGetLastError());
-  k_cgs_reduce<<<h->geo.C, 256, 0, h->stream>>>(K.part, K.seg_off, K.jdev, K.active, ldp, coef);
+  k_cgs_reduce<<<dim3((unsigned)h->geo.C, (unsigned)((ldp + 3) / 4)), 256, 0, h->stream>>>(K.part, K.seg_off, K.jdev,
+                                                                                            K.active, ldp, coef);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
