@@ -219,7 +219,7 @@ def main():
     if args.precond is None:
         args.precond = "block" if args.workload in ("ensemble64", "ellipses200") else "none"
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver is single-GPU in this build",
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver runs on a single GPU",
               file=sys.stderr)
         sys.exit(2)
 

@@ -130,9 +130,9 @@ typedef struct {
                            ratio 1.5-3 at area fraction 0.3] */
   double relax_safety;  /* margin theta of the adaptive relaxed switch point, 0 < theta <= 1 [0.01] */
   double learned_accept;/* SPM_X0_NETWORK: a cell whose fitted network guess leaves a relative residual
-                           above this starts from zero instead (GMRES judges the guess) [0.5] */
+                           above this starts from zero instead (acceptance test of the guess) [0.5] */
   int32_t near_set;     /* SPM_NEAR_SET_3X3 or SPM_NEAR_SET_DILATED [SPM_NEAR_SET_3X3]; with the dilated
-                           set, M = 64, m_wall = 24 and rcond = 1e-10 are the measured choices */
+                           set, M = 64, m_wall = 24 and rcond = 1e-8 are the measured choices */
 } spm_config;
 
 typedef struct {

@@ -930,7 +930,7 @@ int solve_impl(spm_handle* h, const double* sigma0, double* sigma, std::vector<s
     gm_dot(h, K.tmp2, K.tmp2, K.dots);
     double* hd = host_scratch<double>(h, C);
     download(h, hd, K.dots, C * sizeof(double));
-    // plain GMRES judges the guess: a cell whose fitted guess leaves more than learned_accept of
+    // acceptance test of the guess: a cell whose fitted guess leaves more than learned_accept of
     // the zero start's residual starts from zero (a loose guess puts every slowly converging
     // error component into the starting residual and costs iterations)
     std::vector<int32_t> reject(C, 0);

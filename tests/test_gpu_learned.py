@@ -301,10 +301,10 @@ def test_trained_network_gain():
     below the untrained network's. Started from that guess, GMRES nevertheless needs more
     iterations than from zero (in this operator GMRES from the right-hand side itself
     converges superlinearly, and a loose guess puts every slowly converging error component
-    into the starting residual), so plain GMRES judges the guess: a cell whose fitted guess
+    into the starting residual), so the guess must pass a test before it is used: a cell whose fitted guess
     leaves more than learned_accept (0.5) of the zero start's residual starts from zero. The
-    test asserts that the judged learned solve takes no more iterations than the zero start,
-    and records what the unjudged one costs."""
+    test asserts that the tested learned solve takes no more iterations than the zero start,
+    and records what the untested one costs."""
     import time
     spm = _spm()
     from paper_1912_04501_amd import learned as L
@@ -322,7 +322,7 @@ def test_trained_network_gain():
     wl = W.trajectory_cell(7200, lo=10, hi=20)
     out = {}
     for name, n, accept in [("zero", None, 0.5), ("untrained", untrained, 1e9), ("trained", net, 1e9),
-                            ("trained_judged", net, 0.5)]:
+                            ("trained_tested", net, 0.5)]:
         s = spm.Solver("cuda:0", x0=spm.SPM_X0_ZERO if n is None else spm.SPM_X0_NETWORK,
                        learned_accept=accept).set_workload(wl)
         b = s.rhs()
@@ -343,11 +343,11 @@ def test_trained_network_gain():
         print(f"[gain] {name:14s} initial residual {r0:.3e}  GMRES iterations {r['info']['iterations']}  "
               f"solve {1e3 * dt:.1f} ms  guess rejected {r['info']['guess_rejected']}")
     assert out["trained"][0] < out["untrained"][0] <= 1.0 + 1e-9
-    print(f"[gain] unjudged trained network vs zero start: iterations x{out['trained'][1] / out['zero'][1]:.2f}, "
+    print(f"[gain] untested trained network vs zero start: iterations x{out['trained'][1] / out['zero'][1]:.2f}, "
           f"time x{out['trained'][2] / out['zero'][2]:.2f}")
-    judged = out["trained_judged"]
-    assert judged[1] <= out["zero"][1]
-    assert judged[3] == (1 if out["trained"][0] > 0.5 else 0)
+    tested = out["trained_tested"]
+    assert tested[1] <= out["zero"][1]
+    assert tested[3] == (1 if out["trained"][0] > 0.5 else 0)
 
 
 def test_trajectory_cell_full_size_steps():
