@@ -354,6 +354,8 @@ void alloc_krylov(spm_handle* h) {
   ensure(h, K.mask, C);
   ensure(h, K.stamp, C + 2);
   ensure(h, K.jdev, 2);
+  ensure(h, K.gcount, 1);
+  gm_zero_i32(h, K.gcount, 1);
   ensure(h, K.part, (size_t)std::max(1, K.nseg) * (kmax + 1));
   ensure(h, K.tmp, n2);
   ensure(h, K.tmp2, n2);

@@ -144,69 +144,93 @@ void gm_store_next(spm_handle* h) {
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-// One thread per cell: column j of H = h1 + h2 (CGS2), subdiagonal |w|; apply the previous
+// One wavefront per cell: column j of H = h1 + h2 (CGS2), subdiagonal |w|; apply the previous
 // rotations, make rotation j, update g; res = |g_{j+1}| / bnorm; a cell whose residual
-// estimate reaches its tolerance freezes and records the wall clock. Thread 0 then
-// advances j and counts the cells still active.
-__global__ void k_givens(int C, int kmax, int32_t* __restrict__ jdev, const double* __restrict__ h1,
-                         const double* __restrict__ h2, const double* __restrict__ nrm2,
-                         const double* __restrict__ bnorm, const double* __restrict__ tolc, double* __restrict__ H,
-                         double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-                         double* __restrict__ res, int32_t* __restrict__ active, int32_t* __restrict__ kdone,
-                         unsigned long long* __restrict__ stamp) {
-  __shared__ int cnt[1024];
+// estimate reaches its tolerance freezes and records the wall clock. The lanes stage the
+// column and the stored rotations in LDS in pieces of kGivensPiece and write the rotated
+// column back; lane 0 applies the rotations in order (the same arithmetic, in the same order,
+// as one thread working from device memory). The last wavefront to finish (a counter in device
+// memory that it resets) counts the cells still active and advances j.
+constexpr int kGivensPiece = 256;
+
+__global__ __launch_bounds__(64) void k_givens(int C, int kmax, int32_t* __restrict__ jdev,
+                                               const double* __restrict__ h1, const double* __restrict__ h2,
+                                               const double* __restrict__ nrm2, const double* __restrict__ bnorm,
+                                               const double* __restrict__ tolc, double* __restrict__ H,
+                                               double* __restrict__ cs, double* __restrict__ sn,
+                                               double* __restrict__ g, double* __restrict__ res,
+                                               int32_t* __restrict__ active, int32_t* __restrict__ kdone,
+                                               unsigned long long* __restrict__ stamp,
+                                               int32_t* __restrict__ done_count) {
+  __shared__ double hp[kGivensPiece], cp[kGivensPiece], sp[kGivensPiece];
+  const int c = blockIdx.x, lane = threadIdx.x;
   const int j = jdev[0];
   const int ldp = kmax + 1;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) {
-    if (active[c] == 0) continue;
+  if (active[c] != 0) {
     double* col = H + ((int64_t)c * kmax + j) * ldp;
     const double* a1 = h1 + (int64_t)c * ldp;
     const double* a2 = h2 + (int64_t)c * ldp;
     double* csc = cs + (int64_t)c * kmax;
     double* snc = sn + (int64_t)c * kmax;
     double* gc = g + (int64_t)c * ldp;
-    for (int i = 0; i <= j; ++i) col[i] = a1[i] + a2[i];
-    col[j + 1] = sqrt(nrm2[c]);
-    for (int i = 0; i < j; ++i) {
-      const double t = csc[i] * col[i] + snc[i] * col[i + 1];
-      col[i + 1] = -snc[i] * col[i] + csc[i] * col[i + 1];
-      col[i] = t;
+    double x = a1[0] + a2[0];   // h_0, then h_i after rotations 0..i-1 (lane 0's copy is used)
+    for (int i0 = 0; i0 < j; i0 += kGivensPiece) {
+      const int i1 = min(i0 + kGivensPiece, j);
+      for (int i = i0 + lane; i < i1; i += 64) {
+        cp[i - i0] = csc[i];
+        sp[i - i0] = snc[i];
+        hp[i - i0] = a1[i + 1] + a2[i + 1];   // h_{i+1}
+      }
+      __syncthreads();
+      if (lane == 0) {
+        for (int i = i0; i < i1; ++i) {
+          const double y = hp[i - i0], cc = cp[i - i0], ss = sp[i - i0];
+          const double t = cc * x + ss * y;
+          x = -ss * x + cc * y;
+          hp[i - i0] = t;   // rotated h_i
+        }
+      }
+      __syncthreads();
+      for (int i = i0 + lane; i < i1; i += 64) col[i] = hp[i - i0];
+      __syncthreads();
     }
-    const double a = col[j], b = col[j + 1];
-    const double r = hypot(a, b);
-    const double cc = r > 0.0 ? a / r : 1.0, ss = r > 0.0 ? b / r : 0.0;
-    csc[j] = cc;
-    snc[j] = ss;
-    col[j] = r;
-    col[j + 1] = 0.0;
-    gc[j + 1] = -ss * gc[j];
-    gc[j] = cc * gc[j];
-    const double e = fabs(gc[j + 1]) / bnorm[c];
-    res[c] = e;
-    if (!(e > tolc[c]) || j + 1 >= kmax || r == 0.0) {   // converged, out of space, or exact (breakdown)
-      active[c] = 0;
-      kdone[c] = j + 1;
-      stamp[c] = wall_clock64();
+    if (lane == 0) {
+      const double b = sqrt(nrm2[c]);
+      const double r = hypot(x, b);
+      const double cc = r > 0.0 ? x / r : 1.0, ss = r > 0.0 ? b / r : 0.0;
+      csc[j] = cc;
+      snc[j] = ss;
+      col[j] = r;
+      col[j + 1] = 0.0;
+      const double gj = gc[j];
+      gc[j + 1] = -ss * gj;
+      gc[j] = cc * gj;
+      const double e = fabs(gc[j + 1]) / bnorm[c];
+      res[c] = e;
+      if (!(e > tolc[c]) || j + 1 >= kmax || r == 0.0) {   // converged, out of space, or exact (breakdown)
+        active[c] = 0;
+        kdone[c] = j + 1;
+        stamp[c] = wall_clock64();
+      }
     }
   }
-  __syncthreads();
-  int n = 0;
-  for (int c = threadIdx.x; c < C; c += blockDim.x) n += active[c];
-  cnt[threadIdx.x] = n;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int t = 0;
-    for (int k = 0; k < (int)blockDim.x; ++k) t += cnt[k];
-    jdev[1] = t;
-    jdev[0] = j + 1;
+  if (lane == 0) {
+    __threadfence();
+    if (atomicAdd(done_count, 1) == C - 1) {   // the last cell's wavefront
+      __threadfence();
+      int t = 0;
+      for (int k = 0; k < C; ++k) t += active[k];
+      jdev[1] = t;
+      jdev[0] = j + 1;
+      *done_count = 0;
+    }
   }
 }
 
 void gm_givens(spm_handle* h) {
   Krylov& K = h->kr;
-  const int bs = h->geo.C >= 1024 ? 1024 : ((h->geo.C + 63) / 64) * 64;
-  k_givens<<<1, bs, 0, h->stream>>>(h->geo.C, K.kmax, K.jdev, K.h1, K.h2, K.nrm2, K.bnorm, K.tolc, K.H, K.cs, K.sn,
-                                    K.g, K.res, K.active, K.kdone, K.stamp);
+  k_givens<<<h->geo.C, 64, 0, h->stream>>>(h->geo.C, K.kmax, K.jdev, K.h1, K.h2, K.nrm2, K.bnorm, K.tolc, K.H, K.cs,
+                                           K.sn, K.g, K.res, K.active, K.kdone, K.stamp, K.gcount);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -272,22 +296,61 @@ void gm_start(spm_handle* h) {
 }
 
 // y_c = R_c^{-1} g_c[0..k_c) (k_c = kdone, or j for cells still active), then
-// x[r] += sum_{i < k_c} V_i[r] y_c[i].
-__global__ void k_backsolve(int C, int kmax, const int32_t* __restrict__ jdev, const double* __restrict__ H,
-                            const double* __restrict__ g, const int32_t* __restrict__ active,
-                            int32_t* __restrict__ kdone, double* __restrict__ y) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// x[r] += sum_{i < k_c} V_i[r] y_c[i] (k_update_x). One wavefront per cell, column by column:
+// lane r % 64 holds the running right-hand side of rows r (up to kBackRegs per lane); y_i is
+// formed on its lane and broadcast, and every row above takes its column-i term. Cycles longer
+// than 64 kBackRegs iterations are solved row by row on one lane.
+constexpr int kBackRegs = 8;
+
+__global__ __launch_bounds__(64) void k_backsolve(int C, int kmax, const int32_t* __restrict__ jdev,
+                                                  const double* __restrict__ H, const double* __restrict__ g,
+                                                  const int32_t* __restrict__ active, int32_t* __restrict__ kdone,
+                                                  double* __restrict__ y) {
+  const int c = blockIdx.x, lane = threadIdx.x;
   if (c >= C) return;
-  if (active[c] != 0) kdone[c] = jdev[0];
-  const int k = kdone[c];
+  const int k = active[c] != 0 ? jdev[0] : kdone[c];
+  if (lane == 0 && active[c] != 0) kdone[c] = k;
   const int ldp = kmax + 1;
   const double* gc = g + (int64_t)c * ldp;
+  const double* Hc = H + (int64_t)c * kmax * ldp;   // column q of R at Hc + q ldp (rows 0..q)
   double* yc = y + (int64_t)c * kmax;
+  if (k > 64 * kBackRegs) {
+    if (lane == 0)
+      for (int i = k - 1; i >= 0; --i) {
+        double s = gc[i];
+        for (int q = i + 1; q < k; ++q) s -= Hc[(int64_t)q * ldp + i] * yc[q];
+        const double d = Hc[(int64_t)i * ldp + i];
+        yc[i] = d != 0.0 ? s / d : 0.0;
+      }
+    return;
+  }
+  double v[kBackRegs];
+#pragma unroll
+  for (int t = 0; t < kBackRegs; ++t) {
+    const int r = lane + 64 * t;
+    v[t] = r < k ? gc[r] : 0.0;
+  }
   for (int i = k - 1; i >= 0; --i) {
-    double s = gc[i];
-    for (int q = i + 1; q < k; ++q) s -= H[((int64_t)c * kmax + q) * ldp + i] * yc[q];
-    const double d = H[((int64_t)c * kmax + i) * ldp + i];
-    yc[i] = d != 0.0 ? s / d : 0.0;
+    const int owner = i & 63, slot = i >> 6;
+    double vi = 0.0;
+#pragma unroll
+    for (int t = 0; t < kBackRegs; ++t)
+      if (t == slot) vi = v[t];
+    const double d = Hc[(int64_t)i * ldp + i];
+    double yi = d != 0.0 ? vi / d : 0.0;
+    yi = __shfl(yi, owner, 64);
+    const double* Ri = Hc + (int64_t)i * ldp;
+#pragma unroll
+    for (int t = 0; t < kBackRegs; ++t) {
+      const int r = lane + 64 * t;
+      if (t == slot && lane == owner) v[t] = yi;
+      else if (r < i) v[t] = fma(-Ri[r], yi, v[t]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kBackRegs; ++t) {
+    const int r = lane + 64 * t;
+    if (r < k) yc[r] = v[t];
   }
 }
 
@@ -306,7 +369,7 @@ __global__ void k_update_x(const double* __restrict__ V, int64_t n2, int64_t N, 
 
 void gm_backsolve(spm_handle* h) {
   Krylov& K = h->kr;
-  k_backsolve<<<(h->geo.C + 63) / 64, 64, 0, h->stream>>>(h->geo.C, K.kmax, K.jdev, K.H, K.g, K.active, K.kdone, K.yv);
+  k_backsolve<<<h->geo.C, 64, 0, h->stream>>>(h->geo.C, K.kmax, K.jdev, K.H, K.g, K.active, K.kdone, K.yv);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
@@ -320,6 +383,16 @@ void gm_update_only(spm_handle* h, double* x) {
 void gm_backsolve_update(spm_handle* h, double* x) {
   gm_backsolve(h);
   gm_update_only(h, x);
+}
+
+__global__ void k_zero_i32(int64_t n, int32_t* __restrict__ p) {
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r < n) p[r] = 0;
+}
+
+void gm_zero_i32(spm_handle* h, int32_t* p, int64_t n) {
+  k_zero_i32<<<(unsigned)((n + 255) / 256), 256, 0, h->stream>>>(n, p);
+  SPM_HIP_CHECK(hipGetLastError());
 }
 
 __global__ void k_axpby(int64_t n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,

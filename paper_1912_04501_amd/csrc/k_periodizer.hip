@@ -386,6 +386,7 @@ void launch_disc(spm_handle* h) { launch_disc_impl(h, false); }
 
 // One block per cell: g = sum of the cell's chunk partials, F = sum of its particles'
 // forces, xi = Q^+ (g0 - g).
+constexpr int kXiWalls = 3, kXiRows = 4;   // wall points / rows of Q+ per wave
 __global__ __launch_bounds__(1024) void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __restrict__ disc_off,
                      const int32_t* __restrict__ cpoff, const double* __restrict__ disc, const double* __restrict__ pF,
                      const double* __restrict__ Qp_all, const int32_t* __restrict__ active, double* __restrict__ xi_all) {
@@ -413,34 +414,56 @@ __global__ __launch_bounds__(1024) void k_xi(Lat L, const double* __restrict__ c
   __syncthreads();
   const double skew = cskew[cell];
   const double l1 = 1.0, l2 = sqrt(skew * skew + 1.0);
-  // one wave per wall point, lanes over the source chunks, then a fixed butterfly
+  // kXiWalls wall points per wave, lanes over the source chunks, then a fixed butterfly per sum
+  // (the loads of a batch are in flight together)
   const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int wpt = threadIdx.x >> 6; wpt < 2 * m; wpt += nw) {
-    dd s[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  for (int w0 = (threadIdx.x >> 6) * kXiWalls; w0 < 2 * m; w0 += nw * kXiWalls) {
+    dd s[kXiWalls][4];
+#pragma unroll
+    for (int b = 0; b < kXiWalls; ++b)
+      for (int k = 0; k < 4; ++k) s[b][k] = dd{0, 0};
     for (int c = disc_off[cell] + lane; c < disc_off[cell + 1]; c += 64) {
-      const double* o = disc + ((int64_t)c * 2 * m + wpt) * 8;
-      for (int k = 0; k < 4; ++k) s[k] = dd_add(s[k], dd{o[k], o[4 + k]});
+#pragma unroll
+      for (int b = 0; b < kXiWalls; ++b) {
+        if (w0 + b >= 2 * m) break;
+        const double* o = disc + ((int64_t)c * 2 * m + w0 + b) * 8;
+        for (int k = 0; k < 4; ++k) s[b][k] = dd_add(s[b][k], dd{o[k], o[4 + k]});
+      }
     }
-    for (int k = 0; k < 4; ++k) s[k] = dd_wave_sum(s[k]);
+#pragma unroll
+    for (int b = 0; b < kXiWalls; ++b)
+      for (int k = 0; k < 4; ++k) s[b][k] = dd_wave_sum(s[b][k]);
     if (lane == 0) {
-      const bool onD = wpt >= m;
-      const int q = onD ? wpt - m : wpt;
-      const int base = onD ? 4 * m : 0;
-      const double l = onD ? l1 : l2;
-      const double g0[4] = {0.0, 0.0, -Fs[0] / (2.0 * l), -Fs[1] / (2.0 * l)};
-      for (int k = 0; k < 4; ++k) {   // g0 - g, rounded once
-        const dd v = dd_add(dd{g0[k], 0.0}, dd{-s[k].hi, -s[k].lo});
-        gt[base + k * m + q] = v.hi + v.lo;
+      for (int b = 0; b < kXiWalls && w0 + b < 2 * m; ++b) {
+        const int wpt = w0 + b;
+        const bool onD = wpt >= m;
+        const int q = onD ? wpt - m : wpt;
+        const int base = onD ? 4 * m : 0;
+        const double l = onD ? l1 : l2;
+        const double g0[4] = {0.0, 0.0, -Fs[0] / (2.0 * l), -Fs[1] / (2.0 * l)};
+        for (int k = 0; k < 4; ++k) {   // g0 - g, rounded once
+          const dd v = dd_add(dd{g0[k], 0.0}, dd{-s[b][k].hi, -s[b][k].lo});
+          gt[base + k * m + q] = v.hi + v.lo;
+        }
       }
     }
   }
   __syncthreads();
-  // one wave per row of Q+, lanes over its 8m entries; compensated dot product
-  for (int i = threadIdx.x >> 6; i < 2 * M; i += nw) {
-    dd s = {0, 0};
-    for (int r = lane; r < 8 * m; r += 64) s = dd_fma(s, Qp[(int64_t)i * 8 * m + r], gt[r]);
-    s = dd_wave_sum(s);
-    if (lane == 0) xi[i] = s.hi + s.lo;
+  // kXiRows rows of Q+ per wave, lanes over the 8m entries of each; compensated dot products
+  for (int i0 = (threadIdx.x >> 6) * kXiRows; i0 < 2 * M; i0 += nw * kXiRows) {
+    dd s[kXiRows];
+#pragma unroll
+    for (int b = 0; b < kXiRows; ++b) s[b] = dd{0, 0};
+    for (int r = lane; r < 8 * m; r += 64) {
+      const double gr = gt[r];
+#pragma unroll
+      for (int b = 0; b < kXiRows; ++b)
+        if (i0 + b < 2 * M) s[b] = dd_fma(s[b], Qp[(int64_t)(i0 + b) * 8 * m + r], gr);
+    }
+#pragma unroll
+    for (int b = 0; b < kXiRows; ++b) s[b] = dd_wave_sum(s[b]);
+    if (lane == 0)
+      for (int b = 0; b < kXiRows && i0 + b < 2 * M; ++b) xi[i0 + b] = s[b].hi + s[b].lo;
   }
 }
 

@@ -403,6 +403,7 @@ struct Krylov {
   unsigned long long* stamp = nullptr;  // [C + 2] device wall clock at convergence; [C] = solve start,
                                         // [C + 1] = start of the current Krylov cycle
   int32_t* jdev = nullptr;    // [2]: current j, number of active cells
+  int32_t* gcount = nullptr;  // [1] k_givens wavefronts finished in the running launch (the last resets it)
   double* part = nullptr;     // [nseg x (kmax+1)] dot partials
   int32_t nseg = 0;
   int64_t* seg_n0 = nullptr;  // [nseg] node range of each dot segment
@@ -583,6 +584,7 @@ void gm_cgs_pass(spm_handle* h, const double* w, double* coef);
 void gm_update_j(spm_handle* h, const double* coef, double* w);
 void gm_store_next(spm_handle* h);
 void gm_givens(spm_handle* h);
+void gm_zero_i32(spm_handle* h, int32_t* p, int64_t n);
 void gm_copy_in(spm_handle* h);
 void gm_start(spm_handle* h);
 void gm_backsolve_update(spm_handle* h, double* x);
