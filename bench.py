@@ -191,10 +191,11 @@ def main():
     ap.add_argument("--tune-cache", default=None, help="autotuner cache file (reuse launch shapes across runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 256 MiB device copy three times (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["ellipses200", "ensemble64", "learned", "jamming", "islands"],
+    ap.add_argument("--workload", choices=["ellipses200", "ensemble64", "learned", "stepping", "jamming", "islands"],
                     default="ellipses200",
                     help="ellipses200: the 200-ellipse cell (default); ensemble64: 64 independent cells in one "
-                         "launch; learned: time stepping with the trained warm-start network; jamming: two "
+                         "launch; learned: time stepping with the trained warm-start network; stepping: the same held-out "
+                         "trajectory steps without the network; jamming: two "
                          "star-shaped particles sheared into contact (Sec. 8 Examples 4 and 5); islands: K random "
                          "star-shaped islands of 350 nodes (Sec. 8 Example 2 scale) with the FMM near sum")
     ap.add_argument("--islands", default="100,250,500,1000", help="islands: the island counts K")
@@ -244,6 +245,8 @@ def main():
         return bench_learned(args)
     if args.workload == "jamming":
         return bench_jamming(args)
+    if args.workload == "stepping":
+        return bench_stepping(args)
     if args.workload == "islands":
         return bench_islands(args)
     t0 = time.perf_counter()
@@ -605,6 +608,47 @@ def bench_islands(args):
                       "area_fraction": 0.2, "near_sum": "fmm", "fmm_order": st["order"], "precond": "block",
                       "tol": 1e-10},
            "roofline": roofline, "cpu_baseline": cpu, "series": series}
+    print(json.dumps(out), flush=True)
+
+
+def bench_stepping(args):
+    """Forward-Euler time stepping of the three held-out trajectory cells (seeds 6000-6002,
+    70-100 ellipses, dt 0.01) with relaxed FP32 products and the block preconditioner, from
+    a zero guess, without the network: --steps steps per cell after one untimed step (which
+    builds the preconditioner and captures the iteration graphs). Every step re-sets the
+    geometry and solves to the FP64 residual 1e-10. value = steps per second over the three
+    cells."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04501_amd import spm
+    from paper_1912_04501_amd import workloads as W
+    cells, secs, steps = [], 0.0, 0
+    for sd in (6000, 6001, 6002):
+        wl = W.trajectory_cell(sd)
+        s = spm.Solver("cuda:0", precision=spm.SPM_FP32_RELAXED, precond=spm.SPM_PRECOND_BLOCK).set_workload(wl)
+        s.step(0.01, 1, 0.0, wl["centers"], wl["theta"])
+        s.set_workload(wl)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.step(0.01, args.steps, 0.0, wl["centers"], wl["theta"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        secs += dt
+        steps += args.steps
+        its = [i["iterations"] for i in r["infos"]]
+        cells.append({"seed": sd, "N": s.N, "particles": s.No, "ms_per_step": 1e3 * dt / args.steps,
+                      "iterations_mean": float(np.mean(its)),
+                      "max_rel_residual": max(i["rel_residual"] for i in r["infos"])})
+        log(f"[bench] stepping seed {sd}: {cells[-1]}")
+        s.close()
+    out = {"metric": "time steps/s of forward-Euler stepping, relaxed FP32 + block preconditioner (FP64 residual 1e-10)",
+           "value": steps / secs, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": 3,
+           "ms_per_step": 1e3 * secs / steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": {"workload": "trajectories_25-100_ellipses_phi0.3_dt0.01", "eval_seeds": "6000-6002",
+                      "precision": "fp32_relaxed", "precond": "block", "x0": "zero"},
+           "cells": cells, "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
