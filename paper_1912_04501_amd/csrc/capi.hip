@@ -657,9 +657,9 @@ void matvec(spm_handle* h, const double* sigma, double* out, int precision, bool
     launch_fmm(h, h->wk.Tpart);
   else
     launch_near_impl(h, precision, with_active);
-  launch_combine(h, sigma, true, precision);
+  launch_combine(h, sigma, true, precision, with_active);
   if (h->cl.ntargets > 0) {
-    launch_vplus(h, sigma, false);
+    launch_vplus(h, sigma, false, with_active);
     launch_close_apply_impl(h, h->wk.T, precision, with_active);
   }
   if (precision == SPM_FP32) launch_self_fix(h, h->wk.T, with_active);

@@ -30,12 +30,14 @@ __device__ __forceinline__ cplx cinv(cplx a) {
 // nodes pass through LDS in tiles of kVplusTile. Lane `sub` of a node takes k = sub, sub + L,
 // ... (tile sizes are multiples of L) and the lanes' sums are combined by a fixed butterfly.
 __global__ __launch_bounds__(1024) void k_vplus(int64_t N, Geo g, const double* __restrict__ sigma, int L,
-                                                const int32_t* __restrict__ need, double* __restrict__ vp) {
+                                                const int32_t* __restrict__ need, const int32_t* __restrict__ active,
+                                                double* __restrict__ vp) {
   __shared__ double s_yr[kVplusTile], s_yi[kVplusTile];
   __shared__ double s_wr[kVplusTile], s_wi[kVplusTile];
   __shared__ double s_ph[6][kVplusTile];
   const int q = blockIdx.x;
   if (need && need[q] == 0) return;   // no close pair takes this particle as its source
+  if (active && active[g.pcell[q]] == 0) return;   // its cell is not iterating
   const int o = g.poff[q], n = g.pn[q];
   const int R = blockDim.x / L;
   const int j = blockIdx.y * R + threadIdx.x / L;
@@ -116,12 +118,12 @@ inline int vplus_lanes(int nmax) { return nmax <= kVplusTile ? lanes_per_row(nma
 
 // all_particles: every curve (field evaluation near any particle); otherwise only the sources of
 // the close pairs, which is all the operator's close correction reads
-void launch_vplus(spm_handle* h, const double* sigma, bool all_particles) {
+void launch_vplus(spm_handle* h, const double* sigma, bool all_particles, bool with_active) {
   const int L = vplus_lanes(h->geo.nmax);
   const int R = 1024 / L;
   const dim3 grid((unsigned)h->geo.No, (unsigned)((h->geo.nmax + R - 1) / R));
   k_vplus<<<grid, 1024, 0, h->stream>>>(h->geo.N, h->geo, sigma, L, all_particles ? nullptr : h->cl.qsrc,
-                                        h->cl.vp);
+                                        with_active ? h->kr.active : nullptr, h->cl.vp);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

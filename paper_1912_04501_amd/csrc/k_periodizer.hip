@@ -494,22 +494,25 @@ __global__ __launch_bounds__(256) void k_combine(int64_t N, int64_t bt, const in
                                                  const double* __restrict__ sigma, int M,
                                                  const double* __restrict__ px, const double* __restrict__ py,
                                                  const double* __restrict__ xi_all, int with_extra,
-                                                 double* __restrict__ T) {
+                                                 const int32_t* __restrict__ active, double* __restrict__ T) {
   const int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t i = gid / kCombineLanes;
   const int l = (int)(gid % kCombineLanes);
-  const bool live = i < N;
-  const int64_t ii = live ? i : N - 1;   // idle lanes shadow the last target so shuffles stay uniform
-  const int cell = g.ncell[ii];
+  const int64_t i0 = i < N ? i : N - 1;   // idle lanes shadow the last target so shuffles stay uniform
+  const int cell = g.ncell[i0];
+  // targets of cells that are not active (given a mask) are left as they are; the lanes of a
+  // target share its cell, so a group skips together
+  const bool live = i < N && (active == nullptr || active[cell] != 0);
+  const int64_t ii = i0;
   const int64_t li = ii - g.cnoff[cell];
   const int64_t b = cell_blk[cell] + li / bt, local = li % bt;
-  const int s1 = slot_off[b + 1];
+  const int s1 = live ? slot_off[b + 1] : 0;
   double t1 = 0, t2 = 0;
   for (int k = slot_off[b] + l; k < s1; k += kCombineLanes) {
     t1 += Tpart[(int64_t)k * 2 * bt + local];
     t2 += Tpart[(int64_t)k * 2 * bt + bt + local];
   }
-  if (with_extra) {   // the correction field at the target's position in the cell (wrapped node, dilated set)
+  if (with_extra && live) {   // the correction field at the target's position in the cell (wrapped node, dilated set)
     const double xx = g.dilated ? g.xw[ii] : g.x[ii], yy = g.dilated ? g.yw[ii] : g.y[ii];
     const double nx = g.nx[ii], ny = g.ny[ii];
     const double* xi = xi_all + (int64_t)cell * 2 * M;
@@ -535,7 +538,8 @@ __global__ __launch_bounds__(256) void k_combine(int64_t N, int64_t bt, const in
   T[N + i] = t2;
 }
 
-static void combine_into(spm_handle* h, const double* sigma, bool with_self_corr, int precision, double* out) {
+static void combine_into(spm_handle* h, const double* sigma, bool with_self_corr, int precision, double* out,
+                         bool with_active = false) {
   const int64_t N = h->geo.N;
   const NearPlan& P = h->wk.near[precision == SPM_FP64 ? 0 : 1];
   const int64_t threads = N * kCombineLanes;
@@ -545,12 +549,13 @@ static void combine_into(spm_handle* h, const double* sigma, bool with_self_corr
   const int32_t* slot_off = h->fmm.on ? h->fmm.one_block : P.slot_off;
   k_combine<<<(unsigned)((threads + 255) / 256), 256, 0, h->stream>>>(N, bt, cell_blk, slot_off, h->wk.Tpart,
                                                                      h->geo, sigma, h->per.M, h->per.px, h->per.py,
-                                                                     h->wk.xi, with_self_corr ? 1 : 0, out);
+                                                                     h->wk.xi, with_self_corr ? 1 : 0,
+                                                                     with_active ? h->kr.active : nullptr, out);
   SPM_HIP_CHECK(hipGetLastError());
 }
 
-void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision) {
-  combine_into(h, sigma, with_self_corr, precision, h->wk.T);
+void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision, bool with_active) {
+  combine_into(h, sigma, with_self_corr, precision, h->wk.T, with_active);
 }
 
 // The near-image sum alone (stage entry point for checking the near sum).

@@ -555,7 +555,8 @@ void build_near_plan(spm_handle* h, int precision);
 void autotune(spm_handle* h, const char* cache_path, double* best_ms_out);
 double time_near(spm_handle* h, int prec, const NearConfig& c, int reps);
 NearConfig heuristic_near(spm_handle* h, int precision);
-void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision);
+void launch_combine(spm_handle* h, const double* sigma, bool with_self_corr, int precision,
+                    bool with_active = false);
 void launch_disc(spm_handle* h);
 void launch_xi(spm_handle* h);
 void launch_build_Q(spm_handle* h);
@@ -563,7 +564,7 @@ void launch_pinv(spm_handle* h);
 void launch_close_count(spm_handle* h);
 void launch_close_scan(spm_handle* h, int32_t* total_host, int32_t* ntargets_host);
 void launch_close_fill(spm_handle* h);
-void launch_vplus(spm_handle* h, const double* sigma, bool all_particles);
+void launch_vplus(spm_handle* h, const double* sigma, bool all_particles, bool with_active = false);
 void launch_close_sources(spm_handle* h);
 void launch_close_apply(spm_handle* h, const double* sigma, double* T, int precision);
 void launch_self_fix(spm_handle* h, double* T, bool with_active);
