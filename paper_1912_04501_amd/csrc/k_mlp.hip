@@ -5,7 +5,8 @@
 // 256-thread workgroup, four waves of 2 x 2 16x16 MFMA blocks, 32-deep K slices
 // staged through LDS. Operands are FP32 in memory (master weights, activations);
 // in BF16 mode they are rounded to bfloat16 (nearest even) when fragments are
-// built and multiplied with v_mfma_f32_16x16x16_bf16 (FP32 accumulation); in FP32
+// built and multiplied with v_mfma_f32_16x16x32_bf16, the whole 32-deep slice in one
+// instruction per 16x16 block (FP32 accumulation); in FP32
 // mode v_mfma_f32_16x16x4_f32 multiplies them exactly (the gradient-check mode).
 // Bias, ReLU and the ReLU derivative mask are fused into the GEMM epilogue.
 //
@@ -17,7 +18,8 @@ namespace spm {
 
 namespace {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short shortx8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIn = SPM_MLP_IN, kHid = SPM_MLP_HIDDEN, kOut = SPM_MLP_OUT;
@@ -117,24 +119,26 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
     __syncthreads();
     const int lr = lane & 15, lq = lane >> 4;
     if (MODE == SPM_MLP_BF16) {
+      // Lane l holds row (or column) l % 16 and the eight k of group l / 16; A and B use the
+      // same k assignment, so the product is the sum over the whole slice.
+      static_assert(BK == 32, "one 16x16x32 product per slice");
+      shortx8 fa[2], fb[2];
 #pragma unroll
-      for (int ks = 0; ks < BK; ks += 16) {
-        bf16x4 fa[2], fb[2];
+      for (int i = 0; i < 2; ++i) {
+        const float* pa = As + (32 * wm + 16 * i + lr) * LDP + 8 * lq;
+        const float* pb = Bs + (32 * wn + 16 * i + lr) * LDP + 8 * lq;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const float* pa = As + (32 * wm + 16 * i + lr) * LDP + ks + 4 * lq;
-          const float* pb = Bs + (32 * wn + 16 * i + lr) * LDP + ks + 4 * lq;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            fa[i][q] = to_bf16(pa[q]);
-            fb[i][q] = to_bf16(pb[q]);
-          }
+        for (int q = 0; q < 8; ++q) {
+          fa[i][q] = to_bf16(pa[q]);
+          fb[i][q] = to_bf16(pb[q]);
         }
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[i], fb[j], acc[i][j], 0, 0, 0);
       }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, fa[i]),
+                                                              __builtin_bit_cast(bf16x8, fb[j]), acc[i][j], 0, 0, 0);
     } else {
 #pragma unroll
       for (int ks = 0; ks < BK; ks += 4) {
