@@ -504,8 +504,8 @@ struct spm_handle {
   spm::Precond pc;
   spm_mlp* net = nullptr;             // borrowed warm-start network
   double min_gap_est = 0.0;
-  double delta32 = -1.0;
-  std::vector<int32_t> guess_rejected;   // [C] per cell of the last solve: learned guess rejected      // measured relative error of the FP32 operator (< 0: not measured for this geometry)
+  double delta32 = -1.0;              // measured relative error of the FP32 operator (< 0: not measured for this geometry)
+  std::vector<int32_t> guess_rejected;   // [C] per cell of the last solve: learned guess rejected
   double wallclock_hz = 1e8;
 
   // opt-in kernel timing: HIP events around near-sum launches (kernel 0 = FP64, 1 = FP32; FMM: 2 = evaluation, 3 = M2L)
