@@ -1,6 +1,6 @@
 // Autotuner of the near-sum launch shape (block size, targets per lane, LDS tile), run on the handle's own geometry: every candidate is timed with HIP
 // events on the handle's stream; the fastest per precision is kept and optionally
-// cached in a text file keyed by device, node count and precision.
+// cached in a text file keyed by device, node count, precision and near set.
 #include <algorithm>
 #include <cstdio>
 #include <fstream>
@@ -27,7 +27,8 @@ static std::string key_of(spm_handle* h, int prec) {
   std::ostringstream o;
   double work = 0;
   for (const auto& c : h->cells) work += (double)(c.n1 - c.n0) * (double)(c.n1 - c.n0);
-  o << device_name() << " N=" << h->geo.N << " C=" << h->geo.C << " W=" << work << " prec=" << (prec == 0 ? "fp64" : "fp32");
+  o << device_name() << " N=" << h->geo.N << " C=" << h->geo.C << " W=" << work << " prec=" << (prec == 0 ? "fp64" : "fp32")
+    << " set=" << (h->geo.dilated ? "dilated" : "3x3");
   return o.str();
 }
 

@@ -175,7 +175,8 @@ __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets
       } else if (!g.dilated) {
         const float dx = g.xf[i] - g.xf[kk], dy = g.yf[i] - g.yf[kk];
         float a1 = 0.f, a2 = 0.f;
-        gt_pair(dx - shxf, row_terms(dy, shyf, g.nyf[i], f2f[kk]), g.nxf[i], f1f[kk], a1, a2);
+        const PairTerms32 pt = pair_terms32(g.nxf[i], g.nyf[i], f1f[kk], f2f[kk]);
+        gt_pair32(dx - shxf, row_terms32_any(dy, shyf, pt), pt, a1, a2);
         p1 += (double)a1;
         p2 += (double)a2;
       } else {
@@ -308,7 +309,8 @@ __global__ __launch_bounds__(1024) void k_self_fix(int64_t N, Geo g, const doubl
       if (!g.dilated) {
         const float dx = xif - g.xf[kk], dy = yif - g.yf[kk];
         float a1 = 0.f, a2 = 0.f;
-        gt_pair(dx - 0.0f, row_terms(dy, 0.0f, nyif, f2f[kk]), nxif, f1f[kk], a1, a2);
+        const PairTerms32 pt = pair_terms32(nxif, nyif, f1f[kk], f2f[kk]);
+        gt_pair32(dx - 0.0f, row_terms32<true>(dy, 0.0f, pt), pt, a1, a2);
         e1 += (double)a1;
         e2 += (double)a2;
       } else {   // wrapped nodes: the own curve's node kk sits at shift (wrap of i) - (wrap of kk)

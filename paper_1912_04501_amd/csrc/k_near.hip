@@ -20,8 +20,10 @@
 // Inside a unit: one target per lane (or TPT targets i, i + BLOCK, ...), the source tile
 // staged in LDS (every lane of a wave reads the same source: LDS broadcast), the 9 image
 // shifts of the cell applied to the source difference, the three images of a lattice row
-// sharing their row terms.
+// sharing their row terms. In FP32 the pair's (r.n)(r.f) is a quadratic in rx whose
+// coefficients are formed once per source and row (two fused multiply-adds per image).
 #include <algorithm>
+#include <type_traits>
 #include <mutex>
 
 #include "spm_internal.h"
@@ -220,6 +222,15 @@ __device__ __forceinline__ void near_run(typename SrcOf<R, DIL>::type* src, cons
           gt_pair(dx - s.sxA, r0, nxi[t], s.f1, a1[t], a2[t]);
           gt_pair(dx - s.sxB, rB, nxi[t], s.f1, a1[t], a2[t]);
           gt_pair(dx - s.sxC, rB, nxi[t], s.f1, a1[t], a2[t]);
+        } else if constexpr (std::is_same<R, float>::value) {
+          const PairTerms32 pt = pair_terms32(nxi[t], nyi[t], s.f1, s.f2);
+          RowTerms32 row[3];
+          row[0] = row_terms32<false>(dy, sy[0], pt);
+          row[1] = row_terms32<true>(dy, sy[1], pt);
+          row[2] = row_terms32<false>(dy, sy[2], pt);
+#pragma unroll
+          for (int m = 0; m < kShifts; ++m)
+            gt_pair32(m == kShifts / 2 ? dx : dx - sx[m], row[m % 3], pt, a1[t], a2[t]);
         } else {
           RowTerms<R> row[3];
 #pragma unroll

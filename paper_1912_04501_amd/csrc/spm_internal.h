@@ -145,6 +145,56 @@ __device__ __forceinline__ void gt_pair(float rx, const RowTerms<float>& t, floa
   a2 = fmaf(c, t.ry, a2);
 }
 
+// FP32 terms of the 3x3 image set in Horner form. With A = n1 f1, D = n1 f2 + n2 f1 and
+// E = n2 f2 (target normal n, source force f, once per target-source pair),
+//   (r.n)(r.f) = (A rx + B) rx + C,   B = ry D,   C = ry^2 E   (once per lattice row),
+// two fused multiply-adds per image where the product form takes three operations. The row of
+// zero y shift, which holds the target's own node, takes C from the exact square (zero for
+// ry = 0, so the self pair is exactly zero as above); the other rows take it from the floored
+// square they already hold. Every kernel that removes FP32 plain terms of the 3x3 set calls
+// these with the same row rule, so its terms are bit-identical to the near sum's.
+struct PairTerms32 {
+  float A, D, E;
+};
+
+__device__ __forceinline__ PairTerms32 pair_terms32(float nx, float ny, float f1, float f2) {
+  PairTerms32 p;
+  p.A = nx * f1;
+  p.D = fmaf(nx, f2, ny * f1);
+  p.E = ny * f2;
+  return p;
+}
+
+struct RowTerms32 {
+  float ry, ry2, B, C;
+};
+
+template <bool ZERO_ROW>
+__device__ __forceinline__ RowTerms32 row_terms32(float dy, float sy, const PairTerms32& p) {
+  RowTerms32 t;
+  t.ry = dy - sy;
+  t.ry2 = fmaf(t.ry, t.ry, 1e-30f);
+  t.B = t.ry * p.D;
+  t.C = ZERO_ROW ? (t.ry * t.ry) * p.E : t.ry2 * p.E;
+  return t;
+}
+
+// Row terms for a shift known only at run time (the zero-shift row by value, as in the near sum).
+__device__ __forceinline__ RowTerms32 row_terms32_any(float dy, float sy, const PairTerms32& p) {
+  return sy == 0.0f ? row_terms32<true>(dy, sy, p) : row_terms32<false>(dy, sy, p);
+}
+
+__device__ __forceinline__ void gt_pair32(float rx, const RowTerms32& t, const PairTerms32& p, float& a1, float& a2) {
+  const float r2 = fmaf(rx, rx, t.ry2);
+  const float q = fmaf(p.A, rx, t.B);
+  const float pr = fmaf(q, rx, t.C);
+  const float inv = __builtin_amdgcn_rcpf(r2);
+  float c = pr * inv;
+  c = c * inv;
+  a1 = fmaf(c, rx, a1);
+  a2 = fmaf(c, t.ry, a2);
+}
+
 // Accurate FP64 reciprocal (correctly rounded division is not needed here).
 __device__ __forceinline__ double rcp64(double v) {
   const double i0 = __builtin_amdgcn_rcp(v);
