@@ -281,16 +281,18 @@ void launch_close_apply(spm_handle* h, const double* sigma, double* T, int preci
 // a tiny fraction of all pairs) are recomputed in FP64 and the FP32 ones, evaluated
 // with the near kernel's own per-pair arithmetic, are removed:
 //   T_i += -(1/pi) sum_{k on the curve of i} (a64(i, k) - a32(i, k)).
-// One block per particle, one thread per target.
-__global__ __launch_bounds__(1024) void k_self_fix(int64_t N, Geo g, const double* __restrict__ f1,
+// Groups of kSelfFixLanes lanes per target (sources k = sub, sub + lanes, ...), 256-thread
+// blocks over (particle, range of its targets).
+constexpr int kSelfFixLanes = 16;
+__global__ __launch_bounds__(256) void k_self_fix(int64_t N, Geo g, const double* __restrict__ f1,
                                                    const double* __restrict__ f2, const float* __restrict__ f1f,
                                                    const float* __restrict__ f2f, const int32_t* __restrict__ active,
                                                    int L, double* __restrict__ T) {
   const int q = blockIdx.x;
   if (active != nullptr && active[g.pcell[q]] == 0) return;
   const int o = g.poff[q], n = g.pn[q];
-  const int sub = threadIdx.x % L;
-  for (int k0 = threadIdx.x / L; k0 < n; k0 += blockDim.x / L) {
+  const int sub = threadIdx.x % L, per = blockDim.x / L;
+  for (int k0 = blockIdx.y * per + threadIdx.x / L; k0 < n; k0 += gridDim.y * per) {
     const int64_t i = o + k0;
     const double xi = g.x[i], yi = g.y[i], nxi = g.nx[i], nyi = g.ny[i];
     const float xif = g.xf[i], yif = g.yf[i], nxif = g.nxf[i], nyif = g.nyf[i];
@@ -332,8 +334,10 @@ __global__ __launch_bounds__(1024) void k_self_fix(int64_t N, Geo g, const doubl
 }
 
 void launch_self_fix(spm_handle* h, double* T, bool with_active) {
-  k_self_fix<<<h->geo.No, 1024, 0, h->stream>>>(h->geo.N, h->geo, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f,
-                                                with_active ? h->kr.active : nullptr, lanes_per_row(h->geo.nmax), T);
+  const int per = 256 / kSelfFixLanes;
+  const dim3 grid((unsigned)h->geo.No, (unsigned)((h->geo.nmax + per - 1) / per));
+  k_self_fix<<<grid, 256, 0, h->stream>>>(h->geo.N, h->geo, h->wk.f1, h->wk.f2, h->wk.f1f, h->wk.f2f,
+                                          with_active ? h->kr.active : nullptr, kSelfFixLanes, T);
   SPM_HIP_CHECK(hipGetLastError());
 }
 

@@ -385,12 +385,16 @@ void launch_disc_impl(spm_handle* h, bool with_active) {
 void launch_disc(spm_handle* h) { launch_disc_impl(h, false); }
 
 // One block per cell: g = sum of the cell's chunk partials, F = sum of its particles'
-// forces, xi = Q^+ (g0 - g).
-constexpr int kXiWalls = 3, kXiRows = 4;   // wall points / rows of Q+ per wave
-__global__ __launch_bounds__(1024) void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __restrict__ disc_off,
+// forces, xi = Q^+ (g0 - g). Every double-double sum runs along one thread (no cross-lane
+// reductions, which cost far more issue slots than the sums themselves): one thread per
+// (wall point, component) over the chunks in order, then one thread per segment of a row of
+// Q^+, the segment partials of a row summed in order by one thread.
+constexpr int kXiThreads = 1024, kXiBatch = 8;
+__global__ __launch_bounds__(kXiThreads) void k_xi(Lat L, const double* __restrict__ cskew, const int32_t* __restrict__ disc_off,
                      const int32_t* __restrict__ cpoff, const double* __restrict__ disc, const double* __restrict__ pF,
                      const double* __restrict__ Qp_all, const int32_t* __restrict__ active, double* __restrict__ xi_all) {
   __shared__ double gt[8 * 256];
+  __shared__ double part[2 * kXiThreads];   // segment partials (hi, lo) of the rows of Q+
   __shared__ double Fs[2];
   const int cell = blockIdx.x;
   if (active != nullptr && active[cell] == 0) return;
@@ -414,56 +418,63 @@ __global__ __launch_bounds__(1024) void k_xi(Lat L, const double* __restrict__ c
   __syncthreads();
   const double skew = cskew[cell];
   const double l1 = 1.0, l2 = sqrt(skew * skew + 1.0);
-  // kXiWalls wall points per wave, lanes over the source chunks, then a fixed butterfly per sum
-  // (the loads of a batch are in flight together)
-  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
-  for (int w0 = (threadIdx.x >> 6) * kXiWalls; w0 < 2 * m; w0 += nw * kXiWalls) {
-    dd s[kXiWalls][4];
+  // g0 - g at wall point wpt, component k (thread t = 4 wpt + k: neighbouring threads read
+  // neighbouring words of a chunk's partials)
+  const int c0 = disc_off[cell], c1 = disc_off[cell + 1];
+  for (int t = threadIdx.x; t < 8 * m; t += blockDim.x) {
+    const int wpt = t >> 2, k = t & 3;
+    dd sum = {0, 0};
+    int c = c0;
+    for (; c + kXiBatch <= c1; c += kXiBatch) {   // the batch's loads in flight together
+      double hi[kXiBatch], lo[kXiBatch];
 #pragma unroll
-    for (int b = 0; b < kXiWalls; ++b)
-      for (int k = 0; k < 4; ++k) s[b][k] = dd{0, 0};
-    for (int c = disc_off[cell] + lane; c < disc_off[cell + 1]; c += 64) {
-#pragma unroll
-      for (int b = 0; b < kXiWalls; ++b) {
-        if (w0 + b >= 2 * m) break;
-        const double* o = disc + ((int64_t)c * 2 * m + w0 + b) * 8;
-        for (int k = 0; k < 4; ++k) s[b][k] = dd_add(s[b][k], dd{o[k], o[4 + k]});
+      for (int u = 0; u < kXiBatch; ++u) {
+        const double* o = disc + ((int64_t)(c + u) * 2 * m + wpt) * 8;
+        hi[u] = o[k];
+        lo[u] = o[4 + k];
       }
-    }
 #pragma unroll
-    for (int b = 0; b < kXiWalls; ++b)
-      for (int k = 0; k < 4; ++k) s[b][k] = dd_wave_sum(s[b][k]);
-    if (lane == 0) {
-      for (int b = 0; b < kXiWalls && w0 + b < 2 * m; ++b) {
-        const int wpt = w0 + b;
-        const bool onD = wpt >= m;
-        const int q = onD ? wpt - m : wpt;
-        const int base = onD ? 4 * m : 0;
-        const double l = onD ? l1 : l2;
-        const double g0[4] = {0.0, 0.0, -Fs[0] / (2.0 * l), -Fs[1] / (2.0 * l)};
-        for (int k = 0; k < 4; ++k) {   // g0 - g, rounded once
-          const dd v = dd_add(dd{g0[k], 0.0}, dd{-s[b][k].hi, -s[b][k].lo});
-          gt[base + k * m + q] = v.hi + v.lo;
-        }
-      }
+      for (int u = 0; u < kXiBatch; ++u) sum = dd_add(sum, dd{hi[u], lo[u]});
     }
+    for (; c < c1; ++c) {
+      const double* o = disc + ((int64_t)c * 2 * m + wpt) * 8;
+      sum = dd_add(sum, dd{o[k], o[4 + k]});
+    }
+    const bool onD = wpt >= m;
+    const int q = onD ? wpt - m : wpt;
+    const int base = onD ? 4 * m : 0;
+    const double l = onD ? l1 : l2;
+    const double g0 = k < 2 ? 0.0 : -Fs[k - 2] / (2.0 * l);
+    const dd v = dd_add(dd{g0, 0.0}, dd{-sum.hi, -sum.lo});   // g0 - g, rounded once
+    gt[base + k * m + q] = v.hi + v.lo;
   }
   __syncthreads();
-  // kXiRows rows of Q+ per wave, lanes over the 8m entries of each; compensated dot products
-  for (int i0 = (threadIdx.x >> 6) * kXiRows; i0 < 2 * M; i0 += nw * kXiRows) {
-    dd s[kXiRows];
+  // rows of Q+: S segments per row (2M S <= threads), compensated dot products
+  const int rows = 2 * M, n8 = 8 * m;
+  const int S = rows >= kXiThreads ? 1 : kXiThreads / rows;
+  const int seg = (n8 + S - 1) / S;
+  for (int t = threadIdx.x; t < rows * S; t += blockDim.x) {
+    const int i = t / S, j = t - i * S;
+    const int r0 = j * seg, r1 = min(n8, r0 + seg);
+    const double* qrow = Qp + (int64_t)i * n8;
+    dd sum = {0, 0};
+    int r = r0;
+    for (; r + kXiBatch <= r1; r += kXiBatch) {
+      double qv[kXiBatch];
 #pragma unroll
-    for (int b = 0; b < kXiRows; ++b) s[b] = dd{0, 0};
-    for (int r = lane; r < 8 * m; r += 64) {
-      const double gr = gt[r];
+      for (int u = 0; u < kXiBatch; ++u) qv[u] = qrow[r + u];
 #pragma unroll
-      for (int b = 0; b < kXiRows; ++b)
-        if (i0 + b < 2 * M) s[b] = dd_fma(s[b], Qp[(int64_t)(i0 + b) * 8 * m + r], gr);
+      for (int u = 0; u < kXiBatch; ++u) sum = dd_fma(sum, qv[u], gt[r + u]);
     }
-#pragma unroll
-    for (int b = 0; b < kXiRows; ++b) s[b] = dd_wave_sum(s[b]);
-    if (lane == 0)
-      for (int b = 0; b < kXiRows && i0 + b < 2 * M; ++b) xi[i0 + b] = s[b].hi + s[b].lo;
+    for (; r < r1; ++r) sum = dd_fma(sum, qrow[r], gt[r]);
+    part[2 * t] = sum.hi;
+    part[2 * t + 1] = sum.lo;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < rows; i += blockDim.x) {
+    dd sum = {0, 0};
+    for (int j = 0; j < S; ++j) sum = dd_add(sum, dd{part[2 * (i * S + j)], part[2 * (i * S + j) + 1]});
+    xi[i] = sum.hi + sum.lo;
   }
 }
 
