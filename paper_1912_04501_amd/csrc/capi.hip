@@ -1365,6 +1365,7 @@ void build_fmm_plan(spm_handle* h) {
   ensure(h, F.bsrc, nbox);
   ensure(h, F.lists, lists.size());
   ensure(h, F.fact, 2 * p);
+  ensure(h, F.m2l_tab, (size_t)49 * 2 * p * 2);
   ensure(h, F.Mx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.Lx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.one_block, 2);
@@ -1379,10 +1380,11 @@ void build_fmm_plan(spm_handle* h) {
   upload(h, F.bsrc, bsrc.data(), nbox * sizeof(int32_t));
   upload(h, F.lists, lists.data(), lists.size() * sizeof(int32_t));
   upload(h, F.fact, fact.data(), fact.size() * sizeof(double));
+  F.p = p;
+  launch_fmm_tables(h);
   const int32_t one_block[2] = {0, 1};
   upload(h, F.one_block, one_block, sizeof(one_block));
   mark("upload");
-  F.p = p;
   F.L = L;
   F.D0 = D0;
   F.c0x = c0x;

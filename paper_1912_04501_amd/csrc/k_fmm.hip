@@ -65,6 +65,7 @@ struct FmmArgs {
   const double *sx, *sy, *fs1, *fs2;
   const int32_t *leaf_s, *bsrc;
   const double* fact;
+  const cx* m2l_tab;               // [49][2][p] M2L scalings per displacement
   cx *Mx, *Lx;                     // [box][3][p]
 };
 
@@ -196,10 +197,36 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
 // local expansions from the interaction lists, every level in one launch (written, not added).
 // The list (at most 27 source boxes with sources) is formed first; the next box's multipole is
 // loaded into registers while the current one is summed.
+// M2L: one wavefront per target box, lane l (< p) holds term l of its local expansions. Per
+// source box the three multipoles are scaled by rho^k / k! into LDS, lane l takes the Hankel sum
+// over k with (k + l)! and scales it by (-1)^l rho^(l+1) / (h l!). rho = h / (c_t - c_s) depends
+// only on the integer displacement of the two boxes in box units (one of 7 x 7), so both scalings
+// come from per-displacement tables built once per plan; the next box's multipoles and table
+// entries are loaded while the current sum runs.
+constexpr int kM2lMaxP = 64;
+
+// tab[(2 d) p + k] = rho^k / k!, tab[(2 d + 1) p + k] = (-1)^k rho^(k+1) / k!, rho = 1 / D for the
+// displacement D = (c_t - c_s) / h = (d % 7 - 3) + i (d / 7 - 3); zero for the 3 x 3 neighbours.
+__global__ __launch_bounds__(64) void k_fmm_m2l_tables(int p, const double* __restrict__ fact, cx* __restrict__ tab) {
+  const int d = blockIdx.x, k = threadIdx.x;
+  if (k >= p) return;
+  const int ex = d % 7 - 3, ey = d / 7 - 3;
+  cx sk = {0.0, 0.0}, gk = {0.0, 0.0};
+  if (abs(ex) > 1 || abs(ey) > 1) {
+    const cx rho = cdiv({1.0, 0.0}, {(double)ex, (double)ey});
+    const cx rk = cpow(rho, k);
+    sk = rk * (1.0 / fact[k]);
+    gk = rk * rho * (((k & 1) ? -1.0 : 1.0) / fact[k]);
+  }
+  tab[(2 * d) * p + k] = sk;
+  tab[(2 * d + 1) * p + k] = gk;
+}
+
 __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __restrict__ list) {
   __shared__ cx bs[3][64];
   __shared__ double fs[128];
   __shared__ int64_t srcs[27];
+  __shared__ int dsp[27];
   __shared__ int nsrc;
   const int64_t gid = list[blockIdx.x];
   int l = 2;
@@ -208,7 +235,7 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __rest
   const int n = 1 << l;
   const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> l);
   const cx c = box_center(a, l, loc);
-  const double h = a.D0 / n;
+  const double ih = n / a.D0;
   const int k = threadIdx.x, p = a.p;
   for (int i = k; i < 2 * p; i += 64) fs[i] = a.fact[i];
   if (k == 0) {
@@ -220,38 +247,44 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __rest
           const int bx = 2 * qx + (ch & 1), by = 2 * qy + (ch >> 1);
           if (abs(bx - ix) <= 1 && abs(by - iy) <= 1) continue;
           const int64_t sloc = (int64_t)by * n + bx;
-          if (a.bsrc[box_off(l) + sloc] != 0) srcs[cnt++] = sloc;
+          if (a.bsrc[box_off(l) + sloc] != 0) {
+            srcs[cnt] = sloc;
+            dsp[cnt] = (iy - by + 3) * 7 + (ix - bx + 3);
+            ++cnt;
+          }
         }
     nsrc = cnt;
   }
   __syncthreads();
   const int ns = nsrc;
+  const cx* Mb = a.Mx + box_off(l) * 3 * p;
   cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
-  cx nA = {0, 0}, nB = {0, 0}, nC = {0, 0};
+  cx nA = {0, 0}, nB = {0, 0}, nC = {0, 0}, nS = {0, 0}, nG = {0, 0};
   if (ns > 0 && k < p) {
-    const cx* m = a.Mx + (box_off(l) + srcs[0]) * 3 * p;
+    const cx* m = Mb + srcs[0] * 3 * p;
     nA = m[k];
     nB = m[p + k];
     nC = m[2 * p + k];
+    nS = a.m2l_tab[(2 * dsp[0]) * p + k];
+    nG = a.m2l_tab[(2 * dsp[0] + 1) * p + k];
   }
   for (int i = 0; i < ns; ++i) {
-    const int64_t sloc = srcs[i];
-    const cx cs = box_center(a, l, sloc);
-    const cx rho = cdiv({h, 0.0}, c - cs);
-    const cx rk = cpow(rho, k);
+    const cx cs = box_center(a, l, srcs[i]);
+    const cx sk = nS, g = nG * ih;
     __syncthreads();                       // the previous box's sums are done with bs
     if (k < p) {
-      const cx sc = rk * (1.0 / fs[k]);
-      bs[0][k] = nA * sc;
-      bs[1][k] = nB * sc;
-      bs[2][k] = nC * sc;
+      bs[0][k] = nA * sk;
+      bs[1][k] = nB * sk;
+      bs[2][k] = nC * sk;
     }
     __syncthreads();
-    if (i + 1 < ns && k < p) {             // prefetch the next box's multipole
-      const cx* m = a.Mx + (box_off(l) + srcs[i + 1]) * 3 * p;
+    if (i + 1 < ns && k < p) {             // the next box's multipoles and scalings
+      const cx* m = Mb + srcs[i + 1] * 3 * p;
       nA = m[k];
       nB = m[p + k];
       nC = m[2 * p + k];
+      nS = a.m2l_tab[(2 * dsp[i + 1]) * p + k];
+      nG = a.m2l_tab[(2 * dsp[i + 1] + 1) * p + k];
     }
     if (k < p) {
       cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
@@ -261,7 +294,6 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __rest
         sB = cmac(sB, bs[1][m], fm);
         sC = cmac(sC, bs[2][m], fm);
       }
-      const cx g = rk * rho * (((k & 1) ? -1.0 : 1.0) / (h * fs[k]));
       sA = sA * g;
       oA = oA + sA;
       oB = oB + sB * g;
@@ -538,6 +570,7 @@ FmmArgs args(spm_handle* h) {
   a.leaf_s = F.leaf_s;
   a.bsrc = F.bsrc;
   a.fact = F.fact;
+  a.m2l_tab = reinterpret_cast<const cx*>(F.m2l_tab);
   a.Mx = reinterpret_cast<cx*>(F.Mx);
   a.Lx = reinterpret_cast<cx*>(F.Lx);
   return a;
@@ -598,6 +631,13 @@ void launch_fmm_points(spm_handle* h, int64_t nt, const double* xt, const double
 void launch_fmm_velocities(spm_handle* h, double* near3) {
   launch_fmm_upward(h);
   k_fmm_velocities<<<h->geo.No, 64, 0, h->stream>>>(args(h), h->geo, h->cfg.mu, near3);
+  SPM_HIP_CHECK(hipGetLastError());
+}
+
+void launch_fmm_tables(spm_handle* h) {
+  const FmmPlan& F = h->fmm;
+  if (F.p < 1 || F.p > kM2lMaxP) throw ApiError(SPM_EINVAL, "FMM order must be at most 64");
+  k_fmm_m2l_tables<<<49, 64, 0, h->stream>>>(F.p, F.fact, reinterpret_cast<cx*>(F.m2l_tab));
   SPM_HIP_CHECK(hipGetLastError());
 }
 

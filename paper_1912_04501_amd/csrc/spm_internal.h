@@ -416,6 +416,7 @@ struct FmmPlan {
   std::vector<int64_t> seg;               // list segments: P2M, M2M levels L-1..2, M2L, L2L levels 3..L,
                                           // target leaves
   double* fact = nullptr;                 // [2p] factorials
+  double* m2l_tab = nullptr;              // [49 x 2 x p] complex M2L scalings per box displacement
   double *Mx = nullptr, *Lx = nullptr;    // [boxes x 3 x p] complex multipole / local expansions
   int32_t* one_block = nullptr;           // {0, 1}: the combine step reads one block of all N nodes, one slot
   double* vnear = nullptr;                // [3 No] near-image velocity and vorticity at the centres
@@ -625,6 +626,7 @@ void launch_mu_eff_contour(spm_handle* h, int m, double* mu_eff);
 // FMM near sum (k_fmm.hip): plan from the device node positions; evaluation into out [2N]
 void build_fmm_plan(spm_handle* h);
 void launch_fmm(spm_handle* h, double* out);
+void launch_fmm_tables(spm_handle* h);   // per-displacement M2L scalings (once per plan)
 void launch_fmm_velocities(spm_handle* h, double* near3);
 void launch_fmm_points(spm_handle* h, int64_t nt, const double* xt, const double* yt, double* u, double* p);
 void launch_gap(spm_handle* h, double* gap_host, int32_t* overlap_host);
