@@ -218,8 +218,23 @@ __global__ __launch_bounds__(1024) void k_gauss_jordan(const ShapeDesc* __restri
   if (t == 0) status[blockIdx.x] = bad;
 }
 
-// inv[ioff + perm[i] m + r] = (float) X[r][i]: column i of X is column perm[i] of B^-1
-__global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* __restrict__ work,
+// Row segments of a 2n x 2n inverse: segment y holds nodes [y nk, y nk + kn) (kn = min(nk, n - y nk),
+// nk = ceil(n / R) rounded up to even), i.e. rows k and n + k of the inverse for those nodes. Storage is
+// by segment, each segment column-major over its own 2 kn rows (first the kn rows k, then the kn rows
+// n + k), so that the workgroup applying a segment streams one contiguous region:
+//   element (r, c), r = k or n + k with k in segment y: ioff + y (2 nk) m + c (2 kn) + (r < n ? 0 : kn) + k - y nk.
+__host__ __device__ __forceinline__ int precond_seg_nodes(int n, int R) { return 2 * ((n + 2 * R - 1) / (2 * R)); }
+
+__device__ __forceinline__ int64_t precond_index(int n, int R, int r, int c) {
+  const int m = 2 * n, nk = precond_seg_nodes(n, R);
+  const int k = r < n ? r : r - n;
+  const int y = k / nk, k0 = y * nk;
+  const int kn = min(nk, n - k0);
+  return (int64_t)y * 2 * nk * m + (int64_t)c * 2 * kn + (r < n ? 0 : kn) + (k - k0);
+}
+
+// element (r, perm[i]) of the inverse = (float) X[r][i]: column i of X is column perm[i] of B^-1
+__global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* __restrict__ work, int R,
                                 float* __restrict__ inv) {
   const ShapeDesc d = sh[blockIdx.y];
   const int m = 2 * d.n;
@@ -227,17 +242,16 @@ __global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* 
   if (i >= m) return;
   const double* X = work + d.woff;
   const int32_t* perm = reinterpret_cast<const int32_t*>(X + (int64_t)m * m);
-  const int64_t c = perm[i];
-  for (int r = threadIdx.x; r < m; r += blockDim.x) inv[d.ioff + c * m + r] = (float)X[(int64_t)r * m + i];
+  const int c = perm[i];
+  for (int r = threadIdx.x; r < m; r += blockDim.x) inv[d.ioff + precond_index(d.n, R, r, c)] = (float)X[(int64_t)r * m + i];
 }
 
 // Blocks (particle, row segment): out = R (B^-1 (R^T v)) on the particle's nodes, segment y
 // producing nodes [y nk, (y + 1) nk) (rows k and n + k of the 2n x 2n inverse, nk = ceil(n / R)
 // rounded up to even), so that small particle counts still spread over the chip. Particles of
-// inactive cells are skipped when active is given. The inverse is column-major and n is even, so
-// the block's rows form two contiguous ranges of even length read as pairs (8-byte loads); they are
-// split into S = blockDim / nk column groups whose lanes run over consecutive row pairs. The S
-// partial rows are summed in a fixed order.
+// inactive cells are skipped when active is given. The segment's 2 kn rows are contiguous in every
+// column (kn and n even), read as pairs (8-byte loads); the columns are split into S = blockDim / nk
+// groups whose lanes run over consecutive row pairs. The S partial rows are summed in a fixed order.
 __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __restrict__ pshape,
                                                         const int64_t* __restrict__ ioff,
                                                         const float* __restrict__ inv,
@@ -248,7 +262,7 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
   const int q = blockIdx.x;
   if (active && active[g.pcell[q]] == 0) return;
   const int n = g.pn[q], m = 2 * n;
-  const int nk = 2 * ((n + 2 * R - 1) / (2 * R));
+  const int nk = precond_seg_nodes(n, R);
   const int k0 = blockIdx.y * nk;
   if (k0 >= n) return;
   const int kn = min(nk, n - k0);            // even: n and k0 are
@@ -261,17 +275,28 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
     vb[n + k] = -st * a + ct * b;
   }
   __syncthreads();
-  const float2* M2 = reinterpret_cast<const float2*>(inv + ioff[pshape[q]]);
+  const float2* M2 = reinterpret_cast<const float2*>(inv + ioff[pshape[q]] + (int64_t)blockIdx.y * 2 * nk * m);
   const int pairs = nk;                      // row pairs of the block: nk / 2 per range, two ranges
   const int S = max(1, (int)blockDim.x / pairs);
   const int grp = threadIdx.x / pairs, rp = threadIdx.x % pairs;
   const int half = nk / 2;
   const int lk = 2 * (rp < half ? rp : rp - half);   // first node of the pair within the segment
   if (grp < S && lk < kn) {
-    const int r = (rp < half ? 0 : n) + k0 + lk;       // even row of the inverse
+    const int rr = (rp < half ? 0 : kn) + lk;          // even row within the segment
     double a0 = 0.0, a1 = 0.0;
-    for (int c = grp; c < m; c += S) {
-      const float2 w = M2[((int64_t)c * m + r) >> 1];
+    int c = grp;
+    for (; c + 3 * S < m; c += 4 * S) {   // four columns' loads in flight, summed in column order
+      float2 w[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) w[u] = M2[((int64_t)(c + u * S) * 2 * kn + rr) >> 1];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a0 = fma((double)w[u].x, vb[c + u * S], a0);
+        a1 = fma((double)w[u].y, vb[c + u * S], a1);
+      }
+    }
+    for (; c < m; c += S) {
+      const float2 w = M2[((int64_t)c * 2 * kn + rr) >> 1];
       a0 = fma((double)w.x, vb[c], a0);
       a1 = fma((double)w.y, vb[c], a1);
     }
@@ -290,6 +315,11 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
   }
 }
 
+// Row segments per particle: about 1,024 apply workgroups in all, at most 8 per particle.
+static int precond_segments(const spm_handle* h) {
+  return std::max(1, std::min({8, (1024 + h->geo.No - 1) / h->geo.No, h->geo.nmax}));
+}
+
 // Builds the inverses of the shapes listed in h->pc (host keys), in batches whose
 // [B | I] work arrays stay below ~1 GB.
 void build_precond(spm_handle* h) {
@@ -299,6 +329,7 @@ void build_precond(spm_handle* h) {
                                    " nodes per particle");
   const int S = (int)P.keys.size();
   auto nodes = [&](int s) { return (int32_t)P.keys[s][5]; };
+  P.segs = precond_segments(h);
   std::vector<int64_t> ioff(S);
   int64_t total = 0;
   for (int s = 0; s < S; ++s) {
@@ -336,7 +367,7 @@ void build_precond(spm_handle* h) {
     SPM_HIP_CHECK(hipGetLastError());
     k_gauss_jordan<<<nb, 1024, 0, h->stream>>>(P.desc, P.work, P.status);
     SPM_HIP_CHECK(hipGetLastError());
-    k_store_inverse<<<dim3((unsigned)(2 * maxn), (unsigned)nb), 256, 0, h->stream>>>(P.desc, P.work, P.inv);
+    k_store_inverse<<<dim3((unsigned)(2 * maxn), (unsigned)nb), 256, 0, h->stream>>>(P.desc, P.work, P.segs, P.inv);
     SPM_HIP_CHECK(hipGetLastError());
     std::vector<int32_t> st(nb);
     SPM_HIP_CHECK(hipMemcpyAsync(st.data(), P.status, nb * sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
@@ -355,8 +386,8 @@ void launch_precond_apply(spm_handle* h, const double* v, double* out, bool with
   if (h->geo.nmax > kMaxNodesStaged)
     throw ApiError(SPM_EINVAL, "the block preconditioner needs at most " + std::to_string(kMaxNodesStaged) +
                                    " nodes per particle");
-  // row segments per particle: about 1,024 blocks in all, at most 8 per particle
-  const int R = std::max(1, std::min({8, (1024 + h->geo.No - 1) / h->geo.No, h->geo.nmax}));
+  // the row segments the inverses were stored with
+  const int R = P.segs;
   k_precond_apply<<<dim3(h->geo.No, R), 1024, 0, h->stream>>>(h->geo, P.pshape, P.ioff, P.inv,
                                                               with_active ? h->kr.active : nullptr, R, v, out);
   SPM_HIP_CHECK(hipGetLastError());

@@ -509,8 +509,9 @@ struct Precond {
   size_t pshape_cap = 0;
   int64_t* ioff = nullptr;      // [shapes] offset of each inverse
   size_t ioff_cap = 0;
-  float* inv = nullptr;         // inverses, (2n)^2 floats each, column-major
+  float* inv = nullptr;         // inverses, (2n)^2 floats each, by row segment (k_precond.hip)
   size_t inv_cap = 0;
+  int32_t segs = 1;             // row segments of every inverse (the apply's grid.y)
   double* work = nullptr;       // build workspace
   size_t work_cap = 0;
   ShapeDesc* desc = nullptr;
