@@ -321,8 +321,8 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
   const double x0 = wx_all[(int64_t)cell * 2 * L.m + wpt], y0 = wy_all[(int64_t)cell * 2 * L.m + wpt];
   const double nx = onD ? 0.0 : CL.nLx, ny = onD ? 1.0 : CL.nLy;
   // far column/row (-2 along the lattice vector across the wall pair) minus the near one (+1)
-  const double ax = onD ? CL.e2x : 1.0, ay = onD ? 1.0 : 0.0;   // across the wall pair
-  const double bx = onD ? 1.0 : CL.e2x, by = onD ? 0.0 : 1.0;   // along the wall
+  const double ax_ = onD ? CL.e2x : 1.0, ay_ = onD ? 1.0 : 0.0;   // across the wall pair
+  const double bx_ = onD ? 1.0 : CL.e2x, by_ = onD ? 0.0 : 1.0;   // along the wall
   const int64_t j0 = cs0[chunk], j1 = cs1[chunk];
   dd u1 = {0, 0}, u2 = {0, 0}, t1 = {0, 0}, t2 = {0, 0};
   for (int64_t j = j0 + threadIdx.x; j < j1; j += blockDim.x) {
@@ -338,21 +338,28 @@ __global__ __launch_bounds__(256) void k_disc(int64_t N, Lat L, const double* __
       nlo = sb > 0 ? 0 : -1;
       nhi = sb > 0 ? 1 : 0;
     }
+    // the rows of one source: their logarithms combine into one of the product of the squared-distance
+    // ratios, and the source's far-minus-near differences (all rows) are rounded once into the
+    // double-double sums
+    double ratio = 1.0, s1 = 0.0, s2 = 0.0, p1 = 0.0, p2 = 0.0;
     for (int n = nlo; n <= nhi; n += nstep) {
-      const double fx = yj + far * ax + n * bx, fy = zj + far * ay + n * by;
-      const double cx = yj + near * ax + n * bx, cy = zj + near * ay + n * by;
-      // the far-minus-near difference of one source is formed directly (one logarithm of the
-      // ratio of squared distances) and rounded once; the running sums are double-double
-      double v1, v2;
-      stokeslet_diff_uv(x0 - fx, y0 - fy, x0 - cx, y0 - cy, g1, g2, L.inv4pimu, v1, v2);
-      u1 = dd_add_d(u1, v1);
-      u2 = dd_add_d(u2, v2);
-      double p1 = 0, p2 = 0, q1 = 0, q2 = 0;
-      traction_uv(x0 - fx, y0 - fy, nx, ny, g1, g2, p1, p2);
-      traction_uv(x0 - cx, y0 - cy, nx, ny, g1, g2, q1, q2);
-      t1 = dd_add_d(t1, p1 - q1);
-      t2 = dd_add_d(t2, p2 - q2);
+      const double ax = x0 - (yj + far * ax_ + n * bx_), ay = y0 - (zj + far * ay_ + n * by_);
+      const double bxn = x0 - (yj + near * ax_ + n * bx_), byn = y0 - (zj + near * ay_ + n * by_);
+      const double a2 = ax * ax + ay * ay, b2 = bxn * bxn + byn * byn;
+      const double ia2 = rcp64(a2), ib2 = rcp64(b2);
+      ratio *= a2 * ib2;
+      const double af = (ax * g1 + ay * g2) * ia2, bf = (bxn * g1 + byn * g2) * ib2;
+      s1 += ax * af - bxn * bf;
+      s2 += ay * af - byn * bf;
+      const double cf = (ax * nx + ay * ny) * af * ia2, cn = (bxn * nx + byn * ny) * bf * ib2;
+      p1 += cf * ax - cn * bxn;
+      p2 += cf * ay - cn * byn;
     }
+    const double lg = -0.5 * log(ratio);
+    u1 = dd_add_d(u1, L.inv4pimu * (lg * g1 + s1));
+    u2 = dd_add_d(u2, L.inv4pimu * (lg * g2 + s2));
+    t1 = dd_add_d(t1, -(1.0 / kPi) * p1);
+    t2 = dd_add_d(t2, -(1.0 / kPi) * p2);
   }
   u1 = dd_block_sum(u1, sc);
   u2 = dd_block_sum(u2, sc);
