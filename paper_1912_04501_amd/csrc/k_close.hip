@@ -153,7 +153,6 @@ __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets
     // pass 1: den and v for the three densities; plain near-sum terms of this image
     double dr = 0, di = 0, v[6] = {0, 0, 0, 0, 0, 0};
     double p1 = 0, p2 = 0;
-    float p1f = 0.f, p2f = 0.f;
     for (int k = lane; k < n; k += 64) {
       const int64_t kk = o + k;
       const cplx W = {g.xpy[kk] / (double)n, -g.xpx[kk] / (double)n};
@@ -194,8 +193,6 @@ __global__ __launch_bounds__(256) void k_close_apply(int64_t N, int32_t ntargets
         p2 += (double)a2;
       }
     }
-    (void)p1f;
-    (void)p2f;
     dr = wave_sum(dr);
     di = wave_sum(di);
 #pragma unroll
