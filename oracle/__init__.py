@@ -40,9 +40,11 @@ Map of the method (citations are to the paper's sections and equations):
                    (forward, back-propagation, Adam) and the learned warm start
 
 Parity unpinned (consistent by construction only): the absolute velocity gauge
-away from symmetric configurations, the exact truncation of the proxy
-least-squares pseudo-inverse, and the trained network's predictions (their only
-ground truth is the solver's own density).
+away from symmetric configurations, and the trained network's predictions (their
+only ground truth is the solver's own density). The truncation of the proxy
+least-squares pseudo-inverse is pinned to Theorem EBVP: the modes it drops carry
+constant fields spanning both velocity gauges and the pressure gauge, and every
+mode it keeps is further from a constant field.
 """
 from .geometry import Geometry, build_geometry, reduce_skew  # noqa: F401
 from .operator import Problem, make_problem  # noqa: F401

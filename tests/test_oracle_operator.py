@@ -297,6 +297,40 @@ def test_translation_invariance(kw, tol):
     assert np.abs(out[0][0] - out[1][0]).max() < 3 * tol
 
 
+@pytest.mark.parametrize("skew", [0.0, 0.25, 0.5])
+def test_pinv_drops_exactly_the_gauge_modes(skew):
+    """Theorem EBVP: the empty-box problem determines u and p up to a constant velocity and a
+    constant pressure, nothing else. The singular modes of Q (32 circle proxies, m = 24) that the
+    oracle's pseudo-inverse leaves out of its range are read off from Q+ Q itself, not from its
+    rule. There are three of them; the proxy field of each is constant across the cell to 1e-5 of
+    its size; their constants span both velocity gauges and the pressure gauge; and every mode
+    kept is further from a constant field than any mode dropped (a truncation that dropped a real
+    mode, or kept a gauge mode, fails one of these)."""
+    from oracle.kernels import pressure_apply
+    cell = _Cell((skew, 1.0))
+    Wl = periodizer.walls(cell, 24)
+    P = periodizer.proxies(cell, 32, 1.5)
+    Q = periodizer.build_Q(cell, Wl, P, 1.0)
+    _, s, Vt = np.linalg.svd(Q, full_matrices=False)
+    kept = np.linalg.norm(periodizer.pinv_gauge_truncated(Q) @ Q @ Vt.T, axis=0)
+    assert np.all((kept > 1 - 1e-6) | (kept < 1e-6))
+    drop = kept < 0.5
+    assert drop.sum() == 3
+    t = (np.arange(12) + 0.5) / 12 - 0.5
+    X = (t[:, None, None] * cell.e1 + t[None, :, None] * cell.e2).reshape(-1, 2)
+    res, const = np.zeros(len(s)), np.zeros((len(s), 3))
+    for k in range(len(s)):
+        u = periodizer.correction_velocity(P, Vt[k], X, 1.0)
+        p = pressure_apply(X[:, None, :] - P[None], periodizer.xi_to_forces(Vt[k])[None]).sum(1)
+        z = np.stack([u[:, 0], u[:, 1], p], axis=1)
+        const[k] = z.mean(0)
+        res[k] = np.linalg.norm(z - const[k]) / np.linalg.norm(z)
+    print(f"[skew {skew}] dropped: nonconstant part <= {res[drop].max():.1e}; kept: >= {res[~drop].min():.1e}")
+    assert res[drop].max() < 1e-5
+    assert np.linalg.cond(const[drop]) < 100
+    assert res[~drop].min() > res[drop].max()
+
+
 def test_operator_nullspace_structure():
     """1/2 I + K has a 3 N_o-dimensional near-null space (Sec. 5); the completion L
     removes it (P9)."""
