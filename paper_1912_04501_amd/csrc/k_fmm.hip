@@ -24,7 +24,8 @@
 // Interaction lists are the usual ones (children of the parent's neighbours that are not
 // neighbours); leaves evaluate their 3x3 neighbourhood directly, where the pair at zero
 // distance (the target's own node) adds nothing. Every pass is deterministic: one wavefront per box (three per
-// leaf in the evaluation), lanes over expansion terms, fixed loop orders.
+// leaf in the evaluation), lanes over expansion terms (in the multipole pass over runs of terms and source
+// phases), fixed loop orders.
 #include "spm_internal.h"
 
 namespace spm {
@@ -86,58 +87,91 @@ __global__ __launch_bounds__(256) void k_fmm_gather(int64_t ns, const int32_t* _
   fs2[k] = f2[j];
 }
 
-// multipoles of the leaves with sources; lane k holds term k. Sources go 32 at a time: lane t
-// builds source t's power table in LDS (w^i and w^(8 i), i < 8, by repeated products), then term
-// k takes w^k = w^(8 (k >> 3)) w^(k & 7) with one product.
-constexpr int kP2mGroup = 32;
+// multipoles of the leaves with sources. The p terms are cut into eight runs of CS = ceil(p / 8)
+// consecutive powers; the eight lanes of a run take every eighth source of the leaf, so that all
+// 64 lanes work, each on CS terms of its sources. Sources go 64 at a time: lane t stages source
+// t's w = (z_j - c)/h, q_j, q_j conj(z_j - c) and the run starts w^(CS r), r < 8, in LDS; a lane of
+// run r starts from w^(CS r) and steps by w. The eight partial sums of a term are then added in
+// lane order through LDS.
+constexpr int kP2mRuns = 8, kP2mPhases = 8;   // runs of terms x source phases = 64 lanes
+template <int CS>
 __global__ __launch_bounds__(64) void k_fmm_p2m(FmmArgs a, const int32_t* __restrict__ list) {
-  __shared__ cx tab[kP2mGroup][16];
-  __shared__ cx qs[kP2mGroup], ds[kP2mGroup];
+  constexpr int kStage = 64 * (3 + kP2mRuns), kRed = 64 * 3 * CS;
+  __shared__ cx sh[kStage > kRed ? kStage : kRed];
+  cx* const sw = sh;              // w of source t
+  cx* const sq = sh + 64;         // q
+  cx* const sqd = sh + 128;       // q conj(d)
+  cx* const sp = sh + 192;        // w^(CS r) at [t kP2mRuns + r]
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(a.L);
   const cx c = box_center(a, a.L, loc);
   const double ih = (double)(1 << a.L) / a.D0;
-  const int k = threadIdx.x;
-  cx A = {0, 0}, B = {0, 0}, C = {0, 0};
+  const int lane = threadIdx.x, run = lane / kP2mPhases, ph = lane % kP2mPhases;
+  cx A[CS], B[CS], C[CS];
+#pragma unroll
+  for (int i = 0; i < CS; ++i) A[i] = B[i] = C[i] = {0.0, 0.0};
   const int32_t s0 = a.leaf_s[loc], s1 = a.leaf_s[loc + 1];
-  for (int32_t j0 = s0; j0 < s1; j0 += kP2mGroup) {
-    const int32_t j = j0 + k;
-    if (k < kP2mGroup && j < s1) {
+  for (int32_t j0 = s0; j0 < s1; j0 += 64) {
+    const int ng = min(64, (int)(s1 - j0));
+    if (lane < ng) {
+      const int32_t j = j0 + lane;
       const cx d = {a.sx[j] - c.r, a.sy[j] - c.i};
-      const cx w = d * ih;
+      const cx w = d * ih, q = {a.fs1[j], a.fs2[j]};
+      sw[lane] = w;
+      sq[lane] = q;
+      sqd[lane] = q * conj(d);
+      cx wc = w;
+#pragma unroll
+      for (int e = 1; e < CS; ++e) wc = wc * w;
       cx pw = {1.0, 0.0};
-      for (int i = 0; i < 8; ++i) {
-        tab[k][i] = pw;
-        pw = pw * w;
-      }
-      const cx w8 = pw;
-      pw = {1.0, 0.0};
-      for (int i = 0; i < 8; ++i) {
-        tab[k][8 + i] = pw;
-        pw = pw * w8;
-      }
-      qs[k] = {a.fs1[j], a.fs2[j]};
-      ds[k] = conj(d);
-    }
-    __syncthreads();
-    if (k < a.p) {
-      const int ns = min(kP2mGroup, (int)(s1 - j0));
-      for (int t = 0; t < ns; ++t) {
-        const cx wk = tab[t][8 + (k >> 3)] * tab[t][k & 7];
-        const cx q = qs[t];
-        const cx qw = q * wk;
-        A = A + qw;
-        B = cmac(B, conj(q), wk);
-        C = cmac(C, qw, ds[t]);
+#pragma unroll
+      for (int r = 0; r < kP2mRuns; ++r) {
+        sp[lane * kP2mRuns + r] = pw;
+        pw = pw * wc;
       }
     }
     __syncthreads();
+    for (int t = ph; t < ng; t += kP2mPhases) {
+      const cx w = sw[t], q = sq[t], qd = sqd[t];
+      cx pw = sp[t * kP2mRuns + run];
+#pragma unroll
+      for (int i = 0; i < CS; ++i) {
+        A[i] = cmac(A[i], q, pw);
+        B[i] = cmac(B[i], conj(q), pw);
+        C[i] = cmac(C[i], qd, pw);
+        if (i + 1 < CS) pw = pw * w;
+      }
+    }
+    __syncthreads();   // the stage is rewritten next (or reused below)
   }
-  if (k < a.p) {
-    cx* out = a.Mx + gid * 3 * a.p;
-    out[k] = A;
-    out[a.p + k] = B;
-    out[2 * a.p + k] = C;
+  cx* const red = sh;             // lane's partials at [lane 3 CS + series CS + i]
+#pragma unroll
+  for (int i = 0; i < CS; ++i) {
+    red[lane * 3 * CS + i] = A[i];
+    red[lane * 3 * CS + CS + i] = B[i];
+    red[lane * 3 * CS + 2 * CS + i] = C[i];
+  }
+  __syncthreads();
+  for (int o = lane; o < 3 * a.p; o += 64) {
+    const int sr = o / a.p, k = o - sr * a.p;
+    const int r = k / CS, i = k - r * CS;
+    cx acc = {0.0, 0.0};
+    for (int f = 0; f < kP2mPhases; ++f) acc = acc + red[(r * kP2mPhases + f) * 3 * CS + sr * CS + i];
+    a.Mx[gid * 3 * a.p + o] = acc;
+  }
+}
+
+void launch_p2m(const FmmArgs& a, unsigned nb, const int32_t* list, hipStream_t st) {
+  switch ((a.p + kP2mRuns - 1) / kP2mRuns) {
+    case 1: k_fmm_p2m<1><<<nb, 64, 0, st>>>(a, list); break;
+    case 2: k_fmm_p2m<2><<<nb, 64, 0, st>>>(a, list); break;
+    case 3: k_fmm_p2m<3><<<nb, 64, 0, st>>>(a, list); break;
+    case 4: k_fmm_p2m<4><<<nb, 64, 0, st>>>(a, list); break;
+    case 5: k_fmm_p2m<5><<<nb, 64, 0, st>>>(a, list); break;
+    case 6: k_fmm_p2m<6><<<nb, 64, 0, st>>>(a, list); break;
+    case 7: k_fmm_p2m<7><<<nb, 64, 0, st>>>(a, list); break;
+    case 8: k_fmm_p2m<8><<<nb, 64, 0, st>>>(a, list); break;
+    default: throw ApiError(SPM_EINVAL, "FMM order must be between 1 and 64");
   }
 }
 
@@ -610,7 +644,7 @@ int launch_fmm_upward(spm_handle* h) {
                                                                          F.fs2);
   SPM_HIP_CHECK(hipGetLastError());
   int s = 0;
-  if (n_of(s)) k_fmm_p2m<<<n_of(s), 64, 0, h->stream>>>(a, list(s));
+  if (n_of(s)) launch_p2m(a, n_of(s), list(s), h->stream);
   SPM_HIP_CHECK(hipGetLastError());
   ++s;
   for (int l = F.L - 1; l >= 2; --l, ++s) {
