@@ -175,11 +175,17 @@ void launch_p2m(const FmmArgs& a, unsigned nb, const int32_t* list, hipStream_t 
   }
 }
 
+constexpr int kM2lMaxP = 64;   // largest expansion order (LDS and table sizes)
+
 // multipoles of level l from their children at level l + 1; the four children are staged in LDS
-// in one phase (their loads overlap)
+// in one phase (their loads overlap). Term k of a child is a sum of k + 1 products, so each child
+// takes sixteen lanes and its terms go to them in a snake order (rows of sixteen terms, every other
+// row reversed), which evens out the triangular sums; the children's terms are then added in child
+// order through LDS.
 __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t* __restrict__ list) {
-  __shared__ cx ac[4][3][64];
-  __shared__ cx tp[4][64];
+  constexpr int kRows = kM2lMaxP / 16;
+  __shared__ cx ac[4][3][kM2lMaxP];     // child multipoles times 2^-m / m!, then the child sums
+  __shared__ cx tp[4][kM2lMaxP];        // (child offset / parent side)^k / k!
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(l);
   const int n = 1 << l;
@@ -204,22 +210,46 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
     }
   }
   __syncthreads();
-  if (k < p) {
-    cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
-    const double fk = a.fact[k];
-    for (int ch = 0; ch < 4; ++ch) {
-      if (!has[ch]) continue;
+  const int ch = k >> 4, j = k & 15;
+  cx sum[kRows][3];
+  if (has[ch]) {
+#pragma unroll
+    for (int row = 0; row < kRows; ++row) {
+      const int kk = 16 * row + ((row & 1) ? 15 - j : j);
+      if (kk >= p) continue;
       cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
-      for (int m = 0; m <= k; ++m) {
-        const cx t = tp[ch][k - m];
+      for (int m = 0; m <= kk; ++m) {
+        const cx t = tp[ch][kk - m];
         sA = cmac(sA, ac[ch][0][m], t);
         sB = cmac(sB, ac[ch][1][m], t);
         sC = cmac(sC, ac[ch][2][m], t);
       }
-      sA = sA * fk;
+      const double fk = a.fact[kk];
+      sum[row][0] = sA * fk;
+      sum[row][1] = sB * fk;
+      sum[row][2] = sC * fk;
+    }
+  }
+  __syncthreads();   // every lane is done reading the staged multipoles
+  if (has[ch]) {
+#pragma unroll
+    for (int row = 0; row < kRows; ++row) {
+      const int kk = 16 * row + ((row & 1) ? 15 - j : j);
+      if (kk >= p) continue;
+      ac[ch][0][kk] = sum[row][0];
+      ac[ch][1][kk] = sum[row][1];
+      ac[ch][2][kk] = sum[row][2];
+    }
+  }
+  __syncthreads();
+  if (k < p) {
+    cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
+    for (int c4 = 0; c4 < 4; ++c4) {
+      if (!has[c4]) continue;
+      const cx sA = ac[c4][0][k];
       oA = oA + sA;
-      oB = oB + sB * fk;
-      oC = oC + sC * fk + conj(dch[ch]) * sA;
+      oB = oB + ac[c4][1][k];
+      oC = oC + ac[c4][2][k] + conj(dch[c4]) * sA;
     }
     cx* out = a.Mx + gid * 3 * p;
     out[k] = oA;
@@ -237,7 +267,6 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
 // only on the integer displacement of the two boxes in box units (one of 7 x 7), so both scalings
 // come from per-displacement tables built once per plan; the next box's multipoles and table
 // entries are loaded while the current sum runs.
-constexpr int kM2lMaxP = 64;
 
 // tab[(2 d) p + k] = rho^k / k!, tab[(2 d + 1) p + k] = (-1)^k rho^(k+1) / k!, rho = 1 / D for the
 // displacement D = (c_t - c_s) / h = (d % 7 - 3) + i (d / 7 - 3); zero for the 3 x 3 neighbours.
