@@ -261,12 +261,14 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
 // local expansions from the interaction lists, every level in one launch (written, not added).
 // The list (at most 27 source boxes with sources) is formed first; the next box's multipole is
 // loaded into registers while the current one is summed.
-// M2L: one wavefront per target box, lane l (< p) holds term l of its local expansions. Per
-// source box the three multipoles are scaled by rho^k / k! into LDS, lane l takes the Hankel sum
-// over k with (k + l)! and scales it by (-1)^l rho^(l+1) / (h l!). rho = h / (c_t - c_s) depends
-// only on the integer displacement of the two boxes in box units (one of 7 x 7), so both scalings
-// come from per-displacement tables built once per plan; the next box's multipoles and table
-// entries are loaded while the current sum runs.
+// M2L: one wavefront per target box. The source boxes go nb = 64 / ceil(p / 2) at a time (three at
+// 40 terms): their three multipoles, scaled by rho^k / k!, are staged in LDS, and lane (b, j) takes
+// the Hankel sums over k with (k + l)! of box b for the two output terms l = j and j + ceil(p / 2)
+// (each staged value feeds both), scaled by (-1)^l rho^(l+1) / (h l!). rho = h / (c_t - c_s)
+// depends only on the integer displacement of the two boxes in box units (one of 7 x 7), so both
+// scalings come from per-displacement tables built once per plan; the next round's multipoles and
+// table entries are loaded while the current sums run, and the lanes' partial expansions are added
+// over the boxes of a round in a fixed order at the end.
 
 // tab[(2 d) p + k] = rho^k / k!, tab[(2 d + 1) p + k] = (-1)^k rho^(k+1) / k!, rho = 1 / D for the
 // displacement D = (c_t - c_s) / h = (d % 7 - 3) + i (d / 7 - 3); zero for the 3 x 3 neighbours.
@@ -286,8 +288,9 @@ __global__ __launch_bounds__(64) void k_fmm_m2l_tables(int p, const double* __re
 }
 
 __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __restrict__ list) {
-  __shared__ cx bs[3][64];
-  __shared__ double fs[128];
+  __shared__ cx bs[3][2 * kM2lMaxP];   // scaled multipoles of the boxes of a round, [series][box p + k]
+  __shared__ cx red[3][64][2];         // per lane: its two terms' sums, then the reduction over boxes
+  __shared__ double fs[2 * kM2lMaxP];
   __shared__ int64_t srcs[27];
   __shared__ int dsp[27];
   __shared__ int nsrc;
@@ -299,9 +302,9 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __rest
   const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> l);
   const cx c = box_center(a, l, loc);
   const double ih = n / a.D0;
-  const int k = threadIdx.x, p = a.p;
-  for (int i = k; i < 2 * p; i += 64) fs[i] = a.fact[i];
-  if (k == 0) {
+  const int t = threadIdx.x, p = a.p;
+  for (int i = t; i < 2 * p; i += 64) fs[i] = a.fact[i];
+  if (t == 0) {
     const int px = ix >> 1, py = iy >> 1, np = n >> 1;
     int cnt = 0;
     for (int qy = max(py - 1, 0); qy <= min(py + 1, np - 1); ++qy)
@@ -321,53 +324,91 @@ __global__ __launch_bounds__(64) void k_fmm_m2l(FmmArgs a, const int32_t* __rest
   __syncthreads();
   const int ns = nsrc;
   const cx* Mb = a.Mx + box_off(l) * 3 * p;
-  cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
-  cx nA = {0, 0}, nB = {0, 0}, nC = {0, 0}, nS = {0, 0}, nG = {0, 0};
-  if (ns > 0 && k < p) {
-    const cx* m = Mb + srcs[0] * 3 * p;
-    nA = m[k];
-    nB = m[p + k];
-    nC = m[2 * p + k];
-    nS = a.m2l_tab[(2 * dsp[0]) * p + k];
-    nG = a.m2l_tab[(2 * dsp[0] + 1) * p + k];
-  }
-  for (int i = 0; i < ns; ++i) {
-    const cx cs = box_center(a, l, srcs[i]);
-    const cx sk = nS, g = nG * ih;
-    __syncthreads();                       // the previous box's sums are done with bs
-    if (k < p) {
-      bs[0][k] = nA * sk;
-      bs[1][k] = nB * sk;
-      bs[2][k] = nC * sk;
+  // lane (b, j): box b of the round, output terms j and j + hp
+  const int hp = (p + 1) / 2, nb = 64 / hp;
+  const int b = t / hp, j = t % hp;
+  const int l1 = j, l2 = j + hp;
+  const bool act = b < nb, has2 = act && l2 < p;
+  // staging slots of a round: slot q < nb p is term q % p of box q / p; lane t fills slots t and t + 64
+  cx pre[2][4];
+  auto fetch = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = t + 64 * u, bq = q / p, mq = q - bq * p;
+      if (q < nb * p && i0 + bq < ns) {
+        const cx* m = Mb + srcs[i0 + bq] * 3 * p;
+        pre[u][0] = m[mq];
+        pre[u][1] = m[p + mq];
+        pre[u][2] = m[2 * p + mq];
+        pre[u][3] = a.m2l_tab[(2 * dsp[i0 + bq]) * p + mq];
+      }
+    }
+  };
+  fetch(0);
+  cx oA1 = {0, 0}, oB1 = {0, 0}, oC1 = {0, 0}, oA2 = {0, 0}, oB2 = {0, 0}, oC2 = {0, 0};
+  for (int i0 = 0; i0 < ns; i0 += nb) {
+    __syncthreads();                       // the previous round's sums are done with bs
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int q = t + 64 * u, bq = q / p;
+      if (q < nb * p && i0 + bq < ns) {
+        bs[0][q] = pre[u][0] * pre[u][3];
+        bs[1][q] = pre[u][1] * pre[u][3];
+        bs[2][q] = pre[u][2] * pre[u][3];
+      }
     }
     __syncthreads();
-    if (i + 1 < ns && k < p) {             // the next box's multipoles and scalings
-      const cx* m = Mb + srcs[i + 1] * 3 * p;
-      nA = m[k];
-      nB = m[p + k];
-      nC = m[2 * p + k];
-      nS = a.m2l_tab[(2 * dsp[i + 1]) * p + k];
-      nG = a.m2l_tab[(2 * dsp[i + 1] + 1) * p + k];
-    }
-    if (k < p) {
-      cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
+    if (i0 + nb < ns) fetch(i0 + nb);      // the next round's multipoles and scalings
+    const int i = i0 + b;
+    if (act && i < ns) {
+      const cx* g2tab = a.m2l_tab + (2 * dsp[i] + 1) * p;
+      const cx g1 = g2tab[l1] * ih, g2 = has2 ? g2tab[l2] * ih : cx{0, 0};
+      const cx dc = conj(box_center(a, l, srcs[i]) - c);
+      const cx* x0 = bs[0] + b * p;
+      const cx* x1 = bs[1] + b * p;
+      const cx* x2 = bs[2] + b * p;
+      cx sA1 = {0, 0}, sB1 = {0, 0}, sC1 = {0, 0}, sA2 = {0, 0}, sB2 = {0, 0}, sC2 = {0, 0};
+      const int e2 = has2 ? l2 : l1;     // a lane without a second term repeats its first
       for (int m = 0; m < p; ++m) {
-        const double fm = fs[m + k];
-        sA = cmac(sA, bs[0][m], fm);
-        sB = cmac(sB, bs[1][m], fm);
-        sC = cmac(sC, bs[2][m], fm);
+        const double f1 = fs[m + l1], f2 = fs[m + e2];
+        const cx A = x0[m], B = x1[m], C = x2[m];
+        sA1 = cmac(sA1, A, f1);
+        sB1 = cmac(sB1, B, f1);
+        sC1 = cmac(sC1, C, f1);
+        sA2 = cmac(sA2, A, f2);
+        sB2 = cmac(sB2, B, f2);
+        sC2 = cmac(sC2, C, f2);
       }
-      sA = sA * g;
-      oA = oA + sA;
-      oB = oB + sB * g;
-      oC = oC + sC * g + conj(cs - c) * sA;
+      sA1 = sA1 * g1;
+      oA1 = oA1 + sA1;
+      oB1 = oB1 + sB1 * g1;
+      oC1 = oC1 + sC1 * g1 + dc * sA1;
+      sA2 = sA2 * g2;
+      oA2 = oA2 + sA2;
+      oB2 = oB2 + sB2 * g2;
+      oC2 = oC2 + sC2 * g2 + dc * sA2;
     }
   }
-  if (k < p) {
+  __syncthreads();
+  red[0][t][0] = oA1;
+  red[1][t][0] = oB1;
+  red[2][t][0] = oC1;
+  red[0][t][1] = oA2;
+  red[1][t][1] = oB2;
+  red[2][t][1] = oC2;
+  __syncthreads();
+  if (t < p) {                             // term t: the lanes (b, t % hp) in box order
+    const int jj = t < hp ? t : t - hp, w = t < hp ? 0 : 1;
+    cx oA = {0, 0}, oB = {0, 0}, oC = {0, 0};
+    for (int bb = 0; bb < nb; ++bb) {
+      oA = oA + red[0][bb * hp + jj][w];
+      oB = oB + red[1][bb * hp + jj][w];
+      oC = oC + red[2][bb * hp + jj][w];
+    }
     cx* out = a.Lx + gid * 3 * p;
-    out[k] = oA;
-    out[p + k] = oB;
-    out[2 * p + k] = oC;
+    out[t] = oA;
+    out[p + t] = oB;
+    out[2 * p + t] = oC;
   }
 }
 
