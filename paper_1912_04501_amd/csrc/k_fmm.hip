@@ -454,9 +454,12 @@ __global__ __launch_bounds__(64) void k_fmm_l2l(FmmArgs a, int l, const int32_t*
 }
 
 // three wavefronts per target leaf: the sources of the 3x3 neighbour leaves (three contiguous rows
-// of the sorted order, taken as one list) are staged through LDS 192 at a time and each wave takes
-// a third of every chunk; within a wave the leaf's targets (64 at a time) take 64 / n_t lanes each.
-// The wave and lane partial sums are added in a fixed order, then wave 0 adds the local expansion.
+// of the sorted order, taken as one list) are staged through LDS 192 at a time. The leaf's targets
+// go 64 at a time and a batch of n_t takes the whole block: each target floor(192 / n_t) threads,
+// which split every staged chunk of sources between them (about 95% of the threads work over the
+// leaves of a dense cell, against 76% with a third of every chunk per wave and floor(64 / n_t)
+// lanes per target). The threads' partial sums of a target are added in a fixed order, then wave 0
+// adds the local expansion.
 constexpr int kEvalWaves = 3;
 __global__ __launch_bounds__(64 * kEvalWaves) void k_fmm_eval(FmmArgs a, int64_t N, const int32_t* __restrict__ list,
                                                               const int32_t* __restrict__ leaf_t,
@@ -464,7 +467,7 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_fmm_eval(FmmArgs a, int64_t
                                                               double* __restrict__ out) {
   constexpr int B = 64 * kEvalWaves;
   __shared__ double shx[B], shy[B], sf1[B], sf2[B];
-  __shared__ double red1[kEvalWaves][64], red2[kEvalWaves][64];
+  __shared__ double red1[64 * kEvalWaves], red2[64 * kEvalWaves];
   const int64_t gid = list[blockIdx.x];
   const int64_t loc = gid - box_off(a.L);
   const int n = 1 << a.L;
@@ -473,7 +476,6 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_fmm_eval(FmmArgs a, int64_t
   const double h = a.D0 / n;
   const cx* Le = a.Lx + gid * 3 * a.p;
   const int p = a.p;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // the neighbour rows as one list of up to three ranges
   int32_t rb[3], rl[3];
   int nr = 0;
@@ -487,8 +489,8 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_fmm_eval(FmmArgs a, int64_t
   const int32_t t0 = leaf_t[loc], t1 = leaf_t[loc + 1];
   for (int32_t tb = t0; tb < t1; tb += 64) {
     const int nt = min(64, (int)(t1 - tb));
-    const int S = 64 / nt;                 // lanes per target within a wave
-    const int tl = lane % nt, r = lane / nt;
+    const int S = B / nt;                  // threads per target
+    const int tl = threadIdx.x % nt, r = threadIdx.x / nt;
     const bool act = r < S;
     const int64_t i = tperm[tb + tl];
     const double x = g.x[i], y = g.y[i], nx = g.nx[i], ny = g.ny[i];
@@ -510,12 +512,12 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_fmm_eval(FmmArgs a, int64_t
       }
       __syncthreads();
       const int m = min(B, (int)(total - cb));
-      const int q1 = min(m, 64 * (w + 1));
       if (act) {
-        for (int qq = 64 * w + r; qq < q1; qq += S) {
+        for (int qq = r; qq < m; qq += S) {
           const double rx = x - shx[qq], ry = y - shy[qq];
-          // the target's own node (r = 0): the floor keeps 1/|r|^2 finite and (r.n)(r.f) = 0
-          const double ir2 = rcp64(fmax(fma(rx, rx, ry * ry), 1e-300));
+          // the target's own node (r = 0): the added 1e-300 keeps 1/|r|^2 finite (and below the
+          // rounding of every other pair's |r|^2) while (r.n)(r.f) = 0
+          const double ir2 = rcp64(fma(rx, rx, fma(ry, ry, 1e-300)));
           const double cf = ((fma(rx, nx, ry * ny) * fma(rx, sf1[qq], ry * sf2[qq])) * ir2) * ir2;
           d1 = fma(cf, rx, d1);
           d2 = fma(cf, ry, d2);
@@ -523,16 +525,15 @@ __global__ __launch_bounds__(64 * kEvalWaves) void k_fmm_eval(FmmArgs a, int64_t
       }
     }
     __syncthreads();
-    red1[w][lane] = act ? d1 : 0.0;
-    red2[w][lane] = act ? d2 : 0.0;
+    red1[threadIdx.x] = act ? d1 : 0.0;
+    red2[threadIdx.x] = act ? d2 : 0.0;
     __syncthreads();
-    if (w == 0 && lane < nt) {
+    if (threadIdx.x < nt) {
       double e1 = 0.0, e2 = 0.0;
-      for (int ww = 0; ww < kEvalWaves; ++ww)
-        for (int sl = 0; sl < S; ++sl) {
-          e1 += red1[ww][sl * nt + lane];
-          e2 += red2[ww][sl * nt + lane];
-        }
+      for (int sl = 0; sl < S; ++sl) {
+        e1 += red1[sl * nt + threadIdx.x];
+        e2 += red2[sl * nt + threadIdx.x];
+      }
       const cx dz = {x - c.r, y - c.i};
       const cx u = dz * (1.0 / h);
       cx A = {0, 0}, Bv = {0, 0}, Ad = {0, 0}, Cd = {0, 0};
