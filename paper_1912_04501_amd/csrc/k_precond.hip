@@ -246,6 +246,14 @@ __global__ void k_store_inverse(const ShapeDesc* __restrict__ sh, const double* 
   for (int r = threadIdx.x; r < m; r += blockDim.x) inv[d.ioff + precond_index(d.n, R, r, c)] = (float)X[(int64_t)r * m + i];
 }
 
+// Non-temporal load of a pair of inverse entries: each entry is read once per product, and the
+// inverses (about 2 GB for 1000 particles of 350 nodes) would only evict what the caches hold.
+__device__ __forceinline__ float2 stream_load(const float2* p) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v v = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(v.x, v.y);
+}
+
 // Blocks (particle, row segment): out = R (B^-1 (R^T v)) on the particle's nodes, segment y
 // producing nodes [y nk, (y + 1) nk) (rows k and n + k of the 2n x 2n inverse, nk = ceil(n / R)
 // rounded up to even), so that small particle counts still spread over the chip. Particles of
@@ -288,7 +296,7 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
     for (; c + 3 * S < m; c += 4 * S) {   // four columns' loads in flight, summed in column order
       float2 w[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) w[u] = M2[((int64_t)(c + u * S) * 2 * kn + rr) >> 1];
+      for (int u = 0; u < 4; ++u) w[u] = stream_load(M2 + (((int64_t)(c + u * S) * 2 * kn + rr) >> 1));
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         a0 = fma((double)w[u].x, vb[c + u * S], a0);
@@ -296,7 +304,7 @@ __global__ __launch_bounds__(1024) void k_precond_apply(Geo g, const int32_t* __
       }
     }
     for (; c < m; c += S) {
-      const float2 w = M2[((int64_t)c * 2 * kn + rr) >> 1];
+      const float2 w = stream_load(M2 + (((int64_t)c * 2 * kn + rr) >> 1));
       a0 = fma((double)w.x, vb[c], a0);
       a1 = fma((double)w.y, vb[c], a1);
     }
