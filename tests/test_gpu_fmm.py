@@ -77,6 +77,24 @@ def test_fmm_order_limits(order, bound):
     assert err < bound
 
 
+@pytest.mark.parametrize("order,bound", [(33, 1e-10), (13, 3e-4)])
+def test_fmm_odd_order(order, bound):
+    """Odd expansion orders: the multipole pass computes runs of ceil(p / 8) terms (the last run
+    partly past p), and the multipole-to-local pass gives a lane the terms j and j + ceil(p / 2),
+    the second missing for the last j. Same skewed 25-ellipse cell as the order limits."""
+    wl = W.random_ellipses(25, 0.3, seed=7, skew=-0.47)
+    g = geometry.build_geometry(wl)
+    s = _fmm(wl, order)
+    assert s.fmm_stats()["order"] == order
+    sig = W.random_density(g.N, seed=12)
+    T = _n(s.near_traction(torch.as_tensor(sig, device="cuda:0")))
+    ref = _oracle_near(g, sig)
+    dev = np.stack([T[:g.N], T[g.N:]], axis=1)
+    err = np.abs(dev - ref).max() / np.abs(ref).max()
+    print(f"[fmm order {order}] rel err {err:.2e}", flush=True)
+    assert err < bound
+
+
 def test_fmm_near_sum_200_ellipses_sampled():
     """The 200-ellipse, 51,200-node cell: 3,000 sampled targets against the oracle."""
     wl = W.ellipses_200()
