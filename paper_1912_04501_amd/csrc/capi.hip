@@ -1171,6 +1171,8 @@ struct HostArray {
   T* data() { return p.get(); }
 };
 
+size_t fmm_table_doubles(int p);   // the FMM plan's table sizes (k_fmm.hip)
+
 void build_fmm_plan(spm_handle* h) {
   FmmPlan& F = h->fmm;
   F.on = false;
@@ -1365,7 +1367,7 @@ void build_fmm_plan(spm_handle* h) {
   ensure(h, F.bsrc, nbox);
   ensure(h, F.lists, lists.size());
   ensure(h, F.fact, 2 * p);
-  ensure(h, F.m2l_tab, (size_t)49 * 2 * p * 2);
+  ensure(h, F.m2l_tab, fmm_table_doubles(p));
   ensure(h, F.Mx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.Lx, (size_t)nbox * 3 * p * 2);
   ensure(h, F.one_block, 2);

@@ -67,6 +67,8 @@ struct FmmArgs {
   const int32_t *leaf_s, *bsrc;
   const double* fact;
   const cx* m2l_tab;               // [49][2][p] M2L scalings per displacement
+  const cx* m2m_tp;                // [4][p] (child offset / parent side)^k / k!
+  const int32_t* m2m_asg;          // [16][5] M2M terms per lane of a child (-1: none)
   cx *Mx, *Lx;                     // [box][3][p]
 };
 
@@ -176,14 +178,15 @@ void launch_p2m(const FmmArgs& a, unsigned nb, const int32_t* list, hipStream_t 
 }
 
 constexpr int kM2lMaxP = 64;   // largest expansion order (LDS and table sizes)
+constexpr int kM2mLanes = 16, kM2mSlots = 5;   // lanes per child, terms per lane (16 x 5 >= 64)
 
 // multipoles of level l from their children at level l + 1; the four children are staged in LDS
 // in one phase (their loads overlap). Term k of a child is a sum of k + 1 products, so each child
-// takes sixteen lanes and its terms go to them in a snake order (rows of sixteen terms, every other
-// row reversed), which evens out the triangular sums; the children's terms are then added in child
-// order through LDS.
+// takes sixteen lanes and its terms go to them by a table built once per plan (largest sums first,
+// each to the least loaded lane), which evens out the triangular sums; the children's terms are
+// then added in child order through LDS. A child's centre is (+-1 +-i) / 4 parent sides from the
+// parent's at every level, so the powers of that offset come from a table too.
 __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t* __restrict__ list) {
-  constexpr int kRows = kM2lMaxP / 16;
   __shared__ cx ac[4][3][kM2lMaxP];     // child multipoles times 2^-m / m!, then the child sums
   __shared__ cx tp[4][kM2lMaxP];        // (child offset / parent side)^k / k!
   const int64_t gid = list[blockIdx.x];
@@ -191,7 +194,6 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
   const int n = 1 << l;
   const int ix = (int)(loc & (n - 1)), iy = (int)(loc >> l);
   const cx c = box_center(a, l, loc);
-  const double ihP = (double)n / a.D0;
   const int k = threadIdx.x, p = a.p;
   bool has[4];
   cx dch[4];
@@ -206,17 +208,20 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
       ac[ch][0][k] = m[k] * sc;
       ac[ch][1][k] = m[p + k] * sc;
       ac[ch][2][k] = m[2 * p + k] * sc;
-      tp[ch][k] = cpow(dch[ch] * ihP, k) * (1.0 / a.fact[k]);
+      tp[ch][k] = a.m2m_tp[ch * p + k];
     }
   }
   __syncthreads();
   const int ch = k >> 4, j = k & 15;
-  cx sum[kRows][3];
+  int kks[kM2mSlots];
+#pragma unroll
+  for (int sl = 0; sl < kM2mSlots; ++sl) kks[sl] = a.m2m_asg[j * kM2mSlots + sl];
+  cx sum[kM2mSlots][3];
   if (has[ch]) {
 #pragma unroll
-    for (int row = 0; row < kRows; ++row) {
-      const int kk = 16 * row + ((row & 1) ? 15 - j : j);
-      if (kk >= p) continue;
+    for (int row = 0; row < kM2mSlots; ++row) {
+      const int kk = kks[row];
+      if (kk < 0) continue;
       cx sA = {0, 0}, sB = {0, 0}, sC = {0, 0};
       for (int m = 0; m <= kk; ++m) {
         const cx t = tp[ch][kk - m];
@@ -233,9 +238,9 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
   __syncthreads();   // every lane is done reading the staged multipoles
   if (has[ch]) {
 #pragma unroll
-    for (int row = 0; row < kRows; ++row) {
-      const int kk = 16 * row + ((row & 1) ? 15 - j : j);
-      if (kk >= p) continue;
+    for (int row = 0; row < kM2mSlots; ++row) {
+      const int kk = kks[row];
+      if (kk < 0) continue;
       ac[ch][0][kk] = sum[row][0];
       ac[ch][1][kk] = sum[row][1];
       ac[ch][2][kk] = sum[row][2];
@@ -269,6 +274,35 @@ __global__ __launch_bounds__(64) void k_fmm_m2m(FmmArgs a, int l, const int32_t*
 // scalings come from per-displacement tables built once per plan; the next round's multipoles and
 // table entries are loaded while the current sums run, and the lanes' partial expansions are added
 // over the boxes of a round in a fixed order at the end.
+
+// M2M tables: tp[ch p + k] = t^k / k! for the child offset t = (+-1 +-i) / 4 (x by ch & 1, y by
+// ch >> 1); asg[j kM2mSlots + s] = the terms of lane j, the largest sums first, each to the least
+// loaded lane with a free slot (ties to the lowest lane), -1 after the last.
+__global__ __launch_bounds__(64) void k_fmm_m2m_tables(int p, const double* __restrict__ fact, cx* __restrict__ tp,
+                                                       int32_t* __restrict__ asg) {
+  const int k = threadIdx.x;
+  if (k < p)
+    for (int ch = 0; ch < 4; ++ch) {
+      const cx t = {(ch & 1) ? 0.25 : -0.25, (ch >> 1) ? 0.25 : -0.25};
+      tp[ch * p + k] = cpow(t, k) * (1.0 / fact[k]);
+    }
+  if (k == 0) {
+    int load[kM2mLanes], cnt[kM2mLanes];
+    for (int l = 0; l < kM2mLanes; ++l) {
+      load[l] = 0;
+      cnt[l] = 0;
+      for (int sl = 0; sl < kM2mSlots; ++sl) asg[l * kM2mSlots + sl] = -1;
+    }
+    for (int kk = p - 1; kk >= 0; --kk) {
+      int best = -1;
+      for (int l = 0; l < kM2mLanes; ++l)
+        if (cnt[l] < kM2mSlots && (best < 0 || load[l] < load[best])) best = l;
+      asg[best * kM2mSlots + cnt[best]] = kk;
+      ++cnt[best];
+      load[best] += kk + 1;
+    }
+  }
+}
 
 // tab[(2 d) p + k] = rho^k / k!, tab[(2 d + 1) p + k] = (-1)^k rho^(k+1) / k!, rho = 1 / D for the
 // displacement D = (c_t - c_s) / h = (d % 7 - 3) + i (d / 7 - 3); zero for the 3 x 3 neighbours.
@@ -676,6 +710,8 @@ FmmArgs args(spm_handle* h) {
   a.bsrc = F.bsrc;
   a.fact = F.fact;
   a.m2l_tab = reinterpret_cast<const cx*>(F.m2l_tab);
+  a.m2m_tp = a.m2l_tab + (size_t)49 * 2 * F.p;
+  a.m2m_asg = reinterpret_cast<const int32_t*>(a.m2m_tp + (size_t)4 * F.p);
   a.Mx = reinterpret_cast<cx*>(F.Mx);
   a.Lx = reinterpret_cast<cx*>(F.Lx);
   return a;
@@ -739,10 +775,18 @@ void launch_fmm_velocities(spm_handle* h, double* near3) {
   SPM_HIP_CHECK(hipGetLastError());
 }
 
+// doubles of the per-plan tables: M2L scalings [49][2][p] cx, M2M powers [4][p] cx, M2M lanes [16][5] int32
+size_t fmm_table_doubles(int p) {
+  return (size_t)49 * 2 * p * 2 + (size_t)4 * p * 2 + (kM2mLanes * kM2mSlots + 1) / 2;
+}
+
 void launch_fmm_tables(spm_handle* h) {
   const FmmPlan& F = h->fmm;
   if (F.p < 1 || F.p > kM2lMaxP) throw ApiError(SPM_EINVAL, "FMM order must be at most 64");
   k_fmm_m2l_tables<<<49, 64, 0, h->stream>>>(F.p, F.fact, reinterpret_cast<cx*>(F.m2l_tab));
+  SPM_HIP_CHECK(hipGetLastError());
+  cx* tp = reinterpret_cast<cx*>(F.m2l_tab) + (size_t)49 * 2 * F.p;
+  k_fmm_m2m_tables<<<1, 64, 0, h->stream>>>(F.p, F.fact, tp, reinterpret_cast<int32_t*>(tp + (size_t)4 * F.p));
   SPM_HIP_CHECK(hipGetLastError());
 }
 
